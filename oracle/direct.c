@@ -1,0 +1,215 @@
+/*
+ * FP64 direct kernel sums -- TEST INFRASTRUCTURE ONLY.
+ *
+ * This file is part of the oracle: a plain, slow, obviously correct CPU
+ * evaluation of the kernel summation problem g_i(x) = sum_b K_ij(x, y_b) s_j
+ * (Sec. I, Eq. kernelsumlinear; the nonlinear-in-source form Eq. kernelsum
+ * for RPY).  Only the test-suite, the smoke check and the CPU-baseline leg of
+ * the benchmark may load it.  It shares no code with the HIP library.
+ *
+ * Conventions (all kernels):
+ *   r = x - y (target minus source), mu = 1, pairs with r == 0 add nothing.
+ *   Points are AoS [n][3]; values are AoS [n][k].
+ *   OpenMP over targets, each target sums all sources in index order.
+ *
+ * Kernels and where they are defined:
+ *   Laplace L = 1/(4 pi r), dipole L^D_j = -dL/dx_j           Sec. II.A
+ *   Stokeslet G_ij = (delta_ij/r + r_i r_j/r^3)/(8 pi)        Sec. II.B
+ *   RPY G^RPY = (1 + b^2 lap/6) G, target [u, lap u]          Sec. II.B, Eq. RPYkernel
+ *   StokesPVel [f,q] -> [p,u]                                 Sec. II.C, Eqs. stkslp, stkslvel
+ *   Stokes double layer D -> [p,u], T_ijk = -3 r_i r_j r_k/(8 pi r^5)
+ *                                                             Sec. II.C, Eqs. stkdlp, stkdlvel
+ *   Traction sigma = -p I + grad u + grad u^T                 Sec. II.C, Eq. stressdef
+ * Output component orders (the paper prints none; see the oracle README
+ * strings in direct.py): Hessian (xx,xy,xz,yy,yz,zz), D and sigma row-major.
+ */
+#include <math.h>
+#include <stdint.h>
+
+#define PI 3.14159265358979323846
+
+/* Stokeslet: f (3) -> u (3). */
+void oracle_stokeslet(int64_t ns, const double *ys, const double *f,
+                      int64_t nt, const double *xs, double *out)
+{
+    const double c = 1.0 / (8.0 * PI);
+#pragma omp parallel for schedule(dynamic, 16) if (nt * ns > 200000)
+    for (int64_t t = 0; t < nt; ++t) {
+        double u0 = 0, u1 = 0, u2 = 0;
+        for (int64_t s = 0; s < ns; ++s) {
+            double r0 = xs[3*t] - ys[3*s], r1 = xs[3*t+1] - ys[3*s+1], r2 = xs[3*t+2] - ys[3*s+2];
+            double rr = r0*r0 + r1*r1 + r2*r2;
+            if (rr == 0.0) continue;
+            double r = sqrt(rr);
+            double f0 = f[3*s], f1 = f[3*s+1], f2 = f[3*s+2];
+            double rf = r0*f0 + r1*f1 + r2*f2;
+            double a = 1.0 / r, b = rf / (rr * r);
+            u0 += a*f0 + b*r0;
+            u1 += a*f1 + b*r1;
+            u2 += a*f2 + b*r2;
+        }
+        out[3*t] = c*u0; out[3*t+1] = c*u1; out[3*t+2] = c*u2;
+    }
+}
+
+/* RPY: (f1,f2,f3,b) (4) -> (u, lap u) (6).
+ * u = G f + (b^2/6) lap G f,  lap G_ij = (2 delta_ij/r^3 - 6 r_i r_j/r^5)/(8 pi),
+ * lap u = lap G f (the b^2 term drops because lap lap G = 0). */
+void oracle_rpy(int64_t ns, const double *ys, const double *fb,
+                int64_t nt, const double *xs, double *out)
+{
+    const double c = 1.0 / (8.0 * PI);
+#pragma omp parallel for schedule(dynamic, 16) if (nt * ns > 200000)
+    for (int64_t t = 0; t < nt; ++t) {
+        double u[3] = {0, 0, 0}, l[3] = {0, 0, 0};
+        for (int64_t s = 0; s < ns; ++s) {
+            double r[3] = {xs[3*t] - ys[3*s], xs[3*t+1] - ys[3*s+1], xs[3*t+2] - ys[3*s+2]};
+            double rr = r[0]*r[0] + r[1]*r[1] + r[2]*r[2];
+            if (rr == 0.0) continue;
+            double rn = sqrt(rr);
+            const double *fs = fb + 4*s;
+            double b2 = fs[3] * fs[3];
+            double rf = r[0]*fs[0] + r[1]*fs[1] + r[2]*fs[2];
+            double i1 = 1.0 / rn, i3 = i1 / rr, i5 = i3 / rr;
+            /* Stokeslet part */
+            double gd = i1, gr = rf * i3;
+            /* lap G f = 2 f/r^3 - 6 r (r.f)/r^5 */
+            double ld = 2.0 * i3, lr = -6.0 * rf * i5;
+            for (int i = 0; i < 3; ++i) {
+                double g = gd * fs[i] + gr * r[i];
+                double lg = ld * fs[i] + lr * r[i];
+                u[i] += g + (b2 / 6.0) * lg;
+                l[i] += lg;
+            }
+        }
+        for (int i = 0; i < 3; ++i) { out[6*t+i] = c*u[i]; out[6*t+3+i] = c*l[i]; }
+    }
+}
+
+/* Laplace charges q (SL, 1) and dipoles d (DL, 3) -> phi, grad phi and,
+ * when hess != 0, the Hessian (xx,xy,xz,yy,yz,zz).  kt = 4 or 10. */
+void oracle_laplace(int64_t nsl, const double *ysl, const double *q,
+                    int64_t ndl, const double *ydl, const double *d,
+                    int64_t nt, const double *xs, double *out, int hess)
+{
+    const double c = 1.0 / (4.0 * PI);
+    const int kt = hess ? 10 : 4;
+#pragma omp parallel for schedule(dynamic, 16) if (nt * (nsl + ndl) > 200000)
+    for (int64_t t = 0; t < nt; ++t) {
+        double acc[10] = {0};
+        for (int64_t s = 0; s < nsl; ++s) {
+            double r[3] = {xs[3*t] - ysl[3*s], xs[3*t+1] - ysl[3*s+1], xs[3*t+2] - ysl[3*s+2]};
+            double rr = r[0]*r[0] + r[1]*r[1] + r[2]*r[2];
+            if (rr == 0.0) continue;
+            double i1 = 1.0 / sqrt(rr), i3 = i1 / rr, i5 = i3 / rr;
+            double qs = q[s];
+            acc[0] += qs * i1;
+            for (int i = 0; i < 3; ++i) acc[1+i] += -qs * r[i] * i3;
+            if (hess) {
+                int k = 4;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = i; j < 3; ++j)
+                        acc[k++] += qs * (3.0 * r[i] * r[j] * i5 - (i == j ? i3 : 0.0));
+            }
+        }
+        for (int64_t s = 0; s < ndl; ++s) {
+            double r[3] = {xs[3*t] - ydl[3*s], xs[3*t+1] - ydl[3*s+1], xs[3*t+2] - ydl[3*s+2]};
+            double rr = r[0]*r[0] + r[1]*r[1] + r[2]*r[2];
+            if (rr == 0.0) continue;
+            double i1 = 1.0 / sqrt(rr), i3 = i1 / rr, i5 = i3 / rr, i7 = i5 / rr;
+            const double *ds = d + 3*s;
+            double dr = ds[0]*r[0] + ds[1]*r[1] + ds[2]*r[2];
+            acc[0] += dr * i3;
+            for (int i = 0; i < 3; ++i) acc[1+i] += ds[i] * i3 - 3.0 * dr * r[i] * i5;
+            if (hess) {
+                int k = 4;
+                for (int i = 0; i < 3; ++i)
+                    for (int j = i; j < 3; ++j)
+                        acc[k++] += -3.0 * (ds[j] * r[i] + ds[i] * r[j] + (i == j ? dr : 0.0)) * i5
+                                    + 15.0 * dr * r[i] * r[j] * i7;
+            }
+        }
+        for (int k = 0; k < kt; ++k) out[kt*t+k] = c * acc[k];
+    }
+}
+
+/* StokesPVel: SL (f,q) (4) and DL D (9, row-major D[3j+k] = D_jk) -> (p, u) (4). */
+void oracle_pvel(int64_t nsl, const double *ysl, const double *fq,
+                 int64_t ndl, const double *ydl, const double *D,
+                 int64_t nt, const double *xs, double *out)
+{
+    const double c4 = 1.0 / (4.0 * PI), c8 = 1.0 / (8.0 * PI);
+#pragma omp parallel for schedule(dynamic, 16) if (nt * (nsl + ndl) > 200000)
+    for (int64_t t = 0; t < nt; ++t) {
+        double p = 0, u[3] = {0, 0, 0};
+        for (int64_t s = 0; s < nsl; ++s) {
+            double r[3] = {xs[3*t] - ysl[3*s], xs[3*t+1] - ysl[3*s+1], xs[3*t+2] - ysl[3*s+2]};
+            double rr = r[0]*r[0] + r[1]*r[1] + r[2]*r[2];
+            if (rr == 0.0) continue;
+            double i1 = 1.0 / sqrt(rr), i3 = i1 / rr;
+            const double *v = fq + 4*s;
+            double rf = r[0]*v[0] + r[1]*v[1] + r[2]*v[2];
+            p += c4 * rf * i3;
+            for (int i = 0; i < 3; ++i)
+                u[i] += c8 * ((rr * v[i] + r[i] * rf) * i3 - r[i] * v[3] * i3);
+        }
+        for (int64_t s = 0; s < ndl; ++s) {
+            double r[3] = {xs[3*t] - ydl[3*s], xs[3*t+1] - ydl[3*s+1], xs[3*t+2] - ydl[3*s+2]};
+            double rr = r[0]*r[0] + r[1]*r[1] + r[2]*r[2];
+            if (rr == 0.0) continue;
+            double i1 = 1.0 / sqrt(rr), i3 = i1 / rr, i5 = i3 / rr;
+            const double *Ds = D + 9*s;
+            double rDr = 0, tr = Ds[0] + Ds[4] + Ds[8];
+            for (int j = 0; j < 3; ++j)
+                for (int k = 0; k < 3; ++k) rDr += r[j] * Ds[3*j+k] * r[k];
+            p += c4 * (-3.0 * rDr * i5 + tr * i3);
+            for (int i = 0; i < 3; ++i) u[i] += -3.0 * c8 * r[i] * rDr * i5;
+        }
+        out[4*t] = p; out[4*t+1] = u[0]; out[4*t+2] = u[1]; out[4*t+3] = u[2];
+    }
+}
+
+/* Traction sigma (9, row-major sigma[3i+j]) from SL (f,q) and DL D:
+ * sigma = -p I + grad u + grad u^T applied to the PVel flow fields. */
+void oracle_traction(int64_t nsl, const double *ysl, const double *fq,
+                     int64_t ndl, const double *ydl, const double *D,
+                     int64_t nt, const double *xs, double *out)
+{
+    const double c4 = 1.0 / (4.0 * PI);
+#pragma omp parallel for schedule(dynamic, 16) if (nt * (nsl + ndl) > 200000)
+    for (int64_t t = 0; t < nt; ++t) {
+        double sg[9] = {0};
+        for (int64_t s = 0; s < nsl; ++s) {
+            double r[3] = {xs[3*t] - ysl[3*s], xs[3*t+1] - ysl[3*s+1], xs[3*t+2] - ysl[3*s+2]};
+            double rr = r[0]*r[0] + r[1]*r[1] + r[2]*r[2];
+            if (rr == 0.0) continue;
+            double i1 = 1.0 / sqrt(rr), i3 = i1 / rr, i5 = i3 / rr;
+            const double *v = fq + 4*s;
+            double rf = r[0]*v[0] + r[1]*v[1] + r[2]*v[2];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    sg[3*i+j] += -3.0 * c4 * r[i] * r[j] * rf * i5
+                                 - c4 * v[3] * ((i == j ? i3 : 0.0) - 3.0 * r[i] * r[j] * i5);
+        }
+        for (int64_t s = 0; s < ndl; ++s) {
+            double r[3] = {xs[3*t] - ydl[3*s], xs[3*t+1] - ydl[3*s+1], xs[3*t+2] - ydl[3*s+2]};
+            double rr = r[0]*r[0] + r[1]*r[1] + r[2]*r[2];
+            if (rr == 0.0) continue;
+            double i1 = 1.0 / sqrt(rr), i3 = i1 / rr, i5 = i3 / rr, i7 = i5 / rr;
+            const double *Ds = D + 9*s;
+            double tr = Ds[0] + Ds[4] + Ds[8];
+            double w[3];     /* sym(D) r */
+            for (int j = 0; j < 3; ++j) {
+                w[j] = 0;
+                for (int k = 0; k < 3; ++k) w[j] += 0.5 * (Ds[3*j+k] + Ds[3*k+j]) * r[k];
+            }
+            double A = r[0]*w[0] + r[1]*w[1] + r[2]*w[2];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    sg[3*i+j] += c4 * (-(i == j ? tr * i3 : 0.0)
+                                       - 3.0 * (r[i] * w[j] + w[i] * r[j]) * i5
+                                       + 15.0 * A * r[i] * r[j] * i7);
+        }
+        for (int k = 0; k < 9; ++k) out[9*t+k] = sg[k];
+    }
+}

@@ -1,0 +1,152 @@
+/*
+ * FP64 Ewald summation for triply periodic Laplace charges and dipoles --
+ * TEST INFRASTRUCTURE ONLY (part of the oracle; no code shared with the HIP
+ * library).
+ *
+ * Problem: phi(x) = sum_j sum_n [q_j L(x - y_j + nL) + d_j . r/(4 pi |r|^3)]
+ * over the periodic lattice, with L(r) = 1/(4 pi r) (Sec. II.A), the
+ * periodic boundary condition of Sec. III and its appendix on periodicity.
+ * The lattice sum is only conditionally convergent, so the oracle fixes
+ * the textbook Ewald definition: zero net charge is required, the k = 0 term
+ * is dropped and no surface (dipole) term is added ("tin-foil" boundary).
+ *
+ * Split with parameter xi:
+ *   real part   q B0(rho) + (d . r) B(rho)                   (rho = |r|)
+ *               B0 = erfc(xi rho)/(4 pi rho)
+ *               B  = [erfc(xi rho) + 2 xi rho/sqrt(pi) e^{-xi^2 rho^2}]/(4 pi rho^3)
+ *               C  = [3 erfc(xi rho) + 2 xi rho/sqrt(pi) (3 + 2 xi^2 rho^2) e^{-xi^2 rho^2}]/(4 pi rho^5)
+ *               grad: -q B r + d B - (d . r) C r
+ *   reciprocal  (1/V) sum_{k != 0} e^{-k^2/(4 xi^2)}/k^2 Re[S(k) e^{i k.x}],
+ *               S(k) = sum_j (q_j - i k.d_j) e^{-i k.y_j},  k = 2 pi n / L
+ *   self        a target that coincides with source j drops the smooth
+ *               self part: phi -= q_j xi / (2 pi^{3/2}),
+ *               grad phi -= d_j xi^3 / (3 pi^{3/2}).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PI 3.14159265358979323846
+
+/* Linear index of lattice vector n in the cube [-nmax, nmax]^3. */
+static inline int64_t kidx(int nx, int ny, int nz, int nmax)
+{
+    int w = 2 * nmax + 1;
+    return ((int64_t)(nz + nmax) * w + (ny + nmax)) * w + (nx + nmax);
+}
+
+/* Half-space predicate: exactly one of n and -n is kept, n = 0 excluded. */
+static inline int khalf(int nx, int ny, int nz)
+{
+    return nz > 0 || (nz == 0 && (ny > 0 || (ny == 0 && nx > 0)));
+}
+
+/* Structure factor S(k) on the half space of the cube [-nmax,nmax]^3. */
+void oracle_ewald_structure(int64_t ns, const double *ys, const double *q,
+                            const double *d, double L, int nmax,
+                            double *S_re, double *S_im)
+{
+    int w = 2 * nmax + 1;
+    int64_t nk = (int64_t)w * w * w;
+    memset(S_re, 0, sizeof(double) * nk);
+    memset(S_im, 0, sizeof(double) * nk);
+#pragma omp parallel
+    {
+        double *sr = calloc(nk, sizeof(double));
+        double *si = calloc(nk, sizeof(double));
+        double *cx = malloc(sizeof(double) * 6 * w);
+        double *sx = cx + 3 * w;
+#pragma omp for schedule(static)
+        for (int64_t j = 0; j < ns; ++j) {
+            /* e^{-i 2 pi n y_a / L} = cos - i sin, per axis a and n */
+            for (int a = 0; a < 3; ++a)
+                for (int n = -nmax; n <= nmax; ++n) {
+                    double ang = 2.0 * PI * n * ys[3*j+a] / L;
+                    cx[a*w + n + nmax] = cos(ang);
+                    sx[a*w + n + nmax] = -sin(ang);
+                }
+            double qj = q ? q[j] : 0.0;
+            double dx = d ? d[3*j] : 0.0, dy = d ? d[3*j+1] : 0.0, dz = d ? d[3*j+2] : 0.0;
+            for (int nz = 0; nz <= nmax; ++nz)
+                for (int ny = -nmax; ny <= nmax; ++ny)
+                    for (int nx = -nmax; nx <= nmax; ++nx) {
+                        if (!khalf(nx, ny, nz)) continue;
+                        /* phase e^{-i k.y} */
+                        double ar = cx[nx + nmax], ai = sx[nx + nmax];
+                        double br = cx[w + ny + nmax], bi = sx[w + ny + nmax];
+                        double cr = cx[2*w + nz + nmax], ci = sx[2*w + nz + nmax];
+                        double tr = ar*br - ai*bi, ti = ar*bi + ai*br;
+                        double er = tr*cr - ti*ci, ei = tr*ci + ti*cr;
+                        /* amplitude q - i k.d */
+                        double kd = 2.0 * PI / L * (nx*dx + ny*dy + nz*dz);
+                        double mr = qj, mi = -kd;
+                        int64_t id = kidx(nx, ny, nz, nmax);
+                        sr[id] += mr*er - mi*ei;
+                        si[id] += mr*ei + mi*er;
+                    }
+        }
+#pragma omp critical
+        for (int64_t i = 0; i < nk; ++i) { S_re[i] += sr[i]; S_im[i] += si[i]; }
+        free(sr); free(si); free(cx);
+    }
+}
+
+/* phi and grad phi (4 values per target) from the real, reciprocal and self parts. */
+void oracle_ewald_eval(int64_t ns, const double *ys, const double *q, const double *d,
+                       int64_t nt, const double *xs, double L, double xi, double rc,
+                       int nmax, const double *S_re, const double *S_im, double *out)
+{
+    const double V = L * L * L;
+    const int nimg = (int)ceil(rc / L);
+    const double sqpi = sqrt(PI);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nt; ++t) {
+        double acc[4] = {0, 0, 0, 0};
+        const double *x = xs + 3*t;
+        /* real space */
+        for (int64_t j = 0; j < ns; ++j) {
+            double qj = q ? q[j] : 0.0;
+            double dj[3] = {d ? d[3*j] : 0.0, d ? d[3*j+1] : 0.0, d ? d[3*j+2] : 0.0};
+            int self = 0;
+            for (int a = -nimg; a <= nimg; ++a)
+                for (int b = -nimg; b <= nimg; ++b)
+                    for (int c = -nimg; c <= nimg; ++c) {
+                        double r[3] = {x[0] - ys[3*j] + a*L, x[1] - ys[3*j+1] + b*L, x[2] - ys[3*j+2] + c*L};
+                        double rr = r[0]*r[0] + r[1]*r[1] + r[2]*r[2];
+                        if (rr == 0.0) { self = 1; continue; }
+                        if (rr >= rc*rc) continue;
+                        double rho = sqrt(rr), xr = xi * rho;
+                        double ec = erfc(xr), ex = exp(-xr*xr);
+                        double B0 = ec / (4.0*PI*rho);
+                        double B = (ec + 2.0*xr/sqpi*ex) / (4.0*PI*rho*rr);
+                        double C = (3.0*ec + 2.0*xr/sqpi*(3.0 + 2.0*xr*xr)*ex) / (4.0*PI*rho*rr*rr);
+                        double dr = dj[0]*r[0] + dj[1]*r[1] + dj[2]*r[2];
+                        acc[0] += qj * B0 + dr * B;
+                        for (int i = 0; i < 3; ++i)
+                            acc[1+i] += -qj * B * r[i] + dj[i] * B - dr * C * r[i];
+                    }
+            if (self) {
+                acc[0] -= qj * xi / (2.0 * PI * sqpi);
+                for (int i = 0; i < 3; ++i) acc[1+i] -= dj[i] * xi*xi*xi / (3.0 * PI * sqpi);
+            }
+        }
+        /* reciprocal space: the half space counted twice */
+        for (int nz = 0; nz <= nmax; ++nz)
+            for (int ny = -nmax; ny <= nmax; ++ny)
+                for (int nx = -nmax; nx <= nmax; ++nx) {
+                    if (!khalf(nx, ny, nz)) continue;
+                    double k[3] = {2.0*PI*nx/L, 2.0*PI*ny/L, 2.0*PI*nz/L};
+                    double k2 = k[0]*k[0] + k[1]*k[1] + k[2]*k[2];
+                    double g = 2.0 * exp(-k2 / (4.0*xi*xi)) / (k2 * V);
+                    double ph = k[0]*x[0] + k[1]*x[1] + k[2]*x[2];
+                    double cr = cos(ph), ci = sin(ph);
+                    int64_t id = kidx(nx, ny, nz, nmax);
+                    double zr = S_re[id]*cr - S_im[id]*ci;   /* Re[S e^{ikx}] */
+                    double zi = S_re[id]*ci + S_im[id]*cr;   /* Im[S e^{ikx}] */
+                    acc[0] += g * zr;
+                    for (int i = 0; i < 3; ++i) acc[1+i] += -g * k[i] * zi;  /* Re[i k S e^{ikx}] */
+                }
+        for (int i = 0; i < 4; ++i) out[4*t+i] = acc[i];
+    }
+}

@@ -1,0 +1,113 @@
+"""Pins for the oracle's plain FP64 KIFMM.
+
+* one leaf (leaf_cap >= N) leaves only the S->T route: the KIFMM equals the
+  direct sum to round-off;
+* every (target leaf, source leaf) pair is reached by exactly one route
+  (U, or V / W / X of the target leaf or an ancestor);
+* the error against the direct sum falls as the order p grows (Sec. III:
+  exponential convergence in m) for every kernel table;
+* the N=4096 uniform Stokeslet workload at p = 8, leaf_cap = 64.
+"""
+import numpy as np
+import pytest
+
+from oracle import direct, kifmm
+from paper_2010_15155_amd import workloads as W
+
+RNG = np.random.default_rng(2024)
+
+
+def _problem(kernel, n, seed, clustered=False):
+    rng = np.random.default_rng(seed)
+    if clustered:
+        x = W.gaussian_mixture_points(rng, n, rng.uniform(0.3, 0.7, (3, 3)), 0.08)
+    else:
+        x = rng.random((n, 3))
+    if kernel == "Stokeslet":
+        return dict(sl=x, sl_val=rng.standard_normal((n, 3)), trg=x)
+    if kernel == "RPY":
+        v = np.concatenate([rng.standard_normal((n, 3)), rng.uniform(0.002, 0.005, (n, 1))], 1)
+        return dict(sl=x, sl_val=v, trg=x)
+    if kernel == "LapPGrad":
+        q = rng.standard_normal(n)
+        return dict(sl=x, sl_val=q, dl=x, dl_val=rng.standard_normal((n, 3)), trg=x)
+    fq = rng.standard_normal((n, 4))
+    D = rng.standard_normal((n, 9))
+    y = rng.random((n // 2, 3))
+    return dict(sl=y, sl_val=fq[: n // 2], dl=x, dl_val=D, trg=x)
+
+
+KERNELS = ["Stokeslet", "RPY", "LapPGrad", "PVel", "Traction"]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_single_leaf_is_direct(kernel):
+    pb = _problem(kernel, 150, 1)
+    ref = direct.evaluate(kernel, **pb)
+    got = kifmm.evaluate(kernel, p=4, leaf_cap=10_000, **pb)
+    assert np.allclose(got, ref, rtol=1e-13, atol=1e-13 * np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("clustered", [False, True])
+def test_lists_cover_every_pair_once(clustered):
+    pb = _problem("PVel", 3000, 3, clustered)
+    T = kifmm.Tree(pb["sl"], pb["dl"], pb["trg"], (0, 0, 0), 1.0, 40)
+    assert T.level.max() >= 3
+    cnt = T.coverage()
+    assert np.all(cnt == 1)
+    # V lists hold non-adjacent same-level boxes, U lists adjacent leaves
+    for b, vl in T.V.items():
+        for a in vl:
+            assert T.level[a] == T.level[b] and not T.adj[a, b]
+            assert np.max(np.abs(T.anchor[a] - T.anchor[b])) <= 3
+    if clustered:
+        assert sum(len(w) for w in T.W.values()) > 0
+
+
+def test_tree_respects_leaf_cap():
+    pb = _problem("Stokeslet", 2000, 5, True)
+    T = kifmm.Tree(pb["sl"], None, pb["trg"], (0, 0, 0), 1.0, 50)
+    for b in np.nonzero(T.is_leaf)[0]:
+        assert max(len(i) for i in T.idx[b]) <= 50
+    # every point sits in exactly one leaf, inside the leaf's box
+    seen = np.concatenate([T.idx[b][2] for b in np.nonzero(T.is_leaf)[0]])
+    assert np.array_equal(np.sort(seen), np.arange(2000))
+    for b in np.nonzero(T.is_leaf)[0]:
+        c, h = T.centre(b), T.side(b)
+        pts = T.sets[2][T.idx[b][2]]
+        assert np.all(pts >= c - h / 2) and np.all(pts < c + h / 2)
+
+
+def test_surface_point_count():
+    for p in (2, 4, 6, 8, 10, 12):
+        assert len(kifmm.surface_grid(p)) == 6 * (p - 1) ** 2 + 2
+
+
+FIELDS = {"Stokeslet": [(0, 3)], "RPY": [(0, 3), (3, 6)], "LapPGrad": [(0, 1), (1, 4)],
+          "PVel": [(0, 1), (1, 4)], "Traction": [(0, 9)]}
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_error_falls_with_order(kernel):
+    # even orders p = 4 -> 6 (small odd orders converge non-monotonically)
+    pb = _problem(kernel, 600, 11, clustered=True)
+    ref = direct.evaluate(kernel, **pb)
+    T = kifmm.Tree(pb.get("sl"), pb.get("dl"), pb["trg"], (0, 0, 0), 1.0, 40)
+    assert T.level.max() >= 2 and sum(len(v) for v in T.V.values()) > 0
+    got = [kifmm.evaluate(kernel, p=p, tree=T, **pb) for p in (4, 6)]
+    for a, b in FIELDS[kernel]:
+        e4, e6 = (direct.rel_l2(g[:, a:b], ref[:, a:b]) for g in got)
+        assert e6 < 0.3 * e4, (a, b, e4, e6)
+        assert e6 < 1e-3, (a, b, e6)
+
+
+@pytest.mark.slow
+def test_uniform_stokeslet_4096_p8():
+    d = W.uniform_stokeslet(4096, 101)
+    x, f = d["xyz"], d["f"]
+    ref = direct.stokeslet(x, f, x)
+    st = {}
+    got = kifmm.evaluate("Stokeslet", x, f, None, None, x, p=8, leaf_cap=64, stats=st)
+    err = direct.rel_l2(got, ref)
+    assert st["n_v"] > 0 and st["depth"] >= 3
+    assert err < 1e-5
