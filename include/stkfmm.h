@@ -1,0 +1,164 @@
+/*
+ * stkfmm.h -- C ABI of the MI355X kernel aggregated FMM evaluation pass.
+ *
+ * The library evaluates the kernel summation problem
+ *     g_i(x^a) = sum_b K_ij(x^a, y^b) s_j^b            (Sec. I, Eq. kernelsumlinear)
+ * (and its nonlinear-in-source form, Sec. II, Eq. kernelsum, for RPY) with a
+ * kernel independent FMM whose tree-traversal (ML-tree) kernel is the scalar
+ * Laplace kernel for every problem: Laplace problems carry 1 component,
+ * Stokes problems (Stokeslet, RPY, StokesPVel double layer, traction) carry 4
+ * Laplace components (3 Phi_j and one Psi).  The choice of ML-tree kernel is
+ * the paper's kernel aggregation principle (Sec. II, kernel tables): it must
+ * be linear and of low dimension.
+ *
+ * Memory and ownership
+ *   - All point and value arrays are caller-owned DEVICE pointers (HIP global
+ *     memory on the context's device), FP64, contiguous AoS: points [n][3],
+ *     values [n][k].  The library never frees or retains them after a call
+ *     returns, except that stkfmm_set_points keeps its own sorted copies.
+ *   - The library allocates its own device workspace (hipMalloc) in
+ *     stkfmm_set_points and stkfmm_run; it is released by stkfmm_destroy.
+ *   - hip_stream is a hipStream_t (NULL = the default stream).  Work is
+ *     ordered after prior work on that stream; calls return after the result
+ *     is complete (they synchronise the stream).
+ *
+ * Errors
+ *   - No function throws across the ABI.  Every failing call returns a
+ *     status code and records a message readable by stkfmm_last_error.
+ *   - On error, output arrays hold unspecified contents.
+ *
+ * Thread safety: one context per host thread; contexts are independent.
+ */
+#ifndef STKFMM_H
+#define STKFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stkfmm_ctx stkfmm_ctx;
+
+typedef enum {
+    STKFMM_OK = 0,
+    STKFMM_E_ARG = 1,          /* bad argument: NULL, negative size, bad p / leaf_cap, NaN */
+    STKFMM_E_DOMAIN = 2,       /* point outside the box (open BC) or non-zero net charge (periodic) */
+    STKFMM_E_UNSUPPORTED = 3,  /* kernel / boundary combination not implemented */
+    STKFMM_E_NOMEM = 4,        /* device or host allocation failed */
+    STKFMM_E_DEVICE = 5,       /* HIP runtime error */
+    STKFMM_E_ACCURACY = 6,     /* learned mode: sampled error above tolerance after fallback */
+    STKFMM_E_STATE = 7         /* call out of order (run before set_points) */
+} stkfmm_status;
+
+/* Kernel names and value widths follow the appendix table of supported
+ * kernels (tab:implement):                     SL        DL       target
+ *   LAP_PGRAD      q -> phi, grad phi          q (1)     d (3)    (phi, dphi/dx, dphi/dy, dphi/dz) (4)
+ *   STOKESLET      f -> u                      f (3)     --       u (3)
+ *   RPY            [f, b] -> [u, lap u]        f,b (4)   --       (u, lap u) (6)
+ *   PVEL           [f, q], D -> [p, u]         f,q (4)   D (9)    (p, u) (4)
+ *   TRACTION       [f, q], D -> sigma          f,q (4)   D (9)    sigma (9)
+ * D and sigma are row-major 3x3 (D[3j+k] = D_jk, sigma[3i+j]); q in PVEL and
+ * TRACTION is twice the physical source (Sec. II.C); viscosity mu = 1. */
+typedef enum {
+    STKFMM_LAP_PGRAD = 0,
+    STKFMM_STOKESLET = 1,
+    STKFMM_RPY = 2,
+    STKFMM_PVEL = 3,
+    STKFMM_TRACTION = 4
+} stkfmm_kernel;
+
+/* Boundary conditions (Sec. III and its appendix on periodicity).  PXYZ is
+ * implemented for LAP_PGRAD; the others return STKFMM_E_UNSUPPORTED. */
+typedef enum {
+    STKFMM_BC_OPEN = 0,
+    STKFMM_BC_PX = 1,
+    STKFMM_BC_PXY = 2,
+    STKFMM_BC_PXYZ = 3
+} stkfmm_bc;
+
+/* Create a context for the cube [origin, origin + box_len)^3 on HIP device
+ * `device`.  flags: reserved, pass 0.  Operators (surface pseudo-inverses,
+ * M2M/L2L/M2L matrices, periodic operator) are built lazily per order p on
+ * first use and cached in the context.
+ * Errors: E_ARG (out NULL, box_len <= 0 or not finite), E_DEVICE. */
+stkfmm_status stkfmm_setup(stkfmm_ctx **out, const double origin[3], double box_len,
+                           int device, unsigned flags);
+
+/* Build the adaptive octree, the U/V/W/X interaction lists (Sec. II) and
+ * the sorted device copies of the points (t_tree).  Points are device
+ * pointers [n][3] FP64; n_sl or n_dl may be 0 with a NULL pointer.  A kernel
+ * without DL sources requires n_dl == 0.  SL, DL and target sets are
+ * independent and may alias.  p: equivalent-surface order (points per
+ * surface M = 6(p-1)^2 + 2, Sec. III), 2 <= p <= 16.  leaf_cap: a box is
+ * split while it holds more than leaf_cap targets, SL or DL sources (Sec. III
+ * uses 2000); 1 <= leaf_cap.
+ * Open BC: every point must lie in [origin, origin+box_len)^3, else E_DOMAIN.
+ * PXYZ: points are wrapped into the box.
+ * Errors: E_ARG, E_DOMAIN, E_UNSUPPORTED, E_NOMEM, E_DEVICE. */
+stkfmm_status stkfmm_set_points(stkfmm_ctx *ctx, stkfmm_kernel kernel, stkfmm_bc bc,
+                                int64_t n_sl, const double *sl_xyz,
+                                int64_t n_dl, const double *dl_xyz,
+                                int64_t n_trg, const double *trg_xyz,
+                                int p, int leaf_cap, void *hip_stream);
+
+/* The evaluation pass (t_run) on the points of the last stkfmm_set_points:
+ * sl_val [n_sl][k_sl], dl_val [n_dl][k_dl] in, trg_val [n_trg][k_trg] out
+ * (overwritten, user order).  Periodic LAP_PGRAD requires sum q = 0
+ * (relative to sum |q|, 1e-9), else E_DOMAIN; its potential is defined up to
+ * an additive constant (the Ewald convention with the k = 0 term dropped).
+ * Errors: E_STATE (no points set), E_ARG, E_DOMAIN, E_NOMEM, E_DEVICE. */
+stkfmm_status stkfmm_run(stkfmm_ctx *ctx, const double *sl_val, const double *dl_val,
+                         double *trg_val, void *hip_stream);
+
+/* stkfmm_set_points followed by stkfmm_run. */
+stkfmm_status stkfmm_evaluate(stkfmm_ctx *ctx, stkfmm_kernel kernel, stkfmm_bc bc,
+                              int64_t n_sl, const double *sl_xyz, const double *sl_val,
+                              int64_t n_dl, const double *dl_xyz, const double *dl_val,
+                              int64_t n_trg, const double *trg_xyz, double *trg_val,
+                              int p, int leaf_cap, void *hip_stream);
+
+/* FP64 direct sum on the GPU of the same kernel summation problem (the
+ * plain O(N_S N_T) definition, Sec. I) at the given targets: the error judge
+ * of the learned mode and a measurement tool.  Open BC only; same layouts
+ * and conventions as stkfmm_evaluate; pairs with r = 0 contribute nothing.
+ * Errors: E_ARG, E_UNSUPPORTED, E_DEVICE. */
+stkfmm_status stkfmm_direct(stkfmm_ctx *ctx, stkfmm_kernel kernel,
+                            int64_t n_sl, const double *sl_xyz, const double *sl_val,
+                            int64_t n_dl, const double *dl_xyz, const double *dl_val,
+                            int64_t n_trg, const double *trg_xyz, double *trg_val,
+                            void *hip_stream);
+
+/* Value widths of a kernel (tab:implement).  k_dl is 0 for kernels without
+ * DL sources.  Pure host function.  Errors: E_ARG (NULL output, bad kernel). */
+stkfmm_status stkfmm_kernel_dims(stkfmm_kernel kernel, int *k_sl, int *k_dl, int *k_trg);
+
+/* Options (strings):  "precision" = "fp32" | "split_bf16"  (M2L arithmetic),
+ * "svd_tol" = relative truncation of the check-to-equivalent pseudo-inverse
+ * (default 1e-7).  Errors: E_ARG. */
+stkfmm_status stkfmm_set_option(stkfmm_ctx *ctx, const char *key, const char *value);
+
+/* Timings of the last set_points (t_tree_ms) and run (t_run_ms, device event
+ * time).  stage_ms[16] (may be NULL) receives per-stage device times of the
+ * last run in the order: 0 pack, 1 S2M, 2 UC2UE+M2M, 3 M2L, 4 S2L(X),
+ * 5 L2L+DC2DE, 6 L2T+M2T, 7 P2P, 8 combine, 9 periodic; others 0. */
+stkfmm_status stkfmm_get_timings(const stkfmm_ctx *ctx, double *t_tree_ms, double *t_run_ms,
+                                 double stage_ms[16]);
+
+/* Plan statistics of the last set_points; stats[16] receives:
+ * 0 boxes, 1 leaves, 2 depth, 3 P2P pairs (sum over target leaves of
+ * n_trg * sum of U-list source counts), 4 V-list pairs, 5 W-list pairs,
+ * 6 X-list pairs, 7 M (points per surface), 8 n_trg, 9 n_sl, 10 n_dl,
+ * 11 U-list entries; others 0.  Errors: E_ARG, E_STATE. */
+stkfmm_status stkfmm_get_stats(const stkfmm_ctx *ctx, int64_t stats[16]);
+
+/* Last error message of the context (never NULL; "" if none). */
+const char *stkfmm_last_error(const stkfmm_ctx *ctx);
+
+/* Release the context and its device memory.  NULL is ignored. */
+void stkfmm_destroy(stkfmm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STKFMM_H */

@@ -1,0 +1,172 @@
+"""MI355X kernel aggregated FMM: Python binding of ``libstkfmm.so``.
+
+Argument marshalling only: every step of the evaluation pass runs in the
+HIP library behind the C ABI declared in ``include/stkfmm.h``.  PyTorch
+provides device memory (tensors) and the current HIP stream.  There is no
+fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+KERNELS = {"LapPGrad": 0, "Stokeslet": 1, "RPY": 2, "PVel": 3, "Traction": 4}
+BCS = {"open": 0, "PX": 1, "PXY": 2, "PXYZ": 3}
+STATUS = {0: "OK", 1: "E_ARG", 2: "E_DOMAIN", 3: "E_UNSUPPORTED", 4: "E_NOMEM", 5: "E_DEVICE",
+          6: "E_ACCURACY", 7: "E_STATE"}
+STAGES = ["pack", "s2m", "upward", "m2l", "s2l", "downward", "l2t", "p2p", "combine"]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstkfmm.so")
+
+# exported C symbols (kept in step with include/stkfmm.h)
+SYMBOLS = ["stkfmm_setup", "stkfmm_set_points", "stkfmm_run", "stkfmm_evaluate", "stkfmm_direct",
+           "stkfmm_kernel_dims", "stkfmm_set_option", "stkfmm_get_timings", "stkfmm_get_stats",
+           "stkfmm_last_error", "stkfmm_destroy"]
+
+_lib = None
+
+
+class StkfmmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = STATUS.get(status, status)
+
+
+def lib():
+    """Load the HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libstkfmm.so is not built: run __graft_entry__.build() "
+                           "or python paper_2010_15155_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, ci, cd = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    L.stkfmm_setup.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(cd), cd, ci, ctypes.c_uint]
+    L.stkfmm_set_points.argtypes = [vp, ci, ci, i64, vp, i64, vp, i64, vp, ci, ci, vp]
+    L.stkfmm_run.argtypes = [vp, vp, vp, vp, vp]
+    L.stkfmm_evaluate.argtypes = [vp, ci, ci, i64, vp, vp, i64, vp, vp, i64, vp, vp, ci, ci, vp]
+    L.stkfmm_direct.argtypes = [vp, ci, i64, vp, vp, i64, vp, vp, i64, vp, vp, vp]
+    L.stkfmm_kernel_dims.argtypes = [ci, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    L.stkfmm_set_option.argtypes = [vp, ctypes.c_char_p, ctypes.c_char_p]
+    L.stkfmm_get_timings.argtypes = [vp, ctypes.POINTER(cd), ctypes.POINTER(cd), ctypes.POINTER(cd)]
+    L.stkfmm_get_stats.argtypes = [vp, ctypes.POINTER(i64)]
+    L.stkfmm_last_error.argtypes = [vp]
+    L.stkfmm_last_error.restype = ctypes.c_char_p
+    L.stkfmm_destroy.argtypes = [vp]
+    L.stkfmm_destroy.restype = None
+    _lib = L
+    return L
+
+
+def kernel_dims(kernel):
+    k_sl, k_dl, k_t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    st = lib().stkfmm_kernel_dims(KERNELS[kernel], ctypes.byref(k_sl), ctypes.byref(k_dl), ctypes.byref(k_t))
+    if st != 0:
+        raise StkfmmError(st, "kernel_dims")
+    return k_sl.value, k_dl.value, k_t.value
+
+
+def _ptr(t, n_cols, name):
+    """Device pointer of a contiguous float64 CUDA tensor (or None)."""
+    if t is None:
+        return None, 0
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("%s must be a contiguous float64 tensor on the GPU" % name)
+    if n_cols and (t.dim() != 2 or t.shape[1] != n_cols) and not (n_cols == 1 and t.dim() == 1):
+        raise ValueError("%s must have shape [n, %d]" % (name, n_cols))
+    return ctypes.c_void_p(t.data_ptr()), t.shape[0]
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class FMM:
+    """One library context (stkfmm_setup ... stkfmm_destroy)."""
+
+    def __init__(self, origin=(0.0, 0.0, 0.0), box_len=1.0, device=0):
+        self._h = ctypes.c_void_p()
+        org = (ctypes.c_double * 3)(*origin)
+        st = lib().stkfmm_setup(ctypes.byref(self._h), org, float(box_len), int(device), 0)
+        if st != 0:
+            raise StkfmmError(st, "stkfmm_setup")
+        self.device = device
+        self.kernel = None
+        self.n_trg = 0
+
+    def _check(self, st, what):
+        if st != 0:
+            raise StkfmmError(st, "%s: %s" % (what, lib().stkfmm_last_error(self._h).decode()))
+
+    def close(self):
+        if self._h:
+            lib().stkfmm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, key, value):
+        self._check(lib().stkfmm_set_option(self._h, key.encode(), str(value).encode()), "set_option")
+
+    def set_points(self, kernel, sl_xyz=None, dl_xyz=None, trg_xyz=None, p=10, leaf_cap=2000, bc="open"):
+        s, ns = _ptr(sl_xyz, 3, "sl_xyz")
+        d, nd = _ptr(dl_xyz, 3, "dl_xyz")
+        t, nt = _ptr(trg_xyz, 3, "trg_xyz")
+        st = lib().stkfmm_set_points(self._h, KERNELS[kernel], BCS[bc], ns, s, nd, d, nt, t,
+                                     int(p), int(leaf_cap), _stream())
+        self._check(st, "set_points")
+        self.kernel = kernel
+        self.n_trg = nt
+
+    def run(self, sl_val=None, dl_val=None, out=None):
+        import torch
+        k_sl, k_dl, k_t = kernel_dims(self.kernel)
+        s, _ = _ptr(sl_val, k_sl, "sl_val")
+        d, _ = _ptr(dl_val, k_dl, "dl_val")
+        if out is None:
+            out = torch.empty((self.n_trg, k_t), dtype=torch.float64, device="cuda:%d" % self.device)
+        o, _ = _ptr(out, k_t, "trg_val")
+        self._check(lib().stkfmm_run(self._h, s, d, o, _stream()), "run")
+        return out
+
+    def evaluate(self, kernel, sl_xyz=None, sl_val=None, dl_xyz=None, dl_val=None, trg_xyz=None,
+                 p=10, leaf_cap=2000, bc="open"):
+        self.set_points(kernel, sl_xyz, dl_xyz, trg_xyz, p, leaf_cap, bc)
+        return self.run(sl_val, dl_val)
+
+    def direct(self, kernel, sl_xyz=None, sl_val=None, dl_xyz=None, dl_val=None, trg_xyz=None):
+        """FP64 direct sum on the GPU (error judge)."""
+        import torch
+        k_sl, k_dl, k_t = kernel_dims(kernel)
+        s, ns = _ptr(sl_xyz, 3, "sl_xyz")
+        sv, _ = _ptr(sl_val, k_sl, "sl_val")
+        d, nd = _ptr(dl_xyz, 3, "dl_xyz")
+        dv, _ = _ptr(dl_val, k_dl, "dl_val")
+        t, nt = _ptr(trg_xyz, 3, "trg_xyz")
+        out = torch.empty((nt, k_t), dtype=torch.float64, device="cuda:%d" % self.device)
+        o, _ = _ptr(out, k_t, "trg_val")
+        st = lib().stkfmm_direct(self._h, KERNELS[kernel], ns, s, sv, nd, d, dv, nt, t, o, _stream())
+        self._check(st, "direct")
+        return out
+
+    def timings(self):
+        tt, tr = ctypes.c_double(), ctypes.c_double()
+        stg = (ctypes.c_double * 16)()
+        self._check(lib().stkfmm_get_timings(self._h, ctypes.byref(tt), ctypes.byref(tr), stg), "timings")
+        return {"t_tree_ms": tt.value, "t_run_ms": tr.value,
+                "stages_ms": {k: stg[i] for i, k in enumerate(STAGES)}}
+
+    def stats(self):
+        a = (ctypes.c_int64 * 16)()
+        self._check(lib().stkfmm_get_stats(self._h, a), "stats")
+        names = ["boxes", "leaves", "depth", "p2p_pairs", "v_pairs", "w_pairs", "x_pairs", "M",
+                 "n_trg", "n_sl", "n_dl", "u_entries"]
+        return {n: int(a[i]) for i, n in enumerate(names)}

@@ -1,0 +1,983 @@
+// C ABI and evaluation engine of the MI355X kernel aggregated FMM.
+//
+// set_points: host octree + lists (t_tree), operators for p (cached), plan
+//             arrays uploaded in one arena, points packed into leaf order.
+// run:        the evaluation pass (t_run) on two streams:
+//   stream A  pack values -> S2M -> [M2M -> UC2UE] per level (upward) ->
+//             S2L (X) -> M2L (offset-grouped MFMA GEMM + reduce) ->
+//             [periodic] -> [L2L -> DC2DE] per level (downward) -> L2T + M2T
+//   stream B  P2P over U lists (independent of the far field)
+//   join      combine near + far, un-permute into the caller's order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/stkfmm.h"
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace kafmm {
+
+static const KernelInfo kInfo[kNumKernels] = {
+    // k_sl k_dl k_trg ncomp rec_sl rec_dl kt_acc
+    {1, 3, 4, 1, 8, 12, 4},    // LapPGrad
+    {3, 0, 3, 4, 12, 0, 3},    // Stokeslet
+    {4, 0, 6, 4, 12, 0, 6},    // RPY
+    {4, 9, 4, 4, 12, 12, 4},   // PVel
+    {4, 9, 9, 4, 12, 12, 6},   // Traction
+};
+const KernelInfo &kernel_info(int k) { return kInfo[k]; }
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct DevMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DevMem() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t n) {
+        if (n <= bytes) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, std::max<size_t>(n, 256));
+        if (e == hipSuccess) bytes = std::max<size_t>(n, 256);
+        else p = nullptr;
+        return e;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Host staging area for plan arrays: one device allocation, one copy.
+struct Arena {
+    std::vector<char> host;
+    template <class T> size_t add(const std::vector<T> &v) {
+        size_t off = (host.size() + 255) / 256 * 256;
+        host.resize(off + std::max<size_t>(v.size() * sizeof(T), 1));
+        if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
+        return off;
+    }
+};
+
+struct DeviceOps {
+    int p = 0, M = 0, Mp = 0, rank = 0;
+    bool periodic = false;
+    DevMem grid, m2m, l2l, m2l, up1, up2, dn1, dn2, tm2l;
+};
+
+// A batch of translations that share the grouped GEMM and one reduce launch.
+struct Batch {
+    int ntiles = 0, ntasks = 0;
+    size_t tiles = 0, bcol = 0, ycol = 0, rdst = 0, roff = 0, rpair = 0, rscale = 0, rdelta = 0;
+    int npairs = 0;
+    int accumulate = 0;
+};
+
+struct PinvLevel {
+    int ncol = 0;
+    size_t bidx = 0, didx = 0, cidx = 0, cscale = 0;
+};
+
+struct Pair {
+    int src, dst, op;
+    float delta[3];
+    double scale;
+};
+
+}  // namespace
+}  // namespace kafmm
+
+using namespace kafmm;
+
+struct stkfmm_ctx {
+    int device = 0;
+    double origin[3] = {0, 0, 0};
+    double box_len = 1.0;
+    std::string err;
+    double svd_tol = 1e-7;
+    int precision = 0;          // 0 fp32, 1 split_bf16
+    std::map<int, std::unique_ptr<DeviceOps>> ops_cache;   // key: p*2 + periodic
+    hipStream_t side = nullptr; // P2P stream
+    hipEvent_t ev[24] = {};
+    // plan
+    bool planned = false;
+    int kernel = 0, bc = 0, p = 0, leaf_cap = 0;
+    int64_t n_sl = 0, n_dl = 0, n_trg = 0;
+    Tree tree;
+    DeviceOps *ops = nullptr;
+    DevMem arena, sl_rec, dl_rec, trg_rec, up_dens, dn_dens, up_chk, dn_chk, Ybuf, tmp64, near_out, far_out,
+        partial;
+    size_t a_perm_sl = 0, a_perm_dl = 0, a_perm_trg = 0, a_geom = 0, a_box_sl = 0, a_box_dl = 0, a_has_local = 0,
+           a_u_off = 0, a_u_ent = 0, a_w_off = 0, a_w_ent = 0, a_chunks = 0, a_s2m_dst = 0, a_s2m_off = 0,
+           a_s2m_list = 0, a_s2l_dst = 0, a_s2l_off = 0, a_s2l_list = 0;
+    int nchunks = 0, n_s2m = 0, n_s2l = 0, nbox = 0;
+    Batch m2l;
+    std::vector<Batch> m2m, l2l;            // by level (parent level / child level)
+    std::vector<PinvLevel> upinv, dnpinv;   // by level
+    int lmin_up = 0, lmin_dn = 0;
+    size_t ybuf_floats = 0, tmp_doubles = 0;
+    double t_tree_ms = 0, t_run_ms = 0, stage_ms[16] = {};
+};
+
+namespace {
+
+stkfmm_status fail(stkfmm_ctx *c, stkfmm_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                              \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? STKFMM_E_NOMEM : STKFMM_E_DEVICE,              \
+                        std::string("HIP error in ") + #expr + ": " + hipGetErrorString(e_));           \
+    } while (0)
+
+bool kernel_ok(int k) { return k >= 0 && k < kNumKernels; }
+
+stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, DeviceOps **out) {
+    int key = p * 2 + (periodic ? 1 : 0);
+    auto it = c->ops_cache.find(key);
+    if (it != c->ops_cache.end()) {
+        *out = it->second.get();
+        return STKFMM_OK;
+    }
+    Operators h;
+    std::string e = build_operators(p, c->svd_tol, periodic, h);
+    if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
+    auto d = std::make_unique<DeviceOps>();
+    d->p = p;
+    d->M = h.M;
+    d->Mp = h.Mp;
+    d->rank = h.rank;
+    d->periodic = periodic;
+    std::vector<float> g(h.grid.begin(), h.grid.end());
+    auto up = [&](DevMem &m, const void *src, size_t bytes) -> hipError_t {
+        hipError_t er = m.ensure(bytes);
+        if (er != hipSuccess) return er;
+        return hipMemcpy(m.p, src, bytes, hipMemcpyHostToDevice);
+    };
+    HIP_TRY(c, up(d->grid, g.data(), g.size() * sizeof(float)));
+    HIP_TRY(c, up(d->m2m, h.m2m.data(), h.m2m.size() * sizeof(float)));
+    HIP_TRY(c, up(d->l2l, h.l2l.data(), h.l2l.size() * sizeof(float)));
+    HIP_TRY(c, up(d->m2l, h.m2l.data(), h.m2l.size() * sizeof(float)));
+    // UC2UE = P1 P2 ; DC2DE = P2^T P1^T
+    const int M = h.M, r = h.rank;
+    std::vector<double> t1(size_t(r) * M), t2(size_t(M) * r);
+    for (int i = 0; i < M; ++i)
+        for (int k = 0; k < r; ++k) t1[size_t(k) * M + i] = h.up1[size_t(i) * r + k];   // P1^T [r][M]
+    for (int k = 0; k < r; ++k)
+        for (int j = 0; j < M; ++j) t2[size_t(j) * r + k] = h.up2[size_t(k) * M + j];   // P2^T [M][r]
+    HIP_TRY(c, up(d->up1, h.up1.data(), h.up1.size() * sizeof(double)));
+    HIP_TRY(c, up(d->up2, h.up2.data(), h.up2.size() * sizeof(double)));
+    HIP_TRY(c, up(d->dn1, t1.data(), t1.size() * sizeof(double)));
+    HIP_TRY(c, up(d->dn2, t2.data(), t2.size() * sizeof(double)));
+    if (periodic) HIP_TRY(c, up(d->tm2l, h.t_m2l.data(), h.t_m2l.size() * sizeof(double)));
+    *out = d.get();
+    c->ops_cache[key] = std::move(d);
+    return STKFMM_OK;
+}
+
+// Group translation pairs by operator for the GEMM and by destination for the reduce.
+Batch make_batch(Arena &ar, std::vector<Pair> pairs, int nc, int accumulate, size_t &ybuf_floats, int Mp) {
+    Batch b;
+    b.accumulate = accumulate;
+    std::stable_sort(pairs.begin(), pairs.end(), [](const Pair &x, const Pair &y) { return x.op < y.op; });
+    b.npairs = int(pairs.size());
+    std::vector<int> bcol, ycol;
+    std::vector<int4> tiles;
+    for (size_t i = 0; i < pairs.size();) {
+        size_t j = i;
+        while (j < pairs.size() && pairs[j].op == pairs[i].op) ++j;
+        int c0 = int(bcol.size());
+        for (size_t k = i; k < j; ++k)
+            for (int c = 0; c < nc; ++c) {
+                bcol.push_back(pairs[k].src * nc + c);
+                ycol.push_back(int(k) * nc + c);
+            }
+        int ncols = int(bcol.size()) - c0;
+        for (int t = 0; t < ncols; t += 128) tiles.push_back(make_int4(pairs[i].op, c0 + t, std::min(128, ncols - t), 0));
+        i = j;
+    }
+    b.ntiles = int(tiles.size());
+    // reduce by destination, pairs in index order
+    std::vector<int> order(pairs.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = int(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return pairs[x].dst < pairs[y].dst; });
+    std::vector<int> rdst, roff, rpair;
+    std::vector<double> rscale;
+    std::vector<float> rdelta;
+    for (size_t i = 0; i < order.size();) {
+        size_t j = i;
+        while (j < order.size() && pairs[order[j]].dst == pairs[order[i]].dst) ++j;
+        rdst.push_back(pairs[order[i]].dst);
+        roff.push_back(int(rpair.size()));
+        for (size_t k = i; k < j; ++k) {
+            const Pair &pr = pairs[order[k]];
+            rpair.push_back(order[k]);
+            rscale.push_back(pr.scale);
+            rdelta.insert(rdelta.end(), pr.delta, pr.delta + 3);
+        }
+        i = j;
+    }
+    roff.push_back(int(rpair.size()));
+    b.ntasks = int(rdst.size());
+    b.tiles = ar.add(tiles);
+    b.bcol = ar.add(bcol);
+    b.ycol = ar.add(ycol);
+    b.rdst = ar.add(rdst);
+    b.roff = ar.add(roff);
+    b.rpair = ar.add(rpair);
+    b.rscale = ar.add(rscale);
+    b.rdelta = ar.add(rdelta);
+    ybuf_floats = std::max(ybuf_floats, size_t(b.npairs) * nc * Mp);
+    return b;
+}
+
+template <class T> T *at(stkfmm_ctx *c, size_t off) { return reinterpret_cast<T *>(c->arena.as<char>() + off); }
+
+stkfmm_status run_batch(stkfmm_ctx *c, const Batch &b, const float *ops, const float *X, double *chk,
+                        hipStream_t s) {
+    if (b.npairs == 0) return STKFMM_OK;
+    const DeviceOps &o = *c->ops;
+    const int nc = kernel_info(c->kernel).ncomp;
+    GemmArgs g;
+    g.tiles = at<int4>(c, b.tiles);
+    g.ops = ops;
+    g.X = X;
+    g.Y = c->Ybuf.as<float>();
+    g.bcol = at<int>(c, b.bcol);
+    g.ycol = at<int>(c, b.ycol);
+    g.Mp = o.Mp;
+    HIP_TRY(c, launch_gemm_f32(b.ntiles, o.Mp, g, s));
+    ReduceArgs r;
+    r.dst = at<int>(c, b.rdst);
+    r.off = at<int>(c, b.roff);
+    r.pair = at<int>(c, b.rpair);
+    r.scale = at<double>(c, b.rscale);
+    r.delta = at<float>(c, b.rdelta);
+    r.Y = c->Ybuf.as<float>();
+    r.chk = chk;
+    r.M = o.M;
+    r.Mp = o.Mp;
+    r.ncomp = nc;
+    r.accumulate = b.accumulate;
+    HIP_TRY(c, launch_reduce(b.ntasks, r, s));
+    return STKFMM_OK;
+}
+
+// dens(cols) = scale * F1 (F2 chk(cols)) in FP64 (the check-to-equivalent pseudo-inverse)
+stkfmm_status run_pinv(stkfmm_ctx *c, const PinvLevel &pl, const double *F2, const double *F1, const double *chk,
+                       float *dens, hipStream_t s) {
+    if (pl.ncol == 0) return STKFMM_OK;
+    const DeviceOps &o = *c->ops;
+    Gemm64Args a;
+    a.A = F2; a.R = o.rank; a.K = o.M; a.lda = o.M;
+    a.B = chk; a.bidx = at<int>(c, pl.bidx); a.ldb = o.M;
+    a.cidx = at<int>(c, pl.didx); a.cscale = nullptr; a.ldc = o.rank;
+    a.ncol = pl.ncol;
+    HIP_TRY(c, launch_gemm_f64(a, c->tmp64.as<double>(), s));
+    Gemm64Args b;
+    b.A = F1; b.R = o.M; b.K = o.rank; b.lda = o.rank;
+    b.B = c->tmp64.as<double>(); b.bidx = at<int>(c, pl.didx); b.ldb = o.rank;
+    b.cidx = at<int>(c, pl.cidx); b.cscale = at<double>(c, pl.cscale); b.ldc = o.Mp;
+    b.ncol = pl.ncol;
+    HIP_TRY(c, launch_gemm_f64_to_f32(b, dens, s));
+    return STKFMM_OK;
+}
+
+stkfmm_status validate_points(stkfmm_ctx *c, const std::vector<double> &h, int64_t n, bool periodic,
+                              const char *what) {
+    for (int64_t i = 0; i < 3 * n; ++i) {
+        if (!std::isfinite(h[i])) return fail(c, STKFMM_E_ARG, std::string(what) + ": non-finite coordinate");
+        if (!periodic) {
+            double u = (h[i] - c->origin[i % 3]) / c->box_len;
+            if (!(u >= 0.0 && u < 1.0))
+                return fail(c, STKFMM_E_DOMAIN, std::string(what) + ": point outside [origin, origin+box_len)");
+        }
+    }
+    return STKFMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+stkfmm_status stkfmm_kernel_dims(stkfmm_kernel k, int *k_sl, int *k_dl, int *k_trg) {
+    if (!kernel_ok(int(k)) || !k_sl || !k_dl || !k_trg) return STKFMM_E_ARG;
+    *k_sl = kInfo[k].k_sl;
+    *k_dl = kInfo[k].k_dl;
+    *k_trg = kInfo[k].k_trg;
+    return STKFMM_OK;
+}
+
+stkfmm_status stkfmm_setup(stkfmm_ctx **out, const double origin[3], double box_len, int device, unsigned flags) {
+    if (!out) return STKFMM_E_ARG;
+    *out = nullptr;
+    if (!origin || !(box_len > 0) || !std::isfinite(box_len) || flags != 0) return STKFMM_E_ARG;
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(origin[k])) return STKFMM_E_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return STKFMM_E_DEVICE;
+    auto *c = new (std::nothrow) stkfmm_ctx();
+    if (!c) return STKFMM_E_NOMEM;
+    c->device = device;
+    std::memcpy(c->origin, origin, sizeof(c->origin));
+    c->box_len = box_len;
+    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return STKFMM_E_DEVICE;
+    }
+    for (auto &e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            delete c;
+            return STKFMM_E_DEVICE;
+        }
+    *out = c;
+    return STKFMM_OK;
+}
+
+void stkfmm_destroy(stkfmm_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    delete c;
+}
+
+const char *stkfmm_last_error(const stkfmm_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+stkfmm_status stkfmm_set_option(stkfmm_ctx *c, const char *key, const char *value) {
+    if (!c || !key || !value) return STKFMM_E_ARG;
+    std::string k(key), v(value);
+    if (k == "precision") {
+        if (v == "fp32") c->precision = 0;
+        else if (v == "split_bf16") c->precision = 1;
+        else return fail(c, STKFMM_E_ARG, "precision must be fp32 or split_bf16");
+        return STKFMM_OK;
+    }
+    if (k == "svd_tol") {
+        char *end = nullptr;
+        double t = std::strtod(value, &end);
+        if (!end || *end || !(t > 0) || !(t < 1)) return fail(c, STKFMM_E_ARG, "svd_tol must lie in (0, 1)");
+        if (t != c->svd_tol) c->ops_cache.clear();
+        c->svd_tol = t;
+        c->planned = false;
+        return STKFMM_OK;
+    }
+    return fail(c, STKFMM_E_ARG, "unknown option " + k);
+}
+
+stkfmm_status stkfmm_get_timings(const stkfmm_ctx *c, double *t_tree, double *t_run, double stage_ms[16]) {
+    if (!c) return STKFMM_E_ARG;
+    if (t_tree) *t_tree = c->t_tree_ms;
+    if (t_run) *t_run = c->t_run_ms;
+    if (stage_ms) std::memcpy(stage_ms, c->stage_ms, sizeof(c->stage_ms));
+    return STKFMM_OK;
+}
+
+stkfmm_status stkfmm_get_stats(const stkfmm_ctx *c, int64_t st[16]) {
+    if (!c || !st) return STKFMM_E_ARG;
+    if (!c->planned) return STKFMM_E_STATE;
+    std::memset(st, 0, 16 * sizeof(int64_t));
+    const Tree &t = c->tree;
+    st[0] = int64_t(t.boxes.size());
+    st[1] = int64_t(t.leaves.size());
+    st[2] = t.depth;
+    st[3] = t.p2p_pairs;
+    st[4] = int64_t(t.v.size());
+    st[5] = int64_t(t.w.size());
+    st[6] = int64_t(t.x.size());
+    st[7] = c->ops ? c->ops->M : 0;
+    st[8] = c->n_trg;
+    st[9] = c->n_sl;
+    st[10] = c->n_dl;
+    st[11] = int64_t(t.u.size());
+    return STKFMM_OK;
+}
+
+stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc bc, int64_t n_sl,
+                                const double *sl_xyz, int64_t n_dl, const double *dl_xyz, int64_t n_trg,
+                                const double *trg_xyz, int p, int leaf_cap, void *stream) {
+    if (!c) return STKFMM_E_ARG;
+    c->planned = false;
+    if (!kernel_ok(int(kernel))) return fail(c, STKFMM_E_ARG, "unknown kernel");
+    const KernelInfo &ki = kInfo[kernel];
+    if (n_sl < 0 || n_dl < 0 || n_trg < 0) return fail(c, STKFMM_E_ARG, "negative size");
+    if ((n_sl > 0 && !sl_xyz) || (n_dl > 0 && !dl_xyz) || (n_trg > 0 && !trg_xyz))
+        return fail(c, STKFMM_E_ARG, "NULL point array");
+    if (n_dl > 0 && ki.k_dl == 0) return fail(c, STKFMM_E_ARG, "kernel has no double-layer sources");
+    if (n_sl > INT32_MAX / 2 || n_dl > INT32_MAX / 2 || n_trg > INT32_MAX / 2)
+        return fail(c, STKFMM_E_ARG, "too many points");
+    if (p < 2 || p > 16) return fail(c, STKFMM_E_ARG, "p must lie in [2, 16]");
+    if (leaf_cap < 1) return fail(c, STKFMM_E_ARG, "leaf_cap must be >= 1");
+    if (bc != STKFMM_BC_OPEN && bc != STKFMM_BC_PXYZ)
+        return fail(c, STKFMM_E_UNSUPPORTED, "only open and triply periodic boundaries are implemented");
+    if (bc == STKFMM_BC_PXYZ && kernel != STKFMM_LAP_PGRAD)
+        return fail(c, STKFMM_E_UNSUPPORTED, "triply periodic boundary is implemented for LAP_PGRAD");
+    const bool periodic = bc == STKFMM_BC_PXYZ;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(c, hipSetDevice(c->device));
+    auto t0 = std::chrono::steady_clock::now();
+    // host copies of the coordinates (normalised to the unit box, wrapped if periodic)
+    std::vector<double> h[3];
+    const double *src[3] = {sl_xyz, dl_xyz, trg_xyz};
+    const int64_t cnt[3] = {n_sl, n_dl, n_trg};
+    for (int k = 0; k < 3; ++k) {
+        h[k].resize(3 * cnt[k]);
+        if (cnt[k] > 0)
+            HIP_TRY(c, hipMemcpyAsync(h[k].data(), src[k], 3 * cnt[k] * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    const char *names[3] = {"sl_xyz", "dl_xyz", "trg_xyz"};
+    for (int k = 0; k < 3; ++k) {
+        stkfmm_status st = validate_points(c, h[k], cnt[k], periodic, names[k]);
+        if (st != STKFMM_OK) return st;
+        for (int64_t i = 0; i < 3 * cnt[k]; ++i) {
+            double u = (h[k][i] - c->origin[i % 3]) / c->box_len;
+            if (periodic) {
+                u -= std::floor(u);
+                if (u >= 1.0) u = 0.0;
+            }
+            h[k][i] = u;
+        }
+    }
+    Tree &t = c->tree;
+    std::string e = build_tree(h[0].data(), n_sl, h[1].data(), n_dl, h[2].data(), n_trg, leaf_cap, periodic, t);
+    if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
+    DeviceOps *ops = nullptr;
+    stkfmm_status st = get_ops(c, p, periodic, &ops);
+    if (st != STKFMM_OK) return st;
+    c->ops = ops;
+    c->kernel = kernel;
+    c->bc = bc;
+    c->p = p;
+    c->leaf_cap = leaf_cap;
+    c->n_sl = n_sl;
+    c->n_dl = n_dl;
+    c->n_trg = n_trg;
+    const int nb = int(t.boxes.size());
+    c->nbox = nb;
+    const int nc = ki.ncomp, M = ops->M, Mp = ops->Mp;
+
+    // ---------------------------------------------------------------- plan arrays
+    Arena ar;
+    c->a_perm_sl = ar.add(t.perm_sl);
+    c->a_perm_dl = ar.add(t.perm_dl);
+    c->a_perm_trg = ar.add(t.perm_trg);
+    std::vector<double4> geom(nb);
+    std::vector<int2> bsl(nb), bdl(nb);
+    for (int b = 0; b < nb; ++b) {
+        const Box &B = t.boxes[b];
+        double hh = 1.0 / double(1 << B.level);
+        geom[b] = make_double4((B.anchor[0] + 0.5) * hh, (B.anchor[1] + 0.5) * hh, (B.anchor[2] + 0.5) * hh, hh);
+        bsl[b] = make_int2(int(B.sl[0]), int(B.sl[1]));
+        bdl[b] = make_int2(int(B.dl[0]), int(B.dl[1]));
+    }
+    c->a_geom = ar.add(geom);
+    c->a_box_sl = ar.add(bsl);
+    c->a_box_dl = ar.add(bdl);
+    c->a_has_local = ar.add(t.has_local);
+    std::vector<int2> uent(t.u.size()), went(t.w.size()), xent(t.x.size());
+    for (size_t i = 0; i < t.u.size(); ++i) uent[i] = make_int2(t.u[i].box, pack_shift(t.u[i].shift));
+    for (size_t i = 0; i < t.w.size(); ++i) went[i] = make_int2(t.w[i].box, pack_shift(t.w[i].shift));
+    for (size_t i = 0; i < t.x.size(); ++i) xent[i] = make_int2(t.x[i].box, pack_shift(t.x[i].shift));
+    c->a_u_off = ar.add(t.u_off);
+    c->a_u_ent = ar.add(uent);
+    c->a_w_off = ar.add(t.w_off);
+    c->a_w_ent = ar.add(went);
+    std::vector<int4> chunks;
+    for (int b : t.leaves) {
+        const Box &B = t.boxes[b];
+        for (int64_t t0i = B.trg[0]; t0i < B.trg[1]; t0i += 256)
+            chunks.push_back(make_int4(b, int(t0i), int(std::min<int64_t>(t0i + 256, B.trg[1])), 0));
+    }
+    c->nchunks = int(chunks.size());
+    c->a_chunks = ar.add(chunks);
+    // S2M tasks: every leaf with sources; S2L tasks: every box with an X list
+    std::vector<int> s2m_dst, s2m_off, s2l_dst, s2l_off;
+    std::vector<int2> s2m_list, s2l_list;
+    for (int b : t.leaves) {
+        if (t.boxes[b].nsrc_sub == 0) continue;
+        s2m_dst.push_back(b);
+        s2m_off.push_back(int(s2m_list.size()));
+        s2m_list.push_back(make_int2(b, kZeroShift));
+    }
+    s2m_off.push_back(int(s2m_list.size()));
+    for (int b = 0; b < nb; ++b) {
+        if (t.x_off[b + 1] == t.x_off[b] || !t.has_local[b]) continue;
+        s2l_dst.push_back(b);
+        s2l_off.push_back(int(s2l_list.size()));
+        for (int i = t.x_off[b]; i < t.x_off[b + 1]; ++i) s2l_list.push_back(xent[i]);
+    }
+    s2l_off.push_back(int(s2l_list.size()));
+    c->n_s2m = int(s2m_dst.size());
+    c->n_s2l = int(s2l_dst.size());
+    c->a_s2m_dst = ar.add(s2m_dst);
+    c->a_s2m_off = ar.add(s2m_off);
+    c->a_s2m_list = ar.add(s2m_list);
+    c->a_s2l_dst = ar.add(s2l_dst);
+    c->a_s2l_off = ar.add(s2l_off);
+    c->a_s2l_list = ar.add(s2l_list);
+
+    // levels carrying equivalent densities
+    c->lmin_up = periodic ? 0 : 2;
+    c->lmin_dn = periodic ? 0 : 2;
+    c->ybuf_floats = 0;
+    c->tmp_doubles = 0;
+    // M2L: V-list pairs grouped by offset
+    {
+        std::vector<Pair> pairs;
+        for (int b = 0; b < nb; ++b) {
+            if (!t.has_local[b]) continue;
+            const double hb = geom[b].w;
+            for (int i = t.v_off[b]; i < t.v_off[b + 1]; ++i) {
+                Pair pr;
+                pr.src = t.v[i].box;
+                pr.dst = b;
+                int o[3] = {t.v_rel[3 * i], t.v_rel[3 * i + 1], t.v_rel[3 * i + 2]};
+                pr.op = offset_index(o[0], o[1], o[2]);
+                // Psi_B = Psi_A - (c_B - c_A).Phi,  c_A - c_B = o h
+                for (int k = 0; k < 3; ++k) pr.delta[k] = float(-o[k] * hb);
+                pr.scale = 1.0 / hb;
+                pairs.push_back(pr);
+            }
+        }
+        c->m2l = make_batch(ar, pairs, nc, 1, c->ybuf_floats, Mp);
+    }
+    // M2M (by parent level) and L2L (by child level), grouped by octant
+    c->m2m.assign(t.depth + 1, Batch());
+    c->l2l.assign(t.depth + 1, Batch());
+    c->upinv.assign(t.depth + 1, PinvLevel());
+    c->dnpinv.assign(t.depth + 1, PinvLevel());
+    for (int l = 0; l <= t.depth; ++l) {
+        std::vector<Pair> up, dn;
+        std::vector<int> ub, ud, uc, db, dd, dcx;
+        std::vector<double> us, ds;
+        for (int b = t.level_start[l]; b < t.level_start[l + 1]; ++b) {
+            const Box &B = t.boxes[b];
+            const double hb = geom[b].w;
+            if (l >= c->lmin_up && B.nsrc_sub > 0) {
+                for (int o = 0; o < 8 && !B.leaf; ++o) {
+                    int ch = B.child[o];
+                    if (ch < 0 || t.boxes[ch].nsrc_sub == 0) continue;
+                    Pair pr;
+                    pr.src = ch;
+                    pr.dst = b;
+                    pr.op = o;
+                    // Psi_P = Psi_C - (c_P - c_C).Phi
+                    for (int k = 0; k < 3; ++k) pr.delta[k] = float(geom[b].x * 0 + ((&geom[b].x)[k] - (&geom[ch].x)[k]));
+                    pr.scale = 1.0 / hb;
+                    up.push_back(pr);
+                }
+                for (int k = 0; k < nc; ++k) {
+                    ub.push_back(b * nc + k);
+                    ud.push_back(int(ud.size()));
+                    uc.push_back(b * nc + k);
+                    us.push_back(hb);
+                }
+            }
+            if (l >= c->lmin_dn && t.has_local[b]) {
+                if (B.parent >= 0 && t.has_local[B.parent]) {
+                    int o = -1;
+                    for (int k = 0; k < 8; ++k)
+                        if (t.boxes[B.parent].child[k] == b) o = k;
+                    Pair pr;
+                    pr.src = B.parent;
+                    pr.dst = b;
+                    pr.op = o;
+                    // Psi_C = Psi_P - (c_C - c_P).Phi
+                    for (int k = 0; k < 3; ++k) pr.delta[k] = float((&geom[b].x)[k] - (&geom[B.parent].x)[k]);
+                    pr.scale = 1.0 / geom[B.parent].w;
+                    dn.push_back(pr);
+                }
+                for (int k = 0; k < nc; ++k) {
+                    db.push_back(b * nc + k);
+                    dd.push_back(int(dd.size()));
+                    dcx.push_back(b * nc + k);
+                    ds.push_back(hb);
+                }
+            }
+        }
+        c->m2m[l] = make_batch(ar, up, nc, 0, c->ybuf_floats, Mp);
+        c->l2l[l] = make_batch(ar, dn, nc, 1, c->ybuf_floats, Mp);
+        PinvLevel &pu = c->upinv[l];
+        pu.ncol = int(ub.size());
+        pu.bidx = ar.add(ub);
+        pu.didx = ar.add(ud);
+        pu.cidx = ar.add(uc);
+        pu.cscale = ar.add(us);
+        PinvLevel &pd = c->dnpinv[l];
+        pd.ncol = int(db.size());
+        pd.bidx = ar.add(db);
+        pd.didx = ar.add(dd);
+        pd.cidx = ar.add(dcx);
+        pd.cscale = ar.add(ds);
+        c->tmp_doubles = std::max(c->tmp_doubles, size_t(std::max(pu.ncol, pd.ncol)) * ops->rank);
+    }
+    HIP_TRY(c, c->arena.ensure(ar.host.size()));
+    HIP_TRY(c, hipMemcpyAsync(c->arena.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice, s));
+
+    // ---------------------------------------------------------------- work buffers
+    HIP_TRY(c, c->sl_rec.ensure(size_t(std::max<int64_t>(n_sl, 1)) * ki.rec_sl * sizeof(float)));
+    HIP_TRY(c, c->dl_rec.ensure(size_t(std::max<int64_t>(n_dl, 1)) * std::max(ki.rec_dl, 1) * sizeof(float)));
+    HIP_TRY(c, c->trg_rec.ensure(size_t(std::max<int64_t>(n_trg, 1)) * 8 * sizeof(float)));
+    HIP_TRY(c, c->up_dens.ensure(size_t(nb) * nc * Mp * sizeof(float)));
+    HIP_TRY(c, c->dn_dens.ensure(size_t(nb) * nc * Mp * sizeof(float)));
+    HIP_TRY(c, c->up_chk.ensure(size_t(nb) * nc * M * sizeof(double)));
+    HIP_TRY(c, c->dn_chk.ensure(size_t(nb) * nc * M * sizeof(double)));
+    HIP_TRY(c, c->Ybuf.ensure(std::max<size_t>(c->ybuf_floats, 1) * sizeof(float)));
+    HIP_TRY(c, c->tmp64.ensure(std::max<size_t>(c->tmp_doubles, 1) * sizeof(double)));
+    HIP_TRY(c, c->near_out.ensure(size_t(std::max<int64_t>(n_trg, 1)) * ki.kt_acc * sizeof(double)));
+    HIP_TRY(c, c->far_out.ensure(size_t(std::max<int64_t>(n_trg, 1)) * ki.kt_acc * sizeof(double)));
+    HIP_TRY(c, c->partial.ensure(4096 * sizeof(double)));
+    // densities: padding rows stay zero (the GEMM reads Mp rows)
+    HIP_TRY(c, launch_fill_f32(c->up_dens.as<float>(), int64_t(nb) * nc * Mp, 0.0f, s));
+    HIP_TRY(c, launch_fill_f32(c->dn_dens.as<float>(), int64_t(nb) * nc * Mp, 0.0f, s));
+    // source/target positions in leaf order
+    const double3 org = make_double3(c->origin[0], c->origin[1], c->origin[2]);
+    const double inv = 1.0 / c->box_len;
+    HIP_TRY(c, launch_pack_sources(n_sl, sl_xyz, nullptr, at<int32_t>(c, c->a_perm_sl), org, inv, -1, ki.rec_sl,
+                                   c->sl_rec.as<float>(), s));
+    HIP_TRY(c, launch_pack_sources(n_dl, dl_xyz, nullptr, at<int32_t>(c, c->a_perm_dl), org, inv, -1,
+                                   std::max(ki.rec_dl, 8), c->dl_rec.as<float>(), s));
+    HIP_TRY(c, launch_pack_targets(n_trg, trg_xyz, at<int32_t>(c, c->a_perm_trg), org, inv, c->trg_rec.as<float>(), s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->t_tree_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    c->planned = true;
+    return STKFMM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int sl_kind(int k) {
+    switch (k) {
+        case kStokeslet: return 0;
+        case kRPY: return 1;
+        case kLapPGrad: return 2;
+        default: return 4;
+    }
+}
+int dl_kind(int k) { return k == kLapPGrad ? 3 : 5; }
+
+CombineMap combine_map(int k, double L) {
+    CombineMap m;
+    for (int i = 0; i < 10; ++i) {
+        m.src[i] = -1;
+        m.scale[i] = 0;
+    }
+    const double c4 = 1.0 / (4.0 * kPi), c8 = 1.0 / (8.0 * kPi);
+    switch (k) {
+        case kStokeslet:
+            for (int i = 0; i < 3; ++i) m.src[i] = i, m.scale[i] = c8 / L;
+            break;
+        case kRPY:
+            for (int i = 0; i < 3; ++i) m.src[i] = i, m.scale[i] = c8 / L;
+            for (int i = 3; i < 6; ++i) m.src[i] = i, m.scale[i] = c8 / (L * L * L);
+            break;
+        case kLapPGrad:
+            m.src[0] = 0, m.scale[0] = c4 / L;
+            for (int i = 1; i < 4; ++i) m.src[i] = i, m.scale[i] = c4 / (L * L);
+            break;
+        case kPVel:
+            m.src[0] = 0, m.scale[0] = c8 / (L * L);
+            for (int i = 1; i < 4; ++i) m.src[i] = i, m.scale[i] = c8 / L;
+            break;
+        case kTraction: {
+            const int sym[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
+            for (int i = 0; i < 9; ++i) m.src[i] = sym[i], m.scale[i] = c4 / (L * L);
+            break;
+        }
+    }
+    return m;
+}
+
+__global__ void pack_values_kernel(int64_t n, const double *__restrict__ val, const int32_t *__restrict__ perm,
+                                   double inv_len, int kind, int rec, float *__restrict__ out) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t j = perm[i];
+    float *o = out + i * rec;
+    switch (kind) {
+        case 0: {
+            const double *v = val + 3 * j;
+            o[6] = float(v[0]); o[7] = float(v[1]); o[8] = float(v[2]);
+            break;
+        }
+        case 1: {
+            const double *v = val + 4 * j;
+            double b = v[3] * inv_len;
+            o[6] = float(v[0]); o[7] = float(v[1]); o[8] = float(v[2]); o[9] = float(b * b);
+            break;
+        }
+        case 2: o[6] = float(val[j]); break;
+        case 3: {
+            const double *v = val + 3 * j;
+            o[6] = float(v[0] * inv_len); o[7] = float(v[1] * inv_len); o[8] = float(v[2] * inv_len);
+            break;
+        }
+        case 4: {
+            const double *v = val + 4 * j;
+            o[6] = float(v[0]); o[7] = float(v[1]); o[8] = float(v[2]); o[9] = float(v[3]);
+            break;
+        }
+        case 5: {
+            const double *D = val + 9 * j;
+            o[6] = float(D[0] * inv_len);
+            o[7] = float(0.5 * (D[1] + D[3]) * inv_len);
+            o[8] = float(0.5 * (D[2] + D[6]) * inv_len);
+            o[9] = float(D[4] * inv_len);
+            o[10] = float(0.5 * (D[5] + D[7]) * inv_len);
+            o[11] = float(D[8] * inv_len);
+            break;
+        }
+    }
+}
+
+// per-block partial sums of q and |q| (net-charge check of periodic problems)
+__global__ void charge_partials(int64_t n, const double *__restrict__ q, double *__restrict__ part) {
+    __shared__ double s0[256], s1[256];
+    double a = 0, b = 0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        a += q[i];
+        b += fabs(q[i]);
+    }
+    s0[threadIdx.x] = a;
+    s1[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) {
+            s0[threadIdx.x] += s0[threadIdx.x + w];
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s0[0];
+        part[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+stkfmm_status stkfmm_run(stkfmm_ctx *c, const double *sl_val, const double *dl_val, double *trg_val,
+                         void *stream) {
+    if (!c) return STKFMM_E_ARG;
+    if (!c->planned) return fail(c, STKFMM_E_STATE, "stkfmm_run before stkfmm_set_points");
+    if ((c->n_sl > 0 && !sl_val) || (c->n_dl > 0 && !dl_val) || (c->n_trg > 0 && !trg_val))
+        return fail(c, STKFMM_E_ARG, "NULL value array");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(c, hipSetDevice(c->device));
+    const KernelInfo &ki = kInfo[c->kernel];
+    const Tree &t = c->tree;
+    const DeviceOps &o = *c->ops;
+    const int nc = ki.ncomp;
+    const bool periodic = c->bc == STKFMM_BC_PXYZ;
+    if (c->n_trg == 0) return STKFMM_OK;
+    if (periodic && c->n_sl > 0) {
+        // zero net charge (tin-foil Ewald convention needs a neutral cell)
+        const int nbk = 256;
+        hipLaunchKernelGGL(charge_partials, dim3(nbk), dim3(256), 0, s, c->n_sl, sl_val, c->partial.as<double>());
+        HIP_TRY(c, hipGetLastError());
+        std::vector<double> hp(2 * nbk);
+        HIP_TRY(c, hipMemcpyAsync(hp.data(), c->partial.p, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        double q = 0, qa = 0;
+        for (int i = 0; i < nbk; ++i) q += hp[2 * i], qa += hp[2 * i + 1];
+        if (std::fabs(q) > 1e-9 * std::max(1.0, qa))
+            return fail(c, STKFMM_E_DOMAIN, "periodic Laplace needs zero net charge");
+    }
+    hipEvent_t *ev = c->ev;
+    int ne = 0;
+    HIP_TRY(c, hipEventRecord(ev[ne++], s));                  // 0 start
+    const double inv = 1.0 / c->box_len;
+    if (c->n_sl > 0) {
+        hipLaunchKernelGGL(pack_values_kernel, dim3((c->n_sl + 255) / 256), dim3(256), 0, s, c->n_sl, sl_val,
+                           at<int32_t>(c, c->a_perm_sl), inv, sl_kind(c->kernel), ki.rec_sl, c->sl_rec.as<float>());
+        HIP_TRY(c, hipGetLastError());
+    }
+    if (c->n_dl > 0) {
+        hipLaunchKernelGGL(pack_values_kernel, dim3((c->n_dl + 255) / 256), dim3(256), 0, s, c->n_dl, dl_val,
+                           at<int32_t>(c, c->a_perm_dl), inv, dl_kind(c->kernel), ki.rec_dl, c->dl_rec.as<float>());
+        HIP_TRY(c, hipGetLastError());
+    }
+    HIP_TRY(c, hipEventRecord(ev[ne++], s));                  // 1 packed
+    // ---- near field on the side stream
+    HIP_TRY(c, hipStreamWaitEvent(c->side, ev[1], 0));
+    HIP_TRY(c, hipEventRecord(ev[20], c->side));
+    {
+        P2PArgs a;
+        a.chunks = at<int4>(c, c->a_chunks);
+        a.trg = c->trg_rec.as<float>();
+        a.u_off = at<int>(c, c->a_u_off);
+        a.u_ent = at<int2>(c, c->a_u_ent);
+        a.box_sl = at<int2>(c, c->a_box_sl);
+        a.box_dl = at<int2>(c, c->a_box_dl);
+        a.sl = c->sl_rec.as<float>();
+        a.dl = c->dl_rec.as<float>();
+        a.out = c->near_out.as<double>();
+        HIP_TRY(c, launch_p2p(c->kernel, c->nchunks, a, c->side));
+    }
+    HIP_TRY(c, hipEventRecord(ev[21], c->side));
+    // ---- far field
+    const bool far = t.depth >= 2 || periodic;
+    double *upchk = c->up_chk.as<double>(), *dnchk = c->dn_chk.as<double>();
+    float *updens = c->up_dens.as<float>(), *dndens = c->dn_dens.as<float>();
+    auto s2c = [&](int task_n, size_t dst, size_t off, size_t list, double alpha, double *chk, int acc_first) {
+        S2CArgs a;
+        a.dst = at<int>(c, dst);
+        a.list_off = at<int>(c, off);
+        a.list = at<int2>(c, list);
+        a.geom = at<double4>(c, c->a_geom);
+        a.grid = o.grid.as<float>();
+        a.M = o.M;
+        a.alpha = alpha;
+        a.chk = chk;
+        a.src_range = at<int2>(c, c->a_box_sl);
+        a.src = c->sl_rec.as<float>();
+        a.rec = ki.rec_sl;
+        a.accumulate = acc_first;
+        hipError_t e = launch_s2c(sl_kind(c->kernel), task_n, a, s);
+        if (e != hipSuccess) return e;
+        if (ki.k_dl > 0 && c->n_dl > 0) {
+            a.src_range = at<int2>(c, c->a_box_dl);
+            a.src = c->dl_rec.as<float>();
+            a.rec = ki.rec_dl;
+            a.accumulate = 1;
+            e = launch_s2c(dl_kind(c->kernel), task_n, a, s);
+        }
+        return e;
+    };
+    if (far) {
+        // upward pass
+        HIP_TRY(c, s2c(c->n_s2m, c->a_s2m_dst, c->a_s2m_off, c->a_s2m_list, kAlphaOut, upchk, 0));
+        HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 2 S2M
+        for (int l = t.depth; l >= c->lmin_up; --l) {
+            if (l < t.depth) {
+                stkfmm_status st = run_batch(c, c->m2m[l], o.m2m.as<float>(), updens, upchk, s);
+                if (st != STKFMM_OK) return st;
+            }
+            stkfmm_status st = run_pinv(c, c->upinv[l], o.up2.as<double>(), o.up1.as<double>(), upchk, updens, s);
+            if (st != STKFMM_OK) return st;
+        }
+        HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 3 upward
+        HIP_TRY(c, launch_fill_f64(dnchk, int64_t(c->nbox) * nc * o.M, 0.0, s));
+        stkfmm_status st = run_batch(c, c->m2l, o.m2l.as<float>(), updens, dnchk, s);
+        if (st != STKFMM_OK) return st;
+        HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 4 M2L
+        HIP_TRY(c, s2c(c->n_s2l, c->a_s2l_dst, c->a_s2l_off, c->a_s2l_list, kAlphaIn, dnchk, 1));
+        if (periodic) HIP_TRY(c, launch_periodic(o.tm2l.as<double>(), updens, dnchk, o.M, o.Mp, nc, 0, s));
+        HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 5 S2L + periodic
+        for (int l = c->lmin_dn; l <= t.depth; ++l) {
+            st = run_batch(c, c->l2l[l], o.l2l.as<float>(), dndens, dnchk, s);
+            if (st != STKFMM_OK) return st;
+            st = run_pinv(c, c->dnpinv[l], o.dn1.as<double>(), o.dn2.as<double>(), dnchk, dndens, s);
+            if (st != STKFMM_OK) return st;
+        }
+        HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 6 downward
+        L2TArgs a;
+        a.chunks = at<int4>(c, c->a_chunks);
+        a.trg = c->trg_rec.as<float>();
+        a.geom = at<double4>(c, c->a_geom);
+        a.has_local = at<uint8_t>(c, c->a_has_local);
+        a.w_off = at<int>(c, c->a_w_off);
+        a.w_ent = at<int2>(c, c->a_w_ent);
+        a.grid = o.grid.as<float>();
+        a.up_dens = updens;
+        a.dn_dens = dndens;
+        a.M = o.M;
+        a.Mp = o.Mp;
+        a.alpha_in = kAlphaIn;
+        a.alpha_out = kAlphaOut;
+        a.out = c->far_out.as<double>();
+        HIP_TRY(c, launch_l2t(c->kernel, c->nchunks, a, s));
+        HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 7 L2T
+    }
+    HIP_TRY(c, hipStreamWaitEvent(s, ev[21], 0));
+    HIP_TRY(c, hipEventRecord(ev[ne++], s));
+    CombineMap map = combine_map(c->kernel, c->box_len);
+    HIP_TRY(c, launch_combine(c->n_trg, c->near_out.as<double>(), far ? c->far_out.as<double>() : nullptr,
+                              at<int32_t>(c, c->a_perm_trg), ki.kt_acc, ki.k_trg, map, trg_val, s));
+    HIP_TRY(c, hipEventRecord(ev[ne++], s));                  // end
+    HIP_TRY(c, hipStreamSynchronize(s));
+    float ms = 0;
+    HIP_TRY(c, hipEventElapsedTime(&ms, ev[0], ev[ne - 1]));
+    c->t_run_ms = ms;
+    std::memset(c->stage_ms, 0, sizeof(c->stage_ms));
+    HIP_TRY(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
+    c->stage_ms[0] = ms;
+    if (far) {
+        const int map_idx[6] = {1, 2, 3, 4, 5, 6};   // S2M, upward, M2L, S2L(+periodic), downward, L2T
+        for (int i = 0; i < 6; ++i) {
+            HIP_TRY(c, hipEventElapsedTime(&ms, ev[1 + i], ev[2 + i]));
+            c->stage_ms[map_idx[i]] = ms;
+        }
+    }
+    HIP_TRY(c, hipEventElapsedTime(&ms, ev[20], ev[21]));
+    c->stage_ms[7] = ms;
+    HIP_TRY(c, hipEventElapsedTime(&ms, ev[ne - 2], ev[ne - 1]));
+    c->stage_ms[8] = ms;
+    return STKFMM_OK;
+}
+
+stkfmm_status stkfmm_evaluate(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc bc, int64_t n_sl, const double *sl_xyz,
+                              const double *sl_val, int64_t n_dl, const double *dl_xyz, const double *dl_val,
+                              int64_t n_trg, const double *trg_xyz, double *trg_val, int p, int leaf_cap,
+                              void *stream) {
+    stkfmm_status st = stkfmm_set_points(c, kernel, bc, n_sl, sl_xyz, n_dl, dl_xyz, n_trg, trg_xyz, p, leaf_cap,
+                                         stream);
+    if (st != STKFMM_OK) return st;
+    return stkfmm_run(c, sl_val, dl_val, trg_val, stream);
+}
+
+stkfmm_status stkfmm_direct(stkfmm_ctx *c, stkfmm_kernel kernel, int64_t n_sl, const double *sl_xyz,
+                            const double *sl_val, int64_t n_dl, const double *dl_xyz, const double *dl_val,
+                            int64_t n_trg, const double *trg_xyz, double *trg_val, void *stream) {
+    if (!c) return STKFMM_E_ARG;
+    if (!kernel_ok(int(kernel))) return fail(c, STKFMM_E_ARG, "unknown kernel");
+    const KernelInfo &ki = kInfo[kernel];
+    if (n_sl < 0 || n_dl < 0 || n_trg < 0) return fail(c, STKFMM_E_ARG, "negative size");
+    if ((n_sl > 0 && (!sl_xyz || !sl_val)) || (n_dl > 0 && (!dl_xyz || !dl_val)) ||
+        (n_trg > 0 && (!trg_xyz || !trg_val)))
+        return fail(c, STKFMM_E_ARG, "NULL array");
+    if (n_dl > 0 && ki.k_dl == 0) return fail(c, STKFMM_E_ARG, "kernel has no double-layer sources");
+    HIP_TRY(c, hipSetDevice(c->device));
+    DirectArgs a;
+    a.n_sl = n_sl;
+    a.n_dl = n_dl;
+    a.n_trg = n_trg;
+    a.sl = sl_xyz;
+    a.sl_val = sl_val;
+    a.dl = dl_xyz;
+    a.dl_val = dl_val;
+    a.trg = trg_xyz;
+    a.k_sl = ki.k_sl;
+    a.k_dl = ki.k_dl;
+    a.k_trg = ki.k_trg;
+    a.out = trg_val;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(c, launch_direct_f64(kernel, a, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return STKFMM_OK;
+}
+
+}  // extern "C"

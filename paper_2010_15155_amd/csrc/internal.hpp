@@ -1,0 +1,91 @@
+// Internal types of the MI355X kernel aggregated FMM library.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace kafmm {
+
+// Maximum octree depth; Morton keys carry 21 bits per dimension.
+constexpr int kMaxLevel = 20;
+constexpr int kKeyBits = 21;
+
+// Surface radii (in units of half the box side): the upward equivalent and
+// downward check surfaces sit just outside the box, the upward check and
+// downward equivalent surfaces well outside it.  1 < a_in < a_out and
+// a_in + a_out <= 4 keep every M2L check point outside the source box's
+// upward check surface.
+constexpr double kAlphaIn = 1.05;
+constexpr double kAlphaOut = 2.95;
+
+enum Kernel { kLapPGrad = 0, kStokeslet = 1, kRPY = 2, kPVel = 3, kTraction = 4, kNumKernels = 5 };
+
+struct KernelInfo {
+    int k_sl, k_dl, k_trg;   // user value widths
+    int ncomp;               // Laplace components on the ML tree (1 or 4)
+    int rec_sl, rec_dl;      // floats per packed source record (positions + values)
+    int kt_acc;              // accumulated target values (symmetric tensors compressed)
+};
+const KernelInfo &kernel_info(int k);
+
+// Box of the adaptive octree (normalised coordinates: root = [0,1)^3).
+struct Box {
+    int level = 0;
+    int32_t anchor[3] = {0, 0, 0};
+    int parent = -1;
+    int child[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+    bool leaf = true;
+    int64_t sl[2] = {0, 0}, dl[2] = {0, 0}, trg[2] = {0, 0};   // ranges in sorted arrays
+    int64_t nsrc_sub = 0, ntrg_sub = 0;                        // subtree totals
+};
+
+// A list entry: another box (or one of its periodic images) and the image
+// shift in root-box units.
+struct Entry {
+    int box;
+    int8_t shift[3];
+};
+
+struct Tree {
+    std::vector<Box> boxes;          // breadth-first, so level-sorted
+    std::vector<int> leaves;         // box ids of leaves
+    std::vector<int> level_start;    // boxes of level l: [level_start[l], level_start[l+1])
+    std::vector<int32_t> perm_sl, perm_dl, perm_trg;  // sorted position -> user index
+    int depth = 0;
+    bool periodic = false;
+    // Interaction lists (CSR by box id).
+    std::vector<int> u_off, w_off, x_off, v_off;
+    std::vector<Entry> u, w, x;      // U, W per leaf; X per box
+    std::vector<Entry> v;            // V per box (shift unused, offset below)
+    std::vector<int8_t> v_rel;       // 3 per V entry: anchor offset (source - target) at the level
+    std::vector<uint8_t> has_local;  // box receives a downward expansion
+    int64_t p2p_pairs = 0;
+};
+
+// Build the octree and interaction lists.  Coordinates are normalised to
+// [0,1) (already wrapped for periodic trees).  Returns an empty string or an
+// error message.
+std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t n_dl,
+                       const double *trg, int64_t n_trg, int leaf_cap, bool periodic, Tree &t);
+
+// Host-side FP64 operators for order p (unit box: side 1, centre 0).
+struct Operators {
+    int p = 0, M = 0, Mp = 0, rank = 0;
+    std::vector<double> grid;        // [M][3] unit surface lattice in [-1,1]^3
+    // pseudo-inverse factors: UC2UE = P1 * P2 (P1 [M][rank], P2 [rank][M]),
+    // DC2DE = P2^T * P1^T (kernel symmetry), all FP64
+    std::vector<double> up1, up2;
+    std::vector<float> m2m;          // [8][Mp][Mp]  parent check <- child equivalent (parent side 1)
+    std::vector<float> l2l;          // [8][Mp][Mp]  child check <- parent equivalent (parent side 1)
+    std::vector<float> m2l;          // [343][Mp][Mp] check <- equivalent at offset (side 1); |o|<=1 unused
+    std::vector<double> t_m2l;       // [M][M] periodic far-image operator (side 1), empty if unused
+    double svd_tol = 0;
+};
+
+std::string build_operators(int p, double svd_tol, bool periodic, Operators &ops);
+
+// Index of a relative offset o in [-3,3]^3.
+inline int offset_index(int ox, int oy, int oz) { return ((oz + 3) * 7 + (oy + 3)) * 7 + (ox + 3); }
+
+}  // namespace kafmm

@@ -1,0 +1,852 @@
+// HIP kernels (gfx950) of the kernel aggregated FMM evaluation pass.
+//
+// Layouts (all leaf-sorted, normalised coordinates in [0,1)^3):
+//   source record  float[R]: xh yh zh xl yl zl v...   (hi/lo split of FP64)
+//   target record  float[8]: xh yh zh 0 xl yl zl 0
+//   box geometry   double4 : cx cy cz h
+//   densities      float  [box][ncomp][Mp]   (Mp = M rounded up to 32, padding 0)
+//   check values   double [box][ncomp][M]
+//   target values  double [n_trg][NACC]       (near and far parts separately)
+// A target chunk is up to 256 targets of one leaf; its block holds one target
+// per lane.  No floating-point atomics anywhere: every output element has one
+// writer, so results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "kernel_math.hpp"
+#include "kernels.hpp"
+
+namespace kafmm {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ void two_sum_shift(float &hi, float &lo, float s) {
+    // (hi + lo) - s with the rounding error of hi - s moved into lo
+    float sum = hi - s;
+    float bp = sum - hi;
+    float err = (hi - (sum - bp)) + (-s - bp);
+    hi = sum;
+    lo += err;
+}
+
+__device__ __forceinline__ int shift_comp(int code, int k) { return ((code >> (2 * k)) & 3) - 1; }
+
+__global__ void fill_f64(double *p, int64_t n, double v) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
+}
+
+__global__ void fill_f32(float *p, int64_t n, float v) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (; i < n; i += int64_t(gridDim.x) * blockDim.x) p[i] = v;
+}
+
+// ------------------------------------------------------------------ packing
+// kind: 0 Stokeslet f, 1 RPY f,b, 2 Laplace q, 3 Laplace d, 4 Stokes f,q, 5 Stokes D (9 -> sym 6)
+__global__ void pack_sources(int64_t n, const double *__restrict__ xyz, const double *__restrict__ val,
+                             const int32_t *__restrict__ perm, double3 origin, double inv_len,
+                             int kind, int rec, float *__restrict__ out) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t j = perm[i];
+    float *o = out + i * rec;
+    double u[3] = {(xyz[3 * j] - origin.x) * inv_len, (xyz[3 * j + 1] - origin.y) * inv_len,
+                   (xyz[3 * j + 2] - origin.z) * inv_len};
+    for (int k = 0; k < 3; ++k) {
+        double w = u[k] - floor(u[k]);      // wrap (a no-op for validated open-BC input)
+        if (w >= 1.0) w = 0.0;
+        float h = float(w);
+        o[k] = h;
+        o[3 + k] = float(w - double(h));
+    }
+    for (int k = 6; k < rec; ++k) o[k] = 0.0f;
+    if (val == nullptr) return;
+    switch (kind) {
+        case 0: {
+            const double *v = val + 3 * j;
+            o[6] = float(v[0]); o[7] = float(v[1]); o[8] = float(v[2]);
+            break;
+        }
+        case 1: {
+            const double *v = val + 4 * j;
+            double b = v[3] * inv_len;
+            o[6] = float(v[0]); o[7] = float(v[1]); o[8] = float(v[2]); o[9] = float(b * b);
+            break;
+        }
+        case 2: o[6] = float(val[j]); break;
+        case 3: {
+            const double *v = val + 3 * j;
+            o[6] = float(v[0] * inv_len); o[7] = float(v[1] * inv_len); o[8] = float(v[2] * inv_len);
+            break;
+        }
+        case 4: {
+            const double *v = val + 4 * j;
+            o[6] = float(v[0]); o[7] = float(v[1]); o[8] = float(v[2]); o[9] = float(v[3]);
+            break;
+        }
+        case 5: {
+            const double *D = val + 9 * j;
+            double s = inv_len;
+            o[6] = float(D[0] * s);
+            o[7] = float(0.5 * (D[1] + D[3]) * s);
+            o[8] = float(0.5 * (D[2] + D[6]) * s);
+            o[9] = float(D[4] * s);
+            o[10] = float(0.5 * (D[5] + D[7]) * s);
+            o[11] = float(D[8] * s);
+            break;
+        }
+    }
+}
+
+__global__ void pack_targets(int64_t n, const double *__restrict__ xyz, const int32_t *__restrict__ perm,
+                             double3 origin, double inv_len, float *__restrict__ out) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t j = perm[i];
+    double u[3] = {(xyz[3 * j] - origin.x) * inv_len, (xyz[3 * j + 1] - origin.y) * inv_len,
+                   (xyz[3 * j + 2] - origin.z) * inv_len};
+    float4 hi, lo;
+    float *h = &hi.x, *l = &lo.x;
+    for (int k = 0; k < 3; ++k) {
+        double w = u[k] - floor(u[k]);
+        if (w >= 1.0) w = 0.0;
+        h[k] = float(w);
+        l[k] = float(w - double(h[k]));
+    }
+    hi.w = 0.0f;
+    lo.w = 0.0f;
+    reinterpret_cast<float4 *>(out)[2 * i] = hi;
+    reinterpret_cast<float4 *>(out)[2 * i + 1] = lo;
+}
+
+// ------------------------------------------------------------------ P2P (S->T over U lists)
+// FP32 pair arithmetic on hi/lo coordinate differences; each run of 64
+// sources is summed in FP32 and added to FP64 accumulators.
+template <class K>
+__global__ __launch_bounds__(256) void p2p_kernel(P2PArgs a) {
+    const int4 ch = a.chunks[blockIdx.x];
+    const int first = ch.y + int(threadIdx.x & ~63u);
+    if (first >= ch.z) return;                       // whole wave idle
+    const int t = ch.y + int(threadIdx.x);
+    const bool active = t < ch.z;
+    const int ti = active ? t : ch.z - 1;
+    const float4 p0 = reinterpret_cast<const float4 *>(a.trg)[2 * ti];
+    const float4 p1 = reinterpret_cast<const float4 *>(a.trg)[2 * ti + 1];
+    double acc[K::NACC];
+#pragma unroll
+    for (int k = 0; k < K::NACC; ++k) acc[k] = 0.0;
+    const int e0 = a.u_off[ch.x], e1 = a.u_off[ch.x + 1];
+    for (int e = e0; e < e1; ++e) {
+        const int2 en = a.u_ent[e];
+        float xh = p0.x, yh = p0.y, zh = p0.z, xl = p1.x, yl = p1.y, zl = p1.z;
+        if (en.y != kZeroShift) {
+            int sx = shift_comp(en.y, 0), sy = shift_comp(en.y, 1), sz = shift_comp(en.y, 2);
+            if (sx) two_sum_shift(xh, xl, float(sx));
+            if (sy) two_sum_shift(yh, yl, float(sy));
+            if (sz) two_sum_shift(zh, zl, float(sz));
+        }
+        const int2 rs = a.box_sl[en.x];
+        for (int j0 = rs.x; j0 < rs.y; j0 += 64) {
+            const int j1 = min(j0 + 64, rs.y);
+            float part[K::NACC];
+#pragma unroll
+            for (int k = 0; k < K::NACC; ++k) part[k] = 0.0f;
+#pragma unroll 4
+            for (int j = j0; j < j1; ++j) {
+                const float *s = a.sl + int64_t(j) * K::RS;
+                float dx = (xh - s[0]) + (xl - s[3]);
+                float dy = (yh - s[1]) + (yl - s[4]);
+                float dz = (zh - s[2]) + (zl - s[5]);
+                float ri = rsq_or_zero(dx * dx + dy * dy + dz * dz);
+                K::sl(dx, dy, dz, ri, s + 6, part);
+            }
+#pragma unroll
+            for (int k = 0; k < K::NACC; ++k) acc[k] += double(part[k]);
+        }
+        if (K::RD > 0) {
+            const int2 rd = a.box_dl[en.x];
+            for (int j0 = rd.x; j0 < rd.y; j0 += 64) {
+                const int j1 = min(j0 + 64, rd.y);
+                float part[K::NACC];
+#pragma unroll
+                for (int k = 0; k < K::NACC; ++k) part[k] = 0.0f;
+#pragma unroll 4
+                for (int j = j0; j < j1; ++j) {
+                    const float *s = a.dl + int64_t(j) * (K::RD > 0 ? K::RD : 1);
+                    float dx = (xh - s[0]) + (xl - s[3]);
+                    float dy = (yh - s[1]) + (yl - s[4]);
+                    float dz = (zh - s[2]) + (zl - s[5]);
+                    float ri = rsq_or_zero(dx * dx + dy * dy + dz * dz);
+                    K::dl(dx, dy, dz, ri, s + 6, part);
+                }
+#pragma unroll
+                for (int k = 0; k < K::NACC; ++k) acc[k] += double(part[k]);
+            }
+        }
+    }
+    if (active) {
+        double *o = a.out + int64_t(t) * K::NACC;
+#pragma unroll
+        for (int k = 0; k < K::NACC; ++k) o[k] = acc[k];
+    }
+}
+
+// ------------------------------------------------------------------ S2M / S2L surface tiles
+// One block per destination box: check potentials at its M surface points
+// (radius alpha) from the sources of a list of leaves, each source first
+// turned into 4-Laplace charges/dipoles relative to the destination centre.
+constexpr int kS2CTile = 256;
+
+template <int SRC>   // source kind of the staging step, see stage_source
+struct S2CTraits;
+// SRC: 0 Stokeslet f, 1 RPY f,b^2, 2 Laplace q, 3 Laplace d, 4 Stokes f,q, 5 Stokes D^s
+template <> struct S2CTraits<0> { static constexpr int NC = 4, CHG = 1, DIP = 0; };
+template <> struct S2CTraits<1> { static constexpr int NC = 4, CHG = 1, DIP = 1; };
+template <> struct S2CTraits<2> { static constexpr int NC = 1, CHG = 1, DIP = 0; };
+template <> struct S2CTraits<3> { static constexpr int NC = 1, CHG = 0, DIP = 1; };
+template <> struct S2CTraits<4> { static constexpr int NC = 4, CHG = 1, DIP = 0; };
+template <> struct S2CTraits<5> { static constexpr int NC = 4, CHG = 0, DIP = 1; };
+
+// Turn one source record into charges q[c] and dipoles d[c][3] at y_rel (relative to c).
+template <int SRC>
+__device__ __forceinline__ void stage_source(const float *s, float yx, float yy, float yz,
+                                             float *q, float *d) {
+    if (SRC == 0 || SRC == 1 || SRC == 4) {
+        q[0] = s[6]; q[1] = s[7]; q[2] = s[8];
+        q[3] = yx * s[6] + yy * s[7] + yz * s[8] + (SRC == 4 ? s[9] : 0.0f);
+        if (SRC == 1) {
+            float c = s[9] * (1.0f / 3.0f);
+            for (int k = 0; k < 9; ++k) d[k] = 0.0f;
+            d[9] = c * s[6]; d[10] = c * s[7]; d[11] = c * s[8];
+        }
+    } else if (SRC == 2) {
+        q[0] = s[6];
+    } else if (SRC == 3) {
+        d[0] = s[6]; d[1] = s[7]; d[2] = s[8];
+    } else if (SRC == 5) {
+        // Phi_j dipole -D^s_j. ; Psi dipole -D^s (y - c)
+        const float *m = s + 6;   // xx xy xz yy yz zz
+        d[0] = -m[0]; d[1] = -m[1]; d[2] = -m[2];
+        d[3] = -m[1]; d[4] = -m[3]; d[5] = -m[4];
+        d[6] = -m[2]; d[7] = -m[4]; d[8] = -m[5];
+        d[9] = -(m[0] * yx + m[1] * yy + m[2] * yz);
+        d[10] = -(m[1] * yx + m[3] * yy + m[4] * yz);
+        d[11] = -(m[2] * yx + m[4] * yy + m[5] * yz);
+    }
+}
+
+template <int SRC>
+__global__ __launch_bounds__(256) void s2c_kernel(S2CArgs a) {
+    using T = S2CTraits<SRC>;
+    constexpr int NC = T::NC;
+    constexpr int NV = 3 + (T::CHG ? NC : 0) + (T::DIP ? 3 * NC : 0);
+    constexpr int PTS = 6;                         // check points per thread (M <= 1536)
+    __shared__ float tile[kS2CTile * NV];
+    const int task = blockIdx.x;
+    const int dst = a.dst[task];
+    const double4 cb = a.geom[dst];
+    const float rad = float(a.alpha * 0.5 * cb.w);
+    float zx[PTS], zy[PTS], zz[PTS], pot[PTS][NC];
+#pragma unroll
+    for (int i = 0; i < PTS; ++i) {
+        int m = int(threadIdx.x) + 256 * i;
+        int mm = m < a.M ? m : 0;
+        zx[i] = rad * a.grid[3 * mm];
+        zy[i] = rad * a.grid[3 * mm + 1];
+        zz[i] = rad * a.grid[3 * mm + 2];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pot[i][c] = 0.0f;
+    }
+    const int npts = (a.M + 255) / 256;
+    const int l0 = a.list_off[task], l1 = a.list_off[task + 1];
+    for (int l = l0; l < l1; ++l) {
+        const int2 en = a.list[l];
+        const int2 rng = a.src_range[en.x];
+        const double sx = shift_comp(en.y, 0) - cb.x, sy = shift_comp(en.y, 1) - cb.y,
+                     sz = shift_comp(en.y, 2) - cb.z;
+        for (int j0 = rng.x; j0 < rng.y; j0 += kS2CTile) {
+            const int n = min(kS2CTile, rng.y - j0);
+            __syncthreads();
+            if (int(threadIdx.x) < n) {
+                const float *s = a.src + int64_t(j0 + threadIdx.x) * a.rec;
+                float yx = float((double(s[0]) + double(s[3])) + sx);
+                float yy = float((double(s[1]) + double(s[4])) + sy);
+                float yz = float((double(s[2]) + double(s[5])) + sz);
+                float q[4] = {0, 0, 0, 0}, d[12];
+                stage_source<SRC>(s, yx, yy, yz, q, d);
+                float *o = tile + threadIdx.x * NV;
+                o[0] = yx; o[1] = yy; o[2] = yz;
+                int k = 3;
+                if (T::CHG)
+                    for (int c = 0; c < NC; ++c) o[k++] = q[c];
+                if (T::DIP)
+                    for (int c = 0; c < 3 * NC; ++c) o[k++] = d[(NC == 4 ? 0 : 0) + c];
+            }
+            __syncthreads();
+            for (int j = 0; j < n; ++j) {
+                const float *y = tile + j * NV;
+#pragma unroll
+                for (int i = 0; i < PTS; ++i) {
+                    if (i >= npts) break;
+                    float dx = zx[i] - y[0], dy = zy[i] - y[1], dz = zz[i] - y[2];
+                    float ri = rsq_or_zero(dx * dx + dy * dy + dz * dz);
+                    float ri3 = ri * ri * ri;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        float v = 0.0f;
+                        if (T::CHG) v += y[3 + c] * ri;
+                        if (T::DIP) {
+                            const float *dd = y + 3 + (T::CHG ? NC : 0) + 3 * c;
+                            v += (dd[0] * dx + dd[1] * dy + dd[2] * dz) * ri3;
+                        }
+                        pot[i][c] += v;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < PTS; ++i) {
+        int m = int(threadIdx.x) + 256 * i;
+        if (m >= a.M) continue;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double *o = a.chk + (int64_t(dst) * NC + c) * a.M + m;
+            double v = double(pot[i][c]) * kInv4Pi;
+            *o = a.accumulate ? *o + v : v;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ grouped FP32 MFMA GEMM
+// Y[:, col] = A_op * X[:, col] for tiles of 128 columns sharing one operator.
+// A_op: [Mp][Mp] row-major; columns of X and Y are contiguous Mp-vectors
+// addressed through bcol / ycol (units of Mp floats).
+// Block 256 threads = 4 waves in a 2x2 arrangement, each wave 64x64 as 2x2
+// v_mfma_f32_32x32x2f32 tiles; K staged through LDS in steps of 32.
+constexpr int kGT = 128;
+constexpr int kGK = 32;
+constexpr int kGLd = kGK + 1;
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(256) void gemm_f32_mfma(GemmArgs a) {
+    __shared__ float As[kGT * kGLd];
+    __shared__ float Bs[kGT * kGLd];
+    const int4 tile = a.tiles[blockIdx.x];            // op, col0, ncol, -
+    const int row0 = blockIdx.y * kGT;
+    const int Mp = a.Mp;
+    const float *A = a.ops + int64_t(tile.x) * Mp * Mp;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+    // per-thread load slots: 4 float4 of A and of B per K step
+    const float *bptr[4];
+    int lr[4], lk[4];
+    bool arow_ok[4], bcol_ok[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int idx = tid + 256 * i;
+        lr[i] = idx >> 3;
+        lk[i] = (idx & 7) * 4;
+        arow_ok[i] = row0 + lr[i] < Mp;
+        bcol_ok[i] = lr[i] < tile.z;
+        int c = bcol_ok[i] ? a.bcol[tile.y + lr[i]] : 0;
+        bptr[i] = a.X + int64_t(c) * Mp;
+    }
+    for (int k0 = 0; k0 < Mp; k0 += kGK) {
+        float4 ra[4], rb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ra[i] = arow_ok[i] ? *reinterpret_cast<const float4 *>(A + int64_t(row0 + lr[i]) * Mp + k0 + lk[i])
+                               : make_float4(0, 0, 0, 0);
+            rb[i] = bcol_ok[i] ? *reinterpret_cast<const float4 *>(bptr[i] + k0 + lk[i])
+                               : make_float4(0, 0, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float *da = As + lr[i] * kGLd + lk[i];
+            float *db = Bs + lr[i] * kGLd + lk[i];
+            da[0] = ra[i].x; da[1] = ra[i].y; da[2] = ra[i].z; da[3] = ra[i].w;
+            db[0] = rb[i].x; db[1] = rb[i].y; db[2] = rb[i].z; db[3] = rb[i].w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kGK; kk += 2) {
+            const int k = kk + (lane >> 5);
+            float av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) av[i] = As[(wr + 32 * i + (lane & 31)) * kGLd + k];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bv[j] = Bs[(wc + 32 * j + (lane & 31)) * kGLd + k];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    // epilogue: lane holds column (lane & 31) and rows 8*(v/4) + 4*(lane/32) + v%4
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = wc + 32 * j + (lane & 31);
+        if (col >= tile.z) continue;
+        float *Y = a.Y + int64_t(a.ycol[tile.y + col]) * Mp;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int row = row0 + wr + 32 * i + 8 * g + 4 * (lane >> 5);
+                if (row < Mp) {
+                    float4 v = make_float4(acc[i][j][4 * g], acc[i][j][4 * g + 1], acc[i][j][4 * g + 2],
+                                           acc[i][j][4 * g + 3]);
+                    *reinterpret_cast<float4 *>(Y + row) = v;
+                }
+            }
+    }
+}
+
+// ------------------------------------------------------------------ FP64 GEMM (pseudo-inverse)
+// C[col][i] = scale(col) * sum_k A[i][k] * B[col][k],  i < R, k < K.
+// B columns are FP64 (check values) or FP64 scratch; C is FP64 scratch or
+// FP32 densities.  Tile 64 rows x 64 columns, K steps of 16, 4x4 per thread.
+template <typename TC>
+__global__ __launch_bounds__(256) void gemm_f64(Gemm64Args a, TC *C) {
+    __shared__ double As[64][17];
+    __shared__ double Bs[64][17];
+    const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
+    const int tid = threadIdx.x;
+    const int tr = (tid >> 4) * 4, tc = (tid & 15) * 4;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < a.K; k0 += 16) {
+        for (int i = tid; i < 64 * 16; i += 256) {
+            int r = i >> 4, k = i & 15;
+            As[r][k] = (row0 + r < a.R && k0 + k < a.K) ? a.A[int64_t(row0 + r) * a.lda + k0 + k] : 0.0;
+            int c = col0 + r;
+            double b = 0.0;
+            if (c < a.ncol && k0 + k < a.K) {
+                int bc = a.bidx[c];
+                b = a.B[int64_t(bc) * a.ldb + k0 + k];
+            }
+            Bs[r][k] = b;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = As[tr + i][k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Bs[tc + j][k];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        int c = col0 + tc + j;
+        if (c >= a.ncol) continue;
+        double s = a.cscale ? a.cscale[c] : 1.0;
+        TC *o = C + int64_t(a.cidx[c]) * a.ldc;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int r = row0 + tr + i;
+            if (r < a.R) o[r] = TC(s * acc[i][j]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ translation reduce
+// chk[dst][c][m] (+)= sum over pairs p of scale_p * (Y_p[c][m] - [c == 3] delta_p . Y_p[0..2][m])
+// (the Psi origin shift; Laplace problems have one component and no shift).
+__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
+    const int task = blockIdx.x;
+    const int dst = a.dst[task];
+    const int p0 = a.off[task], p1 = a.off[task + 1];
+    const int nc = a.ncomp;
+    for (int m = threadIdx.x; m < a.M; m += blockDim.x) {
+        double acc[4] = {0, 0, 0, 0};
+        for (int p = p0; p < p1; ++p) {
+            const int pr = a.pair[p];
+            const float *Y = a.Y + int64_t(pr) * nc * a.Mp + m;
+            const double s = a.scale[p];
+            if (nc == 4) {
+                double y0 = Y[0], y1 = Y[a.Mp], y2 = Y[2 * a.Mp], y3 = Y[3 * a.Mp];
+                const float *dl = a.delta + 3 * int64_t(p);
+                acc[0] += s * y0;
+                acc[1] += s * y1;
+                acc[2] += s * y2;
+                acc[3] += s * (y3 - (double(dl[0]) * y0 + double(dl[1]) * y1 + double(dl[2]) * y2));
+            } else {
+                acc[0] += s * double(Y[0]);
+            }
+        }
+        for (int c = 0; c < nc; ++c) {
+            double *o = a.chk + (int64_t(dst) * nc + c) * a.M + m;
+            *o = a.accumulate ? *o + acc[c] : acc[c];
+        }
+    }
+}
+
+// periodic far images: chk[root][c][i] += sum_j T[i][j] dens[root][c][j]
+__global__ __launch_bounds__(256) void periodic_kernel(const double *__restrict__ T, const float *__restrict__ dens,
+                                                       double *__restrict__ chk, int M, int Mp, int nc, int root) {
+    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < M * nc; i += blockDim.x * gridDim.x) {
+        int c = i / M, r = i % M;
+        const float *d = dens + (int64_t(root) * nc + c) * Mp;
+        double s = 0.0;
+        for (int j = 0; j < M; ++j) s += T[int64_t(r) * M + j] * double(d[j]);
+        chk[(int64_t(root) * nc + c) * M + r] += s;
+    }
+}
+
+// ------------------------------------------------------------------ L2T / M2T
+// Target values from equivalent densities: the target leaf's downward
+// equivalent points (radius a_out) and the upward equivalent points of its
+// W-list boxes (radius a_in), staged through LDS 256 points at a time.
+template <class E>
+__global__ __launch_bounds__(256) void l2t_kernel(L2TArgs a) {
+    constexpr int NC = E::NC;
+    constexpr int NV = 3 + NC;
+    __shared__ float tile[256 * NV];
+    const int4 ch = a.chunks[blockIdx.x];
+    const int leaf = ch.x;
+    const int t = ch.y + int(threadIdx.x);
+    const bool active = t < ch.z;
+    const int ti = active ? t : ch.z - 1;
+    const double4 cb = a.geom[leaf];
+    const float4 p0 = reinterpret_cast<const float4 *>(a.trg)[2 * ti];
+    const float4 p1 = reinterpret_cast<const float4 *>(a.trg)[2 * ti + 1];
+    // target relative to the leaf centre
+    const float xr = float((double(p0.x) - cb.x) + double(p1.x));
+    const float yr = float((double(p0.y) - cb.y) + double(p1.y));
+    const float zr = float((double(p0.z) - cb.z) + double(p1.z));
+    double acc[E::NACC];
+#pragma unroll
+    for (int k = 0; k < E::NACC; ++k) acc[k] = 0.0;
+    const int nsrc = (a.has_local[leaf] ? 1 : 0) + (a.w_off[leaf + 1] - a.w_off[leaf]);
+    for (int si = 0; si < nsrc; ++si) {
+        int box;
+        double alpha;
+        double ox = 0, oy = 0, oz = 0;      // box centre (image) relative to the leaf centre
+        const float *dens;
+        if (si == 0 && a.has_local[leaf]) {
+            box = leaf;
+            alpha = a.alpha_out;
+            dens = a.dn_dens;
+        } else {
+            const int2 en = a.w_ent[a.w_off[leaf] + si - (a.has_local[leaf] ? 1 : 0)];
+            box = en.x;
+            alpha = a.alpha_in;
+            dens = a.up_dens;
+            const double4 g = a.geom[box];
+            ox = (g.x + shift_comp(en.y, 0)) - cb.x;
+            oy = (g.y + shift_comp(en.y, 1)) - cb.y;
+            oz = (g.z + shift_comp(en.y, 2)) - cb.z;
+        }
+        const double rad = alpha * 0.5 * a.geom[box].w;
+        // s = psi - (x - c_origin).phi with the origin at the equivalent box centre
+        const float cx = xr - float(ox), cy = yr - float(oy), cz = zr - float(oz);
+        float part[E::NACC];
+#pragma unroll
+        for (int k = 0; k < E::NACC; ++k) part[k] = 0.0f;
+        for (int j0 = 0; j0 < a.M; j0 += 256) {
+            const int n = min(256, a.M - j0);
+            __syncthreads();
+            if (int(threadIdx.x) < n) {
+                const int m = j0 + threadIdx.x;
+                float *o = tile + threadIdx.x * NV;
+                o[0] = float(ox + rad * a.grid[3 * m]);
+                o[1] = float(oy + rad * a.grid[3 * m + 1]);
+                o[2] = float(oz + rad * a.grid[3 * m + 2]);
+                for (int c = 0; c < NC; ++c) o[3 + c] = dens[(int64_t(box) * NC + c) * a.Mp + m];
+            }
+            __syncthreads();
+            if (!active) continue;
+#pragma unroll 2
+            for (int j = 0; j < n; ++j) {
+                const float *y = tile + j * NV;
+                float dx = xr - y[0], dy = yr - y[1], dz = zr - y[2];
+                float ri = rsq_or_zero(dx * dx + dy * dy + dz * dz);
+                float s = NC == 4 ? y[6] - (cx * y[3] + cy * y[4] + cz * y[5]) : 0.0f;
+                E::eq(dx, dy, dz, ri, y + 3, s, part);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < E::NACC; ++k) acc[k] += double(part[k]);
+    }
+    if (active) {
+        double *o = a.out + int64_t(t) * E::NACC;
+#pragma unroll
+        for (int k = 0; k < E::NACC; ++k) o[k] = acc[k];
+    }
+}
+
+// ------------------------------------------------------------------ combine + un-permute
+// user[perm[i]][k] = scale_k * (near[i][src_k] + far[i][src_k]); a negative
+// src_k selects nothing (0).  Symmetric tensors are expanded by the map.
+__global__ void combine_kernel(int64_t n, const double *__restrict__ near, const double *__restrict__ far,
+                               const int32_t *__restrict__ perm, int nacc, int kt, CombineMap map,
+                               double *__restrict__ out) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double *o = out + int64_t(perm[i]) * kt;
+    for (int k = 0; k < kt; ++k) {
+        int s = map.src[k];
+        double v = 0.0;
+        if (s >= 0) v = near[i * nacc + s] + (far ? far[i * nacc + s] : 0.0);
+        o[k] = map.scale[k] * v;
+    }
+}
+
+// ------------------------------------------------------------------ FP64 direct sum (error judge)
+template <class K>
+__global__ __launch_bounds__(256) void direct_f64_kernel(DirectArgs a) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool active = t < a.n_trg;
+    const int64_t ti = active ? t : 0;
+    const double x0 = a.trg[3 * ti], x1 = a.trg[3 * ti + 1], x2 = a.trg[3 * ti + 2];
+    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    __shared__ double ys[256 * 13];
+    for (int pass = 0; pass < 2; ++pass) {
+        const int64_t ns = pass == 0 ? a.n_sl : a.n_dl;
+        const double *xyz = pass == 0 ? a.sl : a.dl;
+        const double *val = pass == 0 ? a.sl_val : a.dl_val;
+        const int kv = pass == 0 ? a.k_sl : a.k_dl;
+        for (int64_t j0 = 0; j0 < ns; j0 += 256) {
+            const int n = int(min(int64_t(256), ns - j0));
+            __syncthreads();
+            if (int(threadIdx.x) < n) {
+                double *o = ys + threadIdx.x * 13;
+                const int64_t j = j0 + threadIdx.x;
+                o[0] = xyz[3 * j]; o[1] = xyz[3 * j + 1]; o[2] = xyz[3 * j + 2];
+                for (int k = 0; k < kv; ++k) o[3 + k] = val[j * kv + k];
+            }
+            __syncthreads();
+            if (!active) continue;
+            for (int j = 0; j < n; ++j) {
+                const double *y = ys + j * 13;
+                double r[3] = {x0 - y[0], x1 - y[1], x2 - y[2]};
+                K::pair(pass, r, y + 3, acc);
+            }
+        }
+    }
+    if (active)
+        for (int k = 0; k < a.k_trg; ++k) a.out[t * a.k_trg + k] = acc[k];
+}
+
+// FP64 pair functions in user layouts (outputs already scaled).
+struct F64Stokeslet {
+    __device__ static void pair(int, const double *r, const double *v, double *a) {
+        double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (rr == 0.0) return;
+        double ri = 1.0 / sqrt(rr), ri3 = ri / rr;
+        double rf = r[0] * v[0] + r[1] * v[1] + r[2] * v[2];
+        for (int i = 0; i < 3; ++i) a[i] += kInv8Pi * (v[i] * ri + r[i] * rf * ri3);
+    }
+};
+struct F64RPY {
+    __device__ static void pair(int, const double *r, const double *v, double *a) {
+        double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (rr == 0.0) return;
+        double ri = 1.0 / sqrt(rr), ri3 = ri / rr, ri5 = ri3 / rr;
+        double rf = r[0] * v[0] + r[1] * v[1] + r[2] * v[2], b2 = v[3] * v[3];
+        for (int i = 0; i < 3; ++i) {
+            a[i] += kInv8Pi * ((ri + b2 / 3.0 * ri3) * v[i] + (ri3 - b2 * ri5) * rf * r[i]);
+            a[3 + i] += kInv8Pi * (2.0 * ri3 * v[i] - 6.0 * rf * ri5 * r[i]);
+        }
+    }
+};
+struct F64Lap {
+    __device__ static void pair(int pass, const double *r, const double *v, double *a) {
+        double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (rr == 0.0) return;
+        double ri = 1.0 / sqrt(rr), ri3 = ri / rr, ri5 = ri3 / rr;
+        if (pass == 0) {
+            a[0] += kInv4Pi * v[0] * ri;
+            for (int i = 0; i < 3; ++i) a[1 + i] -= kInv4Pi * v[0] * r[i] * ri3;
+        } else {
+            double dr = v[0] * r[0] + v[1] * r[1] + v[2] * r[2];
+            a[0] += kInv4Pi * dr * ri3;
+            for (int i = 0; i < 3; ++i) a[1 + i] += kInv4Pi * (v[i] * ri3 - 3.0 * dr * r[i] * ri5);
+        }
+    }
+};
+struct F64PVel {
+    __device__ static void pair(int pass, const double *r, const double *v, double *a) {
+        double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (rr == 0.0) return;
+        double ri = 1.0 / sqrt(rr), ri3 = ri / rr, ri5 = ri3 / rr;
+        if (pass == 0) {
+            double rf = r[0] * v[0] + r[1] * v[1] + r[2] * v[2];
+            a[0] += kInv4Pi * rf * ri3;
+            for (int i = 0; i < 3; ++i) a[1 + i] += kInv8Pi * (v[i] * ri + r[i] * (rf - v[3]) * ri3);
+        } else {
+            double A = 0, tr = v[0] + v[4] + v[8];
+            for (int j = 0; j < 3; ++j)
+                for (int k = 0; k < 3; ++k) A += r[j] * v[3 * j + k] * r[k];
+            a[0] += kInv4Pi * (-3.0 * A * ri5 + tr * ri3);
+            for (int i = 0; i < 3; ++i) a[1 + i] += -3.0 * kInv8Pi * r[i] * A * ri5;
+        }
+    }
+};
+struct F64Traction {
+    __device__ static void pair(int pass, const double *r, const double *v, double *a) {
+        double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (rr == 0.0) return;
+        double ri = 1.0 / sqrt(rr), ri3 = ri / rr, ri5 = ri3 / rr, ri7 = ri5 / rr;
+        if (pass == 0) {
+            double rf = r[0] * v[0] + r[1] * v[1] + r[2] * v[2], q = v[3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    a[3 * i + j] += kInv4Pi * (3.0 * (q - rf) * r[i] * r[j] * ri5 - (i == j ? q * ri3 : 0.0));
+        } else {
+            double w[3], tr = v[0] + v[4] + v[8];
+            for (int j = 0; j < 3; ++j) {
+                w[j] = 0;
+                for (int k = 0; k < 3; ++k) w[j] += 0.5 * (v[3 * j + k] + v[3 * k + j]) * r[k];
+            }
+            double A = r[0] * w[0] + r[1] * w[1] + r[2] * w[2];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    a[3 * i + j] += kInv4Pi * (-(i == j ? tr * ri3 : 0.0) - 3.0 * (r[i] * w[j] + w[i] * r[j]) * ri5 +
+                                               15.0 * A * r[i] * r[j] * ri7);
+        }
+    }
+};
+
+// ------------------------------------------------------------------ launchers
+static inline int blocks_for(int64_t n, int b) { return int((n + b - 1) / b); }
+
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int nb = std::min<int64_t>(blocks_for(n, 256), 4096);
+    hipLaunchKernelGGL(fill_f64, dim3(nb), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int nb = std::min<int64_t>(blocks_for(n, 256), 4096);
+    hipLaunchKernelGGL(fill_f32, dim3(nb), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_sources(int64_t n, const double *xyz, const double *val, const int32_t *perm,
+                               double3 origin, double inv_len, int kind, int rec, float *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_sources, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, xyz, val, perm, origin,
+                       inv_len, kind, rec, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_targets(int64_t n, const double *xyz, const int32_t *perm, double3 origin,
+                               double inv_len, float *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_targets, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, xyz, perm, origin, inv_len,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2p(int kernel, int nchunks, const P2PArgs &a, hipStream_t s) {
+    if (nchunks <= 0) return hipSuccess;
+    switch (kernel) {
+        case kStokeslet: hipLaunchKernelGGL(p2p_kernel<DStokeslet>, dim3(nchunks), dim3(256), 0, s, a); break;
+        case kRPY: hipLaunchKernelGGL(p2p_kernel<DRPY>, dim3(nchunks), dim3(256), 0, s, a); break;
+        case kLapPGrad: hipLaunchKernelGGL(p2p_kernel<DLapPGrad>, dim3(nchunks), dim3(256), 0, s, a); break;
+        case kPVel: hipLaunchKernelGGL(p2p_kernel<DPVel>, dim3(nchunks), dim3(256), 0, s, a); break;
+        case kTraction: hipLaunchKernelGGL(p2p_kernel<DTraction>, dim3(nchunks), dim3(256), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_s2c(int src_kind, int ntasks, const S2CArgs &a, hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
+    switch (src_kind) {
+        case 0: hipLaunchKernelGGL(s2c_kernel<0>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case 1: hipLaunchKernelGGL(s2c_kernel<1>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(s2c_kernel<2>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case 3: hipLaunchKernelGGL(s2c_kernel<3>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(s2c_kernel<4>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case 5: hipLaunchKernelGGL(s2c_kernel<5>, dim3(ntasks), dim3(256), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_f32(int ntiles, int Mp, const GemmArgs &a, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gemm_f32_mfma, dim3(ntiles, (Mp + kGT - 1) / kGT), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_f64(const Gemm64Args &a, double *C, hipStream_t s) {
+    if (a.ncol <= 0 || a.R <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gemm_f64<double>, dim3((a.R + 63) / 64, (a.ncol + 63) / 64), dim3(256), 0, s, a, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_f64_to_f32(const Gemm64Args &a, float *C, hipStream_t s) {
+    if (a.ncol <= 0 || a.R <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gemm_f64<float>, dim3((a.R + 63) / 64, (a.ncol + 63) / 64), dim3(256), 0, s, a, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(int ntasks, const ReduceArgs &a, hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_kernel, dim3(ntasks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_periodic(const double *T, const float *dens, double *chk, int M, int Mp, int nc, int root,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(periodic_kernel, dim3(blocks_for(int64_t(M) * nc, 256)), dim3(256), 0, s, T, dens, chk,
+                       M, Mp, nc, root);
+    return hipGetLastError();
+}
+
+hipError_t launch_l2t(int kernel, int nchunks, const L2TArgs &a, hipStream_t s) {
+    if (nchunks <= 0) return hipSuccess;
+    switch (kernel) {
+        case kStokeslet: hipLaunchKernelGGL(l2t_kernel<EStokeslet>, dim3(nchunks), dim3(256), 0, s, a); break;
+        case kRPY: hipLaunchKernelGGL(l2t_kernel<ERPY>, dim3(nchunks), dim3(256), 0, s, a); break;
+        case kLapPGrad: hipLaunchKernelGGL(l2t_kernel<ELapPGrad>, dim3(nchunks), dim3(256), 0, s, a); break;
+        case kPVel: hipLaunchKernelGGL(l2t_kernel<EPVel>, dim3(nchunks), dim3(256), 0, s, a); break;
+        case kTraction: hipLaunchKernelGGL(l2t_kernel<ETraction>, dim3(nchunks), dim3(256), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(int64_t n, const double *near, const double *far, const int32_t *perm, int nacc,
+                          int kt, const CombineMap &map, double *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(combine_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, near, far, perm, nacc, kt,
+                       map, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_direct_f64(int kernel, const DirectArgs &a, hipStream_t s) {
+    if (a.n_trg <= 0) return hipSuccess;
+    dim3 g(blocks_for(a.n_trg, 256));
+    switch (kernel) {
+        case kStokeslet: hipLaunchKernelGGL(direct_f64_kernel<F64Stokeslet>, g, dim3(256), 0, s, a); break;
+        case kRPY: hipLaunchKernelGGL(direct_f64_kernel<F64RPY>, g, dim3(256), 0, s, a); break;
+        case kLapPGrad: hipLaunchKernelGGL(direct_f64_kernel<F64Lap>, g, dim3(256), 0, s, a); break;
+        case kPVel: hipLaunchKernelGGL(direct_f64_kernel<F64PVel>, g, dim3(256), 0, s, a); break;
+        case kTraction: hipLaunchKernelGGL(direct_f64_kernel<F64Traction>, g, dim3(256), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace kafmm

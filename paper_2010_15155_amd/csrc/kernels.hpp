@@ -1,0 +1,118 @@
+// Argument blocks and launchers of the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace kafmm {
+
+// Packed periodic image shift: bits (2k, 2k+1) hold shift_k + 1.
+constexpr int kZeroShift = 1 | (1 << 2) | (1 << 4);
+inline int pack_shift(const int8_t s[3]) { return (s[0] + 1) | ((s[1] + 1) << 2) | ((s[2] + 1) << 4); }
+
+struct P2PArgs {
+    const int4 *chunks;        // {leaf, t0, t1, -}
+    const float *trg;          // [n_trg][8]
+    const int *u_off;          // by box id
+    const int2 *u_ent;         // {source leaf, packed shift}
+    const int2 *box_sl, *box_dl;
+    const float *sl, *dl;      // source records
+    double *out;               // [n_trg][NACC]
+};
+
+struct S2CArgs {
+    const int *dst;            // destination box per task
+    const int *list_off;       // per task: range of source entries
+    const int2 *list;          // {source leaf, packed shift}
+    const int2 *src_range;     // per box: range in the source array
+    const float *src;          // source records
+    int rec;
+    const double4 *geom;
+    const float *grid;         // [M][3] unit lattice
+    int M;
+    double alpha;              // surface radius in half box sides
+    double *chk;               // [box][ncomp][M]
+    int accumulate;
+};
+
+struct GemmArgs {
+    const int4 *tiles;         // {op, col0, ncol, -}
+    const float *ops;          // [nop][Mp][Mp]
+    const float *X;            // density columns
+    float *Y;                  // output columns
+    const int *bcol, *ycol;    // column indices (units of Mp floats)
+    int Mp;
+};
+
+struct Gemm64Args {
+    const double *A;           // [R][K] row-major, leading dimension lda
+    int R, K, lda;
+    const double *B;           // columns: B + bidx[c] * ldb
+    const int *bidx;
+    int ldb;
+    const int *cidx;           // output columns: C + cidx[c] * ldc
+    const double *cscale;      // per-column scale or null
+    int ldc;
+    int ncol;
+};
+
+struct ReduceArgs {
+    const int *dst;            // destination box per task
+    const int *off;            // per task: pair range
+    const int *pair;           // Y pair index per entry
+    const double *scale;       // per entry
+    const float *delta;        // per entry: Psi origin shift (3)
+    const float *Y;
+    double *chk;
+    int M, Mp, ncomp, accumulate;
+};
+
+struct L2TArgs {
+    const int4 *chunks;
+    const float *trg;
+    const double4 *geom;
+    const uint8_t *has_local;
+    const int *w_off;
+    const int2 *w_ent;
+    const float *grid;
+    const float *up_dens, *dn_dens;
+    int M, Mp;
+    double alpha_in, alpha_out;
+    double *out;
+};
+
+struct CombineMap {
+    int src[10];
+    double scale[10];
+};
+
+struct DirectArgs {
+    int64_t n_sl, n_dl, n_trg;
+    const double *sl, *sl_val, *dl, *dl_val, *trg;
+    int k_sl, k_dl, k_trg;
+    double *out;
+};
+
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
+hipError_t launch_pack_sources(int64_t n, const double *xyz, const double *val, const int32_t *perm,
+                               double3 origin, double inv_len, int kind, int rec, float *out, hipStream_t s);
+hipError_t launch_pack_targets(int64_t n, const double *xyz, const int32_t *perm, double3 origin,
+                               double inv_len, float *out, hipStream_t s);
+hipError_t launch_p2p(int kernel, int nchunks, const P2PArgs &a, hipStream_t s);
+hipError_t launch_s2c(int src_kind, int ntasks, const S2CArgs &a, hipStream_t s);
+hipError_t launch_gemm_f32(int ntiles, int Mp, const GemmArgs &a, hipStream_t s);
+hipError_t launch_gemm_f64(const Gemm64Args &a, double *C, hipStream_t s);
+hipError_t launch_gemm_f64_to_f32(const Gemm64Args &a, float *C, hipStream_t s);
+hipError_t launch_reduce(int ntasks, const ReduceArgs &a, hipStream_t s);
+hipError_t launch_periodic(const double *T, const float *dens, double *chk, int M, int Mp, int nc, int root,
+                           hipStream_t s);
+hipError_t launch_l2t(int kernel, int nchunks, const L2TArgs &a, hipStream_t s);
+hipError_t launch_combine(int64_t n, const double *near, const double *far, const int32_t *perm, int nacc,
+                          int kt, const CombineMap &map, double *out, hipStream_t s);
+hipError_t launch_direct_f64(int kernel, const DirectArgs &a, hipStream_t s);
+
+}  // namespace kafmm

@@ -1,0 +1,135 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+* FP64 GPU direct sum (the error judge) == oracle direct sum (round-off);
+* one leaf (leaf_cap >= N): the evaluation pass is the FP32 P2P only, so it
+  must match the direct sum to FP32 accuracy, every kernel;
+* full FMM on clustered points spanning several levels, every kernel,
+  relative L2 error per output field against the direct sum;
+* bitwise determinism of repeated runs; ragged and empty inputs.
+"""
+import numpy as np
+import pytest
+
+from oracle import direct
+from paper_2010_15155_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+KERNELS = ["Stokeslet", "RPY", "LapPGrad", "PVel", "Traction"]
+FIELDS = {"Stokeslet": [("u", 0, 3)], "RPY": [("u", 0, 3), ("lap u", 3, 6)],
+          "LapPGrad": [("phi", 0, 1), ("grad phi", 1, 4)], "PVel": [("p", 0, 1), ("u", 1, 4)],
+          "Traction": [("sigma", 0, 9)]}
+
+
+@pytest.fixture(scope="module")
+def fmm():
+    from paper_2010_15155_amd import FMM
+    assert torch.cuda.is_available()
+    f = FMM()
+    yield f
+    f.close()
+
+
+def _cuda(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def problem(kernel, n, seed, clustered=True):
+    rng = np.random.default_rng(seed)
+    if clustered:
+        x = W.gaussian_mixture_points(rng, n, 0.25 + 0.5 * rng.random((4, 3)), 0.06)
+    else:
+        x = rng.random((n, 3))
+    if kernel == "Stokeslet":
+        return dict(sl_xyz=x, sl_val=rng.standard_normal((n, 3)), trg_xyz=x)
+    if kernel == "RPY":
+        v = np.concatenate([rng.standard_normal((n, 3)), rng.uniform(0.002, 0.005, (n, 1))], 1)
+        return dict(sl_xyz=x, sl_val=v, trg_xyz=x)
+    if kernel == "LapPGrad":
+        return dict(sl_xyz=x, sl_val=rng.standard_normal((n, 1)), dl_xyz=x,
+                    dl_val=rng.standard_normal((n, 3)), trg_xyz=x)
+    y = rng.random((n // 3, 3))
+    return dict(sl_xyz=y, sl_val=rng.standard_normal((n // 3, 4)), dl_xyz=x,
+                dl_val=rng.standard_normal((n, 9)), trg_xyz=x)
+
+
+def oracle_of(kernel, pb):
+    return direct.evaluate(kernel, pb.get("sl_xyz"), pb.get("sl_val"), pb.get("dl_xyz"),
+                           pb.get("dl_val"), pb["trg_xyz"])
+
+
+def field_errors(kernel, got, ref):
+    return {name: direct.rel_l2(got[:, a:b], ref[:, a:b]) for name, a, b in FIELDS[kernel]}
+
+
+def gpu_eval(fmm, kernel, pb, p, cap):
+    args = {k: _cuda(v) for k, v in pb.items()}
+    out = fmm.evaluate(kernel, p=p, leaf_cap=cap, **args)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_direct_f64_matches_oracle(fmm, kernel):
+    pb = problem(kernel, 700, 1)
+    ref = oracle_of(kernel, pb)
+    args = {k: _cuda(v) for k, v in pb.items()}
+    got = fmm.direct(kernel, **args).cpu().numpy()
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_single_leaf_p2p(fmm, kernel):
+    pb = problem(kernel, 3000, 2)
+    ref = oracle_of(kernel, pb)
+    got = gpu_eval(fmm, kernel, pb, p=6, cap=100000)
+    errs = field_errors(kernel, got, ref)
+    print(kernel, "single leaf", errs, flush=True)
+    for e in errs.values():
+        assert e < 2e-6
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_fmm_clustered(fmm, kernel):
+    pb = problem(kernel, 24000, 3)
+    ref = oracle_of(kernel, pb)
+    got = gpu_eval(fmm, kernel, pb, p=8, cap=150)
+    st = fmm.stats()
+    errs = field_errors(kernel, got, ref)
+    print(kernel, "fmm p=8", st, errs, flush=True)
+    assert st["depth"] >= 3 and st["v_pairs"] > 0
+    for e in errs.values():
+        assert e < 1e-5
+
+
+def test_error_falls_with_order(fmm):
+    pb = problem("Stokeslet", 20000, 4)
+    ref = oracle_of("Stokeslet", pb)
+    errs = [direct.rel_l2(gpu_eval(fmm, "Stokeslet", pb, p, 100), ref) for p in (4, 6, 8)]
+    print("stokeslet p=4,6,8", errs, flush=True)
+    assert errs[0] > errs[1] > errs[2]
+
+
+def test_deterministic(fmm):
+    pb = problem("RPY", 15000, 5)
+    a = gpu_eval(fmm, "RPY", pb, 8, 120)
+    b = gpu_eval(fmm, "RPY", pb, 8, 120)
+    assert np.array_equal(a, b)
+
+
+def test_ragged_and_empty(fmm):
+    # 1 target and 1 source; a target set disjoint from the sources; no sources
+    x = np.array([[0.3, 0.4, 0.5]])
+    f = np.array([[1.0, 2.0, 3.0]])
+    out = gpu_eval(fmm, "Stokeslet", dict(sl_xyz=x, sl_val=f, trg_xyz=x), 6, 10)
+    assert np.array_equal(out, np.zeros((1, 3)))
+    rng = np.random.default_rng(9)
+    y = rng.random((777, 3))
+    t = rng.random((333, 3))
+    fv = rng.standard_normal((777, 3))
+    got = gpu_eval(fmm, "Stokeslet", dict(sl_xyz=y, sl_val=fv, trg_xyz=t), 8, 20)
+    ref = direct.stokeslet(y, fv, t)
+    assert direct.rel_l2(got, ref) < 1e-5
+    out = gpu_eval(fmm, "Stokeslet", dict(trg_xyz=t), 6, 20)
+    assert np.array_equal(out, np.zeros((333, 3)))
