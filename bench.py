@@ -80,6 +80,11 @@ def main():
         t_tree = fmm.timings()["t_tree_ms"]
         out, wall, p2p_ms, run_ms, tm = timed_steps(fmm, torch, val, args.steps, args.warmup)
         st = fmm.stats()
+        # one serial pass (P2P before the far field) for standalone stage times
+        fmm.set_option("overlap", "0")
+        fmm.run(val)
+        serial = fmm.timings()
+        fmm.set_option("overlap", "1")
         # accuracy on sampled targets against the FP64 GPU direct sum
         idx = W.sample_indices(args.n, args.samples, 7)
         ti = torch.from_numpy(idx).cuda()
@@ -91,6 +96,7 @@ def main():
                 for n, a, b in fields}
         res[kernel] = dict(ms_per_step=wall * 1e3, run_ms=run_ms, p2p_ms=p2p_ms, t_tree_ms=t_tree,
                            t_plan_ms=t_plan, stats=st, rel_l2=errs, stages_ms=tm["stages_ms"],
+                           stages_serial_ms=serial["stages_ms"], run_serial_ms=serial["t_run_ms"],
                            p2p_pairs_per_s=st["p2p_pairs"] / (p2p_ms * 1e-3), kt=kt)
         fmm.set_option("precision", "fp32")
     S = res["Stokeslet"]
@@ -118,10 +124,13 @@ def main():
         "p2p_pairs_per_s": S["p2p_pairs_per_s"],
         "t_tree_ms": S["t_tree_ms"],
         "stages_ms": S["stages_ms"],
+        "stages_serial_ms": S["stages_serial_ms"],
+        "run_serial_ms": S["run_serial_ms"],
         "plan": S["stats"],
         "rpy": {"ms_per_step": res["RPY"]["ms_per_step"], "rel_l2": res["RPY"]["rel_l2"],
                 "targets_per_s": n / (res["RPY"]["ms_per_step"] * 1e-3),
-                "p2p_pairs_per_s": res["RPY"]["p2p_pairs_per_s"], "stages_ms": res["RPY"]["stages_ms"]},
+                "p2p_pairs_per_s": res["RPY"]["p2p_pairs_per_s"], "stages_ms": res["RPY"]["stages_ms"],
+                "stages_serial_ms": res["RPY"]["stages_serial_ms"]},
         "roofline": {"kernel": "p2p_kernel<DStokeslet>", "bound": "alu", "achieved": achieved,
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,

@@ -135,21 +135,27 @@ stkfmm_status stkfmm_kernel_dims(stkfmm_kernel kernel, int *k_sl, int *k_dl, int
 
 /* Options (strings):  "precision" = "fp32" | "split_bf16"  (M2L arithmetic),
  * "svd_tol" = relative truncation of the check-to-equivalent pseudo-inverse
- * (default 1e-7).  Errors: E_ARG. */
+ * (default 1e-7), "overlap" = "1" (P2P concurrent with the far field, the
+ * default) | "0" (serial, for per-stage timing).  Errors: E_ARG. */
 stkfmm_status stkfmm_set_option(stkfmm_ctx *ctx, const char *key, const char *value);
 
 /* Timings of the last set_points (t_tree_ms) and run (t_run_ms, device event
  * time).  stage_ms[16] (may be NULL) receives per-stage device times of the
- * last run in the order: 0 pack, 1 S2M, 2 UC2UE+M2M, 3 M2L, 4 S2L(X),
- * 5 L2L+DC2DE, 6 L2T+M2T, 7 P2P, 8 combine, 9 periodic; others 0. */
+ * last run in the order: 0 pack, 1 S2M, 2 M2M+UC2UE, 3 M2L, 4 S2L (X list)
+ * and the periodic operator, 5 L2L+DC2DE, 6 L2T+M2T, 7 P2P, 8 combine;
+ * others 0.  P2P runs on an internal stream concurrently with stages 1-6
+ * unless the option "overlap" is "0". */
 stkfmm_status stkfmm_get_timings(const stkfmm_ctx *ctx, double *t_tree_ms, double *t_run_ms,
                                  double stage_ms[16]);
 
 /* Plan statistics of the last set_points; stats[16] receives:
- * 0 boxes, 1 leaves, 2 depth, 3 P2P pairs (sum over target leaves of
+ * 0 boxes, 1 leaves, 2 depth, 3 U-list pairs (sum over target leaves of
  * n_trg * sum of U-list source counts), 4 V-list pairs, 5 W-list pairs,
  * 6 X-list pairs, 7 M (points per surface), 8 n_trg, 9 n_sl, 10 n_dl,
- * 11 U-list entries; others 0.  Errors: E_ARG, E_STATE. */
+ * 11 U-list entries, 12 P2P pairs evaluated (U pairs plus the W and X
+ * pairs summed directly because that is cheaper), 13 W pairs summed
+ * directly, 14 X pairs summed directly, 15 P2P tasks.
+ * Errors: E_ARG, E_STATE. */
 stkfmm_status stkfmm_get_stats(const stkfmm_ctx *ctx, int64_t stats[16]);
 
 /* Last error message of the context (never NULL; "" if none). */

@@ -167,6 +167,6 @@ class FMM:
     def stats(self):
         a = (ctypes.c_int64 * 16)()
         self._check(lib().stkfmm_get_stats(self._h, a), "stats")
-        names = ["boxes", "leaves", "depth", "p2p_pairs", "v_pairs", "w_pairs", "x_pairs", "M",
-                 "n_trg", "n_sl", "n_dl", "u_entries"]
+        names = ["boxes", "leaves", "depth", "u_pairs", "v_pairs", "w_pairs", "x_pairs", "M",
+                 "n_trg", "n_sl", "n_dl", "u_entries", "p2p_pairs", "w_direct", "x_direct", "p2p_tasks"]
         return {n: int(a[i]) for i, n in enumerate(names)}

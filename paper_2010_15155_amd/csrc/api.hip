@@ -90,6 +90,13 @@ struct PinvLevel {
     size_t bidx = 0, didx = 0, cidx = 0, cscale = 0;
 };
 
+// Surface-tile tasks of one phase (S2M or S2L): SL tasks then DL tasks, and
+// the per-destination reduction of their partial check potentials.
+struct S2CPhase {
+    int n_sl = 0, n_dl = 0, n_dst = 0;
+    size_t tasks = 0, rdst = 0, roff = 0, rtask = 0;
+};
+
 struct Pair {
     int src, dst, op;
     float delta[3];
@@ -117,12 +124,15 @@ struct stkfmm_ctx {
     int64_t n_sl = 0, n_dl = 0, n_trg = 0;
     Tree tree;
     DeviceOps *ops = nullptr;
-    DevMem arena, sl_rec, dl_rec, trg_rec, up_dens, dn_dens, up_chk, dn_chk, Ybuf, tmp64, near_out, far_out,
-        partial;
-    size_t a_perm_sl = 0, a_perm_dl = 0, a_perm_trg = 0, a_geom = 0, a_box_sl = 0, a_box_dl = 0, a_has_local = 0,
-           a_u_off = 0, a_u_ent = 0, a_w_off = 0, a_w_ent = 0, a_chunks = 0, a_s2m_dst = 0, a_s2m_off = 0,
-           a_s2m_list = 0, a_s2l_dst = 0, a_s2l_off = 0, a_s2l_list = 0;
-    int nchunks = 0, n_s2m = 0, n_s2l = 0, nbox = 0;
+    DevMem arena, sl_rec, dl_rec, trg_rec, up_dens, dn_dens, up_chk, dn_chk, Ybuf, tmp64, near_part, far_part,
+        s2c_part, partial;
+    size_t a_perm_sl = 0, a_perm_dl = 0, a_perm_trg = 0, a_geom = 0, a_box_sl = 0, a_box_dl = 0, a_chunks = 0,
+           a_chunk_tasks = 0, a_p2p_tasks = 0, a_p2p_ent = 0, a_l2t_tasks = 0, a_l2t_ent = 0;
+    int nchunks = 0, n_p2p_tasks = 0, n_l2t_tasks = 0, nbox = 0;
+    S2CPhase s2m, s2l;
+    int64_t w_direct = 0, x_direct = 0, direct_pairs = 0;
+    int overlap = 1;
+    double w_direct_frac = 0.73, x_direct_frac = 0.5;
     Batch m2l;
     std::vector<Batch> m2m, l2l;            // by level (parent level / child level)
     std::vector<PinvLevel> upinv, dnpinv;   // by level
@@ -371,6 +381,20 @@ stkfmm_status stkfmm_set_option(stkfmm_ctx *c, const char *key, const char *valu
         else return fail(c, STKFMM_E_ARG, "precision must be fp32 or split_bf16");
         return STKFMM_OK;
     }
+    if (k == "overlap") {
+        if (v == "1") c->overlap = 1;
+        else if (v == "0") c->overlap = 0;
+        else return fail(c, STKFMM_E_ARG, "overlap must be 0 or 1");
+        return STKFMM_OK;
+    }
+    if (k == "w_direct_frac" || k == "x_direct_frac") {
+        char *end = nullptr;
+        double t = std::strtod(value, &end);
+        if (!end || *end || !(t >= 0) || !(t <= 16)) return fail(c, STKFMM_E_ARG, k + " must lie in [0, 16]");
+        (k == "w_direct_frac" ? c->w_direct_frac : c->x_direct_frac) = t;
+        c->planned = false;
+        return STKFMM_OK;
+    }
     if (k == "svd_tol") {
         char *end = nullptr;
         double t = std::strtod(value, &end);
@@ -408,6 +432,10 @@ stkfmm_status stkfmm_get_stats(const stkfmm_ctx *c, int64_t st[16]) {
     st[9] = c->n_sl;
     st[10] = c->n_dl;
     st[11] = int64_t(t.u.size());
+    st[12] = c->direct_pairs;
+    st[13] = c->w_direct;
+    st[14] = c->x_direct;
+    st[15] = c->n_p2p_tasks;
     return STKFMM_OK;
 }
 
@@ -492,48 +520,152 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     c->a_geom = ar.add(geom);
     c->a_box_sl = ar.add(bsl);
     c->a_box_dl = ar.add(bdl);
-    c->a_has_local = ar.add(t.has_local);
-    std::vector<int2> uent(t.u.size()), went(t.w.size()), xent(t.x.size());
-    for (size_t i = 0; i < t.u.size(); ++i) uent[i] = make_int2(t.u[i].box, pack_shift(t.u[i].shift));
-    for (size_t i = 0; i < t.w.size(); ++i) went[i] = make_int2(t.w[i].box, pack_shift(t.w[i].shift));
-    for (size_t i = 0; i < t.x.size(); ++i) xent[i] = make_int2(t.x[i].box, pack_shift(t.x[i].shift));
-    c->a_u_off = ar.add(t.u_off);
-    c->a_u_ent = ar.add(uent);
-    c->a_w_off = ar.add(t.w_off);
-    c->a_w_ent = ar.add(went);
-    std::vector<int4> chunks;
+    // ---- direct (P2P) lists per leaf: U, plus W and X pairs cheaper to sum directly.
+    // Per pair of points, a direct Stokes-kernel sum costs about 30 FP32
+    // operations, an M2T evaluation 22 and a surface-tile (S2L) evaluation 15,
+    // so a W pair with fewer than 0.73 M sources and an X pair whose target
+    // box holds fewer than 0.5 M targets go to P2P.  Both routes are exact or
+    // within the far-field error, so this only moves work.
+    std::vector<std::vector<int2>> dlist(nb), wkeep(nb), xkeep(nb);
+    c->w_direct = c->x_direct = 0;
+    for (int b : t.leaves) {
+        if (t.boxes[b].ntrg_sub == 0) continue;
+        for (int i = t.u_off[b]; i < t.u_off[b + 1]; ++i) dlist[b].push_back(make_int2(t.u[i].box, pack_shift(t.u[i].shift)));
+        for (int i = t.w_off[b]; i < t.w_off[b + 1]; ++i) {
+            int2 e = make_int2(t.w[i].box, pack_shift(t.w[i].shift));
+            if (double(t.boxes[e.x].nsrc_sub) < c->w_direct_frac * M) {
+                dlist[b].push_back(e);
+                ++c->w_direct;
+            } else {
+                wkeep[b].push_back(e);
+            }
+        }
+    }
+    std::vector<int> stack;
+    for (int b = 0; b < nb; ++b) {
+        if (!t.has_local[b]) continue;
+        for (int i = t.x_off[b]; i < t.x_off[b + 1]; ++i) {
+            int2 e = make_int2(t.x[i].box, pack_shift(t.x[i].shift));
+            if (double(t.boxes[b].ntrg_sub) < c->x_direct_frac * M) {
+                ++c->x_direct;
+                stack.assign(1, b);
+                while (!stack.empty()) {
+                    int q = stack.back();
+                    stack.pop_back();
+                    const Box &Q = t.boxes[q];
+                    if (Q.ntrg_sub == 0) continue;
+                    if (Q.leaf) dlist[q].push_back(e);
+                    for (int o = 0; o < 8; ++o)
+                        if (Q.child[o] >= 0) stack.push_back(Q.child[o]);
+                }
+            } else {
+                xkeep[b].push_back(e);
+            }
+        }
+    }
+    // ---- target chunks and their P2P / L2T tasks
+    constexpr int64_t kP2PTaskSources = 8192;   // sources per P2P task (balance)
+    constexpr int kL2TTaskSets = 4;              // equivalent-point sets per L2T task
+    std::vector<int4> chunks, chunk_tasks, p2p_tasks, l2t_tasks;
+    std::vector<int2> p2p_ent, l2t_ent;
+    c->direct_pairs = 0;
     for (int b : t.leaves) {
         const Box &B = t.boxes[b];
-        for (int64_t t0i = B.trg[0]; t0i < B.trg[1]; t0i += 256)
+        if (B.trg[1] == B.trg[0]) continue;
+        const int e0 = int(p2p_ent.size());
+        p2p_ent.insert(p2p_ent.end(), dlist[b].begin(), dlist[b].end());
+        const int e1 = int(p2p_ent.size());
+        const int q0 = int(l2t_ent.size());
+        if (t.has_local[b]) l2t_ent.push_back(make_int2(b, kLocalSet));
+        l2t_ent.insert(l2t_ent.end(), wkeep[b].begin(), wkeep[b].end());
+        const int q1 = int(l2t_ent.size());
+        int64_t nsrc_all = 0;
+        for (int e = e0; e < e1; ++e) nsrc_all += t.boxes[p2p_ent[e].x].nsrc_sub;
+        c->direct_pairs += nsrc_all * (B.trg[1] - B.trg[0]);
+        for (int64_t t0i = B.trg[0]; t0i < B.trg[1]; t0i += 256) {
+            const int ci = int(chunks.size());
             chunks.push_back(make_int4(b, int(t0i), int(std::min<int64_t>(t0i + 256, B.trg[1])), 0));
+            int4 ct;
+            ct.x = int(p2p_tasks.size());
+            int64_t acc = 0;
+            int es = e0;
+            for (int e = e0; e < e1; ++e) {
+                int64_t n = t.boxes[p2p_ent[e].x].nsrc_sub;
+                if (acc > 0 && acc + n > kP2PTaskSources) {
+                    p2p_tasks.push_back(make_int4(ci, es, e, 0));
+                    es = e;
+                    acc = 0;
+                }
+                acc += n;
+            }
+            if (e1 > es) p2p_tasks.push_back(make_int4(ci, es, e1, 0));
+            ct.y = int(p2p_tasks.size());
+            ct.z = int(l2t_tasks.size());
+            for (int q = q0; q < q1; q += kL2TTaskSets) l2t_tasks.push_back(make_int4(ci, q, std::min(q1, q + kL2TTaskSets), 0));
+            ct.w = int(l2t_tasks.size());
+            chunk_tasks.push_back(ct);
+        }
     }
     c->nchunks = int(chunks.size());
+    c->n_p2p_tasks = int(p2p_tasks.size());
+    c->n_l2t_tasks = int(l2t_tasks.size());
     c->a_chunks = ar.add(chunks);
-    // S2M tasks: every leaf with sources; S2L tasks: every box with an X list
-    std::vector<int> s2m_dst, s2m_off, s2l_dst, s2l_off;
-    std::vector<int2> s2m_list, s2l_list;
-    for (int b : t.leaves) {
-        if (t.boxes[b].nsrc_sub == 0) continue;
-        s2m_dst.push_back(b);
-        s2m_off.push_back(int(s2m_list.size()));
-        s2m_list.push_back(make_int2(b, kZeroShift));
+    c->a_chunk_tasks = ar.add(chunk_tasks);
+    c->a_p2p_tasks = ar.add(p2p_tasks);
+    c->a_p2p_ent = ar.add(p2p_ent);
+    c->a_l2t_tasks = ar.add(l2t_tasks);
+    c->a_l2t_ent = ar.add(l2t_ent);
+    // ---- surface-tile tasks: S2M (each leaf's own sources) and S2L (kept X pairs)
+    constexpr int kS2CTaskSources = 1024;
+    size_t s2c_tasks_max = 0;
+    auto make_phase = [&](const std::vector<std::pair<int, std::vector<int2>>> &dst_src) {
+        S2CPhase ph;
+        std::vector<int4> tsl, tdl;
+        std::vector<std::vector<int>> own_sl(dst_src.size()), own_dl(dst_src.size());
+        for (size_t d = 0; d < dst_src.size(); ++d) {
+            const int dst = dst_src[d].first;
+            for (const int2 &e : dst_src[d].second) {
+                const Box &A = t.boxes[e.x];
+                for (int64_t j = A.sl[0]; j < A.sl[1]; j += kS2CTaskSources) {
+                    own_sl[d].push_back(int(tsl.size()));
+                    tsl.push_back(make_int4(dst, e.y, int(j), int(std::min<int64_t>(j + kS2CTaskSources, A.sl[1]))));
+                }
+                for (int64_t j = A.dl[0]; j < A.dl[1]; j += kS2CTaskSources) {
+                    own_dl[d].push_back(int(tdl.size()));
+                    tdl.push_back(make_int4(dst, e.y, int(j), int(std::min<int64_t>(j + kS2CTaskSources, A.dl[1]))));
+                }
+            }
+        }
+        ph.n_sl = int(tsl.size());
+        ph.n_dl = int(tdl.size());
+        std::vector<int4> all(tsl);
+        all.insert(all.end(), tdl.begin(), tdl.end());
+        std::vector<int> rdst, roff, rtask;
+        for (size_t d = 0; d < dst_src.size(); ++d) {
+            if (own_sl[d].empty() && own_dl[d].empty()) continue;
+            rdst.push_back(dst_src[d].first);
+            roff.push_back(int(rtask.size()));
+            rtask.insert(rtask.end(), own_sl[d].begin(), own_sl[d].end());
+            for (int q : own_dl[d]) rtask.push_back(ph.n_sl + q);
+        }
+        roff.push_back(int(rtask.size()));
+        ph.n_dst = int(rdst.size());
+        ph.tasks = ar.add(all);
+        ph.rdst = ar.add(rdst);
+        ph.roff = ar.add(roff);
+        ph.rtask = ar.add(rtask);
+        s2c_tasks_max = std::max(s2c_tasks_max, all.size());
+        return ph;
+    };
+    {
+        std::vector<std::pair<int, std::vector<int2>>> up, dn;
+        for (int b : t.leaves)
+            if (t.boxes[b].nsrc_sub > 0) up.push_back({b, {make_int2(b, kZeroShift)}});
+        for (int b = 0; b < nb; ++b)
+            if (t.has_local[b] && !xkeep[b].empty()) dn.push_back({b, xkeep[b]});
+        c->s2m = make_phase(up);
+        c->s2l = make_phase(dn);
     }
-    s2m_off.push_back(int(s2m_list.size()));
-    for (int b = 0; b < nb; ++b) {
-        if (t.x_off[b + 1] == t.x_off[b] || !t.has_local[b]) continue;
-        s2l_dst.push_back(b);
-        s2l_off.push_back(int(s2l_list.size()));
-        for (int i = t.x_off[b]; i < t.x_off[b + 1]; ++i) s2l_list.push_back(xent[i]);
-    }
-    s2l_off.push_back(int(s2l_list.size()));
-    c->n_s2m = int(s2m_dst.size());
-    c->n_s2l = int(s2l_dst.size());
-    c->a_s2m_dst = ar.add(s2m_dst);
-    c->a_s2m_off = ar.add(s2m_off);
-    c->a_s2m_list = ar.add(s2m_list);
-    c->a_s2l_dst = ar.add(s2l_dst);
-    c->a_s2l_off = ar.add(s2l_off);
-    c->a_s2l_list = ar.add(s2l_list);
 
     // levels carrying equivalent densities
     c->lmin_up = periodic ? 0 : 2;
@@ -643,8 +775,9 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     HIP_TRY(c, c->dn_chk.ensure(size_t(nb) * nc * M * sizeof(double)));
     HIP_TRY(c, c->Ybuf.ensure(std::max<size_t>(c->ybuf_floats, 1) * sizeof(float)));
     HIP_TRY(c, c->tmp64.ensure(std::max<size_t>(c->tmp_doubles, 1) * sizeof(double)));
-    HIP_TRY(c, c->near_out.ensure(size_t(std::max<int64_t>(n_trg, 1)) * ki.kt_acc * sizeof(double)));
-    HIP_TRY(c, c->far_out.ensure(size_t(std::max<int64_t>(n_trg, 1)) * ki.kt_acc * sizeof(double)));
+    HIP_TRY(c, c->near_part.ensure(size_t(std::max(c->n_p2p_tasks, 1)) * 256 * ki.kt_acc * sizeof(double)));
+    HIP_TRY(c, c->far_part.ensure(size_t(std::max(c->n_l2t_tasks, 1)) * 256 * ki.kt_acc * sizeof(double)));
+    HIP_TRY(c, c->s2c_part.ensure(std::max<size_t>(s2c_tasks_max, 1) * nc * M * sizeof(float)));
     HIP_TRY(c, c->partial.ensure(4096 * sizeof(double)));
     // densities: padding rows stay zero (the GEMM reads Mp rows)
     HIP_TRY(c, launch_fill_f32(c->up_dens.as<float>(), int64_t(nb) * nc * Mp, 0.0f, s));
@@ -821,55 +954,63 @@ stkfmm_status stkfmm_run(stkfmm_ctx *c, const double *sl_val, const double *dl_v
         HIP_TRY(c, hipGetLastError());
     }
     HIP_TRY(c, hipEventRecord(ev[ne++], s));                  // 1 packed
-    // ---- near field on the side stream
-    HIP_TRY(c, hipStreamWaitEvent(c->side, ev[1], 0));
-    HIP_TRY(c, hipEventRecord(ev[20], c->side));
+    // ---- near field: on the side stream (overlapping the far field) or first on s
+    hipStream_t ps = c->overlap ? c->side : s;
+    if (c->overlap) HIP_TRY(c, hipStreamWaitEvent(c->side, ev[1], 0));
+    HIP_TRY(c, hipEventRecord(ev[20], ps));
     {
         P2PArgs a;
+        a.tasks = at<int4>(c, c->a_p2p_tasks);
         a.chunks = at<int4>(c, c->a_chunks);
         a.trg = c->trg_rec.as<float>();
-        a.u_off = at<int>(c, c->a_u_off);
-        a.u_ent = at<int2>(c, c->a_u_ent);
+        a.ent = at<int2>(c, c->a_p2p_ent);
         a.box_sl = at<int2>(c, c->a_box_sl);
         a.box_dl = at<int2>(c, c->a_box_dl);
         a.sl = c->sl_rec.as<float>();
         a.dl = c->dl_rec.as<float>();
-        a.out = c->near_out.as<double>();
-        HIP_TRY(c, launch_p2p(c->kernel, c->nchunks, a, c->side));
+        a.part = c->near_part.as<double>();
+        HIP_TRY(c, launch_p2p(c->kernel, c->n_p2p_tasks, a, ps));
     }
-    HIP_TRY(c, hipEventRecord(ev[21], c->side));
+    HIP_TRY(c, hipEventRecord(ev[21], ps));
+    if (!c->overlap) HIP_TRY(c, hipEventRecord(ev[1], s));   // far-field stages start after P2P
     // ---- far field
     const bool far = t.depth >= 2 || periodic;
     double *upchk = c->up_chk.as<double>(), *dnchk = c->dn_chk.as<double>();
     float *updens = c->up_dens.as<float>(), *dndens = c->dn_dens.as<float>();
-    auto s2c = [&](int task_n, size_t dst, size_t off, size_t list, double alpha, double *chk, int acc_first) {
+    auto s2c = [&](const S2CPhase &ph, double alpha, double *chk, int accumulate) -> hipError_t {
         S2CArgs a;
-        a.dst = at<int>(c, dst);
-        a.list_off = at<int>(c, off);
-        a.list = at<int2>(c, list);
+        a.tasks = at<int4>(c, ph.tasks);
         a.geom = at<double4>(c, c->a_geom);
         a.grid = o.grid.as<float>();
         a.M = o.M;
         a.alpha = alpha;
-        a.chk = chk;
-        a.src_range = at<int2>(c, c->a_box_sl);
+        a.part = c->s2c_part.as<float>();
         a.src = c->sl_rec.as<float>();
         a.rec = ki.rec_sl;
-        a.accumulate = acc_first;
-        hipError_t e = launch_s2c(sl_kind(c->kernel), task_n, a, s);
+        hipError_t e = launch_s2c(sl_kind(c->kernel), ph.n_sl, a, s);
         if (e != hipSuccess) return e;
-        if (ki.k_dl > 0 && c->n_dl > 0) {
-            a.src_range = at<int2>(c, c->a_box_dl);
+        if (ph.n_dl > 0) {
+            a.tasks = at<int4>(c, ph.tasks) + ph.n_sl;
+            a.part = c->s2c_part.as<float>() + int64_t(ph.n_sl) * nc * o.M;
             a.src = c->dl_rec.as<float>();
             a.rec = ki.rec_dl;
-            a.accumulate = 1;
-            e = launch_s2c(dl_kind(c->kernel), task_n, a, s);
+            e = launch_s2c(dl_kind(c->kernel), ph.n_dl, a, s);
+            if (e != hipSuccess) return e;
         }
-        return e;
+        S2CReduceArgs r;
+        r.dst = at<int>(c, ph.rdst);
+        r.off = at<int>(c, ph.roff);
+        r.task = at<int>(c, ph.rtask);
+        r.part = c->s2c_part.as<float>();
+        r.chk = chk;
+        r.M = o.M;
+        r.ncomp = nc;
+        r.accumulate = accumulate;
+        return launch_s2c_reduce(ph.n_dst, r, s);
     };
     if (far) {
         // upward pass
-        HIP_TRY(c, s2c(c->n_s2m, c->a_s2m_dst, c->a_s2m_off, c->a_s2m_list, kAlphaOut, upchk, 0));
+        HIP_TRY(c, s2c(c->s2m, kAlphaOut, upchk, 0));
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 2 S2M
         for (int l = t.depth; l >= c->lmin_up; --l) {
             if (l < t.depth) {
@@ -884,7 +1025,7 @@ stkfmm_status stkfmm_run(stkfmm_ctx *c, const double *sl_val, const double *dl_v
         stkfmm_status st = run_batch(c, c->m2l, o.m2l.as<float>(), updens, dnchk, s);
         if (st != STKFMM_OK) return st;
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 4 M2L
-        HIP_TRY(c, s2c(c->n_s2l, c->a_s2l_dst, c->a_s2l_off, c->a_s2l_list, kAlphaIn, dnchk, 1));
+        HIP_TRY(c, s2c(c->s2l, kAlphaIn, dnchk, 1));
         if (periodic) HIP_TRY(c, launch_periodic(o.tm2l.as<double>(), updens, dnchk, o.M, o.Mp, nc, 0, s));
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 5 S2L + periodic
         for (int l = c->lmin_dn; l <= t.depth; ++l) {
@@ -895,12 +1036,11 @@ stkfmm_status stkfmm_run(stkfmm_ctx *c, const double *sl_val, const double *dl_v
         }
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 6 downward
         L2TArgs a;
+        a.tasks = at<int4>(c, c->a_l2t_tasks);
         a.chunks = at<int4>(c, c->a_chunks);
         a.trg = c->trg_rec.as<float>();
         a.geom = at<double4>(c, c->a_geom);
-        a.has_local = at<uint8_t>(c, c->a_has_local);
-        a.w_off = at<int>(c, c->a_w_off);
-        a.w_ent = at<int2>(c, c->a_w_ent);
+        a.ent = at<int2>(c, c->a_l2t_ent);
         a.grid = o.grid.as<float>();
         a.up_dens = updens;
         a.dn_dens = dndens;
@@ -908,28 +1048,37 @@ stkfmm_status stkfmm_run(stkfmm_ctx *c, const double *sl_val, const double *dl_v
         a.Mp = o.Mp;
         a.alpha_in = kAlphaIn;
         a.alpha_out = kAlphaOut;
-        a.out = c->far_out.as<double>();
-        HIP_TRY(c, launch_l2t(c->kernel, c->nchunks, a, s));
+        a.part = c->far_part.as<double>();
+        HIP_TRY(c, launch_l2t(c->kernel, c->n_l2t_tasks, a, s));
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 7 L2T
     }
-    HIP_TRY(c, hipStreamWaitEvent(s, ev[21], 0));
+    if (c->overlap) HIP_TRY(c, hipStreamWaitEvent(s, ev[21], 0));
     HIP_TRY(c, hipEventRecord(ev[ne++], s));
-    CombineMap map = combine_map(c->kernel, c->box_len);
-    HIP_TRY(c, launch_combine(c->n_trg, c->near_out.as<double>(), far ? c->far_out.as<double>() : nullptr,
-                              at<int32_t>(c, c->a_perm_trg), ki.kt_acc, ki.k_trg, map, trg_val, s));
+    {
+        CombineArgs a;
+        a.chunks = at<int4>(c, c->a_chunks);
+        a.chunk_tasks = at<int4>(c, c->a_chunk_tasks);
+        a.near = c->near_part.as<double>();
+        a.far = c->far_part.as<double>();
+        a.perm = at<int32_t>(c, c->a_perm_trg);
+        a.nacc = ki.kt_acc;
+        a.kt = ki.k_trg;
+        a.map = combine_map(c->kernel, c->box_len);
+        a.out = trg_val;
+        HIP_TRY(c, launch_combine(c->nchunks, a, s));
+    }
     HIP_TRY(c, hipEventRecord(ev[ne++], s));                  // end
     HIP_TRY(c, hipStreamSynchronize(s));
     float ms = 0;
     HIP_TRY(c, hipEventElapsedTime(&ms, ev[0], ev[ne - 1]));
     c->t_run_ms = ms;
     std::memset(c->stage_ms, 0, sizeof(c->stage_ms));
-    HIP_TRY(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
+    HIP_TRY(c, hipEventElapsedTime(&ms, ev[0], c->overlap ? ev[1] : ev[20]));
     c->stage_ms[0] = ms;
     if (far) {
-        const int map_idx[6] = {1, 2, 3, 4, 5, 6};   // S2M, upward, M2L, S2L(+periodic), downward, L2T
-        for (int i = 0; i < 6; ++i) {
+        for (int i = 0; i < 6; ++i) {   // S2M, upward, M2L, S2L(+periodic), downward, L2T
             HIP_TRY(c, hipEventElapsedTime(&ms, ev[1 + i], ev[2 + i]));
-            c->stage_ms[map_idx[i]] = ms;
+            c->stage_ms[1 + i] = ms;
         }
     }
     HIP_TRY(c, hipEventElapsedTime(&ms, ev[20], ev[21]));

@@ -117,12 +117,17 @@ __global__ void pack_targets(int64_t n, const double *__restrict__ xyz, const in
     reinterpret_cast<float4 *>(out)[2 * i + 1] = lo;
 }
 
-// ------------------------------------------------------------------ P2P (S->T over U lists)
-// FP32 pair arithmetic on hi/lo coordinate differences; each run of 64
-// sources is summed in FP32 and added to FP64 accumulators.
+// ------------------------------------------------------------------ P2P (S->T over direct lists)
+// One block per task: up to 256 targets of one leaf (one per lane) against a
+// slice of the leaf's direct list (U list plus W/X pairs evaluated directly).
+// Source records are wave-uniform, so they arrive through scalar loads.  FP32
+// pair arithmetic on hi/lo coordinate differences; each run of 64 sources is
+// summed in FP32 and added to FP64 accumulators; the task writes its partial
+// sums, which the combine step adds in task order.
 template <class K>
 __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs a) {
-    const int4 ch = a.chunks[blockIdx.x];
+    const int4 task = a.tasks[blockIdx.x];
+    const int4 ch = a.chunks[task.x];
     const int first = ch.y + int(threadIdx.x & ~63u);
     if (first >= ch.z) return;                       // whole wave idle
     const int t = ch.y + int(threadIdx.x);
@@ -133,9 +138,8 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs a) {
     double acc[K::NACC];
 #pragma unroll
     for (int k = 0; k < K::NACC; ++k) acc[k] = 0.0;
-    const int e0 = a.u_off[ch.x], e1 = a.u_off[ch.x + 1];
-    for (int e = e0; e < e1; ++e) {
-        const int2 en = a.u_ent[e];
+    for (int e = task.y; e < task.z; ++e) {
+        const int2 en = a.ent[e];
         float xh = p0.x, yh = p0.y, zh = p0.z, xl = p1.x, yl = p1.y, zl = p1.z;
         if (en.y != kZeroShift) {
             int sx = shift_comp(en.y, 0), sy = shift_comp(en.y, 1), sz = shift_comp(en.y, 2);
@@ -183,7 +187,7 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs a) {
         }
     }
     if (active) {
-        double *o = a.out + int64_t(t) * K::NACC;
+        double *o = a.part + (int64_t(blockIdx.x) * 256 + threadIdx.x) * K::NACC;
 #pragma unroll
         for (int k = 0; k < K::NACC; ++k) o[k] = acc[k];
     }
@@ -240,10 +244,10 @@ __global__ __launch_bounds__(256) void s2c_kernel(S2CArgs a) {
     constexpr int NV = 3 + (T::CHG ? NC : 0) + (T::DIP ? 3 * NC : 0);
     constexpr int PTS = 6;                         // check points per thread (M <= 1536)
     __shared__ float tile[kS2CTile * NV];
-    const int task = blockIdx.x;
-    const int dst = a.dst[task];
-    const double4 cb = a.geom[dst];
+    const int4 task = a.tasks[blockIdx.x];         // {dst, shift, j0, j1}
+    const double4 cb = a.geom[task.x];
     const float rad = float(a.alpha * 0.5 * cb.w);
+    const int npts = (a.M + 255) / 256;
     float zx[PTS], zy[PTS], zz[PTS], pot[PTS][NC];
 #pragma unroll
     for (int i = 0; i < PTS; ++i) {
@@ -255,64 +259,69 @@ __global__ __launch_bounds__(256) void s2c_kernel(S2CArgs a) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) pot[i][c] = 0.0f;
     }
-    const int npts = (a.M + 255) / 256;
-    const int l0 = a.list_off[task], l1 = a.list_off[task + 1];
-    for (int l = l0; l < l1; ++l) {
-        const int2 en = a.list[l];
-        const int2 rng = a.src_range[en.x];
-        const double sx = shift_comp(en.y, 0) - cb.x, sy = shift_comp(en.y, 1) - cb.y,
-                     sz = shift_comp(en.y, 2) - cb.z;
-        for (int j0 = rng.x; j0 < rng.y; j0 += kS2CTile) {
-            const int n = min(kS2CTile, rng.y - j0);
-            __syncthreads();
-            if (int(threadIdx.x) < n) {
-                const float *s = a.src + int64_t(j0 + threadIdx.x) * a.rec;
-                float yx = float((double(s[0]) + double(s[3])) + sx);
-                float yy = float((double(s[1]) + double(s[4])) + sy);
-                float yz = float((double(s[2]) + double(s[5])) + sz);
-                float q[4] = {0, 0, 0, 0}, d[12];
-                stage_source<SRC>(s, yx, yy, yz, q, d);
-                float *o = tile + threadIdx.x * NV;
-                o[0] = yx; o[1] = yy; o[2] = yz;
-                int k = 3;
-                if (T::CHG)
-                    for (int c = 0; c < NC; ++c) o[k++] = q[c];
-                if (T::DIP)
-                    for (int c = 0; c < 3 * NC; ++c) o[k++] = d[(NC == 4 ? 0 : 0) + c];
-            }
-            __syncthreads();
-            for (int j = 0; j < n; ++j) {
-                const float *y = tile + j * NV;
+    const double sx = shift_comp(task.y, 0) - cb.x, sy = shift_comp(task.y, 1) - cb.y,
+                 sz = shift_comp(task.y, 2) - cb.z;
+    for (int j0 = task.z; j0 < task.w; j0 += kS2CTile) {
+        const int n = min(kS2CTile, task.w - j0);
+        __syncthreads();
+        if (int(threadIdx.x) < n) {
+            const float *s = a.src + int64_t(j0 + threadIdx.x) * a.rec;
+            float yx = float((double(s[0]) + double(s[3])) + sx);
+            float yy = float((double(s[1]) + double(s[4])) + sy);
+            float yz = float((double(s[2]) + double(s[5])) + sz);
+            float q[4] = {0, 0, 0, 0}, d[12];
+            stage_source<SRC>(s, yx, yy, yz, q, d);
+            float *o = tile + threadIdx.x * NV;
+            o[0] = yx; o[1] = yy; o[2] = yz;
+            int k = 3;
+            if (T::CHG)
+                for (int c = 0; c < NC; ++c) o[k++] = q[c];
+            if (T::DIP)
+                for (int c = 0; c < 3 * NC; ++c) o[k++] = d[c];
+        }
+        __syncthreads();
+        for (int j = 0; j < n; ++j) {
+            const float *y = tile + j * NV;
 #pragma unroll
-                for (int i = 0; i < PTS; ++i) {
-                    if (i >= npts) break;
-                    float dx = zx[i] - y[0], dy = zy[i] - y[1], dz = zz[i] - y[2];
-                    float ri = rsq_or_zero(dx * dx + dy * dy + dz * dz);
-                    float ri3 = ri * ri * ri;
+            for (int i = 0; i < PTS; ++i) {
+                if (i >= npts) break;
+                float dx = zx[i] - y[0], dy = zy[i] - y[1], dz = zz[i] - y[2];
+                float ri = rsq_or_zero(dx * dx + dy * dy + dz * dz);
+                float ri3 = ri * ri * ri;
 #pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        float v = 0.0f;
-                        if (T::CHG) v += y[3 + c] * ri;
-                        if (T::DIP) {
-                            const float *dd = y + 3 + (T::CHG ? NC : 0) + 3 * c;
-                            v += (dd[0] * dx + dd[1] * dy + dd[2] * dz) * ri3;
-                        }
-                        pot[i][c] += v;
+                for (int c = 0; c < NC; ++c) {
+                    float v = 0.0f;
+                    if (T::CHG) v += y[3 + c] * ri;
+                    if (T::DIP) {
+                        const float *dd = y + 3 + (T::CHG ? NC : 0) + 3 * c;
+                        v += (dd[0] * dx + dd[1] * dy + dd[2] * dz) * ri3;
                     }
+                    pot[i][c] += v;
                 }
             }
         }
     }
+    float *o = a.part + int64_t(blockIdx.x) * NC * a.M;
 #pragma unroll
     for (int i = 0; i < PTS; ++i) {
         int m = int(threadIdx.x) + 256 * i;
         if (m >= a.M) continue;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            double *o = a.chk + (int64_t(dst) * NC + c) * a.M + m;
-            double v = double(pot[i][c]) * kInv4Pi;
-            *o = a.accumulate ? *o + v : v;
-        }
+        for (int c = 0; c < NC; ++c) o[c * a.M + m] = pot[i][c];
+    }
+}
+
+// chk[dst][c][m] (+)= (1/4 pi) sum over the dst's tasks of part[task][c][m], in task order
+__global__ __launch_bounds__(256) void s2c_reduce(S2CReduceArgs a) {
+    const int dst = a.dst[blockIdx.x];
+    const int t0 = a.off[blockIdx.x], t1 = a.off[blockIdx.x + 1];
+    const int n = a.ncomp * a.M;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double acc = 0.0;
+        for (int t = t0; t < t1; ++t) acc += double(a.part[int64_t(a.task[t]) * n + i]);
+        double *o = a.chk + int64_t(dst) * n + i;
+        acc *= kInv4Pi;
+        *o = a.accumulate ? *o + acc : acc;
     }
 }
 
@@ -413,54 +422,80 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma(GemmArgs a) {
 
 // ------------------------------------------------------------------ FP64 GEMM (pseudo-inverse)
 // C[col][i] = scale(col) * sum_k A[i][k] * B[col][k],  i < R, k < K.
-// B columns are FP64 (check values) or FP64 scratch; C is FP64 scratch or
-// FP32 densities.  Tile 64 rows x 64 columns, K steps of 16, 4x4 per thread.
+// B columns are FP64 (check values or scratch); C is FP64 scratch or FP32
+// densities.  Block tile 64 rows x 64 columns, 4 waves in 2x2 each owning
+// 32x32 as 2x2 v_mfma_f64_16x16x4f64 tiles, K staged through LDS by 16.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
 template <typename TC>
 __global__ __launch_bounds__(256) void gemm_f64(Gemm64Args a, TC *C) {
-    __shared__ double As[64][17];
-    __shared__ double Bs[64][17];
+    __shared__ double As[64 * 17];
+    __shared__ double Bs[64 * 17];
     const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;
-    const int tid = threadIdx.x;
-    const int tr = (tid >> 4) * 4, tc = (tid & 15) * 4;
-    double acc[4][4] = {};
-    for (int k0 = 0; k0 < a.K; k0 += 16) {
-        for (int i = tid; i < 64 * 16; i += 256) {
-            int r = i >> 4, k = i & 15;
-            As[r][k] = (row0 + r < a.R && k0 + k < a.K) ? a.A[int64_t(row0 + r) * a.lda + k0 + k] : 0.0;
-            int c = col0 + r;
-            double b = 0.0;
-            if (c < a.ncol && k0 + k < a.K) {
-                int bc = a.bidx[c];
-                b = a.B[int64_t(bc) * a.ldb + k0 + k];
-            }
-            Bs[r][k] = b;
-        }
-        __syncthreads();
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    doublex4 acc[2][2];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            double av[4], bv[4];
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = As[tr + i][k];
+        for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+    // each thread stages 4 elements of A and of B per K step
+    const double *bcol[4];
+    int lr[4], lk[4];
+    bool rok[4], cok[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = Bs[tc + j][k];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
-        }
-        __syncthreads();
+    for (int i = 0; i < 4; ++i) {
+        int idx = tid + 256 * i;
+        lr[i] = idx >> 4;
+        lk[i] = idx & 15;
+        rok[i] = row0 + lr[i] < a.R;
+        cok[i] = col0 + lr[i] < a.ncol;
+        bcol[i] = a.B + int64_t(cok[i] ? a.bidx[col0 + lr[i]] : 0) * a.ldb;
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        int c = col0 + tc + j;
-        if (c >= a.ncol) continue;
-        double s = a.cscale ? a.cscale[c] : 1.0;
-        TC *o = C + int64_t(a.cidx[c]) * a.ldc;
+    for (int k0 = 0; k0 < a.K; k0 += 16) {
+        double ra[4], rb[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            int r = row0 + tr + i;
-            if (r < a.R) o[r] = TC(s * acc[i][j]);
+            const int k = k0 + lk[i];
+            ra[i] = (rok[i] && k < a.K) ? a.A[int64_t(row0 + lr[i]) * a.lda + k] : 0.0;
+            rb[i] = (cok[i] && k < a.K) ? bcol[i][k] : 0.0;
         }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            As[lr[i] * 17 + lk[i]] = ra[i];
+            Bs[lr[i] * 17 + lk[i]] = rb[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            const int k = kk + (lane >> 4);
+            double av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) av[i] = As[(wr + 16 * i + (lane & 15)) * 17 + k];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bv[j] = Bs[(wc + 16 * j + (lane & 15)) * 17 + k];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    // lane holds column (lane & 15) and rows (lane/16) + 4 v of each 16x16 tile
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int c = col0 + wc + 16 * j + (lane & 15);
+        if (c >= a.ncol) continue;
+        const double s = a.cscale ? a.cscale[c] : 1.0;
+        TC *o = C + int64_t(a.cidx[c]) * a.ldc;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = row0 + wr + 16 * i + (lane >> 4) + 4 * v;
+                if (r < a.R) o[r] = TC(s * acc[i][j][v]);
+            }
     }
 }
 
@@ -509,15 +544,18 @@ __global__ __launch_bounds__(256) void periodic_kernel(const double *__restrict_
 }
 
 // ------------------------------------------------------------------ L2T / M2T
-// Target values from equivalent densities: the target leaf's downward
-// equivalent points (radius a_out) and the upward equivalent points of its
-// W-list boxes (radius a_in), staged through LDS 256 points at a time.
+// Target values from equivalent densities.  A task is up to 256 targets of a
+// leaf against a slice of its equivalent-point sets: the leaf's own downward
+// set (radius a_out, entry code kLocalSet) and upward sets of W-list boxes
+// (radius a_in, image shift in the code), staged through LDS 256 points at a
+// time.  Partial sums per task, added by the combine step.
 template <class E>
 __global__ __launch_bounds__(256) void l2t_kernel(L2TArgs a) {
     constexpr int NC = E::NC;
     constexpr int NV = 3 + NC;
     __shared__ float tile[256 * NV];
-    const int4 ch = a.chunks[blockIdx.x];
+    const int4 task = a.tasks[blockIdx.x];
+    const int4 ch = a.chunks[task.x];
     const int leaf = ch.x;
     const int t = ch.y + int(threadIdx.x);
     const bool active = t < ch.z;
@@ -532,28 +570,20 @@ __global__ __launch_bounds__(256) void l2t_kernel(L2TArgs a) {
     double acc[E::NACC];
 #pragma unroll
     for (int k = 0; k < E::NACC; ++k) acc[k] = 0.0;
-    const int nsrc = (a.has_local[leaf] ? 1 : 0) + (a.w_off[leaf + 1] - a.w_off[leaf]);
-    for (int si = 0; si < nsrc; ++si) {
-        int box;
-        double alpha;
-        double ox = 0, oy = 0, oz = 0;      // box centre (image) relative to the leaf centre
-        const float *dens;
-        if (si == 0 && a.has_local[leaf]) {
-            box = leaf;
-            alpha = a.alpha_out;
-            dens = a.dn_dens;
-        } else {
-            const int2 en = a.w_ent[a.w_off[leaf] + si - (a.has_local[leaf] ? 1 : 0)];
-            box = en.x;
-            alpha = a.alpha_in;
-            dens = a.up_dens;
-            const double4 g = a.geom[box];
+    for (int e = task.y; e < task.z; ++e) {
+        const int2 en = a.ent[e];
+        const int box = en.x;
+        const bool local = en.y == kLocalSet;
+        const double4 g = a.geom[box];
+        double ox = 0, oy = 0, oz = 0;      // set's box centre (image) relative to the leaf centre
+        if (!local) {
             ox = (g.x + shift_comp(en.y, 0)) - cb.x;
             oy = (g.y + shift_comp(en.y, 1)) - cb.y;
             oz = (g.z + shift_comp(en.y, 2)) - cb.z;
         }
-        const double rad = alpha * 0.5 * a.geom[box].w;
-        // s = psi - (x - c_origin).phi with the origin at the equivalent box centre
+        const double rad = (local ? a.alpha_out : a.alpha_in) * 0.5 * g.w;
+        const float *dens = local ? a.dn_dens : a.up_dens;
+        // s = psi - (x - c_origin).phi with the origin at the set's box centre
         const float cx = xr - float(ox), cy = yr - float(oy), cz = zr - float(oz);
         float part[E::NACC];
 #pragma unroll
@@ -584,26 +614,35 @@ __global__ __launch_bounds__(256) void l2t_kernel(L2TArgs a) {
         for (int k = 0; k < E::NACC; ++k) acc[k] += double(part[k]);
     }
     if (active) {
-        double *o = a.out + int64_t(t) * E::NACC;
+        double *o = a.part + (int64_t(blockIdx.x) * 256 + threadIdx.x) * E::NACC;
 #pragma unroll
         for (int k = 0; k < E::NACC; ++k) o[k] = acc[k];
     }
 }
 
 // ------------------------------------------------------------------ combine + un-permute
-// user[perm[i]][k] = scale_k * (near[i][src_k] + far[i][src_k]); a negative
-// src_k selects nothing (0).  Symmetric tensors are expanded by the map.
-__global__ void combine_kernel(int64_t n, const double *__restrict__ near, const double *__restrict__ far,
-                               const int32_t *__restrict__ perm, int nacc, int kt, CombineMap map,
-                               double *__restrict__ out) {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double *o = out + int64_t(perm[i]) * kt;
-    for (int k = 0; k < kt; ++k) {
-        int s = map.src[k];
-        double v = 0.0;
-        if (s >= 0) v = near[i * nacc + s] + (far ? far[i * nacc + s] : 0.0);
-        o[k] = map.scale[k] * v;
+// One block per target chunk.  user[perm[t]][k] = scale_k * (sum of the
+// chunk's P2P task partials + sum of its L2T task partials) at component
+// src_k (a negative src_k gives 0); symmetric tensors are expanded by the map.
+__global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
+    const int4 ch = a.chunks[blockIdx.x];
+    const int4 tr = a.chunk_tasks[blockIdx.x];     // {p2p t0, t1, l2t t0, t1}
+    const int t = ch.y + int(threadIdx.x);
+    if (t >= ch.z) return;
+    double v[10];
+    for (int k = 0; k < a.nacc; ++k) v[k] = 0.0;
+    for (int q = tr.x; q < tr.y; ++q) {
+        const double *p = a.near + (int64_t(q) * 256 + threadIdx.x) * a.nacc;
+        for (int k = 0; k < a.nacc; ++k) v[k] += p[k];
+    }
+    for (int q = tr.z; q < tr.w; ++q) {
+        const double *p = a.far + (int64_t(q) * 256 + threadIdx.x) * a.nacc;
+        for (int k = 0; k < a.nacc; ++k) v[k] += p[k];
+    }
+    double *o = a.out + int64_t(a.perm[t]) * a.kt;
+    for (int k = 0; k < a.kt; ++k) {
+        const int s = a.map.src[k];
+        o[k] = s >= 0 ? a.map.scale[k] * v[s] : 0.0;
     }
 }
 
@@ -756,14 +795,14 @@ hipError_t launch_pack_targets(int64_t n, const double *xyz, const int32_t *perm
     return hipGetLastError();
 }
 
-hipError_t launch_p2p(int kernel, int nchunks, const P2PArgs &a, hipStream_t s) {
-    if (nchunks <= 0) return hipSuccess;
+hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
     switch (kernel) {
-        case kStokeslet: hipLaunchKernelGGL(p2p_kernel<DStokeslet>, dim3(nchunks), dim3(256), 0, s, a); break;
-        case kRPY: hipLaunchKernelGGL(p2p_kernel<DRPY>, dim3(nchunks), dim3(256), 0, s, a); break;
-        case kLapPGrad: hipLaunchKernelGGL(p2p_kernel<DLapPGrad>, dim3(nchunks), dim3(256), 0, s, a); break;
-        case kPVel: hipLaunchKernelGGL(p2p_kernel<DPVel>, dim3(nchunks), dim3(256), 0, s, a); break;
-        case kTraction: hipLaunchKernelGGL(p2p_kernel<DTraction>, dim3(nchunks), dim3(256), 0, s, a); break;
+        case kStokeslet: hipLaunchKernelGGL(p2p_kernel<DStokeslet>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kRPY: hipLaunchKernelGGL(p2p_kernel<DRPY>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kLapPGrad: hipLaunchKernelGGL(p2p_kernel<DLapPGrad>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kPVel: hipLaunchKernelGGL(p2p_kernel<DPVel>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kTraction: hipLaunchKernelGGL(p2p_kernel<DTraction>, dim3(ntasks), dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -814,24 +853,28 @@ hipError_t launch_periodic(const double *T, const float *dens, double *chk, int 
     return hipGetLastError();
 }
 
-hipError_t launch_l2t(int kernel, int nchunks, const L2TArgs &a, hipStream_t s) {
-    if (nchunks <= 0) return hipSuccess;
+hipError_t launch_l2t(int kernel, int ntasks, const L2TArgs &a, hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
     switch (kernel) {
-        case kStokeslet: hipLaunchKernelGGL(l2t_kernel<EStokeslet>, dim3(nchunks), dim3(256), 0, s, a); break;
-        case kRPY: hipLaunchKernelGGL(l2t_kernel<ERPY>, dim3(nchunks), dim3(256), 0, s, a); break;
-        case kLapPGrad: hipLaunchKernelGGL(l2t_kernel<ELapPGrad>, dim3(nchunks), dim3(256), 0, s, a); break;
-        case kPVel: hipLaunchKernelGGL(l2t_kernel<EPVel>, dim3(nchunks), dim3(256), 0, s, a); break;
-        case kTraction: hipLaunchKernelGGL(l2t_kernel<ETraction>, dim3(nchunks), dim3(256), 0, s, a); break;
+        case kStokeslet: hipLaunchKernelGGL(l2t_kernel<EStokeslet>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kRPY: hipLaunchKernelGGL(l2t_kernel<ERPY>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kLapPGrad: hipLaunchKernelGGL(l2t_kernel<ELapPGrad>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kPVel: hipLaunchKernelGGL(l2t_kernel<EPVel>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kTraction: hipLaunchKernelGGL(l2t_kernel<ETraction>, dim3(ntasks), dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_combine(int64_t n, const double *near, const double *far, const int32_t *perm, int nacc,
-                          int kt, const CombineMap &map, double *out, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(combine_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, near, far, perm, nacc, kt,
-                       map, out);
+hipError_t launch_combine(int nchunks, const CombineArgs &a, hipStream_t s) {
+    if (nchunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(combine_kernel, dim3(nchunks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_s2c_reduce(int ndst, const S2CReduceArgs &a, hipStream_t s) {
+    if (ndst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(s2c_reduce, dim3(ndst), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -11,31 +11,38 @@ namespace kafmm {
 
 // Packed periodic image shift: bits (2k, 2k+1) hold shift_k + 1.
 constexpr int kZeroShift = 1 | (1 << 2) | (1 << 4);
+// Entry code of an L2T task entry that names the leaf's own downward set.
+constexpr int kLocalSet = 64;
 inline int pack_shift(const int8_t s[3]) { return (s[0] + 1) | ((s[1] + 1) << 2) | ((s[2] + 1) << 4); }
 
 struct P2PArgs {
+    const int4 *tasks;         // {chunk, e0, e1, -}: slice of the leaf's direct list
     const int4 *chunks;        // {leaf, t0, t1, -}
     const float *trg;          // [n_trg][8]
-    const int *u_off;          // by box id
-    const int2 *u_ent;         // {source leaf, packed shift}
+    const int2 *ent;           // direct entries {source box, packed shift}
     const int2 *box_sl, *box_dl;
     const float *sl, *dl;      // source records
-    double *out;               // [n_trg][NACC]
+    double *part;              // [task][256][NACC]
 };
 
 struct S2CArgs {
-    const int *dst;            // destination box per task
-    const int *list_off;       // per task: range of source entries
-    const int2 *list;          // {source leaf, packed shift}
-    const int2 *src_range;     // per box: range in the source array
+    const int4 *tasks;         // {dst box, packed shift, j0, j1}: sources [j0, j1) of src
     const float *src;          // source records
     int rec;
     const double4 *geom;
     const float *grid;         // [M][3] unit lattice
     int M;
     double alpha;              // surface radius in half box sides
+    float *part;               // [task][ncomp][M]
+};
+
+struct S2CReduceArgs {
+    const int *dst;            // destination box per block
+    const int *off;            // per block: range of task indices
+    const int *task;
+    const float *part;
     double *chk;               // [box][ncomp][M]
-    int accumulate;
+    int M, ncomp, accumulate;
 };
 
 struct GemmArgs {
@@ -71,22 +78,31 @@ struct ReduceArgs {
 };
 
 struct L2TArgs {
+    const int4 *tasks;         // {chunk, e0, e1, -}
     const int4 *chunks;
     const float *trg;
     const double4 *geom;
-    const uint8_t *has_local;
-    const int *w_off;
-    const int2 *w_ent;
+    const int2 *ent;           // {box, packed shift | kLocalSet}
     const float *grid;
     const float *up_dens, *dn_dens;
     int M, Mp;
     double alpha_in, alpha_out;
-    double *out;
+    double *part;              // [task][256][NACC]
 };
 
 struct CombineMap {
     int src[10];
     double scale[10];
+};
+
+struct CombineArgs {
+    const int4 *chunks;
+    const int4 *chunk_tasks;   // {p2p t0, t1, l2t t0, t1}
+    const double *near, *far;  // task partials
+    const int32_t *perm;
+    int nacc, kt;
+    CombineMap map;
+    double *out;
 };
 
 struct DirectArgs {
@@ -102,7 +118,7 @@ hipError_t launch_pack_sources(int64_t n, const double *xyz, const double *val, 
                                double3 origin, double inv_len, int kind, int rec, float *out, hipStream_t s);
 hipError_t launch_pack_targets(int64_t n, const double *xyz, const int32_t *perm, double3 origin,
                                double inv_len, float *out, hipStream_t s);
-hipError_t launch_p2p(int kernel, int nchunks, const P2PArgs &a, hipStream_t s);
+hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, hipStream_t s);
 hipError_t launch_s2c(int src_kind, int ntasks, const S2CArgs &a, hipStream_t s);
 hipError_t launch_gemm_f32(int ntiles, int Mp, const GemmArgs &a, hipStream_t s);
 hipError_t launch_gemm_f64(const Gemm64Args &a, double *C, hipStream_t s);
@@ -110,9 +126,9 @@ hipError_t launch_gemm_f64_to_f32(const Gemm64Args &a, float *C, hipStream_t s);
 hipError_t launch_reduce(int ntasks, const ReduceArgs &a, hipStream_t s);
 hipError_t launch_periodic(const double *T, const float *dens, double *chk, int M, int Mp, int nc, int root,
                            hipStream_t s);
-hipError_t launch_l2t(int kernel, int nchunks, const L2TArgs &a, hipStream_t s);
-hipError_t launch_combine(int64_t n, const double *near, const double *far, const int32_t *perm, int nacc,
-                          int kt, const CombineMap &map, double *out, hipStream_t s);
+hipError_t launch_l2t(int kernel, int ntasks, const L2TArgs &a, hipStream_t s);
+hipError_t launch_s2c_reduce(int ndst, const S2CReduceArgs &a, hipStream_t s);
+hipError_t launch_combine(int nchunks, const CombineArgs &a, hipStream_t s);
 hipError_t launch_direct_f64(int kernel, const DirectArgs &a, hipStream_t s);
 
 }  // namespace kafmm
