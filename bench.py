@@ -24,6 +24,23 @@ sys.path.insert(0, ROOT)
 # kernel formulas without the hi/lo coordinate refinement
 P2P_FLOPS = {"Stokeslet": 28, "RPY": 50}
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+PROFILE = os.path.join(ROOT, "profiles", "p2p_stokeslet_1M_clustered_p10.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2010_15155_amd", "csrc", f) for f in ("kernels.hip", "kernel_math.hpp")]
+
+
+def measured_traffic():
+    """HBM bytes per P2P launch from the committed PMC summary, or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        fields = dict(l.split(": ", 1) for l in open(PROFILE).read().splitlines() if ": " in l
+                      and l.split(": ", 1)[0] in ("traffic_bytes_per_launch", "source_sha256"))
+        h = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()[:16]
+        if fields.get("source_sha256", "").strip() != h:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -37,6 +54,9 @@ def parse():
     ap.add_argument("--samples", type=int, default=4096, help="targets checked by the FP64 GPU direct sum")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the measurement, copy a MIB-sized device buffer once (reference "
+                         "kernel for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -133,12 +153,19 @@ def main():
                 "stages_serial_ms": res["RPY"]["stages_serial_ms"]},
         "roofline": {"kernel": "p2p_kernel<DStokeslet>", "bound": "alu", "achieved": achieved,
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "flops_per_pair": P2P_FLOPS["Stokeslet"], "pairs_per_launch": S["stats"]["p2p_pairs"],
                      "avg_launch_ms": S["p2p_ms"]},
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calibrate_copy_bytes"] = args.calibrate_copy * (1 << 20)
     print(json.dumps(line), flush=True)
 
 

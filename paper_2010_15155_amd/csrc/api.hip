@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -133,6 +134,7 @@ struct stkfmm_ctx {
     int64_t w_direct = 0, x_direct = 0, direct_pairs = 0;
     int overlap = 1;
     double w_direct_frac = 0.73, x_direct_frac = 0.5;
+    int64_t p2p_task_sources = 2048;
     Batch m2l;
     std::vector<Batch> m2m, l2l;            // by level (parent level / child level)
     std::vector<PinvLevel> upinv, dnpinv;   // by level
@@ -260,7 +262,7 @@ Batch make_batch(Arena &ar, std::vector<Pair> pairs, int nc, int accumulate, siz
 template <class T> T *at(stkfmm_ctx *c, size_t off) { return reinterpret_cast<T *>(c->arena.as<char>() + off); }
 
 stkfmm_status run_batch(stkfmm_ctx *c, const Batch &b, const float *ops, const float *X, double *chk,
-                        hipStream_t s) {
+                        hipStream_t s, bool split_bf16 = false) {
     if (b.npairs == 0) return STKFMM_OK;
     const DeviceOps &o = *c->ops;
     const int nc = kernel_info(c->kernel).ncomp;
@@ -272,7 +274,8 @@ stkfmm_status run_batch(stkfmm_ctx *c, const Batch &b, const float *ops, const f
     g.bcol = at<int>(c, b.bcol);
     g.ycol = at<int>(c, b.ycol);
     g.Mp = o.Mp;
-    HIP_TRY(c, launch_gemm_f32(b.ntiles, o.Mp, g, s));
+    if (split_bf16) HIP_TRY(c, launch_gemm_bf16x3(b.ntiles, o.Mp, g, s));
+    else HIP_TRY(c, launch_gemm_f32(b.ntiles, o.Mp, g, s));
     ReduceArgs r;
     r.dst = at<int>(c, b.rdst);
     r.off = at<int>(c, b.roff);
@@ -379,6 +382,13 @@ stkfmm_status stkfmm_set_option(stkfmm_ctx *c, const char *key, const char *valu
         if (v == "fp32") c->precision = 0;
         else if (v == "split_bf16") c->precision = 1;
         else return fail(c, STKFMM_E_ARG, "precision must be fp32 or split_bf16");
+        return STKFMM_OK;
+    }
+    if (k == "p2p_task_sources") {
+        long n = std::atol(value);
+        if (n < 64 || n > (1L << 24) || std::to_string(n) != v) return fail(c, STKFMM_E_ARG, "p2p_task_sources must lie in [64, 2^24]");
+        c->p2p_task_sources = n;
+        c->planned = false;
         return STKFMM_OK;
     }
     if (k == "overlap") {
@@ -564,7 +574,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
         }
     }
     // ---- target chunks and their P2P / L2T tasks
-    constexpr int64_t kP2PTaskSources = 8192;   // sources per P2P task (balance)
+    const int64_t kP2PTaskSources = c->p2p_task_sources;   // sources per P2P task (balance)
     constexpr int kL2TTaskSets = 4;              // equivalent-point sets per L2T task
     std::vector<int4> chunks, chunk_tasks, p2p_tasks, l2t_tasks;
     std::vector<int2> p2p_ent, l2t_ent;
@@ -1022,7 +1032,7 @@ stkfmm_status stkfmm_run(stkfmm_ctx *c, const double *sl_val, const double *dl_v
         }
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 3 upward
         HIP_TRY(c, launch_fill_f64(dnchk, int64_t(c->nbox) * nc * o.M, 0.0, s));
-        stkfmm_status st = run_batch(c, c->m2l, o.m2l.as<float>(), updens, dnchk, s);
+        stkfmm_status st = run_batch(c, c->m2l, o.m2l.as<float>(), updens, dnchk, s, c->precision == 1);
         if (st != STKFMM_OK) return st;
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 4 M2L
         HIP_TRY(c, s2c(c->s2l, kAlphaIn, dnchk, 1));

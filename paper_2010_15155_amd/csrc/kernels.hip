@@ -420,6 +420,113 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma(GemmArgs a) {
     }
 }
 
+// ------------------------------------------------------------------ split-BF16 grouped GEMM
+// Same tiling as gemm_f32_mfma, arithmetic in three BF16 passes:
+// A = Ah + Al, X = Xh + Xl (hi = RN_bf16(v), lo = RN_bf16(v - hi)), and
+// Y = Ah Xh + Ah Xl + Al Xh with FP32 accumulation (the Al Xl term, of
+// relative size 2^-16, is dropped).  The split is done while staging tiles
+// to LDS; v_mfma_f32_32x32x16_bf16 takes 8 consecutive k per lane.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kBLd = 40;   // LDS row stride in bf16 (32 + 8): conflict-free 16-byte reads
+
+__global__ __launch_bounds__(256) void gemm_bf16x3_mfma(GemmArgs a) {
+    __shared__ __bf16 Ah[kGT * kBLd], Al[kGT * kBLd], Bh[kGT * kBLd], Bl[kGT * kBLd];
+    const int4 tile = a.tiles[blockIdx.x];
+    const int row0 = blockIdx.y * kGT;
+    const int Mp = a.Mp;
+    const float *A = a.ops + int64_t(tile.x) * Mp * Mp;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+    const float *bptr[4];
+    int lr[4], lk[4];
+    bool arow_ok[4], bcol_ok[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        int idx = tid + 256 * i;
+        lr[i] = idx >> 3;
+        lk[i] = (idx & 7) * 4;
+        arow_ok[i] = row0 + lr[i] < Mp;
+        bcol_ok[i] = lr[i] < tile.z;
+        int c = bcol_ok[i] ? a.bcol[tile.y + lr[i]] : 0;
+        bptr[i] = a.X + int64_t(c) * Mp;
+    }
+    for (int k0 = 0; k0 < Mp; k0 += kGK) {
+        float4 ra[4], rb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ra[i] = arow_ok[i] ? *reinterpret_cast<const float4 *>(A + int64_t(row0 + lr[i]) * Mp + k0 + lk[i])
+                               : make_float4(0, 0, 0, 0);
+            rb[i] = bcol_ok[i] ? *reinterpret_cast<const float4 *>(bptr[i] + k0 + lk[i])
+                               : make_float4(0, 0, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float va[4] = {ra[i].x, ra[i].y, ra[i].z, ra[i].w};
+            const float vb[4] = {rb[i].x, rb[i].y, rb[i].z, rb[i].w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                __bf16 h = __bf16(va[q]);
+                Ah[lr[i] * kBLd + lk[i] + q] = h;
+                Al[lr[i] * kBLd + lk[i] + q] = __bf16(va[q] - float(h));
+                h = __bf16(vb[q]);
+                Bh[lr[i] * kBLd + lk[i] + q] = h;
+                Bl[lr[i] * kBLd + lk[i] + q] = __bf16(vb[q] - float(h));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kGK; kk += 16) {
+            const int ko = kk + 8 * (lane >> 5);
+            bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int r = (wr + 32 * i + (lane & 31)) * kBLd + ko;
+                ah[i] = *reinterpret_cast<const bf16x8 *>(Ah + r);
+                al[i] = *reinterpret_cast<const bf16x8 *>(Al + r);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int r = (wc + 32 * j + (lane & 31)) * kBLd + ko;
+                bh[j] = *reinterpret_cast<const bf16x8 *>(Bh + r);
+                bl[j] = *reinterpret_cast<const bf16x8 *>(Bl + r);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = wc + 32 * j + (lane & 31);
+        if (col >= tile.z) continue;
+        float *Y = a.Y + int64_t(a.ycol[tile.y + col]) * Mp;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int row = row0 + wr + 32 * i + 8 * g + 4 * (lane >> 5);
+                if (row < Mp) {
+                    float4 v = make_float4(acc[i][j][4 * g], acc[i][j][4 * g + 1], acc[i][j][4 * g + 2],
+                                           acc[i][j][4 * g + 3]);
+                    *reinterpret_cast<float4 *>(Y + row) = v;
+                }
+            }
+    }
+}
+
 // ------------------------------------------------------------------ FP64 GEMM (pseudo-inverse)
 // C[col][i] = scale(col) * sum_k A[i][k] * B[col][k],  i < R, k < K.
 // B columns are FP64 (check values or scratch); C is FP64 scratch or FP32
@@ -825,6 +932,12 @@ hipError_t launch_s2c(int src_kind, int ntasks, const S2CArgs &a, hipStream_t s)
 hipError_t launch_gemm_f32(int ntiles, int Mp, const GemmArgs &a, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(gemm_f32_mfma, dim3(ntiles, (Mp + kGT - 1) / kGT), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_bf16x3(int ntiles, int Mp, const GemmArgs &a, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gemm_bf16x3_mfma, dim3(ntiles, (Mp + kGT - 1) / kGT), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

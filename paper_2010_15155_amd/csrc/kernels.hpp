@@ -121,6 +121,7 @@ hipError_t launch_pack_targets(int64_t n, const double *xyz, const int32_t *perm
 hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, hipStream_t s);
 hipError_t launch_s2c(int src_kind, int ntasks, const S2CArgs &a, hipStream_t s);
 hipError_t launch_gemm_f32(int ntiles, int Mp, const GemmArgs &a, hipStream_t s);
+hipError_t launch_gemm_bf16x3(int ntiles, int Mp, const GemmArgs &a, hipStream_t s);
 hipError_t launch_gemm_f64(const Gemm64Args &a, double *C, hipStream_t s);
 hipError_t launch_gemm_f64_to_f32(const Gemm64Args &a, float *C, hipStream_t s);
 hipError_t launch_reduce(int ntasks, const ReduceArgs &a, hipStream_t s);

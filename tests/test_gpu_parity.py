@@ -103,6 +103,25 @@ def test_fmm_clustered(fmm, kernel):
         assert e < 1e-5
 
 
+@pytest.mark.parametrize("kernel", ["Stokeslet", "RPY", "LapPGrad", "Traction"])
+def test_split_bf16_m2l(fmm, kernel):
+    # three BF16 passes drop the lo*lo term (relative 2^-16 per product); the
+    # result must stay within the 1e-5 budget and close to the FP32 path
+    pb = problem(kernel, 24000, 3)
+    ref = oracle_of(kernel, pb)
+    try:
+        fmm.set_option("precision", "split_bf16")
+        got = gpu_eval(fmm, kernel, pb, 8, 150)
+    finally:
+        fmm.set_option("precision", "fp32")
+    f32 = gpu_eval(fmm, kernel, pb, 8, 150)
+    errs = field_errors(kernel, got, ref)
+    print(kernel, "split_bf16", errs, flush=True)
+    for name, e in errs.items():
+        assert e < 1e-5
+        assert e < field_errors(kernel, f32, ref)[name] + 3e-6
+
+
 def test_error_falls_with_order(fmm):
     pb = problem("Stokeslet", 20000, 4)
     ref = oracle_of("Stokeslet", pb)
