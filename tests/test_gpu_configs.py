@@ -1,0 +1,139 @@
+"""GPU parity on the workloads of the benchmark configurations.
+
+* uniform Stokeslet N=4096, p=8, leaf_cap=64 (all targets vs the direct sum);
+* clustered Stokeslet/RPY N=1,048,576, p=10, leaf_cap=2000 -- the launch
+  configuration bench.py times -- on sampled targets the oracle computes one
+  by one, FP32 and split-BF16 M2L;
+* triply periodic Laplace charges + dipoles (zero net charge) against the
+  Ewald oracle, at a small size on all of its structure and at N=4,194,304
+  on sampled targets; plus the paper's translation test (Sec. III.C);
+* sphere double layer (PVel, Traction) on Fibonacci surface points.
+"""
+import numpy as np
+import pytest
+
+from oracle import direct, ewald
+from paper_2010_15155_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fmm():
+    from paper_2010_15155_amd import FMM
+    f = FMM()
+    yield f
+    f.close()
+
+
+def cu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def test_uniform_4096(fmm):
+    d = W.uniform_stokeslet(4096, 101)
+    x, f = d["xyz"], d["f"]
+    out = fmm.evaluate("Stokeslet", cu(x), cu(f), None, None, cu(x), p=8, leaf_cap=64).cpu().numpy()
+    err = rel(out, direct.stokeslet(x, f, x))
+    print("uniform 4096 p=8 cap=64", fmm.stats(), err, flush=True)
+    assert err < 1e-5
+
+
+@pytest.fixture(scope="module")
+def clustered():
+    d = W.clustered_rpy(1_048_576, 201)
+    idx = W.sample_indices(len(d["xyz"]), 256, 3)
+    fb = np.concatenate([d["f"], d["b"][:, None]], 1)
+    return d, idx, fb
+
+
+@pytest.mark.parametrize("kernel", ["Stokeslet", "RPY"])
+@pytest.mark.parametrize("precision", ["fp32", "split_bf16"])
+def test_clustered_1M_bench_config(fmm, clustered, kernel, precision):
+    d, idx, fb = clustered
+    x = d["xyz"]
+    val = d["f"] if kernel == "Stokeslet" else fb
+    fmm.set_option("precision", precision)
+    try:
+        out = fmm.evaluate(kernel, cu(x), cu(val), None, None, cu(x), p=10, leaf_cap=2000)
+    finally:
+        fmm.set_option("precision", "fp32")
+    got = out[torch.from_numpy(idx).cuda()].cpu().numpy()
+    ref = direct.evaluate(kernel, x, val, None, None, x[idx])
+    errs = [rel(got[:, a:b], ref[:, a:b]) for a, b in ((0, 3), (3, 6))[: (1 if kernel == "Stokeslet" else 2)]]
+    print(kernel, precision, "1M sampled", errs, flush=True)
+    assert max(errs) < 1e-5
+
+
+def periodic_problem(n, seed):
+    d = W.periodic_laplace(n, seed)
+    return d["xyz"], d["q"], d["d"]
+
+
+def compare_periodic(got, ref):
+    # potential defined up to a constant: remove the mean difference
+    dphi = got[:, 0] - ref[:, 0]
+    e_phi = float(np.linalg.norm(dphi - dphi.mean()) / np.linalg.norm(ref[:, 0] - ref[:, 0].mean()))
+    e_grad = rel(got[:, 1:], ref[:, 1:])
+    return e_phi, e_grad
+
+
+def test_periodic_laplace_small(fmm):
+    x, q, dp = periodic_problem(32768, 301)
+    out = fmm.evaluate("LapPGrad", cu(x), cu(q[:, None]), cu(x), cu(dp), cu(x), p=8, leaf_cap=128,
+                       bc="PXYZ").cpu().numpy()
+    st = fmm.stats()
+    idx = W.sample_indices(len(x), 400, 5)
+    ref = ewald.laplace_periodic(x, q, dp, x[idx], 1.0)
+    e_phi, e_grad = compare_periodic(out[idx], ref)
+    print("periodic 32768 p=8", st, e_phi, e_grad, flush=True)
+    assert st["depth"] >= 3
+    assert e_phi < 1e-5 and e_grad < 1e-5
+    # translation test: shift all points periodically, values must not change
+    s = np.array([0.31, 0.77, 0.12])
+    out2 = fmm.evaluate("LapPGrad", cu(np.mod(x + s, 1.0)), cu(q[:, None]), cu(np.mod(x + s, 1.0)), cu(dp),
+                        cu(np.mod(x + s, 1.0)), p=8, leaf_cap=128, bc="PXYZ").cpu().numpy()
+    t_phi, t_grad = compare_periodic(out2, out)
+    print("translation", t_phi, t_grad, flush=True)
+    assert t_phi < 1e-5 and t_grad < 1e-5
+
+
+def test_periodic_rejects_net_charge(fmm):
+    from paper_2010_15155_amd import StkfmmError
+    x, q, dp = periodic_problem(2000, 7)
+    fmm.set_points("LapPGrad", cu(x), cu(x), cu(x), p=6, leaf_cap=100, bc="PXYZ")
+    with pytest.raises(StkfmmError) as ei:
+        fmm.run(cu(q[:, None] + 1.0), cu(dp))
+    assert ei.value.status == "E_DOMAIN"
+
+
+@pytest.mark.slow
+def test_periodic_laplace_4M(fmm):
+    x, q, dp = periodic_problem(4_194_304, 301)
+    out = fmm.evaluate("LapPGrad", cu(x), cu(q[:, None]), cu(x), cu(dp), cu(x), p=12, leaf_cap=2000,
+                       bc="PXYZ")
+    idx = W.sample_indices(len(x), 24, 9)
+    got = out[torch.from_numpy(idx).cuda()].cpu().numpy()
+    ref = ewald.laplace_periodic(x, q, dp, x[idx], 1.0, xi=4.0, tol=1e-12)
+    e_phi, e_grad = compare_periodic(got, ref)
+    print("periodic 4M p=12", fmm.stats(), e_phi, e_grad, flush=True)
+    assert e_phi < 1e-5 and e_grad < 1e-5
+
+
+@pytest.mark.parametrize("kernel", ["PVel", "Traction"])
+def test_sphere_double_layer(fmm, kernel):
+    d = W.sphere_doublelayer(n_spheres=300, pts_per_sphere=1000, seed=401)
+    x, D = d["xyz"], d["D"]
+    out = fmm.evaluate(kernel, None, None, cu(x), cu(D), cu(x), p=10, leaf_cap=2000)
+    idx = W.sample_indices(len(x), 1500, 4)
+    got = out[torch.from_numpy(idx).cuda()].cpu().numpy()
+    ref = direct.evaluate(kernel, None, None, x, D, x[idx])
+    fields = [(0, 1), (1, 4)] if kernel == "PVel" else [(0, 9)]
+    errs = [rel(got[:, a:b], ref[:, a:b]) for a, b in fields]
+    print(kernel, "spheres 300k", fmm.stats(), errs, flush=True)
+    assert max(errs) < 1e-5
