@@ -90,9 +90,10 @@ stkfmm_status stkfmm_setup(stkfmm_ctx **out, const double origin[3], double box_
  * pointers [n][3] FP64; n_sl or n_dl may be 0 with a NULL pointer.  A kernel
  * without DL sources requires n_dl == 0.  SL, DL and target sets are
  * independent and may alias.  p: equivalent-surface order (points per
- * surface M = 6(p-1)^2 + 2, Sec. III), 2 <= p <= 16.  leaf_cap: a box is
- * split while it holds more than leaf_cap targets, SL or DL sources (Sec. III
- * uses 2000); 1 <= leaf_cap.
+ * surface M = 6(p-1)^2 + 2, Sec. III), 2 <= p <= 16, or 0 for the learned
+ * order.  leaf_cap: a box is split while it holds more than leaf_cap
+ * targets, SL or DL sources (Sec. III uses 2000); >= 1, or 0 for learned
+ * per-leaf capacities (see the learned mode below).
  * Open BC: every point must lie in [origin, origin+box_len)^3, else E_DOMAIN.
  * PXYZ: points are wrapped into the box.
  * Errors: E_ARG, E_DOMAIN, E_UNSUPPORTED, E_NOMEM, E_DEVICE. */
@@ -136,7 +137,11 @@ stkfmm_status stkfmm_kernel_dims(stkfmm_kernel kernel, int *k_sl, int *k_dl, int
 /* Options (strings):  "precision" = "fp32" | "split_bf16"  (M2L arithmetic),
  * "svd_tol" = relative truncation of the check-to-equivalent pseudo-inverse
  * (default 1e-7), "overlap" = "1" (P2P concurrent with the far field, the
- * default) | "0" (serial, for per-stage timing).  Errors: E_ARG. */
+ * default) | "0" (serial, for per-stage timing), "tol" = accuracy target of
+ * the learned mode (default 1e-5), "p2p_task_sources" = sources per P2P task
+ * (default 2048), "w_direct_frac" / "x_direct_frac" = W / X pairs whose source
+ * count / target count is below this fraction of M are summed directly
+ * (defaults 0.73 / 0.5).  Errors: E_ARG. */
 stkfmm_status stkfmm_set_option(stkfmm_ctx *ctx, const char *key, const char *value);
 
 /* Timings of the last set_points (t_tree_ms) and run (t_run_ms, device event
@@ -157,6 +162,65 @@ stkfmm_status stkfmm_get_timings(const stkfmm_ctx *ctx, double *t_tree_ms, doubl
  * directly, 14 X pairs summed directly, 15 P2P tasks.
  * Errors: E_ARG, E_STATE. */
 stkfmm_status stkfmm_get_stats(const stkfmm_ctx *ctx, int64_t stats[16]);
+
+/* ---------------------------------------------------------------------
+ * Learned order / leaf-capacity mode.  stkfmm_set_points with p = 0 and/or
+ * leaf_cap = 0 builds the reference tree (leaf_cap 2000, Sec. III), computes
+ * 12 features per leaf, runs the predictor network on the GPU and uses, for
+ * each 0 argument, the predicted order (classes 6/8/10/12) and the
+ * predicted per-leaf capacities (classes 250/500/1000/2000, applied by
+ * refining each reference leaf).  The
+ * order is the smallest class whose error over all targets, estimated from a
+ * calibration table (RMS error at each order of training leaves of each
+ * predicted class, weighted by the leaves' target counts), is within 0.8 tol.
+ * The first stkfmm_run of such a plan checks the result on 256 sampled targets
+ * against the FP64 direct sum; above the option "tol" (default 1e-5, relative
+ * L2 per output field) it re-plans with the fixed p = 10, leaf_cap = 2000
+ * and reruns; E_ACCURACY if that too misses tol.  Open BC only.  This mode is
+ * not in the paper, which uses one global order and leaf size (Sec. III). */
+
+/* Number of FP32 parameters of the predictor network.  Layout: mean[12],
+ * std[12] (input scaling), W1[12][64], b1[64], W2[64][64], b2[64], W3[64][8],
+ * b3[8]; logits 0-3 order classes, 4-7 capacity classes.  Pure host. */
+int stkfmm_mlp_nparam(void);
+
+/* Floats of device workspace the network kernels need for a batch. */
+int64_t stkfmm_mlp_workspace(int64_t batch);
+
+/* Install the predictor (host pointer, n = stkfmm_mlp_nparam() + 16): the
+ * network parameters followed by the 4x4 order calibration table
+ * table[class][order class] (relative RMS error, >= 0). */
+stkfmm_status stkfmm_set_predictor(stkfmm_ctx *ctx, const float *params, int n);
+
+/* After set_points: info[12] = {learned, order used, fell back, validated,
+ * order-class histogram (4), capacity-class histogram (4)}; *sampled_err the
+ * checked error (or -1).  Errors: E_ARG. */
+stkfmm_status stkfmm_get_learned(const stkfmm_ctx *ctx, int64_t info[12], double *sampled_err);
+
+/* Features [n_leaf][12] (host, may be NULL) of the current tree's leaves and
+ * the leaf index of every target (host [n_trg], user order, may be NULL);
+ * *n_leaf receives the leaf count.  Errors: E_ARG, E_STATE. */
+stkfmm_status stkfmm_get_leaf_features(stkfmm_ctx *ctx, float *features, int32_t *leaf_of_target,
+                                       int64_t *n_leaf);
+
+/* Modelled cost in seconds [n_leaf][4] (host) of refining each leaf of the
+ * current tree to the capacity classes, from rates = {P2P pairs/s, M2L
+ * flop/s, surface evaluations/s, seconds per box}.  Errors: E_ARG, E_STATE. */
+stkfmm_status stkfmm_get_leaf_costs(stkfmm_ctx *ctx, const double rates[4], double *costs);
+
+/* Predictor network kernels on device buffers (stream-ordered, synchronous).
+ * x [batch][12], logits [batch][8], labels [batch][2] (order class, capacity
+ * class), work >= stkfmm_mlp_workspace(batch) floats; grad, m, v [nparam].
+ * loss_grad writes the mean cross-entropy (two heads, averaged) to *loss
+ * (device) and its gradient; adam applies one bias-corrected Adam step
+ * (beta 0.9, 0.999, eps 1e-8; the input scaling is not updated), step >= 1.
+ * Errors: E_ARG, E_DEVICE. */
+stkfmm_status stkfmm_mlp_forward(const float *params, int64_t batch, const float *x, float *logits,
+                                 float *work, void *hip_stream);
+stkfmm_status stkfmm_mlp_loss_grad(const float *params, int64_t batch, const float *x, const int32_t *labels,
+                                   float *grad, float *loss, float *work, void *hip_stream);
+stkfmm_status stkfmm_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t step, float lr,
+                              void *hip_stream);
 
 /* Last error message of the context (never NULL; "" if none). */
 const char *stkfmm_last_error(const stkfmm_ctx *ctx);

@@ -22,7 +22,11 @@ LIB_PATH = os.path.join(HERE, "libstkfmm.so")
 # exported C symbols (kept in step with include/stkfmm.h)
 SYMBOLS = ["stkfmm_setup", "stkfmm_set_points", "stkfmm_run", "stkfmm_evaluate", "stkfmm_direct",
            "stkfmm_kernel_dims", "stkfmm_set_option", "stkfmm_get_timings", "stkfmm_get_stats",
-           "stkfmm_last_error", "stkfmm_destroy"]
+           "stkfmm_last_error", "stkfmm_destroy", "stkfmm_mlp_nparam", "stkfmm_mlp_workspace",
+           "stkfmm_set_predictor", "stkfmm_get_learned", "stkfmm_get_leaf_features", "stkfmm_get_leaf_costs",
+           "stkfmm_mlp_forward", "stkfmm_mlp_loss_grad", "stkfmm_mlp_adam"]
+ORDER_CLASSES = (6, 8, 10, 12)
+CAP_CLASSES = (250, 500, 1000, 2000)
 
 _lib = None
 
@@ -56,6 +60,16 @@ def lib():
     L.stkfmm_last_error.restype = ctypes.c_char_p
     L.stkfmm_destroy.argtypes = [vp]
     L.stkfmm_destroy.restype = None
+    L.stkfmm_mlp_nparam.argtypes = []
+    L.stkfmm_mlp_workspace.argtypes = [i64]
+    L.stkfmm_mlp_workspace.restype = i64
+    L.stkfmm_set_predictor.argtypes = [vp, vp, ci]
+    L.stkfmm_get_learned.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(cd)]
+    L.stkfmm_get_leaf_features.argtypes = [vp, vp, vp, ctypes.POINTER(i64)]
+    L.stkfmm_get_leaf_costs.argtypes = [vp, ctypes.POINTER(cd), vp]
+    L.stkfmm_mlp_forward.argtypes = [vp, i64, vp, vp, vp, vp]
+    L.stkfmm_mlp_loss_grad.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
+    L.stkfmm_mlp_adam.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, vp]
     _lib = L
     return L
 
@@ -170,3 +184,95 @@ class FMM:
         names = ["boxes", "leaves", "depth", "u_pairs", "v_pairs", "w_pairs", "x_pairs", "M",
                  "n_trg", "n_sl", "n_dl", "u_entries", "p2p_pairs", "w_direct", "x_direct", "p2p_tasks"]
         return {n: int(a[i]) for i, n in enumerate(names)}
+
+    # ---------------------------------------------------------------- learned mode
+    def set_predictor(self, params):
+        """Install predictor parameters (NumPy float32, stkfmm_mlp_nparam() values)."""
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._check(lib().stkfmm_set_predictor(self._h, p.ctypes.data_as(ctypes.c_void_p), int(p.size)),
+                    "set_predictor")
+
+    def learned_info(self):
+        info = (ctypes.c_int64 * 12)()
+        err = ctypes.c_double()
+        self._check(lib().stkfmm_get_learned(self._h, info, ctypes.byref(err)), "get_learned")
+        return {"learned": bool(info[0]), "p": int(info[1]), "fell_back": bool(info[2]),
+                "validated": bool(info[3]), "order_hist": [int(info[4 + k]) for k in range(4)],
+                "cap_hist": [int(info[8 + k]) for k in range(4)], "sampled_err": err.value}
+
+    def leaf_features(self):
+        """(features [n_leaf, 12] float32, leaf index of every target [n_trg]) of the current tree."""
+        import numpy as np
+        n = ctypes.c_int64()
+        self._check(lib().stkfmm_get_leaf_features(self._h, None, None, ctypes.byref(n)), "leaf_features")
+        feat = np.zeros((n.value, 12), dtype=np.float32)
+        lot = np.zeros(self.n_trg, dtype=np.int32)
+        self._check(lib().stkfmm_get_leaf_features(self._h, feat.ctypes.data_as(ctypes.c_void_p),
+                                                   lot.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)),
+                    "leaf_features")
+        return feat, lot
+
+    def leaf_costs(self, rates):
+        """Modelled cost [n_leaf, 4] of refining each leaf to the capacity classes."""
+        import numpy as np
+        n = ctypes.c_int64()
+        self._check(lib().stkfmm_get_leaf_features(self._h, None, None, ctypes.byref(n)), "leaf_costs")
+        r = (ctypes.c_double * 4)(*rates)
+        out = np.zeros((n.value, 4))
+        self._check(lib().stkfmm_get_leaf_costs(self._h, r, out.ctypes.data_as(ctypes.c_void_p)), "leaf_costs")
+        return out
+
+
+def mlp_nparam():
+    return int(lib().stkfmm_mlp_nparam())
+
+
+def _dev(t, dtype, name):
+    import torch
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError("%s must be a contiguous %s tensor on the GPU" % (name, dtype))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _work(batch, device):
+    import torch
+    return torch.empty(int(lib().stkfmm_mlp_workspace(int(batch))), dtype=torch.float32, device=device)
+
+
+def mlp_forward(params, x):
+    """Logits [batch, 8] of the predictor network (device tensors, float32)."""
+    import torch
+    out = torch.empty((x.shape[0], 8), dtype=torch.float32, device=x.device)
+    w = _work(x.shape[0], x.device)
+    st = lib().stkfmm_mlp_forward(_dev(params, torch.float32, "params"), int(x.shape[0]),
+                                  _dev(x, torch.float32, "x"), _dev(out, torch.float32, "logits"),
+                                  _dev(w, torch.float32, "work"), _stream())
+    if st != 0:
+        raise StkfmmError(st, "mlp_forward")
+    return out
+
+
+def mlp_loss_grad(params, x, labels):
+    """(loss, gradient [nparam]) of the mean two-head cross-entropy."""
+    import torch
+    grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    w = _work(x.shape[0], x.device)
+    st = lib().stkfmm_mlp_loss_grad(_dev(params, torch.float32, "params"), int(x.shape[0]),
+                                    _dev(x, torch.float32, "x"), _dev(labels, torch.int32, "labels"),
+                                    _dev(grad, torch.float32, "grad"), _dev(loss, torch.float32, "loss"),
+                                    _dev(w, torch.float32, "work"), _stream())
+    if st != 0:
+        raise StkfmmError(st, "mlp_loss_grad")
+    return loss, grad
+
+
+def mlp_adam(params, grad, m, v, step, lr):
+    """One Adam step in place on the device parameter vector."""
+    import torch
+    st = lib().stkfmm_mlp_adam(_dev(params, torch.float32, "params"), _dev(grad, torch.float32, "grad"),
+                               _dev(m, torch.float32, "m"), _dev(v, torch.float32, "v"), int(step), float(lr),
+                               _stream())
+    if st != 0:
+        raise StkfmmError(st, "mlp_adam")

@@ -133,6 +133,13 @@ struct stkfmm_ctx {
     S2CPhase s2m, s2l;
     int64_t w_direct = 0, x_direct = 0, direct_pairs = 0;
     int overlap = 1;
+    // learned order / capacity mode
+    DevMem predictor, mlp_in, mlp_out, mlp_ws, coords[3], vbuf[4];
+    bool has_predictor = false, learned = false, validated = false, fell_back = false;
+    float order_table[16] = {};
+    double tol = 1e-5, sampled_err = -1.0;
+    int p_hist[4] = {0, 0, 0, 0}, cap_hist[4] = {0, 0, 0, 0};
+    std::vector<double> hcoords[3];      // normalised user-order coordinates of the last plan
     double w_direct_frac = 0.73, x_direct_frac = 0.5;
     int64_t p2p_task_sources = 2048;
     Batch m2l;
@@ -391,6 +398,14 @@ stkfmm_status stkfmm_set_option(stkfmm_ctx *c, const char *key, const char *valu
         c->planned = false;
         return STKFMM_OK;
     }
+    if (k == "tol") {
+        char *end = nullptr;
+        double t = std::strtod(value, &end);
+        if (!end || *end || !(t > 0) || !(t < 1)) return fail(c, STKFMM_E_ARG, "tol must lie in (0, 1)");
+        c->tol = t;
+        c->planned = false;
+        return STKFMM_OK;
+    }
     if (k == "overlap") {
         if (v == "1") c->overlap = 1;
         else if (v == "0") c->overlap = 0;
@@ -462,8 +477,11 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     if (n_dl > 0 && ki.k_dl == 0) return fail(c, STKFMM_E_ARG, "kernel has no double-layer sources");
     if (n_sl > INT32_MAX / 2 || n_dl > INT32_MAX / 2 || n_trg > INT32_MAX / 2)
         return fail(c, STKFMM_E_ARG, "too many points");
-    if (p < 2 || p > 16) return fail(c, STKFMM_E_ARG, "p must lie in [2, 16]");
-    if (leaf_cap < 1) return fail(c, STKFMM_E_ARG, "leaf_cap must be >= 1");
+    if (p != 0 && (p < 2 || p > 16)) return fail(c, STKFMM_E_ARG, "p must be 0 (learned) or lie in [2, 16]");
+    if (leaf_cap < 0) return fail(c, STKFMM_E_ARG, "leaf_cap must be 0 (learned) or >= 1");
+    const bool learned = p == 0 || leaf_cap == 0;
+    if (learned && !c->has_predictor) return fail(c, STKFMM_E_STATE, "learned mode needs stkfmm_set_predictor");
+    if (learned && bc != STKFMM_BC_OPEN) return fail(c, STKFMM_E_UNSUPPORTED, "learned mode is open-boundary only");
     if (bc != STKFMM_BC_OPEN && bc != STKFMM_BC_PXYZ)
         return fail(c, STKFMM_E_UNSUPPORTED, "only open and triply periodic boundaries are implemented");
     if (bc == STKFMM_BC_PXYZ && kernel != STKFMM_LAP_PGRAD)
@@ -496,8 +514,74 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
         }
     }
     Tree &t = c->tree;
-    std::string e = build_tree(h[0].data(), n_sl, h[1].data(), n_dl, h[2].data(), n_trg, leaf_cap, periodic, t);
-    if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
+    c->learned = learned;
+    c->validated = false;
+    c->fell_back = false;
+    c->sampled_err = -1.0;
+    for (int k = 0; k < 4; ++k) c->p_hist[k] = c->cap_hist[k] = 0;
+    std::string e;
+    if (!learned) {
+        e = build_tree(h[0].data(), n_sl, h[1].data(), n_dl, h[2].data(), n_trg, leaf_cap, periodic, t);
+        if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
+    } else {
+        // keep the caller's coordinates for the accuracy check and the fallback
+        for (int k = 0; k < 3; ++k) {
+            HIP_TRY(c, c->coords[k].ensure(std::max<int64_t>(cnt[k], 1) * 3 * sizeof(double)));
+            if (cnt[k] > 0)
+                HIP_TRY(c, hipMemcpyAsync(c->coords[k].p, src[k], cnt[k] * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+        // reference tree, per-leaf features, network on the GPU
+        const int ref_cap = leaf_cap ? leaf_cap : kReferenceCap;
+        e = build_tree(h[0].data(), n_sl, h[1].data(), n_dl, h[2].data(), n_trg, ref_cap, false, t);
+        if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
+        std::vector<float> feat;
+        leaf_features(t, h[0].data(), h[1].data(), h[2].data(), c->tol, feat);
+        const int64_t nl = int64_t(t.leaves.size());
+        HIP_TRY(c, c->mlp_in.ensure(std::max<int64_t>(nl, 1) * kNumFeatures * sizeof(float)));
+        HIP_TRY(c, c->mlp_out.ensure(std::max<int64_t>(nl, 1) * 8 * sizeof(float)));
+        HIP_TRY(c, c->mlp_ws.ensure(std::max<int64_t>(stkfmm_mlp_workspace(nl), 1) * sizeof(float)));
+        HIP_TRY(c, hipMemcpyAsync(c->mlp_in.p, feat.data(), feat.size() * sizeof(float), hipMemcpyHostToDevice, s));
+        stkfmm_status sm = stkfmm_mlp_forward(c->predictor.as<float>(), nl, c->mlp_in.as<float>(), c->mlp_out.as<float>(),
+                                              c->mlp_ws.as<float>(), stream);
+        if (sm != STKFMM_OK) return fail(c, sm, "predictor inference failed");
+        std::vector<float> logits(size_t(nl) * 8);
+        HIP_TRY(c, hipMemcpy(logits.data(), c->mlp_out.p, logits.size() * sizeof(float), hipMemcpyDeviceToHost));
+        // order: the smallest class whose estimated error over all targets,
+        // from the calibration table (RMS error at each order of training
+        // leaves of each predicted class), is within 0.8 tol
+        const float *table = c->order_table;
+        double est[4] = {0, 0, 0, 0}, ntot = 0;
+        std::unordered_map<uint64_t, int> caps;
+        for (int64_t i = 0; i < nl; ++i) {
+            const float *l = &logits[size_t(i) * 8];
+            const int pc = int(std::max_element(l, l + 4) - l), cc = int(std::max_element(l + 4, l + 8) - (l + 4));
+            const Box &B = t.boxes[t.leaves[i]];
+            const double nt = double(B.trg[1] - B.trg[0]);
+            if (nt > 0) {
+                c->p_hist[pc]++;
+                c->cap_hist[cc]++;
+                for (int q = 0; q < 4; ++q) est[q] += nt * double(table[pc * 4 + q]) * double(table[pc * 4 + q]);
+                ntot += nt;
+            }
+            if (leaf_cap == 0 && kCapClasses[cc] < ref_cap)
+                caps[box_hash(B.level, B.anchor[0], B.anchor[1], B.anchor[2])] = kCapClasses[cc];
+        }
+        int pq = 3;
+        for (int q = 0; q < 4; ++q)
+            if (ntot > 0 && std::sqrt(est[q] / ntot) <= 0.8 * c->tol) {
+                pq = q;
+                break;
+            }
+        if (p == 0) p = kOrderClasses[pq];
+        if (leaf_cap == 0) {
+            leaf_cap = ref_cap;
+            if (!caps.empty()) {
+                e = build_tree(h[0].data(), n_sl, h[1].data(), n_dl, h[2].data(), n_trg, ref_cap, false, t, &caps);
+                if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
+            }
+        }
+    }
+    for (int k = 0; k < 3; ++k) c->hcoords[k] = h[k];
     DeviceOps *ops = nullptr;
     stkfmm_status st = get_ops(c, p, periodic, &ops);
     if (st != STKFMM_OK) return st;
@@ -922,8 +1006,11 @@ __global__ void charge_partials(int64_t n, const double *__restrict__ q, double 
 
 extern "C" {
 
-stkfmm_status stkfmm_run(stkfmm_ctx *c, const double *sl_val, const double *dl_val, double *trg_val,
-                         void *stream) {
+}  // extern "C"
+
+namespace {
+
+stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val, double *trg_val, void *stream) {
     if (!c) return STKFMM_E_ARG;
     if (!c->planned) return fail(c, STKFMM_E_STATE, "stkfmm_run before stkfmm_set_points");
     if ((c->n_sl > 0 && !sl_val) || (c->n_dl > 0 && !dl_val) || (c->n_trg > 0 && !trg_val))
@@ -1095,6 +1182,165 @@ stkfmm_status stkfmm_run(stkfmm_ctx *c, const double *sl_val, const double *dl_v
     c->stage_ms[7] = ms;
     HIP_TRY(c, hipEventElapsedTime(&ms, ev[ne - 2], ev[ne - 1]));
     c->stage_ms[8] = ms;
+    return STKFMM_OK;
+}
+
+__global__ void gather_rows(const double *__restrict__ src, const int32_t *__restrict__ idx, int n, int w,
+                            double *__restrict__ dst) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * w) return;
+    dst[i] = src[int64_t(idx[i / w]) * w + i % w];
+}
+
+// Relative L2 error, per output field (the largest is returned), of the
+// last run's result at up to 256 evenly spaced targets against the FP64
+// direct sum on the GPU.
+stkfmm_status sampled_error(stkfmm_ctx *c, const double *sl_val, const double *dl_val, const double *trg_val,
+                            void *stream, double *err) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const KernelInfo &ki = kInfo[c->kernel];
+    const int S = int(std::min<int64_t>(256, c->n_trg)), kt = ki.k_trg;
+    std::vector<int32_t> idx(S);
+    for (int k = 0; k < S; ++k) idx[k] = c->tree.perm_trg[size_t((int64_t(k) * c->n_trg) / S)];
+    HIP_TRY(c, c->vbuf[0].ensure(S * sizeof(int32_t)));
+    HIP_TRY(c, c->vbuf[1].ensure(size_t(S) * kt * sizeof(double)));
+    HIP_TRY(c, c->vbuf[2].ensure(size_t(S) * 3 * sizeof(double)));
+    HIP_TRY(c, c->vbuf[3].ensure(size_t(S) * kt * sizeof(double)));
+    HIP_TRY(c, hipMemcpyAsync(c->vbuf[0].p, idx.data(), S * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(gather_rows, dim3((S * kt + 255) / 256), dim3(256), 0, s, trg_val, c->vbuf[0].as<int32_t>(), S,
+                       kt, c->vbuf[1].as<double>());
+    hipLaunchKernelGGL(gather_rows, dim3((S * 3 + 255) / 256), dim3(256), 0, s, c->coords[2].as<double>(),
+                       c->vbuf[0].as<int32_t>(), S, 3, c->vbuf[2].as<double>());
+    HIP_TRY(c, hipGetLastError());
+    DirectArgs a;
+    a.n_sl = c->n_sl;
+    a.n_dl = c->n_dl;
+    a.n_trg = S;
+    a.sl = c->coords[0].as<double>();
+    a.sl_val = sl_val;
+    a.dl = c->coords[1].as<double>();
+    a.dl_val = dl_val;
+    a.trg = c->vbuf[2].as<double>();
+    a.k_sl = ki.k_sl;
+    a.k_dl = ki.k_dl;
+    a.k_trg = kt;
+    a.out = c->vbuf[3].as<double>();
+    HIP_TRY(c, launch_direct_f64(c->kernel, a, s));
+    std::vector<double> got(size_t(S) * kt), ref(size_t(S) * kt);
+    HIP_TRY(c, hipMemcpyAsync(got.data(), c->vbuf[1].p, got.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(ref.data(), c->vbuf[3].p, ref.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    // output fields: (u), (u, lap u), (phi, grad phi), (p, u), (sigma)
+    static const int fields[kNumKernels][3] = {{0, 1, 4}, {0, 3, 3}, {0, 3, 6}, {0, 1, 4}, {0, 9, 9}};
+    const int *fb = fields[c->kernel];
+    double worst = 0.0;
+    for (int f = 0; f < 2; ++f) {
+        const int a0 = fb[f], a1 = fb[f + 1];
+        if (a1 <= a0) continue;
+        double num = 0, den = 0;
+        for (int k = 0; k < S; ++k)
+            for (int j = a0; j < a1; ++j) {
+                double d = got[size_t(k) * kt + j] - ref[size_t(k) * kt + j];
+                num += d * d;
+                den += ref[size_t(k) * kt + j] * ref[size_t(k) * kt + j];
+            }
+        worst = std::max(worst, den > 0 ? std::sqrt(num / den) : std::sqrt(num));
+    }
+    *err = worst;
+    return STKFMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+stkfmm_status stkfmm_run(stkfmm_ctx *c, const double *sl_val, const double *dl_val, double *trg_val, void *stream) {
+    stkfmm_status st = run_pass(c, sl_val, dl_val, trg_val, stream);
+    if (st != STKFMM_OK || !c->learned || c->validated || c->n_trg == 0) return st;
+    // learned plan: one accuracy check against the FP64 direct sum on sampled
+    // targets; above the tolerance, fall back to the fixed p = 10, leaf_cap = 2000 plan
+    double err = 0.0;
+    st = sampled_error(c, sl_val, dl_val, trg_val, stream, &err);
+    if (st != STKFMM_OK) return st;
+    c->validated = true;
+    c->sampled_err = err;
+    if (err <= c->tol) return STKFMM_OK;
+    int hp[4], hc[4];
+    std::memcpy(hp, c->p_hist, sizeof hp);
+    std::memcpy(hc, c->cap_hist, sizeof hc);
+    st = stkfmm_set_points(c, stkfmm_kernel(c->kernel), stkfmm_bc(c->bc), c->n_sl, c->coords[0].as<double>(), c->n_dl,
+                           c->coords[1].as<double>(), c->n_trg, c->coords[2].as<double>(), 10, kReferenceCap, stream);
+    if (st != STKFMM_OK) return st;
+    st = run_pass(c, sl_val, dl_val, trg_val, stream);
+    if (st != STKFMM_OK) return st;
+    // c->coords still hold the caller's points: the fixed plan does not touch them
+    st = sampled_error(c, sl_val, dl_val, trg_val, stream, &err);
+    if (st != STKFMM_OK) return st;
+    c->learned = true;
+    c->validated = true;
+    c->fell_back = true;
+    c->sampled_err = err;
+    std::memcpy(c->p_hist, hp, sizeof hp);
+    std::memcpy(c->cap_hist, hc, sizeof hc);
+    if (err > c->tol) return fail(c, STKFMM_E_ACCURACY, "sampled error above tol after the fixed-order fallback");
+    return STKFMM_OK;
+}
+
+stkfmm_status stkfmm_set_predictor(stkfmm_ctx *c, const float *params, int n) {
+    if (!c) return STKFMM_E_ARG;
+    const int np = stkfmm_mlp_nparam();
+    if (!params || n != np + 16) return fail(c, STKFMM_E_ARG, "predictor needs stkfmm_mlp_nparam() + 16 floats");
+    for (int k = 0; k < 16; ++k)
+        if (!(params[np + k] >= 0) || !std::isfinite(params[np + k]))
+            return fail(c, STKFMM_E_ARG, "order table entries must be finite and >= 0");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, c->predictor.ensure(size_t(np) * sizeof(float)));
+    HIP_TRY(c, hipMemcpy(c->predictor.p, params, size_t(np) * sizeof(float), hipMemcpyHostToDevice));
+    std::memcpy(c->order_table, params + np, sizeof(c->order_table));
+    c->has_predictor = true;
+    return STKFMM_OK;
+}
+
+stkfmm_status stkfmm_get_learned(const stkfmm_ctx *c, int64_t info[12], double *sampled_err) {
+    if (!c || !info) return STKFMM_E_ARG;
+    info[0] = c->learned;
+    info[1] = c->p;
+    info[2] = c->fell_back;
+    info[3] = c->validated;
+    for (int k = 0; k < 4; ++k) {
+        info[4 + k] = c->p_hist[k];
+        info[8 + k] = c->cap_hist[k];
+    }
+    if (sampled_err) *sampled_err = c->sampled_err;
+    return STKFMM_OK;
+}
+
+stkfmm_status stkfmm_get_leaf_features(stkfmm_ctx *c, float *features, int32_t *leaf_of_target, int64_t *n_leaf) {
+    if (!c || !n_leaf) return STKFMM_E_ARG;
+    if (!c->planned) return fail(c, STKFMM_E_STATE, "no plan");
+    const Tree &t = c->tree;
+    *n_leaf = int64_t(t.leaves.size());
+    if (features) {
+        std::vector<float> f;
+        leaf_features(t, c->hcoords[0].data(), c->hcoords[1].data(), c->hcoords[2].data(), c->tol, f);
+        std::memcpy(features, f.data(), f.size() * sizeof(float));
+    }
+    if (leaf_of_target)
+        for (size_t i = 0; i < t.leaves.size(); ++i) {
+            const Box &B = t.boxes[t.leaves[i]];
+            for (int64_t j = B.trg[0]; j < B.trg[1]; ++j) leaf_of_target[t.perm_trg[j]] = int32_t(i);
+        }
+    return STKFMM_OK;
+}
+
+stkfmm_status stkfmm_get_leaf_costs(stkfmm_ctx *c, const double rates[4], double *costs) {
+    if (!c || !rates || !costs) return STKFMM_E_ARG;
+    if (!c->planned) return fail(c, STKFMM_E_STATE, "no plan");
+    for (int k = 0; k < 4; ++k)
+        if (!(rates[k] > 0)) return fail(c, STKFMM_E_ARG, "rates must be positive");
+    std::vector<double> out;
+    leaf_costs(c->tree, rates, c->ops->M, c->ops->Mp, kInfo[c->kernel].ncomp, out);
+    std::memcpy(costs, out.data(), out.size() * sizeof(double));
     return STKFMM_OK;
 }
 

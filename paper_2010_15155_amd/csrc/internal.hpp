@@ -3,6 +3,7 @@
 
 #include <cstdint>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 namespace kafmm {
@@ -38,7 +39,12 @@ struct Box {
     bool leaf = true;
     int64_t sl[2] = {0, 0}, dl[2] = {0, 0}, trg[2] = {0, 0};   // ranges in sorted arrays
     int64_t nsrc_sub = 0, ntrg_sub = 0;                        // subtree totals
+    int cap = 0;                                               // split threshold of this box
 };
+
+inline uint64_t box_hash(int level, int32_t ax, int32_t ay, int32_t az) {
+    return (uint64_t(level) << 60) | (uint64_t(ax) << 40) | (uint64_t(ay) << 20) | uint64_t(az);
+}
 
 // A list entry: another box (or one of its periodic images) and the image
 // shift in root-box units.
@@ -52,6 +58,7 @@ struct Tree {
     std::vector<int> leaves;         // box ids of leaves
     std::vector<int> level_start;    // boxes of level l: [level_start[l], level_start[l+1])
     std::vector<int32_t> perm_sl, perm_dl, perm_trg;  // sorted position -> user index
+    std::vector<uint64_t> keys_sl, keys_dl, keys_trg; // sorted Morton keys
     int depth = 0;
     bool periodic = false;
     // Interaction lists (CSR by box id).
@@ -66,8 +73,31 @@ struct Tree {
 // Build the octree and interaction lists.  Coordinates are normalised to
 // [0,1) (already wrapped for periodic trees).  Returns an empty string or an
 // error message.
+// leaf_caps (optional): capacity of the boxes named by box_hash and of their
+// descendants; other boxes use leaf_cap.
 std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t n_dl,
-                       const double *trg, int64_t n_trg, int leaf_cap, bool periodic, Tree &t);
+                       const double *trg, int64_t n_trg, int leaf_cap, bool periodic, Tree &t,
+                       const std::unordered_map<uint64_t, int> *leaf_caps = nullptr);
+
+// Morton prefix of a box (its anchor bits interleaved): the box's points have
+// keys in [prefix << 3(21-level), (prefix+1) << 3(21-level)).
+uint64_t morton_prefix(int level, const int32_t anchor[3]);
+
+// ---- learned order / capacity predictor (host side)
+constexpr int kNumFeatures = 12;
+constexpr int kOrderClasses[4] = {6, 8, 10, 12};
+constexpr int kCapClasses[4] = {250, 500, 1000, 2000};
+constexpr int kReferenceCap = 2000;
+
+// Per-leaf features of a tree: coordinates are the normalised user-order
+// arrays the tree was built from.  out: [n_leaf][kNumFeatures].
+void leaf_features(const Tree &t, const double *sl, const double *dl, const double *trg, double tol,
+                   std::vector<float> &out);
+
+// Modelled cost (seconds) of every leaf of a reference tree refined to each
+// capacity class: rates = {P2P pairs/s, M2L flop/s, surface evaluations/s,
+// seconds per box}; M, Mp, ncomp of the order used.  out: [n_leaf][4].
+void leaf_costs(const Tree &t, const double rates[4], int M, int Mp, int ncomp, std::vector<double> &out);
 
 // Host-side FP64 operators for order p (unit box: side 1, centre 0).
 struct Operators {

@@ -70,10 +70,6 @@ Sorted sort_points(const double *x, int64_t n) {
     return s;
 }
 
-inline uint64_t box_hash(int level, int32_t ax, int32_t ay, int32_t az) {
-    return (uint64_t(level) << 60) | (uint64_t(ax) << 40) | (uint64_t(ay) << 20) | uint64_t(az);
-}
-
 struct Img {
     int box;
     std::array<int8_t, 3> s;
@@ -141,29 +137,48 @@ inline int64_t ntrg(const Box &b) { return b.trg[1] - b.trg[0]; }
 
 }  // namespace
 
+uint64_t morton_prefix(int level, const int32_t a[3]) {
+    (void)level;
+    return (spread3(uint32_t(a[0])) << 2) | (spread3(uint32_t(a[1])) << 1) | spread3(uint32_t(a[2]));
+}
+
 std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t n_dl,
-                       const double *trg, int64_t n_trg, int leaf_cap, bool periodic, Tree &t) {
+                       const double *trg, int64_t n_trg, int leaf_cap, bool periodic, Tree &t,
+                       const std::unordered_map<uint64_t, int> *leaf_caps) {
     t = Tree();
     t.periodic = periodic;
     Sorted S[3] = {sort_points(sl, n_sl), sort_points(dl, n_dl), sort_points(trg, n_trg)};
     t.perm_sl = S[0].perm;
     t.perm_dl = S[1].perm;
     t.perm_trg = S[2].perm;
+    t.keys_sl = std::move(S[0].key);
+    t.keys_dl = std::move(S[1].key);
+    t.keys_trg = std::move(S[2].key);
+    const std::vector<uint64_t> *keys[3] = {&t.keys_sl, &t.keys_dl, &t.keys_trg};
+    // a box's capacity: its own entry in leaf_caps, else its parent's
+    auto cap_of = [&](const Box &b, int parent_cap) {
+        if (leaf_caps) {
+            auto it = leaf_caps->find(box_hash(b.level, b.anchor[0], b.anchor[1], b.anchor[2]));
+            if (it != leaf_caps->end()) return it->second;
+        }
+        return parent_cap;
+    };
 
     Box root;
     root.sl[1] = n_sl;
     root.dl[1] = n_dl;
     root.trg[1] = n_trg;
+    root.cap = cap_of(root, leaf_cap);
     t.boxes.push_back(root);
     for (size_t i = 0; i < t.boxes.size(); ++i) {
         Box b = t.boxes[i];
         int64_t cnt = std::max({b.sl[1] - b.sl[0], b.dl[1] - b.dl[0], b.trg[1] - b.trg[0]});
-        if (cnt <= leaf_cap || b.level >= kMaxLevel) continue;
+        if (cnt <= b.cap || b.level >= kMaxLevel) continue;
         const int shift = 3 * (kKeyBits - (b.level + 1));
         int64_t bound[3][9];
         int64_t *rng[3] = {b.sl, b.dl, b.trg};
         for (int s = 0; s < 3; ++s) {
-            const auto &key = S[s].key;
+            const auto &key = *keys[s];
             for (int o = 0; o <= 8; ++o) {
                 auto first = key.begin() + rng[s][0], last = key.begin() + rng[s][1];
                 bound[s][o] = std::partition_point(first, last, [&](uint64_t k) {
@@ -182,6 +197,7 @@ std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t
             c.dl[0] = bound[1][o];  c.dl[1] = bound[1][o + 1];
             c.trg[0] = bound[2][o]; c.trg[1] = bound[2][o + 1];
             if (nsrc(c) + ntrg(c) == 0) continue;
+            c.cap = cap_of(c, b.cap);
             t.boxes[i].child[o] = int(t.boxes.size());
             t.boxes[i].leaf = false;
             t.boxes.push_back(c);

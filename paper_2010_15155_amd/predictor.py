@@ -1,0 +1,226 @@
+"""Training driver of the learned order / leaf-capacity predictor.
+
+Labels come from runs of the method itself (not in the paper, which fixes one
+global order and leaf size, Sec. III):
+  order class     smallest p in {6, 8, 10, 12} whose FMM result on the leaf's
+                  sampled targets has an RMS error, against the FP64 direct
+                  sum computed on the GPU (stkfmm_direct), within
+                  safety * tol * (RMS of the field over all sampled targets):
+                  if every leaf meets it, the relative L2 error over all
+                  targets is within safety * tol;
+  capacity class  the capacity in {250, 500, 1000, 2000} with the smallest
+                  modelled cost for the leaf (stkfmm_get_leaf_costs), with the
+                  model's rates measured on this GPU by `measure_rates`.
+Features: 12 per leaf of the reference tree (leaf_cap 2000), computed by the
+library.  Training runs the library's HIP kernels (forward, loss gradient,
+Adam).  Weights are saved as a float32 .npy (load with allow_pickle=False).
+
+  python -m paper_2010_15155_amd.predictor label --seeds 501:601 --out a.npz
+  python -m paper_2010_15155_amd.predictor train --data a.npz b.npz --out w.npy
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import CAP_CLASSES, FMM, ORDER_CLASSES, mlp_adam, mlp_loss_grad, mlp_nparam, workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(HERE, "predictor_weights.npy")
+N_RANGE = (100_000, 2_000_000)
+
+
+FLOOR = 1.25      # a leaf's order target: max(safety * tol, FLOOR * its best error over orders)
+SAFETY = 0.5
+
+
+def load_weights(path=WEIGHTS):
+    """Network parameters followed by the 4x4 order calibration table."""
+    w = np.load(path, allow_pickle=False)
+    if w.dtype != np.float32 or w.size != mlp_nparam() + 16:
+        raise ValueError("bad predictor weights file %s" % path)
+    return w
+
+
+def order_labels(E, tol=1e-5):
+    """Order class per leaf from its errors at the four orders: the smallest
+    order within max(SAFETY * tol, FLOOR * best error), so leaves whose error
+    floor (FP32 round-off) is above the target do not ask for more order."""
+    target = np.maximum(SAFETY * tol, FLOOR * E.min(axis=1))
+    return (E <= target[:, None]).argmax(axis=1).astype(np.int32)
+
+
+def calibration_table(E, cls):
+    """table[c][q] = RMS over leaves of class c of their error at order class q."""
+    t = np.zeros((4, 4))
+    for c in range(4):
+        m = cls == c
+        t[c] = np.sqrt(np.mean(E[m] ** 2, axis=0)) if m.any() else E.max()
+    return t
+
+
+def measure_rates(fmm, torch, n=1_048_576, p=8):
+    """Cost-model rates from one serial evaluation on this GPU: P2P pairs/s,
+    M2L flop/s, surface-tile evaluations/s, seconds per box."""
+    d = W.clustered_rpy(n, 201)
+    x = torch.from_numpy(d["xyz"]).cuda()
+    f = torch.from_numpy(d["f"]).cuda()
+    fmm.set_option("overlap", "0")
+    fmm.set_points("Stokeslet", x, None, x, p=p, leaf_cap=2000)
+    for _ in range(3):
+        fmm.run(f)
+    st, tm = fmm.stats(), fmm.timings()["stages_ms"]
+    fmm.set_option("overlap", "1")
+    M = st["M"]
+    Mp = (M + 31) // 32 * 32
+    p2p = st["p2p_pairs"] / (tm["p2p"] * 1e-3)
+    m2l = st["v_pairs"] * 2.0 * Mp * Mp * 4 / (tm["m2l"] * 1e-3)
+    evals = (2 * n + 2 * (st["w_pairs"] - st["w_direct"] + st["x_pairs"] - st["x_direct"]) * 300) * M
+    surf = evals / ((tm["s2m"] + tm["s2l"] + tm["l2t"]) * 1e-3)
+    per_box = (tm["upward"] + tm["downward"]) * 1e-3 / max(st["boxes"], 1)
+    return [p2p, m2l, surf, per_box]
+
+
+def label_set(fmm, torch, seed, rates, tol=1e-5, per_leaf=4):
+    """Features and (order, capacity) labels of every leaf with targets of one mixture."""
+    d = W.mixture(seed, N_RANGE)
+    x = torch.from_numpy(d["xyz"]).cuda()
+    f = torch.from_numpy(d["f"]).cuda()
+    outs = {}
+    for p in ORDER_CLASSES:
+        fmm.set_points("Stokeslet", x, None, x, p=p, leaf_cap=2000)
+        outs[p] = fmm.run(f).clone()
+    feat, leaf_of = fmm.leaf_features()
+    fmm.set_points("Stokeslet", x, None, x, p=8, leaf_cap=2000)
+    costs = fmm.leaf_costs(rates)
+    # sampled targets: up to per_leaf per leaf, spread over the leaf
+    rng = np.random.default_rng(seed)
+    order = np.argsort(leaf_of, kind="stable")
+    bounds = np.searchsorted(leaf_of[order], np.arange(len(feat) + 1))
+    sidx, sleaf = [], []
+    for L in range(len(feat)):
+        members = order[bounds[L]:bounds[L + 1]]
+        if len(members) == 0:
+            continue
+        take = rng.choice(members, size=min(per_leaf, len(members)), replace=False)
+        sidx.append(take)
+        sleaf.append(np.full(len(take), L))
+    sidx = np.concatenate(sidx)
+    sleaf = np.concatenate(sleaf)
+    ti = torch.from_numpy(sidx).cuda()
+    ref = fmm.direct("Stokeslet", x, f, None, None, x[ti].contiguous()).cpu().numpy()
+    keep = np.unique(sleaf)
+    labels = np.zeros((len(keep), 2), dtype=np.int32)
+    errs = np.zeros((len(keep), len(ORDER_CLASSES)))
+    rms_all = np.sqrt(np.mean(np.sum(ref ** 2, axis=1)))
+    cnt = np.bincount(sleaf, minlength=len(feat)).astype(np.float64)
+    for k, p in enumerate(ORDER_CLASSES):
+        got = outs[p][ti].cpu().numpy()
+        num = np.zeros(len(feat))
+        np.add.at(num, sleaf, np.sum((got - ref) ** 2, axis=1))
+        errs[:, k] = np.sqrt(num[keep] / cnt[keep]) / rms_all      # leaf RMS error / global RMS field
+    labels[:, 0] = order_labels(errs, tol)
+    labels[:, 1] = costs[keep].argmin(axis=1)
+    return feat[keep], labels, errs, {"seed": seed, "n": len(d["xyz"]), "leaves": len(feat), "k": d["k"]}
+
+
+def train(X, Y, epochs=60, batch=1024, lr=2e-3, seed=0, log=None):
+    """Train on the GPU with the library's kernels; returns float32 parameters."""
+    import torch
+    mean = X.mean(0)
+    std = X.std(0) + 1e-3
+    theta = init_params(seed, mean, std)
+    p = torch.from_numpy(theta).cuda()
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    rng = np.random.default_rng(seed)
+    Xt = torch.from_numpy(X.astype(np.float32)).cuda()
+    Yt = torch.from_numpy(Y.astype(np.int32)).cuda()
+    step = 0
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(len(X))).cuda()
+        tot = 0.0
+        nb = 0
+        for s in range(0, len(X) - batch + 1, batch):
+            idx = perm[s:s + batch]
+            step += 1
+            loss, g = mlp_loss_grad(p, Xt[idx].contiguous(), Yt[idx].contiguous())
+            mlp_adam(p, g, m, v, step, lr)
+            tot += float(loss.cpu())
+            nb += 1
+        if log is not None:
+            log.append({"epoch": ep, "loss": tot / max(nb, 1)})
+    return p.cpu().numpy()
+
+
+def init_params(seed, mean, std):
+    """He-initialised parameters in the library's layout (mean, std, W1, b1, W2, b2, W3, b3)."""
+    rng = np.random.default_rng(seed)
+    F, H, C = 12, 64, 8
+    parts = [np.asarray(mean, np.float64), np.asarray(std, np.float64)]
+    for fi, fo in ((F, H), (H, H), (H, C)):
+        parts.append(rng.standard_normal(fi * fo) * np.sqrt(2.0 / fi))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("label")
+    a.add_argument("--seeds", default="501:701")
+    a.add_argument("--out", required=True)
+    a.add_argument("--rates", default="")
+    t = sub.add_parser("train")
+    t.add_argument("--data", nargs="+", required=True)
+    t.add_argument("--out", default=WEIGHTS)
+    t.add_argument("--epochs", type=int, default=60)
+    args = ap.parse_args(argv)
+    import torch
+    if args.cmd == "label":
+        fmm = FMM()
+        rates = [float(r) for r in args.rates.split(",")] if args.rates else measure_rates(fmm, torch)
+        print(json.dumps({"rates": rates}), flush=True)
+        lo, hi = (int(s) for s in args.seeds.split(":"))
+        Xs, Ys, Es, meta = [], [], [], []
+        for seed in range(lo, hi):
+            t0 = time.time()
+            X, Y, E, info = label_set(fmm, torch, seed, rates)
+            Xs.append(X)
+            Ys.append(Y)
+            Es.append(E)
+            info.update(secs=time.time() - t0, order_hist=np.bincount(Y[:, 0], minlength=4).tolist(),
+                        cap_hist=np.bincount(Y[:, 1], minlength=4).tolist())
+            meta.append(info)
+            print(json.dumps(info), flush=True)
+            np.savez(args.out, X=np.concatenate(Xs), Y=np.concatenate(Ys), E=np.concatenate(Es),
+                     rates=np.array(rates), seeds=np.array([m["seed"] for m in meta]))
+    else:
+        data = [np.load(f, allow_pickle=False) for f in args.data]
+        X = np.concatenate([d["X"] for d in data])
+        Y = np.concatenate([d["Y"] for d in data])
+        E = np.concatenate([d["E"] for d in data])
+        Y[:, 0] = order_labels(E)
+        log = []
+        w = train(X, Y, epochs=args.epochs, log=log)
+        # calibration table on the network's own predicted classes
+        import torch
+        from . import mlp_forward
+        logits = mlp_forward(torch.from_numpy(w).cuda(), torch.from_numpy(X.astype(np.float32)).cuda()).cpu().numpy()
+        pred = logits[:, :4].argmax(axis=1)
+        table = calibration_table(E, pred)
+        np.save(args.out, np.concatenate([w, table.reshape(-1)]).astype(np.float32), allow_pickle=False)
+        acc = [float((pred == Y[:, 0]).mean()), float((logits[:, 4:].argmax(axis=1) == Y[:, 1]).mean())]
+        print(json.dumps({"table": table.tolist(), "train_accuracy": acc}), flush=True)
+        print(json.dumps({"rows": len(X), "final_loss": log[-1]["loss"], "first_loss": log[0]["loss"],
+                          "order_hist": np.bincount(Y[:, 0], minlength=4).tolist(),
+                          "cap_hist": np.bincount(Y[:, 1], minlength=4).tolist()}), flush=True)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
