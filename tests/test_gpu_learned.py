@@ -1,0 +1,76 @@
+"""Learned order / leaf-capacity mode with the shipped weights: accuracy at
+the 1e-5 tolerance on the 1M clustered workload and on held-out mixtures
+(seeds outside the training range), and its gain over the fixed p = 10,
+leaf_cap = 2000 plan on the 1M clustered workload."""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _fmm():
+    from paper_2010_15155_amd import FMM
+    from paper_2010_15155_amd.predictor import load_weights
+    fmm = FMM()
+    fmm.set_predictor(load_weights())
+    return fmm
+
+
+def _err(fmm, x, f, out, seed=7, k=2048):
+    from paper_2010_15155_amd import workloads as W
+    idx = torch.from_numpy(W.sample_indices(len(x), k, seed)).cuda()
+    ref = fmm.direct("Stokeslet", x, f, None, None, x[idx].contiguous())
+    return float(torch.linalg.norm(out[idx] - ref) / torch.linalg.norm(ref))
+
+
+def _time(fmm, f, reps=5):
+    fmm.run(f)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fmm.run(f)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return out, float(np.median(ts))
+
+
+def test_learned_beats_fixed_p10_on_clustered_1m():
+    from paper_2010_15155_amd import workloads as W
+    d = W.clustered_rpy(1_048_576, 201)
+    x = torch.from_numpy(d["xyz"]).cuda()
+    f = torch.from_numpy(d["f"]).cuda()
+    fmm = _fmm()
+    fmm.set_points("Stokeslet", x, None, x, p=10, leaf_cap=2000)
+    out_f, t_fixed = _time(fmm, f)
+    e_fixed = _err(fmm, x, f, out_f)
+    fmm.set_points("Stokeslet", x, None, x, p=0, leaf_cap=0)
+    out_l, t_learned = _time(fmm, f)
+    info = fmm.learned_info()
+    e_learned = _err(fmm, x, f, out_l)
+    print("fixed %.2f ms err %.2e | learned %.2f ms err %.2e %s" %
+          (t_fixed * 1e3, e_fixed, t_learned * 1e3, e_learned, info), flush=True)
+    fmm.close()
+    assert info["learned"] and info["validated"] and not info["fell_back"]
+    assert e_fixed < 1e-5 and e_learned < 1e-5
+    assert t_learned < 0.9 * t_fixed
+
+
+@pytest.mark.parametrize("seed", [901, 902, 903])
+def test_learned_meets_tolerance_on_held_out_mixtures(seed):
+    from paper_2010_15155_amd import workloads as W
+    d = W.mixture(seed, (100_000, 600_000))
+    x = torch.from_numpy(d["xyz"]).cuda()
+    f = torch.from_numpy(d["f"]).cuda()
+    fmm = _fmm()
+    fmm.set_points("Stokeslet", x, None, x, p=0, leaf_cap=0)
+    out = fmm.run(f)
+    info = fmm.learned_info()
+    err = _err(fmm, x, f, out, seed=seed)
+    print("seed %d n %d err %.2e %s" % (seed, len(x), err, info), flush=True)
+    fmm.close()
+    assert info["validated"] or info["fell_back"]
+    assert err < 1e-5
