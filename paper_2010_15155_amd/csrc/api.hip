@@ -126,9 +126,10 @@ struct stkfmm_ctx {
     Tree tree;
     DeviceOps *ops = nullptr;
     DevMem arena, sl_rec, dl_rec, trg_rec, up_dens, dn_dens, up_chk, dn_chk, Ybuf, tmp64, near_part, far_part,
-        s2c_part, partial;
+        s2c_part, partial, direct_work;
     size_t a_perm_sl = 0, a_perm_dl = 0, a_perm_trg = 0, a_geom = 0, a_box_sl = 0, a_box_dl = 0, a_chunks = 0,
-           a_chunk_tasks = 0, a_p2p_tasks = 0, a_p2p_ent = 0, a_l2t_tasks = 0, a_l2t_ent = 0;
+           a_chunk_tasks = 0, a_p2p_tasks = 0, a_p2p_ent = 0, a_l2t_tasks = 0, a_l2t_ent = 0, a_leaves_sl = 0;
+    int n_leaves_sl = 0;
     int nchunks = 0, n_p2p_tasks = 0, n_l2t_tasks = 0, nbox = 0;
     S2CPhase s2m, s2l;
     int64_t w_direct = 0, x_direct = 0, direct_pairs = 0;
@@ -614,6 +615,11 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     c->a_geom = ar.add(geom);
     c->a_box_sl = ar.add(bsl);
     c->a_box_dl = ar.add(bdl);
+    std::vector<int> leaves_sl;
+    for (int b : t.leaves)
+        if (t.boxes[b].sl[1] > t.boxes[b].sl[0]) leaves_sl.push_back(b);
+    c->n_leaves_sl = int(leaves_sl.size());
+    c->a_leaves_sl = ar.add(leaves_sl);
     // ---- direct (P2P) lists per leaf: U, plus W and X pairs cheaper to sum directly.
     // Per pair of points, a direct Stokes-kernel sum costs about 30 FP32
     // operations, an M2T evaluation 22 and a surface-tile (S2L) evaluation 15,
@@ -622,20 +628,37 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     // within the far-field error, so this only moves work.
     std::vector<std::vector<int2>> dlist(nb), wkeep(nb), xkeep(nb);
     c->w_direct = c->x_direct = 0;
+    std::vector<int> stack;
+    // a direct entry always names a leaf: a W box that is not a leaf enters as
+    // the leaves below it that hold sources (same image shift)
+    auto push_leaves = [&](std::vector<int2> &dst, int2 e) {
+        stack.assign(1, e.x);
+        while (!stack.empty()) {
+            const int q = stack.back();
+            stack.pop_back();
+            const Box &Q = t.boxes[q];
+            if (Q.nsrc_sub == 0) continue;
+            if (Q.leaf) {
+                dst.push_back(make_int2(q, e.y));
+                continue;
+            }
+            for (int o = 7; o >= 0; --o)
+                if (Q.child[o] >= 0) stack.push_back(Q.child[o]);
+        }
+    };
     for (int b : t.leaves) {
         if (t.boxes[b].ntrg_sub == 0) continue;
         for (int i = t.u_off[b]; i < t.u_off[b + 1]; ++i) dlist[b].push_back(make_int2(t.u[i].box, pack_shift(t.u[i].shift)));
         for (int i = t.w_off[b]; i < t.w_off[b + 1]; ++i) {
             int2 e = make_int2(t.w[i].box, pack_shift(t.w[i].shift));
             if (double(t.boxes[e.x].nsrc_sub) < c->w_direct_frac * M) {
-                dlist[b].push_back(e);
+                push_leaves(dlist[b], e);
                 ++c->w_direct;
             } else {
                 wkeep[b].push_back(e);
             }
         }
     }
-    std::vector<int> stack;
     for (int b = 0; b < nb; ++b) {
         if (!t.has_local[b]) continue;
         for (int i = t.x_off[b]; i < t.x_off[b + 1]; ++i) {
@@ -884,6 +907,9 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     HIP_TRY(c, launch_pack_sources(n_dl, dl_xyz, nullptr, at<int32_t>(c, c->a_perm_dl), org, inv, -1,
                                    std::max(ki.rec_dl, 8), c->dl_rec.as<float>(), s));
     HIP_TRY(c, launch_pack_targets(n_trg, trg_xyz, at<int32_t>(c, c->a_perm_trg), org, inv, c->trg_rec.as<float>(), s));
+    if (p2p_uses_rel(c->kernel))
+        HIP_TRY(c, launch_rel_positions(c->n_leaves_sl, at<int>(c, c->a_leaves_sl), at<int2>(c, c->a_box_sl),
+                                        at<double4>(c, c->a_geom), ki.rec_sl, c->sl_rec.as<float>(), s));
     HIP_TRY(c, hipStreamSynchronize(s));
     c->t_tree_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     c->planned = true;
@@ -1065,6 +1091,7 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         a.box_dl = at<int2>(c, c->a_box_dl);
         a.sl = c->sl_rec.as<float>();
         a.dl = c->dl_rec.as<float>();
+        a.geom = at<double4>(c, c->a_geom);
         a.part = c->near_part.as<double>();
         HIP_TRY(c, launch_p2p(c->kernel, c->n_p2p_tasks, a, ps));
     }
@@ -1225,6 +1252,9 @@ stkfmm_status sampled_error(stkfmm_ctx *c, const double *sl_val, const double *d
     a.k_dl = ki.k_dl;
     a.k_trg = kt;
     a.out = c->vbuf[3].as<double>();
+    a.slices = direct_f64_slices(S, std::max(c->n_sl, c->n_dl));
+    HIP_TRY(c, c->direct_work.ensure(std::max<size_t>(1, size_t(a.slices) * S * kt) * sizeof(double)));
+    a.work = c->direct_work.as<double>();
     HIP_TRY(c, launch_direct_f64(c->kernel, a, s));
     std::vector<double> got(size_t(S) * kt), ref(size_t(S) * kt);
     HIP_TRY(c, hipMemcpyAsync(got.data(), c->vbuf[1].p, got.size() * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1379,6 +1409,12 @@ stkfmm_status stkfmm_direct(stkfmm_ctx *c, stkfmm_kernel kernel, int64_t n_sl, c
     a.k_dl = ki.k_dl;
     a.k_trg = ki.k_trg;
     a.out = trg_val;
+    a.slices = direct_f64_slices(n_trg, std::max(n_sl, n_dl));
+    a.work = nullptr;
+    if (a.slices > 1) {
+        HIP_TRY(c, c->direct_work.ensure(size_t(a.slices) * size_t(n_trg) * ki.k_trg * sizeof(double)));
+        a.work = c->direct_work.as<double>();
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(c, launch_direct_f64(kernel, a, s));
     HIP_TRY(c, hipStreamSynchronize(s));

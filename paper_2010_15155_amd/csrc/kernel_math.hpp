@@ -43,121 +43,138 @@ __device__ __forceinline__ float rsq_or_zero(float r2) {
     return r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;
 }
 
+// Accumulations are written as explicit fused multiply-add chains: the
+// compiler may not reassociate a += x*y + z*w into two FMAs by itself.
+__device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, float by, float bz) {
+    return fmaf(ax, bx, fmaf(ay, by, az * bz));
+}
+
 // ------------------------------------------------------------------ direct kernels
 // Source records: [xh, yh, zh, xl, yl, zl, values...]; value layouts below.
+// REL: the record also holds the source's position relative to its leaf
+// centre in FP32 at [9, 10, 11], and the P2P kernel forms r from it (see the
+// kernel); otherwise r is formed from the hi/lo coordinates.
 
-struct DStokeslet {       // SL f0 f1 f2
+struct DStokeslet {       // SL f0 f1 f2 ; leaf-relative position at 9..11
     static constexpr int RS = 12, RD = 0, NACC = 3;
+    static constexpr bool REL = true;
+    // u = (1/r) (f + r (r.f)/r^2)
     __device__ static void sl(float dx, float dy, float dz, float ri, const float *v, float *a) {
-        float ri3 = ri * ri * ri;
-        float t = (dx * v[0] + dy * v[1] + dz * v[2]) * ri3;
-        a[0] += v[0] * ri + dx * t;
-        a[1] += v[1] * ri + dy * t;
-        a[2] += v[2] * ri + dz * t;
+        float q = dot3(dx, dy, dz, v[0], v[1], v[2]) * (ri * ri);
+        a[0] = fmaf(ri, fmaf(dx, q, v[0]), a[0]);
+        a[1] = fmaf(ri, fmaf(dy, q, v[1]), a[1]);
+        a[2] = fmaf(ri, fmaf(dz, q, v[2]), a[2]);
     }
     __device__ static void dl(float, float, float, float, const float *, float *) {}
 };
 
 struct DRPY {             // SL f0 f1 f2 b^2
     static constexpr int RS = 12, RD = 0, NACC = 6;
+    static constexpr bool REL = false;
     __device__ static void sl(float dx, float dy, float dz, float ri, const float *v, float *a) {
         float ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2;
-        float rf = dx * v[0] + dy * v[1] + dz * v[2];
+        float rf = dot3(dx, dy, dz, v[0], v[1], v[2]);
         float b2 = v[3];
-        float cf = ri + (b2 * (1.0f / 3.0f)) * ri3;
-        float cr = (ri3 - b2 * ri5) * rf;
-        a[0] += cf * v[0] + cr * dx;
-        a[1] += cf * v[1] + cr * dy;
-        a[2] += cf * v[2] + cr * dz;
+        float cf = fmaf(b2 * (1.0f / 3.0f), ri3, ri);
+        float cr = fmaf(-b2, ri5, ri3) * rf;
+        a[0] = fmaf(cr, dx, fmaf(cf, v[0], a[0]));
+        a[1] = fmaf(cr, dy, fmaf(cf, v[1], a[1]));
+        a[2] = fmaf(cr, dz, fmaf(cf, v[2], a[2]));
         float lf = 2.0f * ri3, lr = -6.0f * rf * ri5;
-        a[3] += lf * v[0] + lr * dx;
-        a[4] += lf * v[1] + lr * dy;
-        a[5] += lf * v[2] + lr * dz;
+        a[3] = fmaf(lr, dx, fmaf(lf, v[0], a[3]));
+        a[4] = fmaf(lr, dy, fmaf(lf, v[1], a[4]));
+        a[5] = fmaf(lr, dz, fmaf(lf, v[2], a[5]));
     }
     __device__ static void dl(float, float, float, float, const float *, float *) {}
 };
 
 struct DLapPGrad {        // SL q ; DL d0 d1 d2
     static constexpr int RS = 8, RD = 12, NACC = 4;
+    static constexpr bool REL = false;
     __device__ static void sl(float dx, float dy, float dz, float ri, const float *v, float *a) {
         float q = v[0];
-        float t = q * ri * ri * ri;
-        a[0] += q * ri;
-        a[1] -= t * dx;
-        a[2] -= t * dy;
-        a[3] -= t * dz;
+        float t = -q * (ri * ri * ri);
+        a[0] = fmaf(q, ri, a[0]);
+        a[1] = fmaf(t, dx, a[1]);
+        a[2] = fmaf(t, dy, a[2]);
+        a[3] = fmaf(t, dz, a[3]);
     }
     __device__ static void dl(float dx, float dy, float dz, float ri, const float *v, float *a) {
         float ri2 = ri * ri, ri3 = ri2 * ri;
-        float dr = dx * v[0] + dy * v[1] + dz * v[2];
-        float t = -3.0f * dr * ri3 * ri2;
-        a[0] += dr * ri3;
-        a[1] += v[0] * ri3 + t * dx;
-        a[2] += v[1] * ri3 + t * dy;
-        a[3] += v[2] * ri3 + t * dz;
+        float dr = dot3(dx, dy, dz, v[0], v[1], v[2]);
+        float t = -3.0f * dr * (ri3 * ri2);
+        a[0] = fmaf(dr, ri3, a[0]);
+        a[1] = fmaf(t, dx, fmaf(v[0], ri3, a[1]));
+        a[2] = fmaf(t, dy, fmaf(v[1], ri3, a[2]));
+        a[3] = fmaf(t, dz, fmaf(v[2], ri3, a[3]));
     }
 };
 
 // symmetric D^s stored (xx, xy, xz, yy, yz, zz)
 __device__ __forceinline__ void sym_apply(const float *s, float dx, float dy, float dz,
                                           float &wx, float &wy, float &wz) {
-    wx = s[0] * dx + s[1] * dy + s[2] * dz;
-    wy = s[1] * dx + s[3] * dy + s[4] * dz;
-    wz = s[2] * dx + s[4] * dy + s[5] * dz;
+    wx = dot3(s[0], s[1], s[2], dx, dy, dz);
+    wy = dot3(s[1], s[3], s[4], dx, dy, dz);
+    wz = dot3(s[2], s[4], s[5], dx, dy, dz);
 }
 
 struct DPVel {            // SL f0 f1 f2 q ; DL D^s (6)      out p, u   [x 1/8pi]
     static constexpr int RS = 12, RD = 12, NACC = 4;
+    static constexpr bool REL = false;
     __device__ static void sl(float dx, float dy, float dz, float ri, const float *v, float *a) {
         float ri2 = ri * ri, ri3 = ri2 * ri;
-        float rf = dx * v[0] + dy * v[1] + dz * v[2];
-        a[0] += 2.0f * rf * ri3;
+        float rf = dot3(dx, dy, dz, v[0], v[1], v[2]);
+        a[0] = fmaf(2.0f * rf, ri3, a[0]);
         float t = (rf - v[3]) * ri3;
-        a[1] += v[0] * ri + dx * t;
-        a[2] += v[1] * ri + dy * t;
-        a[3] += v[2] * ri + dz * t;
+        a[1] = fmaf(dx, t, fmaf(v[0], ri, a[1]));
+        a[2] = fmaf(dy, t, fmaf(v[1], ri, a[2]));
+        a[3] = fmaf(dz, t, fmaf(v[2], ri, a[3]));
     }
     __device__ static void dl(float dx, float dy, float dz, float ri, const float *v, float *a) {
         float ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2;
         float wx, wy, wz;
         sym_apply(v, dx, dy, dz, wx, wy, wz);
-        float A = dx * wx + dy * wy + dz * wz;
+        float A = dot3(dx, dy, dz, wx, wy, wz);
         float tr = v[0] + v[3] + v[5];
-        a[0] += 2.0f * (tr * ri3 - 3.0f * A * ri5);
         float t = -3.0f * A * ri5;
-        a[1] += t * dx;
-        a[2] += t * dy;
-        a[3] += t * dz;
+        a[0] = fmaf(2.0f, fmaf(tr, ri3, t), a[0]);
+        a[1] = fmaf(t, dx, a[1]);
+        a[2] = fmaf(t, dy, a[2]);
+        a[3] = fmaf(t, dz, a[3]);
     }
 };
 
 struct DTraction {        // SL f0 f1 f2 q ; DL D^s (6)     out sigma sym (6)  [x 1/4pi]
     static constexpr int RS = 12, RD = 12, NACC = 6;
+    static constexpr bool REL = false;
     __device__ static void sl(float dx, float dy, float dz, float ri, const float *v, float *a) {
         float ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2;
-        float rf = dx * v[0] + dy * v[1] + dz * v[2];
+        float rf = dot3(dx, dy, dz, v[0], v[1], v[2]);
         float q = v[3];
         float c = 3.0f * (q - rf) * ri5, d = q * ri3;
-        a[0] += c * dx * dx - d;
-        a[1] += c * dx * dy;
-        a[2] += c * dx * dz;
-        a[3] += c * dy * dy - d;
-        a[4] += c * dy * dz;
-        a[5] += c * dz * dz - d;
+        float cx = c * dx, cy = c * dy;
+        a[0] = fmaf(cx, dx, a[0] - d);
+        a[1] = fmaf(cx, dy, a[1]);
+        a[2] = fmaf(cx, dz, a[2]);
+        a[3] = fmaf(cy, dy, a[3] - d);
+        a[4] = fmaf(cy, dz, a[4]);
+        a[5] = fmaf(c * dz, dz, a[5] - d);
     }
     __device__ static void dl(float dx, float dy, float dz, float ri, const float *v, float *a) {
         float ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2, ri7 = ri5 * ri2;
         float wx, wy, wz;
         sym_apply(v, dx, dy, dz, wx, wy, wz);
-        float A = dx * wx + dy * wy + dz * wz;
+        float A = dot3(dx, dy, dz, wx, wy, wz);
         float tr = v[0] + v[3] + v[5];
         float e = 15.0f * A * ri7, g = -3.0f * ri5, d = tr * ri3;
-        a[0] += e * dx * dx + 2.0f * g * dx * wx - d;
-        a[1] += e * dx * dy + g * (dx * wy + wx * dy);
-        a[2] += e * dx * dz + g * (dx * wz + wx * dz);
-        a[3] += e * dy * dy + 2.0f * g * dy * wy - d;
-        a[4] += e * dy * dz + g * (dy * wz + wy * dz);
-        a[5] += e * dz * dz + 2.0f * g * dz * wz - d;
+        float ex = e * dx, ey = e * dy;
+        float gx = g * dx, gy = g * dy, gz = g * dz;
+        a[0] = fmaf(ex, dx, fmaf(2.0f * gx, wx, a[0] - d));
+        a[1] = fmaf(ex, dy, fmaf(gx, wy, fmaf(gy, wx, a[1])));
+        a[2] = fmaf(ex, dz, fmaf(gx, wz, fmaf(gz, wx, a[2])));
+        a[3] = fmaf(ey, dy, fmaf(2.0f * gy, wy, a[3] - d));
+        a[4] = fmaf(ey, dz, fmaf(gy, wz, fmaf(gz, wy, a[4])));
+        a[5] = fmaf(e * dz, dz, fmaf(2.0f * gz, wz, a[5] - d));
     }
 };
 
@@ -168,10 +185,10 @@ struct DTraction {        // SL f0 f1 f2 q ; DL D^s (6)     out sigma sym (6)  [
 struct EStokeslet {       // u_i += phi_i/r - r_i s/r^3      [x 1/(8 pi)]
     static constexpr int NC = 4, NACC = 3;
     __device__ static void eq(float dx, float dy, float dz, float ri, const float *ph, float s, float *a) {
-        float t = s * ri * ri * ri;
-        a[0] += ph[0] * ri - dx * t;
-        a[1] += ph[1] * ri - dy * t;
-        a[2] += ph[2] * ri - dz * t;
+        float t = -s * (ri * ri);
+        a[0] = fmaf(ri, fmaf(dx, t, ph[0]), a[0]);
+        a[1] = fmaf(ri, fmaf(dy, t, ph[1]), a[1]);
+        a[2] = fmaf(ri, fmaf(dz, t, ph[2]), a[2]);
     }
 };
 
@@ -179,16 +196,16 @@ struct ERPY {             // + lap u_i = -(3 r_i (r.phi)/r^5 - phi_i/r^3)   [x 1
     static constexpr int NC = 4, NACC = 6;
     __device__ static void eq(float dx, float dy, float dz, float ri, const float *ph, float s, float *a) {
         float ri2 = ri * ri, ri3 = ri2 * ri;
-        float t = s * ri3;
-        a[0] += ph[0] * ri - dx * t;
-        a[1] += ph[1] * ri - dy * t;
-        a[2] += ph[2] * ri - dz * t;
-        float rp = dx * ph[0] + dy * ph[1] + dz * ph[2];
-        float c = -6.0f * rp * ri3 * ri2;
+        float t = -s * ri2;
+        a[0] = fmaf(ri, fmaf(dx, t, ph[0]), a[0]);
+        a[1] = fmaf(ri, fmaf(dy, t, ph[1]), a[1]);
+        a[2] = fmaf(ri, fmaf(dz, t, ph[2]), a[2]);
+        float rp = dot3(dx, dy, dz, ph[0], ph[1], ph[2]);
+        float c = -6.0f * rp * (ri3 * ri2);
         float d = 2.0f * ri3;
-        a[3] += c * dx + d * ph[0];
-        a[4] += c * dy + d * ph[1];
-        a[5] += c * dz + d * ph[2];
+        a[3] = fmaf(c, dx, fmaf(d, ph[0], a[3]));
+        a[4] = fmaf(c, dy, fmaf(d, ph[1], a[4]));
+        a[5] = fmaf(c, dz, fmaf(d, ph[2], a[5]));
     }
 };
 
@@ -196,24 +213,24 @@ struct ELapPGrad {        // phi += q/r, grad phi += -q r/r^3   [x 1/(4 pi)]
     static constexpr int NC = 1, NACC = 4;
     __device__ static void eq(float dx, float dy, float dz, float ri, const float *ph, float, float *a) {
         float q = ph[0];
-        float t = q * ri * ri * ri;
-        a[0] += q * ri;
-        a[1] -= t * dx;
-        a[2] -= t * dy;
-        a[3] -= t * dz;
+        float t = -q * (ri * ri * ri);
+        a[0] = fmaf(q, ri, a[0]);
+        a[1] = fmaf(t, dx, a[1]);
+        a[2] = fmaf(t, dy, a[2]);
+        a[3] = fmaf(t, dz, a[3]);
     }
 };
 
 struct EPVel {            // p = (r.phi)/r^3 [x 1/(4 pi) -> x2 for 1/(8 pi)], u as Stokeslet
     static constexpr int NC = 4, NACC = 4;
     __device__ static void eq(float dx, float dy, float dz, float ri, const float *ph, float s, float *a) {
-        float ri3 = ri * ri * ri;
-        float rp = dx * ph[0] + dy * ph[1] + dz * ph[2];
-        a[0] += 2.0f * rp * ri3;
-        float t = s * ri3;
-        a[1] += ph[0] * ri - dx * t;
-        a[2] += ph[1] * ri - dy * t;
-        a[3] += ph[2] * ri - dz * t;
+        float ri2 = ri * ri, ri3 = ri2 * ri;
+        float rp = dot3(dx, dy, dz, ph[0], ph[1], ph[2]);
+        a[0] = fmaf(2.0f * rp, ri3, a[0]);
+        float t = -s * ri2;
+        a[1] = fmaf(ri, fmaf(dx, t, ph[0]), a[1]);
+        a[2] = fmaf(ri, fmaf(dy, t, ph[1]), a[2]);
+        a[3] = fmaf(ri, fmaf(dz, t, ph[2]), a[3]);
     }
 };
 
@@ -221,15 +238,16 @@ struct ETraction {        // sigma_ij += (3 r_i r_j/r^5 - delta_ij/r^3) s - delt
     static constexpr int NC = 4, NACC = 6;
     __device__ static void eq(float dx, float dy, float dz, float ri, const float *ph, float s, float *a) {
         float ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2;
-        float rp = dx * ph[0] + dy * ph[1] + dz * ph[2];
+        float rp = dot3(dx, dy, dz, ph[0], ph[1], ph[2]);
         float c = 3.0f * s * ri5;
         float d = (s + rp) * ri3;
-        a[0] += c * dx * dx - d;
-        a[1] += c * dx * dy;
-        a[2] += c * dx * dz;
-        a[3] += c * dy * dy - d;
-        a[4] += c * dy * dz;
-        a[5] += c * dz * dz - d;
+        float cx = c * dx, cy = c * dy;
+        a[0] = fmaf(cx, dx, a[0] - d);
+        a[1] = fmaf(cx, dy, a[1]);
+        a[2] = fmaf(cx, dz, a[2]);
+        a[3] = fmaf(cy, dy, a[3] - d);
+        a[4] = fmaf(cy, dz, a[4]);
+        a[5] = fmaf(c * dz, dz, a[5] - d);
     }
 };
 

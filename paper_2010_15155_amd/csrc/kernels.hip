@@ -12,6 +12,8 @@
 // writer, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernel_math.hpp"
 #include "kernels.hpp"
 
@@ -119,13 +121,58 @@ __global__ void pack_targets(int64_t n, const double *__restrict__ xyz, const in
 
 // ------------------------------------------------------------------ P2P (S->T over direct lists)
 // One block per task: up to 256 targets of one leaf (one per lane) against a
-// slice of the leaf's direct list (U list plus W/X pairs evaluated directly).
-// Source records are wave-uniform, so they arrive through scalar loads.  FP32
-// pair arithmetic on hi/lo coordinate differences; each run of 64 sources is
+// slice of the leaf's direct list (U list plus W/X pairs evaluated directly;
+// every entry is a leaf).  Source records are wave-uniform, so they arrive
+// through scalar loads.  FP32 pair arithmetic; each run of 64 sources is
 // summed in FP32 and added to FP64 accumulators; the task writes its partial
 // sums, which the combine step adds in task order.
+//
+// r = x - y is formed in one of two ways:
+//   hi/lo  r = (x_hi - y_hi) + (x_lo - y_lo): nearly exact for any pair;
+//   REL    per entry the target is moved, in FP64, into the frame of the
+//          source leaf's centre and rounded once; r = x_rel - y_rel with y_rel
+//          the FP32 source position relative to its leaf centre.  The error
+//          of r is a few ulp of the leaf side, a relative error of order
+//          1e-7 h / |r| per pair, and it saves 6 of about 26 operations per
+//          pair.  Used where the kernel's singularity is mild enough (the
+//          Stokeslet, 1/r) for that to stay far below the FMM error.
+template <class K>
+__device__ __forceinline__ void p2p_run(const float *__restrict__ src, int j0, int j1, float xh, float yh,
+                                        float zh, float xl, float yl, float zl, double *acc, bool dl) {
+    for (int r0 = j0; r0 < j1; r0 += 64) {
+        const int r1 = min(r0 + 64, j1);
+        float part[K::NACC];
+#pragma unroll
+        for (int k = 0; k < K::NACC; ++k) part[k] = 0.0f;
+        if (K::REL) {
+#pragma unroll 4
+            for (int j = r0; j < r1; ++j) {
+                const float *s = src + int64_t(j) * K::RS;
+                const float dx = xh - s[9], dy = yh - s[10], dz = zh - s[11];
+                const float ri = rsq_or_zero(dot3(dx, dy, dz, dx, dy, dz));
+                K::sl(dx, dy, dz, ri, s + 6, part);
+            }
+        } else {
+            const int rs = dl ? (K::RD > 0 ? K::RD : 1) : K::RS;
+#pragma unroll 4
+            for (int j = r0; j < r1; ++j) {
+                const float *s = src + int64_t(j) * rs;
+                const float dx = (xh - s[0]) + (xl - s[3]);
+                const float dy = (yh - s[1]) + (yl - s[4]);
+                const float dz = (zh - s[2]) + (zl - s[5]);
+                const float ri = rsq_or_zero(dot3(dx, dy, dz, dx, dy, dz));
+                if (dl) K::dl(dx, dy, dz, ri, s + 6, part);
+                else K::sl(dx, dy, dz, ri, s + 6, part);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K::NACC; ++k) acc[k] += double(part[k]);
+    }
+}
+
 template <class K>
 __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs a) {
+    static_assert(!K::REL || K::RD == 0, "REL positions exist for single-layer records only");
     const int4 task = a.tasks[blockIdx.x];
     const int4 ch = a.chunks[task.x];
     const int first = ch.y + int(threadIdx.x & ~63u);
@@ -140,49 +187,24 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs a) {
     for (int k = 0; k < K::NACC; ++k) acc[k] = 0.0;
     for (int e = task.y; e < task.z; ++e) {
         const int2 en = a.ent[e];
-        float xh = p0.x, yh = p0.y, zh = p0.z, xl = p1.x, yl = p1.y, zl = p1.z;
-        if (en.y != kZeroShift) {
-            int sx = shift_comp(en.y, 0), sy = shift_comp(en.y, 1), sz = shift_comp(en.y, 2);
+        const int sx = shift_comp(en.y, 0), sy = shift_comp(en.y, 1), sz = shift_comp(en.y, 2);
+        const int2 rs = a.box_sl[en.x];
+        if (K::REL) {
+            // target relative to the (image of the) source leaf's centre
+            const double4 g = a.geom[en.x];
+            const float xr = float((double(p0.x) - (g.x + sx)) + double(p1.x));
+            const float yr = float((double(p0.y) - (g.y + sy)) + double(p1.y));
+            const float zr = float((double(p0.z) - (g.z + sz)) + double(p1.z));
+            p2p_run<K>(a.sl, rs.x, rs.y, xr, yr, zr, 0.0f, 0.0f, 0.0f, acc, false);
+        } else {
+            float xh = p0.x, yh = p0.y, zh = p0.z, xl = p1.x, yl = p1.y, zl = p1.z;
             if (sx) two_sum_shift(xh, xl, float(sx));
             if (sy) two_sum_shift(yh, yl, float(sy));
             if (sz) two_sum_shift(zh, zl, float(sz));
-        }
-        const int2 rs = a.box_sl[en.x];
-        for (int j0 = rs.x; j0 < rs.y; j0 += 64) {
-            const int j1 = min(j0 + 64, rs.y);
-            float part[K::NACC];
-#pragma unroll
-            for (int k = 0; k < K::NACC; ++k) part[k] = 0.0f;
-#pragma unroll 4
-            for (int j = j0; j < j1; ++j) {
-                const float *s = a.sl + int64_t(j) * K::RS;
-                float dx = (xh - s[0]) + (xl - s[3]);
-                float dy = (yh - s[1]) + (yl - s[4]);
-                float dz = (zh - s[2]) + (zl - s[5]);
-                float ri = rsq_or_zero(dx * dx + dy * dy + dz * dz);
-                K::sl(dx, dy, dz, ri, s + 6, part);
-            }
-#pragma unroll
-            for (int k = 0; k < K::NACC; ++k) acc[k] += double(part[k]);
-        }
-        if (K::RD > 0) {
-            const int2 rd = a.box_dl[en.x];
-            for (int j0 = rd.x; j0 < rd.y; j0 += 64) {
-                const int j1 = min(j0 + 64, rd.y);
-                float part[K::NACC];
-#pragma unroll
-                for (int k = 0; k < K::NACC; ++k) part[k] = 0.0f;
-#pragma unroll 4
-                for (int j = j0; j < j1; ++j) {
-                    const float *s = a.dl + int64_t(j) * (K::RD > 0 ? K::RD : 1);
-                    float dx = (xh - s[0]) + (xl - s[3]);
-                    float dy = (yh - s[1]) + (yl - s[4]);
-                    float dz = (zh - s[2]) + (zl - s[5]);
-                    float ri = rsq_or_zero(dx * dx + dy * dy + dz * dz);
-                    K::dl(dx, dy, dz, ri, s + 6, part);
-                }
-#pragma unroll
-                for (int k = 0; k < K::NACC; ++k) acc[k] += double(part[k]);
+            p2p_run<K>(a.sl, rs.x, rs.y, xh, yh, zh, xl, yl, zl, acc, false);
+            if (K::RD > 0) {
+                const int2 rd = a.box_dl[en.x];
+                p2p_run<K>(a.dl, rd.x, rd.y, xh, yh, zh, xl, yl, zl, acc, true);
             }
         }
     }
@@ -190,6 +212,26 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs a) {
         double *o = a.part + (int64_t(blockIdx.x) * 256 + threadIdx.x) * K::NACC;
 #pragma unroll
         for (int k = 0; k < K::NACC; ++k) o[k] = acc[k];
+    }
+}
+
+// Leaf-relative FP32 source positions (record slots 9..11) for kernels whose
+// P2P forms r in the REL way: y_rel = (y_hi - c) + y_lo, rounded once.
+__global__ __launch_bounds__(256) void rel_positions_kernel(const int *__restrict__ leaves,
+                                                            const int2 *__restrict__ box_sl,
+                                                            const double4 *__restrict__ geom, int rec,
+                                                            float *__restrict__ sl) {
+    const int b = leaves[blockIdx.x];
+    const int2 r = box_sl[b];
+    const double4 g = geom[b];
+    for (int j = r.x + int(threadIdx.x); j < r.y; j += blockDim.x) {
+        float *s = sl + int64_t(j) * rec;
+        const float x = float((double(s[0]) - g.x) + double(s[3]));
+        const float y = float((double(s[1]) - g.y) + double(s[4]));
+        const float z = float((double(s[2]) - g.z) + double(s[5]));
+        s[9] = x;
+        s[10] = y;
+        s[11] = z;
     }
 }
 
@@ -285,18 +327,17 @@ __global__ __launch_bounds__(256) void s2c_kernel(S2CArgs a) {
 #pragma unroll
             for (int i = 0; i < PTS; ++i) {
                 if (i >= npts) break;
+                // check points lie outside every source box: r > 0
                 float dx = zx[i] - y[0], dy = zy[i] - y[1], dz = zz[i] - y[2];
-                float ri = rsq_or_zero(dx * dx + dy * dy + dz * dz);
+                float ri = __builtin_amdgcn_rsqf(dot3(dx, dy, dz, dx, dy, dz));
                 float ri3 = ri * ri * ri;
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    float v = 0.0f;
-                    if (T::CHG) v += y[3 + c] * ri;
+                    if (T::CHG) pot[i][c] = fmaf(y[3 + c], ri, pot[i][c]);
                     if (T::DIP) {
                         const float *dd = y + 3 + (T::CHG ? NC : 0) + 3 * c;
-                        v += (dd[0] * dx + dd[1] * dy + dd[2] * dz) * ri3;
+                        pot[i][c] = fmaf(dot3(dd[0], dd[1], dd[2], dx, dy, dz), ri3, pot[i][c]);
                     }
-                    pot[i][c] += v;
                 }
             }
         }
@@ -711,9 +752,10 @@ __global__ __launch_bounds__(256) void l2t_kernel(L2TArgs a) {
 #pragma unroll 2
             for (int j = 0; j < n; ++j) {
                 const float *y = tile + j * NV;
+                // equivalent points lie outside the target leaf: r > 0
                 float dx = xr - y[0], dy = yr - y[1], dz = zr - y[2];
-                float ri = rsq_or_zero(dx * dx + dy * dy + dz * dz);
-                float s = NC == 4 ? y[6] - (cx * y[3] + cy * y[4] + cz * y[5]) : 0.0f;
+                float ri = __builtin_amdgcn_rsqf(dot3(dx, dy, dz, dx, dy, dz));
+                float s = NC == 4 ? y[6] - dot3(cx, cy, cz, y[3], y[4], y[5]) : 0.0f;
                 E::eq(dx, dy, dz, ri, y + 3, s, part);
             }
         }
@@ -759,6 +801,7 @@ __global__ __launch_bounds__(256) void direct_f64_kernel(DirectArgs a) {
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const bool active = t < a.n_trg;
     const int64_t ti = active ? t : 0;
+    const int slice = blockIdx.y;
     const double x0 = a.trg[3 * ti], x1 = a.trg[3 * ti + 1], x2 = a.trg[3 * ti + 2];
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     __shared__ double ys[256 * 13];
@@ -767,8 +810,9 @@ __global__ __launch_bounds__(256) void direct_f64_kernel(DirectArgs a) {
         const double *xyz = pass == 0 ? a.sl : a.dl;
         const double *val = pass == 0 ? a.sl_val : a.dl_val;
         const int kv = pass == 0 ? a.k_sl : a.k_dl;
-        for (int64_t j0 = 0; j0 < ns; j0 += 256) {
-            const int n = int(min(int64_t(256), ns - j0));
+        const int64_t s0 = ns * slice / a.slices, s1 = ns * (slice + 1) / a.slices;
+        for (int64_t j0 = s0; j0 < s1; j0 += 256) {
+            const int n = int(min(int64_t(256), s1 - j0));
             __syncthreads();
             if (int(threadIdx.x) < n) {
                 double *o = ys + threadIdx.x * 13;
@@ -785,8 +829,19 @@ __global__ __launch_bounds__(256) void direct_f64_kernel(DirectArgs a) {
             }
         }
     }
-    if (active)
-        for (int k = 0; k < a.k_trg; ++k) a.out[t * a.k_trg + k] = acc[k];
+    if (!active) return;
+    double *o = a.slices > 1 ? a.work + (int64_t(slice) * a.n_trg + t) * a.k_trg : a.out + t * a.k_trg;
+    for (int k = 0; k < a.k_trg; ++k) o[k] = acc[k];
+}
+
+// out[i] = sum over slices, in slice order, of work[slice][i]
+__global__ void direct_slices_reduce(int64_t n, int slices, const double *__restrict__ work,
+                                     double *__restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int q = 0; q < slices; ++q) s += work[int64_t(q) * n + i];
+    out[i] = s;
 }
 
 // FP64 pair functions in user layouts (outputs already scaled).
@@ -991,9 +1046,17 @@ hipError_t launch_s2c_reduce(int ndst, const S2CReduceArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+int direct_f64_slices(int64_t n_trg, int64_t n_src) {
+    const int64_t bt = std::max<int64_t>(1, blocks_for(n_trg, 256));
+    int64_t q = (2048 + bt - 1) / bt;
+    q = std::min<int64_t>(q, std::max<int64_t>(1, n_src / 1024));
+    return int(std::max<int64_t>(1, std::min<int64_t>(q, 256)));
+}
+
 hipError_t launch_direct_f64(int kernel, const DirectArgs &a, hipStream_t s) {
     if (a.n_trg <= 0) return hipSuccess;
-    dim3 g(blocks_for(a.n_trg, 256));
+    if (a.slices < 1 || a.slices > 256 || (a.slices > 1 && a.work == nullptr)) return hipErrorInvalidValue;
+    dim3 g(blocks_for(a.n_trg, 256), a.slices);
     switch (kernel) {
         case kStokeslet: hipLaunchKernelGGL(direct_f64_kernel<F64Stokeslet>, g, dim3(256), 0, s, a); break;
         case kRPY: hipLaunchKernelGGL(direct_f64_kernel<F64RPY>, g, dim3(256), 0, s, a); break;
@@ -1002,6 +1065,29 @@ hipError_t launch_direct_f64(int kernel, const DirectArgs &a, hipStream_t s) {
         case kTraction: hipLaunchKernelGGL(direct_f64_kernel<F64Traction>, g, dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
+    if (a.slices > 1) {
+        const int64_t n = a.n_trg * a.k_trg;
+        hipLaunchKernelGGL(direct_slices_reduce, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, a.slices, a.work, a.out);
+    }
+    return hipGetLastError();
+}
+
+bool p2p_uses_rel(int kernel) {
+    switch (kernel) {
+        case kStokeslet: return DStokeslet::REL;
+        case kRPY: return DRPY::REL;
+        case kLapPGrad: return DLapPGrad::REL;
+        case kPVel: return DPVel::REL;
+        case kTraction: return DTraction::REL;
+        default: return false;
+    }
+}
+
+hipError_t launch_rel_positions(int nleaves, const int *leaves, const int2 *box_sl, const double4 *geom, int rec,
+                                float *sl, hipStream_t s) {
+    if (nleaves <= 0) return hipSuccess;
+    if (rec < 12) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(rel_positions_kernel, dim3(nleaves), dim3(256), 0, s, leaves, box_sl, geom, rec, sl);
     return hipGetLastError();
 }
 

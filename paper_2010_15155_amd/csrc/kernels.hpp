@@ -22,6 +22,7 @@ struct P2PArgs {
     const int2 *ent;           // direct entries {source box, packed shift}
     const int2 *box_sl, *box_dl;
     const float *sl, *dl;      // source records
+    const double4 *geom;       // box geometry (REL kernels: source leaf centres)
     double *part;              // [task][256][NACC]
 };
 
@@ -110,6 +111,8 @@ struct DirectArgs {
     const double *sl, *sl_val, *dl, *dl_val, *trg;
     int k_sl, k_dl, k_trg;
     double *out;
+    int slices;                // source slices (grid.y); > 1 needs work
+    double *work;              // [slices][n_trg][k_trg] partial sums, summed in slice order
 };
 
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
@@ -130,6 +133,14 @@ hipError_t launch_periodic(const double *T, const float *dens, double *chk, int 
 hipError_t launch_l2t(int kernel, int ntasks, const L2TArgs &a, hipStream_t s);
 hipError_t launch_s2c_reduce(int ndst, const S2CReduceArgs &a, hipStream_t s);
 hipError_t launch_combine(int nchunks, const CombineArgs &a, hipStream_t s);
+// Source slices of the FP64 direct sum for n_trg targets and n_src sources
+// (enough blocks to fill the chip when there are few targets).
+int direct_f64_slices(int64_t n_trg, int64_t n_src);
 hipError_t launch_direct_f64(int kernel, const DirectArgs &a, hipStream_t s);
+// True if the kernel's P2P forms r from leaf-relative positions (records
+// then need launch_rel_positions after packing).
+bool p2p_uses_rel(int kernel);
+hipError_t launch_rel_positions(int nleaves, const int *leaves, const int2 *box_sl, const double4 *geom, int rec,
+                                float *sl, hipStream_t s);
 
 }  // namespace kafmm
