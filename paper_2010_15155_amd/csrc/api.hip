@@ -126,10 +126,11 @@ struct stkfmm_ctx {
     Tree tree;
     DeviceOps *ops = nullptr;
     DevMem arena, sl_rec, dl_rec, trg_rec, up_dens, dn_dens, up_chk, dn_chk, Ybuf, tmp64, near_part, far_part,
-        s2c_part, partial, direct_work;
+        s2c_part, partial, direct_work, sl_stage, dl_stage;
     size_t a_perm_sl = 0, a_perm_dl = 0, a_perm_trg = 0, a_geom = 0, a_box_sl = 0, a_box_dl = 0, a_chunks = 0,
-           a_chunk_tasks = 0, a_p2p_tasks = 0, a_p2p_ent = 0, a_l2t_tasks = 0, a_l2t_ent = 0, a_leaves_sl = 0;
-    int n_leaves_sl = 0;
+           a_chunk_tasks = 0, a_p2p_tasks = 0, a_p2p_ent = 0, a_l2t_tasks = 0, a_l2t_ent = 0, a_leaves_sl = 0,
+           a_leaves_dl = 0;
+    int n_leaves_sl = 0, n_leaves_dl = 0;
     int nchunks = 0, n_p2p_tasks = 0, n_l2t_tasks = 0, nbox = 0;
     S2CPhase s2m, s2l;
     int64_t w_direct = 0, x_direct = 0, direct_pairs = 0;
@@ -167,6 +168,17 @@ stkfmm_status fail(stkfmm_ctx *c, stkfmm_status s, const std::string &msg) {
     } while (0)
 
 bool kernel_ok(int k) { return k >= 0 && k < kNumKernels; }
+
+// source kinds of the packing and staging kernels
+int sl_kind(int k) {
+    switch (k) {
+        case kStokeslet: return 0;
+        case kRPY: return 1;
+        case kLapPGrad: return 2;
+        default: return 4;
+    }
+}
+int dl_kind(int k) { return k == kLapPGrad ? 3 : 5; }
 
 stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, DeviceOps **out) {
     int key = p * 2 + (periodic ? 1 : 0);
@@ -282,6 +294,8 @@ stkfmm_status run_batch(stkfmm_ctx *c, const Batch &b, const float *ops, const f
     g.bcol = at<int>(c, b.bcol);
     g.ycol = at<int>(c, b.ycol);
     g.Mp = o.Mp;
+    g.Mr = o.M;
+    g.Mk = std::min(o.Mp, (o.M + 15) / 16 * 16);
     if (split_bf16) HIP_TRY(c, launch_gemm_bf16x3(b.ntiles, o.Mp, g, s));
     else HIP_TRY(c, launch_gemm_f32(b.ntiles, o.Mp, g, s));
     ReduceArgs r;
@@ -594,6 +608,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     c->n_sl = n_sl;
     c->n_dl = n_dl;
     c->n_trg = n_trg;
+    if (t.boxes.size() >= (size_t(1) << 25)) return fail(c, STKFMM_E_UNSUPPORTED, "more than 2^25 boxes");
     const int nb = int(t.boxes.size());
     c->nbox = nb;
     const int nc = ki.ncomp, M = ops->M, Mp = ops->Mp;
@@ -615,11 +630,15 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     c->a_geom = ar.add(geom);
     c->a_box_sl = ar.add(bsl);
     c->a_box_dl = ar.add(bdl);
-    std::vector<int> leaves_sl;
-    for (int b : t.leaves)
+    std::vector<int> leaves_sl, leaves_dl;
+    for (int b : t.leaves) {
         if (t.boxes[b].sl[1] > t.boxes[b].sl[0]) leaves_sl.push_back(b);
+        if (t.boxes[b].dl[1] > t.boxes[b].dl[0]) leaves_dl.push_back(b);
+    }
     c->n_leaves_sl = int(leaves_sl.size());
     c->a_leaves_sl = ar.add(leaves_sl);
+    c->n_leaves_dl = int(leaves_dl.size());
+    c->a_leaves_dl = ar.add(leaves_dl);
     // ---- direct (P2P) lists per leaf: U, plus W and X pairs cheaper to sum directly.
     // Per pair of points, a direct Stokes-kernel sum costs about 30 FP32
     // operations, an M2T evaluation 22 and a surface-tile (S2L) evaluation 15,
@@ -743,13 +762,14 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
             const int dst = dst_src[d].first;
             for (const int2 &e : dst_src[d].second) {
                 const Box &A = t.boxes[e.x];
+                const int code = e.y | (e.x << 6);      // source leaf and image shift
                 for (int64_t j = A.sl[0]; j < A.sl[1]; j += kS2CTaskSources) {
                     own_sl[d].push_back(int(tsl.size()));
-                    tsl.push_back(make_int4(dst, e.y, int(j), int(std::min<int64_t>(j + kS2CTaskSources, A.sl[1]))));
+                    tsl.push_back(make_int4(dst, code, int(j), int(std::min<int64_t>(j + kS2CTaskSources, A.sl[1]))));
                 }
                 for (int64_t j = A.dl[0]; j < A.dl[1]; j += kS2CTaskSources) {
                     own_dl[d].push_back(int(tdl.size()));
-                    tdl.push_back(make_int4(dst, e.y, int(j), int(std::min<int64_t>(j + kS2CTaskSources, A.dl[1]))));
+                    tdl.push_back(make_int4(dst, code, int(j), int(std::min<int64_t>(j + kS2CTaskSources, A.dl[1]))));
                 }
             }
         }
@@ -895,6 +915,10 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     HIP_TRY(c, c->near_part.ensure(size_t(std::max(c->n_p2p_tasks, 1)) * 256 * ki.kt_acc * sizeof(double)));
     HIP_TRY(c, c->far_part.ensure(size_t(std::max(c->n_l2t_tasks, 1)) * 256 * ki.kt_acc * sizeof(double)));
     HIP_TRY(c, c->s2c_part.ensure(std::max<size_t>(s2c_tasks_max, 1) * nc * M * sizeof(float)));
+    HIP_TRY(c, c->sl_stage.ensure(size_t(std::max<int64_t>(n_sl, 1)) * s2c_stage_stride(sl_kind(kernel)) *
+                                  sizeof(float)));
+    HIP_TRY(c, c->dl_stage.ensure(size_t(std::max<int64_t>(n_dl, 1)) * s2c_stage_stride(dl_kind(kernel)) *
+                                  sizeof(float)));
     HIP_TRY(c, c->partial.ensure(4096 * sizeof(double)));
     // densities: padding rows stay zero (the GEMM reads Mp rows)
     HIP_TRY(c, launch_fill_f32(c->up_dens.as<float>(), int64_t(nb) * nc * Mp, 0.0f, s));
@@ -920,15 +944,6 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
 
 namespace {
 
-int sl_kind(int k) {
-    switch (k) {
-        case kStokeslet: return 0;
-        case kRPY: return 1;
-        case kLapPGrad: return 2;
-        default: return 4;
-    }
-}
-int dl_kind(int k) { return k == kLapPGrad ? 3 : 5; }
 
 CombineMap combine_map(int k, double L) {
     CombineMap m;
@@ -1109,15 +1124,13 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         a.M = o.M;
         a.alpha = alpha;
         a.part = c->s2c_part.as<float>();
-        a.src = c->sl_rec.as<float>();
-        a.rec = ki.rec_sl;
+        a.staged = c->sl_stage.as<float>();
         hipError_t e = launch_s2c(sl_kind(c->kernel), ph.n_sl, a, s);
         if (e != hipSuccess) return e;
         if (ph.n_dl > 0) {
             a.tasks = at<int4>(c, ph.tasks) + ph.n_sl;
             a.part = c->s2c_part.as<float>() + int64_t(ph.n_sl) * nc * o.M;
-            a.src = c->dl_rec.as<float>();
-            a.rec = ki.rec_dl;
+            a.staged = c->dl_stage.as<float>();
             e = launch_s2c(dl_kind(c->kernel), ph.n_dl, a, s);
             if (e != hipSuccess) return e;
         }
@@ -1133,6 +1146,14 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         return launch_s2c_reduce(ph.n_dst, r, s);
     };
     if (far) {
+        // sources staged relative to their leaf centres (read by S2M and S2L)
+        HIP_TRY(c, launch_stage_sources(sl_kind(c->kernel), c->n_leaves_sl, at<int>(c, c->a_leaves_sl),
+                                        at<int2>(c, c->a_box_sl), at<double4>(c, c->a_geom), c->sl_rec.as<float>(),
+                                        ki.rec_sl, c->sl_stage.as<float>(), s));
+        if (c->n_dl > 0)
+            HIP_TRY(c, launch_stage_sources(dl_kind(c->kernel), c->n_leaves_dl, at<int>(c, c->a_leaves_dl),
+                                            at<int2>(c, c->a_box_dl), at<double4>(c, c->a_geom),
+                                            c->dl_rec.as<float>(), ki.rec_dl, c->dl_stage.as<float>(), s));
         // upward pass
         HIP_TRY(c, s2c(c->s2m, kAlphaOut, upchk, 0));
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 2 S2M

@@ -236,117 +236,161 @@ __global__ __launch_bounds__(256) void rel_positions_kernel(const int *__restric
 }
 
 // ------------------------------------------------------------------ S2M / S2L surface tiles
-// One block per destination box: check potentials at its M surface points
-// (radius alpha) from the sources of a list of leaves, each source first
-// turned into 4-Laplace charges/dipoles relative to the destination centre.
-constexpr int kS2CTile = 256;
+// Check potentials of the 4-Laplace (or 1-Laplace) densities of a source
+// leaf's points at the M check points of a destination box (radius alpha).
+//
+// Sources are first staged once per run (stage_sources_kernel): position
+// relative to the centre of their own leaf and the Laplace charges/dipoles
+// carried relative to that centre.  A task {dst, shift | src << 6, j0, j1}
+// evaluates sources [j0, j1) of leaf src (image shift) at dst's check
+// points: 256 staged records at a time are copied to LDS and every thread
+// evaluates them at 2-4 check points (reusing each LDS read).  The Psi
+// potential is then moved from the source leaf's origin to dst's:
+// Psi_dst = Psi_src + (c_src - c_dst).Phi.
+//
+// Staged records (RS floats per source), by source kind:
+//   0 Stokeslet f     [yr, f, yr.f, 0]           Phi_j charge f_j, Psi charge yr.f
+//   1 RPY f, b^2      [yr, f, yr.f, 0, m, 0]     + Psi dipole m = (b^2/3) f
+//   2 Laplace q       [yr, q]                    charge
+//   3 Laplace d       [yr, d, 0, 0]              dipole
+//   4 Stokes f, q     [yr, f, yr.f + q, 0]       Phi_j charge f_j, Psi charge
+//   5 Stokes D^s      [yr, D^s (6), 0, 0, 0]     Phi_j dipole -D^s_j., Psi dipole -D^s yr
+constexpr int kS2CTile = 256;   // staged records per LDS tile
 
-template <int SRC>   // source kind of the staging step, see stage_source
-struct S2CTraits;
-// SRC: 0 Stokeslet f, 1 RPY f,b^2, 2 Laplace q, 3 Laplace d, 4 Stokes f,q, 5 Stokes D^s
-template <> struct S2CTraits<0> { static constexpr int NC = 4, CHG = 1, DIP = 0; };
-template <> struct S2CTraits<1> { static constexpr int NC = 4, CHG = 1, DIP = 1; };
-template <> struct S2CTraits<2> { static constexpr int NC = 1, CHG = 1, DIP = 0; };
-template <> struct S2CTraits<3> { static constexpr int NC = 1, CHG = 0, DIP = 1; };
-template <> struct S2CTraits<4> { static constexpr int NC = 4, CHG = 1, DIP = 0; };
-template <> struct S2CTraits<5> { static constexpr int NC = 4, CHG = 0, DIP = 1; };
+template <int SRC> struct S2CKind;
+template <> struct S2CKind<0> { static constexpr int NC = 4, RS = 8; };
+template <> struct S2CKind<1> { static constexpr int NC = 4, RS = 12; };
+template <> struct S2CKind<2> { static constexpr int NC = 1, RS = 4; };
+template <> struct S2CKind<3> { static constexpr int NC = 1, RS = 8; };
+template <> struct S2CKind<4> { static constexpr int NC = 4, RS = 8; };
+template <> struct S2CKind<5> { static constexpr int NC = 4, RS = 12; };
 
-// Turn one source record into charges q[c] and dipoles d[c][3] at y_rel (relative to c).
-template <int SRC>
-__device__ __forceinline__ void stage_source(const float *s, float yx, float yy, float yz,
-                                             float *q, float *d) {
-    if (SRC == 0 || SRC == 1 || SRC == 4) {
-        q[0] = s[6]; q[1] = s[7]; q[2] = s[8];
-        q[3] = yx * s[6] + yy * s[7] + yz * s[8] + (SRC == 4 ? s[9] : 0.0f);
-        if (SRC == 1) {
-            float c = s[9] * (1.0f / 3.0f);
-            for (int k = 0; k < 9; ++k) d[k] = 0.0f;
-            d[9] = c * s[6]; d[10] = c * s[7]; d[11] = c * s[8];
-        }
-    } else if (SRC == 2) {
-        q[0] = s[6];
-    } else if (SRC == 3) {
-        d[0] = s[6]; d[1] = s[7]; d[2] = s[8];
-    } else if (SRC == 5) {
-        // Phi_j dipole -D^s_j. ; Psi dipole -D^s (y - c)
-        const float *m = s + 6;   // xx xy xz yy yz zz
-        d[0] = -m[0]; d[1] = -m[1]; d[2] = -m[2];
-        d[3] = -m[1]; d[4] = -m[3]; d[5] = -m[4];
-        d[6] = -m[2]; d[7] = -m[4]; d[8] = -m[5];
-        d[9] = -(m[0] * yx + m[1] * yy + m[2] * yz);
-        d[10] = -(m[1] * yx + m[3] * yy + m[4] * yz);
-        d[11] = -(m[2] * yx + m[4] * yy + m[5] * yz);
+int s2c_stage_stride(int src_kind) {
+    switch (src_kind) {
+        case 0: return S2CKind<0>::RS;
+        case 1: return S2CKind<1>::RS;
+        case 2: return S2CKind<2>::RS;
+        case 3: return S2CKind<3>::RS;
+        case 4: return S2CKind<4>::RS;
+        case 5: return S2CKind<5>::RS;
+        default: return 0;
     }
 }
 
+// One block per leaf holding sources of this kind; rec = packed record stride.
 template <int SRC>
-__global__ __launch_bounds__(256) void s2c_kernel(S2CArgs a) {
-    using T = S2CTraits<SRC>;
-    constexpr int NC = T::NC;
-    constexpr int NV = 3 + (T::CHG ? NC : 0) + (T::DIP ? 3 * NC : 0);
-    constexpr int PTS = 6;                         // check points per thread (M <= 1536)
-    __shared__ float tile[kS2CTile * NV];
-    const int4 task = a.tasks[blockIdx.x];         // {dst, shift, j0, j1}
-    const double4 cb = a.geom[task.x];
-    const float rad = float(a.alpha * 0.5 * cb.w);
-    const int npts = (a.M + 255) / 256;
+__global__ __launch_bounds__(256) void stage_sources_kernel(const int *__restrict__ leaves,
+                                                            const int2 *__restrict__ box_range,
+                                                            const double4 *__restrict__ geom,
+                                                            const float *__restrict__ src, int rec,
+                                                            float *__restrict__ out) {
+    constexpr int RS = S2CKind<SRC>::RS;
+    const int b = leaves[blockIdx.x];
+    const int2 r = box_range[b];
+    const double4 g = geom[b];
+    for (int j = r.x + int(threadIdx.x); j < r.y; j += blockDim.x) {
+        const float *s = src + int64_t(j) * rec;
+        const float yx = float((double(s[0]) - g.x) + double(s[3]));
+        const float yy = float((double(s[1]) - g.y) + double(s[4]));
+        const float yz = float((double(s[2]) - g.z) + double(s[5]));
+        float o[RS];
+#pragma unroll
+        for (int k = 0; k < RS; ++k) o[k] = 0.0f;
+        o[0] = yx; o[1] = yy; o[2] = yz;
+        if constexpr (SRC == 0 || SRC == 1 || SRC == 4) {
+            o[3] = s[6]; o[4] = s[7]; o[5] = s[8];
+            o[6] = dot3(yx, yy, yz, s[6], s[7], s[8]) + (SRC == 4 ? s[9] : 0.0f);
+            if constexpr (SRC == 1) {
+                const float c = s[9] * (1.0f / 3.0f);
+                o[8] = c * s[6]; o[9] = c * s[7]; o[10] = c * s[8];
+            }
+        } else if constexpr (SRC == 2) {
+            o[3] = s[6];
+        } else if constexpr (SRC == 3) {
+            o[3] = s[6]; o[4] = s[7]; o[5] = s[8];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) o[3 + k] = s[6 + k];
+        }
+        float4 *d = reinterpret_cast<float4 *>(out + int64_t(j) * RS);
+#pragma unroll
+        for (int k = 0; k < RS / 4; ++k) d[k] = make_float4(o[4 * k], o[4 * k + 1], o[4 * k + 2], o[4 * k + 3]);
+    }
+}
+
+template <int SRC, int PTS>
+__global__ __launch_bounds__(1024) void s2c_kernel(S2CArgs a) {
+    constexpr int NC = S2CKind<SRC>::NC, RS = S2CKind<SRC>::RS, R4 = RS / 4;
+    __shared__ float4 tile[kS2CTile * R4];
+    const int4 task = a.tasks[blockIdx.x];         // {dst, shift | src << 6, j0, j1}
+    const int code = task.y & 63, srcbox = task.y >> 6;
+    const double4 cb = a.geom[task.x], ca = a.geom[srcbox];
+    // destination centre relative to the (image of the) source leaf centre
+    const double ox = cb.x - (ca.x + shift_comp(code, 0)), oy = cb.y - (ca.y + shift_comp(code, 1)),
+                 oz = cb.z - (ca.z + shift_comp(code, 2));
+    const double rad = a.alpha * 0.5 * cb.w;
+    const int nthr = int(blockDim.x);
     float zx[PTS], zy[PTS], zz[PTS], pot[PTS][NC];
 #pragma unroll
     for (int i = 0; i < PTS; ++i) {
-        int m = int(threadIdx.x) + 256 * i;
-        int mm = m < a.M ? m : 0;
-        zx[i] = rad * a.grid[3 * mm];
-        zy[i] = rad * a.grid[3 * mm + 1];
-        zz[i] = rad * a.grid[3 * mm + 2];
+        const int m = int(threadIdx.x) + nthr * i;
+        const int mm = m < a.M ? m : 0;
+        zx[i] = float(ox + rad * a.grid[3 * mm]);
+        zy[i] = float(oy + rad * a.grid[3 * mm + 1]);
+        zz[i] = float(oz + rad * a.grid[3 * mm + 2]);
 #pragma unroll
         for (int c = 0; c < NC; ++c) pot[i][c] = 0.0f;
     }
-    const double sx = shift_comp(task.y, 0) - cb.x, sy = shift_comp(task.y, 1) - cb.y,
-                 sz = shift_comp(task.y, 2) - cb.z;
     for (int j0 = task.z; j0 < task.w; j0 += kS2CTile) {
         const int n = min(kS2CTile, task.w - j0);
         __syncthreads();
-        if (int(threadIdx.x) < n) {
-            const float *s = a.src + int64_t(j0 + threadIdx.x) * a.rec;
-            float yx = float((double(s[0]) + double(s[3])) + sx);
-            float yy = float((double(s[1]) + double(s[4])) + sy);
-            float yz = float((double(s[2]) + double(s[5])) + sz);
-            float q[4] = {0, 0, 0, 0}, d[12];
-            stage_source<SRC>(s, yx, yy, yz, q, d);
-            float *o = tile + threadIdx.x * NV;
-            o[0] = yx; o[1] = yy; o[2] = yz;
-            int k = 3;
-            if (T::CHG)
-                for (int c = 0; c < NC; ++c) o[k++] = q[c];
-            if (T::DIP)
-                for (int c = 0; c < 3 * NC; ++c) o[k++] = d[c];
-        }
+        const float4 *src = reinterpret_cast<const float4 *>(a.staged + int64_t(j0) * RS);
+        for (int q = int(threadIdx.x); q < n * R4; q += nthr) tile[q] = src[q];
         __syncthreads();
+#pragma unroll 2
         for (int j = 0; j < n; ++j) {
-            const float *y = tile + j * NV;
+            float y[RS];
+#pragma unroll
+            for (int k = 0; k < R4; ++k) {
+                const float4 v = tile[j * R4 + k];
+                y[4 * k] = v.x; y[4 * k + 1] = v.y; y[4 * k + 2] = v.z; y[4 * k + 3] = v.w;
+            }
 #pragma unroll
             for (int i = 0; i < PTS; ++i) {
-                if (i >= npts) break;
                 // check points lie outside every source box: r > 0
-                float dx = zx[i] - y[0], dy = zy[i] - y[1], dz = zz[i] - y[2];
-                float ri = __builtin_amdgcn_rsqf(dot3(dx, dy, dz, dx, dy, dz));
-                float ri3 = ri * ri * ri;
+                const float dx = zx[i] - y[0], dy = zy[i] - y[1], dz = zz[i] - y[2];
+                const float ri = __builtin_amdgcn_rsqf(dot3(dx, dy, dz, dx, dy, dz));
+                if constexpr (SRC == 0 || SRC == 4) {
 #pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    if (T::CHG) pot[i][c] = fmaf(y[3 + c], ri, pot[i][c]);
-                    if (T::DIP) {
-                        const float *dd = y + 3 + (T::CHG ? NC : 0) + 3 * c;
-                        pot[i][c] = fmaf(dot3(dd[0], dd[1], dd[2], dx, dy, dz), ri3, pot[i][c]);
-                    }
+                    for (int c = 0; c < 4; ++c) pot[i][c] = fmaf(y[3 + c], ri, pot[i][c]);
+                } else if constexpr (SRC == 1) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) pot[i][c] = fmaf(y[3 + c], ri, pot[i][c]);
+                    pot[i][3] = fmaf(dot3(y[8], y[9], y[10], dx, dy, dz), ri * ri * ri, pot[i][3]);
+                } else if constexpr (SRC == 2) {
+                    pot[i][0] = fmaf(y[3], ri, pot[i][0]);
+                } else if constexpr (SRC == 3) {
+                    pot[i][0] = fmaf(dot3(y[3], y[4], y[5], dx, dy, dz), ri * ri * ri, pot[i][0]);
+                } else {
+                    // w = D^s (z - y): Phi_j += -w_j / r^3, Psi += -(yr . w) / r^3
+                    float wx, wy, wz;
+                    sym_apply(y + 3, dx, dy, dz, wx, wy, wz);
+                    const float mri3 = -(ri * ri * ri);
+                    pot[i][0] = fmaf(wx, mri3, pot[i][0]);
+                    pot[i][1] = fmaf(wy, mri3, pot[i][1]);
+                    pot[i][2] = fmaf(wz, mri3, pot[i][2]);
+                    pot[i][3] = fmaf(dot3(y[0], y[1], y[2], wx, wy, wz), mri3, pot[i][3]);
                 }
             }
         }
     }
     float *o = a.part + int64_t(blockIdx.x) * NC * a.M;
+    const float dx = float(-ox), dy = float(-oy), dz = float(-oz);   // c_src - c_dst
 #pragma unroll
     for (int i = 0; i < PTS; ++i) {
-        int m = int(threadIdx.x) + 256 * i;
+        const int m = int(threadIdx.x) + nthr * i;
         if (m >= a.M) continue;
+        if constexpr (NC == 4) pot[i][3] = fmaf(dx, pot[i][0], fmaf(dy, pot[i][1], fmaf(dz, pot[i][2], pot[i][3])));
 #pragma unroll
         for (int c = 0; c < NC; ++c) o[c * a.M + m] = pot[i][c];
     }
@@ -387,6 +431,9 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma(GemmArgs a) {
     const float *A = a.ops + int64_t(tile.x) * Mp * Mp;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    // rows at or past Mr are zero padding: their MFMAs are skipped (the
+    // accumulators stay 0, which is what the padding rows would give)
+    const bool live0 = row0 + wr < a.Mr, live1 = row0 + wr + 32 < a.Mr;
     floatx16 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -408,8 +455,8 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma(GemmArgs a) {
         int c = bcol_ok[i] ? a.bcol[tile.y + lr[i]] : 0;
         bptr[i] = a.X + int64_t(c) * Mp;
     }
-    for (int k0 = 0; k0 < Mp; k0 += kGK) {
-        float4 ra[4], rb[4];
+    float4 ra[4], rb[4];
+    auto load = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             ra[i] = arow_ok[i] ? *reinterpret_cast<const float4 *>(A + int64_t(row0 + lr[i]) * Mp + k0 + lk[i])
@@ -417,6 +464,9 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma(GemmArgs a) {
             rb[i] = bcol_ok[i] ? *reinterpret_cast<const float4 *>(bptr[i] + k0 + lk[i])
                                : make_float4(0, 0, 0, 0);
         }
+    };
+    for (int k0 = 0; k0 < a.Mk; k0 += kGK) {
+        load(k0);
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -426,19 +476,22 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma(GemmArgs a) {
             db[0] = rb[i].x; db[1] = rb[i].y; db[2] = rb[i].z; db[3] = rb[i].w;
         }
         __syncthreads();
+        const int kend = min(kGK, a.Mk - k0);
 #pragma unroll
         for (int kk = 0; kk < kGK; kk += 2) {
-            const int k = kk + (lane >> 5);
-            float av[2], bv[2];
+            if (kk < kend) {
+                const int k = kk + (lane >> 5);
+                float av[2], bv[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) av[i] = As[(wr + 32 * i + (lane & 31)) * kGLd + k];
+                for (int i = 0; i < 2; ++i) av[i] = As[(wr + 32 * i + (lane & 31)) * kGLd + k];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) bv[j] = Bs[(wc + 32 * j + (lane & 31)) * kGLd + k];
+                for (int j = 0; j < 2; ++j) bv[j] = Bs[(wc + 32 * j + (lane & 31)) * kGLd + k];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 2; ++j) {
+                    if (live0) acc[0][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[0], bv[j], acc[0][j], 0, 0, 0);
+                    if (live1) acc[1][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[1], bv[j], acc[1][j], 0, 0, 0);
+                }
+            }
         }
     }
     // epilogue: lane holds column (lane & 31) and rows 8*(v/4) + 4*(lane/32) + v%4
@@ -478,6 +531,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_mfma(GemmArgs a) {
     const float *A = a.ops + int64_t(tile.x) * Mp * Mp;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const bool live0 = row0 + wr < a.Mr, live1 = row0 + wr + 32 < a.Mr;
     floatx16 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -498,8 +552,8 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_mfma(GemmArgs a) {
         int c = bcol_ok[i] ? a.bcol[tile.y + lr[i]] : 0;
         bptr[i] = a.X + int64_t(c) * Mp;
     }
-    for (int k0 = 0; k0 < Mp; k0 += kGK) {
-        float4 ra[4], rb[4];
+    float4 ra[4], rb[4];
+    auto load = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             ra[i] = arow_ok[i] ? *reinterpret_cast<const float4 *>(A + int64_t(row0 + lr[i]) * Mp + k0 + lk[i])
@@ -507,6 +561,9 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_mfma(GemmArgs a) {
             rb[i] = bcol_ok[i] ? *reinterpret_cast<const float4 *>(bptr[i] + k0 + lk[i])
                                : make_float4(0, 0, 0, 0);
         }
+    };
+    for (int k0 = 0; k0 < a.Mk; k0 += kGK) {
+        load(k0);
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -523,8 +580,10 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_mfma(GemmArgs a) {
             }
         }
         __syncthreads();
+        const int kend = min(kGK, a.Mk - k0);
 #pragma unroll
         for (int kk = 0; kk < kGK; kk += 16) {
+            if (kk >= kend) continue;
             const int ko = kk + 8 * (lane >> 5);
             bf16x8 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
@@ -540,13 +599,15 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_mfma(GemmArgs a) {
                 bl[j] = *reinterpret_cast<const bf16x8 *>(Bl + r);
             }
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i) {
+                if (!(i == 0 ? live0 : live1)) continue;
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
                 }
+            }
         }
     }
 #pragma unroll
@@ -650,26 +711,39 @@ __global__ __launch_bounds__(256) void gemm_f64(Gemm64Args a, TC *C) {
 // ------------------------------------------------------------------ translation reduce
 // chk[dst][c][m] (+)= sum over pairs p of scale_p * (Y_p[c][m] - [c == 3] delta_p . Y_p[0..2][m])
 // (the Psi origin shift; Laplace problems have one component and no shift).
-__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
+template <int NC>
+__global__ __launch_bounds__(1024) void reduce_kernel(ReduceArgs a) {
     const int task = blockIdx.x;
     const int dst = a.dst[task];
     const int p0 = a.off[task], p1 = a.off[task + 1];
-    const int nc = a.ncomp;
+    constexpr int nc = NC;
+    constexpr int U = 4;                     // pairs whose loads are issued together
     for (int m = threadIdx.x; m < a.M; m += blockDim.x) {
         double acc[4] = {0, 0, 0, 0};
-        for (int p = p0; p < p1; ++p) {
-            const int pr = a.pair[p];
-            const float *Y = a.Y + int64_t(pr) * nc * a.Mp + m;
-            const double s = a.scale[p];
-            if (nc == 4) {
-                double y0 = Y[0], y1 = Y[a.Mp], y2 = Y[2 * a.Mp], y3 = Y[3 * a.Mp];
-                const float *dl = a.delta + 3 * int64_t(p);
-                acc[0] += s * y0;
-                acc[1] += s * y1;
-                acc[2] += s * y2;
-                acc[3] += s * (y3 - (double(dl[0]) * y0 + double(dl[1]) * y1 + double(dl[2]) * y2));
-            } else {
-                acc[0] += s * double(Y[0]);
+        for (int q0 = p0; q0 < p1; q0 += U) {
+            float y[U][4];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (q0 + u >= p1) break;
+                const float *Y = a.Y + int64_t(a.pair[q0 + u]) * nc * a.Mp + m;
+#pragma unroll
+                for (int c = 0; c < nc; ++c) y[u][c] = Y[c * a.Mp];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = q0 + u;
+                if (p >= p1) break;
+                const double s = a.scale[p];
+                if (nc == 4) {
+                    const double y0 = y[u][0], y1 = y[u][1], y2 = y[u][2], y3 = y[u][3];
+                    const float *dl = a.delta + 3 * int64_t(p);
+                    acc[0] += s * y0;
+                    acc[1] += s * y1;
+                    acc[2] += s * y2;
+                    acc[3] += s * (y3 - (double(dl[0]) * y0 + double(dl[1]) * y1 + double(dl[2]) * y2));
+                } else {
+                    acc[0] += s * double(y[u][0]);
+                }
             }
         }
         for (int c = 0; c < nc; ++c) {
@@ -970,15 +1044,56 @@ hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Check points per thread: the count in {2, 3, 4} that pads the fewest
+// lanes (ties to the larger count, which reads the LDS tile less often).
+static int s2c_points_per_thread(int M) {
+    int best = 2, best_slots = 1 << 30;
+    for (int pts = 2; pts <= 4; ++pts) {
+        const int slots = pts * (((M + pts - 1) / pts + 63) / 64 * 64);
+        if (slots <= best_slots) best = pts, best_slots = slots;
+    }
+    return best;
+}
+
+template <int SRC>
+static void launch_s2c_kind(int ntasks, const S2CArgs &a, hipStream_t s) {
+    const int pts = a.M > 4096 ? 0 : s2c_points_per_thread(a.M);
+    const int nthr = ((a.M + pts - 1) / pts + 63) / 64 * 64;
+    switch (pts) {
+        case 2: hipLaunchKernelGGL((s2c_kernel<SRC, 2>), dim3(ntasks), dim3(nthr), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((s2c_kernel<SRC, 3>), dim3(ntasks), dim3(nthr), 0, s, a); break;
+        default: hipLaunchKernelGGL((s2c_kernel<SRC, 4>), dim3(ntasks), dim3(nthr), 0, s, a); break;
+    }
+}
+
 hipError_t launch_s2c(int src_kind, int ntasks, const S2CArgs &a, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
+    if (a.M < 1 || a.M > 4096) return hipErrorInvalidValue;
     switch (src_kind) {
-        case 0: hipLaunchKernelGGL(s2c_kernel<0>, dim3(ntasks), dim3(256), 0, s, a); break;
-        case 1: hipLaunchKernelGGL(s2c_kernel<1>, dim3(ntasks), dim3(256), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(s2c_kernel<2>, dim3(ntasks), dim3(256), 0, s, a); break;
-        case 3: hipLaunchKernelGGL(s2c_kernel<3>, dim3(ntasks), dim3(256), 0, s, a); break;
-        case 4: hipLaunchKernelGGL(s2c_kernel<4>, dim3(ntasks), dim3(256), 0, s, a); break;
-        case 5: hipLaunchKernelGGL(s2c_kernel<5>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case 0: launch_s2c_kind<0>(ntasks, a, s); break;
+        case 1: launch_s2c_kind<1>(ntasks, a, s); break;
+        case 2: launch_s2c_kind<2>(ntasks, a, s); break;
+        case 3: launch_s2c_kind<3>(ntasks, a, s); break;
+        case 4: launch_s2c_kind<4>(ntasks, a, s); break;
+        case 5: launch_s2c_kind<5>(ntasks, a, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_sources(int src_kind, int nleaves, const int *leaves, const int2 *box_range,
+                                const double4 *geom, const float *src, int rec, float *out, hipStream_t s) {
+    if (nleaves <= 0) return hipSuccess;
+    const int need = src_kind == 2 ? 7 : (src_kind == 1 || src_kind == 4 ? 10 : (src_kind == 5 ? 12 : 9));
+    if (rec < need) return hipErrorInvalidValue;
+    dim3 g(nleaves), b(256);
+    switch (src_kind) {
+        case 0: hipLaunchKernelGGL(stage_sources_kernel<0>, g, b, 0, s, leaves, box_range, geom, src, rec, out); break;
+        case 1: hipLaunchKernelGGL(stage_sources_kernel<1>, g, b, 0, s, leaves, box_range, geom, src, rec, out); break;
+        case 2: hipLaunchKernelGGL(stage_sources_kernel<2>, g, b, 0, s, leaves, box_range, geom, src, rec, out); break;
+        case 3: hipLaunchKernelGGL(stage_sources_kernel<3>, g, b, 0, s, leaves, box_range, geom, src, rec, out); break;
+        case 4: hipLaunchKernelGGL(stage_sources_kernel<4>, g, b, 0, s, leaves, box_range, geom, src, rec, out); break;
+        case 5: hipLaunchKernelGGL(stage_sources_kernel<5>, g, b, 0, s, leaves, box_range, geom, src, rec, out); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -986,12 +1101,14 @@ hipError_t launch_s2c(int src_kind, int ntasks, const S2CArgs &a, hipStream_t s)
 
 hipError_t launch_gemm_f32(int ntiles, int Mp, const GemmArgs &a, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
+    if (a.Mp != Mp || a.Mk % 16 != 0 || a.Mk > Mp || a.Mk < 1 || a.Mr > Mp) return hipErrorInvalidValue;
     hipLaunchKernelGGL(gemm_f32_mfma, dim3(ntiles, (Mp + kGT - 1) / kGT), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_gemm_bf16x3(int ntiles, int Mp, const GemmArgs &a, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
+    if (a.Mp != Mp || a.Mk % 16 != 0 || a.Mk > Mp || a.Mk < 1 || a.Mr > Mp) return hipErrorInvalidValue;
     hipLaunchKernelGGL(gemm_bf16x3_mfma, dim3(ntiles, (Mp + kGT - 1) / kGT), dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -1010,7 +1127,10 @@ hipError_t launch_gemm_f64_to_f32(const Gemm64Args &a, float *C, hipStream_t s) 
 
 hipError_t launch_reduce(int ntasks, const ReduceArgs &a, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(reduce_kernel, dim3(ntasks), dim3(256), 0, s, a);
+    const int nthr = std::min(1024, (a.M + 63) / 64 * 64);
+    if (a.ncomp == 4) hipLaunchKernelGGL(reduce_kernel<4>, dim3(ntasks), dim3(nthr), 0, s, a);
+    else if (a.ncomp == 1) hipLaunchKernelGGL(reduce_kernel<1>, dim3(ntasks), dim3(nthr), 0, s, a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

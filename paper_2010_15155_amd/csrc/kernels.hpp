@@ -27,9 +27,8 @@ struct P2PArgs {
 };
 
 struct S2CArgs {
-    const int4 *tasks;         // {dst box, packed shift, j0, j1}: sources [j0, j1) of src
-    const float *src;          // source records
-    int rec;
+    const int4 *tasks;         // {dst box, packed shift | src leaf << 6, j0, j1}: sources [j0, j1) of src
+    const float *staged;       // staged source records (stage_sources_kernel)
     const double4 *geom;
     const float *grid;         // [M][3] unit lattice
     int M;
@@ -53,6 +52,8 @@ struct GemmArgs {
     float *Y;                  // output columns
     const int *bcol, *ycol;    // column indices (units of Mp floats)
     int Mp;
+    int Mr;                    // rows >= Mr of the operators are zero (skipped)
+    int Mk;                    // columns >= Mk of the operators are zero; multiple of 16, <= Mp
 };
 
 struct Gemm64Args {
@@ -123,6 +124,11 @@ hipError_t launch_pack_targets(int64_t n, const double *xyz, const int32_t *perm
                                double inv_len, float *out, hipStream_t s);
 hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, hipStream_t s);
 hipError_t launch_s2c(int src_kind, int ntasks, const S2CArgs &a, hipStream_t s);
+// Floats per staged source record of a source kind (0 for an unknown kind).
+int s2c_stage_stride(int src_kind);
+// Stage the sources of every listed leaf (box_range: the leaves' SL or DL ranges).
+hipError_t launch_stage_sources(int src_kind, int nleaves, const int *leaves, const int2 *box_range,
+                                const double4 *geom, const float *src, int rec, float *out, hipStream_t s);
 hipError_t launch_gemm_f32(int ntiles, int Mp, const GemmArgs &a, hipStream_t s);
 hipError_t launch_gemm_bf16x3(int ntiles, int Mp, const GemmArgs &a, hipStream_t s);
 hipError_t launch_gemm_f64(const Gemm64Args &a, double *C, hipStream_t s);
