@@ -153,15 +153,18 @@ stkfmm_status stkfmm_set_option(stkfmm_ctx *ctx, const char *key, const char *va
 stkfmm_status stkfmm_get_timings(const stkfmm_ctx *ctx, double *t_tree_ms, double *t_run_ms,
                                  double stage_ms[16]);
 
-/* Plan statistics of the last set_points; stats[16] receives:
+/* Plan statistics of the last set_points; stats[20] receives:
  * 0 boxes, 1 leaves, 2 depth, 3 U-list pairs (sum over target leaves of
  * n_trg * sum of U-list source counts), 4 V-list pairs, 5 W-list pairs,
  * 6 X-list pairs, 7 M (points per surface), 8 n_trg, 9 n_sl, 10 n_dl,
  * 11 U-list entries, 12 P2P pairs evaluated (U pairs plus the W and X
  * pairs summed directly because that is cheaper), 13 W pairs summed
- * directly, 14 X pairs summed directly, 15 P2P tasks.
+ * directly, 14 X pairs summed directly, 15 P2P tasks, 16 rank of the
+ * compressed V-list translations (0: dense), 17 Mp (M padded to 32),
+ * 18 rank of the check-to-equivalent pseudo-inverse, 19 P2P lane pairs
+ * (pairs including the idle lanes of partly filled 64-target waves).
  * Errors: E_ARG, E_STATE. */
-stkfmm_status stkfmm_get_stats(const stkfmm_ctx *ctx, int64_t stats[16]);
+stkfmm_status stkfmm_get_stats(const stkfmm_ctx *ctx, int64_t stats[20]);
 
 /* ---------------------------------------------------------------------
  * Learned order / leaf-capacity mode.  stkfmm_set_points with p = 0 and/or

@@ -179,10 +179,11 @@ class FMM:
                 "stages_ms": {k: stg[i] for i, k in enumerate(STAGES)}}
 
     def stats(self):
-        a = (ctypes.c_int64 * 16)()
+        a = (ctypes.c_int64 * 20)()
         self._check(lib().stkfmm_get_stats(self._h, a), "stats")
         names = ["boxes", "leaves", "depth", "u_pairs", "v_pairs", "w_pairs", "x_pairs", "M",
-                 "n_trg", "n_sl", "n_dl", "u_entries", "p2p_pairs", "w_direct", "x_direct", "p2p_tasks"]
+                 "n_trg", "n_sl", "n_dl", "u_entries", "p2p_pairs", "w_direct", "x_direct", "p2p_tasks",
+                 "m2l_rank", "Mp", "pinv_rank", "p2p_lane_pairs"]
         return {n: int(a[i]) for i, n in enumerate(names)}
 
     # ---------------------------------------------------------------- learned mode

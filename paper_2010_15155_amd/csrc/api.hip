@@ -18,6 +18,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -74,8 +75,10 @@ struct Arena {
 
 struct DeviceOps {
     int p = 0, M = 0, Mp = 0, rank = 0;
+    int kc = 0;                 // compressed V-list rank (0: dense m2l)
     bool periodic = false;
     DevMem grid, m2m, l2l, m2l, up1, up2, dn1, dn2, tm2l;
+    DevMem basis_t, m2l_c;      // U_k^T [kc][Mp], cores [343][kc][kc]
 };
 
 // A batch of translations that share the grouped GEMM and one reduce launch.
@@ -115,6 +118,7 @@ struct stkfmm_ctx {
     double box_len = 1.0;
     std::string err;
     double svd_tol = 1e-7;
+    double m2l_tol = 5e-8;      // compression of the V-list translations (0: dense)
     int precision = 0;          // 0 fp32, 1 split_bf16
     std::map<int, std::unique_ptr<DeviceOps>> ops_cache;   // key: p*2 + periodic
     hipStream_t side = nullptr; // P2P stream
@@ -126,14 +130,14 @@ struct stkfmm_ctx {
     Tree tree;
     DeviceOps *ops = nullptr;
     DevMem arena, sl_rec, dl_rec, trg_rec, up_dens, dn_dens, up_chk, dn_chk, Ybuf, tmp64, near_part, far_part,
-        s2c_part, partial, direct_work, sl_stage, dl_stage;
+        s2c_part, partial, direct_work, sl_stage, dl_stage, up_cmp;
     size_t a_perm_sl = 0, a_perm_dl = 0, a_perm_trg = 0, a_geom = 0, a_box_sl = 0, a_box_dl = 0, a_chunks = 0,
            a_chunk_tasks = 0, a_p2p_tasks = 0, a_p2p_ent = 0, a_l2t_tasks = 0, a_l2t_ent = 0, a_leaves_sl = 0,
-           a_leaves_dl = 0;
-    int n_leaves_sl = 0, n_leaves_dl = 0;
+           a_leaves_dl = 0, a_cmp_tiles = 0, a_cmp_cols = 0;
+    int n_leaves_sl = 0, n_leaves_dl = 0, n_cmp_tiles = 0;
     int nchunks = 0, n_p2p_tasks = 0, n_l2t_tasks = 0, nbox = 0;
     S2CPhase s2m, s2l;
-    int64_t w_direct = 0, x_direct = 0, direct_pairs = 0;
+    int64_t w_direct = 0, x_direct = 0, direct_pairs = 0, p2p_lane_pairs = 0;
     int overlap = 1;
     // learned order / capacity mode
     DevMem predictor, mlp_in, mlp_out, mlp_ws, coords[3], vbuf[4];
@@ -188,13 +192,14 @@ stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, DeviceOps **out) {
         return STKFMM_OK;
     }
     Operators h;
-    std::string e = build_operators(p, c->svd_tol, periodic, h);
+    std::string e = build_operators(p, c->svd_tol, periodic, h, c->m2l_tol);
     if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
     auto d = std::make_unique<DeviceOps>();
     d->p = p;
     d->M = h.M;
     d->Mp = h.Mp;
     d->rank = h.rank;
+    d->kc = h.kc;
     d->periodic = periodic;
     std::vector<float> g(h.grid.begin(), h.grid.end());
     auto up = [&](DevMem &m, const void *src, size_t bytes) -> hipError_t {
@@ -205,7 +210,15 @@ stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, DeviceOps **out) {
     HIP_TRY(c, up(d->grid, g.data(), g.size() * sizeof(float)));
     HIP_TRY(c, up(d->m2m, h.m2m.data(), h.m2m.size() * sizeof(float)));
     HIP_TRY(c, up(d->l2l, h.l2l.data(), h.l2l.size() * sizeof(float)));
-    HIP_TRY(c, up(d->m2l, h.m2l.data(), h.m2l.size() * sizeof(float)));
+    if (h.kc > 0) {
+        std::vector<float> bt(size_t(h.kc) * h.Mp);     // U_k^T
+        for (int i = 0; i < h.Mp; ++i)
+            for (int k = 0; k < h.kc; ++k) bt[size_t(k) * h.Mp + i] = h.cbasis[size_t(i) * h.kc + k];
+        HIP_TRY(c, up(d->basis_t, bt.data(), bt.size() * sizeof(float)));
+        HIP_TRY(c, up(d->m2l_c, h.m2l_c.data(), h.m2l_c.size() * sizeof(float)));
+    } else {
+        HIP_TRY(c, up(d->m2l, h.m2l.data(), h.m2l.size() * sizeof(float)));
+    }
     // UC2UE = P1 P2 ; DC2DE = P2^T P1^T
     const int M = h.M, r = h.rank;
     std::vector<double> t1(size_t(r) * M), t2(size_t(M) * r);
@@ -281,23 +294,28 @@ Batch make_batch(Arena &ar, std::vector<Pair> pairs, int nc, int accumulate, siz
 
 template <class T> T *at(stkfmm_ctx *c, size_t off) { return reinterpret_cast<T *>(c->arena.as<char>() + off); }
 
+// Translations of a batch: the grouped GEMM (dense M x M operators on
+// densities, or, compressed, kc x kc cores on basis coefficients X) and the
+// reduce into the destination check values.
 stkfmm_status run_batch(stkfmm_ctx *c, const Batch &b, const float *ops, const float *X, double *chk,
-                        hipStream_t s, bool split_bf16 = false) {
+                        hipStream_t s, bool split_bf16 = false, bool compressed = false) {
     if (b.npairs == 0) return STKFMM_OK;
     const DeviceOps &o = *c->ops;
     const int nc = kernel_info(c->kernel).ncomp;
+    const int side = compressed ? o.kc : o.Mp;
     GemmArgs g;
     g.tiles = at<int4>(c, b.tiles);
     g.ops = ops;
+    g.opsz = int64_t(side) * side;
     g.X = X;
     g.Y = c->Ybuf.as<float>();
     g.bcol = at<int>(c, b.bcol);
     g.ycol = at<int>(c, b.ycol);
-    g.Mp = o.Mp;
-    g.Mr = o.M;
-    g.Mk = std::min(o.Mp, (o.M + 15) / 16 * 16);
-    if (split_bf16) HIP_TRY(c, launch_gemm_bf16x3(b.ntiles, o.Mp, g, s));
-    else HIP_TRY(c, launch_gemm_f32(b.ntiles, o.Mp, g, s));
+    g.R = g.K = g.xs = g.ys = side;
+    g.Mr = compressed ? o.kc : o.M;
+    g.Mk = compressed ? o.kc : std::min(o.Mp, (o.M + 15) / 16 * 16);
+    if (split_bf16) HIP_TRY(c, launch_gemm_bf16x3(b.ntiles, g, s));
+    else HIP_TRY(c, launch_gemm_f32(b.ntiles, g, s));
     ReduceArgs r;
     r.dst = at<int>(c, b.rdst);
     r.off = at<int>(c, b.roff);
@@ -305,12 +323,38 @@ stkfmm_status run_batch(stkfmm_ctx *c, const Batch &b, const float *ops, const f
     r.scale = at<double>(c, b.rscale);
     r.delta = at<float>(c, b.rdelta);
     r.Y = c->Ybuf.as<float>();
+    r.ys = side;
     r.chk = chk;
     r.M = o.M;
     r.Mp = o.Mp;
     r.ncomp = nc;
     r.accumulate = b.accumulate;
+    r.kc = compressed ? o.kc : 0;
+    r.basis_t = compressed ? o.basis_t.as<float>() : nullptr;
     HIP_TRY(c, launch_reduce(b.ntasks, r, s));
+    return STKFMM_OK;
+}
+
+// Basis coefficients U_k^T x of every box's upward densities (one operator,
+// all columns).
+stkfmm_status run_compress(stkfmm_ctx *c, const float *dens, float *coef, hipStream_t s) {
+    const DeviceOps &o = *c->ops;
+    if (c->n_cmp_tiles == 0) return STKFMM_OK;
+    GemmArgs g;
+    g.tiles = at<int4>(c, c->a_cmp_tiles);
+    g.ops = o.basis_t.as<float>();
+    g.opsz = int64_t(o.kc) * o.Mp;
+    g.X = dens;
+    g.Y = coef;
+    g.bcol = at<int>(c, c->a_cmp_cols);
+    g.ycol = at<int>(c, c->a_cmp_cols);
+    g.R = o.kc;
+    g.K = o.Mp;
+    g.xs = o.Mp;
+    g.ys = o.kc;
+    g.Mr = o.kc;
+    g.Mk = std::min(o.Mp, (o.M + 15) / 16 * 16);
+    HIP_TRY(c, launch_gemm_f32(c->n_cmp_tiles, g, s));
     return STKFMM_OK;
 }
 
@@ -435,6 +479,15 @@ stkfmm_status stkfmm_set_option(stkfmm_ctx *c, const char *key, const char *valu
         c->planned = false;
         return STKFMM_OK;
     }
+    if (k == "m2l_tol") {
+        char *end = nullptr;
+        double t = std::strtod(value, &end);
+        if (!end || *end || !(t >= 0) || !(t < 1)) return fail(c, STKFMM_E_ARG, "m2l_tol must lie in [0, 1)");
+        if (t != c->m2l_tol) c->ops_cache.clear();
+        c->m2l_tol = t;
+        c->planned = false;
+        return STKFMM_OK;
+    }
     if (k == "svd_tol") {
         char *end = nullptr;
         double t = std::strtod(value, &end);
@@ -455,10 +508,10 @@ stkfmm_status stkfmm_get_timings(const stkfmm_ctx *c, double *t_tree, double *t_
     return STKFMM_OK;
 }
 
-stkfmm_status stkfmm_get_stats(const stkfmm_ctx *c, int64_t st[16]) {
+stkfmm_status stkfmm_get_stats(const stkfmm_ctx *c, int64_t st[20]) {
     if (!c || !st) return STKFMM_E_ARG;
     if (!c->planned) return STKFMM_E_STATE;
-    std::memset(st, 0, 16 * sizeof(int64_t));
+    std::memset(st, 0, 20 * sizeof(int64_t));
     const Tree &t = c->tree;
     st[0] = int64_t(t.boxes.size());
     st[1] = int64_t(t.leaves.size());
@@ -476,6 +529,10 @@ stkfmm_status stkfmm_get_stats(const stkfmm_ctx *c, int64_t st[16]) {
     st[13] = c->w_direct;
     st[14] = c->x_direct;
     st[15] = c->n_p2p_tasks;
+    st[16] = c->ops ? c->ops->kc : 0;
+    st[17] = c->ops ? c->ops->Mp : 0;
+    st[18] = c->ops ? c->ops->rank : 0;
+    st[19] = c->p2p_lane_pairs;
     return STKFMM_OK;
 }
 
@@ -705,6 +762,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     std::vector<int4> chunks, chunk_tasks, p2p_tasks, l2t_tasks;
     std::vector<int2> p2p_ent, l2t_ent;
     c->direct_pairs = 0;
+    c->p2p_lane_pairs = 0;
     for (int b : t.leaves) {
         const Box &B = t.boxes[b];
         if (B.trg[1] == B.trg[0]) continue;
@@ -718,6 +776,8 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
         int64_t nsrc_all = 0;
         for (int e = e0; e < e1; ++e) nsrc_all += t.boxes[p2p_ent[e].x].nsrc_sub;
         c->direct_pairs += nsrc_all * (B.trg[1] - B.trg[0]);
+        for (int64_t t0i = B.trg[0]; t0i < B.trg[1]; t0i += 256)
+            c->p2p_lane_pairs += nsrc_all * ((std::min<int64_t>(t0i + 256, B.trg[1]) - t0i + 63) / 64 * 64);
         for (int64_t t0i = B.trg[0]; t0i < B.trg[1]; t0i += 256) {
             const int ci = int(chunks.size());
             chunks.push_back(make_int4(b, int(t0i), int(std::min<int64_t>(t0i + 256, B.trg[1])), 0));
@@ -829,6 +889,17 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
         }
         c->m2l = make_batch(ar, pairs, nc, 1, c->ybuf_floats, Mp);
     }
+    // compression of every box's upward densities (compressed translations)
+    c->n_cmp_tiles = 0;
+    if (ops->kc > 0) {
+        std::vector<int4> tiles;
+        std::vector<int> cols(size_t(nb) * nc);
+        std::iota(cols.begin(), cols.end(), 0);
+        for (int t0 = 0; t0 < nb * nc; t0 += 128) tiles.push_back(make_int4(0, t0, std::min(128, nb * nc - t0), 0));
+        c->n_cmp_tiles = int(tiles.size());
+        c->a_cmp_tiles = ar.add(tiles);
+        c->a_cmp_cols = ar.add(cols);
+    }
     // M2M (by parent level) and L2L (by child level), grouped by octant
     c->m2m.assign(t.depth + 1, Batch());
     c->l2l.assign(t.depth + 1, Batch());
@@ -911,6 +982,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     HIP_TRY(c, c->up_chk.ensure(size_t(nb) * nc * M * sizeof(double)));
     HIP_TRY(c, c->dn_chk.ensure(size_t(nb) * nc * M * sizeof(double)));
     HIP_TRY(c, c->Ybuf.ensure(std::max<size_t>(c->ybuf_floats, 1) * sizeof(float)));
+    if (ops->kc > 0) HIP_TRY(c, c->up_cmp.ensure(size_t(nb) * nc * ops->kc * sizeof(float)));
     HIP_TRY(c, c->tmp64.ensure(std::max<size_t>(c->tmp_doubles, 1) * sizeof(double)));
     HIP_TRY(c, c->near_part.ensure(size_t(std::max(c->n_p2p_tasks, 1)) * 256 * ki.kt_acc * sizeof(double)));
     HIP_TRY(c, c->far_part.ensure(size_t(std::max(c->n_l2t_tasks, 1)) * 256 * ki.kt_acc * sizeof(double)));
@@ -1167,7 +1239,14 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         }
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 3 upward
         HIP_TRY(c, launch_fill_f64(dnchk, int64_t(c->nbox) * nc * o.M, 0.0, s));
-        stkfmm_status st = run_batch(c, c->m2l, o.m2l.as<float>(), updens, dnchk, s, c->precision == 1);
+        stkfmm_status st = STKFMM_OK;
+        if (o.kc > 0) {
+            st = run_compress(c, updens, c->up_cmp.as<float>(), s);
+            if (st != STKFMM_OK) return st;
+            st = run_batch(c, c->m2l, o.m2l_c.as<float>(), c->up_cmp.as<float>(), dnchk, s, c->precision == 1, true);
+        } else {
+            st = run_batch(c, c->m2l, o.m2l.as<float>(), updens, dnchk, s, c->precision == 1);
+        }
         if (st != STKFMM_OK) return st;
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 4 M2L
         HIP_TRY(c, s2c(c->s2l, kAlphaIn, dnchk, 1));
@@ -1390,7 +1469,9 @@ stkfmm_status stkfmm_get_leaf_costs(stkfmm_ctx *c, const double rates[4], double
     for (int k = 0; k < 4; ++k)
         if (!(rates[k] > 0)) return fail(c, STKFMM_E_ARG, "rates must be positive");
     std::vector<double> out;
-    leaf_costs(c->tree, rates, c->ops->M, c->ops->Mp, kInfo[c->kernel].ncomp, out);
+    // M2L work per V pair: 2 side^2 flops per component (side = compressed rank or Mp)
+    const int side = c->ops->kc > 0 ? c->ops->kc : c->ops->Mp;
+    leaf_costs(c->tree, rates, c->ops->M, side, kInfo[c->kernel].ncomp, out);
     std::memcpy(costs, out.data(), out.size() * sizeof(double));
     return STKFMM_OK;
 }

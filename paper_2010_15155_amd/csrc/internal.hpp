@@ -108,12 +108,19 @@ struct Operators {
     std::vector<double> up1, up2;
     std::vector<float> m2m;          // [8][Mp][Mp]  parent check <- child equivalent (parent side 1)
     std::vector<float> l2l;          // [8][Mp][Mp]  child check <- parent equivalent (parent side 1)
-    std::vector<float> m2l;          // [343][Mp][Mp] check <- equivalent at offset (side 1); |o|<=1 unused
+    std::vector<float> m2l;          // [343][Mp][Mp] check <- equivalent at offset (side 1); |o|<=1 unused;
+                                     // empty when the translations are compressed (kc > 0)
+    int kc = 0;                      // rank of the compressed V-list translations (multiple of 32), 0 = dense
+    std::vector<float> cbasis;       // [Mp][kc] basis U_k (rows >= M zero)
+    std::vector<float> m2l_c;        // [343][kc][kc] cores C[o] = U_k^T M2L[o] U_k
     std::vector<double> t_m2l;       // [M][M] periodic far-image operator (side 1), empty if unused
-    double svd_tol = 0;
+    double svd_tol = 0, m2l_tol = 0;
 };
 
-std::string build_operators(int p, double svd_tol, bool periodic, Operators &ops);
+// m2l_tol > 0 compresses the V-list translations (singular values of the
+// stacked operators below m2l_tol times the largest are dropped); 0 keeps
+// them dense.
+std::string build_operators(int p, double svd_tol, bool periodic, Operators &ops, double m2l_tol = 0.0);
 
 // Index of a relative offset o in [-3,3]^3.
 inline int offset_index(int ox, int oy, int oz) { return ((oz + 3) * 7 + (oy + 3)) * 7 + (ox + 3); }

@@ -412,8 +412,8 @@ __global__ __launch_bounds__(256) void s2c_reduce(S2CReduceArgs a) {
 
 // ------------------------------------------------------------------ grouped FP32 MFMA GEMM
 // Y[:, col] = A_op * X[:, col] for tiles of 128 columns sharing one operator.
-// A_op: [Mp][Mp] row-major; columns of X and Y are contiguous Mp-vectors
-// addressed through bcol / ycol (units of Mp floats).
+// A_op: [R][K] row-major (operators opsz floats apart); columns of X (K
+// floats) and Y (R floats) are contiguous, at bcol * xs and ycol * ys.
 // Block 256 threads = 4 waves in a 2x2 arrangement, each wave 64x64 as 2x2
 // v_mfma_f32_32x32x2f32 tiles; K staged through LDS in steps of 32.
 constexpr int kGT = 128;
@@ -427,8 +427,7 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma(GemmArgs a) {
     __shared__ float Bs[kGT * kGLd];
     const int4 tile = a.tiles[blockIdx.x];            // op, col0, ncol, -
     const int row0 = blockIdx.y * kGT;
-    const int Mp = a.Mp;
-    const float *A = a.ops + int64_t(tile.x) * Mp * Mp;
+    const float *A = a.ops + int64_t(tile.x) * a.opsz;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
     // rows at or past Mr are zero padding: their MFMAs are skipped (the
@@ -450,16 +449,16 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma(GemmArgs a) {
         int idx = tid + 256 * i;
         lr[i] = idx >> 3;
         lk[i] = (idx & 7) * 4;
-        arow_ok[i] = row0 + lr[i] < Mp;
+        arow_ok[i] = row0 + lr[i] < a.R;
         bcol_ok[i] = lr[i] < tile.z;
         int c = bcol_ok[i] ? a.bcol[tile.y + lr[i]] : 0;
-        bptr[i] = a.X + int64_t(c) * Mp;
+        bptr[i] = a.X + int64_t(c) * a.xs;
     }
     float4 ra[4], rb[4];
     auto load = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            ra[i] = arow_ok[i] ? *reinterpret_cast<const float4 *>(A + int64_t(row0 + lr[i]) * Mp + k0 + lk[i])
+            ra[i] = arow_ok[i] ? *reinterpret_cast<const float4 *>(A + int64_t(row0 + lr[i]) * a.K + k0 + lk[i])
                                : make_float4(0, 0, 0, 0);
             rb[i] = bcol_ok[i] ? *reinterpret_cast<const float4 *>(bptr[i] + k0 + lk[i])
                                : make_float4(0, 0, 0, 0);
@@ -499,13 +498,13 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma(GemmArgs a) {
     for (int j = 0; j < 2; ++j) {
         const int col = wc + 32 * j + (lane & 31);
         if (col >= tile.z) continue;
-        float *Y = a.Y + int64_t(a.ycol[tile.y + col]) * Mp;
+        float *Y = a.Y + int64_t(a.ycol[tile.y + col]) * a.ys;
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const int row = row0 + wr + 32 * i + 8 * g + 4 * (lane >> 5);
-                if (row < Mp) {
+                if (row < a.R) {
                     float4 v = make_float4(acc[i][j][4 * g], acc[i][j][4 * g + 1], acc[i][j][4 * g + 2],
                                            acc[i][j][4 * g + 3]);
                     *reinterpret_cast<float4 *>(Y + row) = v;
@@ -527,8 +526,7 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_mfma(GemmArgs a) {
     __shared__ __bf16 Ah[kGT * kBLd], Al[kGT * kBLd], Bh[kGT * kBLd], Bl[kGT * kBLd];
     const int4 tile = a.tiles[blockIdx.x];
     const int row0 = blockIdx.y * kGT;
-    const int Mp = a.Mp;
-    const float *A = a.ops + int64_t(tile.x) * Mp * Mp;
+    const float *A = a.ops + int64_t(tile.x) * a.opsz;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
     const bool live0 = row0 + wr < a.Mr, live1 = row0 + wr + 32 < a.Mr;
@@ -547,16 +545,16 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_mfma(GemmArgs a) {
         int idx = tid + 256 * i;
         lr[i] = idx >> 3;
         lk[i] = (idx & 7) * 4;
-        arow_ok[i] = row0 + lr[i] < Mp;
+        arow_ok[i] = row0 + lr[i] < a.R;
         bcol_ok[i] = lr[i] < tile.z;
         int c = bcol_ok[i] ? a.bcol[tile.y + lr[i]] : 0;
-        bptr[i] = a.X + int64_t(c) * Mp;
+        bptr[i] = a.X + int64_t(c) * a.xs;
     }
     float4 ra[4], rb[4];
     auto load = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            ra[i] = arow_ok[i] ? *reinterpret_cast<const float4 *>(A + int64_t(row0 + lr[i]) * Mp + k0 + lk[i])
+            ra[i] = arow_ok[i] ? *reinterpret_cast<const float4 *>(A + int64_t(row0 + lr[i]) * a.K + k0 + lk[i])
                                : make_float4(0, 0, 0, 0);
             rb[i] = bcol_ok[i] ? *reinterpret_cast<const float4 *>(bptr[i] + k0 + lk[i])
                                : make_float4(0, 0, 0, 0);
@@ -614,13 +612,13 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_mfma(GemmArgs a) {
     for (int j = 0; j < 2; ++j) {
         const int col = wc + 32 * j + (lane & 31);
         if (col >= tile.z) continue;
-        float *Y = a.Y + int64_t(a.ycol[tile.y + col]) * Mp;
+        float *Y = a.Y + int64_t(a.ycol[tile.y + col]) * a.ys;
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const int row = row0 + wr + 32 * i + 8 * g + 4 * (lane >> 5);
-                if (row < Mp) {
+                if (row < a.R) {
                     float4 v = make_float4(acc[i][j][4 * g], acc[i][j][4 * g + 1], acc[i][j][4 * g + 2],
                                            acc[i][j][4 * g + 3]);
                     *reinterpret_cast<float4 *>(Y + row) = v;
@@ -725,9 +723,9 @@ __global__ __launch_bounds__(1024) void reduce_kernel(ReduceArgs a) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (q0 + u >= p1) break;
-                const float *Y = a.Y + int64_t(a.pair[q0 + u]) * nc * a.Mp + m;
+                const float *Y = a.Y + int64_t(a.pair[q0 + u]) * nc * a.ys + m;
 #pragma unroll
-                for (int c = 0; c < nc; ++c) y[u][c] = Y[c * a.Mp];
+                for (int c = 0; c < nc; ++c) y[u][c] = Y[c * a.ys];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -749,6 +747,64 @@ __global__ __launch_bounds__(1024) void reduce_kernel(ReduceArgs a) {
         for (int c = 0; c < nc; ++c) {
             double *o = a.chk + (int64_t(dst) * nc + c) * a.M + m;
             *o = a.accumulate ? *o + acc[c] : acc[c];
+        }
+    }
+}
+
+// Compressed translations: the pairs' Y columns hold kc coefficients in the
+// basis U_k.  The block sums them per destination (as reduce_kernel) into
+// LDS, then expands y = U_k * coefficients at the M check points.
+template <int NC>
+__global__ __launch_bounds__(1024) void reduce_expand_kernel(ReduceArgs a) {
+    __shared__ double cf[kMaxCompressed * NC];        // [k][c]
+    const int task = blockIdx.x;
+    const int dst = a.dst[task];
+    const int p0 = a.off[task], p1 = a.off[task + 1];
+    constexpr int U = 4;
+    for (int k = threadIdx.x; k < a.kc; k += blockDim.x) {
+        double acc[4] = {0, 0, 0, 0};
+        for (int q0 = p0; q0 < p1; q0 += U) {
+            float y[U][4];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (q0 + u >= p1) break;
+                const float *Y = a.Y + int64_t(a.pair[q0 + u]) * NC * a.ys + k;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) y[u][c] = Y[c * a.ys];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int p = q0 + u;
+                if (p >= p1) break;
+                const double s = a.scale[p];
+                if (NC == 4) {
+                    const double y0 = y[u][0], y1 = y[u][1], y2 = y[u][2], y3 = y[u][3];
+                    const float *dl = a.delta + 3 * int64_t(p);
+                    acc[0] += s * y0;
+                    acc[1] += s * y1;
+                    acc[2] += s * y2;
+                    acc[3] += s * (y3 - (double(dl[0]) * y0 + double(dl[1]) * y1 + double(dl[2]) * y2));
+                } else {
+                    acc[0] += s * double(y[u][0]);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) cf[k * NC + c] = acc[c];
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < a.M; m += blockDim.x) {
+        double v[4] = {0, 0, 0, 0};
+        const float *ut = a.basis_t + m;                 // U_k^T [kc][Mp], column m
+        for (int k = 0; k < a.kc; ++k) {
+            const double u = ut[int64_t(k) * a.Mp];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) v[c] += u * cf[k * NC + c];
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double *o = a.chk + (int64_t(dst) * NC + c) * a.M + m;
+            *o = a.accumulate ? *o + v[c] : v[c];
         }
     }
 }
@@ -1099,17 +1155,24 @@ hipError_t launch_stage_sources(int src_kind, int nleaves, const int *leaves, co
     return hipGetLastError();
 }
 
-hipError_t launch_gemm_f32(int ntiles, int Mp, const GemmArgs &a, hipStream_t s) {
+// shapes the grouped GEMMs assume: R, K multiples of 32; live extents within
+// them (Mk a multiple of 16); columns at least as long as the operator sides
+static bool gemm_args_ok(const GemmArgs &a) {
+    return a.R > 0 && a.K > 0 && a.R % 32 == 0 && a.K % 32 == 0 && a.Mr >= 1 && a.Mr <= a.R && a.Mk >= 1 &&
+           a.Mk <= a.K && a.Mk % 16 == 0 && a.xs >= a.K && a.ys >= a.R && a.opsz >= int64_t(a.R) * a.K;
+}
+
+hipError_t launch_gemm_f32(int ntiles, const GemmArgs &a, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    if (a.Mp != Mp || a.Mk % 16 != 0 || a.Mk > Mp || a.Mk < 1 || a.Mr > Mp) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(gemm_f32_mfma, dim3(ntiles, (Mp + kGT - 1) / kGT), dim3(256), 0, s, a);
+    if (!gemm_args_ok(a)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gemm_f32_mfma, dim3(ntiles, (a.R + kGT - 1) / kGT), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_gemm_bf16x3(int ntiles, int Mp, const GemmArgs &a, hipStream_t s) {
+hipError_t launch_gemm_bf16x3(int ntiles, const GemmArgs &a, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
-    if (a.Mp != Mp || a.Mk % 16 != 0 || a.Mk > Mp || a.Mk < 1 || a.Mr > Mp) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(gemm_bf16x3_mfma, dim3(ntiles, (Mp + kGT - 1) / kGT), dim3(256), 0, s, a);
+    if (!gemm_args_ok(a)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gemm_bf16x3_mfma, dim3(ntiles, (a.R + kGT - 1) / kGT), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1127,10 +1190,18 @@ hipError_t launch_gemm_f64_to_f32(const Gemm64Args &a, float *C, hipStream_t s) 
 
 hipError_t launch_reduce(int ntasks, const ReduceArgs &a, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
-    const int nthr = std::min(1024, (a.M + 63) / 64 * 64);
-    if (a.ncomp == 4) hipLaunchKernelGGL(reduce_kernel<4>, dim3(ntasks), dim3(nthr), 0, s, a);
-    else if (a.ncomp == 1) hipLaunchKernelGGL(reduce_kernel<1>, dim3(ntasks), dim3(nthr), 0, s, a);
-    else return hipErrorInvalidValue;
+    if (a.ncomp != 1 && a.ncomp != 4) return hipErrorInvalidValue;
+    if (a.kc > 0) {
+        if (a.kc > kMaxCompressed || a.basis_t == nullptr || a.ys < a.kc) return hipErrorInvalidValue;
+        const int nthr = std::min(1024, (std::max(a.M, a.kc) + 63) / 64 * 64);
+        if (a.ncomp == 4) hipLaunchKernelGGL(reduce_expand_kernel<4>, dim3(ntasks), dim3(nthr), 0, s, a);
+        else hipLaunchKernelGGL(reduce_expand_kernel<1>, dim3(ntasks), dim3(nthr), 0, s, a);
+    } else {
+        if (a.ys < a.M) return hipErrorInvalidValue;
+        const int nthr = std::min(1024, (a.M + 63) / 64 * 64);
+        if (a.ncomp == 4) hipLaunchKernelGGL(reduce_kernel<4>, dim3(ntasks), dim3(nthr), 0, s, a);
+        else hipLaunchKernelGGL(reduce_kernel<1>, dim3(ntasks), dim3(nthr), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -47,13 +47,15 @@ struct S2CReduceArgs {
 
 struct GemmArgs {
     const int4 *tiles;         // {op, col0, ncol, -}
-    const float *ops;          // [nop][Mp][Mp]
-    const float *X;            // density columns
-    float *Y;                  // output columns
-    const int *bcol, *ycol;    // column indices (units of Mp floats)
-    int Mp;
+    const float *ops;          // operators [R][K] row-major, opsz floats apart
+    int64_t opsz;
+    const float *X;            // input columns (K floats each, xs apart)
+    float *Y;                  // output columns (R floats each, ys apart)
+    const int *bcol, *ycol;    // column indices (units of xs / ys floats)
+    int R, K;                  // operator shape, multiples of 32
+    int xs, ys;
     int Mr;                    // rows >= Mr of the operators are zero (skipped)
-    int Mk;                    // columns >= Mk of the operators are zero; multiple of 16, <= Mp
+    int Mk;                    // columns >= Mk of the operators are zero; multiple of 16, <= K
 };
 
 struct Gemm64Args {
@@ -68,15 +70,21 @@ struct Gemm64Args {
     int ncol;
 };
 
+// Largest rank of compressed V-list translations.
+constexpr int kMaxCompressed = 512;
+
 struct ReduceArgs {
     const int *dst;            // destination box per task
     const int *off;            // per task: pair range
     const int *pair;           // Y pair index per entry
     const double *scale;       // per entry
     const float *delta;        // per entry: Psi origin shift (3)
-    const float *Y;
+    const float *Y;            // pair columns, ys floats apart per component
+    int ys;
     double *chk;
     int M, Mp, ncomp, accumulate;
+    int kc;                    // > 0: Y holds kc coefficients in the basis below
+    const float *basis_t;      // U_k^T [kc][Mp]
 };
 
 struct L2TArgs {
@@ -129,8 +137,8 @@ int s2c_stage_stride(int src_kind);
 // Stage the sources of every listed leaf (box_range: the leaves' SL or DL ranges).
 hipError_t launch_stage_sources(int src_kind, int nleaves, const int *leaves, const int2 *box_range,
                                 const double4 *geom, const float *src, int rec, float *out, hipStream_t s);
-hipError_t launch_gemm_f32(int ntiles, int Mp, const GemmArgs &a, hipStream_t s);
-hipError_t launch_gemm_bf16x3(int ntiles, int Mp, const GemmArgs &a, hipStream_t s);
+hipError_t launch_gemm_f32(int ntiles, const GemmArgs &a, hipStream_t s);
+hipError_t launch_gemm_bf16x3(int ntiles, const GemmArgs &a, hipStream_t s);
 hipError_t launch_gemm_f64(const Gemm64Args &a, double *C, hipStream_t s);
 hipError_t launch_gemm_f64_to_f32(const Gemm64Args &a, float *C, hipStream_t s);
 hipError_t launch_reduce(int ntasks, const ReduceArgs &a, hipStream_t s);

@@ -16,13 +16,22 @@
 //                 transpose of UC2UE.
 //   M2M[o], L2L[o]  parent/child operators for the 8 octants.
 //   M2L[o]        for the 316 relative offsets of the V list.
+//   M2L basis     optional compression of the V-list translations: with U_k
+//                 the leading left singular vectors of [M2L[o] for all o]
+//                 (eigenvectors of S = sum_o M2L[o] M2L[o]^T; since
+//                 M2L[-o] = M2L[o]^T, U_k also spans the leading right
+//                 singular space), M2L[o] ~ U_k C[o] U_k^T with
+//                 C[o] = U_k^T M2L[o] U_k.  k is the number of singular values
+//                 above m2l_tol times the largest, rounded up to 32.
 //   T_M2L         periodic images beyond the 3x3x3 near block, by Ewald
 //                 summation (triply periodic, Sec. III and its appendix).
 //
 // The SVD is a one-sided Jacobi (Hestenes) iteration with a round-robin
-// pair schedule whose rounds run on host threads.
+// pair schedule whose rounds run on a pool of host threads.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <functional>
 #include <numeric>
 #include <thread>
 
@@ -60,72 +69,122 @@ void laplace_block(const std::vector<double> &g, int M, const double cx[3], doub
     }
 }
 
-template <class F>
-void parallel_for(int n, F &&f) {
-    int nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    if (n < 64 || nt == 1) {
-        for (int i = 0; i < n; ++i) f(i);
-        return;
+// Worker threads that live for one operator build.  each(f) runs f(t) on
+// every thread t in [0, size()) (t = 0 on the caller) and returns when all
+// are done; barrier() synchronises the threads inside such a call.
+class Pool {
+  public:
+    explicit Pool(int nt) : nt_(std::max(1, nt)) {
+        for (int t = 1; t < nt_; ++t) th_.emplace_back([this, t] { worker(t); });
     }
-    std::vector<std::thread> th;
-    for (int t = 0; t < nt; ++t)
-        th.emplace_back([&, t] {
-            for (int i = t; i < n; i += nt) f(i);
+    ~Pool() {
+        stop_.store(true, std::memory_order_release);
+        gen_.fetch_add(1, std::memory_order_acq_rel);
+        for (auto &x : th_) x.join();
+    }
+    int size() const { return nt_; }
+    void each(const std::function<void(int)> &f) {
+        fn_ = &f;
+        done_.store(0, std::memory_order_relaxed);
+        gen_.fetch_add(1, std::memory_order_acq_rel);
+        f(0);
+        while (done_.load(std::memory_order_acquire) != nt_ - 1) std::this_thread::yield();
+    }
+    void barrier() {
+        const int g = bgen_.load(std::memory_order_acquire);
+        if (bcount_.fetch_add(1, std::memory_order_acq_rel) == nt_ - 1) {
+            bcount_.store(0, std::memory_order_relaxed);
+            bgen_.fetch_add(1, std::memory_order_acq_rel);
+        } else {
+            while (bgen_.load(std::memory_order_acquire) == g) std::this_thread::yield();
+        }
+    }
+    // f(i) for i in [0, n), interleaved over the threads
+    template <class F>
+    void parallel_for(int n, F &&f) {
+        each([&](int t) {
+            for (int i = t; i < n; i += nt_) f(i);
         });
-    for (auto &x : th) x.join();
-}
+    }
+
+  private:
+    void worker(int t) {
+        int seen = 0;
+        for (;;) {
+            int g;
+            while ((g = gen_.load(std::memory_order_acquire)) == seen) std::this_thread::yield();
+            seen = g;
+            if (stop_.load(std::memory_order_acquire)) return;
+            (*fn_)(t);
+            done_.fetch_add(1, std::memory_order_acq_rel);
+        }
+    }
+    int nt_;
+    std::vector<std::thread> th_;
+    std::atomic<int> gen_{0}, done_{0}, bcount_{0}, bgen_{0};
+    std::atomic<bool> stop_{false};
+    const std::function<void(int)> *fn_ = nullptr;
+};
+
+int pool_threads() { return int(std::max(1u, std::min(16u, std::thread::hardware_concurrency()))); }
 
 // One-sided Jacobi SVD of the square matrix A (row-major, n x n):
-// A = U diag(s) V^T.  U, V returned row-major n x n; s descending.
-void jacobi_svd(const std::vector<double> &A, int n, std::vector<double> &U,
+// A = U diag(s) V^T.  U, V returned row-major n x n; s descending.  Each
+// round of the round-robin schedule rotates disjoint column pairs, split
+// over the pool's threads.
+void jacobi_svd(Pool &pool, const std::vector<double> &A, int n, std::vector<double> &U,
                 std::vector<double> &s, std::vector<double> &V) {
     const int m = n + (n & 1);                // even number of columns for the schedule
     std::vector<double> a(size_t(m) * n, 0.0), v(size_t(m) * m, 0.0);   // column-major
     for (int j = 0; j < n; ++j)
         for (int i = 0; i < n; ++i) a[size_t(j) * n + i] = A[size_t(i) * n + j];
     for (int j = 0; j < m; ++j) v[size_t(j) * m + j] = 1.0;
-    std::vector<int> ring(m);
-    std::iota(ring.begin(), ring.end(), 0);
+    // round r pairs slot k with slot m-1-k; slot 0 holds column 0 and slot
+    // i >= 1 holds column 1 + ((i - 1 - r) mod (m - 1))
+    auto col = [m](int round, int i) { return i == 0 ? 0 : 1 + ((i - 1 - round) % (m - 1) + (m - 1)) % (m - 1); };
     const double eps = 1e-15;
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0;
-        for (int round = 0; round < m - 1; ++round) {
-            std::vector<double> offr(m / 2, 0.0);
-            parallel_for(m / 2, [&](int k) {
-                int p = ring[k], q = ring[m - 1 - k];
-                if (p > q) std::swap(p, q);
-                double *ap = &a[size_t(p) * n], *aq = &a[size_t(q) * n];
-                double al = 0, be = 0, ga = 0;
-                for (int i = 0; i < n; ++i) {
-                    al += ap[i] * ap[i];
-                    be += aq[i] * aq[i];
-                    ga += ap[i] * aq[i];
+    const int nt = pool.size();
+    std::vector<double> offt(nt, 0.0);
+    pool.each([&](int t) {
+        for (int sweep = 0; sweep < 60; ++sweep) {
+            double off_local = 0.0;
+            for (int round = 0; round < m - 1; ++round) {
+                for (int k = t; k < m / 2; k += nt) {
+                    int p = col(round, k), q = col(round, m - 1 - k);
+                    if (p > q) std::swap(p, q);
+                    double *ap = &a[size_t(p) * n], *aq = &a[size_t(q) * n];
+                    double al = 0, be = 0, ga = 0;
+                    for (int i = 0; i < n; ++i) {
+                        al += ap[i] * ap[i];
+                        be += aq[i] * aq[i];
+                        ga += ap[i] * aq[i];
+                    }
+                    if (ga == 0.0 || std::fabs(ga) <= eps * std::sqrt(al * be)) continue;
+                    off_local = std::max(off_local, std::fabs(ga) / std::sqrt(al * be));
+                    double zeta = (be - al) / (2.0 * ga);
+                    double tt = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                    double c = 1.0 / std::sqrt(1.0 + tt * tt), sn = c * tt;
+                    for (int i = 0; i < n; ++i) {
+                        double x = ap[i], y = aq[i];
+                        ap[i] = c * x - sn * y;
+                        aq[i] = sn * x + c * y;
+                    }
+                    double *vp = &v[size_t(p) * m], *vq = &v[size_t(q) * m];
+                    for (int i = 0; i < m; ++i) {
+                        double x = vp[i], y = vq[i];
+                        vp[i] = c * x - sn * y;
+                        vq[i] = sn * x + c * y;
+                    }
                 }
-                if (ga == 0.0 || std::fabs(ga) <= eps * std::sqrt(al * be)) return;
-                offr[k] = std::fabs(ga) / std::sqrt(al * be);
-                double zeta = (be - al) / (2.0 * ga);
-                double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
-                double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
-                for (int i = 0; i < n; ++i) {
-                    double x = ap[i], y = aq[i];
-                    ap[i] = c * x - sn * y;
-                    aq[i] = sn * x + c * y;
-                }
-                double *vp = &v[size_t(p) * m], *vq = &v[size_t(q) * m];
-                for (int i = 0; i < m; ++i) {
-                    double x = vp[i], y = vq[i];
-                    vp[i] = c * x - sn * y;
-                    vq[i] = sn * x + c * y;
-                }
-            });
-            for (double o : offr) off = std::max(off, o);
-            // rotate the ring, keeping ring[0] fixed
-            int last = ring[m - 1];
-            for (int k = m - 1; k > 1; --k) ring[k] = ring[k - 1];
-            ring[1] = last;
+                pool.barrier();
+            }
+            offt[t] = off_local;
+            pool.barrier();
+            const double off = *std::max_element(offt.begin(), offt.end());
+            pool.barrier();
+            if (off < 1e-14) break;
         }
-        if (off < 1e-14) break;
-    }
+    });
     std::vector<double> nrm(m);
     for (int j = 0; j < m; ++j) {
         double x = 0;
@@ -203,11 +262,13 @@ struct FarImages {
 
 }  // namespace
 
-std::string build_operators(int p, double svd_tol, bool periodic, Operators &ops) {
+std::string build_operators(int p, double svd_tol, bool periodic, Operators &ops, double m2l_tol) {
     if (p < 2 || p > 16) return "p must lie in [2, 16]";
     ops = Operators();
     ops.p = p;
     ops.svd_tol = svd_tol;
+    ops.m2l_tol = m2l_tol;
+    Pool pool(pool_threads());
     surface_lattice(p, ops.grid);
     const int M = int(ops.grid.size() / 3);
     const int Mp = (M + 31) / 32 * 32;
@@ -219,7 +280,7 @@ std::string build_operators(int p, double svd_tol, bool periodic, Operators &ops
     // UC2UE = pinv(L(uc, ue)) = V S^+ U^T
     std::vector<double> K(size_t(M) * M), U, s, V;
     laplace_block(ops.grid, M, zero, aOut, zero, aIn, K.data(), M);
-    jacobi_svd(K, M, U, s, V);
+    jacobi_svd(pool, K, M, U, s, V);
     int r = 0;
     while (r < M && s[r] > svd_tol * s[0]) ++r;
     ops.rank = r;
@@ -243,18 +304,103 @@ std::string build_operators(int p, double svd_tol, bool periodic, Operators &ops
         for (int i = 0; i < M; ++i)
             for (int j = 0; j < M; ++j) ops.l2l[(size_t(o) * Mp + i) * Mp + j] = float(B[size_t(i) * M + j]);
     }
-    // V-list offsets
-    ops.m2l.assign(size_t(343) * Mp * Mp, 0.0f);
-    parallel_for(343, [&](int idx) {
-        int ox = idx % 7 - 3, oy = (idx / 7) % 7 - 3, oz = idx / 49 - 3;
-        if (std::max({std::abs(ox), std::abs(oy), std::abs(oz)}) < 2) return;
-        double c[3] = {double(ox), double(oy), double(oz)};
-        std::vector<double> Bl(size_t(M) * M);
+    // V-list offsets: dense operators, or the compressed basis and cores
+    auto is_v_offset = [](int idx) {
+        const int ox = idx % 7 - 3, oy = (idx / 7) % 7 - 3, oz = idx / 49 - 3;
+        return std::max({std::abs(ox), std::abs(oy), std::abs(oz)}) >= 2;
+    };
+    auto m2l_block = [&](int idx, std::vector<double> &Bl) {
+        const double c[3] = {double(idx % 7 - 3), double((idx / 7) % 7 - 3), double(idx / 49 - 3)};
+        Bl.resize(size_t(M) * M);
         laplace_block(ops.grid, M, zero, aIn, c, aIn, Bl.data(), M);   // target dc <- source ue
-        float *dst = &ops.m2l[size_t(idx) * Mp * Mp];
+    };
+    int kc = 0;
+    std::vector<double> Ub;   // [M][kc] basis (row-major)
+    if (m2l_tol > 0) {
+        // S = sum_o B_o B_o^T, each thread summing its own offsets (upper triangle)
+        const int nt = pool.size();
+        std::vector<std::vector<double>> Sp(nt, std::vector<double>(size_t(M) * M, 0.0));
+        pool.each([&](int t) {
+            std::vector<double> Bl;
+            double *S = Sp[t].data();
+            for (int idx = t; idx < 343; idx += nt) {
+                if (!is_v_offset(idx)) continue;
+                m2l_block(idx, Bl);
+                for (int i = 0; i < M; ++i) {
+                    const double *bi = &Bl[size_t(i) * M];
+                    for (int j = i; j < M; ++j) {
+                        const double *bj = &Bl[size_t(j) * M];
+                        double d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+                        int l = 0;
+                        for (; l + 4 <= M; l += 4) {
+                            d0 += bi[l] * bj[l];
+                            d1 += bi[l + 1] * bj[l + 1];
+                            d2 += bi[l + 2] * bj[l + 2];
+                            d3 += bi[l + 3] * bj[l + 3];
+                        }
+                        for (; l < M; ++l) d0 += bi[l] * bj[l];
+                        S[size_t(i) * M + j] += (d0 + d1) + (d2 + d3);
+                    }
+                }
+            }
+        });
+        std::vector<double> S(size_t(M) * M, 0.0);
+        for (int t = 0; t < nt; ++t)
+            for (size_t e = 0; e < S.size(); ++e) S[e] += Sp[t][e];
         for (int i = 0; i < M; ++i)
-            for (int j = 0; j < M; ++j) dst[size_t(i) * Mp + j] = float(Bl[size_t(i) * M + j]);
-    });
+            for (int j = 0; j < i; ++j) S[size_t(i) * M + j] = S[size_t(j) * M + i];
+        std::vector<double> Us, ss, Vs;
+        jacobi_svd(pool, S, M, Us, ss, Vs);          // S = Us diag(ss) Us^T, ss = singular values^2
+        int k = 0;
+        while (k < M && ss[k] > m2l_tol * m2l_tol * ss[0]) ++k;
+        kc = (k + 31) / 32 * 32;
+        if (kc > M || 4 * kc > 3 * Mp) kc = 0;      // not worth compressing
+        if (kc > 0) {
+            Ub.assign(size_t(M) * kc, 0.0);
+            for (int i = 0; i < M; ++i)
+                for (int j = 0; j < kc; ++j) Ub[size_t(i) * kc + j] = Us[size_t(i) * M + j];
+        }
+    }
+    ops.kc = kc;
+    if (kc == 0) {
+        ops.m2l.assign(size_t(343) * Mp * Mp, 0.0f);
+        pool.parallel_for(343, [&](int idx) {
+            if (!is_v_offset(idx)) return;
+            std::vector<double> Bl;
+            m2l_block(idx, Bl);
+            float *dst = &ops.m2l[size_t(idx) * Mp * Mp];
+            for (int i = 0; i < M; ++i)
+                for (int j = 0; j < M; ++j) dst[size_t(i) * Mp + j] = float(Bl[size_t(i) * M + j]);
+        });
+    } else {
+        ops.cbasis.assign(size_t(Mp) * kc, 0.0f);
+        for (int i = 0; i < M; ++i)
+            for (int j = 0; j < kc; ++j) ops.cbasis[size_t(i) * kc + j] = float(Ub[size_t(i) * kc + j]);
+        ops.m2l_c.assign(size_t(343) * kc * kc, 0.0f);
+        pool.parallel_for(343, [&](int idx) {
+            if (!is_v_offset(idx)) return;
+            std::vector<double> Bl, T(size_t(M) * kc, 0.0), C(size_t(kc) * kc, 0.0);
+            m2l_block(idx, Bl);
+            for (int i = 0; i < M; ++i) {             // T = B U
+                double *ti = &T[size_t(i) * kc];
+                for (int l = 0; l < M; ++l) {
+                    const double b = Bl[size_t(i) * M + l];
+                    const double *ul = &Ub[size_t(l) * kc];
+                    for (int j = 0; j < kc; ++j) ti[j] += b * ul[j];
+                }
+            }
+            for (int l = 0; l < M; ++l) {             // C = U^T T
+                const double *ul = &Ub[size_t(l) * kc], *tl = &T[size_t(l) * kc];
+                for (int i = 0; i < kc; ++i) {
+                    const double u = ul[i];
+                    double *ci = &C[size_t(i) * kc];
+                    for (int j = 0; j < kc; ++j) ci[j] += u * tl[j];
+                }
+            }
+            float *dst = &ops.m2l_c[size_t(idx) * kc * kc];
+            for (size_t e = 0; e < C.size(); ++e) dst[e] = float(C[e]);
+        });
+    }
     if (periodic) {
         // T[i][j] = sum over far images of L(dc_i - ue_j - n); dc and ue are
         // the same point set (radius a_in).  Reciprocal part factorised:
@@ -270,7 +416,7 @@ std::string build_operators(int p, double svd_tol, bool periodic, Operators &ops
                 S[size_t(i) * nk + k] = std::sin(ph);
             }
         ops.t_m2l.assign(size_t(M) * M, 0.0);
-        parallel_for(M, [&](int i) {
+        pool.parallel_for(M, [&](int i) {
             for (int j = 0; j < M; ++j) {
                 double r0 = aIn * (ops.grid[3 * i] - ops.grid[3 * j]);
                 double r1 = aIn * (ops.grid[3 * i + 1] - ops.grid[3 * j + 1]);

@@ -77,9 +77,9 @@ def measure_rates(fmm, torch, n=1_048_576, p=8):
     st, tm = fmm.stats(), fmm.timings()["stages_ms"]
     fmm.set_option("overlap", "1")
     M = st["M"]
-    Mp = (M + 31) // 32 * 32
+    side = st["m2l_rank"] or st["Mp"]          # compressed rank, else M padded to 32
     p2p = st["p2p_pairs"] / (tm["p2p"] * 1e-3)
-    m2l = st["v_pairs"] * 2.0 * Mp * Mp * 4 / (tm["m2l"] * 1e-3)
+    m2l = st["v_pairs"] * 2.0 * side * side * 4 / (tm["m2l"] * 1e-3)
     evals = (2 * n + 2 * (st["w_pairs"] - st["w_direct"] + st["x_pairs"] - st["x_direct"]) * 300) * M
     surf = evals / ((tm["s2m"] + tm["s2l"] + tm["l2t"]) * 1e-3)
     per_box = (tm["upward"] + tm["downward"]) * 1e-3 / max(st["boxes"], 1)
