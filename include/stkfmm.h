@@ -206,10 +206,13 @@ stkfmm_status stkfmm_get_learned(const stkfmm_ctx *ctx, int64_t info[12], double
 stkfmm_status stkfmm_get_leaf_features(stkfmm_ctx *ctx, float *features, int32_t *leaf_of_target,
                                        int64_t *n_leaf);
 
-/* Modelled cost in seconds [n_leaf][4] (host) of refining each leaf of the
- * current tree to the capacity classes, from rates = {P2P pairs/s, M2L
- * flop/s, surface evaluations/s, seconds per box}.  Errors: E_ARG, E_STATE. */
-stkfmm_status stkfmm_get_leaf_costs(stkfmm_ctx *ctx, const double rates[4], double *costs);
+/* Work of the current plan attributed to its targets (host [n_trg][5],
+ * user order): 0 P2P lane pairs (targets counted in whole 64-lane waves
+ * times the sources of the leaf's direct list), 1 P2P wave entries, 2 M2L
+ * flops, 3 surface evaluations (S2M, S2L, L2T, M2T), 4 boxes.  Each box's
+ * work is shared equally by the targets in it.  Used to price capacity
+ * labels for the learned mode.  Errors: E_ARG, E_STATE. */
+stkfmm_status stkfmm_get_plan_work(stkfmm_ctx *ctx, double *work);
 
 /* Predictor network kernels on device buffers (stream-ordered, synchronous).
  * x [batch][12], logits [batch][8], labels [batch][2] (order class, capacity

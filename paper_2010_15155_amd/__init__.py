@@ -23,8 +23,8 @@ LIB_PATH = os.path.join(HERE, "libstkfmm.so")
 SYMBOLS = ["stkfmm_setup", "stkfmm_set_points", "stkfmm_run", "stkfmm_evaluate", "stkfmm_direct",
            "stkfmm_kernel_dims", "stkfmm_set_option", "stkfmm_get_timings", "stkfmm_get_stats",
            "stkfmm_last_error", "stkfmm_destroy", "stkfmm_mlp_nparam", "stkfmm_mlp_workspace",
-           "stkfmm_set_predictor", "stkfmm_get_learned", "stkfmm_get_leaf_features", "stkfmm_get_leaf_costs",
-           "stkfmm_mlp_forward", "stkfmm_mlp_loss_grad", "stkfmm_mlp_adam"]
+           "stkfmm_set_predictor", "stkfmm_get_learned", "stkfmm_get_leaf_features",
+           "stkfmm_get_plan_work", "stkfmm_mlp_forward", "stkfmm_mlp_loss_grad", "stkfmm_mlp_adam"]
 ORDER_CLASSES = (6, 8, 10, 12)
 CAP_CLASSES = (250, 500, 1000, 2000)
 
@@ -66,7 +66,7 @@ def lib():
     L.stkfmm_set_predictor.argtypes = [vp, vp, ci]
     L.stkfmm_get_learned.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(cd)]
     L.stkfmm_get_leaf_features.argtypes = [vp, vp, vp, ctypes.POINTER(i64)]
-    L.stkfmm_get_leaf_costs.argtypes = [vp, ctypes.POINTER(cd), vp]
+    L.stkfmm_get_plan_work.argtypes = [vp, vp]
     L.stkfmm_mlp_forward.argtypes = [vp, i64, vp, vp, vp, vp]
     L.stkfmm_mlp_loss_grad.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
     L.stkfmm_mlp_adam.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, vp]
@@ -214,14 +214,13 @@ class FMM:
                     "leaf_features")
         return feat, lot
 
-    def leaf_costs(self, rates):
-        """Modelled cost [n_leaf, 4] of refining each leaf to the capacity classes."""
+    def plan_work(self):
+        """Work of the current plan per target [n_trg, 5] (user order): P2P lane pairs,
+        P2P wave entries, M2L flops, surface evaluations, boxes."""
         import numpy as np
-        n = ctypes.c_int64()
-        self._check(lib().stkfmm_get_leaf_features(self._h, None, None, ctypes.byref(n)), "leaf_costs")
-        r = (ctypes.c_double * 4)(*rates)
-        out = np.zeros((n.value, 4))
-        self._check(lib().stkfmm_get_leaf_costs(self._h, r, out.ctypes.data_as(ctypes.c_void_p)), "leaf_costs")
+        n = self.stats()["n_trg"]
+        out = np.zeros((n, 5))
+        self._check(lib().stkfmm_get_plan_work(self._h, out.ctypes.data_as(ctypes.c_void_p)), "plan_work")
         return out
 
 

@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <array>
 #include <memory>
 #include <numeric>
 #include <string>
@@ -138,6 +139,9 @@ struct stkfmm_ctx {
     int nchunks = 0, n_p2p_tasks = 0, n_l2t_tasks = 0, nbox = 0;
     S2CPhase s2m, s2l;
     int64_t w_direct = 0, x_direct = 0, direct_pairs = 0, p2p_lane_pairs = 0;
+    // work of the plan by box: P2P lane pairs, P2P wave entries, M2L flops,
+    // surface evaluations (S2M, S2L, L2T/M2T), 1 per box
+    std::vector<std::array<double, 5>> box_work;
     int overlap = 1;
     // learned order / capacity mode
     DevMem predictor, mlp_in, mlp_out, mlp_ws, coords[3], vbuf[4];
@@ -811,6 +815,28 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     c->a_p2p_ent = ar.add(p2p_ent);
     c->a_l2t_tasks = ar.add(l2t_tasks);
     c->a_l2t_ent = ar.add(l2t_ent);
+    // ---- work by box (what the learned capacity labels are priced from)
+    {
+        const int side = ops->kc > 0 ? ops->kc : Mp;
+        c->box_work.assign(nb, std::array<double, 5>{0, 0, 0, 0, 1});
+        for (const int4 &ch : chunks) {
+            const int b = ch.x;
+            int64_t nsrc_all = 0;
+            int ne = 0;
+            for (const int2 &e : dlist[b]) nsrc_all += t.boxes[e.x].nsrc_sub, ++ne;
+            const double waves = double((ch.z - ch.y + 63) / 64);
+            c->box_work[b][0] += 64.0 * waves * double(nsrc_all);
+            c->box_work[b][1] += waves * ne;
+        }
+        for (int b = 0; b < nb; ++b) {
+            const Box &B = t.boxes[b];
+            if (t.has_local[b]) c->box_work[b][2] += double(t.v_off[b + 1] - t.v_off[b]) * 2.0 * side * side * nc;
+            for (const int2 &e : xkeep[b]) c->box_work[b][3] += double(t.boxes[e.x].nsrc_sub) * M;
+            if (!B.leaf) continue;
+            c->box_work[b][3] += double(B.sl[1] - B.sl[0] + B.dl[1] - B.dl[0]) * M;
+            c->box_work[b][3] += double(B.trg[1] - B.trg[0]) * M * ((t.has_local[b] ? 1 : 0) + wkeep[b].size());
+        }
+    }
     // ---- surface-tile tasks: S2M (each leaf's own sources) and S2L (kept X pairs)
     constexpr int kS2CTaskSources = 1024;
     size_t s2c_tasks_max = 0;
@@ -1463,16 +1489,23 @@ stkfmm_status stkfmm_get_leaf_features(stkfmm_ctx *c, float *features, int32_t *
     return STKFMM_OK;
 }
 
-stkfmm_status stkfmm_get_leaf_costs(stkfmm_ctx *c, const double rates[4], double *costs) {
-    if (!c || !rates || !costs) return STKFMM_E_ARG;
+stkfmm_status stkfmm_get_plan_work(stkfmm_ctx *c, double *work) {
+    if (!c || !work) return STKFMM_E_ARG;
     if (!c->planned) return fail(c, STKFMM_E_STATE, "no plan");
-    for (int k = 0; k < 4; ++k)
-        if (!(rates[k] > 0)) return fail(c, STKFMM_E_ARG, "rates must be positive");
-    std::vector<double> out;
-    // M2L work per V pair: 2 side^2 flops per component (side = compressed rank or Mp)
-    const int side = c->ops->kc > 0 ? c->ops->kc : c->ops->Mp;
-    leaf_costs(c->tree, rates, c->ops->M, side, kInfo[c->kernel].ncomp, out);
-    std::memcpy(costs, out.data(), out.size() * sizeof(double));
+    const Tree &t = c->tree;
+    std::vector<double> w(size_t(c->n_trg) * 5, 0.0);      // sorted target order
+    for (size_t b = 0; b < t.boxes.size(); ++b) {
+        const Box &B = t.boxes[b];
+        const int64_t n = B.trg[1] - B.trg[0];
+        if (n <= 0) continue;
+        for (int k = 0; k < 5; ++k) {
+            const double share = c->box_work[b][k] / double(n);
+            if (share == 0.0) continue;
+            for (int64_t i = B.trg[0]; i < B.trg[1]; ++i) w[size_t(i) * 5 + k] += share;
+        }
+    }
+    for (int64_t i = 0; i < c->n_trg; ++i)
+        std::memcpy(work + size_t(t.perm_trg[i]) * 5, &w[size_t(i) * 5], 5 * sizeof(double));
     return STKFMM_OK;
 }
 

@@ -79,9 +79,6 @@ std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t
                        const double *trg, int64_t n_trg, int leaf_cap, bool periodic, Tree &t,
                        const std::unordered_map<uint64_t, int> *leaf_caps = nullptr);
 
-// Morton prefix of a box (its anchor bits interleaved): the box's points have
-// keys in [prefix << 3(21-level), (prefix+1) << 3(21-level)).
-uint64_t morton_prefix(int level, const int32_t anchor[3]);
 
 // ---- learned order / capacity predictor (host side)
 constexpr int kNumFeatures = 12;
@@ -94,10 +91,6 @@ constexpr int kReferenceCap = 2000;
 void leaf_features(const Tree &t, const double *sl, const double *dl, const double *trg, double tol,
                    std::vector<float> &out);
 
-// Modelled cost (seconds) of every leaf of a reference tree refined to each
-// capacity class: rates = {P2P pairs/s, M2L flop/s, surface evaluations/s,
-// seconds per box}; M, Mp, ncomp of the order used.  out: [n_leaf][4].
-void leaf_costs(const Tree &t, const double rates[4], int M, int Mp, int ncomp, std::vector<double> &out);
 
 // Host-side FP64 operators for order p (unit box: side 1, centre 0).
 struct Operators {

@@ -137,11 +137,6 @@ inline int64_t ntrg(const Box &b) { return b.trg[1] - b.trg[0]; }
 
 }  // namespace
 
-uint64_t morton_prefix(int level, const int32_t a[3]) {
-    (void)level;
-    return (spread3(uint32_t(a[0])) << 2) | (spread3(uint32_t(a[1])) << 1) | spread3(uint32_t(a[2]));
-}
-
 std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t n_dl,
                        const double *trg, int64_t n_trg, int leaf_cap, bool periodic, Tree &t,
                        const std::unordered_map<uint64_t, int> *leaf_caps) {

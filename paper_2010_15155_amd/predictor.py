@@ -5,17 +5,19 @@ global order and leaf size, Sec. III):
   order class     smallest p in {6, 8, 10, 12} whose FMM result on the leaf's
                   sampled targets has an RMS error, against the FP64 direct
                   sum computed on the GPU (stkfmm_direct), within
-                  safety * tol * (RMS of the field over all sampled targets):
-                  if every leaf meets it, the relative L2 error over all
-                  targets is within safety * tol;
-  capacity class  the capacity in {250, 500, 1000, 2000} with the smallest
-                  modelled cost for the leaf (stkfmm_get_leaf_costs), with the
-                  model's rates measured on this GPU by `measure_rates`.
+                  max(safety * tol * (RMS of the field over all sampled
+                  targets), FLOOR * the leaf's smallest error over the orders);
+  capacity class  the capacity in {250, 500, 1000, 2000} whose plan, built
+                  with that capacity everywhere, gives the leaf's targets the
+                  smallest cost: the plan's work attributed to its targets
+                  (stkfmm_get_plan_work: P2P lane pairs and wave entries, M2L
+                  flops, surface evaluations, boxes) priced by unit costs that
+                  `fit_costs` fits to measured stage times on this GPU.
 Features: 12 per leaf of the reference tree (leaf_cap 2000), computed by the
 library.  Training runs the library's HIP kernels (forward, loss gradient,
 Adam).  Weights are saved as a float32 .npy (load with allow_pickle=False).
 
-  python -m paper_2010_15155_amd.predictor label --seeds 501:601 --out a.npz
+  python -m paper_2010_15155_amd.predictor label --seeds 501:601 --out a.npz   (fits the costs first)
   python -m paper_2010_15155_amd.predictor train --data a.npz b.npz --out w.npy
 """
 from __future__ import annotations
@@ -64,29 +66,35 @@ def calibration_table(E, cls):
     return t
 
 
-def measure_rates(fmm, torch, n=1_048_576, p=8):
-    """Cost-model rates from one serial evaluation on this GPU: P2P pairs/s,
-    M2L flop/s, surface-tile evaluations/s, seconds per box."""
-    d = W.clustered_rpy(n, 201)
-    x = torch.from_numpy(d["xyz"]).cuda()
-    f = torch.from_numpy(d["f"]).cuda()
+def fit_costs(fmm, torch, p=8, caps=(250, 500, 1000, 2000), seeds=(201, 911, 912)):
+    """Unit costs (seconds) of the five plan-work components, least-squares fits
+    of serial stage times over plans at several uniform capacities: P2P time on
+    lane pairs and wave entries, M2L time on flops, S2M + S2L + L2T time on
+    surface evaluations, the remaining stages on boxes (plus a constant)."""
+    rows, times = [], []
     fmm.set_option("overlap", "0")
-    fmm.set_points("Stokeslet", x, None, x, p=p, leaf_cap=2000)
-    for _ in range(3):
-        fmm.run(f)
-    st, tm = fmm.stats(), fmm.timings()["stages_ms"]
+    for seed in seeds:
+        d = W.clustered_rpy(1_048_576, seed) if seed == 201 else W.mixture(seed, (500_000, 2_000_000))
+        x = torch.from_numpy(d["xyz"]).cuda()
+        f = torch.from_numpy(d["f"]).cuda()
+        for cap in caps:
+            fmm.set_points("Stokeslet", x, None, x, p=p, leaf_cap=cap)
+            for _ in range(3):
+                fmm.run(f)
+            tm = fmm.timings()["stages_ms"]
+            rows.append(fmm.plan_work().sum(axis=0))
+            times.append([tm["p2p"], tm["m2l"], tm["s2m"] + tm["s2l"] + tm["l2t"],
+                          tm["upward"] + tm["downward"] + tm["pack"] + tm["combine"]])
     fmm.set_option("overlap", "1")
-    M = st["M"]
-    side = st["m2l_rank"] or st["Mp"]          # compressed rank, else M padded to 32
-    p2p = st["p2p_pairs"] / (tm["p2p"] * 1e-3)
-    m2l = st["v_pairs"] * 2.0 * side * side * 4 / (tm["m2l"] * 1e-3)
-    evals = (2 * n + 2 * (st["w_pairs"] - st["w_direct"] + st["x_pairs"] - st["x_direct"]) * 300) * M
-    surf = evals / ((tm["s2m"] + tm["s2l"] + tm["l2t"]) * 1e-3)
-    per_box = (tm["upward"] + tm["downward"]) * 1e-3 / max(st["boxes"], 1)
-    return [p2p, m2l, surf, per_box]
+    A, T = np.array(rows), np.array(times) * 1e-3
+    lane, entry = np.linalg.lstsq(A[:, :2], T[:, 0], rcond=None)[0]
+    flop = np.linalg.lstsq(A[:, 2:3], T[:, 1], rcond=None)[0][0]
+    ev = np.linalg.lstsq(A[:, 3:4], T[:, 2], rcond=None)[0][0]
+    box = np.linalg.lstsq(np.c_[A[:, 4], np.ones(len(A))], T[:, 3], rcond=None)[0][0]
+    return [float(max(v, 0.0)) for v in (lane, entry, flop, ev, box)]
 
 
-def label_set(fmm, torch, seed, rates, tol=1e-5, per_leaf=4):
+def label_set(fmm, torch, seed, costs, tol=1e-5, per_leaf=4, p_cap=8):
     """Features and (order, capacity) labels of every leaf with targets of one mixture."""
     d = W.mixture(seed, N_RANGE)
     x = torch.from_numpy(d["xyz"]).cuda()
@@ -96,8 +104,12 @@ def label_set(fmm, torch, seed, rates, tol=1e-5, per_leaf=4):
         fmm.set_points("Stokeslet", x, None, x, p=p, leaf_cap=2000)
         outs[p] = fmm.run(f).clone()
     feat, leaf_of = fmm.leaf_features()
-    fmm.set_points("Stokeslet", x, None, x, p=8, leaf_cap=2000)
-    costs = fmm.leaf_costs(rates)
+    # capacity: each uniform-capacity plan's work on the leaf's targets, priced
+    price = np.asarray(costs, dtype=np.float64)
+    cap_cost = np.zeros((len(feat), len(CAP_CLASSES)))
+    for q, cap in enumerate(CAP_CLASSES):
+        fmm.set_points("Stokeslet", x, None, x, p=p_cap, leaf_cap=cap)
+        cap_cost[:, q] = np.bincount(leaf_of, weights=fmm.plan_work() @ price, minlength=len(feat))
     # sampled targets: up to per_leaf per leaf, spread over the leaf
     rng = np.random.default_rng(seed)
     order = np.argsort(leaf_of, kind="stable")
@@ -125,7 +137,7 @@ def label_set(fmm, torch, seed, rates, tol=1e-5, per_leaf=4):
         np.add.at(num, sleaf, np.sum((got - ref) ** 2, axis=1))
         errs[:, k] = np.sqrt(num[keep] / cnt[keep]) / rms_all      # leaf RMS error / global RMS field
     labels[:, 0] = order_labels(errs, tol)
-    labels[:, 1] = costs[keep].argmin(axis=1)
+    labels[:, 1] = cap_cost[keep].argmin(axis=1)
     return feat[keep], labels, errs, {"seed": seed, "n": len(d["xyz"]), "leaves": len(feat), "k": d["k"]}
 
 
@@ -175,7 +187,7 @@ def main(argv=None):
     a = sub.add_parser("label")
     a.add_argument("--seeds", default="501:701")
     a.add_argument("--out", required=True)
-    a.add_argument("--rates", default="")
+    a.add_argument("--costs", default="", help="five unit costs (default: fit them first)")
     t = sub.add_parser("train")
     t.add_argument("--data", nargs="+", required=True)
     t.add_argument("--out", default=WEIGHTS)
@@ -184,13 +196,13 @@ def main(argv=None):
     import torch
     if args.cmd == "label":
         fmm = FMM()
-        rates = [float(r) for r in args.rates.split(",")] if args.rates else measure_rates(fmm, torch)
-        print(json.dumps({"rates": rates}), flush=True)
+        costs = [float(r) for r in args.costs.split(",")] if args.costs else fit_costs(fmm, torch)
+        print(json.dumps({"costs": costs}), flush=True)
         lo, hi = (int(s) for s in args.seeds.split(":"))
         Xs, Ys, Es, meta = [], [], [], []
         for seed in range(lo, hi):
             t0 = time.time()
-            X, Y, E, info = label_set(fmm, torch, seed, rates)
+            X, Y, E, info = label_set(fmm, torch, seed, costs)
             Xs.append(X)
             Ys.append(Y)
             Es.append(E)
@@ -199,7 +211,7 @@ def main(argv=None):
             meta.append(info)
             print(json.dumps(info), flush=True)
             np.savez(args.out, X=np.concatenate(Xs), Y=np.concatenate(Ys), E=np.concatenate(Es),
-                     rates=np.array(rates), seeds=np.array([m["seed"] for m in meta]))
+                     costs=np.array(costs), seeds=np.array([m["seed"] for m in meta]))
     else:
         data = [np.load(f, allow_pickle=False) for f in args.data]
         X = np.concatenate([d["X"] for d in data])
