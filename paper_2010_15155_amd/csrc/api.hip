@@ -78,7 +78,7 @@ struct DeviceOps {
     int p = 0, M = 0, Mp = 0, rank = 0;
     int kc = 0;                 // compressed V-list rank (0: dense m2l)
     bool periodic = false;
-    DevMem grid, m2m, l2l, m2l, up1, up2, dn1, dn2, tm2l;
+    DevMem grid, m2m, l2l, m2l, uc2ue, dc2de, tm2l;   // pseudo-inverses [M][M] FP64
     DevMem basis_t, m2l_c;      // U_k^T [kc][Mp], cores [343][kc][kc]
 };
 
@@ -92,7 +92,7 @@ struct Batch {
 
 struct PinvLevel {
     int ncol = 0;
-    size_t bidx = 0, didx = 0, cidx = 0, cscale = 0;
+    size_t bidx = 0, cidx = 0, cscale = 0;
 };
 
 // Surface-tile tasks of one phase (S2M or S2L): SL tasks then DL tasks, and
@@ -130,7 +130,7 @@ struct stkfmm_ctx {
     int64_t n_sl = 0, n_dl = 0, n_trg = 0;
     Tree tree;
     DeviceOps *ops = nullptr;
-    DevMem arena, sl_rec, dl_rec, trg_rec, up_dens, dn_dens, up_chk, dn_chk, Ybuf, tmp64, near_part, far_part,
+    DevMem arena, sl_rec, dl_rec, trg_rec, up_dens, dn_dens, up_chk, dn_chk, Ybuf, near_part, far_part,
         s2c_part, partial, direct_work, sl_stage, dl_stage, up_cmp;
     size_t a_perm_sl = 0, a_perm_dl = 0, a_perm_trg = 0, a_geom = 0, a_box_sl = 0, a_box_dl = 0, a_chunks = 0,
            a_chunk_tasks = 0, a_p2p_tasks = 0, a_p2p_ent = 0, a_l2t_tasks = 0, a_l2t_ent = 0, a_leaves_sl = 0,
@@ -156,7 +156,7 @@ struct stkfmm_ctx {
     std::vector<Batch> m2m, l2l;            // by level (parent level / child level)
     std::vector<PinvLevel> upinv, dnpinv;   // by level
     int lmin_up = 0, lmin_dn = 0;
-    size_t ybuf_floats = 0, tmp_doubles = 0;
+    size_t ybuf_floats = 0;
     double t_tree_ms = 0, t_run_ms = 0, stage_ms[16] = {};
 };
 
@@ -223,17 +223,21 @@ stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, DeviceOps **out) {
     } else {
         HIP_TRY(c, up(d->m2l, h.m2l.data(), h.m2l.size() * sizeof(float)));
     }
-    // UC2UE = P1 P2 ; DC2DE = P2^T P1^T
+    // UC2UE = P1 P2 and DC2DE = UC2UE^T, formed once in FP64: one GEMM per
+    // level applies them
     const int M = h.M, r = h.rank;
-    std::vector<double> t1(size_t(r) * M), t2(size_t(M) * r);
+    std::vector<double> uc(size_t(M) * M, 0.0), dc(size_t(M) * M);
     for (int i = 0; i < M; ++i)
-        for (int k = 0; k < r; ++k) t1[size_t(k) * M + i] = h.up1[size_t(i) * r + k];   // P1^T [r][M]
-    for (int k = 0; k < r; ++k)
-        for (int j = 0; j < M; ++j) t2[size_t(j) * r + k] = h.up2[size_t(k) * M + j];   // P2^T [M][r]
-    HIP_TRY(c, up(d->up1, h.up1.data(), h.up1.size() * sizeof(double)));
-    HIP_TRY(c, up(d->up2, h.up2.data(), h.up2.size() * sizeof(double)));
-    HIP_TRY(c, up(d->dn1, t1.data(), t1.size() * sizeof(double)));
-    HIP_TRY(c, up(d->dn2, t2.data(), t2.size() * sizeof(double)));
+        for (int k = 0; k < r; ++k) {
+            const double a = h.up1[size_t(i) * r + k];
+            const double *b = &h.up2[size_t(k) * M];
+            double *o = &uc[size_t(i) * M];
+            for (int j = 0; j < M; ++j) o[j] += a * b[j];
+        }
+    for (int i = 0; i < M; ++i)
+        for (int j = 0; j < M; ++j) dc[size_t(j) * M + i] = uc[size_t(i) * M + j];
+    HIP_TRY(c, up(d->uc2ue, uc.data(), uc.size() * sizeof(double)));
+    HIP_TRY(c, up(d->dc2de, dc.data(), dc.size() * sizeof(double)));
     if (periodic) HIP_TRY(c, up(d->tm2l, h.t_m2l.data(), h.t_m2l.size() * sizeof(double)));
     *out = d.get();
     c->ops_cache[key] = std::move(d);
@@ -363,19 +367,15 @@ stkfmm_status run_compress(stkfmm_ctx *c, const float *dens, float *coef, hipStr
 }
 
 // dens(cols) = scale * F1 (F2 chk(cols)) in FP64 (the check-to-equivalent pseudo-inverse)
-stkfmm_status run_pinv(stkfmm_ctx *c, const PinvLevel &pl, const double *F2, const double *F1, const double *chk,
-                       float *dens, hipStream_t s) {
+// dens(cols) = scale * P chk(cols) in FP64, P the check-to-equivalent
+// pseudo-inverse (M x M), written as FP32 densities
+stkfmm_status run_pinv(stkfmm_ctx *c, const PinvLevel &pl, const double *P, const double *chk, float *dens,
+                       hipStream_t s) {
     if (pl.ncol == 0) return STKFMM_OK;
     const DeviceOps &o = *c->ops;
-    Gemm64Args a;
-    a.A = F2; a.R = o.rank; a.K = o.M; a.lda = o.M;
-    a.B = chk; a.bidx = at<int>(c, pl.bidx); a.ldb = o.M;
-    a.cidx = at<int>(c, pl.didx); a.cscale = nullptr; a.ldc = o.rank;
-    a.ncol = pl.ncol;
-    HIP_TRY(c, launch_gemm_f64(a, c->tmp64.as<double>(), s));
     Gemm64Args b;
-    b.A = F1; b.R = o.M; b.K = o.rank; b.lda = o.rank;
-    b.B = c->tmp64.as<double>(); b.bidx = at<int>(c, pl.didx); b.ldb = o.rank;
+    b.A = P; b.R = o.M; b.K = o.M; b.lda = o.M;
+    b.B = chk; b.bidx = at<int>(c, pl.bidx); b.ldb = o.M;
     b.cidx = at<int>(c, pl.cidx); b.cscale = at<double>(c, pl.cscale); b.ldc = o.Mp;
     b.ncol = pl.ncol;
     HIP_TRY(c, launch_gemm_f64_to_f32(b, dens, s));
@@ -894,7 +894,6 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     c->lmin_up = periodic ? 0 : 2;
     c->lmin_dn = periodic ? 0 : 2;
     c->ybuf_floats = 0;
-    c->tmp_doubles = 0;
     // M2L: V-list pairs grouped by offset
     {
         std::vector<Pair> pairs;
@@ -933,7 +932,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     c->dnpinv.assign(t.depth + 1, PinvLevel());
     for (int l = 0; l <= t.depth; ++l) {
         std::vector<Pair> up, dn;
-        std::vector<int> ub, ud, uc, db, dd, dcx;
+        std::vector<int> ub, uc, db, dcx;
         std::vector<double> us, ds;
         for (int b = t.level_start[l]; b < t.level_start[l + 1]; ++b) {
             const Box &B = t.boxes[b];
@@ -953,7 +952,6 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
                 }
                 for (int k = 0; k < nc; ++k) {
                     ub.push_back(b * nc + k);
-                    ud.push_back(int(ud.size()));
                     uc.push_back(b * nc + k);
                     us.push_back(hb);
                 }
@@ -974,7 +972,6 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
                 }
                 for (int k = 0; k < nc; ++k) {
                     db.push_back(b * nc + k);
-                    dd.push_back(int(dd.size()));
                     dcx.push_back(b * nc + k);
                     ds.push_back(hb);
                 }
@@ -985,16 +982,13 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
         PinvLevel &pu = c->upinv[l];
         pu.ncol = int(ub.size());
         pu.bidx = ar.add(ub);
-        pu.didx = ar.add(ud);
         pu.cidx = ar.add(uc);
         pu.cscale = ar.add(us);
         PinvLevel &pd = c->dnpinv[l];
         pd.ncol = int(db.size());
         pd.bidx = ar.add(db);
-        pd.didx = ar.add(dd);
         pd.cidx = ar.add(dcx);
         pd.cscale = ar.add(ds);
-        c->tmp_doubles = std::max(c->tmp_doubles, size_t(std::max(pu.ncol, pd.ncol)) * ops->rank);
     }
     HIP_TRY(c, c->arena.ensure(ar.host.size()));
     HIP_TRY(c, hipMemcpyAsync(c->arena.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice, s));
@@ -1009,7 +1003,6 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     HIP_TRY(c, c->dn_chk.ensure(size_t(nb) * nc * M * sizeof(double)));
     HIP_TRY(c, c->Ybuf.ensure(std::max<size_t>(c->ybuf_floats, 1) * sizeof(float)));
     if (ops->kc > 0) HIP_TRY(c, c->up_cmp.ensure(size_t(nb) * nc * ops->kc * sizeof(float)));
-    HIP_TRY(c, c->tmp64.ensure(std::max<size_t>(c->tmp_doubles, 1) * sizeof(double)));
     HIP_TRY(c, c->near_part.ensure(size_t(std::max(c->n_p2p_tasks, 1)) * 256 * ki.kt_acc * sizeof(double)));
     HIP_TRY(c, c->far_part.ensure(size_t(std::max(c->n_l2t_tasks, 1)) * 256 * ki.kt_acc * sizeof(double)));
     HIP_TRY(c, c->s2c_part.ensure(std::max<size_t>(s2c_tasks_max, 1) * nc * M * sizeof(float)));
@@ -1260,7 +1253,7 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
                 stkfmm_status st = run_batch(c, c->m2m[l], o.m2m.as<float>(), updens, upchk, s);
                 if (st != STKFMM_OK) return st;
             }
-            stkfmm_status st = run_pinv(c, c->upinv[l], o.up2.as<double>(), o.up1.as<double>(), upchk, updens, s);
+            stkfmm_status st = run_pinv(c, c->upinv[l], o.uc2ue.as<double>(), upchk, updens, s);
             if (st != STKFMM_OK) return st;
         }
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 3 upward
@@ -1281,7 +1274,7 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         for (int l = c->lmin_dn; l <= t.depth; ++l) {
             st = run_batch(c, c->l2l[l], o.l2l.as<float>(), dndens, dnchk, s);
             if (st != STKFMM_OK) return st;
-            st = run_pinv(c, c->dnpinv[l], o.dn1.as<double>(), o.dn2.as<double>(), dnchk, dndens, s);
+            st = run_pinv(c, c->dnpinv[l], o.dc2de.as<double>(), dnchk, dndens, s);
             if (st != STKFMM_OK) return st;
         }
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 6 downward

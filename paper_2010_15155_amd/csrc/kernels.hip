@@ -136,6 +136,33 @@ __global__ void pack_targets(int64_t n, const double *__restrict__ xyz, const in
 //          1e-7 h / |r| per pair, and it saves 6 of about 26 operations per
 //          pair.  Used where the kernel's singularity is mild enough (the
 //          Stokeslet, 1/r) for that to stay far below the FMM error.
+//
+// Coincident points (r = 0) contribute nothing.  Only the target leaf's own
+// entry can hold them (equal positions fall in the same leaf), so the REL
+// loop guards 1/r against r = 0 there and nowhere else; distinct points of
+// different leaves closer than about 2^-22 of the root box, which FP32
+// leaf-relative positions cannot separate, give a non-finite result.
+template <class K, bool GUARD>
+__device__ __forceinline__ void p2p_rel_run(const float *__restrict__ src, int j0, int j1, float xr, float yr,
+                                            float zr, double *acc) {
+    for (int r0 = j0; r0 < j1; r0 += 64) {
+        const int r1 = min(r0 + 64, j1);
+        float part[K::NACC];
+#pragma unroll
+        for (int k = 0; k < K::NACC; ++k) part[k] = 0.0f;
+#pragma unroll 4
+        for (int j = r0; j < r1; ++j) {
+            const float *s = src + int64_t(j) * K::RS;
+            const float dx = xr - s[9], dy = yr - s[10], dz = zr - s[11];
+            const float r2 = dot3(dx, dy, dz, dx, dy, dz);
+            const float ri = GUARD ? rsq_or_zero(r2) : __builtin_amdgcn_rsqf(r2);
+            K::sl(dx, dy, dz, ri, s + 6, part);
+        }
+#pragma unroll
+        for (int k = 0; k < K::NACC; ++k) acc[k] += double(part[k]);
+    }
+}
+
 template <class K>
 __device__ __forceinline__ void p2p_run(const float *__restrict__ src, int j0, int j1, float xh, float yh,
                                         float zh, float xl, float yl, float zl, double *acc, bool dl) {
@@ -144,26 +171,16 @@ __device__ __forceinline__ void p2p_run(const float *__restrict__ src, int j0, i
         float part[K::NACC];
 #pragma unroll
         for (int k = 0; k < K::NACC; ++k) part[k] = 0.0f;
-        if (K::REL) {
+        const int rs = dl ? (K::RD > 0 ? K::RD : 1) : K::RS;
 #pragma unroll 4
-            for (int j = r0; j < r1; ++j) {
-                const float *s = src + int64_t(j) * K::RS;
-                const float dx = xh - s[9], dy = yh - s[10], dz = zh - s[11];
-                const float ri = rsq_or_zero(dot3(dx, dy, dz, dx, dy, dz));
-                K::sl(dx, dy, dz, ri, s + 6, part);
-            }
-        } else {
-            const int rs = dl ? (K::RD > 0 ? K::RD : 1) : K::RS;
-#pragma unroll 4
-            for (int j = r0; j < r1; ++j) {
-                const float *s = src + int64_t(j) * rs;
-                const float dx = (xh - s[0]) + (xl - s[3]);
-                const float dy = (yh - s[1]) + (yl - s[4]);
-                const float dz = (zh - s[2]) + (zl - s[5]);
-                const float ri = rsq_or_zero(dot3(dx, dy, dz, dx, dy, dz));
-                if (dl) K::dl(dx, dy, dz, ri, s + 6, part);
-                else K::sl(dx, dy, dz, ri, s + 6, part);
-            }
+        for (int j = r0; j < r1; ++j) {
+            const float *s = src + int64_t(j) * rs;
+            const float dx = (xh - s[0]) + (xl - s[3]);
+            const float dy = (yh - s[1]) + (yl - s[4]);
+            const float dz = (zh - s[2]) + (zl - s[5]);
+            const float ri = rsq_or_zero(dot3(dx, dy, dz, dx, dy, dz));
+            if (dl) K::dl(dx, dy, dz, ri, s + 6, part);
+            else K::sl(dx, dy, dz, ri, s + 6, part);
         }
 #pragma unroll
         for (int k = 0; k < K::NACC; ++k) acc[k] += double(part[k]);
@@ -195,7 +212,8 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs a) {
             const float xr = float((double(p0.x) - (g.x + sx)) + double(p1.x));
             const float yr = float((double(p0.y) - (g.y + sy)) + double(p1.y));
             const float zr = float((double(p0.z) - (g.z + sz)) + double(p1.z));
-            p2p_run<K>(a.sl, rs.x, rs.y, xr, yr, zr, 0.0f, 0.0f, 0.0f, acc, false);
+            if (en.x == ch.x && en.y == kZeroShift) p2p_rel_run<K, true>(a.sl, rs.x, rs.y, xr, yr, zr, acc);
+            else p2p_rel_run<K, false>(a.sl, rs.x, rs.y, xr, yr, zr, acc);
         } else {
             float xh = p0.x, yh = p0.y, zh = p0.z, xl = p1.x, yl = p1.y, zl = p1.z;
             if (sx) two_sum_shift(xh, xl, float(sx));
@@ -422,11 +440,15 @@ constexpr int kGLd = kGK + 1;
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-__global__ __launch_bounds__(256) void gemm_f32_mfma(GemmArgs a) {
-    __shared__ float As[kGT * kGLd];
+// WR row waves x 2 column waves: block tile (64 WR) rows x 128 columns.
+template <int WR>
+__global__ __launch_bounds__(128 * WR) void gemm_f32_mfma(GemmArgs a) {
+    constexpr int TR = 64 * WR, NT = 128 * WR;
+    constexpr int NA = TR * 8 / NT, NB = (kGT * 8 + NT - 1) / NT;   // float4 slots per thread
+    __shared__ float As[TR * kGLd];
     __shared__ float Bs[kGT * kGLd];
     const int4 tile = a.tiles[blockIdx.x];            // op, col0, ncol, -
-    const int row0 = blockIdx.y * kGT;
+    const int row0 = blockIdx.y * TR;
     const float *A = a.ops + int64_t(tile.x) * a.opsz;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
@@ -440,38 +462,45 @@ __global__ __launch_bounds__(256) void gemm_f32_mfma(GemmArgs a) {
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
-    // per-thread load slots: 4 float4 of A and of B per K step
-    const float *bptr[4];
-    int lr[4], lk[4];
-    bool arow_ok[4], bcol_ok[4];
+    // per-thread load slots: float4s of A (row, k) and of B (column, k) per K step
+    int ar[NA], ak[NA], br[NB], bk[NB];
+    bool arow_ok[NA], bcol_ok[NB];
+    const float *bptr[NB];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        int idx = tid + 256 * i;
-        lr[i] = idx >> 3;
-        lk[i] = (idx & 7) * 4;
-        arow_ok[i] = row0 + lr[i] < a.R;
-        bcol_ok[i] = lr[i] < tile.z;
-        int c = bcol_ok[i] ? a.bcol[tile.y + lr[i]] : 0;
+    for (int i = 0; i < NA; ++i) {
+        const int idx = tid + NT * i;
+        ar[i] = idx >> 3;
+        ak[i] = (idx & 7) * 4;
+        arow_ok[i] = row0 + ar[i] < a.R;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int idx = tid + NT * i;
+        br[i] = idx >> 3;
+        bk[i] = (idx & 7) * 4;
+        bcol_ok[i] = idx < kGT * 8 && br[i] < tile.z;
+        const int c = bcol_ok[i] ? a.bcol[tile.y + br[i]] : 0;
         bptr[i] = a.X + int64_t(c) * a.xs;
     }
-    float4 ra[4], rb[4];
-    auto load = [&](int k0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            ra[i] = arow_ok[i] ? *reinterpret_cast<const float4 *>(A + int64_t(row0 + lr[i]) * a.K + k0 + lk[i])
-                               : make_float4(0, 0, 0, 0);
-            rb[i] = bcol_ok[i] ? *reinterpret_cast<const float4 *>(bptr[i] + k0 + lk[i])
-                               : make_float4(0, 0, 0, 0);
-        }
-    };
     for (int k0 = 0; k0 < a.Mk; k0 += kGK) {
-        load(k0);
+        float4 ra[NA], rb[NB];
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+            ra[i] = arow_ok[i] ? *reinterpret_cast<const float4 *>(A + int64_t(row0 + ar[i]) * a.K + k0 + ak[i])
+                               : make_float4(0, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            rb[i] = bcol_ok[i] ? *reinterpret_cast<const float4 *>(bptr[i] + k0 + bk[i]) : make_float4(0, 0, 0, 0);
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            float *da = As + lr[i] * kGLd + lk[i];
-            float *db = Bs + lr[i] * kGLd + lk[i];
+        for (int i = 0; i < NA; ++i) {
+            float *da = As + ar[i] * kGLd + ak[i];
             da[0] = ra[i].x; da[1] = ra[i].y; da[2] = ra[i].z; da[3] = ra[i].w;
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            if (tid + NT * i >= kGT * 8) continue;
+            float *db = Bs + br[i] * kGLd + bk[i];
             db[0] = rb[i].x; db[1] = rb[i].y; db[2] = rb[i].z; db[3] = rb[i].w;
         }
         __syncthreads();
@@ -1165,7 +1194,11 @@ static bool gemm_args_ok(const GemmArgs &a) {
 hipError_t launch_gemm_f32(int ntiles, const GemmArgs &a, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     if (!gemm_args_ok(a)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(gemm_f32_mfma, dim3(ntiles, (a.R + kGT - 1) / kGT), dim3(256), 0, s, a);
+    // 192-row tiles when they cover R exactly and 128-row tiles do not
+    if (a.R % 192 == 0 && a.R % 128 != 0)
+        hipLaunchKernelGGL(gemm_f32_mfma<3>, dim3(ntiles, a.R / 192), dim3(384), 0, s, a);
+    else
+        hipLaunchKernelGGL(gemm_f32_mfma<2>, dim3(ntiles, (a.R + kGT - 1) / kGT), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
