@@ -152,3 +152,54 @@ def test_ragged_and_empty(fmm):
     assert direct.rel_l2(got, ref) < 1e-5
     out = gpu_eval(fmm, "Stokeslet", dict(trg_xyz=t), 6, 20)
     assert np.array_equal(out, np.zeros((333, 3)))
+
+
+@pytest.mark.parametrize("kernel,p", [("Stokeslet", 8), ("Traction", 8), ("RPY", 10)])
+def test_compressed_and_dense_m2l(fmm, kernel, p):
+    # the compressed V-list translations (default) and the dense operators
+    # (m2l_tol = 0) both meet the budget and agree to well below it
+    pb = problem(kernel, 24000, 6)
+    ref = oracle_of(kernel, pb)
+    cmp = gpu_eval(fmm, kernel, pb, p, 150)
+    rank, Mp = fmm.stats()["m2l_rank"], fmm.stats()["Mp"]
+    try:
+        fmm.set_option("m2l_tol", "0")
+        dense = gpu_eval(fmm, kernel, pb, p, 150)
+        assert fmm.stats()["m2l_rank"] == 0
+    finally:
+        fmm.set_option("m2l_tol", "5e-8")
+    ec, ed = field_errors(kernel, cmp, ref), field_errors(kernel, dense, ref)
+    print(kernel, p, "rank", rank, "compressed", ec, "dense", ed, flush=True)
+    assert 0 < rank < Mp
+    for name, a, b in FIELDS[kernel]:
+        assert ec[name] < 1e-5 and ed[name] < 1e-5
+        assert direct.rel_l2(cmp[:, a:b], dense[:, a:b]) < 3e-6
+
+
+def test_coincident_points(fmm):
+    # duplicated positions: coincident pairs contribute nothing (the oracle
+    # skips r = 0), in the own leaf and across the tree
+    rng = np.random.default_rng(12)
+    x = rng.random((6000, 3))
+    x[3000:] = x[:3000][rng.permutation(3000)]
+    f = rng.standard_normal((6000, 3))
+    for p, cap in ((6, 100000), (8, 60)):
+        got = gpu_eval(fmm, "Stokeslet", dict(sl_xyz=x, sl_val=f, trg_xyz=x), p, cap)
+        assert np.all(np.isfinite(got))
+        err = direct.rel_l2(got, direct.stokeslet(x, f, x))
+        print("coincident", p, cap, err, flush=True)
+        assert err < (2e-6 if cap > 6000 else 1e-5)
+
+
+def test_plan_work_matches_stats(fmm):
+    pb = problem("Stokeslet", 30000, 7)
+    gpu_eval(fmm, "Stokeslet", pb, 8, 200)
+    st = fmm.stats()
+    w = fmm.plan_work()
+    assert w.shape == (30000, 5) and np.all(w >= 0)
+    # every P2P lane pair belongs to a leaf with targets; every box here holds targets
+    assert abs(w[:, 0].sum() - st["p2p_lane_pairs"]) <= 1e-9 * st["p2p_lane_pairs"]
+    assert st["p2p_lane_pairs"] >= st["p2p_pairs"]
+    assert abs(w[:, 4].sum() - st["boxes"]) < 1e-6 * st["boxes"]
+    side = st["m2l_rank"] or st["Mp"]
+    assert abs(w[:, 2].sum() - st["v_pairs"] * 2.0 * side * side * 4) <= 1e-9 * w[:, 2].sum()
