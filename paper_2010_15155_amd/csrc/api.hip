@@ -248,7 +248,22 @@ stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, DeviceOps **out) {
 Batch make_batch(Arena &ar, std::vector<Pair> pairs, int nc, int accumulate, size_t &ybuf_floats, int Mp) {
     Batch b;
     b.accumulate = accumulate;
-    std::stable_sort(pairs.begin(), pairs.end(), [](const Pair &x, const Pair &y) { return x.op < y.op; });
+    // stable counting sorts: by operator for the GEMM tiles, by destination for the reduce
+    auto stable_order = [&](auto key, int nkey) {
+        std::vector<int> start(nkey + 1, 0), order(pairs.size());
+        for (const Pair &pr : pairs) ++start[key(pr) + 1];
+        for (int k = 0; k < nkey; ++k) start[k + 1] += start[k];
+        for (size_t i = 0; i < pairs.size(); ++i) order[start[key(pairs[i])]++] = int(i);
+        return order;
+    };
+    {
+        int nop = 0;
+        for (const Pair &pr : pairs) nop = std::max(nop, pr.op + 1);
+        const std::vector<int> byop = stable_order([](const Pair &pr) { return pr.op; }, nop);
+        std::vector<Pair> sorted(pairs.size());
+        for (size_t i = 0; i < byop.size(); ++i) sorted[i] = pairs[byop[i]];
+        pairs.swap(sorted);
+    }
     b.npairs = int(pairs.size());
     std::vector<int> bcol, ycol;
     std::vector<int4> tiles;
@@ -267,9 +282,9 @@ Batch make_batch(Arena &ar, std::vector<Pair> pairs, int nc, int accumulate, siz
     }
     b.ntiles = int(tiles.size());
     // reduce by destination, pairs in index order
-    std::vector<int> order(pairs.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = int(i);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return pairs[x].dst < pairs[y].dst; });
+    int ndst = 0;
+    for (const Pair &pr : pairs) ndst = std::max(ndst, pr.dst + 1);
+    const std::vector<int> order = stable_order([](const Pair &pr) { return pr.dst; }, ndst);
     std::vector<int> rdst, roff, rpair;
     std::vector<double> rscale;
     std::vector<float> rdelta;

@@ -22,6 +22,7 @@
 #include <unordered_map>
 
 #include "internal.hpp"
+#include "pool.hpp"
 
 namespace kafmm {
 
@@ -56,16 +57,61 @@ struct Sorted {
     std::vector<int32_t> perm;
 };
 
-Sorted sort_points(const double *x, int64_t n) {
-    std::vector<std::pair<uint64_t, int32_t>> kv(n);
-    for (int64_t i = 0; i < n; ++i) kv[i] = {morton(x + 3 * i), int32_t(i)};
-    std::sort(kv.begin(), kv.end());
+// Stable LSD radix sort of the 63-bit Morton keys (six 11-bit digits) with
+// the input index as payload: ties keep input order, as the tree requires.
+Sorted sort_points(Pool &pool, const double *x, int64_t n) {
     Sorted s;
     s.key.resize(n);
     s.perm.resize(n);
-    for (int64_t i = 0; i < n; ++i) {
-        s.key[i] = kv[i].first;
-        s.perm[i] = kv[i].second;
+    if (n == 0) return s;
+    std::vector<uint64_t> k2(n);
+    std::vector<int32_t> p2(n);
+    const int nt = pool.size();
+    pool.each([&](int t) {
+        for (int64_t i = n * t / nt; i < n * (t + 1) / nt; ++i) {
+            s.key[i] = morton(x + 3 * i);
+            s.perm[i] = int32_t(i);
+        }
+    });
+    // each pass: per-thread histograms of contiguous chunks, offsets in
+    // (digit, thread) order, then each thread scatters its chunk in order
+    constexpr int kDigit = 11, kBins = 1 << kDigit;
+    std::vector<int64_t> count(size_t(nt) * kBins);
+    uint64_t *ka = s.key.data(), *kb = k2.data();
+    int32_t *pa = s.perm.data(), *pb = p2.data();
+    for (int shift = 0; shift < 3 * kKeyBits; shift += kDigit) {
+        pool.each([&](int t) {
+            int64_t *c = &count[size_t(t) * kBins];
+            std::fill(c, c + kBins, 0);
+            for (int64_t i = n * t / nt; i < n * (t + 1) / nt; ++i) ++c[(ka[i] >> shift) & (kBins - 1)];
+        });
+        int64_t sum = 0;
+        bool trivial = false;
+        for (int b = 0; b < kBins; ++b) {
+            int64_t tot = 0;
+            for (int t = 0; t < nt; ++t) tot += count[size_t(t) * kBins + b];
+            if (tot == n) trivial = true;      // one digit value: the pass is a no-op
+            for (int t = 0; t < nt; ++t) {
+                const int64_t c = count[size_t(t) * kBins + b];
+                count[size_t(t) * kBins + b] = sum;
+                sum += c;
+            }
+        }
+        if (trivial) continue;
+        pool.each([&](int t) {
+            int64_t *c = &count[size_t(t) * kBins];
+            for (int64_t i = n * t / nt; i < n * (t + 1) / nt; ++i) {
+                const int64_t d = c[(ka[i] >> shift) & (kBins - 1)]++;
+                kb[d] = ka[i];
+                pb[d] = pa[i];
+            }
+        });
+        std::swap(ka, kb);
+        std::swap(pa, pb);
+    }
+    if (ka != s.key.data()) {
+        std::memcpy(s.key.data(), ka, size_t(n) * sizeof(uint64_t));
+        std::memcpy(s.perm.data(), pa, size_t(n) * sizeof(int32_t));
     }
     return s;
 }
@@ -142,7 +188,12 @@ std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t
                        const std::unordered_map<uint64_t, int> *leaf_caps) {
     t = Tree();
     t.periodic = periodic;
-    Sorted S[3] = {sort_points(sl, n_sl), sort_points(dl, n_dl), sort_points(trg, n_trg)};
+    // sets given by the same array are sorted once
+    Pool pool(pool_threads());
+    Sorted S[3];
+    S[0] = sort_points(pool, sl, n_sl);
+    S[1] = (dl == sl && n_dl == n_sl) ? S[0] : sort_points(pool, dl, n_dl);
+    S[2] = (trg == sl && n_trg == n_sl) ? S[0] : (trg == dl && n_trg == n_dl) ? S[1] : sort_points(pool, trg, n_trg);
     t.perm_sl = S[0].perm;
     t.perm_dl = S[1].perm;
     t.perm_trg = S[2].perm;
@@ -213,7 +264,7 @@ std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t
     // ------------------------------------------------------------ lists
     Lister L(t);
     std::vector<std::vector<Img>> U(nb), W(nb), X(nb), V(nb);
-    std::vector<Img> col, pcol;
+    std::vector<Img> col;
     // U and W by descending from the colleagues of each leaf
     for (int b : t.leaves) {
         L.colleagues(b, col);
@@ -253,31 +304,35 @@ std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t
         for (const Img &e : W[b])
             X[e.box].push_back({b, {int8_t(-e.s[0]), int8_t(-e.s[1]), int8_t(-e.s[2])}});
     // V: children of the parent's colleagues that are not adjacent
-    std::vector<std::array<int8_t, 3>> vrel;
-    for (int b = 1; b < nb; ++b) {
-        L.colleagues(t.boxes[b].parent, pcol);
-        for (const Img &c : pcol)
-            for (int o = 0; o < 8; ++o) {
-                int ch = t.boxes[c.box].child[o];
-                if (ch < 0 || L.adjacent(ch, c.s, b)) continue;
-                V[b].push_back({ch, c.s});
-            }
-    }
+    pool.each([&](int th) {
+        std::vector<Img> pc;
+        for (int b = 1 + th; b < nb; b += pool.size()) {
+            L.colleagues(t.boxes[b].parent, pc);
+            for (const Img &c : pc)
+                for (int o = 0; o < 8; ++o) {
+                    int ch = t.boxes[c.box].child[o];
+                    if (ch < 0 || L.adjacent(ch, c.s, b)) continue;
+                    V[b].push_back({ch, c.s});
+                }
+        }
+    });
 
     // ------------------------------------------------------------ prune and flatten
     auto flatten = [&](std::vector<std::vector<Img>> &lists, std::vector<int> &off,
                        std::vector<Entry> &ent, bool need_src, bool need_trg) {
         off.assign(nb + 1, 0);
         ent.clear();
-        for (int b = 0; b < nb; ++b) {
-            off[b] = int(ent.size());
-            const Box &B = t.boxes[b];
-            if (need_trg && (B.leaf ? ntrg(B) : B.ntrg_sub) == 0) continue;
-            // deterministic order: by box id then shift
+        // deterministic order: by box id then shift
+        pool.parallel_for(nb, [&](int b) {
             std::sort(lists[b].begin(), lists[b].end(), [](const Img &p, const Img &q) {
                 if (p.box != q.box) return p.box < q.box;
                 return p.s < q.s;
             });
+        });
+        for (int b = 0; b < nb; ++b) {
+            off[b] = int(ent.size());
+            const Box &B = t.boxes[b];
+            if (need_trg && (B.leaf ? ntrg(B) : B.ntrg_sub) == 0) continue;
             for (const Img &e : lists[b]) {
                 if (need_src && t.boxes[e.box].nsrc_sub == 0) continue;
                 Entry en;
