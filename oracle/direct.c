@@ -16,6 +16,9 @@
  *   Laplace L = 1/(4 pi r), dipole L^D_j = -dL/dx_j           Sec. II.A
  *   Stokeslet G_ij = (delta_ij/r + r_i r_j/r^3)/(8 pi)        Sec. II.B
  *   RPY G^RPY = (1 + b^2 lap/6) G, target [u, lap u]          Sec. II.B, Eq. RPYkernel
+ *   regularized Stokeslet G^eps = H1(r) delta + H2(r) r r^T,
+ *     H1 = (r^2 + 2 eps^2)/(8 pi (r^2+eps^2)^(3/2)), H2 = 1/(8 pi (r^2+eps^2)^(3/2))
+ *                                                             Sec. II.B, tab:ktab_reg
  *   StokesPVel [f,q] -> [p,u]                                 Sec. II.C, Eqs. stkslp, stkslvel
  *   Stokes double layer D -> [p,u], T_ijk = -3 r_i r_j r_k/(8 pi r^5)
  *                                                             Sec. II.C, Eqs. stkdlp, stkdlvel
@@ -47,6 +50,33 @@ void oracle_stokeslet(int64_t ns, const double *ys, const double *f,
             u0 += a*f0 + b*r0;
             u1 += a*f1 + b*r1;
             u2 += a*f2 + b*r2;
+        }
+        out[3*t] = c*u0; out[3*t+1] = c*u1; out[3*t+2] = c*u2;
+    }
+}
+
+/* Regularized Stokeslet: (f1,f2,f3,eps) (4) -> u (3).  The kernel is bounded,
+ * so only a coincident pair with eps == 0 is skipped. */
+void oracle_stokes_reg(int64_t ns, const double *ys, const double *fe,
+                       int64_t nt, const double *xs, double *out)
+{
+    const double c = 1.0 / (8.0 * PI);
+#pragma omp parallel for schedule(dynamic, 16) if (nt * ns > 200000)
+    for (int64_t t = 0; t < nt; ++t) {
+        double u0 = 0, u1 = 0, u2 = 0;
+        for (int64_t s = 0; s < ns; ++s) {
+            double r0 = xs[3*t] - ys[3*s], r1 = xs[3*t+1] - ys[3*s+1], r2 = xs[3*t+2] - ys[3*s+2];
+            double rr = r0*r0 + r1*r1 + r2*r2;
+            const double *fs = fe + 4*s;
+            double e2 = fs[3] * fs[3];
+            double d = rr + e2;
+            if (d == 0.0) continue;
+            double d32 = d * sqrt(d);
+            double h1 = (rr + 2.0 * e2) / d32, h2 = 1.0 / d32;
+            double rf = r0*fs[0] + r1*fs[1] + r2*fs[2];
+            u0 += h1*fs[0] + h2*rf*r0;
+            u1 += h1*fs[1] + h2*rf*r1;
+            u2 += h1*fs[2] + h2*rf*r2;
         }
         out[3*t] = c*u0; out[3*t+1] = c*u1; out[3*t+2] = c*u2;
     }

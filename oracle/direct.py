@@ -29,7 +29,7 @@ def lib():
     if _lib is None:
         path = _build.build()
         _lib = ctypes.CDLL(path)
-        for name in ("oracle_stokeslet", "oracle_rpy"):
+        for name in ("oracle_stokeslet", "oracle_rpy", "oracle_stokes_reg"):
             getattr(_lib, name).argtypes = [_i64, _dp, _dp, _i64, _dp, _dp]
         _lib.oracle_laplace.argtypes = [_i64, _dp, _dp, _i64, _dp, _dp, _i64, _dp, _dp, ctypes.c_int]
         for name in ("oracle_pvel", "oracle_traction"):
@@ -75,6 +75,16 @@ def rpy(src, fb, trg):
     return out
 
 
+def stokes_reg(src, fe, trg):
+    """Regularized Stokeslet [f, eps] -> u (Sec. II.B, tab:ktab_reg)."""
+    src, ns = _arr(src, 3)
+    fe, _ = _arr(fe, 4)
+    trg, nt = _arr(trg, 3)
+    out = np.zeros((nt, 3))
+    lib().oracle_stokes_reg(ns, _p(src), _p(fe), nt, _p(trg), _p(out))
+    return out
+
+
 def laplace(sl=None, q=None, dl=None, d=None, trg=None, hess=False):
     sl, nsl = _arr(sl, 3)
     q, _ = _arr(q)
@@ -114,6 +124,8 @@ def evaluate(kernel, sl=None, sl_val=None, dl=None, dl_val=None, trg=None):
         return stokeslet(sl, sl_val, trg)
     if kernel == "RPY":
         return rpy(sl, sl_val, trg)
+    if kernel == "StokesRegVel":
+        return stokes_reg(sl, sl_val, trg)
     if kernel == "LapPGrad":
         return laplace(sl, sl_val, dl, dl_val, trg)
     if kernel == "LapPGradGrad":

@@ -165,6 +165,77 @@ def test_rpy_operator_identity_and_far_field():
     assert errs[1] / errs[2] == pytest.approx(4.0, rel=1e-6)
 
 
+# ---------------------------------------------------------------- regularized Stokeslet
+def test_stokes_reg_eps0_is_stokeslet():
+    y, f = _pts(6), RNG.standard_normal((6, 3))
+    x = _probe()
+    out = direct.stokes_reg(y, np.concatenate([f, np.zeros((6, 1))], 1), x)
+    assert np.allclose(out, direct.stokeslet(y, f, x), rtol=1e-14, atol=1e-15)
+
+
+def test_stokes_reg_far_field_is_rpy_with_matching_radius():
+    # for r >> eps: G^eps = G + (eps^2/2) (delta/r^3 - 3 r r/r^5)/(8 pi) + O(eps^4/r^5),
+    # i.e. the RPY far field with b^2 = 3 eps^2/2
+    one = np.array([[0.0, 0, 0]])
+    f = np.array([[0.4, -1.0, 0.6]])
+    eps = 0.01
+    fe = np.concatenate([f, [[eps]]], 1)
+    fb = np.concatenate([f, [[np.sqrt(1.5) * eps]]], 1)
+    rel = []
+    for R in (0.1, 0.2, 0.4):
+        x = np.array([[R, -0.4 * R, 0.7 * R]])
+        ue = direct.stokes_reg(one, fe, x)
+        rest = ue - direct.rpy(one, fb, x)[:, :3]
+        rel.append(np.linalg.norm(rest) / np.linalg.norm(ue - direct.stokeslet(one, f, x)))
+    # the remainder relative to the eps^2 term falls like (eps/r)^2
+    assert rel[0] < 0.05
+    assert rel[0] / rel[1] == pytest.approx(4.0, rel=2e-2)
+    assert rel[1] / rel[2] == pytest.approx(4.0, rel=2e-2)
+
+
+def test_stokes_reg_solves_stokes_with_the_blob_force():
+    # u = G^eps f is the Stokes flow of the force density psi^eps f with the
+    # blob psi^eps = 15 eps^4 / (8 pi (r^2+eps^2)^(7/2)) (Sec. II.B): div u = 0
+    # and lap u - grad p + psi^eps f = 0, with the pressure of this blob
+    # p = (f.r)(2 r^2 + 5 eps^2) / (8 pi (r^2+eps^2)^(5/2)), checked inside the blob core
+    y = np.array([[0.05, -0.02, 0.03]])
+    f = np.array([[0.3, 0.8, -0.5]])
+    eps = 0.2
+    fe = np.concatenate([f, [[eps]]], 1)
+    x = y + np.array([[0.1, 0.05, -0.08], [-0.15, 0.2, 0.1], [0.3, -0.1, 0.25], [0.02, 0.01, -0.03]])
+    u = lambda xx: direct.stokes_reg(y, fe, xx)
+
+    def p(xx):
+        r = xx - y
+        rr = np.sum(r * r, axis=1)
+        return ((r @ f[0]) * (2 * rr + 5 * eps ** 2) / (8 * np.pi * (rr + eps ** 2) ** 2.5))[:, None]
+
+    J = _fd.grad(u, x, h=1e-3)
+    # the 4th-order difference error here is ~h^4 |u^(5)| ~ 1e-9 of |grad u|
+    assert np.max(np.abs(np.trace(J, axis1=1, axis2=2))) < 1e-8 * np.max(np.abs(J))
+    lap = _fd.laplacian(u, x, h=1e-3)
+    gp = _fd.grad(p, x, h=1e-3)[:, 0, :]
+    rr = np.sum((x - y) ** 2, axis=1)
+    psi = 15 * eps ** 4 / (8 * np.pi * (rr + eps ** 2) ** 3.5)
+    resid = lap - gp + psi[:, None] * f
+    assert np.max(np.abs(resid)) < 1e-7 * np.max(np.abs(psi[:, None] * f))
+
+
+def test_stokes_reg_reciprocity_and_bounded_self_term():
+    ya, fa = _pts(5), RNG.standard_normal((5, 3))
+    yb, fb = _pts(4, 0.5, 0.9), RNG.standard_normal((4, 3))
+    e = 0.05
+    ea = np.concatenate([fa, np.full((5, 1), e)], 1)
+    eb = np.concatenate([fb, np.full((4, 1), e)], 1)
+    lhs = np.sum(fb * direct.stokes_reg(ya, ea, yb))
+    rhs = np.sum(fa * direct.stokes_reg(yb, eb, ya))
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+    # a coincident pair with eps > 0 is finite: u = f / (4 pi eps)
+    one = np.array([[0.2, 0.3, 0.4]])
+    got = direct.stokes_reg(one, np.array([[1.0, -2.0, 0.5, e]]), one)
+    assert np.allclose(got, np.array([[1.0, -2.0, 0.5]]) / (4 * np.pi * e), rtol=1e-14)
+
+
 # ---------------------------------------------------------------- double layer / PVel
 def test_double_layer_net_flux():
     # flux of u out of any sphere around a double-layer source = -tr(D)/2 (Sec. II.C)
