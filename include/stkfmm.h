@@ -58,6 +58,10 @@ typedef enum {
  *   RPY            [f, b] -> [u, lap u]        f,b (4)   --       (u, lap u) (6)
  *   PVEL           [f, q], D -> [p, u]         f,q (4)   D (9)    (p, u) (4)
  *   TRACTION       [f, q], D -> sigma          f,q (4)   D (9)    sigma (9)
+ *   STOKES_REG_VEL [f, eps] -> u               f,eps (4) --       u (3)
+ * STOKES_REG_VEL is the regularized Stokeslet of the blob psi^eps (Sec. II.B,
+ * tab:ktab_reg), eps >= 0 per source; its far field is represented to
+ * O((eps/r)^4), so eps must be far smaller than the smallest leaf box.
  * D and sigma are row-major 3x3 (D[3j+k] = D_jk, sigma[3i+j]); q in PVEL and
  * TRACTION is twice the physical source (Sec. II.C); viscosity mu = 1. */
 typedef enum {
@@ -65,7 +69,8 @@ typedef enum {
     STKFMM_STOKESLET = 1,
     STKFMM_RPY = 2,
     STKFMM_PVEL = 3,
-    STKFMM_TRACTION = 4
+    STKFMM_TRACTION = 4,
+    STKFMM_STOKES_REG_VEL = 5
 } stkfmm_kernel;
 
 /* Boundary conditions (Sec. III and its appendix on periodicity).  PXYZ is

@@ -36,6 +36,7 @@ static const KernelInfo kInfo[kNumKernels] = {
     {4, 0, 6, 4, 12, 0, 6},    // RPY
     {4, 9, 4, 4, 12, 12, 4},   // PVel
     {4, 9, 9, 4, 12, 12, 6},   // Traction
+    {4, 0, 3, 4, 12, 0, 3},    // StokesRegVel
 };
 const KernelInfo &kernel_info(int k) { return kInfo[k]; }
 
@@ -177,15 +178,19 @@ stkfmm_status fail(stkfmm_ctx *c, stkfmm_status s, const std::string &msg) {
 
 bool kernel_ok(int k) { return k >= 0 && k < kNumKernels; }
 
-// source kinds of the packing and staging kernels
+// source kinds of the packing kernel; stage_kind: of the surface tiles
 int sl_kind(int k) {
     switch (k) {
         case kStokeslet: return 0;
         case kRPY: return 1;
         case kLapPGrad: return 2;
+        case kStokesRegVel: return 6;
         default: return 4;
     }
 }
+// The regularized Stokeslet's far field is the RPY one with b^2 = 3 eps^2 / 2
+// (to O(eps^4 / r^5)): its packed records carry that b^2 where RPY's do.
+int stage_kind(int k) { return k == kStokesRegVel ? 1 : sl_kind(k); }
 int dl_kind(int k) { return k == kLapPGrad ? 3 : 5; }
 
 stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, DeviceOps **out) {
@@ -1021,7 +1026,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     HIP_TRY(c, c->near_part.ensure(size_t(std::max(c->n_p2p_tasks, 1)) * 256 * ki.kt_acc * sizeof(double)));
     HIP_TRY(c, c->far_part.ensure(size_t(std::max(c->n_l2t_tasks, 1)) * 256 * ki.kt_acc * sizeof(double)));
     HIP_TRY(c, c->s2c_part.ensure(std::max<size_t>(s2c_tasks_max, 1) * nc * M * sizeof(float)));
-    HIP_TRY(c, c->sl_stage.ensure(size_t(std::max<int64_t>(n_sl, 1)) * s2c_stage_stride(sl_kind(kernel)) *
+    HIP_TRY(c, c->sl_stage.ensure(size_t(std::max<int64_t>(n_sl, 1)) * s2c_stage_stride(stage_kind(kernel)) *
                                   sizeof(float)));
     HIP_TRY(c, c->dl_stage.ensure(size_t(std::max<int64_t>(n_dl, 1)) * s2c_stage_stride(dl_kind(kernel)) *
                                   sizeof(float)));
@@ -1032,10 +1037,10 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     // source/target positions in leaf order
     const double3 org = make_double3(c->origin[0], c->origin[1], c->origin[2]);
     const double inv = 1.0 / c->box_len;
-    HIP_TRY(c, launch_pack_sources(n_sl, sl_xyz, nullptr, at<int32_t>(c, c->a_perm_sl), org, inv, -1, ki.rec_sl,
+    HIP_TRY(c, launch_pack_sources(n_sl, sl_xyz, at<int32_t>(c, c->a_perm_sl), org, inv, ki.rec_sl,
                                    c->sl_rec.as<float>(), s));
-    HIP_TRY(c, launch_pack_sources(n_dl, dl_xyz, nullptr, at<int32_t>(c, c->a_perm_dl), org, inv, -1,
-                                   std::max(ki.rec_dl, 8), c->dl_rec.as<float>(), s));
+    HIP_TRY(c, launch_pack_sources(n_dl, dl_xyz, at<int32_t>(c, c->a_perm_dl), org, inv, std::max(ki.rec_dl, 8),
+                                   c->dl_rec.as<float>(), s));
     HIP_TRY(c, launch_pack_targets(n_trg, trg_xyz, at<int32_t>(c, c->a_perm_trg), org, inv, c->trg_rec.as<float>(), s));
     if (p2p_uses_rel(c->kernel))
         HIP_TRY(c, launch_rel_positions(c->n_leaves_sl, at<int>(c, c->a_leaves_sl), at<int2>(c, c->a_box_sl),
@@ -1060,6 +1065,7 @@ CombineMap combine_map(int k, double L) {
     const double c4 = 1.0 / (4.0 * kPi), c8 = 1.0 / (8.0 * kPi);
     switch (k) {
         case kStokeslet:
+        case kStokesRegVel:
             for (int i = 0; i < 3; ++i) m.src[i] = i, m.scale[i] = c8 / L;
             break;
         case kRPY:
@@ -1120,6 +1126,14 @@ __global__ void pack_values_kernel(int64_t n, const double *__restrict__ val, co
             o[9] = float(D[4] * inv_len);
             o[10] = float(0.5 * (D[5] + D[7]) * inv_len);
             o[11] = float(D[8] * inv_len);
+            break;
+        }
+        case 6: {   // regularized Stokeslet: f, then (3/2) eps^2 (far field) and eps^2 (P2P)
+            const double *v = val + 4 * j;
+            const double e = v[3] * inv_len;
+            o[6] = float(v[0]); o[7] = float(v[1]); o[8] = float(v[2]);
+            o[9] = float(1.5 * e * e);
+            o[10] = float(e * e);
             break;
         }
     }
@@ -1231,7 +1245,7 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         a.alpha = alpha;
         a.part = c->s2c_part.as<float>();
         a.staged = c->sl_stage.as<float>();
-        hipError_t e = launch_s2c(sl_kind(c->kernel), ph.n_sl, a, s);
+        hipError_t e = launch_s2c(stage_kind(c->kernel), ph.n_sl, a, s);
         if (e != hipSuccess) return e;
         if (ph.n_dl > 0) {
             a.tasks = at<int4>(c, ph.tasks) + ph.n_sl;
@@ -1253,7 +1267,7 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
     };
     if (far) {
         // sources staged relative to their leaf centres (read by S2M and S2L)
-        HIP_TRY(c, launch_stage_sources(sl_kind(c->kernel), c->n_leaves_sl, at<int>(c, c->a_leaves_sl),
+        HIP_TRY(c, launch_stage_sources(stage_kind(c->kernel), c->n_leaves_sl, at<int>(c, c->a_leaves_sl),
                                         at<int2>(c, c->a_box_sl), at<double4>(c, c->a_geom), c->sl_rec.as<float>(),
                                         ki.rec_sl, c->sl_stage.as<float>(), s));
         if (c->n_dl > 0)
@@ -1395,7 +1409,7 @@ stkfmm_status sampled_error(stkfmm_ctx *c, const double *sl_val, const double *d
     HIP_TRY(c, hipMemcpyAsync(ref.data(), c->vbuf[3].p, ref.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     // output fields: (u), (u, lap u), (phi, grad phi), (p, u), (sigma)
-    static const int fields[kNumKernels][3] = {{0, 1, 4}, {0, 3, 3}, {0, 3, 6}, {0, 1, 4}, {0, 9, 9}};
+    static const int fields[kNumKernels][3] = {{0, 1, 4}, {0, 3, 3}, {0, 3, 6}, {0, 1, 4}, {0, 9, 9}, {0, 3, 3}};
     const int *fb = fields[c->kernel];
     double worst = 0.0;
     for (int f = 0; f < 2; ++f) {

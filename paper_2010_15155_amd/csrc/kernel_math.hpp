@@ -6,6 +6,8 @@
 //
 // Direct (S->T) kernels, with their definitions:
 //   Stokeslet   u  = (f/r + r (r.f)/r^3)                            [x 1/8pi] Sec. II.B
+//   RegStokeslet u = H1 f + H2 r (r.f), s = r^2 + eps^2, H1 = (r^2 + 2 eps^2)/s^(3/2),
+//               H2 = 1/s^(3/2)                                      [x 1/8pi] Sec. II.B
 //   RPY         u  = (1/r + b^2/(3 r^3)) f + (1/r^3 - b^2/r^5) r (r.f)
 //               lap u = 2 f/r^3 - 6 r (r.f)/r^5                     [x 1/8pi] Eq. RPYkernel
 //   Laplace     phi = q/r + d.r/r^3, grad phi = -q r/r^3 + d/r^3 - 3 (d.r) r/r^5
@@ -64,6 +66,25 @@ struct DStokeslet {       // SL f0 f1 f2 ; leaf-relative position at 9..11
         a[0] = fmaf(ri, fmaf(dx, q, v[0]), a[0]);
         a[1] = fmaf(ri, fmaf(dy, q, v[1]), a[1]);
         a[2] = fmaf(ri, fmaf(dz, q, v[2]), a[2]);
+    }
+    __device__ static void dl(float, float, float, float, const float *, float *) {}
+};
+
+struct DStokesReg {       // SL f0 f1 f2, (3/2) eps^2, eps^2
+    static constexpr int RS = 12, RD = 0, NACC = 3;
+    static constexpr bool REL = false;
+    // u = H1 f + H2 (r.f) r with s = r^2 + eps^2: H1 = (s + eps^2)/s^(3/2),
+    // H2 = 1/s^(3/2)  (the ri argument is unused: s replaces r^2)
+    __device__ static void sl(float dx, float dy, float dz, float, const float *v, float *a) {
+        const float e2 = v[4];
+        const float s = dot3(dx, dy, dz, dx, dy, dz) + e2;
+        const float ri = rsq_or_zero(s);
+        const float h2 = ri * ri * ri;
+        const float h1 = (s + e2) * h2;
+        const float t = dot3(dx, dy, dz, v[0], v[1], v[2]) * h2;
+        a[0] = fmaf(dx, t, fmaf(h1, v[0], a[0]));
+        a[1] = fmaf(dy, t, fmaf(h1, v[1], a[1]));
+        a[2] = fmaf(dz, t, fmaf(h1, v[2], a[2]));
     }
     __device__ static void dl(float, float, float, float, const float *, float *) {}
 };

@@ -42,10 +42,10 @@ __global__ void fill_f32(float *p, int64_t n, float v) {
 }
 
 // ------------------------------------------------------------------ packing
-// kind: 0 Stokeslet f, 1 RPY f,b, 2 Laplace q, 3 Laplace d, 4 Stokes f,q, 5 Stokes D (9 -> sym 6)
-__global__ void pack_sources(int64_t n, const double *__restrict__ xyz, const double *__restrict__ val,
-                             const int32_t *__restrict__ perm, double3 origin, double inv_len,
-                             int kind, int rec, float *__restrict__ out) {
+// Leaf-sorted source positions (hi/lo FP32 of the normalised FP64 value);
+// value slots are zeroed here and written by each run's value packing.
+__global__ void pack_sources(int64_t n, const double *__restrict__ xyz, const int32_t *__restrict__ perm,
+                             double3 origin, double inv_len, int rec, float *__restrict__ out) {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t j = perm[i];
@@ -60,42 +60,6 @@ __global__ void pack_sources(int64_t n, const double *__restrict__ xyz, const do
         o[3 + k] = float(w - double(h));
     }
     for (int k = 6; k < rec; ++k) o[k] = 0.0f;
-    if (val == nullptr) return;
-    switch (kind) {
-        case 0: {
-            const double *v = val + 3 * j;
-            o[6] = float(v[0]); o[7] = float(v[1]); o[8] = float(v[2]);
-            break;
-        }
-        case 1: {
-            const double *v = val + 4 * j;
-            double b = v[3] * inv_len;
-            o[6] = float(v[0]); o[7] = float(v[1]); o[8] = float(v[2]); o[9] = float(b * b);
-            break;
-        }
-        case 2: o[6] = float(val[j]); break;
-        case 3: {
-            const double *v = val + 3 * j;
-            o[6] = float(v[0] * inv_len); o[7] = float(v[1] * inv_len); o[8] = float(v[2] * inv_len);
-            break;
-        }
-        case 4: {
-            const double *v = val + 4 * j;
-            o[6] = float(v[0]); o[7] = float(v[1]); o[8] = float(v[2]); o[9] = float(v[3]);
-            break;
-        }
-        case 5: {
-            const double *D = val + 9 * j;
-            double s = inv_len;
-            o[6] = float(D[0] * s);
-            o[7] = float(0.5 * (D[1] + D[3]) * s);
-            o[8] = float(0.5 * (D[2] + D[6]) * s);
-            o[9] = float(D[4] * s);
-            o[10] = float(0.5 * (D[5] + D[7]) * s);
-            o[11] = float(D[8] * s);
-            break;
-        }
-    }
 }
 
 __global__ void pack_targets(int64_t n, const double *__restrict__ xyz, const int32_t *__restrict__ perm,
@@ -1013,6 +977,16 @@ struct F64Stokeslet {
         for (int i = 0; i < 3; ++i) a[i] += kInv8Pi * (v[i] * ri + r[i] * rf * ri3);
     }
 };
+struct F64StokesReg {     // v = f, eps
+    __device__ static void pair(int, const double *r, const double *v, double *a) {
+        const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const double e2 = v[3] * v[3], s = rr + e2;
+        if (s == 0.0) return;
+        const double h2 = 1.0 / (s * sqrt(s)), h1 = (rr + 2.0 * e2) * h2;
+        const double rf = r[0] * v[0] + r[1] * v[1] + r[2] * v[2];
+        for (int i = 0; i < 3; ++i) a[i] += kInv8Pi * (h1 * v[i] + h2 * rf * r[i]);
+    }
+};
 struct F64RPY {
     __device__ static void pair(int, const double *r, const double *v, double *a) {
         double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
@@ -1100,11 +1074,11 @@ hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_pack_sources(int64_t n, const double *xyz, const double *val, const int32_t *perm,
-                               double3 origin, double inv_len, int kind, int rec, float *out, hipStream_t s) {
+hipError_t launch_pack_sources(int64_t n, const double *xyz, const int32_t *perm, double3 origin, double inv_len,
+                               int rec, float *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(pack_sources, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, xyz, val, perm, origin,
-                       inv_len, kind, rec, out);
+    hipLaunchKernelGGL(pack_sources, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, xyz, perm, origin, inv_len, rec,
+                       out);
     return hipGetLastError();
 }
 
@@ -1124,6 +1098,7 @@ hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, hipStream_t s) {
         case kLapPGrad: hipLaunchKernelGGL(p2p_kernel<DLapPGrad>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kPVel: hipLaunchKernelGGL(p2p_kernel<DPVel>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kTraction: hipLaunchKernelGGL(p2p_kernel<DTraction>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kStokesRegVel: hipLaunchKernelGGL(p2p_kernel<DStokesReg>, dim3(ntasks), dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1253,6 +1228,7 @@ hipError_t launch_l2t(int kernel, int ntasks, const L2TArgs &a, hipStream_t s) {
         case kLapPGrad: hipLaunchKernelGGL(l2t_kernel<ELapPGrad>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kPVel: hipLaunchKernelGGL(l2t_kernel<EPVel>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kTraction: hipLaunchKernelGGL(l2t_kernel<ETraction>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kStokesRegVel: hipLaunchKernelGGL(l2t_kernel<EStokeslet>, dim3(ntasks), dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1287,6 +1263,7 @@ hipError_t launch_direct_f64(int kernel, const DirectArgs &a, hipStream_t s) {
         case kLapPGrad: hipLaunchKernelGGL(direct_f64_kernel<F64Lap>, g, dim3(256), 0, s, a); break;
         case kPVel: hipLaunchKernelGGL(direct_f64_kernel<F64PVel>, g, dim3(256), 0, s, a); break;
         case kTraction: hipLaunchKernelGGL(direct_f64_kernel<F64Traction>, g, dim3(256), 0, s, a); break;
+        case kStokesRegVel: hipLaunchKernelGGL(direct_f64_kernel<F64StokesReg>, g, dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     if (a.slices > 1) {
@@ -1303,6 +1280,7 @@ bool p2p_uses_rel(int kernel) {
         case kLapPGrad: return DLapPGrad::REL;
         case kPVel: return DPVel::REL;
         case kTraction: return DTraction::REL;
+        case kStokesRegVel: return DStokesReg::REL;
         default: return false;
     }
 }

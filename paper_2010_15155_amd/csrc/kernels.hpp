@@ -126,8 +126,8 @@ struct DirectArgs {
 
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t s);
-hipError_t launch_pack_sources(int64_t n, const double *xyz, const double *val, const int32_t *perm,
-                               double3 origin, double inv_len, int kind, int rec, float *out, hipStream_t s);
+hipError_t launch_pack_sources(int64_t n, const double *xyz, const int32_t *perm, double3 origin, double inv_len,
+                               int rec, float *out, hipStream_t s);
 hipError_t launch_pack_targets(int64_t n, const double *xyz, const int32_t *perm, double3 origin,
                                double inv_len, float *out, hipStream_t s);
 hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, hipStream_t s);

@@ -16,8 +16,8 @@ from paper_2010_15155_amd import workloads as W
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-KERNELS = ["Stokeslet", "RPY", "LapPGrad", "PVel", "Traction"]
-FIELDS = {"Stokeslet": [("u", 0, 3)], "RPY": [("u", 0, 3), ("lap u", 3, 6)],
+KERNELS = ["Stokeslet", "RPY", "LapPGrad", "PVel", "Traction", "StokesRegVel"]
+FIELDS = {"Stokeslet": [("u", 0, 3)], "RPY": [("u", 0, 3), ("lap u", 3, 6)], "StokesRegVel": [("u", 0, 3)],
           "LapPGrad": [("phi", 0, 1), ("grad phi", 1, 4)], "PVel": [("p", 0, 1), ("u", 1, 4)],
           "Traction": [("sigma", 0, 9)]}
 
@@ -45,6 +45,10 @@ def problem(kernel, n, seed, clustered=True):
         return dict(sl_xyz=x, sl_val=rng.standard_normal((n, 3)), trg_xyz=x)
     if kernel == "RPY":
         v = np.concatenate([rng.standard_normal((n, 3)), rng.uniform(0.002, 0.005, (n, 1))], 1)
+        return dict(sl_xyz=x, sl_val=v, trg_xyz=x)
+    if kernel == "StokesRegVel":
+        # blobs far smaller than the smallest leaf (tab:ktab_reg)
+        v = np.concatenate([rng.standard_normal((n, 3)), rng.uniform(1e-4, 1e-3, (n, 1))], 1)
         return dict(sl_xyz=x, sl_val=v, trg_xyz=x)
     if kernel == "LapPGrad":
         return dict(sl_xyz=x, sl_val=rng.standard_normal((n, 1)), dl_xyz=x,
