@@ -19,6 +19,7 @@
  *   regularized Stokeslet G^eps = H1(r) delta + H2(r) r r^T,
  *     H1 = (r^2 + 2 eps^2)/(8 pi (r^2+eps^2)^(3/2)), H2 = 1/(8 pi (r^2+eps^2)^(3/2))
  *                                                             Sec. II.B, tab:ktab_reg
+ *   regularized force + torque -> [u, omega]                  Sec. II.B, tab:ktab_regftvw
  *   StokesPVel [f,q] -> [p,u]                                 Sec. II.C, Eqs. stkslp, stkslvel
  *   Stokes double layer D -> [p,u], T_ijk = -3 r_i r_j r_k/(8 pi r^5)
  *                                                             Sec. II.C, Eqs. stkdlp, stkdlvel
@@ -79,6 +80,50 @@ void oracle_stokes_reg(int64_t ns, const double *ys, const double *fe,
             u2 += h1*fs[2] + h2*rf*r2;
         }
         out[3*t] = c*u0; out[3*t+1] = c*u1; out[3*t+2] = c*u2;
+    }
+}
+
+/* Regularized force and torque: (f1,f2,f3,t1,t2,t3,eps) (7) -> (u, omega) (6),
+ * u = G^eps f + T^eps t, omega = Omega^eps f + W^eps t with
+ *   G^eps_ij = H1 delta_ij + H2 r_i r_j,   Omega^eps_ij = T^eps_ij = Q eps_ijk r_k / 2,
+ *   W^eps_ij = (D1 delta_ij + D2 r_i r_j) / 4, s = r^2 + eps^2 and
+ *   H1 = (r^2 + 2 eps^2)/(8 pi s^(3/2)), H2 = 1/(8 pi s^(3/2)),
+ *   Q = (2 r^2 + 5 eps^2)/(8 pi s^(5/2)),
+ *   D1 = (10 eps^4 - 7 eps^2 r^2 - 2 r^4)/(8 pi s^(7/2)), D2 = (21 eps^2 + 6 r^2)/(8 pi s^(7/2))
+ * (Sec. II.B, the force-torque extension).  eps_ijk r_k a_j = (a x r)_i. */
+void oracle_stokes_reg_ft(int64_t ns, const double *ys, const double *fte,
+                          int64_t nt, const double *xs, double *out)
+{
+    const double c = 1.0 / (8.0 * PI);
+#pragma omp parallel for schedule(dynamic, 16) if (nt * ns > 200000)
+    for (int64_t t = 0; t < nt; ++t) {
+        double u[3] = {0, 0, 0}, w[3] = {0, 0, 0};
+        for (int64_t s = 0; s < ns; ++s) {
+            double r[3] = {xs[3*t] - ys[3*s], xs[3*t+1] - ys[3*s+1], xs[3*t+2] - ys[3*s+2]};
+            double rr = r[0]*r[0] + r[1]*r[1] + r[2]*r[2];
+            const double *v = fte + 7*s;
+            const double *f = v, *tq = v + 3;
+            double e2 = v[6] * v[6];
+            double d = rr + e2;
+            if (d == 0.0) continue;
+            double sq = sqrt(d), d3 = d * sq, d5 = d3 * d, d7 = d5 * d;
+            double h1 = (rr + 2.0 * e2) / d3, h2 = 1.0 / d3;
+            double q = (2.0 * rr + 5.0 * e2) / d5;
+            double D1 = (10.0 * e2 * e2 - 7.0 * e2 * rr - 2.0 * rr * rr) / d7;
+            double D2 = (21.0 * e2 + 6.0 * rr) / d7;
+            double rf = r[0]*f[0] + r[1]*f[1] + r[2]*f[2];
+            double rt = r[0]*tq[0] + r[1]*tq[1] + r[2]*tq[2];
+            double txr[3] = {tq[1]*r[2] - tq[2]*r[1], tq[2]*r[0] - tq[0]*r[2], tq[0]*r[1] - tq[1]*r[0]};
+            double fxr[3] = {f[1]*r[2] - f[2]*r[1], f[2]*r[0] - f[0]*r[2], f[0]*r[1] - f[1]*r[0]};
+            for (int i = 0; i < 3; ++i) {
+                u[i] += h1 * f[i] + h2 * rf * r[i] + 0.5 * q * txr[i];
+                w[i] += 0.5 * q * fxr[i] + 0.25 * (D1 * tq[i] + D2 * rt * r[i]);
+            }
+        }
+        for (int i = 0; i < 3; ++i) {
+            out[6*t + i] = c * u[i];
+            out[6*t + 3 + i] = c * w[i];
+        }
     }
 }
 

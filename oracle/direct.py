@@ -29,7 +29,7 @@ def lib():
     if _lib is None:
         path = _build.build()
         _lib = ctypes.CDLL(path)
-        for name in ("oracle_stokeslet", "oracle_rpy", "oracle_stokes_reg"):
+        for name in ("oracle_stokeslet", "oracle_rpy", "oracle_stokes_reg", "oracle_stokes_reg_ft"):
             getattr(_lib, name).argtypes = [_i64, _dp, _dp, _i64, _dp, _dp]
         _lib.oracle_laplace.argtypes = [_i64, _dp, _dp, _i64, _dp, _dp, _i64, _dp, _dp, ctypes.c_int]
         for name in ("oracle_pvel", "oracle_traction"):
@@ -85,6 +85,16 @@ def stokes_reg(src, fe, trg):
     return out
 
 
+def stokes_reg_ft(src, fte, trg):
+    """Regularized force and torque [f, t, eps] -> [u, omega] (Sec. II.B)."""
+    src, ns = _arr(src, 3)
+    fte, _ = _arr(fte, 7)
+    trg, nt = _arr(trg, 3)
+    out = np.zeros((nt, 6))
+    lib().oracle_stokes_reg_ft(ns, _p(src), _p(fte), nt, _p(trg), _p(out))
+    return out
+
+
 def laplace(sl=None, q=None, dl=None, d=None, trg=None, hess=False):
     sl, nsl = _arr(sl, 3)
     q, _ = _arr(q)
@@ -126,6 +136,8 @@ def evaluate(kernel, sl=None, sl_val=None, dl=None, dl_val=None, trg=None):
         return rpy(sl, sl_val, trg)
     if kernel == "StokesRegVel":
         return stokes_reg(sl, sl_val, trg)
+    if kernel == "StokesRegVelOmega":
+        return stokes_reg_ft(sl, sl_val, trg)
     if kernel == "LapPGrad":
         return laplace(sl, sl_val, dl, dl_val, trg)
     if kernel == "LapPGradGrad":

@@ -236,6 +236,43 @@ def test_stokes_reg_reciprocity_and_bounded_self_term():
     assert np.allclose(got, np.array([[1.0, -2.0, 0.5]]) / (4 * np.pi * e), rtol=1e-14)
 
 
+def _curl(fun, x, h=1e-3):
+    J = _fd.grad(fun, x, h=h)            # J[n, i, l] = d u_i / d x_l
+    return np.stack([J[:, 2, 1] - J[:, 1, 2], J[:, 0, 2] - J[:, 2, 0], J[:, 1, 0] - J[:, 0, 1]], 1)
+
+
+def test_stokes_reg_ft_parts():
+    # force part = regularized Stokeslet; torque velocity = (1/2) curl of the
+    # regularized Stokeslet of the torque (the regularized rotlet); angular
+    # velocity = (1/2) curl u of the whole field (force and torque parts)
+    y = _pts(4)
+    f, t = RNG.standard_normal((4, 3)), RNG.standard_normal((4, 3))
+    eps = RNG.uniform(0.05, 0.2, 4)
+    x = _probe()
+    fe = np.concatenate([f, eps[:, None]], 1)
+    te = np.concatenate([t, eps[:, None]], 1)
+    only_f = direct.stokes_reg_ft(y, np.concatenate([f, 0 * t, eps[:, None]], 1), x)
+    assert np.allclose(only_f[:, :3], direct.stokes_reg(y, fe, x), rtol=1e-14, atol=1e-15)
+    only_t = direct.stokes_reg_ft(y, np.concatenate([0 * f, t, eps[:, None]], 1), x)
+    rot = 0.5 * _curl(lambda xx: direct.stokes_reg(y, te, xx), x)
+    assert np.allclose(only_t[:, :3], rot, rtol=1e-7, atol=1e-9 * np.abs(rot).max())
+    fte = np.concatenate([f, t, eps[:, None]], 1)
+    both = direct.stokes_reg_ft(y, fte, x)
+    w = 0.5 * _curl(lambda xx: direct.stokes_reg_ft(y, fte, xx)[:, :3], x)
+    assert np.allclose(both[:, 3:], w, rtol=1e-7, atol=1e-9 * np.abs(w).max())
+    assert np.allclose(both, only_f + only_t, rtol=1e-13, atol=1e-15)
+
+
+def test_stokes_reg_ft_eps0_rotlet():
+    y, t = _pts(3), RNG.standard_normal((3, 3))
+    x = _probe()
+    out = direct.stokes_reg_ft(y, np.concatenate([0 * t, t, np.zeros((3, 1))], 1), x)
+    r = x[:, None, :] - y[None, :, :]
+    rn = np.linalg.norm(r, axis=2)
+    expect = np.sum(np.cross(t[None, :, :], r) / rn[:, :, None] ** 3, axis=1) / (8 * np.pi)
+    assert np.allclose(out[:, :3], expect, rtol=1e-13, atol=1e-15)
+
+
 # ---------------------------------------------------------------- double layer / PVel
 def test_double_layer_net_flux():
     # flux of u out of any sphere around a double-layer source = -tr(D)/2 (Sec. II.C)
