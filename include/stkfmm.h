@@ -59,9 +59,12 @@ typedef enum {
  *   PVEL           [f, q], D -> [p, u]         f,q (4)   D (9)    (p, u) (4)
  *   TRACTION       [f, q], D -> sigma          f,q (4)   D (9)    sigma (9)
  *   STOKES_REG_VEL [f, eps] -> u               f,eps (4) --       u (3)
+ *   STOKES_REG_VEL_OMEGA [f, t, eps] -> [u, w] f,t,eps (7) --     (u, angular velocity) (6)
  * STOKES_REG_VEL is the regularized Stokeslet of the blob psi^eps (Sec. II.B,
  * tab:ktab_reg), eps >= 0 per source; its far field is represented to
  * O((eps/r)^4), so eps must be far smaller than the smallest leaf box.
+ * STOKES_REG_VEL_OMEGA adds point torques t and the angular velocity
+ * w = curl(u)/2 (the force-torque extension of Sec. II.B, tab:ktab_regftvw).
  * D and sigma are row-major 3x3 (D[3j+k] = D_jk, sigma[3i+j]); q in PVEL and
  * TRACTION is twice the physical source (Sec. II.C); viscosity mu = 1. */
 typedef enum {
@@ -70,7 +73,8 @@ typedef enum {
     STKFMM_RPY = 2,
     STKFMM_PVEL = 3,
     STKFMM_TRACTION = 4,
-    STKFMM_STOKES_REG_VEL = 5
+    STKFMM_STOKES_REG_VEL = 5,
+    STKFMM_STOKES_REG_VEL_OMEGA = 6
 } stkfmm_kernel;
 
 /* Boundary conditions (Sec. III and its appendix on periodicity).  PXYZ is

@@ -37,6 +37,7 @@ static const KernelInfo kInfo[kNumKernels] = {
     {4, 9, 4, 4, 12, 12, 4},   // PVel
     {4, 9, 9, 4, 12, 12, 6},   // Traction
     {4, 0, 3, 4, 12, 0, 3},    // StokesRegVel
+    {7, 0, 6, 4, 16, 0, 6},    // StokesRegVelOmega
 };
 const KernelInfo &kernel_info(int k) { return kInfo[k]; }
 
@@ -185,12 +186,13 @@ int sl_kind(int k) {
         case kRPY: return 1;
         case kLapPGrad: return 2;
         case kStokesRegVel: return 6;
+        case kStokesRegVelOmega: return 7;
         default: return 4;
     }
 }
 // The regularized Stokeslet's far field is the RPY one with b^2 = 3 eps^2 / 2
 // (to O(eps^4 / r^5)): its packed records carry that b^2 where RPY's do.
-int stage_kind(int k) { return k == kStokesRegVel ? 1 : sl_kind(k); }
+int stage_kind(int k) { return k == kStokesRegVel ? 1 : sl_kind(k); }   // kind 7 packs and stages alike
 int dl_kind(int k) { return k == kLapPGrad ? 3 : 5; }
 
 stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, DeviceOps **out) {
@@ -1068,6 +1070,10 @@ CombineMap combine_map(int k, double L) {
         case kStokesRegVel:
             for (int i = 0; i < 3; ++i) m.src[i] = i, m.scale[i] = c8 / L;
             break;
+        case kStokesRegVelOmega:
+            for (int i = 0; i < 3; ++i) m.src[i] = i, m.scale[i] = c8 / L;
+            for (int i = 3; i < 6; ++i) m.src[i] = i, m.scale[i] = c8 / (L * L);
+            break;
         case kRPY:
             for (int i = 0; i < 3; ++i) m.src[i] = i, m.scale[i] = c8 / L;
             for (int i = 3; i < 6; ++i) m.src[i] = i, m.scale[i] = c8 / (L * L * L);
@@ -1126,6 +1132,15 @@ __global__ void pack_values_kernel(int64_t n, const double *__restrict__ val, co
             o[9] = float(D[4] * inv_len);
             o[10] = float(0.5 * (D[5] + D[7]) * inv_len);
             o[11] = float(D[8] * inv_len);
+            break;
+        }
+        case 7: {   // regularized force and torque: f, t / L, (3/2) eps^2, eps^2
+            const double *v = val + 7 * j;
+            const double e = v[6] * inv_len;
+            o[6] = float(v[0]); o[7] = float(v[1]); o[8] = float(v[2]);
+            o[9] = float(v[3] * inv_len); o[10] = float(v[4] * inv_len); o[11] = float(v[5] * inv_len);
+            o[12] = float(1.5 * e * e);
+            o[13] = float(e * e);
             break;
         }
         case 6: {   // regularized Stokeslet: f, then (3/2) eps^2 (far field) and eps^2 (P2P)
@@ -1409,7 +1424,7 @@ stkfmm_status sampled_error(stkfmm_ctx *c, const double *sl_val, const double *d
     HIP_TRY(c, hipMemcpyAsync(ref.data(), c->vbuf[3].p, ref.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     // output fields: (u), (u, lap u), (phi, grad phi), (p, u), (sigma)
-    static const int fields[kNumKernels][3] = {{0, 1, 4}, {0, 3, 3}, {0, 3, 6}, {0, 1, 4}, {0, 9, 9}, {0, 3, 3}};
+    static const int fields[kNumKernels][3] = {{0, 1, 4}, {0, 3, 3}, {0, 3, 6}, {0, 1, 4}, {0, 9, 9}, {0, 3, 3}, {0, 3, 6}};
     const int *fb = fields[c->kernel];
     double worst = 0.0;
     for (int f = 0; f < 2; ++f) {

@@ -8,6 +8,8 @@
 //   Stokeslet   u  = (f/r + r (r.f)/r^3)                            [x 1/8pi] Sec. II.B
 //   RegStokeslet u = H1 f + H2 r (r.f), s = r^2 + eps^2, H1 = (r^2 + 2 eps^2)/s^(3/2),
 //               H2 = 1/s^(3/2)                                      [x 1/8pi] Sec. II.B
+//   RegStokes FT u += (Q/2) t x r, omega = (Q/2) f x r + (D1 t + D2 (r.t) r)/4
+//               (Q, D1, D2 of Sec. II.B's force-torque extension)     [x 1/8pi]
 //   RPY         u  = (1/r + b^2/(3 r^3)) f + (1/r^3 - b^2/r^5) r (r.f)
 //               lap u = 2 f/r^3 - 6 r (r.f)/r^5                     [x 1/8pi] Eq. RPYkernel
 //   Laplace     phi = q/r + d.r/r^3, grad phi = -q r/r^3 + d/r^3 - 3 (d.r) r/r^5
@@ -85,6 +87,35 @@ struct DStokesReg {       // SL f0 f1 f2, (3/2) eps^2, eps^2
         a[0] = fmaf(dx, t, fmaf(h1, v[0], a[0]));
         a[1] = fmaf(dy, t, fmaf(h1, v[1], a[1]));
         a[2] = fmaf(dz, t, fmaf(h1, v[2], a[2]));
+    }
+    __device__ static void dl(float, float, float, float, const float *, float *) {}
+};
+
+struct DStokesRegFT {     // SL f0 f1 f2 t0 t1 t2, (3/2) eps^2, eps^2     out u, omega
+    static constexpr int RS = 16, RD = 0, NACC = 6;
+    static constexpr bool REL = false;
+    // with s = r^2 + eps^2 (so r^2 + 2 eps^2 = s + eps^2, 2 r^2 + 5 eps^2 = 2 s + 3 eps^2,
+    // 10 eps^4 - 7 eps^2 r^2 - 2 r^4 = 15 eps^4 - 3 eps^2 s - 2 s^2, 21 eps^2 + 6 r^2 = 15 eps^2 + 6 s):
+    //   u     += H1 f + H2 (r.f) r + (Q/2) t x r
+    //   omega += (Q/2) f x r + (D1 t + D2 (r.t) r) / 4
+    __device__ static void sl(float dx, float dy, float dz, float, const float *v, float *a) {
+        const float e2 = v[7];
+        const float s = dot3(dx, dy, dz, dx, dy, dz) + e2;
+        const float ri = rsq_or_zero(s);
+        const float ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2, ri7 = ri5 * ri2;
+        const float h1 = (s + e2) * ri3;
+        const float hq = 0.5f * fmaf(2.0f, s, 3.0f * e2) * ri5;
+        const float d1 = 0.25f * fmaf(15.0f * e2, e2, -s * fmaf(3.0f, e2, 2.0f * s)) * ri7;
+        const float d2 = 0.25f * fmaf(6.0f, s, 15.0f * e2) * ri7;
+        const float f0 = v[0], f1 = v[1], f2 = v[2], t0 = v[3], t1 = v[4], t2 = v[5];
+        const float tu = dot3(dx, dy, dz, f0, f1, f2) * ri3;
+        const float tw = dot3(dx, dy, dz, t0, t1, t2) * d2;
+        a[0] = fmaf(hq, t1 * dz - t2 * dy, fmaf(dx, tu, fmaf(h1, f0, a[0])));
+        a[1] = fmaf(hq, t2 * dx - t0 * dz, fmaf(dy, tu, fmaf(h1, f1, a[1])));
+        a[2] = fmaf(hq, t0 * dy - t1 * dx, fmaf(dz, tu, fmaf(h1, f2, a[2])));
+        a[3] = fmaf(hq, f1 * dz - f2 * dy, fmaf(dx, tw, fmaf(d1, t0, a[3])));
+        a[4] = fmaf(hq, f2 * dx - f0 * dz, fmaf(dy, tw, fmaf(d1, t1, a[4])));
+        a[5] = fmaf(hq, f0 * dy - f1 * dx, fmaf(dz, tw, fmaf(d1, t2, a[5])));
     }
     __device__ static void dl(float, float, float, float, const float *, float *) {}
 };
@@ -210,6 +241,19 @@ struct EStokeslet {       // u_i += phi_i/r - r_i s/r^3      [x 1/(8 pi)]
         a[0] = fmaf(ri, fmaf(dx, t, ph[0]), a[0]);
         a[1] = fmaf(ri, fmaf(dy, t, ph[1]), a[1]);
         a[2] = fmaf(ri, fmaf(dz, t, ph[2]), a[2]);
+    }
+};
+
+struct EStokesFT {        // u as EStokeslet; omega = (1/2) curl Phi: += phi x r / r^3   [x 1/(8 pi)]
+    static constexpr int NC = 4, NACC = 6;
+    __device__ static void eq(float dx, float dy, float dz, float ri, const float *ph, float s, float *a) {
+        const float ri2 = ri * ri, t = -s * ri2, ri3 = ri2 * ri;
+        a[0] = fmaf(ri, fmaf(dx, t, ph[0]), a[0]);
+        a[1] = fmaf(ri, fmaf(dy, t, ph[1]), a[1]);
+        a[2] = fmaf(ri, fmaf(dz, t, ph[2]), a[2]);
+        a[3] = fmaf(ri3, ph[1] * dz - ph[2] * dy, a[3]);
+        a[4] = fmaf(ri3, ph[2] * dx - ph[0] * dz, a[4]);
+        a[5] = fmaf(ri3, ph[0] * dy - ph[1] * dx, a[5]);
     }
 };
 

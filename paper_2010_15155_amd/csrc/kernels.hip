@@ -237,6 +237,9 @@ __global__ __launch_bounds__(256) void rel_positions_kernel(const int *__restric
 //   3 Laplace d       [yr, d, 0, 0]              dipole
 //   4 Stokes f, q     [yr, f, yr.f + q, 0]       Phi_j charge f_j, Psi charge
 //   5 Stokes D^s      [yr, D^s (6), 0, 0, 0]     Phi_j dipole -D^s_j., Psi dipole -D^s yr
+//   7 regularized     [yr, f, yr.f, 0, t, 0,     Phi_j charge f_j, Psi charge yr.f; the torque
+//     force, torque    m, 0]                      (rotlet) as Phi_i dipoles (e_i x t)/2 and, with
+//                                                 the eps^2 term, Psi dipole m = (eps^2/2) f + (yr x t)/2
 constexpr int kS2CTile = 256;   // staged records per LDS tile
 
 template <int SRC> struct S2CKind;
@@ -246,6 +249,7 @@ template <> struct S2CKind<2> { static constexpr int NC = 1, RS = 4; };
 template <> struct S2CKind<3> { static constexpr int NC = 1, RS = 8; };
 template <> struct S2CKind<4> { static constexpr int NC = 4, RS = 8; };
 template <> struct S2CKind<5> { static constexpr int NC = 4, RS = 12; };
+template <> struct S2CKind<7> { static constexpr int NC = 4, RS = 16; };
 
 int s2c_stage_stride(int src_kind) {
     switch (src_kind) {
@@ -255,6 +259,7 @@ int s2c_stage_stride(int src_kind) {
         case 3: return S2CKind<3>::RS;
         case 4: return S2CKind<4>::RS;
         case 5: return S2CKind<5>::RS;
+        case 7: return S2CKind<7>::RS;
         default: return 0;
     }
 }
@@ -290,6 +295,16 @@ __global__ __launch_bounds__(256) void stage_sources_kernel(const int *__restric
             o[3] = s[6];
         } else if constexpr (SRC == 3) {
             o[3] = s[6]; o[4] = s[7]; o[5] = s[8];
+        } else if constexpr (SRC == 7) {
+            // record: f at 6..8, t at 9..11, (3/2) eps^2 at 12
+            const float f0 = s[6], f1 = s[7], f2 = s[8], t0 = s[9], t1 = s[10], t2 = s[11];
+            const float ce = s[12] * (1.0f / 3.0f);     // eps^2 / 2
+            o[3] = f0; o[4] = f1; o[5] = f2;
+            o[6] = dot3(yx, yy, yz, f0, f1, f2);
+            o[8] = t0; o[9] = t1; o[10] = t2;
+            o[12] = fmaf(ce, f0, 0.5f * (yy * t2 - yz * t1));
+            o[13] = fmaf(ce, f1, 0.5f * (yz * t0 - yx * t2));
+            o[14] = fmaf(ce, f2, 0.5f * (yx * t1 - yy * t0));
         } else {
 #pragma unroll
             for (int k = 0; k < 6; ++k) o[3 + k] = s[6 + k];
@@ -353,6 +368,15 @@ __global__ __launch_bounds__(1024) void s2c_kernel(S2CArgs a) {
                     pot[i][0] = fmaf(y[3], ri, pot[i][0]);
                 } else if constexpr (SRC == 3) {
                     pot[i][0] = fmaf(dot3(y[3], y[4], y[5], dx, dy, dz), ri * ri * ri, pot[i][0]);
+                } else if constexpr (SRC == 7) {
+                    // charges; Phi_i dipoles (e_i x t)/2: (e_i x t).d / 2 = (t x d)_i / 2; Psi dipole
+                    const float ri3 = ri * ri * ri, hr3 = 0.5f * ri3;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) pot[i][c] = fmaf(y[3 + c], ri, pot[i][c]);
+                    pot[i][0] = fmaf(hr3, y[9] * dz - y[10] * dy, pot[i][0]);
+                    pot[i][1] = fmaf(hr3, y[10] * dx - y[8] * dz, pot[i][1]);
+                    pot[i][2] = fmaf(hr3, y[8] * dy - y[9] * dx, pot[i][2]);
+                    pot[i][3] = fmaf(dot3(y[12], y[13], y[14], dx, dy, dz), ri3, pot[i][3]);
                 } else {
                     // w = D^s (z - y): Phi_j += -w_j / r^3, Psi += -(yr . w) / r^3
                     float wx, wy, wz;
@@ -987,6 +1011,24 @@ struct F64StokesReg {     // v = f, eps
         for (int i = 0; i < 3; ++i) a[i] += kInv8Pi * (h1 * v[i] + h2 * rf * r[i]);
     }
 };
+struct F64StokesRegFT {   // v = f, t, eps -> u, omega
+    __device__ static void pair(int, const double *r, const double *v, double *a) {
+        const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        const double e2 = v[6] * v[6], s = rr + e2;
+        if (s == 0.0) return;
+        const double sq = sqrt(s), s3 = s * sq, s5 = s3 * s, s7 = s5 * s;
+        const double h1 = (rr + 2.0 * e2) / s3, h2 = 1.0 / s3, q = (2.0 * rr + 5.0 * e2) / s5;
+        const double d1 = (10.0 * e2 * e2 - 7.0 * e2 * rr - 2.0 * rr * rr) / s7, d2 = (21.0 * e2 + 6.0 * rr) / s7;
+        const double *f = v, *t = v + 3;
+        const double rf = r[0] * f[0] + r[1] * f[1] + r[2] * f[2], rt = r[0] * t[0] + r[1] * t[1] + r[2] * t[2];
+        const double txr[3] = {t[1] * r[2] - t[2] * r[1], t[2] * r[0] - t[0] * r[2], t[0] * r[1] - t[1] * r[0]};
+        const double fxr[3] = {f[1] * r[2] - f[2] * r[1], f[2] * r[0] - f[0] * r[2], f[0] * r[1] - f[1] * r[0]};
+        for (int i = 0; i < 3; ++i) {
+            a[i] += kInv8Pi * (h1 * f[i] + h2 * rf * r[i] + 0.5 * q * txr[i]);
+            a[3 + i] += kInv8Pi * (0.5 * q * fxr[i] + 0.25 * (d1 * t[i] + d2 * rt * r[i]));
+        }
+    }
+};
 struct F64RPY {
     __device__ static void pair(int, const double *r, const double *v, double *a) {
         double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
@@ -1099,6 +1141,9 @@ hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, hipStream_t s) {
         case kPVel: hipLaunchKernelGGL(p2p_kernel<DPVel>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kTraction: hipLaunchKernelGGL(p2p_kernel<DTraction>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kStokesRegVel: hipLaunchKernelGGL(p2p_kernel<DStokesReg>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kStokesRegVelOmega:
+            hipLaunchKernelGGL(p2p_kernel<DStokesRegFT>, dim3(ntasks), dim3(256), 0, s, a);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1136,6 +1181,7 @@ hipError_t launch_s2c(int src_kind, int ntasks, const S2CArgs &a, hipStream_t s)
         case 3: launch_s2c_kind<3>(ntasks, a, s); break;
         case 4: launch_s2c_kind<4>(ntasks, a, s); break;
         case 5: launch_s2c_kind<5>(ntasks, a, s); break;
+        case 7: launch_s2c_kind<7>(ntasks, a, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1144,7 +1190,7 @@ hipError_t launch_s2c(int src_kind, int ntasks, const S2CArgs &a, hipStream_t s)
 hipError_t launch_stage_sources(int src_kind, int nleaves, const int *leaves, const int2 *box_range,
                                 const double4 *geom, const float *src, int rec, float *out, hipStream_t s) {
     if (nleaves <= 0) return hipSuccess;
-    const int need = src_kind == 2 ? 7 : (src_kind == 1 || src_kind == 4 ? 10 : (src_kind == 5 ? 12 : 9));
+    const int need = src_kind == 2 ? 7 : src_kind == 1 || src_kind == 4 ? 10 : src_kind == 5 ? 12 : src_kind == 7 ? 13 : 9;
     if (rec < need) return hipErrorInvalidValue;
     dim3 g(nleaves), b(256);
     switch (src_kind) {
@@ -1154,6 +1200,7 @@ hipError_t launch_stage_sources(int src_kind, int nleaves, const int *leaves, co
         case 3: hipLaunchKernelGGL(stage_sources_kernel<3>, g, b, 0, s, leaves, box_range, geom, src, rec, out); break;
         case 4: hipLaunchKernelGGL(stage_sources_kernel<4>, g, b, 0, s, leaves, box_range, geom, src, rec, out); break;
         case 5: hipLaunchKernelGGL(stage_sources_kernel<5>, g, b, 0, s, leaves, box_range, geom, src, rec, out); break;
+        case 7: hipLaunchKernelGGL(stage_sources_kernel<7>, g, b, 0, s, leaves, box_range, geom, src, rec, out); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1229,6 +1276,7 @@ hipError_t launch_l2t(int kernel, int ntasks, const L2TArgs &a, hipStream_t s) {
         case kPVel: hipLaunchKernelGGL(l2t_kernel<EPVel>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kTraction: hipLaunchKernelGGL(l2t_kernel<ETraction>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kStokesRegVel: hipLaunchKernelGGL(l2t_kernel<EStokeslet>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kStokesRegVelOmega: hipLaunchKernelGGL(l2t_kernel<EStokesFT>, dim3(ntasks), dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1264,6 +1312,9 @@ hipError_t launch_direct_f64(int kernel, const DirectArgs &a, hipStream_t s) {
         case kPVel: hipLaunchKernelGGL(direct_f64_kernel<F64PVel>, g, dim3(256), 0, s, a); break;
         case kTraction: hipLaunchKernelGGL(direct_f64_kernel<F64Traction>, g, dim3(256), 0, s, a); break;
         case kStokesRegVel: hipLaunchKernelGGL(direct_f64_kernel<F64StokesReg>, g, dim3(256), 0, s, a); break;
+        case kStokesRegVelOmega:
+            hipLaunchKernelGGL(direct_f64_kernel<F64StokesRegFT>, g, dim3(256), 0, s, a);
+            break;
         default: return hipErrorInvalidValue;
     }
     if (a.slices > 1) {
@@ -1281,6 +1332,7 @@ bool p2p_uses_rel(int kernel) {
         case kPVel: return DPVel::REL;
         case kTraction: return DTraction::REL;
         case kStokesRegVel: return DStokesReg::REL;
+        case kStokesRegVelOmega: return DStokesRegFT::REL;
         default: return false;
     }
 }

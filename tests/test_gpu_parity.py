@@ -16,8 +16,9 @@ from paper_2010_15155_amd import workloads as W
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-KERNELS = ["Stokeslet", "RPY", "LapPGrad", "PVel", "Traction", "StokesRegVel"]
+KERNELS = ["Stokeslet", "RPY", "LapPGrad", "PVel", "Traction", "StokesRegVel", "StokesRegVelOmega"]
 FIELDS = {"Stokeslet": [("u", 0, 3)], "RPY": [("u", 0, 3), ("lap u", 3, 6)], "StokesRegVel": [("u", 0, 3)],
+          "StokesRegVelOmega": [("u", 0, 3), ("omega", 3, 6)],
           "LapPGrad": [("phi", 0, 1), ("grad phi", 1, 4)], "PVel": [("p", 0, 1), ("u", 1, 4)],
           "Traction": [("sigma", 0, 9)]}
 
@@ -49,6 +50,9 @@ def problem(kernel, n, seed, clustered=True):
     if kernel == "StokesRegVel":
         # blobs far smaller than the smallest leaf (tab:ktab_reg)
         v = np.concatenate([rng.standard_normal((n, 3)), rng.uniform(1e-4, 1e-3, (n, 1))], 1)
+        return dict(sl_xyz=x, sl_val=v, trg_xyz=x)
+    if kernel == "StokesRegVelOmega":
+        v = np.concatenate([rng.standard_normal((n, 6)), rng.uniform(1e-4, 1e-3, (n, 1))], 1)
         return dict(sl_xyz=x, sl_val=v, trg_xyz=x)
     if kernel == "LapPGrad":
         return dict(sl_xyz=x, sl_val=rng.standard_normal((n, 1)), dl_xyz=x,
