@@ -54,6 +54,7 @@ typedef enum {
 /* Kernel names and value widths follow the appendix table of supported
  * kernels (tab:implement):                     SL        DL       target
  *   LAP_PGRAD      q -> phi, grad phi          q (1)     d (3)    (phi, dphi/dx, dphi/dy, dphi/dz) (4)
+ *   LAP_PGRADGRAD  q -> phi, grad, Hessian     q (1)     d (3)    (phi, grad phi, xx xy xz yy yz zz) (10)
  *   STOKESLET      f -> u                      f (3)     --       u (3)
  *   RPY            [f, b] -> [u, lap u]        f,b (4)   --       (u, lap u) (6)
  *   PVEL           [f, q], D -> [p, u]         f,q (4)   D (9)    (p, u) (4)
@@ -74,7 +75,8 @@ typedef enum {
     STKFMM_PVEL = 3,
     STKFMM_TRACTION = 4,
     STKFMM_STOKES_REG_VEL = 5,
-    STKFMM_STOKES_REG_VEL_OMEGA = 6
+    STKFMM_STOKES_REG_VEL_OMEGA = 6,
+    STKFMM_LAP_PGRADGRAD = 7
 } stkfmm_kernel;
 
 /* Boundary conditions (Sec. III and its appendix on periodicity).  PXYZ is

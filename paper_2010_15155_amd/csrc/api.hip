@@ -38,6 +38,7 @@ static const KernelInfo kInfo[kNumKernels] = {
     {4, 9, 9, 4, 12, 12, 6},   // Traction
     {4, 0, 3, 4, 12, 0, 3},    // StokesRegVel
     {7, 0, 6, 4, 16, 0, 6},    // StokesRegVelOmega
+    {1, 3, 10, 1, 8, 12, 10},  // LapPGradGrad
 };
 const KernelInfo &kernel_info(int k) { return kInfo[k]; }
 
@@ -184,7 +185,8 @@ int sl_kind(int k) {
     switch (k) {
         case kStokeslet: return 0;
         case kRPY: return 1;
-        case kLapPGrad: return 2;
+        case kLapPGrad:
+        case kLapPGradGrad: return 2;
         case kStokesRegVel: return 6;
         case kStokesRegVelOmega: return 7;
         default: return 4;
@@ -193,7 +195,7 @@ int sl_kind(int k) {
 // The regularized Stokeslet's far field is the RPY one with b^2 = 3 eps^2 / 2
 // (to O(eps^4 / r^5)): its packed records carry that b^2 where RPY's do.
 int stage_kind(int k) { return k == kStokesRegVel ? 1 : sl_kind(k); }   // kind 7 packs and stages alike
-int dl_kind(int k) { return k == kLapPGrad ? 3 : 5; }
+int dl_kind(int k) { return k == kLapPGrad || k == kLapPGradGrad ? 3 : 5; }
 
 stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, DeviceOps **out) {
     int key = p * 2 + (periodic ? 1 : 0);
@@ -1079,8 +1081,11 @@ CombineMap combine_map(int k, double L) {
             for (int i = 3; i < 6; ++i) m.src[i] = i, m.scale[i] = c8 / (L * L * L);
             break;
         case kLapPGrad:
+        case kLapPGradGrad:
             m.src[0] = 0, m.scale[0] = c4 / L;
             for (int i = 1; i < 4; ++i) m.src[i] = i, m.scale[i] = c4 / (L * L);
+            if (k == kLapPGradGrad)
+                for (int i = 4; i < 10; ++i) m.src[i] = i, m.scale[i] = c4 / (L * L * L);
             break;
         case kPVel:
             m.src[0] = 0, m.scale[0] = c8 / (L * L);
@@ -1424,10 +1429,11 @@ stkfmm_status sampled_error(stkfmm_ctx *c, const double *sl_val, const double *d
     HIP_TRY(c, hipMemcpyAsync(ref.data(), c->vbuf[3].p, ref.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     // output fields: (u), (u, lap u), (phi, grad phi), (p, u), (sigma)
-    static const int fields[kNumKernels][3] = {{0, 1, 4}, {0, 3, 3}, {0, 3, 6}, {0, 1, 4}, {0, 9, 9}, {0, 3, 3}, {0, 3, 6}};
+    static const int fields[kNumKernels][4] = {{0, 1, 4, 4}, {0, 3, 3, 3}, {0, 3, 6, 6}, {0, 1, 4, 4},
+                                               {0, 9, 9, 9}, {0, 3, 3, 3}, {0, 3, 6, 6}, {0, 1, 4, 10}};
     const int *fb = fields[c->kernel];
     double worst = 0.0;
-    for (int f = 0; f < 2; ++f) {
+    for (int f = 0; f < 3; ++f) {
         const int a0 = fb[f], a1 = fb[f + 1];
         if (a1 <= a0) continue;
         double num = 0, den = 0;

@@ -162,6 +162,49 @@ struct DLapPGrad {        // SL q ; DL d0 d1 d2
     }
 };
 
+// Laplace with the Hessian (xx, xy, xz, yy, yz, zz) after phi and grad phi:
+//   charge q:  d_i d_j (q/r) = q (3 r_i r_j/r^5 - delta_ij/r^3)
+//   dipole d:  d_i d_j (d.r/r^3) = -3 (d_i r_j + d_j r_i + (d.r) delta_ij)/r^5 + 15 (d.r) r_i r_j/r^7
+__device__ __forceinline__ void lap_hess_charge(float dx, float dy, float dz, float q, float ri, float *a) {
+    const float ri3 = ri * ri * ri, c = 3.0f * q * ri3 * ri * ri, d = q * ri3;
+    a[0] = fmaf(q, ri, a[0]);
+    a[1] = fmaf(-d, dx, a[1]);
+    a[2] = fmaf(-d, dy, a[2]);
+    a[3] = fmaf(-d, dz, a[3]);
+    const float cx = c * dx, cy = c * dy;
+    a[4] = fmaf(cx, dx, a[4] - d);
+    a[5] = fmaf(cx, dy, a[5]);
+    a[6] = fmaf(cx, dz, a[6]);
+    a[7] = fmaf(cy, dy, a[7] - d);
+    a[8] = fmaf(cy, dz, a[8]);
+    a[9] = fmaf(c * dz, dz, a[9] - d);
+}
+
+struct DLapPGradGrad {    // SL q ; DL d0 d1 d2      out phi, grad phi, Hessian (10)
+    static constexpr int RS = 8, RD = 12, NACC = 10;
+    static constexpr bool REL = false;
+    __device__ static void sl(float dx, float dy, float dz, float ri, const float *v, float *a) {
+        lap_hess_charge(dx, dy, dz, v[0], ri, a);
+    }
+    __device__ static void dl(float dx, float dy, float dz, float ri, const float *v, float *a) {
+        const float ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2, ri7 = ri5 * ri2;
+        const float d0 = v[0], d1 = v[1], d2 = v[2];
+        const float dr = dot3(dx, dy, dz, d0, d1, d2);
+        const float t = -3.0f * dr * ri5, g = -3.0f * ri5, e = 15.0f * dr * ri7;
+        a[0] = fmaf(dr, ri3, a[0]);
+        a[1] = fmaf(t, dx, fmaf(d0, ri3, a[1]));
+        a[2] = fmaf(t, dy, fmaf(d1, ri3, a[2]));
+        a[3] = fmaf(t, dz, fmaf(d2, ri3, a[3]));
+        const float ex = e * dx, ey = e * dy;
+        a[4] = fmaf(ex, dx, fmaf(g, 2.0f * d0 * dx, a[4] + t));
+        a[5] = fmaf(ex, dy, fmaf(g, fmaf(d0, dy, d1 * dx), a[5]));
+        a[6] = fmaf(ex, dz, fmaf(g, fmaf(d0, dz, d2 * dx), a[6]));
+        a[7] = fmaf(ey, dy, fmaf(g, 2.0f * d1 * dy, a[7] + t));
+        a[8] = fmaf(ey, dz, fmaf(g, fmaf(d1, dz, d2 * dy), a[8]));
+        a[9] = fmaf(e * dz, dz, fmaf(g, 2.0f * d2 * dz, a[9] + t));
+    }
+};
+
 // symmetric D^s stored (xx, xy, xz, yy, yz, zz)
 __device__ __forceinline__ void sym_apply(const float *s, float dx, float dy, float dz,
                                           float &wx, float &wy, float &wz) {
@@ -283,6 +326,13 @@ struct ELapPGrad {        // phi += q/r, grad phi += -q r/r^3   [x 1/(4 pi)]
         a[1] = fmaf(t, dx, a[1]);
         a[2] = fmaf(t, dy, a[2]);
         a[3] = fmaf(t, dz, a[3]);
+    }
+};
+
+struct ELapPGradGrad {    // phi, grad phi, Hessian of q/r   [x 1/(4 pi)]
+    static constexpr int NC = 1, NACC = 10;
+    __device__ static void eq(float dx, float dy, float dz, float ri, const float *ph, float, float *a) {
+        lap_hess_charge(dx, dy, dz, ph[0], ri, a);
     }
 };
 

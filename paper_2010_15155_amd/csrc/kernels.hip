@@ -1029,6 +1029,29 @@ struct F64StokesRegFT {   // v = f, t, eps -> u, omega
         }
     }
 };
+struct F64LapHess {       // SL q, DL d -> phi, grad phi, Hessian (xx, xy, xz, yy, yz, zz)
+    __device__ static void pair(int pass, const double *r, const double *v, double *a) {
+        const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (rr == 0.0) return;
+        const double i1 = 1.0 / sqrt(rr), i3 = i1 / rr, i5 = i3 / rr, i7 = i5 / rr;
+        int k = 4;
+        if (pass == 0) {
+            const double q = v[0];
+            a[0] += kInv4Pi * q * i1;
+            for (int i = 0; i < 3; ++i) a[1 + i] -= kInv4Pi * q * r[i] * i3;
+            for (int i = 0; i < 3; ++i)
+                for (int j = i; j < 3; ++j) a[k++] += kInv4Pi * q * (3.0 * r[i] * r[j] * i5 - (i == j ? i3 : 0.0));
+        } else {
+            const double dr = v[0] * r[0] + v[1] * r[1] + v[2] * r[2];
+            a[0] += kInv4Pi * dr * i3;
+            for (int i = 0; i < 3; ++i) a[1 + i] += kInv4Pi * (v[i] * i3 - 3.0 * dr * r[i] * i5);
+            for (int i = 0; i < 3; ++i)
+                for (int j = i; j < 3; ++j)
+                    a[k++] += kInv4Pi * (-3.0 * (v[j] * r[i] + v[i] * r[j] + (i == j ? dr : 0.0)) * i5 +
+                                         15.0 * dr * r[i] * r[j] * i7);
+        }
+    }
+};
 struct F64RPY {
     __device__ static void pair(int, const double *r, const double *v, double *a) {
         double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
@@ -1141,6 +1164,7 @@ hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, hipStream_t s) {
         case kPVel: hipLaunchKernelGGL(p2p_kernel<DPVel>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kTraction: hipLaunchKernelGGL(p2p_kernel<DTraction>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kStokesRegVel: hipLaunchKernelGGL(p2p_kernel<DStokesReg>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kLapPGradGrad: hipLaunchKernelGGL(p2p_kernel<DLapPGradGrad>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kStokesRegVelOmega:
             hipLaunchKernelGGL(p2p_kernel<DStokesRegFT>, dim3(ntasks), dim3(256), 0, s, a);
             break;
@@ -1276,6 +1300,7 @@ hipError_t launch_l2t(int kernel, int ntasks, const L2TArgs &a, hipStream_t s) {
         case kPVel: hipLaunchKernelGGL(l2t_kernel<EPVel>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kTraction: hipLaunchKernelGGL(l2t_kernel<ETraction>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kStokesRegVel: hipLaunchKernelGGL(l2t_kernel<EStokeslet>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kLapPGradGrad: hipLaunchKernelGGL(l2t_kernel<ELapPGradGrad>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kStokesRegVelOmega: hipLaunchKernelGGL(l2t_kernel<EStokesFT>, dim3(ntasks), dim3(256), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
@@ -1312,6 +1337,7 @@ hipError_t launch_direct_f64(int kernel, const DirectArgs &a, hipStream_t s) {
         case kPVel: hipLaunchKernelGGL(direct_f64_kernel<F64PVel>, g, dim3(256), 0, s, a); break;
         case kTraction: hipLaunchKernelGGL(direct_f64_kernel<F64Traction>, g, dim3(256), 0, s, a); break;
         case kStokesRegVel: hipLaunchKernelGGL(direct_f64_kernel<F64StokesReg>, g, dim3(256), 0, s, a); break;
+        case kLapPGradGrad: hipLaunchKernelGGL(direct_f64_kernel<F64LapHess>, g, dim3(256), 0, s, a); break;
         case kStokesRegVelOmega:
             hipLaunchKernelGGL(direct_f64_kernel<F64StokesRegFT>, g, dim3(256), 0, s, a);
             break;
@@ -1332,6 +1358,7 @@ bool p2p_uses_rel(int kernel) {
         case kPVel: return DPVel::REL;
         case kTraction: return DTraction::REL;
         case kStokesRegVel: return DStokesReg::REL;
+        case kLapPGradGrad: return DLapPGradGrad::REL;
         case kStokesRegVelOmega: return DStokesRegFT::REL;
         default: return false;
     }

@@ -16,10 +16,12 @@ from paper_2010_15155_amd import workloads as W
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-KERNELS = ["Stokeslet", "RPY", "LapPGrad", "PVel", "Traction", "StokesRegVel", "StokesRegVelOmega"]
+KERNELS = ["Stokeslet", "RPY", "LapPGrad", "PVel", "Traction", "StokesRegVel", "StokesRegVelOmega",
+           "LapPGradGrad"]
 FIELDS = {"Stokeslet": [("u", 0, 3)], "RPY": [("u", 0, 3), ("lap u", 3, 6)], "StokesRegVel": [("u", 0, 3)],
           "StokesRegVelOmega": [("u", 0, 3), ("omega", 3, 6)],
-          "LapPGrad": [("phi", 0, 1), ("grad phi", 1, 4)], "PVel": [("p", 0, 1), ("u", 1, 4)],
+          "LapPGrad": [("phi", 0, 1), ("grad phi", 1, 4)],
+          "LapPGradGrad": [("phi", 0, 1), ("grad phi", 1, 4), ("hess phi", 4, 10)], "PVel": [("p", 0, 1), ("u", 1, 4)],
           "Traction": [("sigma", 0, 9)]}
 
 
@@ -54,7 +56,7 @@ def problem(kernel, n, seed, clustered=True):
     if kernel == "StokesRegVelOmega":
         v = np.concatenate([rng.standard_normal((n, 6)), rng.uniform(1e-4, 1e-3, (n, 1))], 1)
         return dict(sl_xyz=x, sl_val=v, trg_xyz=x)
-    if kernel == "LapPGrad":
+    if kernel in ("LapPGrad", "LapPGradGrad"):
         return dict(sl_xyz=x, sl_val=rng.standard_normal((n, 1)), dl_xyz=x,
                     dl_val=rng.standard_normal((n, 3)), trg_xyz=x)
     y = rng.random((n // 3, 3))
