@@ -24,6 +24,7 @@
  *   Stokes double layer D -> [p,u], T_ijk = -3 r_i r_j r_k/(8 pi r^5)
  *                                                             Sec. II.C, Eqs. stkdlp, stkdlvel
  *   Traction sigma = -p I + grad u + grad u^T                 Sec. II.C, Eq. stressdef
+ *   PVelGrad / PVelLaplacian: (p, u) and their derivatives   tab:implement
  * Output component orders (the paper prints none; see the oracle README
  * strings in direct.py): Hessian (xx,xy,xz,yy,yz,zz), D and sigma row-major.
  */
@@ -241,6 +242,83 @@ void oracle_pvel(int64_t nsl, const double *ysl, const double *fq,
             for (int i = 0; i < 3; ++i) u[i] += -3.0 * c8 * r[i] * rDr * i5;
         }
         out[4*t] = p; out[4*t+1] = u[0]; out[4*t+2] = u[1]; out[4*t+3] = u[2];
+    }
+}
+
+/* PVel with derivatives: SL (f,q) and DL D -> when lap == 0 (PVelGrad)
+ * (p, u, grad p, grad u) with grad u[3i+j] = du_i/dx_j (16 values); when
+ * lap != 0 (PVelLaplacian) (p, u, lap u) (7 values).  Per source, with
+ * rf = r.f, A = r.D.r, w = D^s r:
+ *   SL  u_i = (f_i/r + r_i (rf - q)/r^3)/(8 pi),  p = rf/(4 pi r^3)
+ *       du_i/dx_j = (-f_i r_j/r^3 + delta_ij (rf - q)/r^3 + r_i f_j/r^3
+ *                    - 3 r_i r_j (rf - q)/r^5)/(8 pi)
+ *       dp/dx_j = (f_j/r^3 - 3 rf r_j/r^5)/(4 pi)
+ *       lap u_i = (2 f_i/r^3 - 6 r_i rf/r^5)/(8 pi)  (the q r/r^3 part is harmonic)
+ *   DL  u_i = -3 r_i A/(8 pi r^5),  p = (-3 A/r^5 + tr D/r^3)/(4 pi)
+ *       du_i/dx_j = -3 (delta_ij A/r^5 + 2 r_i w_j/r^5 - 5 r_i r_j A/r^7)/(8 pi)
+ *       dp/dx_j = (-6 w_j/r^5 + 15 A r_j/r^7 - 3 tr D r_j/r^5)/(4 pi)
+ *       lap u_i = -3 lap(r_i A/r^5)/(8 pi), lap(r_i g) = r_i lap g + 2 d_i g with
+ *       g = A/r^5, lap g = 2 tr D/r^5:  lap u_i = (-6 tr D r_i/r^5 - 12 w_i/r^5
+ *       + 30 A r_i/r^7)/(8 pi). */
+void oracle_pvel_deriv(int64_t nsl, const double *ysl, const double *fq,
+                       int64_t ndl, const double *ydl, const double *D,
+                       int64_t nt, const double *xs, double *out, int lap)
+{
+    const double c4 = 1.0 / (4.0 * PI), c8 = 1.0 / (8.0 * PI);
+    const int kt = lap ? 7 : 16;
+#pragma omp parallel for schedule(dynamic, 16) if (nt * (nsl + ndl) > 200000)
+    for (int64_t t = 0; t < nt; ++t) {
+        double p = 0, u[3] = {0, 0, 0}, gp[3] = {0, 0, 0}, gu[9] = {0}, lu[3] = {0, 0, 0};
+        for (int64_t s = 0; s < nsl; ++s) {
+            double r[3] = {xs[3*t] - ysl[3*s], xs[3*t+1] - ysl[3*s+1], xs[3*t+2] - ysl[3*s+2]};
+            double rr = r[0]*r[0] + r[1]*r[1] + r[2]*r[2];
+            if (rr == 0.0) continue;
+            double i1 = 1.0 / sqrt(rr), i3 = i1 / rr, i5 = i3 / rr;
+            const double *f = fq + 4*s;
+            double rf = r[0]*f[0] + r[1]*f[1] + r[2]*f[2], g = rf - f[3];
+            p += c4 * rf * i3;
+            for (int i = 0; i < 3; ++i) {
+                u[i] += c8 * (f[i] * i1 + r[i] * g * i3);
+                gp[i] += c4 * (f[i] * i3 - 3.0 * rf * r[i] * i5);
+                lu[i] += c8 * (2.0 * f[i] * i3 - 6.0 * r[i] * rf * i5);
+                for (int j = 0; j < 3; ++j)
+                    gu[3*i+j] += c8 * (-f[i] * r[j] * i3 + (i == j ? g * i3 : 0.0) + r[i] * f[j] * i3
+                                       - 3.0 * r[i] * r[j] * g * i5);
+            }
+        }
+        for (int64_t s = 0; s < ndl; ++s) {
+            double r[3] = {xs[3*t] - ydl[3*s], xs[3*t+1] - ydl[3*s+1], xs[3*t+2] - ydl[3*s+2]};
+            double rr = r[0]*r[0] + r[1]*r[1] + r[2]*r[2];
+            if (rr == 0.0) continue;
+            double i1 = 1.0 / sqrt(rr), i3 = i1 / rr, i5 = i3 / rr, i7 = i5 / rr;
+            const double *Ds = D + 9*s;
+            double A = 0, tr = Ds[0] + Ds[4] + Ds[8], w[3];
+            for (int j = 0; j < 3; ++j) {
+                w[j] = 0;
+                for (int k = 0; k < 3; ++k) {
+                    A += r[j] * Ds[3*j+k] * r[k];
+                    w[j] += 0.5 * (Ds[3*j+k] + Ds[3*k+j]) * r[k];
+                }
+            }
+            p += c4 * (-3.0 * A * i5 + tr * i3);
+            for (int i = 0; i < 3; ++i) {
+                u[i] += -3.0 * c8 * r[i] * A * i5;
+                gp[i] += c4 * (-6.0 * w[i] * i5 + 15.0 * A * r[i] * i7 - 3.0 * tr * r[i] * i5);
+                lu[i] += c8 * (-6.0 * tr * r[i] * i5 - 12.0 * w[i] * i5 + 30.0 * A * r[i] * i7);
+                for (int j = 0; j < 3; ++j)
+                    gu[3*i+j] += -3.0 * c8 * ((i == j ? A * i5 : 0.0) + 2.0 * r[i] * w[j] * i5
+                                              - 5.0 * r[i] * r[j] * A * i7);
+            }
+        }
+        double *o = out + kt * t;
+        o[0] = p;
+        for (int i = 0; i < 3; ++i) o[1+i] = u[i];
+        if (lap) {
+            for (int i = 0; i < 3; ++i) o[4+i] = lu[i];
+        } else {
+            for (int i = 0; i < 3; ++i) o[4+i] = gp[i];
+            for (int k = 0; k < 9; ++k) o[7+k] = gu[k];
+        }
     }
 }
 

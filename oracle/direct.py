@@ -32,6 +32,7 @@ def lib():
         for name in ("oracle_stokeslet", "oracle_rpy", "oracle_stokes_reg", "oracle_stokes_reg_ft"):
             getattr(_lib, name).argtypes = [_i64, _dp, _dp, _i64, _dp, _dp]
         _lib.oracle_laplace.argtypes = [_i64, _dp, _dp, _i64, _dp, _dp, _i64, _dp, _dp, ctypes.c_int]
+        _lib.oracle_pvel_deriv.argtypes = [_i64, _dp, _dp, _i64, _dp, _dp, _i64, _dp, _dp, ctypes.c_int]
         for name in ("oracle_pvel", "oracle_traction"):
             getattr(_lib, name).argtypes = [_i64, _dp, _dp, _i64, _dp, _dp, _i64, _dp, _dp]
         _lib.oracle_ewald_structure.argtypes = [_i64, _dp, _dp, _dp, ctypes.c_double,
@@ -117,6 +118,18 @@ def pvel(sl=None, fq=None, dl=None, D=None, trg=None):
     return out
 
 
+def pvel_grad(sl=None, fq=None, dl=None, D=None, trg=None, lap=False):
+    """(p, u, grad p, grad u) (16), or with lap=True (p, u, lap u) (7)."""
+    sl, nsl = _arr(sl, 3)
+    fq, _ = _arr(fq, 4)
+    dl, ndl = _arr(dl, 3)
+    D, _ = _arr(D, 9)
+    trg, nt = _arr(trg, 3)
+    out = np.zeros((nt, 7 if lap else 16))
+    lib().oracle_pvel_deriv(nsl, _p(sl), _p(fq), ndl, _p(dl), _p(D), nt, _p(trg), _p(out), int(lap))
+    return out
+
+
 def traction(sl=None, fq=None, dl=None, D=None, trg=None):
     sl, nsl = _arr(sl, 3)
     fq, _ = _arr(fq, 4)
@@ -146,6 +159,10 @@ def evaluate(kernel, sl=None, sl_val=None, dl=None, dl_val=None, trg=None):
         return pvel(sl, sl_val, dl, dl_val, trg)
     if kernel == "Traction":
         return traction(sl, sl_val, dl, dl_val, trg)
+    if kernel == "PVelGrad":
+        return pvel_grad(sl, sl_val, dl, dl_val, trg)
+    if kernel == "PVelLaplacian":
+        return pvel_grad(sl, sl_val, dl, dl_val, trg, lap=True)
     raise ValueError("unknown kernel %r" % kernel)
 
 

@@ -359,6 +359,30 @@ def test_stresslet_special_case_pressure():
     assert np.allclose(c[:, 0], 0, atol=1e-14)
 
 
+def test_pvel_derivatives_are_fd_of_pvel():
+    # grad p, grad u and lap u of the (p, u) field, SL (f, q) and DL D together
+    y, fq = _pts(4), RNG.standard_normal((4, 4))
+    yd, D = _pts(3, 0.4, 0.8), RNG.standard_normal((3, 9))
+    x = _probe()
+    pu = lambda xx: direct.pvel(y, fq, yd, D, xx)
+    g = direct.pvel_grad(y, fq, yd, D, x)
+    lap = direct.pvel_grad(y, fq, yd, D, x, lap=True)
+    assert np.allclose(g[:, :4], pu(x), rtol=1e-13, atol=1e-15)
+    assert np.allclose(lap[:, :4], pu(x), rtol=1e-13, atol=1e-15)
+    J = _fd.grad(pu, x, h=1e-3)                    # [n, k, j] = d (p,u)_k / dx_j
+    assert np.allclose(g[:, 4:7], J[:, 0, :], rtol=1e-7, atol=1e-9 * np.abs(J).max())
+    assert np.allclose(g[:, 7:].reshape(-1, 3, 3), J[:, 1:, :], rtol=1e-7, atol=1e-9 * np.abs(J).max())
+    L = _fd.laplacian(lambda xx: pu(xx)[:, 1:], x, h=2e-3)
+    assert np.allclose(lap[:, 4:], L, rtol=1e-6, atol=1e-8 * np.abs(L).max())
+    # Stokes equations (mu = 1): lap u = grad p, div u = 0 (q = 0 here)
+    fq0 = fq.copy()
+    fq0[:, 3] = 0
+    g0 = direct.pvel_grad(y, fq0, yd, D, x)
+    l0 = direct.pvel_grad(y, fq0, yd, D, x, lap=True)
+    assert np.allclose(l0[:, 4:], g0[:, 4:7], rtol=1e-10, atol=1e-12 * np.abs(g0[:, 4:7]).max())
+    assert np.allclose(np.trace(g0[:, 7:].reshape(-1, 3, 3), axis1=1, axis2=2), 0, atol=1e-10 * np.abs(g0).max())
+
+
 def test_rel_l2():
     assert direct.rel_l2([1.0, 0.0], [1.0, 0.0]) == 0.0
     assert direct.rel_l2([2.0, 0.0], [1.0, 0.0]) == 1.0
