@@ -58,6 +58,9 @@ typedef enum {
  *   STOKESLET      f -> u                      f (3)     --       u (3)
  *   RPY            [f, b] -> [u, lap u]        f,b (4)   --       (u, lap u) (6)
  *   PVEL           [f, q], D -> [p, u]         f,q (4)   D (9)    (p, u) (4)
+ *   PVEL_GRAD      [f, q], D -> [p, u, grad p, grad u]
+ *                                              f,q (4)   D (9)    (p, u, grad p, grad u) (16)
+ *   PVEL_LAPLACIAN [f, q], D -> [p, u, lap u]  f,q (4)   D (9)    (p, u, lap u) (7)
  *   TRACTION       [f, q], D -> sigma          f,q (4)   D (9)    sigma (9)
  *   STOKES_REG_VEL [f, eps] -> u               f,eps (4) --       u (3)
  *   STOKES_REG_VEL_OMEGA [f, t, eps] -> [u, w] f,t,eps (7) --     (u, angular velocity) (6)
@@ -66,8 +69,10 @@ typedef enum {
  * O((eps/r)^4), so eps must be far smaller than the smallest leaf box.
  * STOKES_REG_VEL_OMEGA adds point torques t and the angular velocity
  * w = curl(u)/2 (the force-torque extension of Sec. II.B, tab:ktab_regftvw).
- * D and sigma are row-major 3x3 (D[3j+k] = D_jk, sigma[3i+j]); q in PVEL and
- * TRACTION is twice the physical source (Sec. II.C); viscosity mu = 1. */
+ * D, sigma and grad u are row-major 3x3 (D[3j+k] = D_jk, sigma[3i+j],
+ * grad u[3i+j] = du_i/dx_j); q in the PVEL kernels and TRACTION is twice the
+ * physical source (Sec. II.C); viscosity mu = 1.  Away from the sources
+ * lap u = grad p (the Stokes equations), and PVEL_LAPLACIAN returns it as such. */
 typedef enum {
     STKFMM_LAP_PGRAD = 0,
     STKFMM_STOKESLET = 1,
@@ -76,7 +81,9 @@ typedef enum {
     STKFMM_TRACTION = 4,
     STKFMM_STOKES_REG_VEL = 5,
     STKFMM_STOKES_REG_VEL_OMEGA = 6,
-    STKFMM_LAP_PGRADGRAD = 7
+    STKFMM_LAP_PGRADGRAD = 7,
+    STKFMM_PVEL_GRAD = 8,
+    STKFMM_PVEL_LAPLACIAN = 9
 } stkfmm_kernel;
 
 /* Boundary conditions (Sec. III and its appendix on periodicity).  PXYZ is

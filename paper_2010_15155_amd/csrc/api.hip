@@ -39,6 +39,8 @@ static const KernelInfo kInfo[kNumKernels] = {
     {4, 0, 3, 4, 12, 0, 3},    // StokesRegVel
     {7, 0, 6, 4, 16, 0, 6},    // StokesRegVelOmega
     {1, 3, 10, 1, 8, 12, 10},  // LapPGradGrad
+    {4, 9, 16, 4, 12, 12, 16}, // PVelGrad
+    {4, 9, 7, 4, 12, 12, 7},   // PVelLaplacian
 };
 const KernelInfo &kernel_info(int k) { return kInfo[k]; }
 
@@ -1062,7 +1064,7 @@ namespace {
 
 CombineMap combine_map(int k, double L) {
     CombineMap m;
-    for (int i = 0; i < 10; ++i) {
+    for (int i = 0; i < kMaxAcc; ++i) {
         m.src[i] = -1;
         m.scale[i] = 0;
     }
@@ -1088,8 +1090,14 @@ CombineMap combine_map(int k, double L) {
                 for (int i = 4; i < 10; ++i) m.src[i] = i, m.scale[i] = c4 / (L * L * L);
             break;
         case kPVel:
+        case kPVelGrad:
+        case kPVelLaplacian:
             m.src[0] = 0, m.scale[0] = c8 / (L * L);
             for (int i = 1; i < 4; ++i) m.src[i] = i, m.scale[i] = c8 / L;
+            if (k == kPVel) break;
+            for (int i = 4; i < 7; ++i) m.src[i] = i, m.scale[i] = c8 / (L * L * L);
+            if (k == kPVelGrad)
+                for (int i = 7; i < 16; ++i) m.src[i] = i, m.scale[i] = c8 / (L * L);
             break;
         case kTraction: {
             const int sym[9] = {0, 1, 2, 1, 3, 4, 2, 4, 5};
@@ -1428,12 +1436,15 @@ stkfmm_status sampled_error(stkfmm_ctx *c, const double *sl_val, const double *d
     HIP_TRY(c, hipMemcpyAsync(got.data(), c->vbuf[1].p, got.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipMemcpyAsync(ref.data(), c->vbuf[3].p, ref.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
-    // output fields: (u), (u, lap u), (phi, grad phi), (p, u), (sigma)
-    static const int fields[kNumKernels][4] = {{0, 1, 4, 4}, {0, 3, 3, 3}, {0, 3, 6, 6}, {0, 1, 4, 4},
-                                               {0, 9, 9, 9}, {0, 3, 3, 3}, {0, 3, 6, 6}, {0, 1, 4, 10}};
+    // output fields: (u), (u, lap u), (phi, grad phi), (p, u), (sigma), (u, omega),
+    // (phi, grad phi, Hessian), (p, u, grad p, grad u), (p, u, lap u)
+    static const int fields[kNumKernels][5] = {{0, 1, 4, 4, 4},  {0, 3, 3, 3, 3},  {0, 3, 6, 6, 6},
+                                               {0, 1, 4, 4, 4},  {0, 9, 9, 9, 9},  {0, 3, 3, 3, 3},
+                                               {0, 3, 6, 6, 6},  {0, 1, 4, 10, 10}, {0, 1, 4, 7, 16},
+                                               {0, 1, 4, 7, 7}};
     const int *fb = fields[c->kernel];
     double worst = 0.0;
-    for (int f = 0; f < 3; ++f) {
+    for (int f = 0; f < 4; ++f) {
         const int a0 = fb[f], a1 = fb[f + 1];
         if (a1 <= a0) continue;
         double num = 0, den = 0;

@@ -21,7 +21,7 @@ constexpr double kAlphaIn = 1.05;
 constexpr double kAlphaOut = 2.95;
 
 enum Kernel { kLapPGrad = 0, kStokeslet = 1, kRPY = 2, kPVel = 3, kTraction = 4, kStokesRegVel = 5,
-              kStokesRegVelOmega = 6, kLapPGradGrad = 7, kNumKernels = 8 };
+              kStokesRegVelOmega = 6, kLapPGradGrad = 7, kPVelGrad = 8, kPVelLaplacian = 9, kNumKernels = 10 };
 
 struct KernelInfo {
     int k_sl, k_dl, k_trg;   // user value widths

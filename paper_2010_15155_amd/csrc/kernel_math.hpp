@@ -17,6 +17,12 @@
 //   PVel SL     p = 2 (r.f)/r^3, u = (r^2 f + r (r.f) - q r)/r^3    [x 1/8pi] Eqs. stkslp, stkslvel
 //   PVel DL     p = 2 (-3 A/r^5 + tr D/r^3), u = -3 r A/r^5, A = r.D.r
 //                                                                   [x 1/8pi] Eqs. stkdlp, stkdlvel
+//   PVel grad   SL d_j p = 2 (f_j/r^3 - 3 rf r_j/r^5), rf = r.f,
+//               d_j u_i = r_i f_j/r^3 - f_i r_j/r^3 + delta_ij g/r^3 - 3 g r_i r_j/r^5, g = rf - q
+//               DL d_j p = -12 w_j/r^5 + (30 A/r^7 - 6 tr D/r^5) r_j,
+//               d_j u_i = -3 delta_ij A/r^5 - 6 r_i w_j/r^5 + 15 A r_i r_j/r^7
+//               lap u = grad p for both (Stokes equations; the q r/r^3 part is harmonic)
+//                                                                   [x 1/8pi] tab:implement
 //   Traction SL sigma = 3 (q - r.f) r r^T/r^5 - q I/r^3             [x 1/4pi] Eq. stressdef
 //   Traction DL sigma = -tr D I/r^3 - 3 (r w^T + w r^T)/r^5 + 15 A r r^T/r^7, w = D^s r
 //                                                                   [x 1/4pi] Eq. stressdef
@@ -273,6 +279,70 @@ struct DTraction {        // SL f0 f1 f2 q ; DL D^s (6)     out sigma sym (6)  [
     }
 };
 
+// PVel with its derivatives: out p, u, grad p (7), and with GRADU grad u
+// row-major (d_j u_i at 7 + 3 i + j, 16).  grad p doubles as lap u.
+template <bool GRADU>
+struct DPVelDeriv {       // SL f0 f1 f2 q ; DL D^s (6)                  [x 1/8pi]
+    static constexpr int RS = 12, RD = 12, NACC = GRADU ? 16 : 7;
+    static constexpr bool REL = false;
+    __device__ static void sl(float dx, float dy, float dz, float ri, const float *v, float *a) {
+        const float ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2;
+        const float rf = dot3(dx, dy, dz, v[0], v[1], v[2]);
+        const float g = rf - v[3], t = g * ri3;
+        a[0] = fmaf(2.0f * rf, ri3, a[0]);
+        a[1] = fmaf(dx, t, fmaf(v[0], ri, a[1]));
+        a[2] = fmaf(dy, t, fmaf(v[1], ri, a[2]));
+        a[3] = fmaf(dz, t, fmaf(v[2], ri, a[3]));
+        const float c = -6.0f * rf * ri5, d = 2.0f * ri3;
+        a[4] = fmaf(c, dx, fmaf(d, v[0], a[4]));
+        a[5] = fmaf(c, dy, fmaf(d, v[1], a[5]));
+        a[6] = fmaf(c, dz, fmaf(d, v[2], a[6]));
+        if constexpr (GRADU) {
+            const float r[3] = {dx, dy, dz};
+            const float F[3] = {v[0] * ri3, v[1] * ri3, v[2] * ri3};
+            const float e = -3.0f * g * ri5;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const float er = e * r[i];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    float &o = a[7 + 3 * i + j];
+                    o = fmaf(er, r[j], fmaf(r[i], F[j], fmaf(-F[i], r[j], i == j ? o + t : o)));
+                }
+            }
+        }
+    }
+    __device__ static void dl(float dx, float dy, float dz, float ri, const float *v, float *a) {
+        const float ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2, ri7 = ri5 * ri2;
+        float wx, wy, wz;
+        sym_apply(v, dx, dy, dz, wx, wy, wz);
+        const float A = dot3(dx, dy, dz, wx, wy, wz);
+        const float tr = v[0] + v[3] + v[5];
+        const float t = -3.0f * A * ri5;
+        a[0] = fmaf(2.0f, fmaf(tr, ri3, t), a[0]);
+        a[1] = fmaf(t, dx, a[1]);
+        a[2] = fmaf(t, dy, a[2]);
+        a[3] = fmaf(t, dz, a[3]);
+        const float c = fmaf(30.0f * A, ri7, -6.0f * tr * ri5), d = -12.0f * ri5;
+        a[4] = fmaf(c, dx, fmaf(d, wx, a[4]));
+        a[5] = fmaf(c, dy, fmaf(d, wy, a[5]));
+        a[6] = fmaf(c, dz, fmaf(d, wz, a[6]));
+        if constexpr (GRADU) {
+            const float r[3] = {dx, dy, dz}, w[3] = {wx, wy, wz};
+            const float h = 15.0f * A * ri7, g = -6.0f * ri5;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const float hr = h * r[i], gr = g * r[i];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    float &o = a[7 + 3 * i + j];
+                    o = fmaf(hr, r[j], fmaf(gr, w[j], i == j ? o + t : o));
+                }
+            }
+        }
+    }
+};
+
 // ------------------------------------------------------------------ 4-Laplace target side
 // Equivalent point with charges phi[0..2], psi (Stokes) or q (Laplace);
 // s = psi - (x - c).phi is formed per target by the caller.
@@ -346,6 +416,41 @@ struct EPVel {            // p = (r.phi)/r^3 [x 1/(4 pi) -> x2 for 1/(8 pi)], u 
         a[1] = fmaf(ri, fmaf(dx, t, ph[0]), a[1]);
         a[2] = fmaf(ri, fmaf(dy, t, ph[1]), a[2]);
         a[3] = fmaf(ri, fmaf(dz, t, ph[2]), a[3]);
+    }
+};
+
+// p, u, grad p (= lap u) and with GRADU grad u of one equivalent point, with
+// s = psi - (x - c).phi (so d_k s = -phi_k):
+//   d_k u_i = (phi_k r_i - phi_i r_k)/r^3 + s (3 r_i r_k/r^5 - delta_ik/r^3)   [x 1/(8 pi)]
+template <bool GRADU>
+struct EPVelDeriv {
+    static constexpr int NC = 4, NACC = GRADU ? 16 : 7;
+    __device__ static void eq(float dx, float dy, float dz, float ri, const float *ph, float s, float *a) {
+        const float ri2 = ri * ri, ri3 = ri2 * ri, ri5 = ri3 * ri2;
+        const float rp = dot3(dx, dy, dz, ph[0], ph[1], ph[2]);
+        a[0] = fmaf(2.0f * rp, ri3, a[0]);
+        const float t = -s * ri2;
+        a[1] = fmaf(ri, fmaf(dx, t, ph[0]), a[1]);
+        a[2] = fmaf(ri, fmaf(dy, t, ph[1]), a[2]);
+        a[3] = fmaf(ri, fmaf(dz, t, ph[2]), a[3]);
+        const float c = -6.0f * rp * ri5, d = 2.0f * ri3;
+        a[4] = fmaf(c, dx, fmaf(d, ph[0], a[4]));
+        a[5] = fmaf(c, dy, fmaf(d, ph[1], a[5]));
+        a[6] = fmaf(c, dz, fmaf(d, ph[2], a[6]));
+        if constexpr (GRADU) {
+            const float r[3] = {dx, dy, dz};
+            const float P[3] = {ph[0] * ri3, ph[1] * ri3, ph[2] * ri3};
+            const float e = 3.0f * s * ri5, sd = s * ri3;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const float er = e * r[i];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    float &o = a[7 + 3 * i + k];
+                    o = fmaf(er, r[k], fmaf(P[k], r[i], fmaf(-P[i], r[k], i == k ? o - sd : o)));
+                }
+            }
+        }
     }
 };
 

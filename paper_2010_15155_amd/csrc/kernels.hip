@@ -925,7 +925,7 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs a) {
     const int4 tr = a.chunk_tasks[blockIdx.x];     // {p2p t0, t1, l2t t0, t1}
     const int t = ch.y + int(threadIdx.x);
     if (t >= ch.z) return;
-    double v[10];
+    double v[kMaxAcc];
     for (int k = 0; k < a.nacc; ++k) v[k] = 0.0;
     for (int q = tr.x; q < tr.y; ++q) {
         const double *p = a.near + (int64_t(q) * 256 + threadIdx.x) * a.nacc;
@@ -950,7 +950,7 @@ __global__ __launch_bounds__(256) void direct_f64_kernel(DirectArgs a) {
     const int64_t ti = active ? t : 0;
     const int slice = blockIdx.y;
     const double x0 = a.trg[3 * ti], x1 = a.trg[3 * ti + 1], x2 = a.trg[3 * ti + 2];
-    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double acc[kMaxAcc] = {};
     __shared__ double ys[256 * 13];
     for (int pass = 0; pass < 2; ++pass) {
         const int64_t ns = pass == 0 ? a.n_sl : a.n_dl;
@@ -1097,6 +1097,43 @@ struct F64PVel {
         }
     }
 };
+// (p, u, grad p, grad u) (16), or with LAP (p, u, lap u) (7)
+template <bool LAP>
+struct F64PVelDeriv {
+    __device__ static void pair(int pass, const double *r, const double *v, double *a) {
+        double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (rr == 0.0) return;
+        double ri = 1.0 / sqrt(rr), ri3 = ri / rr, ri5 = ri3 / rr, ri7 = ri5 / rr;
+        if (pass == 0) {
+            const double rf = r[0] * v[0] + r[1] * v[1] + r[2] * v[2], g = rf - v[3];
+            a[0] += kInv4Pi * rf * ri3;
+            for (int i = 0; i < 3; ++i) {
+                a[1 + i] += kInv8Pi * (v[i] * ri + r[i] * g * ri3);
+                a[4 + i] += kInv8Pi * (2.0 * v[i] * ri3 - 6.0 * rf * r[i] * ri5);
+                if (!LAP)
+                    for (int j = 0; j < 3; ++j)
+                        a[7 + 3 * i + j] += kInv8Pi * ((r[i] * v[j] - v[i] * r[j] + (i == j ? g : 0.0)) * ri3 -
+                                                       3.0 * g * r[i] * r[j] * ri5);
+            }
+        } else {
+            double w[3], tr = v[0] + v[4] + v[8];
+            for (int j = 0; j < 3; ++j) {
+                w[j] = 0;
+                for (int k = 0; k < 3; ++k) w[j] += 0.5 * (v[3 * j + k] + v[3 * k + j]) * r[k];
+            }
+            const double A = r[0] * w[0] + r[1] * w[1] + r[2] * w[2];
+            a[0] += kInv4Pi * (-3.0 * A * ri5 + tr * ri3);
+            for (int i = 0; i < 3; ++i) {
+                a[1 + i] += -3.0 * kInv8Pi * r[i] * A * ri5;
+                a[4 + i] += kInv8Pi * (-12.0 * w[i] * ri5 + (30.0 * A * ri7 - 6.0 * tr * ri5) * r[i]);
+                if (!LAP)
+                    for (int j = 0; j < 3; ++j)
+                        a[7 + 3 * i + j] += -3.0 * kInv8Pi * ((i == j ? A * ri5 : 0.0) + 2.0 * r[i] * w[j] * ri5 -
+                                                              5.0 * r[i] * r[j] * A * ri7);
+            }
+        }
+    }
+};
 struct F64Traction {
     __device__ static void pair(int pass, const double *r, const double *v, double *a) {
         double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
@@ -1167,6 +1204,10 @@ hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, hipStream_t s) {
         case kLapPGradGrad: hipLaunchKernelGGL(p2p_kernel<DLapPGradGrad>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kStokesRegVelOmega:
             hipLaunchKernelGGL(p2p_kernel<DStokesRegFT>, dim3(ntasks), dim3(256), 0, s, a);
+            break;
+        case kPVelGrad: hipLaunchKernelGGL(p2p_kernel<DPVelDeriv<true>>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kPVelLaplacian:
+            hipLaunchKernelGGL(p2p_kernel<DPVelDeriv<false>>, dim3(ntasks), dim3(256), 0, s, a);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -1302,6 +1343,10 @@ hipError_t launch_l2t(int kernel, int ntasks, const L2TArgs &a, hipStream_t s) {
         case kStokesRegVel: hipLaunchKernelGGL(l2t_kernel<EStokeslet>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kLapPGradGrad: hipLaunchKernelGGL(l2t_kernel<ELapPGradGrad>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kStokesRegVelOmega: hipLaunchKernelGGL(l2t_kernel<EStokesFT>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kPVelGrad: hipLaunchKernelGGL(l2t_kernel<EPVelDeriv<true>>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kPVelLaplacian:
+            hipLaunchKernelGGL(l2t_kernel<EPVelDeriv<false>>, dim3(ntasks), dim3(256), 0, s, a);
+            break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1341,6 +1386,10 @@ hipError_t launch_direct_f64(int kernel, const DirectArgs &a, hipStream_t s) {
         case kStokesRegVelOmega:
             hipLaunchKernelGGL(direct_f64_kernel<F64StokesRegFT>, g, dim3(256), 0, s, a);
             break;
+        case kPVelGrad: hipLaunchKernelGGL(direct_f64_kernel<F64PVelDeriv<false>>, g, dim3(256), 0, s, a); break;
+        case kPVelLaplacian:
+            hipLaunchKernelGGL(direct_f64_kernel<F64PVelDeriv<true>>, g, dim3(256), 0, s, a);
+            break;
         default: return hipErrorInvalidValue;
     }
     if (a.slices > 1) {
@@ -1360,6 +1409,8 @@ bool p2p_uses_rel(int kernel) {
         case kStokesRegVel: return DStokesReg::REL;
         case kLapPGradGrad: return DLapPGradGrad::REL;
         case kStokesRegVelOmega: return DStokesRegFT::REL;
+        case kPVelGrad: return DPVelDeriv<true>::REL;
+        case kPVelLaplacian: return DPVelDeriv<false>::REL;
         default: return false;
     }
 }

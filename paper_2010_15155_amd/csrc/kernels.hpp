@@ -100,9 +100,11 @@ struct L2TArgs {
     double *part;              // [task][256][NACC]
 };
 
+constexpr int kMaxAcc = 16;    // most accumulated / output components of any kernel
+
 struct CombineMap {
-    int src[10];
-    double scale[10];
+    int src[kMaxAcc];
+    double scale[kMaxAcc];
 };
 
 struct CombineArgs {

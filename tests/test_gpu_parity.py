@@ -17,12 +17,14 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 KERNELS = ["Stokeslet", "RPY", "LapPGrad", "PVel", "Traction", "StokesRegVel", "StokesRegVelOmega",
-           "LapPGradGrad"]
+           "LapPGradGrad", "PVelGrad", "PVelLaplacian"]
 FIELDS = {"Stokeslet": [("u", 0, 3)], "RPY": [("u", 0, 3), ("lap u", 3, 6)], "StokesRegVel": [("u", 0, 3)],
           "StokesRegVelOmega": [("u", 0, 3), ("omega", 3, 6)],
           "LapPGrad": [("phi", 0, 1), ("grad phi", 1, 4)],
           "LapPGradGrad": [("phi", 0, 1), ("grad phi", 1, 4), ("hess phi", 4, 10)], "PVel": [("p", 0, 1), ("u", 1, 4)],
-          "Traction": [("sigma", 0, 9)]}
+          "Traction": [("sigma", 0, 9)],
+          "PVelGrad": [("p", 0, 1), ("u", 1, 4), ("grad p", 4, 7), ("grad u", 7, 16)],
+          "PVelLaplacian": [("p", 0, 1), ("u", 1, 4), ("lap u", 4, 7)]}
 
 
 @pytest.fixture(scope="module")
