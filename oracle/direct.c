@@ -25,6 +25,7 @@
  *                                                             Sec. II.C, Eqs. stkdlp, stkdlvel
  *   Traction sigma = -p I + grad u + grad u^T                 Sec. II.C, Eq. stressdef
  *   PVelGrad / PVelLaplacian: (p, u) and their derivatives   tab:implement
+ *   LapQPGradGrad phi = Q_jk d_j d_k L                       Sec. II.A, tab:implement
  * Output component orders (the paper prints none; see the oracle README
  * strings in direct.py): Hessian (xx,xy,xz,yy,yz,zz), D and sigma row-major.
  */
@@ -206,6 +207,51 @@ void oracle_laplace(int64_t nsl, const double *ysl, const double *q,
             }
         }
         for (int k = 0; k < kt; ++k) out[kt*t+k] = c * acc[k];
+    }
+}
+
+/* Laplace quadrupoles Q (9, row-major Q[3j+k] = Q_jk) -> phi, grad phi,
+ * Hessian (xx,xy,xz,yy,yz,zz) (10).  phi = Q_jk d_j d_k L with L = 1/(4 pi r)
+ * (Sec. II.A, the quadrupole kernel), so the outputs contract Q with the
+ * second, third and fourth derivatives of 1/r:
+ *   T2_jk   = 3 r_j r_k/r^5 - delta_jk/r^3
+ *   T3_ijk  = -15 r_i r_j r_k/r^7 + 3 (delta_ij r_k + delta_ik r_j + delta_jk r_i)/r^5
+ *   T4_lijk = 105 r_l r_i r_j r_k/r^9 - 15 (six delta_ab r_c r_d terms)/r^7
+ *             + 3 (delta_li delta_jk + delta_lj delta_ik + delta_lk delta_ij)/r^5 */
+static double kd(int a, int b) { return a == b ? 1.0 : 0.0; }
+
+void oracle_laplace_quad(int64_t nq, const double *y, const double *Q,
+                         int64_t nt, const double *xs, double *out)
+{
+    const double c = 1.0 / (4.0 * PI);
+#pragma omp parallel for schedule(dynamic, 16) if (nt * nq > 200000)
+    for (int64_t t = 0; t < nt; ++t) {
+        double acc[10] = {0};
+        for (int64_t s = 0; s < nq; ++s) {
+            double r[3] = {xs[3*t] - y[3*s], xs[3*t+1] - y[3*s+1], xs[3*t+2] - y[3*s+2]};
+            double rr = r[0]*r[0] + r[1]*r[1] + r[2]*r[2];
+            if (rr == 0.0) continue;
+            double i1 = 1.0 / sqrt(rr), i3 = i1 / rr, i5 = i3 / rr, i7 = i5 / rr, i9 = i7 / rr;
+            const double *Qs = Q + 9*s;
+            for (int j = 0; j < 3; ++j)
+                for (int k = 0; k < 3; ++k) {
+                    const double q = Qs[3*j+k];
+                    acc[0] += q * (3.0 * r[j] * r[k] * i5 - kd(j, k) * i3);
+                    for (int i = 0; i < 3; ++i)
+                        acc[1+i] += q * (-15.0 * r[i] * r[j] * r[k] * i7
+                                         + 3.0 * (kd(i, j) * r[k] + kd(i, k) * r[j] + kd(j, k) * r[i]) * i5);
+                    int h = 4;
+                    for (int l = 0; l < 3; ++l)
+                        for (int i = l; i < 3; ++i) {
+                            double t4 = 105.0 * r[l] * r[i] * r[j] * r[k] * i9
+                                      - 15.0 * (kd(l, i) * r[j] * r[k] + kd(l, j) * r[i] * r[k] + kd(l, k) * r[i] * r[j]
+                                                + kd(i, j) * r[l] * r[k] + kd(i, k) * r[l] * r[j] + kd(j, k) * r[l] * r[i]) * i7
+                                      + 3.0 * (kd(l, i) * kd(j, k) + kd(l, j) * kd(i, k) + kd(l, k) * kd(i, j)) * i5;
+                            acc[h++] += q * t4;
+                        }
+                }
+        }
+        for (int k = 0; k < 10; ++k) out[10*t+k] = c * acc[k];
     }
 }
 

@@ -32,6 +32,7 @@ def lib():
         for name in ("oracle_stokeslet", "oracle_rpy", "oracle_stokes_reg", "oracle_stokes_reg_ft"):
             getattr(_lib, name).argtypes = [_i64, _dp, _dp, _i64, _dp, _dp]
         _lib.oracle_laplace.argtypes = [_i64, _dp, _dp, _i64, _dp, _dp, _i64, _dp, _dp, ctypes.c_int]
+        _lib.oracle_laplace_quad.argtypes = [_i64, _dp, _dp, _i64, _dp, _dp]
         _lib.oracle_pvel_deriv.argtypes = [_i64, _dp, _dp, _i64, _dp, _dp, _i64, _dp, _dp, ctypes.c_int]
         for name in ("oracle_pvel", "oracle_traction"):
             getattr(_lib, name).argtypes = [_i64, _dp, _dp, _i64, _dp, _dp, _i64, _dp, _dp]
@@ -107,6 +108,16 @@ def laplace(sl=None, q=None, dl=None, d=None, trg=None, hess=False):
     return out
 
 
+def laplace_quad(sl=None, Q=None, trg=None):
+    """Quadrupoles Q (9, row-major) -> phi, grad phi, Hessian (xx,xy,xz,yy,yz,zz)."""
+    sl, nsl = _arr(sl, 3)
+    Q, _ = _arr(Q, 9)
+    trg, nt = _arr(trg, 3)
+    out = np.zeros((nt, 10))
+    lib().oracle_laplace_quad(nsl, _p(sl), _p(Q), nt, _p(trg), _p(out))
+    return out
+
+
 def pvel(sl=None, fq=None, dl=None, D=None, trg=None):
     sl, nsl = _arr(sl, 3)
     fq, _ = _arr(fq, 4)
@@ -155,6 +166,8 @@ def evaluate(kernel, sl=None, sl_val=None, dl=None, dl_val=None, trg=None):
         return laplace(sl, sl_val, dl, dl_val, trg)
     if kernel == "LapPGradGrad":
         return laplace(sl, sl_val, dl, dl_val, trg, hess=True)
+    if kernel == "LapQPGradGrad":
+        return laplace_quad(sl, sl_val, trg)
     if kernel == "PVel":
         return pvel(sl, sl_val, dl, dl_val, trg)
     if kernel == "Traction":

@@ -383,6 +383,50 @@ def test_pvel_derivatives_are_fd_of_pvel():
     assert np.allclose(np.trace(g0[:, 7:].reshape(-1, 3, 3), axis1=1, axis2=2), 0, atol=1e-10 * np.abs(g0).max())
 
 
+def _quad_as_charges(y, Q, h):
+    # Q_jk d_j d_k L(x - y) = Q_jk d/dy_j d/dy_k L(x - y): the central difference
+    # in y puts charges Q_jk/(4 h^2) (+, -, -, +) at y +- h e_j +- h e_k
+    pos, q = [], []
+    for s in range(len(y)):
+        for j in range(3):
+            for k in range(3):
+                for sj, sk, sg in ((1, 1, 1), (1, -1, -1), (-1, 1, -1), (-1, -1, 1)):
+                    p = y[s].copy()
+                    p[j] += sj * h
+                    p[k] += sk * h
+                    pos.append(p)
+                    q.append(sg * Q[s, 3 * j + k] / (4 * h * h))
+    return np.array(pos), np.array(q)
+
+
+def test_quadrupole_is_the_limit_of_charges():
+    # every output (phi, grad phi, Hessian) against the charge kernel applied
+    # to the finite-difference charges, Richardson-extrapolated (error O(h^4))
+    y, Q = _pts(3), RNG.standard_normal((3, 9))
+    x = _probe()
+    got = direct.laplace_quad(y, Q, x)
+    ref = []
+    for h in (2e-3, 4e-3):
+        pos, q = _quad_as_charges(y, Q, h)
+        ref.append(direct.laplace(pos, q, None, None, x, hess=True))
+    ref = (4 * ref[0] - ref[1]) / 3
+    assert np.allclose(got, ref, rtol=1e-8, atol=1e-8 * np.abs(ref).max())
+
+
+def test_quadrupole_invariants():
+    y, x = _pts(4), _probe()
+    # the isotropic and the antisymmetric parts of Q make no field
+    assert np.abs(direct.laplace_quad(y, np.tile(np.eye(3).ravel(), (4, 1)), x)).max() < 1e-13
+    A = RNG.standard_normal((4, 3, 3))
+    assert np.abs(direct.laplace_quad(y, (A - A.transpose(0, 2, 1)).reshape(4, 9), x)).max() < 1e-13
+    # harmonic: zero Hessian trace; grad phi = FD of phi
+    Q = RNG.standard_normal((4, 9))
+    g = direct.laplace_quad(y, Q, x)
+    assert np.allclose(g[:, 4] + g[:, 7] + g[:, 9], 0, atol=1e-12 * np.abs(g).max())
+    J = _fd.grad(lambda xx: direct.laplace_quad(y, Q, xx)[:, :1], x, h=1e-3)
+    assert np.allclose(g[:, 1:4], J[:, 0, :], rtol=1e-7, atol=1e-9 * np.abs(J).max())
+
+
 def test_rel_l2():
     assert direct.rel_l2([1.0, 0.0], [1.0, 0.0]) == 0.0
     assert direct.rel_l2([2.0, 0.0], [1.0, 0.0]) == 1.0
