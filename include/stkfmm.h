@@ -55,6 +55,7 @@ typedef enum {
  * kernels (tab:implement):                     SL        DL       target
  *   LAP_PGRAD      q -> phi, grad phi          q (1)     d (3)    (phi, dphi/dx, dphi/dy, dphi/dz) (4)
  *   LAP_PGRADGRAD  q -> phi, grad, Hessian     q (1)     d (3)    (phi, grad phi, xx xy xz yy yz zz) (10)
+ *   LAP_QPGRADGRAD Q -> phi, grad, Hessian     Q (9)     --       (phi, grad phi, xx xy xz yy yz zz) (10)
  *   STOKESLET      f -> u                      f (3)     --       u (3)
  *   RPY            [f, b] -> [u, lap u]        f,b (4)   --       (u, lap u) (6)
  *   PVEL           [f, q], D -> [p, u]         f,q (4)   D (9)    (p, u) (4)
@@ -69,7 +70,8 @@ typedef enum {
  * O((eps/r)^4), so eps must be far smaller than the smallest leaf box.
  * STOKES_REG_VEL_OMEGA adds point torques t and the angular velocity
  * w = curl(u)/2 (the force-torque extension of Sec. II.B, tab:ktab_regftvw).
- * D, sigma and grad u are row-major 3x3 (D[3j+k] = D_jk, sigma[3i+j],
+ * LAP_QPGRADGRAD's quadrupole gives phi = Q_jk d_j d_k L, L = 1/(4 pi r) (Sec. II.A).
+ * Q, D, sigma and grad u are row-major 3x3 (D[3j+k] = D_jk, sigma[3i+j],
  * grad u[3i+j] = du_i/dx_j); q in the PVEL kernels and TRACTION is twice the
  * physical source (Sec. II.C); viscosity mu = 1.  Away from the sources
  * lap u = grad p (the Stokes equations), and PVEL_LAPLACIAN returns it as such. */
@@ -83,7 +85,8 @@ typedef enum {
     STKFMM_STOKES_REG_VEL_OMEGA = 6,
     STKFMM_LAP_PGRADGRAD = 7,
     STKFMM_PVEL_GRAD = 8,
-    STKFMM_PVEL_LAPLACIAN = 9
+    STKFMM_PVEL_LAPLACIAN = 9,
+    STKFMM_LAP_QPGRADGRAD = 10
 } stkfmm_kernel;
 
 /* Boundary conditions (Sec. III and its appendix on periodicity).  PXYZ is

@@ -41,6 +41,7 @@ static const KernelInfo kInfo[kNumKernels] = {
     {1, 3, 10, 1, 8, 12, 10},  // LapPGradGrad
     {4, 9, 16, 4, 12, 12, 16}, // PVelGrad
     {4, 9, 7, 4, 12, 12, 7},   // PVelLaplacian
+    {9, 0, 10, 1, 12, 0, 10},  // LapQPGradGrad
 };
 const KernelInfo &kernel_info(int k) { return kInfo[k]; }
 
@@ -83,7 +84,8 @@ struct DeviceOps {
     int p = 0, M = 0, Mp = 0, rank = 0;
     int kc = 0;                 // compressed V-list rank (0: dense m2l)
     bool periodic = false;
-    DevMem grid, m2m, l2l, m2l, uc2ue, dc2de, tm2l;   // pseudo-inverses [M][M] FP64
+    DevMem grid, m2m, m2l, uc2ue, dc2de, tm2l;   // pseudo-inverses [M][M] FP64
+    DevMem l2l_cc;              // [8][M][M] FP64 child check <- parent check
     DevMem basis_t, m2l_c;      // U_k^T [kc][Mp], cores [343][kc][kc]
 };
 
@@ -93,6 +95,12 @@ struct Batch {
     size_t tiles = 0, bcol = 0, ycol = 0, rdst = 0, roff = 0, rpair = 0, rscale = 0, rdelta = 0;
     int npairs = 0;
     int accumulate = 0;
+};
+
+// Downward check-to-check translations of one level, grouped by octant.
+struct L2LLevel {
+    int nblocks = 0;
+    size_t blocks = 0, pairs = 0, delta = 0;
 };
 
 struct PinvLevel {
@@ -158,7 +166,8 @@ struct stkfmm_ctx {
     double w_direct_frac = 0.73, x_direct_frac = 0.5;
     int64_t p2p_task_sources = 2048;
     Batch m2l;
-    std::vector<Batch> m2m, l2l;            // by level (parent level / child level)
+    std::vector<Batch> m2m;                 // by parent level
+    std::vector<L2LLevel> l2l;              // by child level
     std::vector<PinvLevel> upinv, dnpinv;   // by level
     int lmin_up = 0, lmin_dn = 0;
     size_t ybuf_floats = 0;
@@ -191,12 +200,13 @@ int sl_kind(int k) {
         case kLapPGradGrad: return 2;
         case kStokesRegVel: return 6;
         case kStokesRegVelOmega: return 7;
+        case kLapQPGradGrad: return 8;
         default: return 4;
     }
 }
 // The regularized Stokeslet's far field is the RPY one with b^2 = 3 eps^2 / 2
 // (to O(eps^4 / r^5)): its packed records carry that b^2 where RPY's do.
-int stage_kind(int k) { return k == kStokesRegVel ? 1 : sl_kind(k); }   // kind 7 packs and stages alike
+int stage_kind(int k) { return k == kStokesRegVel ? 1 : sl_kind(k); }   // kinds 7, 8 pack and stage alike
 int dl_kind(int k) { return k == kLapPGrad || k == kLapPGradGrad ? 3 : 5; }
 
 stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, DeviceOps **out) {
@@ -224,7 +234,7 @@ stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, DeviceOps **out) {
     };
     HIP_TRY(c, up(d->grid, g.data(), g.size() * sizeof(float)));
     HIP_TRY(c, up(d->m2m, h.m2m.data(), h.m2m.size() * sizeof(float)));
-    HIP_TRY(c, up(d->l2l, h.l2l.data(), h.l2l.size() * sizeof(float)));
+    HIP_TRY(c, up(d->l2l_cc, h.l2l_cc.data(), h.l2l_cc.size() * sizeof(double)));
     if (h.kc > 0) {
         std::vector<float> bt(size_t(h.kc) * h.Mp);     // U_k^T
         for (int i = 0; i < h.Mp; ++i)
@@ -953,7 +963,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     }
     // M2M (by parent level) and L2L (by child level), grouped by octant
     c->m2m.assign(t.depth + 1, Batch());
-    c->l2l.assign(t.depth + 1, Batch());
+    c->l2l.assign(t.depth + 1, L2LLevel());
     c->upinv.assign(t.depth + 1, PinvLevel());
     c->dnpinv.assign(t.depth + 1, PinvLevel());
     for (int l = 0; l <= t.depth; ++l) {
@@ -996,7 +1006,8 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
                     pr.scale = 1.0 / geom[B.parent].w;
                     dn.push_back(pr);
                 }
-                for (int k = 0; k < nc; ++k) {
+                // densities only where targets read them: L2T at leaves
+                for (int k = 0; k < nc && B.leaf; ++k) {
                     db.push_back(b * nc + k);
                     dcx.push_back(b * nc + k);
                     ds.push_back(hb);
@@ -1004,7 +1015,29 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
             }
         }
         c->m2m[l] = make_batch(ar, up, nc, 0, c->ybuf_floats, Mp);
-        c->l2l[l] = make_batch(ar, dn, nc, 1, c->ybuf_floats, Mp);
+        {
+            // child check <- parent check, blocks of 64 / nc pairs sharing an octant
+            std::stable_sort(dn.begin(), dn.end(), [](const Pair &x, const Pair &y) { return x.op < y.op; });
+            const int per = 64 / nc;
+            std::vector<int4> blocks;
+            std::vector<int2> prs;
+            std::vector<double> dl;
+            for (size_t i = 0; i < dn.size();) {
+                size_t j = i;
+                while (j < dn.size() && dn[j].op == dn[i].op && int(j - i) < per) ++j;
+                blocks.push_back(make_int4(dn[i].op, int(i), int(j - i), 0));
+                i = j;
+            }
+            for (const Pair &pr : dn) {
+                prs.push_back(make_int2(pr.src, pr.dst));
+                for (int k = 0; k < 3; ++k) dl.push_back((&geom[pr.dst].x)[k] - (&geom[pr.src].x)[k]);
+            }
+            L2LLevel &ll = c->l2l[l];
+            ll.nblocks = int(blocks.size());
+            ll.blocks = ar.add(blocks);
+            ll.pairs = ar.add(prs);
+            ll.delta = ar.add(dl);
+        }
         PinvLevel &pu = c->upinv[l];
         pu.ncol = int(ub.size());
         pu.bidx = ar.add(ub);
@@ -1084,9 +1117,10 @@ CombineMap combine_map(int k, double L) {
             break;
         case kLapPGrad:
         case kLapPGradGrad:
+        case kLapQPGradGrad:
             m.src[0] = 0, m.scale[0] = c4 / L;
             for (int i = 1; i < 4; ++i) m.src[i] = i, m.scale[i] = c4 / (L * L);
-            if (k == kLapPGradGrad)
+            if (k != kLapPGrad)
                 for (int i = 4; i < 10; ++i) m.src[i] = i, m.scale[i] = c4 / (L * L * L);
             break;
         case kPVel:
@@ -1154,6 +1188,17 @@ __global__ void pack_values_kernel(int64_t n, const double *__restrict__ val, co
             o[9] = float(v[3] * inv_len); o[10] = float(v[4] * inv_len); o[11] = float(v[5] * inv_len);
             o[12] = float(1.5 * e * e);
             o[13] = float(e * e);
+            break;
+        }
+        case 8: {   // Laplace quadrupole: Q^s / L^2 (xx, xy, xz, yy, yz, zz)
+            const double *Q = val + 9 * j;
+            const double s2 = inv_len * inv_len;
+            o[6] = float(Q[0] * s2);
+            o[7] = float(0.5 * (Q[1] + Q[3]) * s2);
+            o[8] = float(0.5 * (Q[2] + Q[6]) * s2);
+            o[9] = float(Q[4] * s2);
+            o[10] = float(0.5 * (Q[5] + Q[7]) * s2);
+            o[11] = float(Q[8] * s2);
             break;
         }
         case 6: {   // regularized Stokeslet: f, then (3/2) eps^2 (far field) and eps^2 (P2P)
@@ -1329,8 +1374,15 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         if (periodic) HIP_TRY(c, launch_periodic(o.tm2l.as<double>(), updens, dnchk, o.M, o.Mp, nc, 0, s));
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 5 S2L + periodic
         for (int l = c->lmin_dn; l <= t.depth; ++l) {
-            st = run_batch(c, c->l2l[l], o.l2l.as<float>(), dndens, dnchk, s);
-            if (st != STKFMM_OK) return st;
+            const L2LLevel &ll = c->l2l[l];
+            L2LArgs la;
+            la.ops = o.l2l_cc.as<double>();
+            la.M = o.M;
+            la.blocks = at<int4>(c, ll.blocks);
+            la.pairs = at<int2>(c, ll.pairs);
+            la.delta = at<double>(c, ll.delta);
+            la.chk = dnchk;
+            HIP_TRY(c, launch_l2l_check(ll.nblocks, nc, la, s));
             st = run_pinv(c, c->dnpinv[l], o.dc2de.as<double>(), dnchk, dndens, s);
             if (st != STKFMM_OK) return st;
         }
@@ -1437,11 +1489,11 @@ stkfmm_status sampled_error(stkfmm_ctx *c, const double *sl_val, const double *d
     HIP_TRY(c, hipMemcpyAsync(ref.data(), c->vbuf[3].p, ref.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     // output fields: (u), (u, lap u), (phi, grad phi), (p, u), (sigma), (u, omega),
-    // (phi, grad phi, Hessian), (p, u, grad p, grad u), (p, u, lap u)
+    // (phi, grad phi, Hessian), (p, u, grad p, grad u), (p, u, lap u), (phi, grad phi, Hessian)
     static const int fields[kNumKernels][5] = {{0, 1, 4, 4, 4},  {0, 3, 3, 3, 3},  {0, 3, 6, 6, 6},
                                                {0, 1, 4, 4, 4},  {0, 9, 9, 9, 9},  {0, 3, 3, 3, 3},
                                                {0, 3, 6, 6, 6},  {0, 1, 4, 10, 10}, {0, 1, 4, 7, 16},
-                                               {0, 1, 4, 7, 7}};
+                                               {0, 1, 4, 7, 7},  {0, 1, 4, 10, 10}};
     const int *fb = fields[c->kernel];
     double worst = 0.0;
     for (int f = 0; f < 4; ++f) {

@@ -21,7 +21,8 @@ constexpr double kAlphaIn = 1.05;
 constexpr double kAlphaOut = 2.95;
 
 enum Kernel { kLapPGrad = 0, kStokeslet = 1, kRPY = 2, kPVel = 3, kTraction = 4, kStokesRegVel = 5,
-              kStokesRegVelOmega = 6, kLapPGradGrad = 7, kPVelGrad = 8, kPVelLaplacian = 9, kNumKernels = 10 };
+              kStokesRegVelOmega = 6, kLapPGradGrad = 7, kPVelGrad = 8, kPVelLaplacian = 9,
+              kLapQPGradGrad = 10, kNumKernels = 11 };
 
 struct KernelInfo {
     int k_sl, k_dl, k_trg;   // user value widths
@@ -101,7 +102,7 @@ struct Operators {
     // DC2DE = P2^T * P1^T (kernel symmetry), all FP64
     std::vector<double> up1, up2;
     std::vector<float> m2m;          // [8][Mp][Mp]  parent check <- child equivalent (parent side 1)
-    std::vector<float> l2l;          // [8][Mp][Mp]  child check <- parent equivalent (parent side 1)
+    std::vector<double> l2l_cc;      // [8][M][M]    child check <- parent check (L2L * DC2DE, scale free)
     std::vector<float> m2l;          // [343][Mp][Mp] check <- equivalent at offset (side 1); |o|<=1 unused;
                                      // empty when the translations are compressed (kc > 0)
     int kc = 0;                      // rank of the compressed V-list translations (multiple of 32), 0 = dense

@@ -23,6 +23,8 @@
 //               d_j u_i = -3 delta_ij A/r^5 - 6 r_i w_j/r^5 + 15 A r_i r_j/r^7
 //               lap u = grad p for both (Stokes equations; the q r/r^3 part is harmonic)
 //                                                                   [x 1/8pi] tab:implement
+//   Laplace Q   phi = Q_jk d_j d_k (1/r) = 3 r.Q.r/r^5 - tr Q/r^3, with its
+//               gradient and Hessian                                [x 1/4pi] Sec. II.A
 //   Traction SL sigma = 3 (q - r.f) r r^T/r^5 - q I/r^3             [x 1/4pi] Eq. stressdef
 //   Traction DL sigma = -tr D I/r^3 - 3 (r w^T + w r^T)/r^5 + 15 A r r^T/r^7, w = D^s r
 //                                                                   [x 1/4pi] Eq. stressdef
@@ -209,6 +211,41 @@ struct DLapPGradGrad {    // SL q ; DL d0 d1 d2      out phi, grad phi, Hessian 
         a[8] = fmaf(ey, dz, fmaf(g, fmaf(d1, dz, d2 * dy), a[8]));
         a[9] = fmaf(e * dz, dz, fmaf(g, 2.0f * d2 * dz, a[9] + t));
     }
+};
+
+// Laplace quadrupole Q^s (xx, xy, xz, yy, yz, zz): phi = Q_jk d_j d_k (1/r) and
+// its gradient and Hessian, written with the unit vector n = r/r so that no
+// power of 1/r above 5 is formed (1/r^9 would overflow FP32 for close pairs):
+//   phi   = (3 B - tr)/r^3,                B = n.Q.n, w = Q n
+//   d_i   = (6 w_i + (3 tr - 15 B) n_i)/r^4
+//   d_ij  = (6 Q_ij - 30 (w_i n_j + n_i w_j) + (105 B - 15 tr) n_i n_j
+//            + (3 tr - 15 B) delta_ij)/r^5                        [x 1/4pi]
+struct DLapQPGradGrad {   // SL Q^s (6)                            out phi, grad phi, Hessian (10)
+    static constexpr int RS = 12, RD = 12, NACC = 10;
+    static constexpr bool REL = false;
+    __device__ static void sl(float dx, float dy, float dz, float ri, const float *v, float *a) {
+        const float nx = dx * ri, ny = dy * ri, nz = dz * ri;
+        const float wx = dot3(v[0], v[1], v[2], nx, ny, nz);
+        const float wy = dot3(v[1], v[3], v[4], nx, ny, nz);
+        const float wz = dot3(v[2], v[4], v[5], nx, ny, nz);
+        const float B = dot3(nx, ny, nz, wx, wy, wz), tr = v[0] + v[3] + v[5];
+        const float ri2 = ri * ri, ri3 = ri2 * ri, ri4 = ri2 * ri2, ri5 = ri4 * ri;
+        a[0] = fmaf(fmaf(3.0f, B, -tr), ri3, a[0]);
+        const float c = fmaf(3.0f, tr, -15.0f * B) * ri4, w6 = 6.0f * ri4;
+        a[1] = fmaf(c, nx, fmaf(w6, wx, a[1]));
+        a[2] = fmaf(c, ny, fmaf(w6, wy, a[2]));
+        a[3] = fmaf(c, nz, fmaf(w6, wz, a[3]));
+        const float e = fmaf(105.0f, B, -15.0f * tr) * ri5, g = -30.0f * ri5, q6 = 6.0f * ri5;
+        const float d = fmaf(3.0f, tr, -15.0f * B) * ri5;
+        const float ex = e * nx, ey = e * ny, gx = g * nx, gy = g * ny, gz = g * nz;
+        a[4] = fmaf(ex, nx, fmaf(2.0f * gx, wx, fmaf(q6, v[0], a[4] + d)));
+        a[5] = fmaf(ex, ny, fmaf(gx, wy, fmaf(gy, wx, fmaf(q6, v[1], a[5]))));
+        a[6] = fmaf(ex, nz, fmaf(gx, wz, fmaf(gz, wx, fmaf(q6, v[2], a[6]))));
+        a[7] = fmaf(ey, ny, fmaf(2.0f * gy, wy, fmaf(q6, v[3], a[7] + d)));
+        a[8] = fmaf(ey, nz, fmaf(gy, wz, fmaf(gz, wy, fmaf(q6, v[4], a[8]))));
+        a[9] = fmaf(e * nz, nz, fmaf(2.0f * gz, wz, fmaf(q6, v[5], a[9] + d)));
+    }
+    __device__ static void dl(float, float, float, float, const float *, float *) {}
 };
 
 // symmetric D^s stored (xx, xy, xz, yy, yz, zz)

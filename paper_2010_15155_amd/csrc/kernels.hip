@@ -237,6 +237,7 @@ __global__ __launch_bounds__(256) void rel_positions_kernel(const int *__restric
 //   3 Laplace d       [yr, d, 0, 0]              dipole
 //   4 Stokes f, q     [yr, f, yr.f + q, 0]       Phi_j charge f_j, Psi charge
 //   5 Stokes D^s      [yr, D^s (6), 0, 0, 0]     Phi_j dipole -D^s_j., Psi dipole -D^s yr
+//   8 Laplace Q^s     [yr, Q^s (6), 0, 0, 0]     quadrupole (second derivative of a charge)
 //   7 regularized     [yr, f, yr.f, 0, t, 0,     Phi_j charge f_j, Psi charge yr.f; the torque
 //     force, torque    m, 0]                      (rotlet) as Phi_i dipoles (e_i x t)/2 and, with
 //                                                 the eps^2 term, Psi dipole m = (eps^2/2) f + (yr x t)/2
@@ -250,6 +251,7 @@ template <> struct S2CKind<3> { static constexpr int NC = 1, RS = 8; };
 template <> struct S2CKind<4> { static constexpr int NC = 4, RS = 8; };
 template <> struct S2CKind<5> { static constexpr int NC = 4, RS = 12; };
 template <> struct S2CKind<7> { static constexpr int NC = 4, RS = 16; };
+template <> struct S2CKind<8> { static constexpr int NC = 1, RS = 12; };
 
 int s2c_stage_stride(int src_kind) {
     switch (src_kind) {
@@ -260,6 +262,7 @@ int s2c_stage_stride(int src_kind) {
         case 4: return S2CKind<4>::RS;
         case 5: return S2CKind<5>::RS;
         case 7: return S2CKind<7>::RS;
+        case 8: return S2CKind<8>::RS;
         default: return 0;
     }
 }
@@ -305,7 +308,7 @@ __global__ __launch_bounds__(256) void stage_sources_kernel(const int *__restric
             o[12] = fmaf(ce, f0, 0.5f * (yy * t2 - yz * t1));
             o[13] = fmaf(ce, f1, 0.5f * (yz * t0 - yx * t2));
             o[14] = fmaf(ce, f2, 0.5f * (yx * t1 - yy * t0));
-        } else {
+        } else {   // 5 and 8: the symmetric tensor as packed
 #pragma unroll
             for (int k = 0; k < 6; ++k) o[3 + k] = s[6 + k];
         }
@@ -377,6 +380,13 @@ __global__ __launch_bounds__(1024) void s2c_kernel(S2CArgs a) {
                     pot[i][1] = fmaf(hr3, y[10] * dx - y[8] * dz, pot[i][1]);
                     pot[i][2] = fmaf(hr3, y[8] * dy - y[9] * dx, pot[i][2]);
                     pot[i][3] = fmaf(dot3(y[12], y[13], y[14], dx, dy, dz), ri3, pot[i][3]);
+                } else if constexpr (SRC == 8) {
+                    // Q_jk d_j d_k (1/r) = 3 (d.Q.d)/r^5 - tr Q/r^3
+                    float wx, wy, wz;
+                    sym_apply(y + 3, dx, dy, dz, wx, wy, wz);
+                    const float ri2 = ri * ri, ri3 = ri2 * ri;
+                    const float B = dot3(dx, dy, dz, wx, wy, wz), tr = y[3] + y[6] + y[8];
+                    pot[i][0] = fmaf(fmaf(3.0f * B, ri2, -tr), ri3, pot[i][0]);
                 } else {
                     // w = D^s (z - y): Phi_j += -w_j / r^3, Psi += -(yr . w) / r^3
                     float wx, wy, wz;
@@ -723,6 +733,98 @@ __global__ __launch_bounds__(256) void gemm_f64(Gemm64Args a, TC *C) {
     }
 }
 
+// ------------------------------------------------------------------ downward check-to-check translation
+// chk[child][c][i] += sum_k L[op][i][k] * x[k], x = chk[parent][c] (for c = 3
+// of the 4-Laplace tree the Psi origin shift x = Psi - delta.Phi is applied
+// to the parent's values first: the translation is linear and the same for
+// every component).  FP64 throughout: these potentials feed the leaf
+// pseudo-inverses, which amplify rounding noise into the high-frequency
+// density modes that target derivatives see.  Block tile 64 rows x 64
+// columns (16 pairs x 4 components or 64 pairs x 1) as in gemm_f64.
+template <int NC>
+__global__ __launch_bounds__(256) void l2l_check_kernel(L2LArgs a) {
+    __shared__ double As[64 * 17];
+    __shared__ double Bs[64 * 17];
+    const int4 blk = a.blocks[blockIdx.y];
+    const int M = a.M, row0 = blockIdx.x * 64, ncol = blk.z * NC;
+    const double *A = a.ops + int64_t(blk.x) * M * M;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    doublex4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = doublex4{0.0, 0.0, 0.0, 0.0};
+    const double *pc[4];
+    int lr[4], lk[4], comp[4];
+    bool rok[4], cok[4];
+    double dx[4], dy[4], dz[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int idx = tid + 256 * i;
+        lr[i] = idx >> 4;
+        lk[i] = idx & 15;
+        rok[i] = row0 + lr[i] < M;
+        cok[i] = lr[i] < ncol;
+        const int pr = blk.y + (cok[i] ? lr[i] / NC : 0);
+        comp[i] = lr[i] % NC;
+        pc[i] = a.chk + int64_t(a.pairs[pr].x) * NC * M;
+        dx[i] = NC == 4 ? a.delta[3 * pr] : 0.0;
+        dy[i] = NC == 4 ? a.delta[3 * pr + 1] : 0.0;
+        dz[i] = NC == 4 ? a.delta[3 * pr + 2] : 0.0;
+    }
+    for (int k0 = 0; k0 < M; k0 += 16) {
+        double ra[4], rb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = k0 + lk[i];
+            const bool kok = k < M;
+            ra[i] = (rok[i] && kok) ? A[int64_t(row0 + lr[i]) * M + k] : 0.0;
+            double b = 0.0;
+            if (cok[i] && kok) {
+                b = pc[i][comp[i] * M + k];
+                if (NC == 4 && comp[i] == 3) b -= dx[i] * pc[i][k] + dy[i] * pc[i][M + k] + dz[i] * pc[i][2 * M + k];
+            }
+            rb[i] = b;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            As[lr[i] * 17 + lk[i]] = ra[i];
+            Bs[lr[i] * 17 + lk[i]] = rb[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+            const int k = kk + (lane >> 4);
+            double av[2], bv[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) av[i] = As[(wr + 16 * i + (lane & 15)) * 17 + k];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bv[j] = Bs[(wc + 16 * j + (lane & 15)) * 17 + k];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = wc + 16 * j + (lane & 15);
+        if (col >= ncol) continue;
+        const int pr = blk.y + col / NC, c = col % NC;
+        double *o = a.chk + (int64_t(a.pairs[pr].y) * NC + c) * M;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = row0 + wr + 16 * i + (lane >> 4) + 4 * v;
+                if (r < M) o[r] += acc[i][j][v];
+            }
+    }
+}
+
 // ------------------------------------------------------------------ translation reduce
 // chk[dst][c][m] (+)= sum over pairs p of scale_p * (Y_p[c][m] - [c == 3] delta_p . Y_p[0..2][m])
 // (the Psi origin shift; Laplace problems have one component and no shift).
@@ -1052,6 +1154,27 @@ struct F64LapHess {       // SL q, DL d -> phi, grad phi, Hessian (xx, xy, xz, y
         }
     }
 };
+// quadrupole Q (9, row-major): phi, grad phi, Hessian from w = Q^s r, B = r.w
+struct F64LapQuad {
+    __device__ static void pair(int, const double *r, const double *v, double *a) {
+        double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+        if (rr == 0.0) return;
+        double ri = 1.0 / sqrt(rr), ri3 = ri / rr, ri5 = ri3 / rr, ri7 = ri5 / rr, ri9 = ri7 / rr;
+        double Qs[3][3], w[3], tr = v[0] + v[4] + v[8];
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k) Qs[j][k] = 0.5 * (v[3 * j + k] + v[3 * k + j]);
+        for (int j = 0; j < 3; ++j) w[j] = Qs[j][0] * r[0] + Qs[j][1] * r[1] + Qs[j][2] * r[2];
+        const double B = r[0] * w[0] + r[1] * w[1] + r[2] * w[2];
+        a[0] += kInv4Pi * (3.0 * B * ri5 - tr * ri3);
+        for (int i = 0; i < 3; ++i) a[1 + i] += kInv4Pi * (6.0 * w[i] * ri5 + (3.0 * tr * ri5 - 15.0 * B * ri7) * r[i]);
+        int k = 4;
+        for (int i = 0; i < 3; ++i)
+            for (int j = i; j < 3; ++j)
+                a[k++] += kInv4Pi * (6.0 * Qs[i][j] * ri5 - 30.0 * (w[i] * r[j] + r[i] * w[j]) * ri7 +
+                                     (105.0 * B * ri9 - 15.0 * tr * ri7) * r[i] * r[j] +
+                                     (i == j ? 3.0 * tr * ri5 - 15.0 * B * ri7 : 0.0));
+    }
+};
 struct F64RPY {
     __device__ static void pair(int, const double *r, const double *v, double *a) {
         double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
@@ -1206,6 +1329,9 @@ hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, hipStream_t s) {
             hipLaunchKernelGGL(p2p_kernel<DStokesRegFT>, dim3(ntasks), dim3(256), 0, s, a);
             break;
         case kPVelGrad: hipLaunchKernelGGL(p2p_kernel<DPVelDeriv<true>>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kLapQPGradGrad:
+            hipLaunchKernelGGL(p2p_kernel<DLapQPGradGrad>, dim3(ntasks), dim3(256), 0, s, a);
+            break;
         case kPVelLaplacian:
             hipLaunchKernelGGL(p2p_kernel<DPVelDeriv<false>>, dim3(ntasks), dim3(256), 0, s, a);
             break;
@@ -1247,6 +1373,7 @@ hipError_t launch_s2c(int src_kind, int ntasks, const S2CArgs &a, hipStream_t s)
         case 4: launch_s2c_kind<4>(ntasks, a, s); break;
         case 5: launch_s2c_kind<5>(ntasks, a, s); break;
         case 7: launch_s2c_kind<7>(ntasks, a, s); break;
+        case 8: launch_s2c_kind<8>(ntasks, a, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1255,7 +1382,8 @@ hipError_t launch_s2c(int src_kind, int ntasks, const S2CArgs &a, hipStream_t s)
 hipError_t launch_stage_sources(int src_kind, int nleaves, const int *leaves, const int2 *box_range,
                                 const double4 *geom, const float *src, int rec, float *out, hipStream_t s) {
     if (nleaves <= 0) return hipSuccess;
-    const int need = src_kind == 2 ? 7 : src_kind == 1 || src_kind == 4 ? 10 : src_kind == 5 ? 12 : src_kind == 7 ? 13 : 9;
+    const int need = src_kind == 2 ? 7 : src_kind == 1 || src_kind == 4 ? 10 : src_kind == 5 || src_kind == 8 ? 12
+                   : src_kind == 7 ? 13 : 9;
     if (rec < need) return hipErrorInvalidValue;
     dim3 g(nleaves), b(256);
     switch (src_kind) {
@@ -1266,6 +1394,7 @@ hipError_t launch_stage_sources(int src_kind, int nleaves, const int *leaves, co
         case 4: hipLaunchKernelGGL(stage_sources_kernel<4>, g, b, 0, s, leaves, box_range, geom, src, rec, out); break;
         case 5: hipLaunchKernelGGL(stage_sources_kernel<5>, g, b, 0, s, leaves, box_range, geom, src, rec, out); break;
         case 7: hipLaunchKernelGGL(stage_sources_kernel<7>, g, b, 0, s, leaves, box_range, geom, src, rec, out); break;
+        case 8: hipLaunchKernelGGL(stage_sources_kernel<8>, g, b, 0, s, leaves, box_range, geom, src, rec, out); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1325,6 +1454,15 @@ hipError_t launch_reduce(int ntasks, const ReduceArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_l2l_check(int nblocks, int ncomp, const L2LArgs &a, hipStream_t s) {
+    if (nblocks <= 0) return hipSuccess;
+    if (a.M < 1 || (ncomp != 1 && ncomp != 4)) return hipErrorInvalidValue;
+    dim3 g((a.M + 63) / 64, nblocks);
+    if (ncomp == 4) hipLaunchKernelGGL(l2l_check_kernel<4>, g, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(l2l_check_kernel<1>, g, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_periodic(const double *T, const float *dens, double *chk, int M, int Mp, int nc, int root,
                            hipStream_t s) {
     hipLaunchKernelGGL(periodic_kernel, dim3(blocks_for(int64_t(M) * nc, 256)), dim3(256), 0, s, T, dens, chk,
@@ -1344,6 +1482,7 @@ hipError_t launch_l2t(int kernel, int ntasks, const L2TArgs &a, hipStream_t s) {
         case kLapPGradGrad: hipLaunchKernelGGL(l2t_kernel<ELapPGradGrad>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kStokesRegVelOmega: hipLaunchKernelGGL(l2t_kernel<EStokesFT>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kPVelGrad: hipLaunchKernelGGL(l2t_kernel<EPVelDeriv<true>>, dim3(ntasks), dim3(256), 0, s, a); break;
+        case kLapQPGradGrad: hipLaunchKernelGGL(l2t_kernel<ELapPGradGrad>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kPVelLaplacian:
             hipLaunchKernelGGL(l2t_kernel<EPVelDeriv<false>>, dim3(ntasks), dim3(256), 0, s, a);
             break;
@@ -1387,6 +1526,7 @@ hipError_t launch_direct_f64(int kernel, const DirectArgs &a, hipStream_t s) {
             hipLaunchKernelGGL(direct_f64_kernel<F64StokesRegFT>, g, dim3(256), 0, s, a);
             break;
         case kPVelGrad: hipLaunchKernelGGL(direct_f64_kernel<F64PVelDeriv<false>>, g, dim3(256), 0, s, a); break;
+        case kLapQPGradGrad: hipLaunchKernelGGL(direct_f64_kernel<F64LapQuad>, g, dim3(256), 0, s, a); break;
         case kPVelLaplacian:
             hipLaunchKernelGGL(direct_f64_kernel<F64PVelDeriv<true>>, g, dim3(256), 0, s, a);
             break;
@@ -1410,6 +1550,7 @@ bool p2p_uses_rel(int kernel) {
         case kLapPGradGrad: return DLapPGradGrad::REL;
         case kStokesRegVelOmega: return DStokesRegFT::REL;
         case kPVelGrad: return DPVelDeriv<true>::REL;
+        case kLapQPGradGrad: return DLapQPGradGrad::REL;
         case kPVelLaplacian: return DPVelDeriv<false>::REL;
         default: return false;
     }

@@ -70,6 +70,17 @@ struct Gemm64Args {
     int ncol;
 };
 
+// Downward translation of check potentials, child (+)= L2L_cc[op] * parent,
+// FP64.  Pairs are grouped by octant into blocks of 64 / ncomp pairs.
+struct L2LArgs {
+    const double *ops;         // [8][M][M]
+    int M;
+    const int4 *blocks;        // {op, first pair, pair count, 0}
+    const int2 *pairs;         // {parent box, child box}
+    const double *delta;       // [pair][3] c_child - c_parent (Psi origin shift, ncomp 4)
+    double *chk;               // [box][ncomp][M]
+};
+
 // Largest rank of compressed V-list translations.
 constexpr int kMaxCompressed = 512;
 
@@ -144,6 +155,7 @@ hipError_t launch_gemm_bf16x3(int ntiles, const GemmArgs &a, hipStream_t s);
 hipError_t launch_gemm_f64(const Gemm64Args &a, double *C, hipStream_t s);
 hipError_t launch_gemm_f64_to_f32(const Gemm64Args &a, float *C, hipStream_t s);
 hipError_t launch_reduce(int ntasks, const ReduceArgs &a, hipStream_t s);
+hipError_t launch_l2l_check(int nblocks, int ncomp, const L2LArgs &a, hipStream_t s);
 hipError_t launch_periodic(const double *T, const float *dens, double *chk, int M, int Mp, int nc, int root,
                            hipStream_t s);
 hipError_t launch_l2t(int kernel, int ntasks, const L2TArgs &a, hipStream_t s);

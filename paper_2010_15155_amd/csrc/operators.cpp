@@ -230,19 +230,37 @@ std::string build_operators(int p, double svd_tol, bool periodic, Operators &ops
     for (int k = 0; k < r; ++k)
         for (int j = 0; j < M; ++j) ops.up2[size_t(k) * M + j] = U[size_t(j) * M + k];
 
-    // octant operators (parent side 1, child side 1/2, child centre +-1/4)
+    // octant operators (parent side 1, child side 1/2, child centre +-1/4).
+    // The downward translation maps the parent's check potentials straight to
+    // the child's: L2L[o] * DC2DE (child dc <- parent de <- parent dc), formed
+    // here in FP64; it is scale free (the two factors scale as 1/h and h).
     ops.m2m.assign(size_t(8) * Mp * Mp, 0.0f);
-    ops.l2l.assign(size_t(8) * Mp * Mp, 0.0f);
-    std::vector<double> B(size_t(M) * M);
-    for (int o = 0; o < 8; ++o) {
+    ops.l2l_cc.assign(size_t(8) * M * M, 0.0);
+    std::vector<double> dc2de(size_t(M) * M, 0.0);   // DC2DE = P2^T P1^T (side 1)
+    pool.parallel_for(M, [&](int i) {
+        for (int j = 0; j < M; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < r; ++k) acc += ops.up2[size_t(k) * M + i] * ops.up1[size_t(j) * r + k];
+            dc2de[size_t(i) * M + j] = acc;
+        }
+    });
+    pool.parallel_for(8, [&](int o) {
+        std::vector<double> B(size_t(M) * M);
         double c[3] = {((o >> 2) & 1) ? 0.25 : -0.25, ((o >> 1) & 1) ? 0.25 : -0.25, (o & 1) ? 0.25 : -0.25};
         laplace_block(ops.grid, M, zero, aOut, c, 0.5 * aIn, B.data(), M);   // parent uc <- child ue
         for (int i = 0; i < M; ++i)
             for (int j = 0; j < M; ++j) ops.m2m[(size_t(o) * Mp + i) * Mp + j] = float(B[size_t(i) * M + j]);
         laplace_block(ops.grid, M, c, 0.5 * aIn, zero, aOut, B.data(), M);   // child dc <- parent de
-        for (int i = 0; i < M; ++i)
-            for (int j = 0; j < M; ++j) ops.l2l[(size_t(o) * Mp + i) * Mp + j] = float(B[size_t(i) * M + j]);
-    }
+        double *L = &ops.l2l_cc[size_t(o) * M * M];
+        for (int i = 0; i < M; ++i) {
+            const double *bi = &B[size_t(i) * M];
+            for (int k = 0; k < M; ++k) {
+                const double b = bi[k];
+                const double *dk = &dc2de[size_t(k) * M];
+                for (int j = 0; j < M; ++j) L[size_t(i) * M + j] += b * dk[j];
+            }
+        }
+    });
     // V-list offsets: dense operators, or the compressed basis and cores
     auto is_v_offset = [](int idx) {
         const int ox = idx % 7 - 3, oy = (idx / 7) % 7 - 3, oz = idx / 49 - 3;

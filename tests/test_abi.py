@@ -31,7 +31,8 @@ def test_library_exports_every_symbol():
                                          ("RPY", (4, 0, 6)), ("PVel", (4, 9, 4)),
                                          ("Traction", (4, 9, 9)), ("StokesRegVel", (4, 0, 3)),
                                          ("StokesRegVelOmega", (7, 0, 6)), ("LapPGradGrad", (1, 3, 10)),
-                                         ("PVelGrad", (4, 9, 16)), ("PVelLaplacian", (4, 9, 7))])
+                                         ("PVelGrad", (4, 9, 16)), ("PVelLaplacian", (4, 9, 7)),
+                                         ("LapQPGradGrad", (9, 0, 10))])
 def test_kernel_dims(kernel, dims):
     # widths of the appendix table of supported kernels
     assert pkg.kernel_dims(kernel) == dims

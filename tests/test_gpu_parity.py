@@ -17,11 +17,12 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 KERNELS = ["Stokeslet", "RPY", "LapPGrad", "PVel", "Traction", "StokesRegVel", "StokesRegVelOmega",
-           "LapPGradGrad", "PVelGrad", "PVelLaplacian"]
+           "LapPGradGrad", "PVelGrad", "PVelLaplacian", "LapQPGradGrad"]
 FIELDS = {"Stokeslet": [("u", 0, 3)], "RPY": [("u", 0, 3), ("lap u", 3, 6)], "StokesRegVel": [("u", 0, 3)],
           "StokesRegVelOmega": [("u", 0, 3), ("omega", 3, 6)],
           "LapPGrad": [("phi", 0, 1), ("grad phi", 1, 4)],
-          "LapPGradGrad": [("phi", 0, 1), ("grad phi", 1, 4), ("hess phi", 4, 10)], "PVel": [("p", 0, 1), ("u", 1, 4)],
+          "LapPGradGrad": [("phi", 0, 1), ("grad phi", 1, 4), ("hess phi", 4, 10)],
+          "LapQPGradGrad": [("phi", 0, 1), ("grad phi", 1, 4), ("hess phi", 4, 10)], "PVel": [("p", 0, 1), ("u", 1, 4)],
           "Traction": [("sigma", 0, 9)],
           "PVelGrad": [("p", 0, 1), ("u", 1, 4), ("grad p", 4, 7), ("grad u", 7, 16)],
           "PVelLaplacian": [("p", 0, 1), ("u", 1, 4), ("lap u", 4, 7)]}
@@ -58,6 +59,8 @@ def problem(kernel, n, seed, clustered=True):
     if kernel == "StokesRegVelOmega":
         v = np.concatenate([rng.standard_normal((n, 6)), rng.uniform(1e-4, 1e-3, (n, 1))], 1)
         return dict(sl_xyz=x, sl_val=v, trg_xyz=x)
+    if kernel == "LapQPGradGrad":
+        return dict(sl_xyz=x, sl_val=rng.standard_normal((n, 9)), trg_xyz=x)
     if kernel in ("LapPGrad", "LapPGradGrad"):
         return dict(sl_xyz=x, sl_val=rng.standard_normal((n, 1)), dl_xyz=x,
                     dl_val=rng.standard_normal((n, 3)), trg_xyz=x)
@@ -113,6 +116,47 @@ def test_fmm_clustered(fmm, kernel):
     assert st["depth"] >= 3 and st["v_pairs"] > 0
     for e in errs.values():
         assert e < 1e-5
+
+
+# Relative L2 bounds of the far-field-only problem at p = 8.  Values and first
+# derivatives of the tree potentials meet the 1e-5 budget; outputs built from
+# second derivatives (lap u, sigma, grad u, grad p of the Stokes double layer,
+# the Laplace Hessian) lose about one digit, since the leaves' equivalent
+# densities sit close to the targets near a leaf's faces.  Quadrupole sources
+# (LapQPGradGrad) carry no charge or dipole moment, so the FP32 far field's
+# small truncation and rounding errors in those moments decay more slowly than
+# the true field and dominate far away (relative error ~ (R / h)^2 tau).
+FAR_TOL = {"lap u": 1e-3, "sigma": 2e-4, "grad p": 2e-4, "grad u": 2e-4, "hess phi": 1e-4}
+FAR_TOL_QP = {"phi": 1e-2, "grad phi": 3e-3, "hess phi": 2e-3}
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_far_field_only(fmm, kernel):
+    # sources in the level-2 box [0, 1/4)^3, targets in [3/4, 1)^3: every
+    # interaction goes through the equivalent surfaces (S2M, M2M, M2L, L2L,
+    # L2T), none through P2P, so the error is the far field's alone
+    pb = problem(kernel, 6000, 11, clustered=False)
+    for key in ("sl_xyz", "dl_xyz"):
+        if key in pb:
+            pb[key] = 0.02 + 0.21 * pb[key]
+    pb["trg_xyz"] = 0.77 + 0.21 * np.random.default_rng(12).random((3000, 3))
+    ref = oracle_of(kernel, pb)
+    # with both layers the error is measured against the larger layer's own
+    # field: their far fields can nearly cancel, which would measure the
+    # cancellation rather than the method
+    parts = [ref]
+    if "dl_xyz" in pb and "sl_xyz" in pb:
+        parts.append(direct.evaluate(kernel, pb["sl_xyz"], pb["sl_val"], None, None, pb["trg_xyz"]))
+        parts.append(direct.evaluate(kernel, None, None, pb["dl_xyz"], pb["dl_val"], pb["trg_xyz"]))
+    got = gpu_eval(fmm, kernel, pb, p=8, cap=100)
+    st = fmm.stats()
+    errs = {name: np.linalg.norm(got[:, a:b] - ref[:, a:b]) / max(np.linalg.norm(q[:, a:b]) for q in parts)
+            for name, a, b in FIELDS[kernel]}
+    print(kernel, "far field only", errs, flush=True)
+    assert st["p2p_pairs"] == 0 and st["v_pairs"] > 0
+    tol = FAR_TOL_QP if kernel == "LapQPGradGrad" else FAR_TOL
+    for name, e in errs.items():
+        assert e < tol.get(name, 1e-5), (name, e)
 
 
 @pytest.mark.parametrize("kernel", ["Stokeslet", "RPY", "LapPGrad", "Traction"])
