@@ -90,12 +90,19 @@ typedef enum {
 } stkfmm_kernel;
 
 /* Boundary conditions (Sec. III and its appendix on periodicity).  PXYZ is
- * implemented for LAP_PGRAD; the others return STKFMM_E_UNSUPPORTED. */
+ * implemented for LAP_PGRAD.  WALL (Sec. III, the no-slip wall section,
+ * tab:rpywall) is an open domain bounded below by a no-slip wall on the
+ * plane z = origin[2], for STOKESLET and RPY only, fixed p and leaf_cap only:
+ * the flow is assembled from three (Stokeslet) or four (RPY) free-space
+ * summations over the sources and their mirror images, on a cube of side
+ * 2 box_len holding both; all points must lie in [origin, origin + box_len)^3.
+ * The others return STKFMM_E_UNSUPPORTED. */
 typedef enum {
     STKFMM_BC_OPEN = 0,
     STKFMM_BC_PX = 1,
     STKFMM_BC_PXY = 2,
-    STKFMM_BC_PXYZ = 3
+    STKFMM_BC_PXYZ = 3,
+    STKFMM_BC_WALL = 4
 } stkfmm_bc;
 
 /* Create a context for the cube [origin, origin + box_len)^3 on HIP device
@@ -170,7 +177,8 @@ stkfmm_status stkfmm_set_option(stkfmm_ctx *ctx, const char *key, const char *va
  * last run in the order: 0 pack, 1 S2M, 2 M2M+UC2UE, 3 M2L, 4 S2L (X list)
  * and the periodic operator, 5 L2L+DC2DE, 6 L2T+M2T, 7 P2P, 8 combine;
  * others 0.  P2P runs on an internal stream concurrently with stages 1-6
- * unless the option "overlap" is "0". */
+ * unless the option "overlap" is "0".  For a WALL plan the times and stages
+ * are summed over its summations. */
 stkfmm_status stkfmm_get_timings(const stkfmm_ctx *ctx, double *t_tree_ms, double *t_run_ms,
                                  double stage_ms[16]);
 
@@ -184,7 +192,8 @@ stkfmm_status stkfmm_get_timings(const stkfmm_ctx *ctx, double *t_tree_ms, doubl
  * compressed V-list translations (0: dense), 17 Mp (M padded to 32),
  * 18 rank of the check-to-equivalent pseudo-inverse, 19 P2P lane pairs
  * (pairs including the idle lanes of partly filled 64-target waves).
- * Errors: E_ARG, E_STATE. */
+ * For a WALL plan: the statistics of its Stokes summation (sources and
+ * their images).  Errors: E_ARG, E_STATE. */
 stkfmm_status stkfmm_get_stats(const stkfmm_ctx *ctx, int64_t stats[20]);
 
 /* ---------------------------------------------------------------------
@@ -232,7 +241,8 @@ stkfmm_status stkfmm_get_leaf_features(stkfmm_ctx *ctx, float *features, int32_t
  * times the sources of the leaf's direct list), 1 P2P wave entries, 2 M2L
  * flops, 3 surface evaluations (S2M, S2L, L2T, M2T), 4 boxes.  Each box's
  * work is shared equally by the targets in it.  Used to price capacity
- * labels for the learned mode.  Errors: E_ARG, E_STATE. */
+ * labels for the learned mode.  Errors: E_ARG, E_STATE, E_UNSUPPORTED
+ * (WALL plans). */
 stkfmm_status stkfmm_get_plan_work(stkfmm_ctx *ctx, double *work);
 
 /* Predictor network kernels on device buffers (stream-ordered, synchronous).

@@ -13,7 +13,7 @@ import os
 KERNELS = {"LapPGrad": 0, "Stokeslet": 1, "RPY": 2, "PVel": 3, "Traction": 4, "StokesRegVel": 5,
            "StokesRegVelOmega": 6, "LapPGradGrad": 7, "PVelGrad": 8, "PVelLaplacian": 9,
            "LapQPGradGrad": 10}
-BCS = {"open": 0, "PX": 1, "PXY": 2, "PXYZ": 3}
+BCS = {"open": 0, "PX": 1, "PXY": 2, "PXYZ": 3, "wall": 4}
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_DOMAIN", 3: "E_UNSUPPORTED", 4: "E_NOMEM", 5: "E_DEVICE",
           6: "E_ACCURACY", 7: "E_STATE"}
 STAGES = ["pack", "s2m", "upward", "m2l", "s2l", "downward", "l2t", "p2p", "combine"]

@@ -86,6 +86,7 @@ struct DeviceOps {
     bool periodic = false;
     DevMem grid, m2m, m2l, uc2ue, dc2de, tm2l;   // pseudo-inverses [M][M] FP64
     DevMem l2l_cc;              // [8][M][M] FP64 child check <- parent check
+    DevMem uc2ue_m1, uc2ue_m2;  // UC2UE without the monopole / monopole and dipole
     DevMem basis_t, m2l_c;      // U_k^T [kc][Mp], cores [343][kc][kc]
 };
 
@@ -126,6 +127,20 @@ struct Pair {
 
 using namespace kafmm;
 
+// No-slip wall plan: the free-space summations of the image system (S, SD,
+// SDZ and, for RPY, Q), each its own context on the cube of side 2 box_len
+// below which the images lie, and the buffers of their sources and results.
+struct WallPlan {
+    stkfmm_ctx *sub[4] = {nullptr, nullptr, nullptr, nullptr};
+    int nsub = 0;
+    int rpy = 0;
+    int64_t n_src = 0, n_trg = 0;
+    DevMem src, trg, y2, yi, vs, sd_dl, sdz_sl, sdz_dl, q, out[4];
+    ~WallPlan() {
+        for (stkfmm_ctx *c : sub) stkfmm_destroy(c);
+    }
+};
+
 struct stkfmm_ctx {
     int device = 0;
     double origin[3] = {0, 0, 0};
@@ -156,6 +171,10 @@ struct stkfmm_ctx {
     // surface evaluations (S2M, S2L, L2T/M2T), 1 per box
     std::vector<std::array<double, 5>> box_work;
     int overlap = 1;
+    // sources' vanishing moments: 0 none, 1 charge (dipoles only), 2 charge
+    // and dipole (quadrupoles only); picks the moment-free UC2UE
+    int moments = 0;
+    std::unique_ptr<WallPlan> wall;   // no-slip wall plans (bc WALL)
     // learned order / capacity mode
     DevMem predictor, mlp_in, mlp_out, mlp_ws, coords[3], vbuf[4];
     bool has_predictor = false, learned = false, validated = false, fell_back = false;
@@ -259,6 +278,37 @@ stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, DeviceOps **out) {
         for (int j = 0; j < M; ++j) dc[size_t(j) * M + i] = uc[size_t(i) * M + j];
     HIP_TRY(c, up(d->uc2ue, uc.data(), uc.size() * sizeof(double)));
     HIP_TRY(c, up(d->dc2de, dc.data(), dc.size() * sizeof(double)));
+    // Moment-free variants for boxes whose sources carry no charge (dipoles
+    // only) or no charge and no dipole moment (quadrupoles only): the fitted
+    // density's monopole sum_i s_i (and dipole sum_i s_i y_i, y relative to
+    // the box centre) are projected out, (I - W W^T) UC2UE with W the
+    // orthonormal basis of {1} or {1, y_x, y_y, y_z} on the equivalent
+    // surface.  The truncated fit and FP32 rounding leave small moments
+    // there whose fields decay more slowly than the true field's and would
+    // dominate it far away.  On the symmetric lattice the four vectors are
+    // orthogonal, so W is them normalised.
+    {
+        std::vector<double> w[4];
+        for (int k = 0; k < 4; ++k) {
+            w[k].resize(M);
+            double nn = 0.0;
+            for (int i = 0; i < M; ++i) {
+                w[k][i] = k == 0 ? 1.0 : h.grid[3 * size_t(i) + (k - 1)];
+                nn += w[k][i] * w[k][i];
+            }
+            for (double &v : w[k]) v /= std::sqrt(nn);
+        }
+        std::vector<double> pm(uc);
+        for (int nk = 1; nk <= 4; nk += 3) {
+            for (int k = (nk == 1 ? 0 : 1); k < nk; ++k)
+                for (int j = 0; j < M; ++j) {
+                    double t = 0.0;
+                    for (int i = 0; i < M; ++i) t += w[k][i] * pm[size_t(i) * M + j];
+                    for (int i = 0; i < M; ++i) pm[size_t(i) * M + j] -= w[k][i] * t;
+                }
+            HIP_TRY(c, up(nk == 1 ? d->uc2ue_m1 : d->uc2ue_m2, pm.data(), pm.size() * sizeof(double)));
+        }
+    }
     if (periodic) HIP_TRY(c, up(d->tm2l, h.t_m2l.data(), h.t_m2l.size() * sizeof(double)));
     *out = d.get();
     c->ops_cache[key] = std::move(d);
@@ -431,6 +481,158 @@ stkfmm_status validate_points(stkfmm_ctx *c, const std::vector<double> &h, int64
     return STKFMM_OK;
 }
 
+// ---------------------------------------------------------------- no-slip wall
+// Plan of the wall boundary: validate the points in the caller's box, mirror
+// the sources, plan each summation of the image system on its own context.
+stkfmm_status wall_set_points(stkfmm_ctx *c, int kernel, int64_t n_src, const double *src, int64_t n_trg,
+                              const double *trg, int p, int leaf_cap, void *stream) {
+    if (kernel != kStokeslet && kernel != kRPY)
+        return fail(c, STKFMM_E_UNSUPPORTED, "the wall boundary is implemented for STOKESLET and RPY");
+    if (p == 0 || leaf_cap == 0) return fail(c, STKFMM_E_UNSUPPORTED, "learned mode is open-boundary only");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(c, hipSetDevice(c->device));
+    auto t0 = std::chrono::steady_clock::now();
+    {
+        std::vector<double> h;
+        const double *pts[2] = {src, trg};
+        const int64_t cnt[2] = {n_src, n_trg};
+        const char *names[2] = {"sl_xyz", "trg_xyz"};
+        for (int k = 0; k < 2; ++k) {
+            h.resize(3 * cnt[k]);
+            if (cnt[k] > 0)
+                HIP_TRY(c, hipMemcpyAsync(h.data(), pts[k], 3 * cnt[k] * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_TRY(c, hipStreamSynchronize(s));
+            stkfmm_status st = validate_points(c, h, cnt[k], false, names[k]);
+            if (st != STKFMM_OK) return st;
+        }
+    }
+    if (!c->wall) c->wall = std::make_unique<WallPlan>();
+    WallPlan &w = *c->wall;
+    w.rpy = kernel == kRPY;
+    w.nsub = w.rpy ? 4 : 3;
+    w.n_src = n_src;
+    w.n_trg = n_trg;
+    // the summations run on the cube of side 2L whose lower half holds the images
+    const double org[3] = {c->origin[0], c->origin[1], c->origin[2] - c->box_len};
+    for (int k = 0; k < w.nsub; ++k) {
+        if (w.sub[k]) continue;
+        stkfmm_status st = stkfmm_setup(&w.sub[k], org, 2.0 * c->box_len, c->device, 0);
+        if (st != STKFMM_OK) return fail(c, st, "wall summation context");
+        stkfmm_ctx *sc = w.sub[k];
+        sc->svd_tol = c->svd_tol;
+        sc->m2l_tol = c->m2l_tol;
+        sc->precision = c->precision;
+        sc->overlap = c->overlap;
+        sc->p2p_task_sources = c->p2p_task_sources;
+        sc->w_direct_frac = c->w_direct_frac;
+        sc->x_direct_frac = c->x_direct_frac;
+    }
+    const int64_t n = n_src, ns = std::max<int64_t>(n, 1), nt = std::max<int64_t>(n_trg, 1);
+    HIP_TRY(c, w.src.ensure(size_t(ns) * 3 * sizeof(double)));
+    HIP_TRY(c, w.trg.ensure(size_t(nt) * 3 * sizeof(double)));
+    HIP_TRY(c, w.y2.ensure(size_t(ns) * 6 * sizeof(double)));
+    HIP_TRY(c, w.yi.ensure(size_t(ns) * 3 * sizeof(double)));
+    HIP_TRY(c, w.vs.ensure(size_t(ns) * 2 * 4 * sizeof(double)));
+    HIP_TRY(c, w.sd_dl.ensure(size_t(ns) * 3 * sizeof(double)));
+    HIP_TRY(c, w.sdz_sl.ensure(size_t(ns) * sizeof(double)));
+    HIP_TRY(c, w.sdz_dl.ensure(size_t(ns) * 3 * sizeof(double)));
+    HIP_TRY(c, w.q.ensure(size_t(ns) * 9 * sizeof(double)));
+    HIP_TRY(c, w.out[0].ensure(size_t(nt) * 6 * sizeof(double)));
+    HIP_TRY(c, w.out[1].ensure(size_t(nt) * 10 * sizeof(double)));
+    HIP_TRY(c, w.out[2].ensure(size_t(nt) * 4 * sizeof(double)));
+    HIP_TRY(c, w.out[3].ensure(size_t(nt) * 10 * sizeof(double)));
+    if (n > 0) HIP_TRY(c, hipMemcpyAsync(w.src.p, src, size_t(n) * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (n_trg > 0)
+        HIP_TRY(c, hipMemcpyAsync(w.trg.p, trg, size_t(n_trg) * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(c, launch_wall_positions(n, w.src.as<double>(), c->origin[2], w.y2.as<double>(), w.yi.as<double>(), s));
+    if (n > 0 && n_trg > 0) {
+        const double *y2 = w.y2.as<double>(), *yi = w.yi.as<double>(), *xt = w.trg.as<double>();
+        struct Sum {
+            stkfmm_kernel k;
+            int64_t nsl;
+            const double *sl;
+            int64_t ndl;
+            const double *dl;
+        };
+        const Sum sums[4] = {
+            {STKFMM_RPY, 2 * n, y2, 0, nullptr},   // b = 0 for the Stokeslet: hi/lo P2P
+            {w.rpy ? STKFMM_LAP_PGRADGRAD : STKFMM_LAP_PGRAD, 0, nullptr, n, yi},
+            {STKFMM_LAP_PGRAD, n, yi, w.rpy ? n : 0, w.rpy ? yi : nullptr},
+            {STKFMM_LAP_QPGRADGRAD, n, yi, 0, nullptr},
+        };
+        for (int k = 0; k < w.nsub; ++k) {
+            stkfmm_status st = stkfmm_set_points(w.sub[k], sums[k].k, STKFMM_BC_OPEN, sums[k].nsl, sums[k].sl,
+                                                 sums[k].ndl, sums[k].dl, n_trg, xt, p, leaf_cap, stream);
+            if (st != STKFMM_OK) return fail(c, st, std::string("wall summation: ") + w.sub[k]->err);
+        }
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->kernel = kernel;
+    c->bc = STKFMM_BC_WALL;
+    c->p = p;
+    c->leaf_cap = leaf_cap;
+    c->n_sl = n_src;
+    c->n_dl = 0;
+    c->n_trg = n_trg;
+    c->learned = false;
+    c->validated = false;
+    c->ops = nullptr;
+    c->t_tree_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    c->planned = true;
+    return STKFMM_OK;
+}
+
+// The evaluation pass of a wall plan: image strengths, the summations on the
+// caller's stream, the assembly at the targets.
+stkfmm_status wall_run(stkfmm_ctx *c, const double *sl_val, const double *dl_val, double *trg_val, void *stream) {
+    WallPlan &w = *c->wall;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dl_val) return fail(c, STKFMM_E_ARG, "the wall kernels have no double-layer sources");
+    if (w.n_trg == 0) return STKFMM_OK;
+    if (!trg_val || (w.n_src > 0 && !sl_val)) return fail(c, STKFMM_E_ARG, "NULL value array");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const int kt = w.rpy ? 6 : 3;
+    std::memset(c->stage_ms, 0, sizeof(c->stage_ms));
+    c->t_run_ms = 0.0;
+    if (w.n_src == 0) {
+        HIP_TRY(c, launch_fill_f64(trg_val, w.n_trg * kt, 0.0, s));
+        return STKFMM_OK;
+    }
+    WallValueArgs va;
+    va.n = w.n_src;
+    va.y = w.src.as<double>();
+    va.val = sl_val;
+    va.rpy = w.rpy;
+    va.zw = c->origin[2];
+    va.vs = w.vs.as<double>();
+    va.sd_dl = w.sd_dl.as<double>();
+    va.sdz_sl = w.sdz_sl.as<double>();
+    va.sdz_dl = w.sdz_dl.as<double>();
+    va.q = w.q.as<double>();
+    HIP_TRY(c, launch_wall_values(va, s));
+    const double *sl[4] = {va.vs, nullptr, va.sdz_sl, va.q};
+    const double *dl[4] = {nullptr, va.sd_dl, w.rpy ? va.sdz_dl : nullptr, nullptr};
+    for (int k = 0; k < w.nsub; ++k) {
+        stkfmm_status st = stkfmm_run(w.sub[k], sl[k], dl[k], w.out[k].as<double>(), stream);
+        if (st != STKFMM_OK) return fail(c, st, std::string("wall summation: ") + w.sub[k]->err);
+        c->t_run_ms += w.sub[k]->t_run_ms;
+        for (int i = 0; i < 16; ++i) c->stage_ms[i] += w.sub[k]->stage_ms[i];
+    }
+    WallAssembleArgs aa;
+    aa.nt = w.n_trg;
+    aa.x = w.trg.as<double>();
+    aa.zw = c->origin[2];
+    aa.rpy = w.rpy;
+    aa.us = w.out[0].as<double>();
+    aa.sd = w.out[1].as<double>();
+    aa.ksd = w.rpy ? 10 : 4;
+    aa.sdz = w.out[2].as<double>();
+    aa.qp = w.rpy ? w.out[3].as<double>() : nullptr;
+    aa.out = trg_val;
+    HIP_TRY(c, launch_wall_assemble(aa, s));
+    return STKFMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -483,6 +685,12 @@ const char *stkfmm_last_error(const stkfmm_ctx *c) { return c ? c->err.c_str() :
 
 stkfmm_status stkfmm_set_option(stkfmm_ctx *c, const char *key, const char *value) {
     if (!c || !key || !value) return STKFMM_E_ARG;
+    if (c->wall)   // the wall plan's summations follow the context's options
+        for (stkfmm_ctx *sc : c->wall->sub)
+            if (sc) {
+                stkfmm_status st = stkfmm_set_option(sc, key, value);
+                if (st != STKFMM_OK) return fail(c, st, sc->err);
+            }
     std::string k(key), v(value);
     if (k == "precision") {
         if (v == "fp32") c->precision = 0;
@@ -551,6 +759,13 @@ stkfmm_status stkfmm_get_timings(const stkfmm_ctx *c, double *t_tree, double *t_
 stkfmm_status stkfmm_get_stats(const stkfmm_ctx *c, int64_t st[20]) {
     if (!c || !st) return STKFMM_E_ARG;
     if (!c->planned) return STKFMM_E_STATE;
+    if (c->bc == STKFMM_BC_WALL) {
+        if (c->wall && c->wall->sub[0] && c->wall->sub[0]->planned) return stkfmm_get_stats(c->wall->sub[0], st);
+        std::memset(st, 0, 20 * sizeof(int64_t));
+        st[8] = c->n_trg;
+        st[9] = c->n_sl;
+        return STKFMM_OK;
+    }
     std::memset(st, 0, 20 * sizeof(int64_t));
     const Tree &t = c->tree;
     st[0] = int64_t(t.boxes.size());
@@ -594,8 +809,10 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     const bool learned = p == 0 || leaf_cap == 0;
     if (learned && !c->has_predictor) return fail(c, STKFMM_E_STATE, "learned mode needs stkfmm_set_predictor");
     if (learned && bc != STKFMM_BC_OPEN) return fail(c, STKFMM_E_UNSUPPORTED, "learned mode is open-boundary only");
+    if (bc == STKFMM_BC_WALL)
+        return wall_set_points(c, int(kernel), n_sl, sl_xyz, n_trg, trg_xyz, p, leaf_cap, stream);
     if (bc != STKFMM_BC_OPEN && bc != STKFMM_BC_PXYZ)
-        return fail(c, STKFMM_E_UNSUPPORTED, "only open and triply periodic boundaries are implemented");
+        return fail(c, STKFMM_E_UNSUPPORTED, "only open, triply periodic and wall boundaries are implemented");
     if (bc == STKFMM_BC_PXYZ && kernel != STKFMM_LAP_PGRAD)
         return fail(c, STKFMM_E_UNSUPPORTED, "triply periodic boundary is implemented for LAP_PGRAD");
     const bool periodic = bc == STKFMM_BC_PXYZ;
@@ -700,6 +917,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     c->ops = ops;
     c->kernel = kernel;
     c->bc = bc;
+    c->moments = kernel == STKFMM_LAP_QPGRADGRAD ? 2 : (n_sl == 0 && n_dl > 0) ? 1 : 0;
     c->p = p;
     c->leaf_cap = leaf_cap;
     c->n_sl = n_sl;
@@ -1355,7 +1573,8 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
                 stkfmm_status st = run_batch(c, c->m2m[l], o.m2m.as<float>(), updens, upchk, s);
                 if (st != STKFMM_OK) return st;
             }
-            stkfmm_status st = run_pinv(c, c->upinv[l], o.uc2ue.as<double>(), upchk, updens, s);
+            const DevMem &P = c->moments == 2 ? o.uc2ue_m2 : c->moments == 1 ? o.uc2ue_m1 : o.uc2ue;
+            stkfmm_status st = run_pinv(c, c->upinv[l], P.as<double>(), upchk, updens, s);
             if (st != STKFMM_OK) return st;
         }
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 3 upward
@@ -1517,6 +1736,7 @@ stkfmm_status sampled_error(stkfmm_ctx *c, const double *sl_val, const double *d
 extern "C" {
 
 stkfmm_status stkfmm_run(stkfmm_ctx *c, const double *sl_val, const double *dl_val, double *trg_val, void *stream) {
+    if (c && c->planned && c->bc == STKFMM_BC_WALL) return wall_run(c, sl_val, dl_val, trg_val, stream);
     stkfmm_status st = run_pass(c, sl_val, dl_val, trg_val, stream);
     if (st != STKFMM_OK || !c->learned || c->validated || c->n_trg == 0) return st;
     // learned plan: one accuracy check against the FP64 direct sum on sampled
@@ -1580,6 +1800,7 @@ stkfmm_status stkfmm_get_learned(const stkfmm_ctx *c, int64_t info[12], double *
 stkfmm_status stkfmm_get_leaf_features(stkfmm_ctx *c, float *features, int32_t *leaf_of_target, int64_t *n_leaf) {
     if (!c || !n_leaf) return STKFMM_E_ARG;
     if (!c->planned) return fail(c, STKFMM_E_STATE, "no plan");
+    if (c->bc == STKFMM_BC_WALL) return fail(c, STKFMM_E_UNSUPPORTED, "wall plans have no single tree");
     const Tree &t = c->tree;
     *n_leaf = int64_t(t.leaves.size());
     if (features) {
@@ -1598,6 +1819,7 @@ stkfmm_status stkfmm_get_leaf_features(stkfmm_ctx *c, float *features, int32_t *
 stkfmm_status stkfmm_get_plan_work(stkfmm_ctx *c, double *work) {
     if (!c || !work) return STKFMM_E_ARG;
     if (!c->planned) return fail(c, STKFMM_E_STATE, "no plan");
+    if (c->bc == STKFMM_BC_WALL) return fail(c, STKFMM_E_UNSUPPORTED, "wall plans have no single tree");
     const Tree &t = c->tree;
     std::vector<double> w(size_t(c->n_trg) * 5, 0.0);      // sorted target order
     for (size_t b = 0; b < t.boxes.size(); ++b) {

@@ -156,6 +156,34 @@ hipError_t launch_gemm_f64(const Gemm64Args &a, double *C, hipStream_t s);
 hipError_t launch_gemm_f64_to_f32(const Gemm64Args &a, float *C, hipStream_t s);
 hipError_t launch_reduce(int ntasks, const ReduceArgs &a, hipStream_t s);
 hipError_t launch_l2l_check(int nblocks, int ncomp, const L2LArgs &a, hipStream_t s);
+
+// No-slip wall image summations (wall.hip).  Sources in the caller's order.
+struct WallValueArgs {
+    int64_t n;                 // sources
+    const double *y;           // [n][3]
+    const double *val;         // [n][3] f, or [n][4] (f, b) when rpy
+    int rpy;
+    double zw;                 // wall plane z
+    double *vs;                // [2n][4] S summation, RPY (sources, then images)
+    double *sd_dl;             // [n][3]      SD image dipoles
+    double *sdz_sl, *sdz_dl;   // [n], [n][3] SDZ image charges, dipoles (rpy)
+    double *q;                 // [n][9]      image quadrupoles (rpy)
+};
+struct WallAssembleArgs {
+    int64_t nt;
+    const double *x;           // [nt][3] targets
+    double zw;
+    int rpy;
+    const double *us;          // [nt][6] (u, lap u) of the S summation
+    const double *sd;          // [nt][ksd] phi, grad phi[, Hessian]
+    int ksd;                   // 4, or 10 (rpy)
+    const double *sdz;         // [nt][4]
+    const double *qp;          // [nt][10] (rpy)
+    double *out;               // [nt][3] or [nt][6]
+};
+hipError_t launch_wall_positions(int64_t n, const double *y, double zw, double *y2, double *yi, hipStream_t s);
+hipError_t launch_wall_values(const WallValueArgs &a, hipStream_t s);
+hipError_t launch_wall_assemble(const WallAssembleArgs &a, hipStream_t s);
 hipError_t launch_periodic(const double *T, const float *dens, double *chk, int M, int Mp, int nc, int root,
                            hipStream_t s);
 hipError_t launch_l2t(int kernel, int ntasks, const L2TArgs &a, hipStream_t s);
