@@ -169,7 +169,10 @@ stkfmm_status stkfmm_kernel_dims(stkfmm_kernel kernel, int *k_sl, int *k_dl, int
  * the learned mode (default 1e-5), "p2p_task_sources" = sources per P2P task
  * (default 2048), "w_direct_frac" / "x_direct_frac" = W / X pairs whose source
  * count / target count is below this fraction of M are summed directly
- * (defaults 0.73 / 0.5).  Errors: E_ARG. */
+ * (defaults 0.73 / 0.5), "m2l_tol" = relative singular-value cut of the
+ * shared basis that compresses the V-list translations (default 5e-8: rank
+ * 192 at p = 8; learned plans use tol / 50 unless it was set, rank 160 at
+ * p = 8 for tol 1e-5; "0" keeps them dense).  Errors: E_ARG. */
 stkfmm_status stkfmm_set_option(stkfmm_ctx *ctx, const char *key, const char *value);
 
 /* Timings of the last set_points (t_tree_ms) and run (t_run_ms, device event

@@ -148,8 +148,9 @@ struct stkfmm_ctx {
     std::string err;
     double svd_tol = 1e-7;
     double m2l_tol = 5e-8;      // compression of the V-list translations (0: dense)
+    bool m2l_tol_set = false;   // set by the caller (else learned plans use tol / 50)
     int precision = 0;          // 0 fp32, 1 split_bf16
-    std::map<int, std::unique_ptr<DeviceOps>> ops_cache;   // key: p*2 + periodic
+    std::map<std::pair<int, double>, std::unique_ptr<DeviceOps>> ops_cache;   // key: (p*2 + periodic, m2l_tol)
     hipStream_t side = nullptr; // P2P stream
     hipEvent_t ev[24] = {};
     // plan
@@ -228,15 +229,15 @@ int sl_kind(int k) {
 int stage_kind(int k) { return k == kStokesRegVel ? 1 : sl_kind(k); }   // kinds 7, 8 pack and stage alike
 int dl_kind(int k) { return k == kLapPGrad || k == kLapPGradGrad ? 3 : 5; }
 
-stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, DeviceOps **out) {
-    int key = p * 2 + (periodic ? 1 : 0);
+stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, double m2l_tol, DeviceOps **out) {
+    const std::pair<int, double> key(p * 2 + (periodic ? 1 : 0), m2l_tol);
     auto it = c->ops_cache.find(key);
     if (it != c->ops_cache.end()) {
         *out = it->second.get();
         return STKFMM_OK;
     }
     Operators h;
-    std::string e = build_operators(p, c->svd_tol, periodic, h, c->m2l_tol);
+    std::string e = build_operators(p, c->svd_tol, periodic, h, m2l_tol);
     if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
     auto d = std::make_unique<DeviceOps>();
     d->p = p;
@@ -733,6 +734,7 @@ stkfmm_status stkfmm_set_option(stkfmm_ctx *c, const char *key, const char *valu
         if (!end || *end || !(t >= 0) || !(t < 1)) return fail(c, STKFMM_E_ARG, "m2l_tol must lie in [0, 1)");
         if (t != c->m2l_tol) c->ops_cache.clear();
         c->m2l_tol = t;
+        c->m2l_tol_set = true;
         c->planned = false;
         return STKFMM_OK;
     }
@@ -912,7 +914,10 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     }
     for (int k = 0; k < 3; ++k) c->hcoords[k] = h[k];
     DeviceOps *ops = nullptr;
-    stkfmm_status st = get_ops(c, p, periodic, &ops);
+    // learned plans size the translation compression to the error budget
+    // (rank 160 at p = 8 for tol 1e-5) unless the caller set m2l_tol
+    const double m2l_tol = learned && !c->m2l_tol_set && c->m2l_tol > 0 ? c->tol / 50.0 : c->m2l_tol;
+    stkfmm_status st = get_ops(c, p, periodic, m2l_tol, &ops);
     if (st != STKFMM_OK) return st;
     c->ops = ops;
     c->kernel = kernel;
