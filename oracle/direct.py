@@ -40,7 +40,7 @@ def lib():
                                                 ctypes.c_int, _dp, _dp]
         _lib.oracle_ewald_eval.argtypes = [_i64, _dp, _dp, _dp, _i64, _dp, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_double, ctypes.c_int,
-                                           _dp, _dp, _dp]
+                                           _dp, _dp, _dp, ctypes.c_int]
     return _lib
 
 

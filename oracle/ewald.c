@@ -15,12 +15,20 @@
  *               B0 = erfc(xi rho)/(4 pi rho)
  *               B  = [erfc(xi rho) + 2 xi rho/sqrt(pi) e^{-xi^2 rho^2}]/(4 pi rho^3)
  *               C  = [3 erfc(xi rho) + 2 xi rho/sqrt(pi) (3 + 2 xi^2 rho^2) e^{-xi^2 rho^2}]/(4 pi rho^5)
+ *               D  = [15 erfc(xi rho) + 2 xi rho/sqrt(pi) (15 + 10 xi^2 rho^2 + 4 xi^4 rho^4)
+ *                     e^{-xi^2 rho^2}]/(4 pi rho^7)
  *               grad: -q B r + d B - (d . r) C r
+ *               Hessian: q (C r r^T - B I)
+ *                        - C (d r^T + r d^T) - (d . r) C I + (d . r) D r r^T
  *   reciprocal  (1/V) sum_{k != 0} e^{-k^2/(4 xi^2)}/k^2 Re[S(k) e^{i k.x}],
  *               S(k) = sum_j (q_j - i k.d_j) e^{-i k.y_j},  k = 2 pi n / L
+ *   reciprocal Hessian: -k k^T g Re[S(k) e^{i k.x}]
  *   self        a target that coincides with source j drops the smooth
  *               self part: phi -= q_j xi / (2 pi^{3/2}),
- *               grad phi -= d_j xi^3 / (3 pi^{3/2}).
+ *               grad phi -= d_j xi^3 / (3 pi^{3/2}),
+ *               Hessian += q_j xi^3 / (3 pi^{3/2}) I (the dipole's smooth
+ *               part is odd, its second derivatives vanish at the source).
+ * Hessian order (xx, xy, xz, yy, yz, zz).
  */
 #include <math.h>
 #include <stdint.h>
@@ -92,17 +100,19 @@ void oracle_ewald_structure(int64_t ns, const double *ys, const double *q,
     }
 }
 
-/* phi and grad phi (4 values per target) from the real, reciprocal and self parts. */
+/* phi and grad phi (4 values per target), and with hess != 0 the Hessian
+ * (10 values), from the real, reciprocal and self parts. */
 void oracle_ewald_eval(int64_t ns, const double *ys, const double *q, const double *d,
                        int64_t nt, const double *xs, double L, double xi, double rc,
-                       int nmax, const double *S_re, const double *S_im, double *out)
+                       int nmax, const double *S_re, const double *S_im, double *out, int hess)
 {
+    const int kt = hess ? 10 : 4;
     const double V = L * L * L;
     const int nimg = (int)ceil(rc / L);
     const double sqpi = sqrt(PI);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < nt; ++t) {
-        double acc[4] = {0, 0, 0, 0};
+        double acc[10] = {0};
         const double *x = xs + 3*t;
         /* real space */
         for (int64_t j = 0; j < ns; ++j) {
@@ -125,10 +135,26 @@ void oracle_ewald_eval(int64_t ns, const double *ys, const double *q, const doub
                         acc[0] += qj * B0 + dr * B;
                         for (int i = 0; i < 3; ++i)
                             acc[1+i] += -qj * B * r[i] + dj[i] * B - dr * C * r[i];
+                        if (hess) {
+                            double x2 = xr*xr;
+                            double D = (15.0*ec + 2.0*xr/sqpi*(15.0 + 10.0*x2 + 4.0*x2*x2)*ex) / (4.0*PI*rho*rr*rr*rr);
+                            int h = 4;
+                            for (int i = 0; i < 3; ++i)
+                                for (int k = i; k < 3; ++k) {
+                                    double dik = (i == k) ? 1.0 : 0.0;
+                                    acc[h++] += qj * (C * r[i] * r[k] - B * dik)
+                                              - C * (dj[i] * r[k] + r[i] * dj[k]) - dr * C * dik + dr * D * r[i] * r[k];
+                                }
+                        }
                     }
             if (self) {
                 acc[0] -= qj * xi / (2.0 * PI * sqpi);
                 for (int i = 0; i < 3; ++i) acc[1+i] -= dj[i] * xi*xi*xi / (3.0 * PI * sqpi);
+                if (hess) {
+                    acc[4] += qj * xi*xi*xi / (3.0 * PI * sqpi);
+                    acc[7] += qj * xi*xi*xi / (3.0 * PI * sqpi);
+                    acc[9] += qj * xi*xi*xi / (3.0 * PI * sqpi);
+                }
             }
         }
         /* reciprocal space: the half space counted twice */
@@ -146,7 +172,12 @@ void oracle_ewald_eval(int64_t ns, const double *ys, const double *q, const doub
                     double zi = S_re[id]*ci + S_im[id]*cr;   /* Im[S e^{ikx}] */
                     acc[0] += g * zr;
                     for (int i = 0; i < 3; ++i) acc[1+i] += -g * k[i] * zi;  /* Re[i k S e^{ikx}] */
+                    if (hess) {
+                        int h = 4;
+                        for (int i = 0; i < 3; ++i)
+                            for (int m = i; m < 3; ++m) acc[h++] += -g * k[i] * k[m] * zr;
+                    }
                 }
-        for (int i = 0; i < 4; ++i) out[4*t+i] = acc[i];
+        for (int i = 0; i < kt; ++i) out[kt*t+i] = acc[i];
     }
 }

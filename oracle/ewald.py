@@ -1,6 +1,6 @@
 """FP64 Ewald sums for triply periodic Laplace (oracle) -- TEST INFRASTRUCTURE.
 
-Wraps ``ewald.c``.  Evaluates (phi, grad phi) at targets for charges q and
+Wraps ``ewald.c``.  Evaluates (phi, grad phi[, Hessian]) at targets for charges q and
 dipoles d in a periodic cube of side L: the periodic boundary condition of
 Sec. III and its appendix on periodicity, with the conventions the paper
 leaves open fixed as: zero net charge, k = 0 term dropped, no surface term
@@ -36,8 +36,9 @@ def structure(src, q, d, L, nmax):
     return sr, si
 
 
-def laplace_periodic(src, q, d, trg, L=1.0, xi=None, tol=1e-13, S=None):
-    """(phi, grad phi) [nt, 4] of periodic charges q [ns] and dipoles d [ns,3].
+def laplace_periodic(src, q, d, trg, L=1.0, xi=None, tol=1e-13, S=None, hess=False):
+    """(phi, grad phi) [nt, 4] of periodic charges q [ns] and dipoles d [ns,3];
+    with hess=True also the Hessian (xx, xy, xz, yy, yz, zz) [nt, 10].
 
     ``S`` may pass a precomputed structure factor (same src/q/d/L/xi/tol)."""
     if q is not None and abs(float(np.sum(q))) > 1e-9 * max(1.0, float(np.sum(np.abs(q)))):
@@ -49,7 +50,7 @@ def laplace_periodic(src, q, d, trg, L=1.0, xi=None, tol=1e-13, S=None):
     q, _ = _arr(q)
     d, _ = _arr(d, 3)
     trg, nt = _arr(trg, 3)
-    out = np.zeros((nt, 4))
+    out = np.zeros((nt, 10 if hess else 4))
     lib().oracle_ewald_eval(ns, _p(src), _p(q), _p(d), nt, _p(trg), float(L), float(xi),
-                            float(rc), int(nmax), _p(S[0]), _p(S[1]), _p(out))
+                            float(rc), int(nmax), _p(S[0]), _p(S[1]), _p(out), int(hess))
     return out

@@ -123,3 +123,25 @@ def test_image_sum_of_neutral_dipole_free_cell():
 def test_rejects_net_charge():
     with pytest.raises(ValueError):
         ewald.laplace_periodic(np.zeros((1, 3)), np.ones(1), None, np.ones((1, 3)) * 0.5)
+
+
+def test_hessian_is_fd_of_gradient_and_harmonic():
+    y, q, d = _cell()
+    x = RNG.random((4, 3))
+    S = ewald.structure(y, q, d, 1.0, ewald.parameters(1.0)[2])
+    out = ewald.laplace_periodic(y, q, d, x, 1.0, S=S, hess=True)
+    assert np.allclose(out[:, :4], ewald.laplace_periodic(y, q, d, x, 1.0, S=S), rtol=1e-14, atol=1e-14)
+    J = _fd.grad(lambda xx: ewald.laplace_periodic(y, q, d, xx, 1.0, S=S)[:, 1:4], x, h=1e-3)
+    H = np.stack([J[:, 0, 0], J[:, 0, 1], J[:, 0, 2], J[:, 1, 1], J[:, 1, 2], J[:, 2, 2]], 1)
+    assert np.allclose(out[:, 4:], H, rtol=1e-6, atol=1e-7 * np.abs(H).max())
+    # symmetric FD Jacobian, and zero net charge: harmonic between the sources
+    assert np.allclose(J[:, 0, 1], J[:, 1, 0], rtol=1e-6, atol=1e-7 * np.abs(H).max())
+    assert np.abs(out[:, 4] + out[:, 7] + out[:, 9]).max() < 1e-10 * np.abs(out[:, 4:]).max()
+
+
+def test_hessian_xi_independence_at_coincident_targets():
+    # the self terms: targets on the sources themselves
+    y, q, d = _cell()
+    ref = ewald.laplace_periodic(y, q, d, y, 1.0, xi=4.0, hess=True)
+    out = ewald.laplace_periodic(y, q, d, y, 1.0, xi=8.0, hess=True)
+    assert np.allclose(out, ref, rtol=1e-10, atol=1e-10 * np.max(np.abs(ref)))
