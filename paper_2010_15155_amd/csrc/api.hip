@@ -815,8 +815,8 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
         return wall_set_points(c, int(kernel), n_sl, sl_xyz, n_trg, trg_xyz, p, leaf_cap, stream);
     if (bc != STKFMM_BC_OPEN && bc != STKFMM_BC_PXYZ)
         return fail(c, STKFMM_E_UNSUPPORTED, "only open, triply periodic and wall boundaries are implemented");
-    if (bc == STKFMM_BC_PXYZ && kernel != STKFMM_LAP_PGRAD)
-        return fail(c, STKFMM_E_UNSUPPORTED, "triply periodic boundary is implemented for LAP_PGRAD");
+    if (bc == STKFMM_BC_PXYZ && kernel != STKFMM_LAP_PGRAD && kernel != STKFMM_LAP_PGRADGRAD)
+        return fail(c, STKFMM_E_UNSUPPORTED, "triply periodic boundary is implemented for LAP_PGRAD and LAP_PGRADGRAD");
     const bool periodic = bc == STKFMM_BC_PXYZ;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(c, hipSetDevice(c->device));

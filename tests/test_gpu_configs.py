@@ -103,6 +103,25 @@ def test_periodic_laplace_small(fmm):
     assert t_phi < 1e-5 and t_grad < 1e-5
 
 
+def test_periodic_laplace_hessian(fmm):
+    # LapPGradGrad on the same periodic tree: phi, grad phi and the Hessian
+    # against the Ewald oracle, and the translation test
+    x, q, dp = periodic_problem(32768, 302)
+    out = fmm.evaluate("LapPGradGrad", cu(x), cu(q[:, None]), cu(x), cu(dp), cu(x), p=8, leaf_cap=128,
+                       bc="PXYZ").cpu().numpy()
+    idx = W.sample_indices(len(x), 400, 6)
+    ref = ewald.laplace_periodic(x, q, dp, x[idx], 1.0, hess=True)
+    e_phi, e_grad = compare_periodic(out[idx, :4], ref[:, :4])
+    e_hess = rel(out[idx, 4:], ref[:, 4:])
+    print("periodic hessian 32768 p=8", e_phi, e_grad, e_hess, flush=True)
+    assert e_phi < 1e-5 and e_grad < 1e-5 and e_hess < 1e-5
+    s = np.array([0.63, 0.08, 0.41])
+    xs = np.mod(x + s, 1.0)
+    out2 = fmm.evaluate("LapPGradGrad", cu(xs), cu(q[:, None]), cu(xs), cu(dp), cu(xs), p=8, leaf_cap=128,
+                        bc="PXYZ").cpu().numpy()
+    assert rel(out2[:, 4:], out[:, 4:]) < 1e-5
+
+
 def test_periodic_rejects_net_charge(fmm):
     from paper_2010_15155_amd import StkfmmError
     x, q, dp = periodic_problem(2000, 7)
