@@ -36,9 +36,9 @@ def lib():
         _lib.oracle_pvel_deriv.argtypes = [_i64, _dp, _dp, _i64, _dp, _dp, _i64, _dp, _dp, ctypes.c_int]
         for name in ("oracle_pvel", "oracle_traction"):
             getattr(_lib, name).argtypes = [_i64, _dp, _dp, _i64, _dp, _dp, _i64, _dp, _dp]
-        _lib.oracle_ewald_structure.argtypes = [_i64, _dp, _dp, _dp, ctypes.c_double,
+        _lib.oracle_ewald_structure.argtypes = [_i64, _dp, _dp, _dp, _dp, ctypes.c_double,
                                                 ctypes.c_int, _dp, _dp]
-        _lib.oracle_ewald_eval.argtypes = [_i64, _dp, _dp, _dp, _i64, _dp, ctypes.c_double,
+        _lib.oracle_ewald_eval.argtypes = [_i64, _dp, _dp, _dp, _dp, _i64, _dp, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                            _dp, _dp, _dp, ctypes.c_int]
     return _lib

@@ -3,7 +3,8 @@
  * TEST INFRASTRUCTURE ONLY (part of the oracle; no code shared with the HIP
  * library).
  *
- * Problem: phi(x) = sum_j sum_n [q_j L(x - y_j + nL) + d_j . r/(4 pi |r|^3)]
+ * Problem: phi(x) = sum_j sum_n [q_j L(x - y_j + nL) + d_j . r/(4 pi |r|^3)
+ *                                + Q_j : grad grad L(x - y_j + nL)]
  * over the periodic lattice, with L(r) = 1/(4 pi r) (Sec. II.A), the
  * periodic boundary condition of Sec. III and its appendix on periodicity.
  * The lattice sum is only conditionally convergent, so the oracle fixes
@@ -28,6 +29,16 @@
  *               grad phi -= d_j xi^3 / (3 pi^{3/2}),
  *               Hessian += q_j xi^3 / (3 pi^{3/2}) I (the dipole's smooth
  *               part is odd, its second derivatives vanish at the source).
+ * Quadrupoles Q (9, row-major; the symmetric part acts), with
+ * E = [105 erfc + 2 xi rho/sqrt(pi) (105 + 70 x^2 + 28 x^4 + 8 x^6) e^{-x^2}]/(4 pi rho^9),
+ * x = xi rho, A = r.Q.r, w = Q r, T = tr Q:
+ *   real      phi  C A - B T
+ *             grad -D A r + 2 C w + C T r
+ *             Hess E A r r^T - D A I - 2 D (r w^T + w r^T) + 2 C Q - D T r r^T + C T I
+ *   reciprocal amplitude -k.Q.k in S(k)
+ *   self      phi += T xi^3/(3 pi^{3/2}),
+ *             Hess -= 2 xi^5/(5 pi^{3/2}) (T I + 2 Q)  (fourth derivatives of the
+ *             smooth part erf(xi r)/(4 pi r) at r = 0).
  * Hessian order (xx, xy, xz, yy, yz, zz).
  */
 #include <math.h>
@@ -52,7 +63,7 @@ static inline int khalf(int nx, int ny, int nz)
 
 /* Structure factor S(k) on the half space of the cube [-nmax,nmax]^3. */
 void oracle_ewald_structure(int64_t ns, const double *ys, const double *q,
-                            const double *d, double L, int nmax,
+                            const double *d, const double *Q, double L, int nmax,
                             double *S_re, double *S_im)
 {
     int w = 2 * nmax + 1;
@@ -86,9 +97,14 @@ void oracle_ewald_structure(int64_t ns, const double *ys, const double *q,
                         double cr = cx[2*w + nz + nmax], ci = sx[2*w + nz + nmax];
                         double tr = ar*br - ai*bi, ti = ar*bi + ai*br;
                         double er = tr*cr - ti*ci, ei = tr*ci + ti*cr;
-                        /* amplitude q - i k.d */
+                        /* amplitude q - i k.d - k.Q.k */
                         double kd = 2.0 * PI / L * (nx*dx + ny*dy + nz*dz);
                         double mr = qj, mi = -kd;
+                        if (Q) {
+                            const double kv[3] = {2.0 * PI / L * nx, 2.0 * PI / L * ny, 2.0 * PI / L * nz};
+                            for (int a = 0; a < 3; ++a)
+                                for (int b = 0; b < 3; ++b) mr -= kv[a] * Q[9*j + 3*a + b] * kv[b];
+                        }
                         int64_t id = kidx(nx, ny, nz, nmax);
                         sr[id] += mr*er - mi*ei;
                         si[id] += mr*ei + mi*er;
@@ -103,7 +119,7 @@ void oracle_ewald_structure(int64_t ns, const double *ys, const double *q,
 /* phi and grad phi (4 values per target), and with hess != 0 the Hessian
  * (10 values), from the real, reciprocal and self parts. */
 void oracle_ewald_eval(int64_t ns, const double *ys, const double *q, const double *d,
-                       int64_t nt, const double *xs, double L, double xi, double rc,
+                       const double *Q, int64_t nt, const double *xs, double L, double xi, double rc,
                        int nmax, const double *S_re, const double *S_im, double *out, int hess)
 {
     const int kt = hess ? 10 : 4;
@@ -118,6 +134,12 @@ void oracle_ewald_eval(int64_t ns, const double *ys, const double *q, const doub
         for (int64_t j = 0; j < ns; ++j) {
             double qj = q ? q[j] : 0.0;
             double dj[3] = {d ? d[3*j] : 0.0, d ? d[3*j+1] : 0.0, d ? d[3*j+2] : 0.0};
+            double Qs[3][3] = {{0}}, Tq = 0.0;
+            if (Q) {
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) Qs[a][b] = 0.5 * (Q[9*j + 3*a + b] + Q[9*j + 3*b + a]);
+                Tq = Qs[0][0] + Qs[1][1] + Qs[2][2];
+            }
             int self = 0;
             for (int a = -nimg; a <= nimg; ++a)
                 for (int b = -nimg; b <= nimg; ++b)
@@ -135,15 +157,31 @@ void oracle_ewald_eval(int64_t ns, const double *ys, const double *q, const doub
                         acc[0] += qj * B0 + dr * B;
                         for (int i = 0; i < 3; ++i)
                             acc[1+i] += -qj * B * r[i] + dj[i] * B - dr * C * r[i];
+                        double x2 = xr*xr;
+                        double D = (15.0*ec + 2.0*xr/sqpi*(15.0 + 10.0*x2 + 4.0*x2*x2)*ex) / (4.0*PI*rho*rr*rr*rr);
+                        double w[3] = {0, 0, 0}, A = 0.0;
+                        if (Q) {
+                            for (int a = 0; a < 3; ++a) {
+                                for (int b = 0; b < 3; ++b) w[a] += Qs[a][b] * r[b];
+                                A += r[a] * w[a];
+                            }
+                            acc[0] += C * A - B * Tq;
+                            for (int i = 0; i < 3; ++i) acc[1+i] += -D * A * r[i] + 2.0 * C * w[i] + C * Tq * r[i];
+                        }
                         if (hess) {
-                            double x2 = xr*xr;
-                            double D = (15.0*ec + 2.0*xr/sqpi*(15.0 + 10.0*x2 + 4.0*x2*x2)*ex) / (4.0*PI*rho*rr*rr*rr);
                             int h = 4;
                             for (int i = 0; i < 3; ++i)
                                 for (int k = i; k < 3; ++k) {
                                     double dik = (i == k) ? 1.0 : 0.0;
-                                    acc[h++] += qj * (C * r[i] * r[k] - B * dik)
+                                    acc[h] += qj * (C * r[i] * r[k] - B * dik)
                                               - C * (dj[i] * r[k] + r[i] * dj[k]) - dr * C * dik + dr * D * r[i] * r[k];
+                                    if (Q) {
+                                        double E = (105.0*ec + 2.0*xr/sqpi*(105.0 + 70.0*x2 + 28.0*x2*x2 + 8.0*x2*x2*x2)*ex)
+                                                   / (4.0*PI*rho*rr*rr*rr*rr);
+                                        acc[h] += E * A * r[i] * r[k] - D * A * dik - 2.0 * D * (r[i] * w[k] + w[i] * r[k])
+                                                + 2.0 * C * Qs[i][k] - D * Tq * r[i] * r[k] + C * Tq * dik;
+                                    }
+                                    ++h;
                                 }
                         }
                     }
@@ -154,6 +192,15 @@ void oracle_ewald_eval(int64_t ns, const double *ys, const double *q, const doub
                     acc[4] += qj * xi*xi*xi / (3.0 * PI * sqpi);
                     acc[7] += qj * xi*xi*xi / (3.0 * PI * sqpi);
                     acc[9] += qj * xi*xi*xi / (3.0 * PI * sqpi);
+                }
+                if (Q) {
+                    acc[0] += Tq * xi*xi*xi / (3.0 * PI * sqpi);
+                    if (hess) {
+                        const double c5 = 2.0 * xi*xi*xi*xi*xi / (5.0 * PI * sqpi);
+                        int h = 4;
+                        for (int i = 0; i < 3; ++i)
+                            for (int k = i; k < 3; ++k) acc[h++] -= c5 * ((i == k ? Tq : 0.0) + 2.0 * Qs[i][k]);
+                    }
                 }
             }
         }

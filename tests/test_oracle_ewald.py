@@ -145,3 +145,49 @@ def test_hessian_xi_independence_at_coincident_targets():
     ref = ewald.laplace_periodic(y, q, d, y, 1.0, xi=4.0, hess=True)
     out = ewald.laplace_periodic(y, q, d, y, 1.0, xi=8.0, hess=True)
     assert np.allclose(out, ref, rtol=1e-10, atol=1e-10 * np.max(np.abs(ref)))
+
+
+def _quads(n=6):
+    y = RNG.random((n, 3))
+    Q = RNG.standard_normal((n, 9))
+    return y, Q
+
+
+def test_quadrupole_xi_independence():
+    y, Q = _quads()
+    for x in (RNG.random((5, 3)), y):      # away from and on the sources (self terms)
+        ref = ewald.laplace_periodic(y, None, None, x, 1.0, xi=4.0, hess=True, Q=Q)
+        out = ewald.laplace_periodic(y, None, None, x, 1.0, xi=8.0, hess=True, Q=Q)
+        assert np.allclose(out, ref, rtol=1e-10, atol=1e-10 * np.max(np.abs(ref)))
+
+
+def test_quadrupole_is_limit_of_dipole_pairs():
+    # Q_ab d_a d_b L = d/dy_a d/dy_b L: dipoles (Q_ab/eps) e_b at y +- eps e_a / 2
+    y, Q = _quads(2)
+    x = np.array([[0.61, 0.12, 0.84], [0.07, 0.33, 0.21], [0.93, 0.95, 0.52]])
+    got = ewald.laplace_periodic(y, None, None, x, 1.0, hess=True, Q=Q)
+    res = []
+    for eps in (2e-3, 4e-3):
+        pos, dip = [], []
+        for s in range(len(y)):
+            for a in range(3):
+                for b in range(3):
+                    e_a, e_b = np.eye(3)[a], np.eye(3)[b]
+                    pos += [y[s] + eps * e_a / 2, y[s] - eps * e_a / 2]
+                    dip += [Q[s, 3 * a + b] / eps * e_b, -Q[s, 3 * a + b] / eps * e_b]
+        res.append(ewald.laplace_periodic(np.array(pos), None, np.array(dip), x, 1.0, hess=True))
+    ref = (4 * res[0] - res[1]) / 3
+    assert np.allclose(got, ref, rtol=1e-7, atol=1e-8 * np.max(np.abs(ref)))
+
+
+def test_quadrupole_gradient_and_hessian_are_fd():
+    y, Q = _quads()
+    x = RNG.random((4, 3))
+    S = ewald.structure(y, None, None, 1.0, ewald.parameters(1.0)[2], Q)
+    f = lambda xx: ewald.laplace_periodic(y, None, None, xx, 1.0, S=S, Q=Q)
+    out = ewald.laplace_periodic(y, None, None, x, 1.0, S=S, hess=True, Q=Q)
+    J = _fd.grad(lambda xx: f(xx)[:, :1], x, h=1e-3)[:, 0, :]
+    assert np.allclose(out[:, 1:4], J, rtol=1e-6, atol=1e-7 * np.abs(J).max())
+    Jg = _fd.grad(lambda xx: f(xx)[:, 1:4], x, h=1e-3)
+    H = np.stack([Jg[:, 0, 0], Jg[:, 0, 1], Jg[:, 0, 2], Jg[:, 1, 1], Jg[:, 1, 2], Jg[:, 2, 2]], 1)
+    assert np.allclose(out[:, 4:], H, rtol=1e-6, atol=1e-7 * np.abs(H).max())
