@@ -90,8 +90,8 @@ typedef enum {
 } stkfmm_kernel;
 
 /* Boundary conditions (Sec. III and its appendix on periodicity).  PXYZ is
- * implemented for LAP_PGRAD and LAP_PGRADGRAD (zero net charge; Ewald's
- * convention: no k = 0 term, no surface term).  WALL (Sec. III, the no-slip wall section,
+ * implemented for LAP_PGRAD, LAP_PGRADGRAD and LAP_QPGRADGRAD (zero net
+ * charge; Ewald's convention: no k = 0 term, no surface term).  WALL (Sec. III, the no-slip wall section,
  * tab:rpywall) is an open domain bounded below by a no-slip wall on the
  * plane z = origin[2], for STOKESLET and RPY only, fixed p and leaf_cap only:
  * the flow is assembled from three (Stokeslet) or four (RPY) free-space

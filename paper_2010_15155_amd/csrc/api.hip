@@ -815,8 +815,9 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
         return wall_set_points(c, int(kernel), n_sl, sl_xyz, n_trg, trg_xyz, p, leaf_cap, stream);
     if (bc != STKFMM_BC_OPEN && bc != STKFMM_BC_PXYZ)
         return fail(c, STKFMM_E_UNSUPPORTED, "only open, triply periodic and wall boundaries are implemented");
-    if (bc == STKFMM_BC_PXYZ && kernel != STKFMM_LAP_PGRAD && kernel != STKFMM_LAP_PGRADGRAD)
-        return fail(c, STKFMM_E_UNSUPPORTED, "triply periodic boundary is implemented for LAP_PGRAD and LAP_PGRADGRAD");
+    if (bc == STKFMM_BC_PXYZ && kernel != STKFMM_LAP_PGRAD && kernel != STKFMM_LAP_PGRADGRAD &&
+        kernel != STKFMM_LAP_QPGRADGRAD)
+        return fail(c, STKFMM_E_UNSUPPORTED, "triply periodic boundary is implemented for the Laplace kernels");
     const bool periodic = bc == STKFMM_BC_PXYZ;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(c, hipSetDevice(c->device));
@@ -1480,8 +1481,9 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
     const int nc = ki.ncomp;
     const bool periodic = c->bc == STKFMM_BC_PXYZ;
     if (c->n_trg == 0) return STKFMM_OK;
-    if (periodic && c->n_sl > 0) {
-        // zero net charge (tin-foil Ewald convention needs a neutral cell)
+    if (periodic && c->n_sl > 0 && c->kernel != kLapQPGradGrad) {
+        // zero net charge (tin-foil Ewald convention needs a neutral cell;
+        // quadrupoles carry none)
         const int nbk = 256;
         hipLaunchKernelGGL(charge_partials, dim3(nbk), dim3(256), 0, s, c->n_sl, sl_val, c->partial.as<double>());
         HIP_TRY(c, hipGetLastError());

@@ -122,6 +122,20 @@ def test_periodic_laplace_hessian(fmm):
     assert rel(out2[:, 4:], out[:, 4:]) < 1e-5
 
 
+def test_periodic_laplace_quadrupoles(fmm):
+    rng = np.random.default_rng(303)
+    x = rng.random((32768, 3))
+    Q = rng.standard_normal((32768, 9))
+    out = fmm.evaluate("LapQPGradGrad", cu(x), cu(Q), None, None, cu(x), p=8, leaf_cap=128,
+                       bc="PXYZ").cpu().numpy()
+    idx = W.sample_indices(len(x), 300, 7)
+    ref = ewald.laplace_periodic(x, None, None, x[idx], 1.0, hess=True, Q=Q)
+    e_phi, e_grad = compare_periodic(out[idx, :4], ref[:, :4])
+    e_hess = rel(out[idx, 4:], ref[:, 4:])
+    print("periodic quadrupoles 32768 p=8", e_phi, e_grad, e_hess, flush=True)
+    assert e_phi < 1e-5 and e_grad < 1e-5 and e_hess < 1e-5
+
+
 def test_periodic_rejects_net_charge(fmm):
     from paper_2010_15155_amd import StkfmmError
     x, q, dp = periodic_problem(2000, 7)
