@@ -71,14 +71,49 @@ def parse():
     return args
 
 
-def measure(fmm, torch, W, kernel, x, val, p, cap, args, precision="fp32"):
+FIELDS = {"Stokeslet": [("u", 0, 3)], "StokesRegVel": [("u", 0, 3)], "RPY": [("u", 0, 3), ("lap_u", 3, 6)]}
+
+
+def wall_direct(fmm, torch, y, fb, xt):
+    """(u, lap u) of RPY above the wall z = 0 at targets xt: the image
+    summations of the paper's wall table (with the SD charges -f3/2, +f3/2
+    and the quadrupole at the image), each by the library's FP64 direct sum,
+    assembled in FP64 -- the reference for the wall plan's error."""
+    f, b = fb[:, :3], fb[:, 3]
+    h = y[:, 2]
+    yi = y * torch.tensor([1.0, 1.0, -1.0], dtype=y.dtype, device=y.device)
+    y2 = torch.cat([y, yi]).contiguous()
+    z = torch.zeros_like(h)
+    vs = torch.cat([torch.stack([f[:, 0], f[:, 1], z, b], 1), torch.stack([-f[:, 0], -f[:, 1], z, b], 1)])
+    S = fmm.direct("RPY", y2, vs.contiguous(), None, None, xt)
+    sd_q = torch.cat([-0.5 * f[:, 2], 0.5 * f[:, 2]])[:, None].contiguous()
+    sd_d = (h[:, None] * torch.stack([-f[:, 0], -f[:, 1], f[:, 2]], 1)).contiguous()
+    SD = fmm.direct("LapPGradGrad", y2, sd_q, yi.contiguous(), sd_d, xt)
+    dz = torch.stack([z, z, b * b / 6.0 * f[:, 2]], 1)
+    Z = fmm.direct("LapPGrad", y2, torch.cat([0.5 * h * f[:, 2], -0.5 * h * f[:, 2]])[:, None].contiguous(),
+                   y2, torch.cat([dz, dz]).contiguous(), xt)
+    Q = torch.zeros((len(y), 9), dtype=y.dtype, device=y.device)
+    Q[:, 0] = f[:, 2]
+    Q[:, 4] = f[:, 2]
+    Q[:, 6] = f[:, 0]
+    Q[:, 7] = f[:, 1]
+    Q *= (b * b / 3.0)[:, None]
+    QP = fmm.direct("LapQPGradGrad", yi.contiguous(), Q, None, None, xt)
+    x3 = xt[:, 2:3]
+    u = S[:, :3] + Z[:, 1:4] + x3 * (SD[:, 1:4] + QP[:, 1:4])
+    u[:, 2] -= SD[:, 0] + QP[:, 0]
+    col3 = lambda H: torch.stack([H[:, 6], H[:, 8], H[:, 9]], 1)
+    return torch.cat([u, S[:, 3:] + 2.0 * (col3(SD) + col3(QP))], 1)
+
+
+def measure(fmm, torch, W, kernel, x, val, p, cap, args, precision="fp32", bc="open"):
     """Plan once, then time `steps` evaluation passes after `warmup`; error on
     sampled targets against the FP64 GPU direct sum."""
     learned = p == 0 or cap == 0
     fmm.set_option("precision", precision)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    fmm.set_points(kernel, x, None, x, p=p, leaf_cap=cap)
+    fmm.set_points(kernel, x, None, x, p=p, leaf_cap=cap, bc=bc)
     t_tree = fmm.timings()["t_tree_ms"]
     if learned:
         fmm.run(val)                  # the first run of a learned plan carries its accuracy check
@@ -104,9 +139,12 @@ def measure(fmm, torch, W, kernel, x, val, p, cap, args, precision="fp32"):
     serial = fmm.timings()
     fmm.set_option("overlap", "1")
     idx = torch.from_numpy(W.sample_indices(len(x), args.samples, 7)).cuda()
-    ref = fmm.direct(kernel, x, val, None, None, x[idx].contiguous())
+    if bc == "wall":
+        ref = wall_direct(fmm, torch, x, val, x[idx].contiguous())
+    else:
+        ref = fmm.direct(kernel, x, val, None, None, x[idx].contiguous())
     got = out[idx]
-    fields = {"Stokeslet": [("u", 0, 3)], "RPY": [("u", 0, 3), ("lap_u", 3, 6)]}[kernel]
+    fields = FIELDS[kernel]
     errs = {n: float(torch.linalg.norm(got[:, a:b] - ref[:, a:b]) / torch.linalg.norm(ref[:, a:b]))
             for n, a, b in fields}
     fmm.set_option("precision", "fp32")
@@ -114,7 +152,8 @@ def measure(fmm, torch, W, kernel, x, val, p, cap, args, precision="fp32"):
          "p2p_ms": float(np.mean(p2p_ms)), "p2p_pairs_per_s": st["p2p_pairs"] / (np.mean(p2p_ms) * 1e-3),
          "rel_l2": errs, "t_tree_ms": t_tree, "t_plan_ms": t_plan, "stages_ms": tm["stages_ms"],
          "stages_serial_ms": serial["stages_ms"], "run_serial_ms": serial["t_run_ms"], "plan": st,
-         "p": info["p"] if info else p, "leaf_cap": "per leaf" if cap == 0 else cap, "precision": precision}
+         "p": info["p"] if info else p, "leaf_cap": "per leaf" if cap == 0 else cap, "precision": precision,
+         "bc": bc}
     if info:
         r["learned"] = info
     return r
@@ -173,6 +212,15 @@ def main():
         line["learned_split_bf16"] = measure(fmm, torch, W, "Stokeslet", x, f, 0, 0, args, "split_bf16")
         fb = torch.from_numpy(np.concatenate([d["f"], d["b"][:, None]], 1)).cuda()
         line["rpy_fixed_p10"] = measure(fmm, torch, W, "RPY", x, fb, 10, 2000, args)
+        # the widened rows on the same points: regularized Stokeslet (blob
+        # sizes well below the smallest leaves) and RPY above a no-slip wall
+        # at z = 0 (the points lie above it)
+        rng = np.random.default_rng(202)
+        fe = torch.from_numpy(np.concatenate([d["f"], rng.uniform(5e-5, 1e-4, (n, 1))], 1)).cuda()
+        line["widened"] = {
+            "stokes_reg_vel_p8": measure(fmm, torch, W, "StokesRegVel", x, fe, 8, 1000, args),
+            "rpy_wall_p10": measure(fmm, torch, W, "RPY", x, fb, 10, 1000, args, bc="wall"),
+        }
     fmm.close()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)

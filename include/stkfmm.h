@@ -109,7 +109,8 @@ typedef enum {
 /* Create a context for the cube [origin, origin + box_len)^3 on HIP device
  * `device`.  flags: reserved, pass 0.  Operators (surface pseudo-inverses,
  * M2M/L2L/M2L matrices, periodic operator) are built lazily per order p on
- * first use and cached in the context.
+ * first use and shared by all contexts of the process on that device (one
+ * set per p, periodicity, "svd_tol" and "m2l_tol"), kept until it exits.
  * Errors: E_ARG (out NULL, box_len <= 0 or not finite), E_DEVICE. */
 stkfmm_status stkfmm_setup(stkfmm_ctx **out, const double origin[3], double box_len,
                            int device, unsigned flags);

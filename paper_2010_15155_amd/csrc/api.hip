@@ -17,6 +17,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <tuple>
 #include <array>
 #include <memory>
 #include <numeric>
@@ -150,7 +152,6 @@ struct stkfmm_ctx {
     double m2l_tol = 5e-8;      // compression of the V-list translations (0: dense)
     bool m2l_tol_set = false;   // set by the caller (else learned plans use tol / 50)
     int precision = 0;          // 0 fp32, 1 split_bf16
-    std::map<std::pair<int, double>, std::unique_ptr<DeviceOps>> ops_cache;   // key: (p*2 + periodic, m2l_tol)
     hipStream_t side = nullptr; // P2P stream
     hipEvent_t ev[24] = {};
     // plan
@@ -229,10 +230,20 @@ int sl_kind(int k) {
 int stage_kind(int k) { return k == kStokesRegVel ? 1 : sl_kind(k); }   // kinds 7, 8 pack and stage alike
 int dl_kind(int k) { return k == kLapPGrad || k == kLapPGradGrad ? 3 : 5; }
 
+// Device operators are shared by every context of the process (the summations
+// of a wall plan, repeated contexts): one set per (device, p, periodic,
+// svd_tol, m2l_tol), built on first use and kept until the process ends (the
+// map is never destroyed, so no device memory is freed after the runtime has
+// shut down).
+using OpsKey = std::tuple<int, int, bool, double, double>;
+std::mutex g_ops_mutex;
+std::map<OpsKey, std::unique_ptr<DeviceOps>> *g_ops = new std::map<OpsKey, std::unique_ptr<DeviceOps>>();
+
 stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, double m2l_tol, DeviceOps **out) {
-    const std::pair<int, double> key(p * 2 + (periodic ? 1 : 0), m2l_tol);
-    auto it = c->ops_cache.find(key);
-    if (it != c->ops_cache.end()) {
+    std::lock_guard<std::mutex> lock(g_ops_mutex);
+    const OpsKey key(c->device, p, periodic, c->svd_tol, m2l_tol);
+    auto it = g_ops->find(key);
+    if (it != g_ops->end()) {
         *out = it->second.get();
         return STKFMM_OK;
     }
@@ -312,7 +323,7 @@ stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, double m2l_tol, Devic
     }
     if (periodic) HIP_TRY(c, up(d->tm2l, h.t_m2l.data(), h.t_m2l.size() * sizeof(double)));
     *out = d.get();
-    c->ops_cache[key] = std::move(d);
+    (*g_ops)[key] = std::move(d);
     return STKFMM_OK;
 }
 
@@ -732,7 +743,6 @@ stkfmm_status stkfmm_set_option(stkfmm_ctx *c, const char *key, const char *valu
         char *end = nullptr;
         double t = std::strtod(value, &end);
         if (!end || *end || !(t >= 0) || !(t < 1)) return fail(c, STKFMM_E_ARG, "m2l_tol must lie in [0, 1)");
-        if (t != c->m2l_tol) c->ops_cache.clear();
         c->m2l_tol = t;
         c->m2l_tol_set = true;
         c->planned = false;
@@ -742,7 +752,6 @@ stkfmm_status stkfmm_set_option(stkfmm_ctx *c, const char *key, const char *valu
         char *end = nullptr;
         double t = std::strtod(value, &end);
         if (!end || *end || !(t > 0) || !(t < 1)) return fail(c, STKFMM_E_ARG, "svd_tol must lie in (0, 1)");
-        if (t != c->svd_tol) c->ops_cache.clear();
         c->svd_tol = t;
         c->planned = false;
         return STKFMM_OK;
