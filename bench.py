@@ -163,8 +163,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the evaluation pass is not sharded across GPUs "
-              "in this build (see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the evaluation pass is not sharded across GPUs",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2010_15155_amd import FMM, workloads as W

@@ -17,7 +17,11 @@ Features: 12 per leaf of the reference tree (leaf_cap 2000), computed by the
 library.  Training runs the library's HIP kernels (forward, loss gradient,
 Adam).  Weights are saved as a float32 .npy (load with allow_pickle=False).
 
+Plans are priced with the translation compression the learned mode uses
+(m2l_tol = tol / 50), since the M2L work and its speed depend on it.
+
   python -m paper_2010_15155_amd.predictor label --seeds 501:601 --out a.npz   (fits the costs first)
+  python -m paper_2010_15155_amd.predictor relabel-caps --data a.npz --out b.npz   (new costs, same order labels)
   python -m paper_2010_15155_amd.predictor train --data a.npz b.npz --out w.npy
 """
 from __future__ import annotations
@@ -66,12 +70,29 @@ def calibration_table(E, cls):
     return t
 
 
+def learned_compression(fmm, tol=1e-5):
+    """Price plans with the V-list compression of learned plans."""
+    fmm.set_option("m2l_tol", repr(tol / 50.0))
+
+
+def cap_costs(fmm, torch, x, costs, n_leaf, leaf_of, p_cap=8):
+    """[n_leaf, 4] cost of each leaf's targets under the plan built with each
+    capacity class everywhere: the plan's work on them priced by `costs`."""
+    price = np.asarray(costs, dtype=np.float64)
+    out = np.zeros((n_leaf, len(CAP_CLASSES)))
+    for q, cap in enumerate(CAP_CLASSES):
+        fmm.set_points("Stokeslet", x, None, x, p=p_cap, leaf_cap=cap)
+        out[:, q] = np.bincount(leaf_of, weights=fmm.plan_work() @ price, minlength=n_leaf)
+    return out
+
+
 def fit_costs(fmm, torch, p=8, caps=(250, 500, 1000, 2000), seeds=(201, 911, 912)):
     """Unit costs (seconds) of the five plan-work components, least-squares fits
     of serial stage times over plans at several uniform capacities: P2P time on
     lane pairs and wave entries, M2L time on flops, S2M + S2L + L2T time on
     surface evaluations, the remaining stages on boxes (plus a constant)."""
     rows, times = [], []
+    learned_compression(fmm)
     fmm.set_option("overlap", "0")
     for seed in seeds:
         d = W.clustered_rpy(1_048_576, seed) if seed == 201 else W.mixture(seed, (500_000, 2_000_000))
@@ -105,11 +126,8 @@ def label_set(fmm, torch, seed, costs, tol=1e-5, per_leaf=4, p_cap=8):
         outs[p] = fmm.run(f).clone()
     feat, leaf_of = fmm.leaf_features()
     # capacity: each uniform-capacity plan's work on the leaf's targets, priced
-    price = np.asarray(costs, dtype=np.float64)
-    cap_cost = np.zeros((len(feat), len(CAP_CLASSES)))
-    for q, cap in enumerate(CAP_CLASSES):
-        fmm.set_points("Stokeslet", x, None, x, p=p_cap, leaf_cap=cap)
-        cap_cost[:, q] = np.bincount(leaf_of, weights=fmm.plan_work() @ price, minlength=len(feat))
+    learned_compression(fmm, tol)
+    cap_cost = cap_costs(fmm, torch, x, costs, len(feat), leaf_of, p_cap)
     # sampled targets: up to per_leaf per leaf, spread over the leaf
     rng = np.random.default_rng(seed)
     order = np.argsort(leaf_of, kind="stable")
@@ -139,6 +157,20 @@ def label_set(fmm, torch, seed, costs, tol=1e-5, per_leaf=4, p_cap=8):
     labels[:, 0] = order_labels(errs, tol)
     labels[:, 1] = cap_cost[keep].argmin(axis=1)
     return feat[keep], labels, errs, {"seed": seed, "n": len(d["xyz"]), "leaves": len(feat), "k": d["k"]}
+
+
+def relabel_caps(fmm, torch, seed, costs, p_cap=8):
+    """Capacity labels of one mixture's leaves (the rows `label_set` kept: every
+    leaf of the leaf_cap 2000 tree, all of which hold targets) under new unit
+    costs; the order labels do not depend on them."""
+    d = W.mixture(seed, N_RANGE)
+    x = torch.from_numpy(d["xyz"]).cuda()
+    fmm.set_points("Stokeslet", x, None, x, p=p_cap, leaf_cap=2000)
+    feat, leaf_of = fmm.leaf_features()
+    learned_compression(fmm)
+    cost = cap_costs(fmm, torch, x, costs, len(feat), leaf_of, p_cap)
+    keep = np.unique(leaf_of)
+    return feat[keep], cost[keep].argmin(axis=1).astype(np.int32)
 
 
 def train(X, Y, epochs=60, batch=1024, lr=2e-3, seed=0, log=None):
@@ -188,6 +220,10 @@ def main(argv=None):
     a.add_argument("--seeds", default="501:701")
     a.add_argument("--out", required=True)
     a.add_argument("--costs", default="", help="five unit costs (default: fit them first)")
+    r = sub.add_parser("relabel-caps")
+    r.add_argument("--data", required=True)
+    r.add_argument("--out", required=True)
+    r.add_argument("--costs", default="", help="five unit costs (default: fit them first)")
     t = sub.add_parser("train")
     t.add_argument("--data", nargs="+", required=True)
     t.add_argument("--out", default=WEIGHTS)
@@ -212,6 +248,28 @@ def main(argv=None):
             print(json.dumps(info), flush=True)
             np.savez(args.out, X=np.concatenate(Xs), Y=np.concatenate(Ys), E=np.concatenate(Es),
                      costs=np.array(costs), seeds=np.array([m["seed"] for m in meta]))
+    elif args.cmd == "relabel-caps":
+        fmm = FMM()
+        costs = [float(r) for r in args.costs.split(",")] if args.costs else fit_costs(fmm, torch)
+        print(json.dumps({"costs": costs}), flush=True)
+        old = np.load(args.data, allow_pickle=False)
+        X, Y = old["X"].copy(), old["Y"].copy()
+        row = 0
+        for seed in old["seeds"]:
+            t0 = time.time()
+            feat, cap = relabel_caps(fmm, torch, int(seed), costs)
+            n = len(feat)
+            if not np.allclose(feat, X[row:row + n], rtol=1e-5, atol=1e-6):
+                raise RuntimeError("seed %d: leaves differ from the stored rows" % seed)
+            changed = int((Y[row:row + n, 1] != cap).sum())
+            Y[row:row + n, 1] = cap
+            row += n
+            print(json.dumps({"seed": int(seed), "leaves": n, "changed": changed,
+                              "cap_hist": np.bincount(cap, minlength=4).tolist(),
+                              "secs": time.time() - t0}), flush=True)
+        if row != len(X):
+            raise RuntimeError("stored rows %d, relabelled %d" % (len(X), row))
+        np.savez(args.out, X=X, Y=Y, E=old["E"], costs=np.array(costs), seeds=old["seeds"])
     else:
         data = [np.load(f, allow_pickle=False) for f in args.data]
         X = np.concatenate([d["X"] for d in data])
