@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-headline", action="store_true",
                     help="measure the learned Stokeslet plan only (for profiler runs)")
+    ap.add_argument("--only-plan", action="store_true",
+                    help="measure the plan time with the GPU and the host tree builders only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the measurement, copy a MIB-sized device buffer once (reference "
                          "kernel for scaling hardware byte counters)")
@@ -159,6 +161,26 @@ def measure(fmm, torch, W, kernel, x, val, p, cap, args, precision="fp32", bc="o
     return r
 
 
+def tree_build(FMM, x):
+    """Plan time (stkfmm_set_points: octree, lists and plan arrays; operators
+    cached) with the octree and lists built by the GPU kernels or on the host."""
+    out = {}
+    for cap in (2000, 500):
+        row = {}
+        for how in ("gpu", "host"):
+            f = FMM()
+            f.set_option("tree", how)
+            ts = []
+            for _ in range(4):
+                f.set_points("Stokeslet", x, None, x, p=8, leaf_cap=cap)
+                ts.append(f.timings()["t_tree_ms"])
+            row[how + "_ms"] = float(np.median(ts[1:]))
+            row["boxes"] = f.stats()["boxes"]
+            f.close()
+        out["leaf_cap_%d" % cap] = row
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -173,6 +195,9 @@ def main():
     d = W.clustered_rpy(args.n, 201)
     x = torch.from_numpy(d["xyz"]).cuda()
     f = torch.from_numpy(d["f"]).cuda()
+    if args.only_plan:
+        print(json.dumps({"plan_ms": tree_build(FMM, x)}), flush=True)
+        return
     fmm = FMM()
     fmm.set_predictor(load_weights())
     L = measure(fmm, torch, W, "Stokeslet", x, f, 0, 0, args)
@@ -221,6 +246,7 @@ def main():
             "stokes_reg_vel_p8": measure(fmm, torch, W, "StokesRegVel", x, fe, 8, 1000, args),
             "rpy_wall_p10": measure(fmm, torch, W, "RPY", x, fb, 10, 1000, args, bc="wall"),
         }
+        line["plan_ms"] = tree_build(FMM, x)
     fmm.close()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)

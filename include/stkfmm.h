@@ -174,7 +174,10 @@ stkfmm_status stkfmm_kernel_dims(stkfmm_kernel kernel, int *k_sl, int *k_dl, int
  * (defaults 0.73 / 0.5), "m2l_tol" = relative singular-value cut of the
  * shared basis that compresses the V-list translations (default 5e-8: rank
  * 192 at p = 8; learned plans use tol / 50 unless it was set, rank 160 at
- * p = 8 for tol 1e-5; "0" keeps them dense).  Errors: E_ARG. */
+ * p = 8 for tol 1e-5; "0" keeps them dense), "tree" = "gpu" (the default:
+ * Morton keys, the sort, the refinement and the U/V/W/X lists are built by
+ * the library's HIP kernels from the device coordinates) | "host" (the same
+ * tree built on host threads).  Errors: E_ARG. */
 stkfmm_status stkfmm_set_option(stkfmm_ctx *ctx, const char *key, const char *value);
 
 /* Timings of the last set_points (t_tree_ms) and run (t_run_ms, device event
@@ -200,6 +203,26 @@ stkfmm_status stkfmm_get_timings(const stkfmm_ctx *ctx, double *t_tree_ms, doubl
  * For a WALL plan: the statistics of its Stokes summation (sources and
  * their images).  Errors: E_ARG, E_STATE. */
 stkfmm_status stkfmm_get_stats(const stkfmm_ctx *ctx, int64_t stats[20]);
+
+/* The adaptive octree and interaction lists of the last set_points (Sec. II:
+ * the tree and the U, V, W, X lists of KIFMM), copied to caller-owned host
+ * memory.  sizes[8] (out): n_box, n_u, n_v, n_w, n_x (list entries), n_sl,
+ * n_dl, n_trg.  With box == NULL only sizes are written; else all of:
+ *   box  [n_box][12] int32: level, anchor x, y, z (in cells of the level),
+ *        parent (-1 for the root), is_leaf, then the [begin, end) ranges of
+ *        the box's SL, DL and target points in the sorted orders;
+ *   perm [n_sl + n_dl + n_trg] int32: sorted position -> input index, SL
+ *        then DL then targets (points sorted by Morton key, ties by index);
+ *   off  [4][n_box + 1] int32: CSR offsets of the U, V, W, X lists by box;
+ *   ent  [n_u + n_v + n_w + n_x][4] int32: U, then V, W, X entries: source
+ *        box and periodic image shift (x, y, z, in root-box lengths).
+ * Boxes are breadth-first (level by level, each level in Morton order);
+ * entries within a list are ordered by (box, shift); entries whose box holds
+ * no sources and the lists of boxes without targets are dropped.
+ * Errors: E_ARG, E_STATE (no plan), E_UNSUPPORTED (WALL plans hold one tree
+ * per summation). */
+stkfmm_status stkfmm_get_tree(const stkfmm_ctx *ctx, int64_t sizes[8], int32_t *box, int32_t *perm,
+                              int32_t *off, int32_t *ent);
 
 /* ---------------------------------------------------------------------
  * Learned order / leaf-capacity mode.  stkfmm_set_points with p = 0 and/or

@@ -213,6 +213,23 @@ def pinv(K, tol):
 # --------------------------------------------------------------------------
 # Octree and interaction lists
 # --------------------------------------------------------------------------
+def morton_order(x, origin, L0, bits=21):
+    """Sorted position -> input index of points along the Z-order (Morton)
+    curve of the 2^bits grid over [origin, origin + L0)^3: points compare by
+    the octant digits of their cells from the root down (within a level the
+    x bit is the most significant), ties by input index.  Coordinates on the
+    upper face fall into the last cell."""
+    x = np.asarray(x, dtype=np.float64).reshape(-1, 3)
+    u = (x - np.asarray(origin, dtype=np.float64)) / L0
+    cell = np.clip(np.floor(u * 2.0 ** bits), 0, 2 ** bits - 1).astype(np.int64)
+    key = np.zeros(len(x), dtype=np.uint64)
+    for lev in range(bits):
+        sh = bits - 1 - lev
+        digit = ((cell[:, 0] >> sh) & 1) * 4 + ((cell[:, 1] >> sh) & 1) * 2 + ((cell[:, 2] >> sh) & 1)
+        key = key * np.uint64(8) + digit.astype(np.uint64)
+    return np.lexsort((np.arange(len(x)), key))
+
+
 class Tree:
     """Adaptive octree over the union of SL, DL and target points."""
 

@@ -26,7 +26,8 @@ SYMBOLS = ["stkfmm_setup", "stkfmm_set_points", "stkfmm_run", "stkfmm_evaluate",
            "stkfmm_kernel_dims", "stkfmm_set_option", "stkfmm_get_timings", "stkfmm_get_stats",
            "stkfmm_last_error", "stkfmm_destroy", "stkfmm_mlp_nparam", "stkfmm_mlp_workspace",
            "stkfmm_set_predictor", "stkfmm_get_learned", "stkfmm_get_leaf_features",
-           "stkfmm_get_plan_work", "stkfmm_mlp_forward", "stkfmm_mlp_loss_grad", "stkfmm_mlp_adam"]
+           "stkfmm_get_plan_work", "stkfmm_mlp_forward", "stkfmm_mlp_loss_grad", "stkfmm_mlp_adam",
+           "stkfmm_get_tree"]
 ORDER_CLASSES = (6, 8, 10, 12)
 CAP_CLASSES = (250, 500, 1000, 2000)
 
@@ -58,6 +59,7 @@ def lib():
     L.stkfmm_set_option.argtypes = [vp, ctypes.c_char_p, ctypes.c_char_p]
     L.stkfmm_get_timings.argtypes = [vp, ctypes.POINTER(cd), ctypes.POINTER(cd), ctypes.POINTER(cd)]
     L.stkfmm_get_stats.argtypes = [vp, ctypes.POINTER(i64)]
+    L.stkfmm_get_tree.argtypes = [vp, ctypes.POINTER(i64), vp, vp, vp, vp]
     L.stkfmm_last_error.argtypes = [vp]
     L.stkfmm_last_error.restype = ctypes.c_char_p
     L.stkfmm_destroy.argtypes = [vp]
@@ -187,6 +189,29 @@ class FMM:
                  "n_trg", "n_sl", "n_dl", "u_entries", "p2p_pairs", "w_direct", "x_direct", "p2p_tasks",
                  "m2l_rank", "Mp", "pinv_rank", "p2p_lane_pairs"]
         return {n: int(a[i]) for i, n in enumerate(names)}
+
+    def tree(self):
+        """The octree and U/V/W/X lists of the current plan as NumPy arrays: box [n_box, 12]
+        (level, anchor xyz, parent, is_leaf, SL/DL/target ranges), perm_sl/perm_dl/perm_trg
+        (sorted position -> input index) and, per list, CSR offsets [n_box + 1] and entries
+        [n, 4] (box, shift xyz)."""
+        import numpy as np
+        sz = (ctypes.c_int64 * 8)()
+        self._check(lib().stkfmm_get_tree(self._h, sz, None, None, None, None), "get_tree")
+        nb, nu, nv, nw, nx, ns, nd, nt = (int(v) for v in sz)
+        box = np.zeros((nb, 12), dtype=np.int32)
+        perm = np.zeros(ns + nd + nt, dtype=np.int32)
+        off = np.zeros((4, nb + 1), dtype=np.int32)
+        ent = np.zeros((nu + nv + nw + nx, 4), dtype=np.int32)
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        self._check(lib().stkfmm_get_tree(self._h, sz, ptr(box), ptr(perm), ptr(off), ptr(ent)), "get_tree")
+        out = {"box": box, "perm_sl": perm[:ns], "perm_dl": perm[ns:ns + nd], "perm_trg": perm[ns + nd:]}
+        e0 = 0
+        for q, (name, n) in enumerate(zip("UVWX", (nu, nv, nw, nx))):
+            out[name + "_off"] = off[q]
+            out[name] = ent[e0:e0 + n]
+            e0 += n
+        return out
 
     # ---------------------------------------------------------------- learned mode
     def set_predictor(self, params):

@@ -173,6 +173,7 @@ struct stkfmm_ctx {
     // surface evaluations (S2M, S2L, L2T/M2T), 1 per box
     std::vector<std::array<double, 5>> box_work;
     int overlap = 1;
+    int tree_gpu = 1;           // build the octree and lists on the GPU (0: host)
     // sources' vanishing moments: 0 none, 1 charge (dipoles only), 2 charge
     // and dipole (quadrupoles only); picks the moment-free UC2UE
     int moments = 0;
@@ -725,6 +726,13 @@ stkfmm_status stkfmm_set_option(stkfmm_ctx *c, const char *key, const char *valu
         c->planned = false;
         return STKFMM_OK;
     }
+    if (k == "tree") {
+        if (v == "gpu") c->tree_gpu = 1;
+        else if (v == "host") c->tree_gpu = 0;
+        else return fail(c, STKFMM_E_ARG, "tree must be gpu or host");
+        c->planned = false;
+        return STKFMM_OK;
+    }
     if (k == "overlap") {
         if (v == "1") c->overlap = 1;
         else if (v == "0") c->overlap = 0;
@@ -802,6 +810,48 @@ stkfmm_status stkfmm_get_stats(const stkfmm_ctx *c, int64_t st[20]) {
     return STKFMM_OK;
 }
 
+stkfmm_status stkfmm_get_tree(const stkfmm_ctx *c, int64_t sizes[8], int32_t *box, int32_t *perm, int32_t *off,
+                              int32_t *ent) {
+    if (!c || !sizes) return STKFMM_E_ARG;
+    if (c->wall) return STKFMM_E_UNSUPPORTED;
+    if (!c->planned) return STKFMM_E_STATE;
+    const Tree &t = c->tree;
+    const int64_t nb = int64_t(t.boxes.size());
+    const std::vector<Entry> *L[4] = {&t.u, &t.v, &t.w, &t.x};
+    const std::vector<int> *O[4] = {&t.u_off, &t.v_off, &t.w_off, &t.x_off};
+    sizes[0] = nb;
+    for (int q = 0; q < 4; ++q) sizes[1 + q] = int64_t(L[q]->size());
+    sizes[5] = int64_t(t.perm_sl.size());
+    sizes[6] = int64_t(t.perm_dl.size());
+    sizes[7] = int64_t(t.perm_trg.size());
+    if (!box) return STKFMM_OK;
+    if (!perm || !off || !ent) return STKFMM_E_ARG;
+    for (int64_t b = 0; b < nb; ++b) {
+        const Box &B = t.boxes[b];
+        int32_t *o = box + 12 * b;
+        o[0] = B.level;
+        for (int k = 0; k < 3; ++k) o[1 + k] = B.anchor[k];
+        o[4] = B.parent;
+        o[5] = B.leaf ? 1 : 0;
+        o[6] = int32_t(B.sl[0]);  o[7] = int32_t(B.sl[1]);
+        o[8] = int32_t(B.dl[0]);  o[9] = int32_t(B.dl[1]);
+        o[10] = int32_t(B.trg[0]); o[11] = int32_t(B.trg[1]);
+    }
+    std::copy(t.perm_sl.begin(), t.perm_sl.end(), perm);
+    std::copy(t.perm_dl.begin(), t.perm_dl.end(), perm + sizes[5]);
+    std::copy(t.perm_trg.begin(), t.perm_trg.end(), perm + sizes[5] + sizes[6]);
+    int64_t e0 = 0;
+    for (int q = 0; q < 4; ++q) {
+        std::copy(O[q]->begin(), O[q]->end(), off + q * (nb + 1));
+        for (const Entry &en : *L[q]) {
+            int32_t *o = ent + 4 * e0++;
+            o[0] = en.box;
+            for (int k = 0; k < 3; ++k) o[1 + k] = en.shift[k];
+        }
+    }
+    return STKFMM_OK;
+}
+
 stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc bc, int64_t n_sl,
                                 const double *sl_xyz, int64_t n_dl, const double *dl_xyz, int64_t n_trg,
                                 const double *trg_xyz, int p, int leaf_cap, void *stream) {
@@ -861,8 +911,14 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     c->sampled_err = -1.0;
     for (int k = 0; k < 4; ++k) c->p_hist[k] = c->cap_hist[k] = 0;
     std::string e;
+    // the octree on the GPU from the caller's coordinates, or on the host
+    // from the normalised copies (the same tree)
+    auto build = [&](int cap, bool per, const std::unordered_map<uint64_t, int> *caps) {
+        if (c->tree_gpu) return build_tree_gpu(src, cnt, c->origin, c->box_len, cap, per, t, caps, stream);
+        return build_tree(h[0].data(), n_sl, h[1].data(), n_dl, h[2].data(), n_trg, cap, per, t, caps);
+    };
     if (!learned) {
-        e = build_tree(h[0].data(), n_sl, h[1].data(), n_dl, h[2].data(), n_trg, leaf_cap, periodic, t);
+        e = build(leaf_cap, periodic, nullptr);
         if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
     } else {
         // keep the caller's coordinates for the accuracy check and the fallback
@@ -873,7 +929,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
         }
         // reference tree, per-leaf features, network on the GPU
         const int ref_cap = leaf_cap ? leaf_cap : kReferenceCap;
-        e = build_tree(h[0].data(), n_sl, h[1].data(), n_dl, h[2].data(), n_trg, ref_cap, false, t);
+        e = build(ref_cap, false, nullptr);
         if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
         std::vector<float> feat;
         leaf_features(t, h[0].data(), h[1].data(), h[2].data(), c->tol, feat);
@@ -917,7 +973,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
         if (leaf_cap == 0) {
             leaf_cap = ref_cap;
             if (!caps.empty()) {
-                e = build_tree(h[0].data(), n_sl, h[1].data(), n_dl, h[2].data(), n_trg, ref_cap, false, t, &caps);
+                e = build(ref_cap, false, &caps);
                 if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
             }
         }

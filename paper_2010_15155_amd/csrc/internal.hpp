@@ -81,6 +81,17 @@ std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t
                        const double *trg, int64_t n_trg, int leaf_cap, bool periodic, Tree &t,
                        const std::unordered_map<uint64_t, int> *leaf_caps = nullptr);
 
+// The same tree built on the GPU from the caller's device coordinates
+// (sl, dl, trg: [n][3] FP64, normalised with origin and box_len, wrapped if
+// periodic), on the HIP stream `stream`.  Leaves keys_* empty.
+std::string build_tree_gpu(const double *const xyz[3], const int64_t n[3], const double origin[3], double box_len,
+                           int leaf_cap, bool periodic, Tree &t,
+                           const std::unordered_map<uint64_t, int> *leaf_caps, void *stream);
+
+// V-list anchor offsets, local-expansion flags and the P2P pair count of a
+// tree whose boxes and lists are set.
+void finish_tree(Tree &t);
+
 
 // ---- learned order / capacity predictor (host side)
 constexpr int kNumFeatures = 12;

@@ -347,6 +347,12 @@ std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t
     flatten(W, t.w_off, t.w, true, true);
     flatten(X, t.x_off, t.x, true, true);
     flatten(V, t.v_off, t.v, true, true);
+    finish_tree(t);
+    return "";
+}
+
+void finish_tree(Tree &t) {
+    const int nb = int(t.boxes.size());
     t.v_rel.resize(3 * t.v.size());
     for (int b = 0; b < nb; ++b) {
         const Box &B = t.boxes[b];
@@ -362,7 +368,7 @@ std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t
         if (B.ntrg_sub == 0) continue;
         bool loc = (t.v_off[b + 1] > t.v_off[b]) || (t.x_off[b + 1] > t.x_off[b]);
         if (B.parent >= 0 && t.has_local[B.parent]) loc = true;
-        if (b == 0 && periodic) loc = true;
+        if (b == 0 && t.periodic) loc = true;
         t.has_local[b] = loc;
     }
     t.p2p_pairs = 0;
@@ -371,7 +377,6 @@ std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t
         for (int i = t.u_off[b]; i < t.u_off[b + 1]; ++i) s += t.boxes[t.u[i].box].nsrc_sub;
         t.p2p_pairs += s * ntrg(t.boxes[b]);
     }
-    return "";
 }
 
 }  // namespace kafmm

@@ -6,7 +6,10 @@
   (U, or V / W / X of the target leaf or an ancestor);
 * the error against the direct sum falls as the order p grows (Sec. III:
   exponential convergence in m) for every kernel table;
-* the N=4096 uniform Stokeslet workload at p = 8, leaf_cap = 64.
+* the N=4096 uniform Stokeslet workload at p = 8, leaf_cap = 64;
+* the Morton order of the points is the lexicographic order of their cells'
+  octant digits (computed level by level, without bit interleaving), and
+  every box of the tree holds an interval of it.
 """
 import numpy as np
 import pytest
@@ -76,6 +79,44 @@ def test_tree_respects_leaf_cap():
         c, h = T.centre(b), T.side(b)
         pts = T.sets[2][T.idx[b][2]]
         assert np.all(pts >= c - h / 2) and np.all(pts < c + h / 2)
+
+
+def _digit_tuple(p, bits=21):
+    # octant digits of the point's cells from the root down, each level on
+    # its own (floor(u 2^l) mod 2 per dimension), with no bit interleaving
+    out = []
+    for lev in range(1, bits + 1):
+        c = [min(int(np.floor(v * 2.0 ** lev)), 2 ** lev - 1) % 2 for v in p]
+        out.append(4 * c[0] + 2 * c[1] + c[2])
+    return tuple(out)
+
+
+def test_morton_order_is_the_octant_digit_order():
+    rng = np.random.default_rng(11)
+    x = rng.random((300, 3))
+    x[:40] = x[40:80]                         # duplicates: ties keep input order
+    x[80:120] = np.round(x[80:120] * 8) / 8   # points on cell faces of several levels
+    x[120:130, 0] = 1.0 - 2.0 ** -60          # next to the upper face
+    want = sorted(range(len(x)), key=lambda i: (_digit_tuple(x[i]), i))
+    assert np.array_equal(kifmm.morton_order(x, (0, 0, 0), 1.0), want)
+    # the eight octant centres at level 1 come in digit order x*4 + y*2 + z
+    c = np.array([[(o >> 2) & 1, (o >> 1) & 1, o & 1] for o in range(8)]) * 0.5 + 0.25
+    perm = np.array([5, 0, 7, 2, 6, 1, 4, 3])
+    assert np.array_equal(perm[kifmm.morton_order(c[perm], (0, 0, 0), 1.0)], np.arange(8))
+
+
+def test_tree_boxes_are_morton_intervals():
+    pb = _problem("PVel", 3000, 7, True)
+    T = kifmm.Tree(pb["sl"], pb["dl"], pb["trg"], (0, 0, 0), 1.0, 40)
+    for k in range(3):
+        if len(T.sets[k]) == 0:
+            continue
+        pos = np.empty(len(T.sets[k]), dtype=np.int64)
+        pos[kifmm.morton_order(T.sets[k], (0, 0, 0), 1.0)] = np.arange(len(T.sets[k]))
+        for b in range(T.nbox):
+            p = np.sort(pos[T.idx[b][k]])
+            if len(p):
+                assert p[-1] - p[0] + 1 == len(p)
 
 
 def test_surface_point_count():
