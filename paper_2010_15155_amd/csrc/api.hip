@@ -71,12 +71,25 @@ struct DevMem {
     template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
-// Host staging area for plan arrays: one device allocation, one copy.
+// Host staging area for plan arrays: one device allocation, one copy.  The
+// context keeps it between plans (clear() keeps the memory), so a re-plan
+// of a similar problem writes into pages it already holds.
 struct Arena {
     std::vector<char> host;
+    size_t used = 0;
+    void clear() { used = 0; }
+    // room for n values of T (uninitialised); ptr<T>(off) is valid until
+    // the next reserve or add
+    template <class T> size_t reserve(size_t n) {
+        const size_t off = (used + 255) / 256 * 256;
+        const size_t bytes = std::max<size_t>(n * sizeof(T), 1);
+        if (off + bytes > host.size()) host.resize(std::max(off + bytes, host.size() + host.size() / 2));
+        used = off + bytes;
+        return off;
+    }
+    template <class T> T *ptr(size_t off) { return reinterpret_cast<T *>(host.data() + off); }
     template <class T> size_t add(const std::vector<T> &v) {
-        size_t off = (host.size() + 255) / 256 * 256;
-        host.resize(off + std::max<size_t>(v.size() * sizeof(T), 1));
+        const size_t off = reserve<T>(v.size());
         if (!v.empty()) std::memcpy(host.data() + off, v.data(), v.size() * sizeof(T));
         return off;
     }
@@ -160,6 +173,7 @@ struct stkfmm_ctx {
     int64_t n_sl = 0, n_dl = 0, n_trg = 0;
     Tree tree;
     DeviceOps *ops = nullptr;
+    Arena staging;              // host image of `arena`, reused between plans
     DevMem arena, sl_rec, dl_rec, trg_rec, up_dens, dn_dens, up_chk, dn_chk, Ybuf, near_part, far_part,
         s2c_part, partial, direct_work, sl_stage, dl_stage, up_cmp;
     size_t a_perm_sl = 0, a_perm_dl = 0, a_perm_trg = 0, a_geom = 0, a_box_sl = 0, a_box_dl = 0, a_chunks = 0,
@@ -185,6 +199,7 @@ struct stkfmm_ctx {
     double tol = 1e-5, sampled_err = -1.0;
     int p_hist[4] = {0, 0, 0, 0}, cap_hist[4] = {0, 0, 0, 0};
     std::vector<double> hcoords[3];      // normalised user-order coordinates of the last plan
+    bool hcoords_valid = false;          // (else copied from coords[] when asked for)
     double w_direct_frac = 0.73, x_direct_frac = 0.5;
     int64_t p2p_task_sources = 2048;
     Batch m2l;
@@ -329,38 +344,38 @@ stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, double m2l_tol, Devic
 }
 
 // Group translation pairs by operator for the GEMM and by destination for the reduce.
-Batch make_batch(Arena &ar, std::vector<Pair> pairs, int nc, int accumulate, size_t &ybuf_floats, int Mp) {
+Batch make_batch(Arena &ar, std::vector<Pair> &pairs, int nc, int accumulate, size_t &ybuf_floats, int Mp) {
     Batch b;
     b.accumulate = accumulate;
+    const size_t np = pairs.size();
     // stable counting sorts: by operator for the GEMM tiles, by destination for the reduce
     auto stable_order = [&](auto key, int nkey) {
-        std::vector<int> start(nkey + 1, 0), order(pairs.size());
+        std::vector<int> start(nkey + 1, 0), order(np);
         for (const Pair &pr : pairs) ++start[key(pr) + 1];
         for (int k = 0; k < nkey; ++k) start[k + 1] += start[k];
-        for (size_t i = 0; i < pairs.size(); ++i) order[start[key(pairs[i])]++] = int(i);
+        for (size_t i = 0; i < np; ++i) order[start[key(pairs[i])]++] = int(i);
         return order;
     };
     {
         int nop = 0;
         for (const Pair &pr : pairs) nop = std::max(nop, pr.op + 1);
         const std::vector<int> byop = stable_order([](const Pair &pr) { return pr.op; }, nop);
-        std::vector<Pair> sorted(pairs.size());
-        for (size_t i = 0; i < byop.size(); ++i) sorted[i] = pairs[byop[i]];
+        std::vector<Pair> sorted(np);
+        for (size_t i = 0; i < np; ++i) sorted[i] = pairs[byop[i]];
         pairs.swap(sorted);
     }
-    b.npairs = int(pairs.size());
-    std::vector<int> bcol, ycol;
+    b.npairs = int(np);
+    std::vector<int> bcol(np * nc), ycol(np * nc);
     std::vector<int4> tiles;
-    for (size_t i = 0; i < pairs.size();) {
+    for (size_t k = 0; k < np; ++k)
+        for (int c = 0; c < nc; ++c) {
+            bcol[k * nc + c] = pairs[k].src * nc + c;
+            ycol[k * nc + c] = int(k) * nc + c;
+        }
+    for (size_t i = 0; i < np;) {
         size_t j = i;
-        while (j < pairs.size() && pairs[j].op == pairs[i].op) ++j;
-        int c0 = int(bcol.size());
-        for (size_t k = i; k < j; ++k)
-            for (int c = 0; c < nc; ++c) {
-                bcol.push_back(pairs[k].src * nc + c);
-                ycol.push_back(int(k) * nc + c);
-            }
-        int ncols = int(bcol.size()) - c0;
+        while (j < np && pairs[j].op == pairs[i].op) ++j;
+        const int c0 = int(i) * nc, ncols = int(j - i) * nc;
         for (int t = 0; t < ncols; t += 128) tiles.push_back(make_int4(pairs[i].op, c0 + t, std::min(128, ncols - t), 0));
         i = j;
     }
@@ -369,23 +384,23 @@ Batch make_batch(Arena &ar, std::vector<Pair> pairs, int nc, int accumulate, siz
     int ndst = 0;
     for (const Pair &pr : pairs) ndst = std::max(ndst, pr.dst + 1);
     const std::vector<int> order = stable_order([](const Pair &pr) { return pr.dst; }, ndst);
-    std::vector<int> rdst, roff, rpair;
-    std::vector<double> rscale;
-    std::vector<float> rdelta;
-    for (size_t i = 0; i < order.size();) {
+    std::vector<int> rdst, roff, rpair(np);
+    std::vector<double> rscale(np);
+    std::vector<float> rdelta(3 * np);
+    for (size_t i = 0; i < np;) {
         size_t j = i;
-        while (j < order.size() && pairs[order[j]].dst == pairs[order[i]].dst) ++j;
+        while (j < np && pairs[order[j]].dst == pairs[order[i]].dst) ++j;
         rdst.push_back(pairs[order[i]].dst);
-        roff.push_back(int(rpair.size()));
+        roff.push_back(int(i));
         for (size_t k = i; k < j; ++k) {
             const Pair &pr = pairs[order[k]];
-            rpair.push_back(order[k]);
-            rscale.push_back(pr.scale);
-            rdelta.insert(rdelta.end(), pr.delta, pr.delta + 3);
+            rpair[k] = order[k];
+            rscale[k] = pr.scale;
+            for (int q = 0; q < 3; ++q) rdelta[3 * k + q] = pr.delta[q];
         }
         i = j;
     }
-    roff.push_back(int(rpair.size()));
+    roff.push_back(int(np));
     b.ntasks = int(rdst.size());
     b.tiles = ar.add(tiles);
     b.bcol = ar.add(bcol);
@@ -395,7 +410,84 @@ Batch make_batch(Arena &ar, std::vector<Pair> pairs, int nc, int accumulate, siz
     b.rpair = ar.add(rpair);
     b.rscale = ar.add(rscale);
     b.rdelta = ar.add(rdelta);
-    ybuf_floats = std::max(ybuf_floats, size_t(b.npairs) * nc * Mp);
+    ybuf_floats = std::max(ybuf_floats, np * nc * Mp);
+    return b;
+}
+
+// The V-list batch (M2L), straight from the lists: pairs grouped by
+// relative offset (stable in box order) for the GEMM tiles, and per
+// destination box its pairs in that order for the reduce; the same arrays
+// as make_batch gives for the pairs listed box by box.
+Batch make_v_batch(Arena &ar, const Tree &t, const std::vector<double4> &geom, int nc, size_t &ybuf_floats, int Mp) {
+    Batch b;
+    b.accumulate = 1;
+    const int nb = int(t.boxes.size());
+    const int64_t ne = int64_t(t.v.size());
+    std::vector<int16_t> op(ne, -1);
+    std::vector<int> start(344, 0);
+    for (int d = 0; d < nb; ++d) {
+        if (!t.has_local[d]) continue;
+        for (int i = t.v_off[d]; i < t.v_off[d + 1]; ++i) {
+            const int8_t *o = &t.v_rel[3 * size_t(i)];
+            op[i] = int16_t(offset_index(o[0], o[1], o[2]));
+            ++start[op[i] + 1];
+        }
+    }
+    for (int k = 0; k < 343; ++k) start[k + 1] += start[k];
+    const int np = start[343];
+    b.npairs = np;
+    std::vector<int4> tiles;
+    for (int k = 0; k < 343; ++k)
+        for (int c0 = start[k] * nc, c1 = start[k + 1] * nc, c = c0; c < c1; c += 128)
+            tiles.push_back(make_int4(k, c, std::min(128, c1 - c), 0));
+    b.ntiles = int(tiles.size());
+    int ndst = 0;
+    for (int d = 0; d < nb; ++d) ndst += t.has_local[d] && t.v_off[d + 1] > t.v_off[d];
+    // the large arrays are written in place in the staging area
+    b.tiles = ar.add(tiles);
+    b.bcol = ar.reserve<int>(size_t(np) * nc);
+    b.ycol = ar.reserve<int>(size_t(np) * nc);
+    b.rdst = ar.reserve<int>(ndst);
+    b.roff = ar.reserve<int>(size_t(ndst) + 1);
+    b.rpair = ar.reserve<int>(np);
+    b.rscale = ar.reserve<double>(np);
+    b.rdelta = ar.reserve<float>(3 * size_t(np));
+    int *bcol = ar.ptr<int>(b.bcol), *ycol = ar.ptr<int>(b.ycol), *rdst = ar.ptr<int>(b.rdst);
+    int *roff = ar.ptr<int>(b.roff), *rpair = ar.ptr<int>(b.rpair);
+    double *rscale = ar.ptr<double>(b.rscale);
+    float *rdelta = ar.ptr<float>(b.rdelta);
+    // a destination's pairs have distinct offsets, and positions grow with
+    // the offset, so visiting its entries by offset gives them in position
+    // order (the reduce order)
+    std::vector<int> next(start.begin(), start.end() - 1), slot(343, -1);
+    int q = 0, r = 0;
+    for (int d = 0; d < nb; ++d) {
+        if (!t.has_local[d] || t.v_off[d + 1] == t.v_off[d]) continue;
+        rdst[q] = d;
+        roff[q] = r;
+        ++q;
+        for (int i = t.v_off[d]; i < t.v_off[d + 1]; ++i) slot[op[i]] = i;
+        const double hb = geom[d].w;
+        for (int o3 = 0; o3 < 343; ++o3) {
+            const int i = slot[o3];
+            if (i < 0) continue;
+            slot[o3] = -1;
+            const int k = next[o3]++;
+            for (int c = 0; c < nc; ++c) {
+                bcol[size_t(k) * nc + c] = t.v[i].box * nc + c;
+                ycol[size_t(k) * nc + c] = k * nc + c;
+            }
+            const int8_t *o = &t.v_rel[3 * size_t(i)];
+            rpair[r] = k;
+            rscale[r] = 1.0 / hb;
+            // Psi_B = Psi_A - (c_B - c_A).Phi,  c_A - c_B = o h
+            for (int k3 = 0; k3 < 3; ++k3) rdelta[3 * size_t(r) + k3] = float(-o[k3] * hb);
+            ++r;
+        }
+    }
+    roff[q] = r;
+    b.ntasks = ndst;
+    ybuf_floats = std::max(ybuf_floats, size_t(np) * nc * Mp);
     return b;
 }
 
@@ -489,6 +581,34 @@ stkfmm_status validate_points(stkfmm_ctx *c, const std::vector<double> &h, int64
             double u = (h[i] - c->origin[i % 3]) / c->box_len;
             if (!(u >= 0.0 && u < 1.0))
                 return fail(c, STKFMM_E_DOMAIN, std::string(what) + ": point outside [origin, origin+box_len)");
+        }
+    }
+    return STKFMM_OK;
+}
+
+// Host copies of point sets (device [n][3]) normalised to the unit box,
+// wrapped if periodic; optionally validated first.
+stkfmm_status copy_coords(stkfmm_ctx *c, const double *const src[3], const int64_t cnt[3], bool periodic,
+                          bool validate, std::vector<double> h[3], hipStream_t s) {
+    for (int k = 0; k < 3; ++k) {
+        h[k].resize(3 * cnt[k]);
+        if (cnt[k] > 0)
+            HIP_TRY(c, hipMemcpyAsync(h[k].data(), src[k], 3 * cnt[k] * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    const char *names[3] = {"sl_xyz", "dl_xyz", "trg_xyz"};
+    for (int k = 0; k < 3; ++k) {
+        if (validate) {
+            stkfmm_status st = validate_points(c, h[k], cnt[k], periodic, names[k]);
+            if (st != STKFMM_OK) return st;
+        }
+        for (int64_t i = 0; i < 3 * cnt[k]; ++i) {
+            double u = (h[k][i] - c->origin[i % 3]) / c->box_len;
+            if (periodic) {
+                u -= std::floor(u);
+                if (u >= 1.0) u = 0.0;
+            }
+            h[k][i] = u;
         }
     }
     return STKFMM_OK;
@@ -881,28 +1001,33 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(c, hipSetDevice(c->device));
     auto t0 = std::chrono::steady_clock::now();
-    // host copies of the coordinates (normalised to the unit box, wrapped if periodic)
-    std::vector<double> h[3];
     const double *src[3] = {sl_xyz, dl_xyz, trg_xyz};
     const int64_t cnt[3] = {n_sl, n_dl, n_trg};
-    for (int k = 0; k < 3; ++k) {
-        h[k].resize(3 * cnt[k]);
-        if (cnt[k] > 0)
-            HIP_TRY(c, hipMemcpyAsync(h[k].data(), src[k], 3 * cnt[k] * sizeof(double), hipMemcpyDeviceToHost, s));
-    }
-    HIP_TRY(c, hipStreamSynchronize(s));
     const char *names[3] = {"sl_xyz", "dl_xyz", "trg_xyz"};
-    for (int k = 0; k < 3; ++k) {
-        stkfmm_status st = validate_points(c, h[k], cnt[k], periodic, names[k]);
+    // host copies of the coordinates (normalised, wrapped if periodic) where
+    // the host needs them: the host tree builder and the learned mode's leaf
+    // features; else the points are only checked, on the GPU
+    std::vector<double> h[3];
+    const bool host_coords = learned || !c->tree_gpu;
+    if (host_coords) {
+        stkfmm_status st = copy_coords(c, src, cnt, periodic, true, h, s);
         if (st != STKFMM_OK) return st;
-        for (int64_t i = 0; i < 3 * cnt[k]; ++i) {
-            double u = (h[k][i] - c->origin[i % 3]) / c->box_len;
-            if (periodic) {
-                u -= std::floor(u);
-                if (u >= 1.0) u = 0.0;
-            }
-            h[k][i] = u;
+    } else {
+        for (int k = 0; k < 3; ++k) {
+            bool nonfinite = false, outside = false;
+            std::string e = check_points_gpu(src[k], cnt[k], c->origin, c->box_len, periodic, &nonfinite, &outside, stream);
+            if (!e.empty()) return fail(c, STKFMM_E_DEVICE, e);
+            if (nonfinite) return fail(c, STKFMM_E_ARG, std::string(names[k]) + ": non-finite coordinate");
+            if (outside)
+                return fail(c, STKFMM_E_DOMAIN, std::string(names[k]) + ": point outside [origin, origin+box_len)");
         }
+    }
+    // the caller's coordinates, kept for the accuracy check and fallback of
+    // learned plans and for leaf features asked for later
+    for (int k = 0; k < 3; ++k) {
+        HIP_TRY(c, c->coords[k].ensure(std::max<int64_t>(cnt[k], 1) * 3 * sizeof(double)));
+        if (cnt[k] > 0)
+            HIP_TRY(c, hipMemcpyAsync(c->coords[k].p, src[k], cnt[k] * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
     }
     Tree &t = c->tree;
     c->learned = learned;
@@ -921,12 +1046,6 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
         e = build(leaf_cap, periodic, nullptr);
         if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
     } else {
-        // keep the caller's coordinates for the accuracy check and the fallback
-        for (int k = 0; k < 3; ++k) {
-            HIP_TRY(c, c->coords[k].ensure(std::max<int64_t>(cnt[k], 1) * 3 * sizeof(double)));
-            if (cnt[k] > 0)
-                HIP_TRY(c, hipMemcpyAsync(c->coords[k].p, src[k], cnt[k] * 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
-        }
         // reference tree, per-leaf features, network on the GPU
         const int ref_cap = leaf_cap ? leaf_cap : kReferenceCap;
         e = build(ref_cap, false, nullptr);
@@ -978,7 +1097,8 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
             }
         }
     }
-    for (int k = 0; k < 3; ++k) c->hcoords[k] = h[k];
+    for (int k = 0; k < 3; ++k) c->hcoords[k].swap(h[k]);
+    c->hcoords_valid = host_coords;
     DeviceOps *ops = nullptr;
     // learned plans size the translation compression to the error budget
     // (rank 160 at p = 8 for tol 1e-5) unless the caller set m2l_tol
@@ -1000,7 +1120,8 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     const int nc = ki.ncomp, M = ops->M, Mp = ops->Mp;
 
     // ---------------------------------------------------------------- plan arrays
-    Arena ar;
+    Arena &ar = c->staging;
+    ar.clear();
     c->a_perm_sl = ar.add(t.perm_sl);
     c->a_perm_dl = ar.add(t.perm_dl);
     c->a_perm_trg = ar.add(t.perm_trg);
@@ -1220,25 +1341,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     c->lmin_dn = periodic ? 0 : 2;
     c->ybuf_floats = 0;
     // M2L: V-list pairs grouped by offset
-    {
-        std::vector<Pair> pairs;
-        for (int b = 0; b < nb; ++b) {
-            if (!t.has_local[b]) continue;
-            const double hb = geom[b].w;
-            for (int i = t.v_off[b]; i < t.v_off[b + 1]; ++i) {
-                Pair pr;
-                pr.src = t.v[i].box;
-                pr.dst = b;
-                int o[3] = {t.v_rel[3 * i], t.v_rel[3 * i + 1], t.v_rel[3 * i + 2]};
-                pr.op = offset_index(o[0], o[1], o[2]);
-                // Psi_B = Psi_A - (c_B - c_A).Phi,  c_A - c_B = o h
-                for (int k = 0; k < 3; ++k) pr.delta[k] = float(-o[k] * hb);
-                pr.scale = 1.0 / hb;
-                pairs.push_back(pr);
-            }
-        }
-        c->m2l = make_batch(ar, pairs, nc, 1, c->ybuf_floats, Mp);
-    }
+    c->m2l = make_v_batch(ar, t, geom, nc, c->ybuf_floats, Mp);
     // compression of every box's upward densities (compressed translations)
     c->n_cmp_tiles = 0;
     if (ops->kc > 0) {
@@ -1338,8 +1441,8 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
         pd.cidx = ar.add(dcx);
         pd.cscale = ar.add(ds);
     }
-    HIP_TRY(c, c->arena.ensure(ar.host.size()));
-    HIP_TRY(c, hipMemcpyAsync(c->arena.p, ar.host.data(), ar.host.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, c->arena.ensure(ar.used));
+    HIP_TRY(c, hipMemcpyAsync(c->arena.p, ar.host.data(), ar.used, hipMemcpyHostToDevice, s));
 
     // ---------------------------------------------------------------- work buffers
     HIP_TRY(c, c->sl_rec.ensure(size_t(std::max<int64_t>(n_sl, 1)) * ki.rec_sl * sizeof(float)));
@@ -1876,6 +1979,13 @@ stkfmm_status stkfmm_get_leaf_features(stkfmm_ctx *c, float *features, int32_t *
     const Tree &t = c->tree;
     *n_leaf = int64_t(t.leaves.size());
     if (features) {
+        if (!c->hcoords_valid) {
+            const double *src[3] = {c->coords[0].as<double>(), c->coords[1].as<double>(), c->coords[2].as<double>()};
+            const int64_t cnt[3] = {c->n_sl, c->n_dl, c->n_trg};
+            stkfmm_status st = copy_coords(c, src, cnt, c->bc == STKFMM_BC_PXYZ, false, c->hcoords, nullptr);
+            if (st != STKFMM_OK) return st;
+            c->hcoords_valid = true;
+        }
         std::vector<float> f;
         leaf_features(t, c->hcoords[0].data(), c->hcoords[1].data(), c->hcoords[2].data(), c->tol, f);
         std::memcpy(features, f.data(), f.size() * sizeof(float));

@@ -88,6 +88,11 @@ std::string build_tree_gpu(const double *const xyz[3], const int64_t n[3], const
                            int leaf_cap, bool periodic, Tree &t,
                            const std::unordered_map<uint64_t, int> *leaf_caps, void *stream);
 
+// Checks the caller's device coordinates [n][3] on the GPU: any not finite,
+// and (open boundary) any point outside [origin, origin + box_len)^3.
+std::string check_points_gpu(const double *xyz, int64_t n, const double origin[3], double box_len, bool periodic,
+                             bool *nonfinite, bool *outside, void *stream);
+
 // V-list anchor offsets, local-expansion flags and the P2P pair count of a
 // tree whose boxes and lists are set.
 void finish_tree(Tree &t);

@@ -527,115 +527,128 @@ struct UWArgs {
     ListView v;
     int nleaf;
     const int32_t *leaves;
-    int nb;
-    uint32_t *ucnt, *wcnt, *xcnt;      // [nb + 1] per box (x: pairs emitted by the leaf)
-    const uint32_t *uofs, *wofs, *xofs; // fill pass
-    uint64_t *uent, *went, *xkey;       // x: (A << 30) | (B << 5) | code of the reversed shift
+    uint32_t *total;          // count pass: U, W, X entries
+    uint32_t *cursor;         // fill pass: next free position of U, W, X
+    uint64_t *ukey, *wkey, *xkey;
     int *overflow;
 };
 
-// U(B): leaves adjacent to leaf B at any level; W(B): descendants of B's
-// colleagues not adjacent to B whose parent is; each W entry A of B with
-// sources in B and targets in A is an X pair (A gets B).
+// One thread per (leaf B, slot): slots 0..26 take B's colleague of that
+// index, slot 27 the coarser levels.
+//   U(B): leaves adjacent to B at any level -- coarser ones are the leaf
+//   colleagues of B's ancestors adjacent to B, the others are reached by
+//   descending from B's colleagues through adjacent boxes;
+//   W(B): descendants of B's colleagues not adjacent to B whose parent is;
+//   X: each W entry A of B with sources in B and targets in A gives A the
+//   entry B.
+// Entries are keyed (owner << 30) | (box << 5) | shift code and written at
+// positions claimed atomically; sorting the keys afterwards gives every list
+// in (box, shift) order, independent of the claim order.
+template <bool FILL>
 __global__ void uw_list_kernel(UWArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.nleaf) return;
-    const int b = a.leaves[i];
+    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= int64_t(a.nleaf) * 28) return;
+    const int slot = int(g % 28);
+    const int b = a.leaves[g / 28];
     const ListView &v = a.v;
     const GBox B = v.box[b];
-    const bool fill = a.uofs != nullptr;
     const bool keep = gb_ntrg(B) > 0, src_b = gb_nsrc(B) > 0;
-    uint64_t *uo = fill ? a.uent + a.uofs[b] : nullptr;
-    uint64_t *wo = fill ? a.went + a.wofs[b] : nullptr;
-    uint64_t *xo = fill ? a.xkey + a.xofs[b] : nullptr;
-    uint32_t nu = 0, nw = 0, nx = 0;
+    uint32_t n[3] = {0, 0, 0};
+    auto emit_u = [&](uint64_t e) {
+        if (FILL) a.ukey[atomicAdd(&a.cursor[0], 1u)] = (uint64_t(b) << 30) | e;
+        else ++n[0];
+    };
+    auto emit_w = [&](uint64_t e) {
+        if (FILL) a.wkey[atomicAdd(&a.cursor[1], 1u)] = (uint64_t(b) << 30) | e;
+        else ++n[1];
+    };
+    auto emit_x = [&](int A, const int s[3]) {
+        if (FILL)
+            a.xkey[atomicAdd(&a.cursor[2], 1u)] = (uint64_t(A) << 30) | (uint64_t(b) << 5) |
+                                                  uint64_t(9 * (1 - s[0]) + 3 * (1 - s[1]) + (1 - s[2]));
+        else ++n[2];
+    };
     uint64_t col[27];
     int s[3];
-    // coarser leaves: colleagues of each ancestor that are leaves adjacent to B
-    for (int p = B.parent; p >= 0; p = v.box[p].parent) {
-        const int nc = colleagues(v, p, col);
-        for (int k = 0; k < nc; ++k) {
-            const int A = ent_box(col[k]);
-            if (!v.box[A].leaf) continue;
-            ent_shift(col[k], s);
-            if (!adjacent(v, A, s, b)) continue;
-            if (keep && gb_nsrc(v.box[A]) > 0) {
-                if (fill) uo[nu] = col[k];
-                ++nu;
+    if (slot == 27) {
+        for (int p = B.parent; p >= 0; p = v.box[p].parent) {
+            const int nc = colleagues(v, p, col);
+            for (int k = 0; k < nc; ++k) {
+                const int A = ent_box(col[k]);
+                if (!v.box[A].leaf) continue;
+                ent_shift(col[k], s);
+                if (adjacent(v, A, s, b) && keep && gb_nsrc(v.box[A]) > 0) emit_u(col[k]);
             }
         }
-    }
-    // same level and finer: descend from B's colleagues
-    uint64_t stack[kStack];
-    const int nc = colleagues(v, b, col);
-    for (int k = 0; k < nc; ++k) {
-        const int C = ent_box(col[k]);
-        ent_shift(col[k], s);
-        const bool self = C == b && s[0] == 0 && s[1] == 0 && s[2] == 0;
-        if (self || v.box[C].leaf) {
-            if (keep && gb_nsrc(v.box[C]) > 0) {
-                if (fill) uo[nu] = col[k];
-                ++nu;
-            }
-            continue;
-        }
-        int top = 0;
-        stack[top++] = col[k];
-        while (top > 0) {
-            const uint64_t d = stack[--top];
-            const GBox &Dx = v.box[ent_box(d)];
-            for (int o = 0; o < 8; ++o) {
-                const int ch = Dx.child[o];
-                if (ch < 0) continue;
-                const uint64_t e = ent_of(ch, s[0], s[1], s[2]);
-                const GBox &Ch = v.box[ch];
-                if (adjacent(v, ch, s, b)) {
-                    if (Ch.leaf) {
-                        if (keep && gb_nsrc(Ch) > 0) {
-                            if (fill) uo[nu] = e;
-                            ++nu;
+    } else {
+        const int nc = colleagues(v, b, col);
+        if (slot < nc) {
+            const int C = ent_box(col[slot]);
+            ent_shift(col[slot], s);
+            const bool self = C == b && s[0] == 0 && s[1] == 0 && s[2] == 0;
+            if (self || v.box[C].leaf) {
+                if (keep && gb_nsrc(v.box[C]) > 0) emit_u(col[slot]);
+            } else {
+                uint64_t stack[kStack];
+                int top = 0;
+                stack[top++] = col[slot];
+                while (top > 0) {
+                    const GBox &Dx = v.box[ent_box(stack[--top])];
+                    for (int o = 0; o < 8; ++o) {
+                        const int ch = Dx.child[o];
+                        if (ch < 0) continue;
+                        const uint64_t e = ent_of(ch, s[0], s[1], s[2]);
+                        const GBox &Ch = v.box[ch];
+                        if (adjacent(v, ch, s, b)) {
+                            if (Ch.leaf) {
+                                if (keep && gb_nsrc(Ch) > 0) emit_u(e);
+                            } else if (top < kStack) {
+                                stack[top++] = e;
+                            } else {
+                                atomicExch(a.overflow, 1);
+                            }
+                        } else {
+                            if (keep && gb_nsrc(Ch) > 0) emit_w(e);
+                            if (src_b && gb_ntrg(Ch) > 0) emit_x(ch, s);
                         }
-                    } else if (top < kStack) {
-                        stack[top++] = e;
-                    } else {
-                        atomicExch(a.overflow, 1);
-                    }
-                } else {
-                    if (keep && gb_nsrc(Ch) > 0) {
-                        if (fill) wo[nw] = e;
-                        ++nw;
-                    }
-                    if (src_b && gb_ntrg(Ch) > 0) {
-                        if (fill)
-                            xo[nx] = (uint64_t(ch) << 30) | (uint64_t(b) << 5) |
-                                     uint64_t(9 * (1 - s[0]) + 3 * (1 - s[1]) + (1 - s[2]));
-                        ++nx;
                     }
                 }
             }
         }
     }
-    if (fill) {
-        sort_entries(uo, int(nu));
-        sort_entries(wo, int(nw));
-    } else {
-        a.ucnt[b] = nu;
-        a.wcnt[b] = nw;
-        a.xcnt[b] = nx;
+    if (!FILL)
+        for (int q = 0; q < 3; ++q)
+            if (n[q]) atomicAdd(&a.total[q], n[q]);
+}
+
+// list lengths per owning box from the sorted keys, and the entries (box, shift)
+__global__ void key_count_kernel(int64_t n, const uint64_t *key, uint32_t *cnt) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    atomicAdd(&cnt[key[i] >> 30], 1u);
+}
+
+__global__ void key_entries_kernel(int64_t n, const uint64_t *key, uint64_t *ent) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    ent[i] = key[i] & ((uint64_t(1) << 30) - 1);
+}
+
+// flags[0]: some coordinate is not finite; flags[1]: (open boundary) some
+// point lies outside [origin, origin + len)^3, with the host's expression
+__global__ void check_points_kernel(int64_t n3, const double *xyz, double ox, double oy, double oz, double len,
+                                    int periodic, uint32_t *flags) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n3) return;
+    const double v = xyz[i];
+    if (!isfinite(v)) {
+        atomicOr(&flags[0], 1u);
+        return;
     }
-}
-
-// X counts per target box from the sorted pairs, and the entries (B, shift)
-__global__ void x_count_kernel(int64_t n, const uint64_t *xkey, uint32_t *cnt) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    atomicAdd(&cnt[xkey[i] >> 30], 1u);
-}
-
-__global__ void x_entries_kernel(int64_t n, const uint64_t *xkey, uint64_t *xent) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    xent[i] = xkey[i] & ((uint64_t(1) << 30) - 1);
+    if (periodic) return;
+    const int k = int(i % 3);
+    const double u = (v - (k == 0 ? ox : k == 1 ? oy : oz)) / len;
+    if (!(u >= 0.0 && u < 1.0)) atomicOr(&flags[1], 1u);
 }
 
 __global__ void fill_u32(uint32_t *d, int64_t n, uint32_t v) {
@@ -644,6 +657,26 @@ __global__ void fill_u32(uint32_t *d, int64_t n, uint32_t v) {
 }
 
 }  // namespace
+
+std::string check_points_gpu(const double *xyz, int64_t n, const double origin[3], double box_len, bool periodic,
+                             bool *nonfinite, bool *outside, void *stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    *nonfinite = *outside = false;
+    if (n <= 0) return "";
+    DevArr flags;
+    TRY(flags.ensure(8));
+    hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, s, flags.as<uint32_t>(), int64_t(2), 0u);
+    TRY(hipGetLastError());
+    hipLaunchKernelGGL(check_points_kernel, dim3(nblk(3 * n, 256)), dim3(256), 0, s, 3 * n, xyz, origin[0], origin[1],
+                       origin[2], box_len, periodic ? 1 : 0, flags.as<uint32_t>());
+    TRY(hipGetLastError());
+    uint32_t h[2] = {0, 0};
+    TRY(hipMemcpyAsync(h, flags.p, 8, hipMemcpyDeviceToHost, s));
+    TRY(hipStreamSynchronize(s));
+    *nonfinite = h[0] != 0;
+    *outside = h[1] != 0;
+    return "";
+}
 
 std::string build_tree_gpu(const double *const xyz[3], const int64_t n[3], const double origin[3], double box_len,
                            int leaf_cap, bool periodic, Tree &t,
@@ -771,79 +804,78 @@ std::string build_tree_gpu(const double *const xyz[3], const int64_t n[3], const
     for (int l = 0; l <= kLevels; ++l) lv.level_start[l] = l <= depth + 1 ? level_start[l] : nb;
     lv.depth = depth;
     lv.periodic = periodic ? 1 : 0;
-    DevArr dleaves, ucnt, wcnt, xcnt, vcnt, uent, went, vent, xkey, xval, xcount, xent, oflow;
+    DevArr dleaves, vcnt, vent, cnt3, oflow;
+    DevArr lkey[3], lval[3], lent[3], lcnt[3];   // U, W, X: keys, sort payload, entries, counts by box
     TRY(dleaves.ensure(size_t(std::max(nleaf, 1)) * 4));
     TRY(hipMemcpyAsync(dleaves.p, leaves.data(), size_t(nleaf) * 4, hipMemcpyHostToDevice, s));
-    for (DevArr *d : {&ucnt, &wcnt, &xcnt, &vcnt, &xcount}) TRY(d->ensure(size_t(nb + 1) * 4));
+    TRY(vcnt.ensure(size_t(nb + 1) * 4));
     TRY(scr.ensure(scan_scratch(nb + 1) * 4));
+    TRY(cnt3.ensure(6 * 4));
     TRY(oflow.ensure(4));
+    hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, s, cnt3.as<uint32_t>(), int64_t(6), 0u);
+    TRY(hipGetLastError());
     hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, s, oflow.as<uint32_t>(), int64_t(1), 0u);
     TRY(hipGetLastError());
-    for (DevArr *d : {&ucnt, &wcnt, &xcnt}) {
-        hipLaunchKernelGGL(fill_u32, dim3(nblk(nb + 1, 256)), dim3(256), 0, s, d->as<uint32_t>(), int64_t(nb + 1), 0u);
-        TRY(hipGetLastError());
-    }
-    // count pass
+    // count passes
     VArgs va{lv, nb, vcnt.as<uint32_t>(), nullptr, nullptr};
     hipLaunchKernelGGL(v_list_kernel, dim3(nblk(nb + 1, 128)), dim3(128), 0, s, va);
     TRY(hipGetLastError());
-    UWArgs ua{lv, nleaf, dleaves.as<int32_t>(), nb, ucnt.as<uint32_t>(), wcnt.as<uint32_t>(), xcnt.as<uint32_t>(),
-              nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, oflow.as<int>()};
-    if (nleaf > 0) {
-        hipLaunchKernelGGL(uw_list_kernel, dim3(nblk(nleaf, 64)), dim3(64), 0, s, ua);
-        TRY(hipGetLastError());
-    }
-    uint32_t tot[4] = {0, 0, 0, 0};
-    DevArr *cs[4] = {&ucnt, &vcnt, &wcnt, &xcnt};
-    for (int q = 0; q < 4; ++q) {
-        TRY(scan_exclusive(cs[q]->as<uint32_t>(), nb + 1, scr.as<uint32_t>(), s));
-        TRY(hipMemcpyAsync(&tot[q], cs[q]->as<uint32_t>() + nb, 4, hipMemcpyDeviceToHost, s));
-    }
+    UWArgs ua{lv, nleaf, dleaves.as<int32_t>(), cnt3.as<uint32_t>(), cnt3.as<uint32_t>() + 3, nullptr, nullptr,
+              nullptr, oflow.as<int>()};
+    const int64_t nthr = int64_t(nleaf) * 28;
+    hipLaunchKernelGGL(uw_list_kernel<false>, dim3(nblk(nthr, 64)), dim3(64), 0, s, ua);
+    TRY(hipGetLastError());
+    TRY(scan_exclusive(vcnt.as<uint32_t>(), nb + 1, scr.as<uint32_t>(), s));
+    uint32_t tot[4] = {0, 0, 0, 0}, uwx[3] = {0, 0, 0};   // tot: U, V, W, X
+    TRY(hipMemcpyAsync(&tot[1], vcnt.as<uint32_t>() + nb, 4, hipMemcpyDeviceToHost, s));
+    TRY(hipMemcpyAsync(uwx, cnt3.p, 12, hipMemcpyDeviceToHost, s));
     int of = 0;
     TRY(hipMemcpyAsync(&of, oflow.p, 4, hipMemcpyDeviceToHost, s));
     TRY(hipStreamSynchronize(s));
     if (of) return "GPU tree build: descent stack overflow";
-    TRY(uent.ensure(size_t(std::max<uint32_t>(tot[0], 1)) * 8));
+    tot[0] = uwx[0];
+    tot[2] = uwx[1];
+    tot[3] = uwx[2];
     TRY(vent.ensure(size_t(std::max<uint32_t>(tot[1], 1)) * 8));
-    TRY(went.ensure(size_t(std::max<uint32_t>(tot[2], 1)) * 8));
-    TRY(xkey.ensure(size_t(std::max<uint32_t>(tot[3], 1)) * 8));
-    TRY(xval.ensure(size_t(std::max<uint32_t>(tot[3], 1)) * 4));
-    TRY(xent.ensure(size_t(std::max<uint32_t>(tot[3], 1)) * 8));
-    // fill pass
+    for (int q = 0; q < 3; ++q) {
+        const size_t m = std::max<uint32_t>(uwx[q], 1);
+        TRY(lkey[q].ensure(m * 8));
+        TRY(lval[q].ensure(m * 4));
+        TRY(lent[q].ensure(m * 8));
+        TRY(lcnt[q].ensure(size_t(nb + 1) * 4));
+    }
+    // fill passes
     va.ofs = vcnt.as<uint32_t>();
     va.ent = vent.as<uint64_t>();
     hipLaunchKernelGGL(v_list_kernel, dim3(nblk(nb + 1, 128)), dim3(128), 0, s, va);
     TRY(hipGetLastError());
-    ua.uofs = ucnt.as<uint32_t>();
-    ua.wofs = wcnt.as<uint32_t>();
-    ua.xofs = xcnt.as<uint32_t>();
-    ua.uent = uent.as<uint64_t>();
-    ua.went = went.as<uint64_t>();
-    ua.xkey = xkey.as<uint64_t>();
-    if (nleaf > 0) {
-        hipLaunchKernelGGL(uw_list_kernel, dim3(nblk(nleaf, 64)), dim3(64), 0, s, ua);
-        TRY(hipGetLastError());
-    }
-    // X: pairs sorted by (target box, source box, shift), counted per target box
-    hipLaunchKernelGGL(fill_u32, dim3(nblk(nb + 1, 256)), dim3(256), 0, s, xcount.as<uint32_t>(), int64_t(nb + 1), 0u);
+    ua.ukey = lkey[0].as<uint64_t>();
+    ua.wkey = lkey[1].as<uint64_t>();
+    ua.xkey = lkey[2].as<uint64_t>();
+    hipLaunchKernelGGL(uw_list_kernel<true>, dim3(nblk(nthr, 64)), dim3(64), 0, s, ua);
     TRY(hipGetLastError());
-    if (tot[3] > 0) {
-        hipLaunchKernelGGL(fill_u32, dim3(nblk(tot[3], 256)), dim3(256), 0, s, xval.as<uint32_t>(), int64_t(tot[3]), 0u);
+    // U, W by (leaf, box, shift); X by (target box, source leaf, shift); then
+    // the list lengths by owning box
+    for (int q = 0; q < 3; ++q) {
+        hipLaunchKernelGGL(fill_u32, dim3(nblk(nb + 1, 256)), dim3(256), 0, s, lcnt[q].as<uint32_t>(), int64_t(nb + 1), 0u);
         TRY(hipGetLastError());
-        TRY(radix_sort(xkey.as<uint64_t>(), xval.as<int32_t>(), tot[3], 55, sb, s));
-        hipLaunchKernelGGL(x_count_kernel, dim3(nblk(tot[3], 256)), dim3(256), 0, s, int64_t(tot[3]),
-                           xkey.as<uint64_t>(), xcount.as<uint32_t>());
+        if (uwx[q] == 0) continue;
+        hipLaunchKernelGGL(fill_u32, dim3(nblk(uwx[q], 256)), dim3(256), 0, s, lval[q].as<uint32_t>(), int64_t(uwx[q]), 0u);
         TRY(hipGetLastError());
-        hipLaunchKernelGGL(x_entries_kernel, dim3(nblk(tot[3], 256)), dim3(256), 0, s, int64_t(tot[3]),
-                           xkey.as<uint64_t>(), xent.as<uint64_t>());
+        TRY(radix_sort(lkey[q].as<uint64_t>(), lval[q].as<int32_t>(), uwx[q], 55, sb, s));
+        hipLaunchKernelGGL(key_count_kernel, dim3(nblk(uwx[q], 256)), dim3(256), 0, s, int64_t(uwx[q]),
+                           lkey[q].as<uint64_t>(), lcnt[q].as<uint32_t>());
+        TRY(hipGetLastError());
+        hipLaunchKernelGGL(key_entries_kernel, dim3(nblk(uwx[q], 256)), dim3(256), 0, s, int64_t(uwx[q]),
+                           lkey[q].as<uint64_t>(), lent[q].as<uint64_t>());
         TRY(hipGetLastError());
     }
-    TRY(scan_exclusive(xcount.as<uint32_t>(), nb + 1, scr.as<uint32_t>(), s));
+    for (int q = 0; q < 3; ++q) TRY(scan_exclusive(lcnt[q].as<uint32_t>(), nb + 1, scr.as<uint32_t>(), s));
     // ---------------------------------------------------------------- to the host
     std::vector<uint32_t> off[4];
     std::vector<uint64_t> ent[4];
-    DevArr *os[4] = {&ucnt, &vcnt, &wcnt, &xcount};
-    DevArr *es[4] = {&uent, &vent, &went, &xent};
+    DevArr *os[4] = {&lcnt[0], &vcnt, &lcnt[1], &lcnt[2]};
+    DevArr *es[4] = {&lent[0], &vent, &lent[1], &lent[2]};
     for (int q = 0; q < 4; ++q) {
         off[q].resize(nb + 1);
         ent[q].resize(tot[q]);

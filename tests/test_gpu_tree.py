@@ -194,3 +194,37 @@ def test_results_identical_on_either_tree():
         f.set_option("tree", how)
         outs[how] = f.evaluate("RPY", sl_xyz=x, sl_val=fb, trg_xyz=x, p=6, leaf_cap=400).clone()
     assert torch.equal(outs["gpu"], outs["host"])
+
+
+@pytest.mark.parametrize("how", ["gpu", "host"])
+def test_point_checks(how):
+    from paper_2010_15155_amd import StkfmmError
+    rng = np.random.default_rng(3)
+    x = rng.random((5000, 3))
+    f = FMM()
+    f.set_option("tree", how)
+    bad = x.copy()
+    bad[1234, 1] = np.nan
+    with pytest.raises(StkfmmError) as ei:
+        f.set_points("Stokeslet", _cuda(x), None, _cuda(bad), p=6, leaf_cap=100)
+    assert ei.value.status == "E_ARG" and "trg_xyz" in str(ei.value)
+    out = x.copy()
+    out[4321, 2] = 1.0                           # the upper face is outside the half-open box
+    with pytest.raises(StkfmmError) as ei:
+        f.set_points("Stokeslet", _cuda(out), None, _cuda(x), p=6, leaf_cap=100)
+    assert ei.value.status == "E_DOMAIN" and "sl_xyz" in str(ei.value)
+    # periodic plans wrap instead
+    f.set_points("LapPGrad", _cuda(out), None, _cuda(x), p=6, leaf_cap=100, bc="PXYZ")
+
+
+def test_leaf_features_after_a_gpu_tree_plan():
+    d = W.mixture(905, (200_000, 200_000))
+    x = _cuda(d["xyz"])
+    feats = {}
+    for how in ("gpu", "host"):
+        f = FMM()
+        f.set_option("tree", how)
+        f.set_points("Stokeslet", x, None, x, p=8, leaf_cap=2000)
+        feats[how] = f.leaf_features()
+    assert np.array_equal(feats["gpu"][0], feats["host"][0])
+    assert np.array_equal(feats["gpu"][1], feats["host"][1])
