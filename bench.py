@@ -161,6 +161,38 @@ def measure(fmm, torch, W, kernel, x, val, p, cap, args, precision="fp32", bc="o
     return r
 
 
+def periodic_stokeslet(FMM, torch, n, args, p=8, cap=500):
+    """Triply periodic Stokeslet on n uniform points (zero net force): time per
+    pass, and as accuracy the translation test, the relative difference
+    between the pass and the pass on all points moved together (a sampled
+    Ewald reference at this size is beyond the CPU oracle's budget)."""
+    rng = np.random.default_rng(501)
+    x = rng.random((n, 3))
+    f = rng.standard_normal((n, 3))
+    f -= f.mean(axis=0)
+    fmm = FMM()
+    xd, fd = torch.from_numpy(x).cuda(), torch.from_numpy(f).cuda()
+    fmm.set_points("Stokeslet", xd, None, xd, p=p, leaf_cap=cap, bc="PXYZ")
+    for _ in range(args.warmup):
+        fmm.run(fd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = fmm.run(fd)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    out = out.clone()
+    stages = fmm.timings()["stages_ms"]
+    xs = torch.from_numpy(np.mod(x + np.array([0.31, 0.57, 0.89]), 1.0)).cuda()
+    fmm.set_points("Stokeslet", xs, None, xs, p=p, leaf_cap=cap, bc="PXYZ")
+    out2 = fmm.run(fd)
+    diff = float(torch.linalg.norm(out2 - out) / torch.linalg.norm(out))
+    fmm.close()
+    return {"ms_per_step": wall * 1e3, "targets_per_s": n / wall, "p": p, "leaf_cap": cap,
+            "translation_rel_diff": diff, "stages_ms": stages,
+            "workload": "%d uniform points in the unit cube, PXYZ, sum f = 0" % n}
+
+
 def tree_build(FMM, x):
     """Plan time (stkfmm_set_points: octree, lists and plan arrays; operators
     cached) with the octree and lists built by the GPU kernels or on the host."""
@@ -245,6 +277,7 @@ def main():
         line["widened"] = {
             "stokes_reg_vel_p8": measure(fmm, torch, W, "StokesRegVel", x, fe, 8, 1000, args),
             "rpy_wall_p10": measure(fmm, torch, W, "RPY", x, fb, 10, 1000, args, bc="wall"),
+            "stokeslet_pxyz_p8": periodic_stokeslet(FMM, torch, n, args),
         }
         line["plan_ms"] = tree_build(FMM, x)
     fmm.close()

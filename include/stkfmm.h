@@ -43,7 +43,7 @@ typedef struct stkfmm_ctx stkfmm_ctx;
 typedef enum {
     STKFMM_OK = 0,
     STKFMM_E_ARG = 1,          /* bad argument: NULL, negative size, bad p / leaf_cap, NaN */
-    STKFMM_E_DOMAIN = 2,       /* point outside the box (open BC) or non-zero net charge (periodic) */
+    STKFMM_E_DOMAIN = 2,       /* point outside the box (open BC) or non-zero net charge / force (periodic) */
     STKFMM_E_UNSUPPORTED = 3,  /* kernel / boundary combination not implemented */
     STKFMM_E_NOMEM = 4,        /* device or host allocation failed */
     STKFMM_E_DEVICE = 5,       /* HIP runtime error */
@@ -91,7 +91,10 @@ typedef enum {
 
 /* Boundary conditions (Sec. III and its appendix on periodicity).  PXYZ is
  * implemented for LAP_PGRAD, LAP_PGRADGRAD and LAP_QPGRADGRAD (zero net
- * charge; Ewald's convention: no k = 0 term, no surface term).  WALL (Sec. III, the no-slip wall section,
+ * charge; Ewald's convention: no k = 0 term, no surface term) and for
+ * STOKESLET (zero net force; the Fourier series of the periodic Stokes
+ * equations without its k = 0 term, i.e. zero mean velocity, summed with
+ * Hasimoto's Ewald split).  WALL (Sec. III, the no-slip wall section,
  * tab:rpywall) is an open domain bounded below by a no-slip wall on the
  * plane z = origin[2], for STOKESLET and RPY only, fixed p and leaf_cap only:
  * the flow is assembled from three (Stokeslet) or four (RPY) free-space
@@ -138,6 +141,8 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *ctx, stkfmm_kernel kernel, stkfmm_bc
  * (overwritten, user order).  Periodic LAP_PGRAD requires sum q = 0
  * (relative to sum |q|, 1e-9), else E_DOMAIN; its potential is defined up to
  * an additive constant (the Ewald convention with the k = 0 term dropped).
+ * Periodic STOKESLET requires each component of sum f to vanish (relative to
+ * sum |f_k|, 1e-9), else E_DOMAIN.
  * Errors: E_STATE (no points set), E_ARG, E_DOMAIN, E_NOMEM, E_DEVICE. */
 stkfmm_status stkfmm_run(stkfmm_ctx *ctx, const double *sl_val, const double *dl_val,
                          double *trg_val, void *hip_stream);

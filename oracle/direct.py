@@ -41,6 +41,8 @@ def lib():
         _lib.oracle_ewald_eval.argtypes = [_i64, _dp, _dp, _dp, _dp, _i64, _dp, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                            _dp, _dp, _dp, ctypes.c_int]
+        _lib.oracle_stokes_ewald_real.argtypes = [_i64, _dp, _dp, _i64, _dp, ctypes.c_double, ctypes.c_double,
+                                                  ctypes.c_double, _dp]
     return _lib
 
 

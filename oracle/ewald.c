@@ -228,3 +228,46 @@ void oracle_ewald_eval(int64_t ns, const double *ys, const double *q, const doub
         for (int i = 0; i < kt; ++i) out[kt*t+i] = acc[i];
     }
 }
+
+/*
+ * Real-space part of the triply periodic Stokeslet (Hasimoto split; the
+ * reciprocal part is summed in stokes_periodic.py, which states the
+ * definition): for each target, every image of every source within rc,
+ *   8 pi G_R(r) = (erfc(xi r)/r - c e) I + (erfc(xi r)/r + c e) r r^T/r^2,
+ *   c = 2 xi/sqrt(pi), e = exp(-xi^2 r^2),
+ * and for a target on a source the self term -xi/(2 pi^{3/2}) f.
+ * out [nt][3] is overwritten.
+ */
+void oracle_stokes_ewald_real(int64_t ns, const double *ys, const double *f, int64_t nt, const double *xs,
+                              double L, double xi, double rc, double *out)
+{
+    const double c = 2.0 * xi / sqrt(PI);
+    const int nimg = (int)floor(rc / L + 0.5);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        double u[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < ns; ++j) {
+            double d[3];
+            int same = 1;
+            for (int k = 0; k < 3; ++k) {
+                d[k] = xs[3 * t + k] - ys[3 * j + k];
+                same = same && d[k] == 0.0;
+                d[k] -= L * nearbyint(d[k] / L);
+            }
+            if (same)
+                for (int k = 0; k < 3; ++k) u[k] -= xi / (2.0 * PI * sqrt(PI)) * 8.0 * PI * f[3 * j + k];
+            for (int a = -nimg; a <= nimg; ++a)
+                for (int b = -nimg; b <= nimg; ++b)
+                    for (int e3 = -nimg; e3 <= nimg; ++e3) {
+                        const double r[3] = {d[0] - L * a, d[1] - L * b, d[2] - L * e3};
+                        const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                        if (rr >= rc * rc || rr == 0.0) continue;
+                        const double rho = sqrt(rr), e = exp(-xi * xi * rr), ec = erfc(xi * rho) / rho;
+                        const double A = ec - c * e, B = (ec + c * e) / rr;
+                        const double rf = r[0] * f[3 * j] + r[1] * f[3 * j + 1] + r[2] * f[3 * j + 2];
+                        for (int k = 0; k < 3; ++k) u[k] += A * f[3 * j + k] + B * rf * r[k];
+                    }
+        }
+        for (int k = 0; k < 3; ++k) out[3 * t + k] = u[k] / (8.0 * PI);
+    }
+}

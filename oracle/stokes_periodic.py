@@ -1,0 +1,70 @@
+"""Triply periodic Stokeslet by Ewald summation (oracle) -- TEST INFRASTRUCTURE ONLY.
+
+The periodic boundary condition of Sec. III (and its appendix on
+periodicity) for the Stokeslet of Sec. II.B (viscosity 1):
+
+    u(x) = sum_j sum_n G(x - y_j - n L) f_j,   G(r) = (I/r + r r^T/r^3) / (8 pi).
+
+The lattice sum does not converge absolutely; the oracle fixes the usual
+definition through the Fourier series of the periodic Stokes equations,
+u_hat(k) = (I - k k^T/k^2) f_hat(k) / k^2: the net force must vanish and
+the k = 0 term is dropped (the mean velocity over the cell is zero).
+
+Ewald split with the Hasimoto factor phi(k) = (1 + k^2/(4 xi^2)) e^{-k^2/(4 xi^2)}:
+  reciprocal  (1/V) sum_{k != 0} phi(k)/k^2 (I - k k^T/k^2) Re[S(k) e^{i k.x}],
+              S(k) = sum_j f_j e^{-i k.y_j},  k = 2 pi m / L;
+  real        the remaining part, G = (I lap - grad grad) B / (8 pi) with
+              B'(r) = erfc(xi r) (the biharmonic generator of the split-off
+              part, whose transform is -8 pi (1 - phi)/k^4):
+              8 pi G_R(r) = (erfc(xi r)/r - c e) I + (erfc(xi r)/r + c e) r r^T/r^2,
+              c = 2 xi / sqrt(pi), e = exp(-xi^2 r^2);
+  self        a target on source j drops the smooth part of its own term,
+              lim_{r->0} (G - G_R) f_j = 4 xi/(8 pi sqrt(pi)) f_j:
+              u -= xi / (2 pi^{3/2}) f_j.
+The real part's integral vanishes (1 - phi = O(k^4)), so no constant term
+arises.  FP64: the real part by plain loops in ewald.c, the reciprocal part
+with NumPy.
+"""
+import numpy as np
+
+from .direct import _p, lib
+
+PI = np.pi
+
+
+def parameters(L, xi=None, tol=1e-15):
+    """(xi, real cutoff, reciprocal cutoff index) for relative truncation tol."""
+    if xi is None:
+        xi = 4.0 / L
+    s = np.sqrt(-np.log(tol)) + 0.5
+    rc = s / xi
+    nmax = int(np.ceil(2.0 * xi * s * L / (2.0 * PI)))
+    return xi, rc, nmax
+
+
+def stokeslet_periodic(src, f, trg, L=1.0, xi=None, tol=1e-15):
+    """Periodic Stokeslet velocity [m, 3] at trg [m, 3] of forces f [n, 3] at src [n, 3]."""
+    y = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3)
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1, 3)
+    x = np.ascontiguousarray(trg, dtype=np.float64).reshape(-1, 3)
+    xi, rc, nmax = parameters(L, xi, tol)
+    u = np.zeros((len(x), 3))
+    if len(y) == 0 or len(x) == 0:
+        return u
+    # real space and self terms (ewald.c, plain loops over targets, sources
+    # and the images within rc)
+    lib().oracle_stokes_ewald_real(len(y), _p(y), _p(f), len(x), _p(x), float(L), float(xi), float(rc), _p(u))
+    # reciprocal space: every k != 0 in the cube [-nmax, nmax]^3
+    m = np.arange(-nmax, nmax + 1)
+    K = np.stack(np.meshgrid(m, m, m, indexing="ij"), axis=-1).reshape(-1, 3).astype(np.float64)
+    K = K[np.any(K != 0, axis=1)] * (2.0 * PI / L)
+    k2 = np.sum(K * K, axis=1)
+    g = (1.0 + k2 / (4.0 * xi * xi)) * np.exp(-k2 / (4.0 * xi * xi)) / k2
+    S = np.zeros((len(K), 3), dtype=np.complex128)        # S(k), summed over source blocks
+    for j0 in range(0, len(y), 1024):
+        S += np.exp(-1j * (K @ y[j0:j0 + 1024].T)) @ f[j0:j0 + 1024]
+    PS = S - K * (np.sum(K * S, axis=1) / k2)[:, None]    # (I - k k^T/k^2) S
+    W = g[:, None] * PS / L ** 3
+    for i0 in range(0, len(x), 1024):
+        u[i0:i0 + 1024] += np.real(np.exp(1j * (x[i0:i0 + 1024] @ K.T)) @ W)
+    return u

@@ -10,7 +10,7 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libstkfmm.so")
 ARCH = os.environ.get("STKFMM_ARCH", "gfx950")
 
-HIP_SOURCES = ["kernels.hip", "api.hip", "mlp.hip", "wall.hip", "tree_gpu.hip"]
+HIP_SOURCES = ["kernels.hip", "api.hip", "mlp.hip", "wall.hip", "tree_gpu.hip", "periodic.hip"]
 CPP_SOURCES = ["tree.cpp", "operators.cpp", "learn.cpp"]
 HIP_FLAGS = ["-O3", "--offload-arch=" + ARCH, "-std=c++17", "-fPIC", "-Wall",
              # no packed FP32 instructions (v_pk_*_f32) anywhere

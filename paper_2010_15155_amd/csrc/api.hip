@@ -105,6 +105,16 @@ struct DeviceOps {
     DevMem basis_t, m2l_c;      // U_k^T [kc][Mp], cores [343][kc][kc]
 };
 
+// Far images of the triply periodic Stokeslet: Q [3M][3M], the upward check
+// points X and the downward equivalent points Z [M][3] of the root, at a
+// fixed order (p = 10, whatever the tree's order) so that they stay well
+// below the tree's error.
+constexpr int kStokesFarOrder = 10;
+struct StokesFarOps {
+    int M = 0;
+    DevMem Q, X, Z;
+};
+
 // A batch of translations that share the grouped GEMM and one reduce launch.
 struct Batch {
     int ntiles = 0, ntasks = 0;
@@ -174,6 +184,8 @@ struct stkfmm_ctx {
     Tree tree;
     DeviceOps *ops = nullptr;
     Arena staging;              // host image of `arena`, reused between plans
+    StokesFarOps *stk = nullptr; // periodic Stokeslet: far-image operator
+    DevMem stk_F, stk_part;     // root check flow and far-image forces, partial sums
     DevMem arena, sl_rec, dl_rec, trg_rec, up_dens, dn_dens, up_chk, dn_chk, Ybuf, near_part, far_part,
         s2c_part, partial, direct_work, sl_stage, dl_stage, up_cmp;
     size_t a_perm_sl = 0, a_perm_dl = 0, a_perm_trg = 0, a_geom = 0, a_box_sl = 0, a_box_dl = 0, a_chunks = 0,
@@ -340,6 +352,35 @@ stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, double m2l_tol, Devic
     if (periodic) HIP_TRY(c, up(d->tm2l, h.t_m2l.data(), h.t_m2l.size() * sizeof(double)));
     *out = d.get();
     (*g_ops)[key] = std::move(d);
+    return STKFMM_OK;
+}
+
+// The triply periodic Stokeslet's far-image operator, one per (device,
+// svd_tol), built on first use and kept like the operator sets.
+std::map<std::tuple<int, double>, std::unique_ptr<StokesFarOps>> *g_stk =
+    new std::map<std::tuple<int, double>, std::unique_ptr<StokesFarOps>>();
+
+stkfmm_status get_periodic_stokes(stkfmm_ctx *c, StokesFarOps **out) {
+    std::lock_guard<std::mutex> lock(g_ops_mutex);
+    const auto key = std::make_tuple(c->device, c->svd_tol);
+    auto it = g_stk->find(key);
+    if (it != g_stk->end()) {
+        *out = it->second.get();
+        return STKFMM_OK;
+    }
+    std::vector<double> Q, X, Z;
+    std::string e = build_periodic_stokes(kStokesFarOrder, c->svd_tol, Q, X, Z);
+    if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
+    auto d = std::make_unique<StokesFarOps>();
+    d->M = int(X.size() / 3);
+    HIP_TRY(c, d->Q.ensure(Q.size() * sizeof(double)));
+    HIP_TRY(c, hipMemcpy(d->Q.p, Q.data(), Q.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(c, d->X.ensure(X.size() * sizeof(double)));
+    HIP_TRY(c, hipMemcpy(d->X.p, X.data(), X.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(c, d->Z.ensure(Z.size() * sizeof(double)));
+    HIP_TRY(c, hipMemcpy(d->Z.p, Z.data(), Z.size() * sizeof(double), hipMemcpyHostToDevice));
+    *out = d.get();
+    (*g_stk)[key] = std::move(d);
     return STKFMM_OK;
 }
 
@@ -995,8 +1036,9 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     if (bc != STKFMM_BC_OPEN && bc != STKFMM_BC_PXYZ)
         return fail(c, STKFMM_E_UNSUPPORTED, "only open, triply periodic and wall boundaries are implemented");
     if (bc == STKFMM_BC_PXYZ && kernel != STKFMM_LAP_PGRAD && kernel != STKFMM_LAP_PGRADGRAD &&
-        kernel != STKFMM_LAP_QPGRADGRAD)
-        return fail(c, STKFMM_E_UNSUPPORTED, "triply periodic boundary is implemented for the Laplace kernels");
+        kernel != STKFMM_LAP_QPGRADGRAD && kernel != STKFMM_STOKESLET)
+        return fail(c, STKFMM_E_UNSUPPORTED,
+                    "triply periodic boundary is implemented for the Laplace kernels and STOKESLET");
     const bool periodic = bc == STKFMM_BC_PXYZ;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(c, hipSetDevice(c->device));
@@ -1105,6 +1147,14 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     const double m2l_tol = learned && !c->m2l_tol_set && c->m2l_tol > 0 ? c->tol / 50.0 : c->m2l_tol;
     stkfmm_status st = get_ops(c, p, periodic, m2l_tol, &ops);
     if (st != STKFMM_OK) return st;
+    c->stk = nullptr;
+    if (periodic && kernel == STKFMM_STOKESLET) {
+        st = get_periodic_stokes(c, &c->stk);
+        if (st != STKFMM_OK) return st;
+        const int Mf = c->stk->M;
+        HIP_TRY(c, c->stk_F.ensure(size_t(6) * Mf * sizeof(double)));
+        HIP_TRY(c, c->stk_part.ensure(size_t(std::max(stokes_root_chunks(n_sl), 1)) * 3 * Mf * sizeof(double)));
+    }
     c->ops = ops;
     c->kernel = kernel;
     c->bc = bc;
@@ -1649,7 +1699,22 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
     const int nc = ki.ncomp;
     const bool periodic = c->bc == STKFMM_BC_PXYZ;
     if (c->n_trg == 0) return STKFMM_OK;
-    if (periodic && c->n_sl > 0 && c->kernel != kLapQPGradGrad) {
+    if (periodic && c->n_sl > 0 && c->kernel == kStokeslet) {
+        // zero net force (the Ewald convention drops the k = 0 mode)
+        const int nbk = 256;
+        HIP_TRY(c, launch_force_partials(c->n_sl, sl_val, nbk, c->partial.as<double>(), s));
+        std::vector<double> hp(4 * nbk);
+        HIP_TRY(c, hipMemcpyAsync(hp.data(), c->partial.p, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        double f[3] = {0, 0, 0}, fa = 0;
+        for (int i = 0; i < nbk; ++i) {
+            for (int k = 0; k < 3; ++k) f[k] += hp[4 * i + k];
+            fa += hp[4 * i + 3];
+        }
+        for (int k = 0; k < 3; ++k)
+            if (std::fabs(f[k]) > 1e-9 * std::max(1.0, fa))
+                return fail(c, STKFMM_E_DOMAIN, "periodic Stokes needs zero net force");
+    } else if (periodic && c->n_sl > 0 && c->kernel != kLapQPGradGrad) {
         // zero net charge (tin-foil Ewald convention needs a neutral cell;
         // quadrupoles carry none)
         const int nbk = 256;
@@ -1765,7 +1830,11 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         if (st != STKFMM_OK) return st;
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 4 M2L
         HIP_TRY(c, s2c(c->s2l, kAlphaIn, dnchk, 1));
-        if (periodic) HIP_TRY(c, launch_periodic(o.tm2l.as<double>(), updens, dnchk, o.M, o.Mp, nc, 0, s));
+        if (periodic && nc == 1) HIP_TRY(c, launch_periodic(o.tm2l.as<double>(), updens, dnchk, o.M, o.Mp, nc, 0, s));
+        if (periodic && c->kernel == kStokeslet)
+            HIP_TRY(c, launch_stokes_far_forces(c->n_sl, c->sl_rec.as<float>(), ki.rec_sl, c->stk->X.as<double>(),
+                                                c->stk->Q.as<double>(), c->stk->M, c->stk_part.as<double>(),
+                                                c->stk_F.as<double>(), c->stk_F.as<double>() + 3 * c->stk->M, s));
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 5 S2L + periodic
         for (int l = c->lmin_dn; l <= t.depth; ++l) {
             const L2LLevel &ll = c->l2l[l];
@@ -1812,6 +1881,11 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         a.map = combine_map(c->kernel, c->box_len);
         a.out = trg_val;
         HIP_TRY(c, launch_combine(c->nchunks, a, s));
+        if (periodic && c->kernel == kStokeslet)
+            HIP_TRY(c, launch_stokes_far_targets(c->n_trg, c->trg_rec.as<float>(), at<int32_t>(c, c->a_perm_trg),
+                                                 c->stk_F.as<double>() + 3 * c->stk->M, c->stk->Z.as<double>(),
+                                                 c->stk->M, 1.0 / c->box_len,
+                                                 trg_val, s));
     }
     HIP_TRY(c, hipEventRecord(ev[ne++], s));                  // end
     HIP_TRY(c, hipStreamSynchronize(s));

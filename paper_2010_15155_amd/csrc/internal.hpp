@@ -133,6 +133,15 @@ struct Operators {
 // them dense.
 std::string build_operators(int p, double svd_tol, bool periodic, Operators &ops, double m2l_tol = 0.0);
 
+// Far images of the triply periodic Stokeslet at the root (unit box centred
+// at the origin): Q [3M][3M] maps the root's flow at its M upward check
+// points X [M][3] (the Stokeslet sum of the sources inside the root) to
+// Stokeslet forces on the M downward equivalent points Z [M][3] whose flow
+// inside the root is that of all images n with max|n_k| >= 2 (Hasimoto's
+// Ewald sum, zero net force).
+std::string build_periodic_stokes(int p, double svd_tol, std::vector<double> &Q, std::vector<double> &X,
+                                  std::vector<double> &Z);
+
 // Index of a relative offset o in [-3,3]^3.
 inline int offset_index(int ox, int oy, int oz) { return ((oz + 3) * 7 + (oy + 3)) * 7 + (ox + 3); }
 

@@ -25,6 +25,9 @@
 //                 above m2l_tol times the largest, rounded up to 32.
 //   T_M2L         periodic images beyond the 3x3x3 near block, by Ewald
 //                 summation (triply periodic, Sec. III and its appendix).
+//   periodic Stokes  the far images of the root for the triply periodic
+//                 Stokeslet (Hasimoto's Ewald split), applied through
+//                 Stokeslet fits at the root: see build_periodic_stokes.
 //
 // The SVD is a one-sided Jacobi (Hestenes) iteration with a round-robin
 // pair schedule whose rounds run on a pool of host threads.
@@ -199,7 +202,217 @@ struct FarImages {
     }
 };
 
+// Far images of the triply periodic Stokeslet G(r) = (I/r + r r^T/r^3)/(8 pi)
+// of a unit force at separation r: all images n with max|n_k| >= 2 of the
+// unit lattice, i.e. the Ewald sum minus the 27 near images.  The Ewald sum
+// uses Hasimoto's split phi(k) = (1 + k^2/(4 xi^2)) exp(-k^2/(4 xi^2)) of the
+// Fourier series (I - k k^T/k^2)/k^2 (net force zero, k = 0 dropped):
+//   real part     8 pi G_R = (erfc(xi r)/r - c e) I + (erfc(xi r)/r + c e) r r^T/r^2,
+//                 c = 2 xi/sqrt(pi), e = exp(-xi^2 r^2)  (G_R = (I lap - grad grad) B/(8 pi),
+//                 B' = erfc(xi r));
+//   near images   minus their smooth part G - G_R, which at r = 0 is 2c I/(8 pi);
+//   reciprocal    sum_{k != 0} phi(k)/k^2 (I - k k^T/k^2) cos(k.r).
+struct StokesFarImages {
+    double xi, rc, c;
+    std::vector<double> kx, ky, kz, kw;   // half-space reciprocal vectors, weight 2 phi/k^2
+
+    StokesFarImages() {
+        xi = 4.0;
+        const double s = std::sqrt(-std::log(1e-16)) + 0.5;
+        rc = s / xi;
+        c = 2.0 * xi / std::sqrt(kPi);
+        const int nmax = int(std::ceil(2.0 * xi * s / (2.0 * kPi)));
+        for (int a = -nmax; a <= nmax; ++a)
+            for (int b = -nmax; b <= nmax; ++b)
+                for (int q = 0; q <= nmax; ++q) {
+                    const bool half = q > 0 || (q == 0 && (b > 0 || (b == 0 && a > 0)));
+                    if (!half) continue;
+                    const double k0 = 2 * kPi * a, k1 = 2 * kPi * b, k2 = 2 * kPi * q;
+                    const double kk = k0 * k0 + k1 * k1 + k2 * k2, t = kk / (4 * xi * xi);
+                    kx.push_back(k0);
+                    ky.push_back(k1);
+                    kz.push_back(k2);
+                    kw.push_back(2.0 * (1.0 + t) * std::exp(-t) / kk);
+                }
+    }
+
+    // real-space part of the far-image block at separation r, added to B (3x3)
+    void real_part(const double r[3], double B[9]) const {
+        auto add = [&](const double x[3], double A, double Bc) {
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) B[3 * i + j] += (i == j ? A : 0.0) + Bc * x[i] * x[j];
+        };
+        const double inv8pi = 1.0 / (8.0 * kPi);
+        for (int a = -1; a <= 1; ++a)
+            for (int b = -1; b <= 1; ++b)
+                for (int q = -1; q <= 1; ++q) {
+                    const double x[3] = {r[0] + a, r[1] + b, r[2] + q};
+                    const double rho = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+                    if (rho == 0.0) {
+                        add(x, -2.0 * c * inv8pi, 0.0);
+                        continue;
+                    }
+                    const double e = std::exp(-xi * xi * rho * rho), ef = std::erf(xi * rho) / rho;
+                    add(x, -(ef + c * e) * inv8pi, -(ef - c * e) / (rho * rho) * inv8pi);
+                }
+        int lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = int(std::floor(-r[k] - rc));
+            hi[k] = int(std::ceil(-r[k] + rc));
+        }
+        for (int a = lo[0]; a <= hi[0]; ++a)
+            for (int b = lo[1]; b <= hi[1]; ++b)
+                for (int q = lo[2]; q <= hi[2]; ++q) {
+                    if (std::abs(a) <= 1 && std::abs(b) <= 1 && std::abs(q) <= 1) continue;
+                    const double x[3] = {r[0] + a, r[1] + b, r[2] + q};
+                    const double rr = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+                    if (rr >= rc * rc) continue;
+                    const double rho = std::sqrt(rr);
+                    const double e = std::exp(-xi * xi * rr), ec = std::erfc(xi * rho) / rho;
+                    add(x, (ec - c * e) * inv8pi, (ec + c * e) / rr * inv8pi);
+                }
+    }
+};
+
+// Stokeslet block G(x - y) (row-major 3x3)
+void stokeslet_block(const double x[3], const double y[3], double G[9]) {
+    const double r[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
+    const double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2], ri = 1.0 / std::sqrt(r2);
+    const double s = ri / (8.0 * kPi), s3 = s / r2;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) G[3 * i + j] = (i == j ? s : 0.0) + s3 * r[i] * r[j];
+}
+
+// X <- pinv(G) X for a square n x n G (truncated SVD, relative tol), X n x m
+void apply_pinv(Pool &pool, const std::vector<double> &G, int n, double tol, std::vector<double> &X, int m) {
+    std::vector<double> U, sv, V;
+    jacobi_svd(pool, G, n, U, sv, V);
+    int r = 0;
+    while (r < n && sv[r] > tol * sv[0]) ++r;
+    std::vector<double> Y(size_t(r) * m, 0.0);   // diag(1/s) U^T X
+    pool.parallel_for(r, [&](int k) {
+        double *y = &Y[size_t(k) * m];
+        for (int i = 0; i < n; ++i) {
+            const double u = U[size_t(i) * n + k];
+            const double *x = &X[size_t(i) * m];
+            for (int j = 0; j < m; ++j) y[j] += u * x[j];
+        }
+        for (int j = 0; j < m; ++j) y[j] /= sv[k];
+    });
+    pool.parallel_for(n, [&](int i) {
+        double *x = &X[size_t(i) * m];
+        std::fill(x, x + m, 0.0);
+        for (int k = 0; k < r; ++k) {
+            const double v = V[size_t(i) * n + k];
+            const double *y = &Y[size_t(k) * m];
+            for (int j = 0; j < m; ++j) x[j] += v * y[j];
+        }
+    });
+}
+
 }  // namespace
+
+std::string build_periodic_stokes(int p, double svd_tol, std::vector<double> &Q, std::vector<double> &X,
+                                  std::vector<double> &Z) {
+    if (p < 2 || p > 16) return "p must lie in [2, 16]";
+    Pool pool(pool_threads());
+    std::vector<double> g;
+    surface_lattice(p, g);
+    const int M = int(g.size() / 3), n3 = 3 * M;
+    const double aIn = 0.5 * kAlphaIn, aOut = 0.5 * kAlphaOut;
+    auto pt = [&](int m, double a, double x[3]) {
+        for (int k = 0; k < 3; ++k) x[k] = a * g[3 * m + k];
+    };
+    std::vector<double> G(size_t(n3) * n3);
+    auto fill_stokeslet = [&](double ax, double ay) {
+        pool.parallel_for(M, [&](int i) {
+            double x[3], y[3], B[9];
+            pt(i, ax, x);
+            for (int m = 0; m < M; ++m) {
+                pt(m, ay, y);
+                stokeslet_block(x, y, B);
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) G[size_t(3 * i + a) * n3 + 3 * m + b] = B[3 * a + b];
+            }
+        });
+    };
+    // Stokeslet forces on the upward equivalent points (radius a_in) with the
+    // root's flow on its upward check surface (radius a_out): W = pinv(G_up).
+    // The downward fit (check points at a_in, equivalent points at a_out)
+    // has the transposed matrix (G is even and symmetric), so its
+    // pseudo-inverse is W^T.
+    std::vector<double> W(size_t(n3) * n3, 0.0);
+    for (int i = 0; i < n3; ++i) W[size_t(i) * n3 + i] = 1.0;
+    fill_stokeslet(aOut, aIn);
+    apply_pinv(pool, G, n3, svd_tol, W, n3);
+    // their far images at the downward check points (radius a_in, as the
+    // upward equivalent points)
+    StokesFarImages far;
+    const int nk = int(far.kw.size());
+    std::vector<double> C(size_t(M) * nk), S(size_t(M) * nk), KK(size_t(6) * nk);
+    for (int k = 0; k < nk; ++k) {
+        const double kk = far.kx[k] * far.kx[k] + far.ky[k] * far.ky[k] + far.kz[k] * far.kz[k];
+        const double kv[3] = {far.kx[k], far.ky[k], far.kz[k]};
+        int q = 0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = a; b < 3; ++b) KK[size_t(q++) * nk + k] = kv[a] * kv[b] / kk;
+    }
+    for (int i = 0; i < M; ++i)
+        for (int k = 0; k < nk; ++k) {
+            const double ph = aIn * (far.kx[k] * g[3 * i] + far.ky[k] * g[3 * i + 1] + far.kz[k] * g[3 * i + 2]);
+            C[size_t(i) * nk + k] = std::cos(ph);
+            S[size_t(i) * nk + k] = std::sin(ph);
+        }
+    std::vector<double> T(size_t(n3) * n3);
+    pool.parallel_for(M, [&](int i) {
+        for (int m = 0; m < M; ++m) {
+            const double r[3] = {aIn * (g[3 * i] - g[3 * m]), aIn * (g[3 * i + 1] - g[3 * m + 1]),
+                                 aIn * (g[3 * i + 2] - g[3 * m + 2])};
+            double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            far.real_part(r, B);
+            double s0 = 0.0, sq[6] = {0, 0, 0, 0, 0, 0};
+            const double *ci = &C[size_t(i) * nk], *cm = &C[size_t(m) * nk];
+            const double *si = &S[size_t(i) * nk], *sm = &S[size_t(m) * nk];
+            for (int k = 0; k < nk; ++k) {
+                const double w = far.kw[k] * (ci[k] * cm[k] + si[k] * sm[k]);
+                s0 += w;
+                for (int q = 0; q < 6; ++q) sq[q] += w * KK[size_t(q) * nk + k];
+            }
+            const int qi[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    T[size_t(3 * i + a) * n3 + 3 * m + b] = B[3 * a + b] + (a == b ? s0 : 0.0) - sq[qi[a][b]];
+        }
+    });
+    std::vector<double> TW(size_t(n3) * n3, 0.0);   // T W
+    pool.parallel_for(n3, [&](int i) {
+        double *y = &TW[size_t(i) * n3];
+        for (int k = 0; k < n3; ++k) {
+            const double t = T[size_t(i) * n3 + k];
+            const double *w = &W[size_t(k) * n3];
+            for (int j = 0; j < n3; ++j) y[j] += t * w[j];
+        }
+    });
+    // Stokeslet forces on the downward equivalent points (radius a_out) with
+    // that field on the downward check surface (inside it they give the far
+    // images' flow): Q = W^T T W
+    Q.assign(size_t(n3) * n3, 0.0);
+    pool.parallel_for(n3, [&](int i) {
+        double *y = &Q[size_t(i) * n3];
+        for (int k = 0; k < n3; ++k) {
+            const double w = W[size_t(k) * n3 + i];
+            const double *t = &TW[size_t(k) * n3];
+            for (int j = 0; j < n3; ++j) y[j] += w * t[j];
+        }
+    });
+    X.resize(size_t(n3));
+    Z.resize(size_t(n3));
+    for (int m = 0; m < M; ++m) {
+        pt(m, aOut, &X[3 * size_t(m)]);
+        pt(m, aOut, &Z[3 * size_t(m)]);
+    }
+    return "";
+}
 
 std::string build_operators(int p, double svd_tol, bool periodic, Operators &ops, double m2l_tol) {
     if (p < 2 || p > 16) return "p must lie in [2, 16]";

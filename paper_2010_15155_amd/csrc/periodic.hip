@@ -1,0 +1,209 @@
+// Triply periodic Stokeslet: the root's far images (Sec. III and its
+// appendix on periodicity).  The near images (max|n_k| <= 1) are part of the
+// tree's shifted lists; the others reach the targets through Stokeslet forces
+// F on the root's downward equivalent points: the root's flow is summed
+// directly at its upward check points (V), and F = Q V with Q from the host
+// (Stokeslet fits and Hasimoto's Ewald split, zero net force).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace kafmm {
+
+namespace {
+
+constexpr double kInv8Pi = 0.039788735772973836;   // 1/(8 pi)
+
+constexpr int kRootChunk = 4096;   // sources per block of the check-surface sum
+constexpr int kRootPer = 6;        // check points per thread (M <= 1536)
+
+// part[chunk][3m + a] = 8 pi x the flow at check point X_m (relative to the
+// root centre) of the chunk's sources (sorted records: hi, lo position in the
+// unit box, f at slots 6..8); FP32 pair sums per LDS tile, FP64 across tiles
+__global__ __launch_bounds__(256) void stokes_root_check_kernel(int64_t n, const float *__restrict__ src, int rec,
+                                                                const double *__restrict__ X, int M,
+                                                                double *__restrict__ part) {
+    __shared__ float tile[256 * 6];
+    const int64_t j0 = int64_t(blockIdx.x) * kRootChunk, j1 = min(n, j0 + kRootChunk);
+    float x[kRootPer][3];
+    double acc[kRootPer][3];
+#pragma unroll
+    for (int q = 0; q < kRootPer; ++q) {
+        const int m = int(threadIdx.x) + 256 * q;
+        for (int k = 0; k < 3; ++k) {
+            x[q][k] = m < M ? float(X[3 * m + k]) : 0.0f;
+            acc[q][k] = 0.0;
+        }
+    }
+    for (int64_t t0 = j0; t0 < j1; t0 += 256) {
+        const int cnt = int(min<int64_t>(256, j1 - t0));
+        __syncthreads();
+        if (int(threadIdx.x) < cnt) {
+            const float *r = src + (t0 + threadIdx.x) * rec;
+            float *o = tile + 6 * threadIdx.x;
+            for (int k = 0; k < 3; ++k) {
+                o[k] = float((double(r[k]) - 0.5) + double(r[3 + k]));
+                o[3 + k] = r[6 + k];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kRootPer; ++q) {
+            if (int(threadIdx.x) + 256 * q >= M) continue;
+            float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
+            for (int j = 0; j < cnt; ++j) {
+                const float *y = tile + 6 * j;
+                const float r0 = x[q][0] - y[0], r1 = x[q][1] - y[1], r2 = x[q][2] - y[2];
+                const float ri = __builtin_amdgcn_rsqf(r0 * r0 + r1 * r1 + r2 * r2);
+                const float rf = (r0 * y[3] + r1 * y[4] + r2 * y[5]) * ri * ri * ri;
+                u0 += y[3] * ri + r0 * rf;
+                u1 += y[4] * ri + r1 * rf;
+                u2 += y[5] * ri + r2 * rf;
+            }
+            acc[q][0] += double(u0);
+            acc[q][1] += double(u1);
+            acc[q][2] += double(u2);
+        }
+    }
+    double *o = part + int64_t(blockIdx.x) * 3 * M;
+#pragma unroll
+    for (int q = 0; q < kRootPer; ++q) {
+        const int m = int(threadIdx.x) + 256 * q;
+        if (m < M)
+            for (int k = 0; k < 3; ++k) o[3 * m + k] = acc[q][k];
+    }
+}
+
+// V[r] = sum over chunks of part[chunk][r], in chunk order
+__global__ __launch_bounds__(256) void stokes_root_reduce_kernel(const double *__restrict__ part, int nchunks, int n3,
+                                                                 double *__restrict__ V) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n3) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += part[int64_t(c) * n3 + r];
+    V[r] = s;
+}
+
+// F[r] = sum_k Q[r][k] V[k] / (8 pi)
+__global__ __launch_bounds__(256) void stokes_far_forces_kernel(const double *__restrict__ Q,
+                                                                const double *__restrict__ V, int n3,
+                                                                double *__restrict__ F) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n3) return;
+    const double *q = Q + int64_t(r) * n3;
+    double s = 0.0;
+    for (int k = 0; k < n3; ++k) s += q[k] * V[k];
+    F[r] = s * kInv8Pi;
+}
+
+// out[perm[i]][a] += scale sum_m G(x_i - z_m) F_m, x_i the sorted target
+// (hi + lo, unit box) relative to the root centre; F and z staged in LDS.
+// The far images' flow is smooth in the box (z_m lie outside it): FP32 pair
+// terms, summed per tile in FP32 and across tiles in FP64.
+__global__ __launch_bounds__(256) void stokes_far_targets_kernel(int64_t n, const float *__restrict__ trg,
+                                                                 const int32_t *__restrict__ perm,
+                                                                 const double *__restrict__ F,
+                                                                 const double *__restrict__ Z, int M, double scale,
+                                                                 double *__restrict__ out) {
+    __shared__ float tile[256 * 6];
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool active = i < n;
+    float x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+    if (active) {
+        const float4 h = reinterpret_cast<const float4 *>(trg)[2 * i];
+        const float4 l = reinterpret_cast<const float4 *>(trg)[2 * i + 1];
+        x0 = float((double(h.x) - 0.5) + double(l.x));
+        x1 = float((double(h.y) - 0.5) + double(l.y));
+        x2 = float((double(h.z) - 0.5) + double(l.z));
+    }
+    double u[3] = {0, 0, 0};
+    for (int j0 = 0; j0 < M; j0 += 256) {
+        const int cnt = min(256, M - j0);
+        __syncthreads();
+        if (int(threadIdx.x) < cnt) {
+            const int m = j0 + threadIdx.x;
+            float *o = tile + 6 * threadIdx.x;
+            for (int k = 0; k < 3; ++k) {
+                o[k] = float(Z[3 * m + k]);
+                o[3 + k] = float(F[3 * m + k]);
+            }
+        }
+        __syncthreads();
+        if (!active) continue;
+        float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
+        for (int j = 0; j < cnt; ++j) {
+            const float *t = tile + 6 * j;
+            const float r0 = x0 - t[0], r1 = x1 - t[1], r2 = x2 - t[2];
+            const float ri = __builtin_amdgcn_rsqf(r0 * r0 + r1 * r1 + r2 * r2);
+            const float rf = (r0 * t[3] + r1 * t[4] + r2 * t[5]) * ri * ri * ri;
+            v0 += t[3] * ri + r0 * rf;
+            v1 += t[4] * ri + r1 * rf;
+            v2 += t[5] * ri + r2 * rf;
+        }
+        u[0] += double(v0);
+        u[1] += double(v1);
+        u[2] += double(v2);
+    }
+    if (!active) return;
+    double *o = out + 3 * int64_t(perm[i]);
+    for (int k = 0; k < 3; ++k) o[k] += scale * kInv8Pi * u[k];
+}
+
+// per-block partial sums of f (3 components) and |f| (net-force check)
+__global__ __launch_bounds__(256) void force_partials_kernel(int64_t n, const double *__restrict__ f,
+                                                             double *__restrict__ part) {
+    __shared__ double s[4][256];
+    double a[4] = {0, 0, 0, 0};
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        for (int k = 0; k < 3; ++k) {
+            const double v = f[3 * i + k];
+            a[k] += v;
+            a[3] += fabs(v);
+        }
+    for (int k = 0; k < 4; ++k) s[k][threadIdx.x] = a[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w)
+            for (int k = 0; k < 4; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) part[4 * blockIdx.x + k] = s[k][0];
+}
+
+}  // namespace
+
+int stokes_root_chunks(int64_t n) { return int((n + kRootChunk - 1) / kRootChunk); }
+
+hipError_t launch_stokes_far_forces(int64_t n_src, const float *src, int rec, const double *X, const double *Q, int M,
+                                    double *part, double *V, double *F, hipStream_t s) {
+    if (M > 256 * kRootPer) return hipErrorInvalidValue;
+    const int nch = stokes_root_chunks(n_src), n3 = 3 * M;
+    if (nch > 0) {
+        hipLaunchKernelGGL(stokes_root_check_kernel, dim3(nch), dim3(256), 0, s, n_src, src, rec, X, M, part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(stokes_root_reduce_kernel, dim3((n3 + 255) / 256), dim3(256), 0, s, part, nch, n3, V);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(stokes_far_forces_kernel, dim3((n3 + 255) / 256), dim3(256), 0, s, Q, V, n3, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_stokes_far_targets(int64_t n, const float *trg, const int32_t *perm, const double *F,
+                                     const double *Z, int M, double scale, double *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(stokes_far_targets_kernel, dim3(int((n + 255) / 256)), dim3(256), 0, s, n, trg, perm, F, Z, M,
+                       scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_force_partials(int64_t n, const double *f, int nblocks, double *part, hipStream_t s) {
+    hipLaunchKernelGGL(force_partials_kernel, dim3(nblocks), dim3(256), 0, s, n, f, part);
+    return hipGetLastError();
+}
+
+}  // namespace kafmm

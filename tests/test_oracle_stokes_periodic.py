@@ -1,0 +1,67 @@
+"""Pins for the oracle's triply periodic Stokeslet (Ewald, Hasimoto split).
+
+* the sum does not depend on the split parameter xi (real and reciprocal
+  parts trade places), at targets off the sources and on them (self term);
+* it is periodic in the targets and invariant when sources and targets move
+  together;
+* next to a source it is the free-space Stokeslet (the normalisation
+  1/(8 pi)): r u(y + r e) -> (I + e e^T) f / (8 pi) as r -> 0;
+* it is divergence free (central differences).
+"""
+import numpy as np
+import pytest
+
+from oracle.stokes_periodic import stokeslet_periodic
+
+
+def _problem(n, seed):
+    rng = np.random.default_rng(seed)
+    y = rng.random((n, 3))
+    f = rng.standard_normal((n, 3))
+    f -= f.mean(axis=0)                      # zero net force
+    return rng, y, f
+
+
+def test_split_parameter_independence():
+    rng, y, f = _problem(40, 1)
+    x = np.concatenate([rng.random((30, 3)), y[:6]])
+    u = [stokeslet_periodic(y, f, x, xi=xi) for xi in (3.0, 5.0, 8.0)]
+    scale = np.abs(u[0]).max()
+    assert np.abs(u[1] - u[0]).max() < 1e-13 * scale
+    assert np.abs(u[2] - u[0]).max() < 1e-13 * scale
+
+
+def test_periodic_and_translation_invariant():
+    rng, y, f = _problem(30, 2)
+    x = rng.random((20, 3))
+    # keep targets away from sources so that rounding of shifted positions is harmless
+    d = np.min(np.linalg.norm(x[:, None] - y[None], axis=2), axis=1)
+    x = x[d > 0.05]
+    u = stokeslet_periodic(y, f, x)
+    up = stokeslet_periodic(y, f, x + np.array([1.0, -2.0, 1.0]))
+    assert np.abs(up - u).max() < 1e-12 * np.abs(u).max()
+    s = np.array([0.37, 0.81, 0.13])
+    ut = stokeslet_periodic((y + s) % 1.0, f, (x + s) % 1.0)
+    assert np.abs(ut - u).max() < 1e-12 * np.abs(u).max()
+
+
+def test_free_space_limit_next_to_a_source():
+    rng, y, f = _problem(20, 3)
+    e = np.array([0.6, 0.0, 0.8])
+    want = (f[0] + e * (e @ f[0])) / (8 * np.pi)
+    for r in (1e-5, 1e-6):
+        got = stokeslet_periodic(y, f, (y[0] + r * e)[None])[0] * r
+        assert np.abs(got - want).max() < 30 * r * np.abs(want).max()
+
+
+def test_divergence_free():
+    rng, y, f = _problem(25, 4)
+    x = rng.random((6, 3))
+    h = 1e-4
+    div = np.zeros(len(x))
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        div += (stokeslet_periodic(y, f, x + e)[:, k] - stokeslet_periodic(y, f, x - e)[:, k]) / (2 * h)
+    grad_scale = np.abs(stokeslet_periodic(y, f, x)).max() / 0.05
+    assert np.abs(div).max() < 1e-6 * grad_scale
