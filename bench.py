@@ -64,6 +64,8 @@ def parse():
                     help="measure the learned Stokeslet plan only (for profiler runs)")
     ap.add_argument("--only-plan", action="store_true",
                     help="measure the plan time with the GPU and the host tree builders only")
+    ap.add_argument("--only-periodic", action="store_true",
+                    help="measure the triply periodic Stokeslet row only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the measurement, copy a MIB-sized device buffer once (reference "
                          "kernel for scaling hardware byte counters)")
@@ -229,6 +231,9 @@ def main():
     f = torch.from_numpy(d["f"]).cuda()
     if args.only_plan:
         print(json.dumps({"plan_ms": tree_build(FMM, x)}), flush=True)
+        return
+    if args.only_periodic:
+        print(json.dumps({"stokeslet_pxyz_p8": periodic_stokeslet(FMM, torch, args.n, args)}), flush=True)
         return
     fmm = FMM()
     fmm.set_predictor(load_weights())

@@ -86,16 +86,23 @@ __global__ __launch_bounds__(256) void stokes_root_reduce_kernel(const double *_
     V[r] = s;
 }
 
-// F[r] = sum_k Q[r][k] V[k] / (8 pi)
+// F[r] = sum_k Q[r][k] V[k] / (8 pi): one block per row, strided partial
+// sums reduced in LDS (a fixed order)
 __global__ __launch_bounds__(256) void stokes_far_forces_kernel(const double *__restrict__ Q,
                                                                 const double *__restrict__ V, int n3,
                                                                 double *__restrict__ F) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n3) return;
+    __shared__ double red[256];
+    const int r = blockIdx.x;
     const double *q = Q + int64_t(r) * n3;
     double s = 0.0;
-    for (int k = 0; k < n3; ++k) s += q[k] * V[k];
-    F[r] = s * kInv8Pi;
+    for (int k = threadIdx.x; k < n3; k += 256) s += q[k] * V[k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) F[r] = red[0] * kInv8Pi;
 }
 
 // out[perm[i]][a] += scale sum_m G(x_i - z_m) F_m, x_i the sorted target
@@ -189,7 +196,7 @@ hipError_t launch_stokes_far_forces(int64_t n_src, const float *src, int rec, co
     hipLaunchKernelGGL(stokes_root_reduce_kernel, dim3((n3 + 255) / 256), dim3(256), 0, s, part, nch, n3, V);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(stokes_far_forces_kernel, dim3((n3 + 255) / 256), dim3(256), 0, s, Q, V, n3, F);
+    hipLaunchKernelGGL(stokes_far_forces_kernel, dim3(n3), dim3(256), 0, s, Q, V, n3, F);
     return hipGetLastError();
 }
 
