@@ -92,9 +92,9 @@ typedef enum {
 /* Boundary conditions (Sec. III and its appendix on periodicity).  PXYZ is
  * implemented for LAP_PGRAD, LAP_PGRADGRAD and LAP_QPGRADGRAD (zero net
  * charge; Ewald's convention: no k = 0 term, no surface term) and for
- * STOKESLET (zero net force; the Fourier series of the periodic Stokes
- * equations without its k = 0 term, i.e. zero mean velocity, summed with
- * Hasimoto's Ewald split).  WALL (Sec. III, the no-slip wall section,
+ * STOKESLET and RPY (zero net force; the Fourier series of the periodic
+ * Stokes equations without its k = 0 term, i.e. zero mean velocity, summed
+ * with Hasimoto's Ewald split).  WALL (Sec. III, the no-slip wall section,
  * tab:rpywall) is an open domain bounded below by a no-slip wall on the
  * plane z = origin[2], for STOKESLET and RPY only, fixed p and leaf_cap only:
  * the flow is assembled from three (Stokeslet) or four (RPY) free-space
@@ -141,8 +141,8 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *ctx, stkfmm_kernel kernel, stkfmm_bc
  * (overwritten, user order).  Periodic LAP_PGRAD requires sum q = 0
  * (relative to sum |q|, 1e-9), else E_DOMAIN; its potential is defined up to
  * an additive constant (the Ewald convention with the k = 0 term dropped).
- * Periodic STOKESLET requires each component of sum f to vanish (relative to
- * sum |f_k|, 1e-9), else E_DOMAIN.
+ * Periodic STOKESLET and RPY require each component of sum f to vanish
+ * (relative to sum |f_k|, 1e-9), else E_DOMAIN.
  * Errors: E_STATE (no points set), E_ARG, E_DOMAIN, E_NOMEM, E_DEVICE. */
 stkfmm_status stkfmm_run(stkfmm_ctx *ctx, const double *sl_val, const double *dl_val,
                          double *trg_val, void *hip_stream);

@@ -43,6 +43,8 @@ def lib():
                                            _dp, _dp, _dp, ctypes.c_int]
         _lib.oracle_stokes_ewald_real.argtypes = [_i64, _dp, _dp, _i64, _dp, ctypes.c_double, ctypes.c_double,
                                                   ctypes.c_double, _dp]
+        _lib.oracle_stokes_lap_ewald_real.argtypes = [_i64, _dp, _dp, _dp, _i64, _dp, ctypes.c_double,
+                                                      ctypes.c_double, ctypes.c_double, _dp]
     return _lib
 
 

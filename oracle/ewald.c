@@ -271,3 +271,52 @@ void oracle_stokes_ewald_real(int64_t ns, const double *ys, const double *f, int
         for (int k = 0; k < 3; ++k) out[3 * t + k] = u[k] / (8.0 * PI);
     }
 }
+
+/*
+ * Real-space part of the triply periodic Laplacian of the Stokeslet,
+ * lap G = (2 I/r^3 - 6 r r^T/r^5)/(8 pi) (Hasimoto split as above): with
+ * H = lap B_R = 2 erfc(xi r)/r - c e,
+ *   8 pi lap G_R = [c e (8 xi^2 - 4 xi^4 r^2 + 2/r^2) + 2 erfc(xi r)/r^3] I
+ *                + [c e (-4 xi^2 + 4 xi^4 r^2 - 6/r^2) - 6 erfc(xi r)/r^3] r r^T/r^2,
+ * and for a target on a source the self term +(5/3) xi^3/pi^{3/2} f (minus
+ * the smooth part at r = 0, -(5/3) xi^3/pi^{3/2} I).  w [ns] weights each
+ * source (b^2/6 for the RPY velocity, 1 for its Laplacian).  out [nt][3] is
+ * overwritten.
+ */
+void oracle_stokes_lap_ewald_real(int64_t ns, const double *ys, const double *f, const double *w, int64_t nt,
+                                  const double *xs, double L, double xi, double rc, double *out)
+{
+    const double c = 2.0 * xi / sqrt(PI);
+    const int nimg = (int)floor(rc / L + 0.5);
+    const double x2 = xi * xi, x4 = x2 * x2;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        double u[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < ns; ++j) {
+            double d[3], fw[3];
+            int same = 1;
+            for (int k = 0; k < 3; ++k) {
+                d[k] = xs[3 * t + k] - ys[3 * j + k];
+                same = same && d[k] == 0.0;
+                d[k] -= L * nearbyint(d[k] / L);
+                fw[k] = w[j] * f[3 * j + k];
+            }
+            if (same)
+                for (int k = 0; k < 3; ++k) u[k] += 5.0 / 3.0 * xi * x2 / (PI * sqrt(PI)) * 8.0 * PI * fw[k];
+            for (int a = -nimg; a <= nimg; ++a)
+                for (int b = -nimg; b <= nimg; ++b)
+                    for (int e3 = -nimg; e3 <= nimg; ++e3) {
+                        const double r[3] = {d[0] - L * a, d[1] - L * b, d[2] - L * e3};
+                        const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                        if (rr >= rc * rc || rr == 0.0) continue;
+                        const double rho = sqrt(rr), e = exp(-x2 * rr), ec = erfc(xi * rho) / (rho * rr);
+                        const double A = c * e * (8.0 * x2 - 4.0 * x4 * rr + 2.0 / rr) + 2.0 * ec;
+                        const double B = (c * e * (-4.0 * x2 + 4.0 * x4 * rr - 6.0 / rr) - 6.0 * ec) / rr;
+                        const double rf = r[0] * fw[0] + r[1] * fw[1] + r[2] * fw[2];
+                        for (int k = 0; k < 3; ++k) u[k] += A * fw[k] + B * rf * r[k];
+                    }
+        }
+        for (int k = 0; k < 3; ++k) out[3 * t + k] = u[k] / (8.0 * PI);
+    }
+}
+

@@ -68,3 +68,54 @@ def stokeslet_periodic(src, f, trg, L=1.0, xi=None, tol=1e-15):
     for i0 in range(0, len(x), 1024):
         u[i0:i0 + 1024] += np.real(np.exp(1j * (x[i0:i0 + 1024] @ K.T)) @ W)
     return u
+
+
+def _reciprocal(y, fw, x, L, xi, nmax, lap):
+    """(1/V) sum_{k != 0} a(k) (I - k k^T/k^2) Re[S(k) e^{i k.x}], S = sum_j fw_j e^{-i k.y_j},
+    a = phi/k^2 (the Stokeslet) or -phi (its Laplacian)."""
+    m = np.arange(-nmax, nmax + 1)
+    K = np.stack(np.meshgrid(m, m, m, indexing="ij"), axis=-1).reshape(-1, 3).astype(np.float64)
+    K = K[np.any(K != 0, axis=1)] * (2.0 * PI / L)
+    k2 = np.sum(K * K, axis=1)
+    phi = (1.0 + k2 / (4.0 * xi * xi)) * np.exp(-k2 / (4.0 * xi * xi))
+    a = -phi if lap else phi / k2
+    S = np.zeros((len(K), 3), dtype=np.complex128)
+    for j0 in range(0, len(y), 1024):
+        S += np.exp(-1j * (K @ y[j0:j0 + 1024].T)) @ fw[j0:j0 + 1024]
+    PS = S - K * (np.sum(K * S, axis=1) / k2)[:, None]
+    Wk = a[:, None] * PS / L ** 3
+    u = np.zeros((len(x), 3))
+    for i0 in range(0, len(x), 1024):
+        u[i0:i0 + 1024] = np.real(np.exp(1j * (x[i0:i0 + 1024] @ K.T)) @ Wk)
+    return u
+
+
+def stokes_lap_periodic(src, f, w, trg, L=1.0, xi=None, tol=1e-15):
+    """Periodic sum of the Stokeslet's Laplacian, lap G = (2 I/r^3 - 6 r r^T/r^5)/(8 pi),
+    applied to w_j f_j [m, 3] (same convention: zero net force, k = 0 dropped;
+    pairs with r = 0 left out).  Reciprocal amplitude -phi(k) (I - k k^T/k^2);
+    real part and self term in ewald.c."""
+    y = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3)
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1, 3)
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+    x = np.ascontiguousarray(trg, dtype=np.float64).reshape(-1, 3)
+    xi, rc, nmax = parameters(L, xi, tol)
+    nmax += 2                      # phi(k) k^2 decays more slowly than phi(k)/k^2
+    u = np.zeros((len(x), 3))
+    if len(y) == 0 or len(x) == 0:
+        return u
+    lib().oracle_stokes_lap_ewald_real(len(y), _p(y), _p(f), _p(w), len(x), _p(x), float(L), float(xi), float(rc),
+                                       _p(u))
+    return u + _reciprocal(y, w[:, None] * f, x, L, xi, nmax, True)
+
+
+def rpy_periodic(src, fb, trg, L=1.0, xi=None, tol=1e-15):
+    """Periodic RPY (Sec. II.B: u = (1 + b^2/6 lap) G f for r > 0) with its
+    Laplacian: [m, 6] = (u, lap u).  Off the sources lap^2 G = 0, so
+    lap u is the periodic sum of lap G f; f must sum to zero."""
+    fb = np.ascontiguousarray(fb, dtype=np.float64).reshape(-1, 4)
+    f, b2 = fb[:, :3], fb[:, 3] ** 2
+    u = stokeslet_periodic(src, f, trg, L, xi, tol) + stokes_lap_periodic(src, f, b2 / 6.0, trg, L, xi, tol)
+    lap = stokes_lap_periodic(src, f, np.ones(len(f)), trg, L, xi, tol)
+    return np.concatenate([u, lap], axis=1)
+

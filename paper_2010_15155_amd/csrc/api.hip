@@ -1036,9 +1036,9 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     if (bc != STKFMM_BC_OPEN && bc != STKFMM_BC_PXYZ)
         return fail(c, STKFMM_E_UNSUPPORTED, "only open, triply periodic and wall boundaries are implemented");
     if (bc == STKFMM_BC_PXYZ && kernel != STKFMM_LAP_PGRAD && kernel != STKFMM_LAP_PGRADGRAD &&
-        kernel != STKFMM_LAP_QPGRADGRAD && kernel != STKFMM_STOKESLET)
+        kernel != STKFMM_LAP_QPGRADGRAD && kernel != STKFMM_STOKESLET && kernel != STKFMM_RPY)
         return fail(c, STKFMM_E_UNSUPPORTED,
-                    "triply periodic boundary is implemented for the Laplace kernels and STOKESLET");
+                    "triply periodic boundary is implemented for the Laplace kernels, STOKESLET and RPY");
     const bool periodic = bc == STKFMM_BC_PXYZ;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(c, hipSetDevice(c->device));
@@ -1148,7 +1148,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     stkfmm_status st = get_ops(c, p, periodic, m2l_tol, &ops);
     if (st != STKFMM_OK) return st;
     c->stk = nullptr;
-    if (periodic && kernel == STKFMM_STOKESLET) {
+    if (periodic && (kernel == STKFMM_STOKESLET || kernel == STKFMM_RPY)) {
         st = get_periodic_stokes(c, &c->stk);
         if (st != STKFMM_OK) return st;
         const int Mf = c->stk->M;
@@ -1699,10 +1699,11 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
     const int nc = ki.ncomp;
     const bool periodic = c->bc == STKFMM_BC_PXYZ;
     if (c->n_trg == 0) return STKFMM_OK;
-    if (periodic && c->n_sl > 0 && c->kernel == kStokeslet) {
+    const bool pstokes = periodic && (c->kernel == kStokeslet || c->kernel == kRPY);
+    if (pstokes && c->n_sl > 0) {
         // zero net force (the Ewald convention drops the k = 0 mode)
         const int nbk = 256;
-        HIP_TRY(c, launch_force_partials(c->n_sl, sl_val, nbk, c->partial.as<double>(), s));
+        HIP_TRY(c, launch_force_partials(c->n_sl, sl_val, ki.k_sl, nbk, c->partial.as<double>(), s));
         std::vector<double> hp(4 * nbk);
         HIP_TRY(c, hipMemcpyAsync(hp.data(), c->partial.p, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
@@ -1831,8 +1832,9 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 4 M2L
         HIP_TRY(c, s2c(c->s2l, kAlphaIn, dnchk, 1));
         if (periodic && nc == 1) HIP_TRY(c, launch_periodic(o.tm2l.as<double>(), updens, dnchk, o.M, o.Mp, nc, 0, s));
-        if (periodic && c->kernel == kStokeslet)
-            HIP_TRY(c, launch_stokes_far_forces(c->n_sl, c->sl_rec.as<float>(), ki.rec_sl, c->stk->X.as<double>(),
+        if (pstokes)
+            HIP_TRY(c, launch_stokes_far_forces(c->n_sl, c->sl_rec.as<float>(), ki.rec_sl, c->kernel == kRPY,
+                                                c->stk->X.as<double>(),
                                                 c->stk->Q.as<double>(), c->stk->M, c->stk_part.as<double>(),
                                                 c->stk_F.as<double>(), c->stk_F.as<double>() + 3 * c->stk->M, s));
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 5 S2L + periodic
@@ -1881,10 +1883,11 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         a.map = combine_map(c->kernel, c->box_len);
         a.out = trg_val;
         HIP_TRY(c, launch_combine(c->nchunks, a, s));
-        if (periodic && c->kernel == kStokeslet)
+        if (pstokes)
             HIP_TRY(c, launch_stokes_far_targets(c->n_trg, c->trg_rec.as<float>(), at<int32_t>(c, c->a_perm_trg),
-                                                 c->stk_F.as<double>() + 3 * c->stk->M, c->stk->Z.as<double>(),
-                                                 c->stk->M, 1.0 / c->box_len,
+                                                 c->kernel == kRPY, c->stk_F.as<double>() + 3 * c->stk->M,
+                                                 c->stk->Z.as<double>(), c->stk->M, 1.0 / c->box_len,
+                                                 1.0 / (c->box_len * c->box_len * c->box_len),
                                                  trg_val, s));
     }
     HIP_TRY(c, hipEventRecord(ev[ne++], s));                  // end

@@ -187,14 +187,16 @@ hipError_t launch_wall_assemble(const WallAssembleArgs &a, hipStream_t s);
 // Triply periodic Stokeslet (periodic.hip): the root's flow V at its upward
 // check points X (sorted SL records, chunks of 4096 sources, partial sums in
 // part [chunks][3M]), then the far images' forces F = Q V / (8 pi); targets
-// (sorted, unit-box records) add scale * sum_m G(x - Z_m) F_m in user order;
-// per-block sums of f and |f| (4 doubles per block).
+// (sorted, unit-box records) add scale * sum_m G(x - Z_m) F_m in user order
+// (RPY: also lap u, scale_lap); per-block sums of f and |f| (4 doubles per
+// block, values `stride` apart).
 int stokes_root_chunks(int64_t n);
-hipError_t launch_stokes_far_forces(int64_t n_src, const float *src, int rec, const double *X, const double *Q, int M,
-                                    double *part, double *V, double *F, hipStream_t s);
-hipError_t launch_stokes_far_targets(int64_t n, const float *trg, const int32_t *perm, const double *F,
-                                     const double *Z, int M, double scale, double *out, hipStream_t s);
-hipError_t launch_force_partials(int64_t n, const double *f, int nblocks, double *part, hipStream_t s);
+hipError_t launch_stokes_far_forces(int64_t n_src, const float *src, int rec, bool rpy, const double *X,
+                                    const double *Q, int M, double *part, double *V, double *F, hipStream_t s);
+hipError_t launch_stokes_far_targets(int64_t n, const float *trg, const int32_t *perm, bool rpy, const double *F,
+                                     const double *Z, int M, double scale, double scale_lap, double *out,
+                                     hipStream_t s);
+hipError_t launch_force_partials(int64_t n, const double *f, int stride, int nblocks, double *part, hipStream_t s);
 hipError_t launch_periodic(const double *T, const float *dens, double *chk, int M, int Mp, int nc, int root,
                            hipStream_t s);
 hipError_t launch_l2t(int kernel, int ntasks, const L2TArgs &a, hipStream_t s);

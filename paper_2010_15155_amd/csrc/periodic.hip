@@ -22,10 +22,12 @@ constexpr int kRootPer = 6;        // check points per thread (M <= 1536)
 // part[chunk][3m + a] = 8 pi x the flow at check point X_m (relative to the
 // root centre) of the chunk's sources (sorted records: hi, lo position in the
 // unit box, f at slots 6..8); FP32 pair sums per LDS tile, FP64 across tiles
+// RPY sources (b^2 at slot 9, unit-box units) add (b^2/6) lap G f.
+template <bool RPY>
 __global__ __launch_bounds__(256) void stokes_root_check_kernel(int64_t n, const float *__restrict__ src, int rec,
                                                                 const double *__restrict__ X, int M,
                                                                 double *__restrict__ part) {
-    __shared__ float tile[256 * 6];
+    __shared__ float tile[256 * 7];
     const int64_t j0 = int64_t(blockIdx.x) * kRootChunk, j1 = min(n, j0 + kRootChunk);
     float x[kRootPer][3];
     double acc[kRootPer][3];
@@ -42,11 +44,12 @@ __global__ __launch_bounds__(256) void stokes_root_check_kernel(int64_t n, const
         __syncthreads();
         if (int(threadIdx.x) < cnt) {
             const float *r = src + (t0 + threadIdx.x) * rec;
-            float *o = tile + 6 * threadIdx.x;
+            float *o = tile + 7 * threadIdx.x;
             for (int k = 0; k < 3; ++k) {
                 o[k] = float((double(r[k]) - 0.5) + double(r[3 + k]));
                 o[3 + k] = r[6 + k];
             }
+            o[6] = RPY ? r[9] * (1.0f / 6.0f) : 0.0f;
         }
         __syncthreads();
 #pragma unroll
@@ -54,13 +57,17 @@ __global__ __launch_bounds__(256) void stokes_root_check_kernel(int64_t n, const
             if (int(threadIdx.x) + 256 * q >= M) continue;
             float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
             for (int j = 0; j < cnt; ++j) {
-                const float *y = tile + 6 * j;
+                const float *y = tile + 7 * j;
                 const float r0 = x[q][0] - y[0], r1 = x[q][1] - y[1], r2 = x[q][2] - y[2];
                 const float ri = __builtin_amdgcn_rsqf(r0 * r0 + r1 * r1 + r2 * r2);
-                const float rf = (r0 * y[3] + r1 * y[4] + r2 * y[5]) * ri * ri * ri;
-                u0 += y[3] * ri + r0 * rf;
-                u1 += y[4] * ri + r1 * rf;
-                u2 += y[5] * ri + r2 * rf;
+                const float ri2 = ri * ri, ri3 = ri2 * ri;
+                const float rdf = r0 * y[3] + r1 * y[4] + r2 * y[5];
+                // G f = f/r + r (r.f)/r^3;  (b^2/6) lap G f = (b^2/6) (2 f/r^3 - 6 r (r.f)/r^5)
+                const float cf = RPY ? ri + 2.0f * y[6] * ri3 : ri;
+                const float cr = RPY ? (rdf * ri3) * (1.0f - 6.0f * y[6] * ri2) : rdf * ri3;
+                u0 += y[3] * cf + r0 * cr;
+                u1 += y[4] * cf + r1 * cr;
+                u2 += y[5] * cf + r2 * cr;
             }
             acc[q][0] += double(u0);
             acc[q][1] += double(u1);
@@ -109,11 +116,13 @@ __global__ __launch_bounds__(256) void stokes_far_forces_kernel(const double *__
 // (hi + lo, unit box) relative to the root centre; F and z staged in LDS.
 // The far images' flow is smooth in the box (z_m lie outside it): FP32 pair
 // terms, summed per tile in FP32 and across tiles in FP64.
+// RPY targets also take lap u = sum_m lap G(x - z_m) F_m (scale_lap).
+template <bool RPY>
 __global__ __launch_bounds__(256) void stokes_far_targets_kernel(int64_t n, const float *__restrict__ trg,
                                                                  const int32_t *__restrict__ perm,
                                                                  const double *__restrict__ F,
                                                                  const double *__restrict__ Z, int M, double scale,
-                                                                 double *__restrict__ out) {
+                                                                 double scale_lap, double *__restrict__ out) {
     __shared__ float tile[256 * 6];
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const bool active = i < n;
@@ -125,7 +134,7 @@ __global__ __launch_bounds__(256) void stokes_far_targets_kernel(int64_t n, cons
         x1 = float((double(h.y) - 0.5) + double(l.y));
         x2 = float((double(h.z) - 0.5) + double(l.z));
     }
-    double u[3] = {0, 0, 0};
+    double u[3] = {0, 0, 0}, w[3] = {0, 0, 0};
     for (int j0 = 0; j0 < M; j0 += 256) {
         const int cnt = min(256, M - j0);
         __syncthreads();
@@ -139,33 +148,47 @@ __global__ __launch_bounds__(256) void stokes_far_targets_kernel(int64_t n, cons
         }
         __syncthreads();
         if (!active) continue;
-        float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
+        float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, l0 = 0.0f, l1 = 0.0f, l2 = 0.0f;
         for (int j = 0; j < cnt; ++j) {
             const float *t = tile + 6 * j;
             const float r0 = x0 - t[0], r1 = x1 - t[1], r2 = x2 - t[2];
             const float ri = __builtin_amdgcn_rsqf(r0 * r0 + r1 * r1 + r2 * r2);
-            const float rf = (r0 * t[3] + r1 * t[4] + r2 * t[5]) * ri * ri * ri;
+            const float ri2 = ri * ri, ri3 = ri2 * ri;
+            const float rdf = r0 * t[3] + r1 * t[4] + r2 * t[5];
+            const float rf = rdf * ri3;
             v0 += t[3] * ri + r0 * rf;
             v1 += t[4] * ri + r1 * rf;
             v2 += t[5] * ri + r2 * rf;
+            if (RPY) {
+                // lap G F = 2 F/r^3 - 6 r (r.F)/r^5
+                const float c6 = -6.0f * rf * ri2;
+                l0 += 2.0f * t[3] * ri3 + r0 * c6;
+                l1 += 2.0f * t[4] * ri3 + r1 * c6;
+                l2 += 2.0f * t[5] * ri3 + r2 * c6;
+            }
         }
         u[0] += double(v0);
         u[1] += double(v1);
         u[2] += double(v2);
+        w[0] += double(l0);
+        w[1] += double(l1);
+        w[2] += double(l2);
     }
     if (!active) return;
-    double *o = out + 3 * int64_t(perm[i]);
+    double *o = out + (RPY ? 6 : 3) * int64_t(perm[i]);
     for (int k = 0; k < 3; ++k) o[k] += scale * kInv8Pi * u[k];
+    if (RPY)
+        for (int k = 0; k < 3; ++k) o[3 + k] += scale_lap * kInv8Pi * w[k];
 }
 
 // per-block partial sums of f (3 components) and |f| (net-force check)
-__global__ __launch_bounds__(256) void force_partials_kernel(int64_t n, const double *__restrict__ f,
+__global__ __launch_bounds__(256) void force_partials_kernel(int64_t n, const double *__restrict__ f, int stride,
                                                              double *__restrict__ part) {
     __shared__ double s[4][256];
     double a[4] = {0, 0, 0, 0};
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
         for (int k = 0; k < 3; ++k) {
-            const double v = f[3 * i + k];
+            const double v = f[stride * i + k];
             a[k] += v;
             a[3] += fabs(v);
         }
@@ -184,12 +207,16 @@ __global__ __launch_bounds__(256) void force_partials_kernel(int64_t n, const do
 
 int stokes_root_chunks(int64_t n) { return int((n + kRootChunk - 1) / kRootChunk); }
 
-hipError_t launch_stokes_far_forces(int64_t n_src, const float *src, int rec, const double *X, const double *Q, int M,
-                                    double *part, double *V, double *F, hipStream_t s) {
+hipError_t launch_stokes_far_forces(int64_t n_src, const float *src, int rec, bool rpy, const double *X,
+                                    const double *Q, int M, double *part, double *V, double *F, hipStream_t s) {
     if (M > 256 * kRootPer) return hipErrorInvalidValue;
+    if (rpy && rec < 10) return hipErrorInvalidValue;
     const int nch = stokes_root_chunks(n_src), n3 = 3 * M;
     if (nch > 0) {
-        hipLaunchKernelGGL(stokes_root_check_kernel, dim3(nch), dim3(256), 0, s, n_src, src, rec, X, M, part);
+        if (rpy)
+            hipLaunchKernelGGL(stokes_root_check_kernel<true>, dim3(nch), dim3(256), 0, s, n_src, src, rec, X, M, part);
+        else
+            hipLaunchKernelGGL(stokes_root_check_kernel<false>, dim3(nch), dim3(256), 0, s, n_src, src, rec, X, M, part);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -200,16 +227,20 @@ hipError_t launch_stokes_far_forces(int64_t n_src, const float *src, int rec, co
     return hipGetLastError();
 }
 
-hipError_t launch_stokes_far_targets(int64_t n, const float *trg, const int32_t *perm, const double *F,
-                                     const double *Z, int M, double scale, double *out, hipStream_t s) {
+hipError_t launch_stokes_far_targets(int64_t n, const float *trg, const int32_t *perm, bool rpy, const double *F,
+                                     const double *Z, int M, double scale, double scale_lap, double *out,
+                                     hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(stokes_far_targets_kernel, dim3(int((n + 255) / 256)), dim3(256), 0, s, n, trg, perm, F, Z, M,
-                       scale, out);
+    const dim3 g(int((n + 255) / 256)), b(256);
+    if (rpy)
+        hipLaunchKernelGGL(stokes_far_targets_kernel<true>, g, b, 0, s, n, trg, perm, F, Z, M, scale, scale_lap, out);
+    else
+        hipLaunchKernelGGL(stokes_far_targets_kernel<false>, g, b, 0, s, n, trg, perm, F, Z, M, scale, scale_lap, out);
     return hipGetLastError();
 }
 
-hipError_t launch_force_partials(int64_t n, const double *f, int nblocks, double *part, hipStream_t s) {
-    hipLaunchKernelGGL(force_partials_kernel, dim3(nblocks), dim3(256), 0, s, n, f, part);
+hipError_t launch_force_partials(int64_t n, const double *f, int stride, int nblocks, double *part, hipStream_t s) {
+    hipLaunchKernelGGL(force_partials_kernel, dim3(nblocks), dim3(256), 0, s, n, f, stride, part);
     return hipGetLastError();
 }
 

@@ -5,13 +5,15 @@
   through the root operator;
 * the FMM at p = 8 on uniform and clustered points, and at p = 10;
 * the translation test (moving all points together changes nothing);
-* a non-zero net force is rejected.
+* a non-zero net force is rejected;
+* RPY (u and lap u) on the same path: the root's check-surface flow takes
+  the (b^2/6) lap G term, the targets the far images' lap u.
 """
 import numpy as np
 import pytest
 import torch
 
-from oracle.stokes_periodic import stokeslet_periodic
+from oracle.stokes_periodic import rpy_periodic, stokeslet_periodic
 from paper_2010_15155_amd import FMM, StkfmmError, workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -90,3 +92,33 @@ def test_rejects_net_force(fmm):
     with pytest.raises(StkfmmError) as ei:
         fmm.run(cu(f + np.array([0.0, 1e-3, 0.0])))
     assert ei.value.status == "E_DOMAIN"
+
+
+def _rpy(n, seed, clustered=False):
+    x, f = _problem(n, seed, clustered)
+    b = np.random.default_rng(seed + 100).uniform(0.002, 0.005, n)
+    return x, np.concatenate([f, b[:, None]], 1)
+
+
+@pytest.mark.parametrize("n,cap,p,tol_u,tol_lap", [(600, 1000, 8, 1e-5, 2e-6), (8192, 64, 8, 1e-5, 2e-6),
+                                                   (8192, 64, 10, 5e-6, 2e-6)])
+def test_rpy(fmm, n, cap, p, tol_u, tol_lap):
+    x, fb = _rpy(n, 11)
+    print("periodic RPY", n, "points, p", p, flush=True)
+    out = fmm.evaluate("RPY", sl_xyz=cu(x), sl_val=cu(fb), trg_xyz=cu(x), p=p, leaf_cap=cap,
+                       bc="PXYZ").cpu().numpy()
+    idx = W.sample_indices(len(x), min(n, 300), 5)
+    ref = rpy_periodic(x, fb, x[idx])
+    e_u, e_lap = rel(out[idx, :3], ref[:, :3]), rel(out[idx, 3:], ref[:, 3:])
+    print("  rel L2 u", e_u, "lap u", e_lap, flush=True)
+    assert e_u < tol_u and e_lap < tol_lap
+
+
+def test_rpy_rejects_net_force(fmm):
+    x, fb = _rpy(2000, 12)
+    fb[:, 0] += 1e-3
+    fmm.set_points("RPY", cu(x), None, cu(x), p=6, leaf_cap=100, bc="PXYZ")
+    with pytest.raises(StkfmmError) as ei:
+        fmm.run(cu(fb))
+    assert ei.value.status == "E_DOMAIN"
+

@@ -65,3 +65,44 @@ def test_divergence_free():
         div += (stokeslet_periodic(y, f, x + e)[:, k] - stokeslet_periodic(y, f, x - e)[:, k]) / (2 * h)
     grad_scale = np.abs(stokeslet_periodic(y, f, x)).max() / 0.05
     assert np.abs(div).max() < 1e-6 * grad_scale
+
+
+def test_laplacian_split_parameter_independence():
+    from oracle.stokes_periodic import stokes_lap_periodic
+    rng, y, f = _problem(40, 7)
+    x = np.concatenate([rng.random((20, 3)), y[:5]])
+    w = rng.uniform(0.5, 2.0, len(y))
+    a = [stokes_lap_periodic(y, f, w, x, xi=xi) for xi in (3.0, 5.0, 8.0)]
+    scale = np.abs(a[0]).max()
+    assert np.abs(a[1] - a[0]).max() < 1e-13 * scale
+    assert np.abs(a[2] - a[0]).max() < 1e-13 * scale
+
+
+def test_laplacian_is_the_laplacian_of_the_flow():
+    # Richardson-extrapolated central second differences of the periodic
+    # Stokeslet sum, at targets away from the sources
+    from oracle.stokes_periodic import stokes_lap_periodic
+    rng, y, f = _problem(30, 8)
+    x = rng.random((40, 3))
+    x = x[np.min(np.linalg.norm(((x[:, None] - y[None]) + 0.5) % 1.0 - 0.5, axis=2), axis=1) > 0.1][:6]
+
+    def fd(h):
+        lap = -6.0 * stokeslet_periodic(y, f, x)
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = h
+            lap += stokeslet_periodic(y, f, x + e) + stokeslet_periodic(y, f, x - e)
+        return lap / h ** 2
+
+    lap = (4.0 * fd(1e-3) - fd(2e-3)) / 3.0
+    ref = stokes_lap_periodic(y, f, np.ones(len(y)), x)
+    assert np.abs(lap - ref).max() < 1e-5 * np.abs(ref).max()
+
+
+def test_rpy_without_radii_is_the_stokeslet():
+    from oracle.stokes_periodic import rpy_periodic, stokes_lap_periodic
+    rng, y, f = _problem(30, 9)
+    x = np.concatenate([rng.random((10, 3)), y[:4]])
+    out = rpy_periodic(y, np.concatenate([f, np.zeros((len(f), 1))], 1), x)
+    assert np.allclose(out[:, :3], stokeslet_periodic(y, f, x), rtol=0, atol=1e-14 * np.abs(out[:, :3]).max())
+    assert np.allclose(out[:, 3:], stokes_lap_periodic(y, f, np.ones(len(y)), x), rtol=0, atol=0)
