@@ -122,3 +122,13 @@ def test_rpy_rejects_net_force(fmm):
         fmm.run(cu(fb))
     assert ei.value.status == "E_DOMAIN"
 
+
+def test_separate_targets(fmm):
+    x, f = _problem(4096, 13)
+    t = np.random.default_rng(14).uniform(-0.3, 1.3, (700, 3))   # wrapped by the plan
+    out = fmm.evaluate("Stokeslet", sl_xyz=cu(x), sl_val=cu(f), trg_xyz=cu(t), p=8, leaf_cap=64,
+                       bc="PXYZ").cpu().numpy()
+    e = rel(out, stokeslet_periodic(x, f, t))
+    print("periodic Stokeslet, separate targets", e, flush=True)
+    assert e < 1e-5
+
