@@ -201,8 +201,23 @@ def periodic_stokeslet(FMM, torch, n, args, p=8, cap=500, kernel="Stokeslet"):
 
 def tree_build(FMM, x):
     """Plan time (stkfmm_set_points: octree, lists and plan arrays; operators
-    cached) with the octree and lists built by the GPU kernels or on the host."""
+    cached) with the octree and lists built by the GPU kernels or on the host,
+    at fixed leaf capacities and for the learned plan (two trees, the leaf
+    features and the network)."""
+    from paper_2010_15155_amd.predictor import load_weights
     out = {}
+    row = {}
+    for how in ("gpu", "host"):
+        f = FMM()
+        f.set_option("tree", how)
+        f.set_predictor(load_weights())
+        ts = []
+        for _ in range(4):
+            f.set_points("Stokeslet", x, None, x, p=0, leaf_cap=0)
+            ts.append(f.timings()["t_tree_ms"])
+        row[how + "_ms"] = float(np.median(ts[1:]))
+        f.close()
+    out["learned"] = row
     for cap in (2000, 500):
         row = {}
         for how in ("gpu", "host"):
