@@ -45,6 +45,8 @@ def lib():
                                                   ctypes.c_double, _dp]
         _lib.oracle_stokes_lap_ewald_real.argtypes = [_i64, _dp, _dp, _dp, _i64, _dp, ctypes.c_double,
                                                       ctypes.c_double, ctypes.c_double, _dp]
+        _lib.oracle_stokes_dl_ewald_real.argtypes = [_i64, _dp, _dp, _i64, _dp, ctypes.c_double, ctypes.c_double,
+                                                     ctypes.c_double, _dp]
     return _lib
 
 

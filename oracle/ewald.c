@@ -320,3 +320,54 @@ void oracle_stokes_lap_ewald_real(int64_t ns, const double *ys, const double *f,
     }
 }
 
+/*
+ * Real-space part of the triply periodic double layer grad G : D^s (the
+ * Stokeslet's gradient contracted with the symmetric part of D, Hasimoto
+ * split as above): with A = erfc(xi r)/r - c e, B = (erfc(xi r)/r + c e)/r^2
+ * (8 pi G_R = A I + B r r^T),
+ *   8 pi (grad G_R : D)_i = (A'/r + B) (D r)_i + (B'/r (r.D.r) + B tr D) r_i,
+ *   A'/r + B = 2 c xi^2 e,  B'/r = -3 erfc(xi r)/r^5 - 3 c e/r^4 - 2 c xi^2 e/r^2.
+ * The smooth part is odd: no self term.  D [ns][9] row-major; out [nt][3]
+ * overwritten.
+ */
+void oracle_stokes_dl_ewald_real(int64_t ns, const double *ys, const double *D, int64_t nt, const double *xs,
+                                 double L, double xi, double rc, double *out)
+{
+    const double c = 2.0 * xi / sqrt(PI);
+    const int nimg = (int)floor(rc / L + 0.5);
+    const double x2 = xi * xi;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < nt; ++t) {
+        double u[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < ns; ++j) {
+            double d[3], S[9];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) S[3 * a + b] = 0.5 * (D[9 * j + 3 * a + b] + D[9 * j + 3 * b + a]);
+            const double tr = S[0] + S[4] + S[8];
+            for (int k = 0; k < 3; ++k) {
+                d[k] = xs[3 * t + k] - ys[3 * j + k];
+                d[k] -= L * nearbyint(d[k] / L);
+            }
+            for (int a = -nimg; a <= nimg; ++a)
+                for (int b = -nimg; b <= nimg; ++b)
+                    for (int e3 = -nimg; e3 <= nimg; ++e3) {
+                        const double r[3] = {d[0] - L * a, d[1] - L * b, d[2] - L * e3};
+                        const double rr = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                        if (rr >= rc * rc || rr == 0.0) continue;
+                        const double rho = sqrt(rr), e = exp(-x2 * rr), ec = erfc(xi * rho);
+                        const double c1 = 2.0 * c * x2 * e;
+                        const double bpr = -3.0 * ec / (rr * rr * rho) - 3.0 * c * e / (rr * rr) - 2.0 * c * x2 * e / rr;
+                        const double B = (ec / rho + c * e) / rr;
+                        double Dr[3], rDr = 0.0;
+                        for (int k = 0; k < 3; ++k) {
+                            Dr[k] = S[3 * k] * r[0] + S[3 * k + 1] * r[1] + S[3 * k + 2] * r[2];
+                            rDr += r[k] * Dr[k];
+                        }
+                        const double c2 = bpr * rDr + B * tr;
+                        for (int k = 0; k < 3; ++k) u[k] += c1 * Dr[k] + c2 * r[k];
+                    }
+        }
+        for (int k = 0; k < 3; ++k) out[3 * t + k] = u[k] / (8.0 * PI);
+    }
+}
+

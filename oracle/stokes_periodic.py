@@ -119,3 +119,63 @@ def rpy_periodic(src, fb, trg, L=1.0, xi=None, tol=1e-15):
     lap = stokes_lap_periodic(src, f, np.ones(len(f)), trg, L, xi, tol)
     return np.concatenate([u, lap], axis=1)
 
+
+def stokes_dl_periodic(src, D, trg, L=1.0, xi=None, tol=1e-15):
+    """Periodic sum of grad G : D^s [m, 3], (grad G : D)_i = sum_jk d_k G_ij D_jk,
+    D [n, 9] row-major (its symmetric part acts).  Reciprocal amplitude
+    i phi(k)/k^2 (I - k k^T/k^2) D^s k; real part in ewald.c; no self term
+    (the smooth part is odd)."""
+    y = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3)
+    D = np.ascontiguousarray(D, dtype=np.float64).reshape(-1, 9)
+    x = np.ascontiguousarray(trg, dtype=np.float64).reshape(-1, 3)
+    xi, rc, nmax = parameters(L, xi, tol)
+    nmax += 1                      # phi(k)/k decays more slowly than phi(k)/k^2
+    u = np.zeros((len(x), 3))
+    if len(y) == 0 or len(x) == 0:
+        return u
+    lib().oracle_stokes_dl_ewald_real(len(y), _p(y), _p(D), len(x), _p(x), float(L), float(xi), float(rc), _p(u))
+    m = np.arange(-nmax, nmax + 1)
+    K = np.stack(np.meshgrid(m, m, m, indexing="ij"), axis=-1).reshape(-1, 3).astype(np.float64)
+    K = K[np.any(K != 0, axis=1)] * (2.0 * PI / L)
+    k2 = np.sum(K * K, axis=1)
+    phi = (1.0 + k2 / (4.0 * xi * xi)) * np.exp(-k2 / (4.0 * xi * xi))
+    Ds = 0.5 * (D + D.reshape(-1, 3, 3).transpose(0, 2, 1).reshape(-1, 9))
+    S = np.zeros((len(K), 3), dtype=np.complex128)     # sum_j (D_j k) e^{-i k.y_j}
+    for j0 in range(0, len(y), 512):
+        E = np.exp(-1j * (K @ y[j0:j0 + 512].T))                          # [nk, nb]
+        Dk = np.einsum("bij,kj->kbi", Ds[j0:j0 + 512].reshape(-1, 3, 3), K)  # [nk, nb, 3]
+        S += np.einsum("kb,kbi->ki", E, Dk)
+    PS = S - K * (np.sum(K * S, axis=1) / k2)[:, None]
+    Wk = 1j * (phi / k2)[:, None] * PS / L ** 3
+    for i0 in range(0, len(x), 1024):
+        u[i0:i0 + 1024] += np.real(np.exp(1j * (x[i0:i0 + 1024] @ K.T)) @ Wk)
+    return u
+
+
+def pvel_periodic(sl, fq, dl, D, trg, L=1.0, tol=1e-13):
+    """Periodic PVel [m, 4] = (p, u) of single-layer sources (f, q) [n, 4] at sl
+    and double-layer sources D [n, 9] at dl (Sec. II.B's pressure-velocity
+    kernels): sum f, sum q and sum tr D must vanish.  Written with the Laplace
+    Ewald sums (``ewald``) and the periodic Stokeslet and its gradient:
+      u = G f + (q/2) grad L + grad G : D^s + (tr D/2) grad L,
+      p = -sum_j d_j (L f_j) - D^s : grad grad L  (L = 1/(4 pi r))."""
+    from . import ewald
+    x = np.ascontiguousarray(trg, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros((len(x), 4))
+    if sl is not None and len(sl):
+        sl = np.ascontiguousarray(sl, dtype=np.float64).reshape(-1, 3)
+        fq = np.ascontiguousarray(fq, dtype=np.float64).reshape(-1, 4)
+        out[:, 1:] += stokeslet_periodic(sl, fq[:, :3], x, L)
+        out[:, 1:] += ewald.laplace_periodic(sl, 0.5 * fq[:, 3], None, x, L, tol=tol)[:, 1:]
+        for j in range(3):
+            out[:, 0] -= ewald.laplace_periodic(sl, fq[:, j], None, x, L, tol=tol)[:, 1 + j]
+    if dl is not None and len(dl):
+        dl = np.ascontiguousarray(dl, dtype=np.float64).reshape(-1, 3)
+        D = np.ascontiguousarray(D, dtype=np.float64).reshape(-1, 9)
+        tr = D[:, 0] + D[:, 4] + D[:, 8]
+        out[:, 1:] += stokes_dl_periodic(dl, D, x, L)
+        out[:, 1:] += ewald.laplace_periodic(dl, 0.5 * tr, None, x, L, tol=tol)[:, 1:]
+        Ds = 0.5 * (D + D.reshape(-1, 3, 3).transpose(0, 2, 1).reshape(-1, 9))
+        out[:, 0] += ewald.laplace_periodic(dl, None, None, x, L, tol=tol, Q=-Ds)[:, 0]
+    return out
+

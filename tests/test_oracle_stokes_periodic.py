@@ -106,3 +106,74 @@ def test_rpy_without_radii_is_the_stokeslet():
     out = rpy_periodic(y, np.concatenate([f, np.zeros((len(f), 1))], 1), x)
     assert np.allclose(out[:, :3], stokeslet_periodic(y, f, x), rtol=0, atol=1e-14 * np.abs(out[:, :3]).max())
     assert np.allclose(out[:, 3:], stokes_lap_periodic(y, f, np.ones(len(y)), x), rtol=0, atol=0)
+
+
+def _dl_problem(seed):
+    rng = np.random.default_rng(seed)
+    sl = rng.random((15, 3))
+    fq = rng.standard_normal((15, 4))
+    fq -= fq.mean(axis=0)                       # zero net force and net source
+    dl = rng.random((10, 3))
+    D = rng.standard_normal((10, 9))
+    D[:, [0, 4, 8]] -= (D[:, 0] + D[:, 4] + D[:, 8]).mean() / 3.0   # zero net tr D
+    return rng, sl, fq, dl, D
+
+
+def test_double_layer_split_parameter_independence():
+    from oracle.stokes_periodic import stokes_dl_periodic
+    rng, _, _, dl, D = _dl_problem(21)
+    x = np.concatenate([rng.random((10, 3)), dl[:3]])
+    a = [stokes_dl_periodic(dl, D, x, xi=xi) for xi in (3.0, 5.0, 8.0)]
+    scale = np.abs(a[0]).max()
+    assert np.abs(a[1] - a[0]).max() < 1e-13 * scale
+    assert np.abs(a[2] - a[0]).max() < 1e-13 * scale
+
+
+def test_double_layer_is_the_limit_of_force_pairs():
+    # grad G : D^s = sum_k d_k G D^s_{.k}: pairs -D^s_{.k} at y + h e_k and
+    # +D^s_{.k} at y - h e_k of the (pinned) periodic Stokeslet, over 2h
+    from oracle.stokes_periodic import stokes_dl_periodic
+    rng, _, _, y, D = _dl_problem(22)
+    Ds = 0.5 * (D + D.reshape(-1, 3, 3).transpose(0, 2, 1).reshape(-1, 9))
+    x = rng.random((5, 3))
+    h = 1e-5
+    u = np.zeros((5, 3))
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        F = np.concatenate([-Ds.reshape(-1, 3, 3)[:, :, k], Ds.reshape(-1, 3, 3)[:, :, k]])
+        u += stokeslet_periodic(np.concatenate([y + e, y - e]), F, x) / (2 * h)
+    ref = stokes_dl_periodic(y, D, x)
+    assert np.abs(u - ref).max() < 1e-6 * np.abs(ref).max()
+
+
+def test_pvel_next_to_sources():
+    from oracle.stokes_periodic import pvel_periodic
+    rng, sl, fq, dl, D = _dl_problem(23)
+    e = np.array([0.6, 0.0, 0.8])
+    r = 1e-5
+    Dm = 0.5 * (D[0].reshape(3, 3) + D[0].reshape(3, 3).T)
+    out = pvel_periodic(sl, fq, dl, D, (dl[0] + r * e)[None])[0]
+    want_u = -(3.0 / (8 * np.pi)) * e * (e @ Dm @ e)
+    want_p = (-3.0 * (e @ Dm @ e) + np.trace(Dm)) / (4 * np.pi)
+    assert np.abs(out[1:] * r ** 2 - want_u).max() < 1e-4 * np.abs(want_u).max()
+    assert abs(out[0] * r ** 3 - want_p) < 1e-4 * abs(want_p)
+    out = pvel_periodic(sl, fq, dl, D, (sl[0] + r * e)[None])[0]
+    f, q = fq[0, :3], fq[0, 3]
+    assert abs(out[0] * r ** 2 - (e @ f) / (4 * np.pi)) < 1e-3 * abs(e @ f) / (4 * np.pi)
+    want = (f + e * (e @ f) - q * e / r) / (8 * np.pi)     # G f / r and the source term
+    assert np.abs(out[1:] * r - want).max() < 1e-3 * np.abs(want).max()
+
+
+def test_pvel_divergence_free():
+    from oracle.stokes_periodic import pvel_periodic
+    rng, sl, fq, dl, D = _dl_problem(24)
+    x = rng.random((4, 3))
+    h = 1e-4
+    div = np.zeros(len(x))
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = h
+        div += (pvel_periodic(sl, fq, dl, D, x + e)[:, 1 + k] - pvel_periodic(sl, fq, dl, D, x - e)[:, 1 + k]) / (2 * h)
+    grad_scale = np.abs(pvel_periodic(sl, fq, dl, D, x)[:, 1:]).max() / 0.05
+    assert np.abs(div).max() < 1e-6 * grad_scale
