@@ -21,6 +21,26 @@ MADELUNG_NACL = 1.747564594633182  # rock-salt structure, nearest-neighbour unit
 RNG = np.random.default_rng(777)
 
 
+@pytest.fixture(autouse=True)
+def _fresh_rng():
+    # every test draws the same sequence, whatever runs before it
+    global RNG
+    RNG = np.random.default_rng(777)
+
+
+def _away(y, k, dmin=0.15, L=1.0):
+    """k points at least dmin from every point of y and its periodic images
+    (finite differences and limits of point pairs need the distance)."""
+    out = []
+    while len(out) < k:
+        c = RNG.random(3) * L
+        d = c - y
+        d -= L * np.round(d / L)
+        if np.min(np.linalg.norm(d, axis=1)) >= dmin:
+            out.append(c)
+    return np.array(out)
+
+
 def _cell(n=12, L=1.0):
     y = RNG.random((n, 3)) * L
     q = RNG.standard_normal(n)
@@ -71,7 +91,7 @@ def test_translation_invariance():
 
 def test_gradient_is_fd():
     y, q, d = _cell()
-    x = RNG.random((4, 3))
+    x = _away(y, 4)
     S = ewald.structure(y, q, d, 1.0, ewald.parameters(1.0)[2])
     fun = lambda xx: ewald.laplace_periodic(y, q, d, xx, 1.0, S=S)[:, :1]
     g = _fd.grad(fun, x, h=1e-3)[:, 0, :]
@@ -127,7 +147,7 @@ def test_rejects_net_charge():
 
 def test_hessian_is_fd_of_gradient_and_harmonic():
     y, q, d = _cell()
-    x = RNG.random((4, 3))
+    x = _away(y, 4)
     S = ewald.structure(y, q, d, 1.0, ewald.parameters(1.0)[2])
     out = ewald.laplace_periodic(y, q, d, x, 1.0, S=S, hess=True)
     assert np.allclose(out[:, :4], ewald.laplace_periodic(y, q, d, x, 1.0, S=S), rtol=1e-14, atol=1e-14)
@@ -163,8 +183,9 @@ def test_quadrupole_xi_independence():
 
 def test_quadrupole_is_limit_of_dipole_pairs():
     # Q_ab d_a d_b L = d/dy_a d/dy_b L: dipoles (Q_ab/eps) e_b at y +- eps e_a / 2
-    y, Q = _quads(2)
+    _, Q = _quads(2)
     x = np.array([[0.61, 0.12, 0.84], [0.07, 0.33, 0.21], [0.93, 0.95, 0.52]])
+    y = _away(x, 2)
     got = ewald.laplace_periodic(y, None, None, x, 1.0, hess=True, Q=Q)
     res = []
     for eps in (2e-3, 4e-3):
@@ -182,7 +203,7 @@ def test_quadrupole_is_limit_of_dipole_pairs():
 
 def test_quadrupole_gradient_and_hessian_are_fd():
     y, Q = _quads()
-    x = RNG.random((4, 3))
+    x = _away(y, 4)
     S = ewald.structure(y, None, None, 1.0, ewald.parameters(1.0)[2], Q)
     f = lambda xx: ewald.laplace_periodic(y, None, None, xx, 1.0, S=S, Q=Q)
     out = ewald.laplace_periodic(y, None, None, x, 1.0, S=S, hess=True, Q=Q)
