@@ -75,7 +75,8 @@ def parse():
     return args
 
 
-FIELDS = {"Stokeslet": [("u", 0, 3)], "StokesRegVel": [("u", 0, 3)], "RPY": [("u", 0, 3), ("lap_u", 3, 6)]}
+FIELDS = {"Stokeslet": [("u", 0, 3)], "StokesRegVel": [("u", 0, 3)], "RPY": [("u", 0, 3), ("lap_u", 3, 6)],
+          "PVel": [("p", 0, 1), ("u", 1, 4)]}
 
 
 def wall_direct(fmm, torch, y, fb, xt):
@@ -164,39 +165,63 @@ def measure(fmm, torch, W, kernel, x, val, p, cap, args, precision="fp32", bc="o
 
 
 def periodic_stokeslet(FMM, torch, n, args, p=8, cap=500, kernel="Stokeslet"):
-    """Triply periodic Stokeslet (or RPY, radii U[0.002, 0.005]) on n uniform
-    points (zero net force): time per pass, and as accuracy the translation
-    test, the relative difference between the pass and the pass on all points
-    moved together (a sampled Ewald reference at this size is beyond the CPU
-    oracle's budget)."""
+    """Triply periodic Stokeslet (or RPY, radii U[0.002, 0.005]; or PVel, half
+    the points single-layer (f, q), half double-layer D, every point a
+    target) on n uniform points (zero net force, flux and tr D): time per
+    pass, and as accuracy the translation test, the relative difference
+    between the pass and the pass on all points moved together (PVel's
+    pressure up to a constant; a sampled Ewald reference at this size is
+    beyond the CPU oracle's budget)."""
     rng = np.random.default_rng(501)
     x = rng.random((n, 3))
-    f = rng.standard_normal((n, 3))
+    ns = n // 2 if kernel == "PVel" else n
+    f = rng.standard_normal((ns, 3))
     f -= f.mean(axis=0)
+    dl = dd = None
     if kernel == "RPY":
         f = np.concatenate([f, rng.uniform(0.002, 0.005, (n, 1))], 1)
+    elif kernel == "PVel":
+        q = rng.standard_normal(ns)
+        f = np.concatenate([f, (q - q.mean())[:, None]], 1)
+        D = rng.standard_normal((n - ns, 9))
+        D[:, [0, 4, 8]] -= (D[:, 0] + D[:, 4] + D[:, 8]).mean() / 3.0
+        dd = torch.from_numpy(D).cuda()
     fmm = FMM()
-    xd, fd = torch.from_numpy(x).cuda(), torch.from_numpy(f).cuda()
-    fmm.set_points(kernel, xd, None, xd, p=p, leaf_cap=cap, bc="PXYZ")
+
+    def plan(shift):
+        xs = torch.from_numpy(np.mod(x + shift, 1.0)).cuda()
+        sl = xs[:ns]
+        dl = xs[ns:] if kernel == "PVel" else None
+        fmm.set_points(kernel, sl, dl, xs, p=p, leaf_cap=cap, bc="PXYZ")
+
+    fd = torch.from_numpy(f).cuda()
+    plan(np.zeros(3))
     for _ in range(args.warmup):
-        fmm.run(fd)
+        fmm.run(fd, dd)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        out = fmm.run(fd)
+        out = fmm.run(fd, dd)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps
     out = out.clone()
     stages = fmm.timings()["stages_ms"]
-    xs = torch.from_numpy(np.mod(x + np.array([0.31, 0.57, 0.89]), 1.0)).cuda()
-    fmm.set_points(kernel, xs, None, xs, p=p, leaf_cap=cap, bc="PXYZ")
-    out2 = fmm.run(fd)
-    diff = {name: float(torch.linalg.norm(out2[:, a:b] - out[:, a:b]) / torch.linalg.norm(out[:, a:b]))
-            for name, a, b in FIELDS[kernel]}
+    plan(np.array([0.31, 0.57, 0.89]))
+    out2 = fmm.run(fd, dd)
+    diff = {}
+    for name, a, b in FIELDS[kernel]:
+        d = out2[:, a:b] - out[:, a:b]
+        ref = out[:, a:b]
+        if kernel == "PVel" and name == "p":
+            d, ref = d - d.mean(), ref - ref.mean()
+        diff[name] = float(torch.linalg.norm(d) / torch.linalg.norm(ref))
     fmm.close()
+    what = {"PVel": "%d single-layer and %d double-layer sources, every point a target" % (ns, n - ns)}
     return {"ms_per_step": wall * 1e3, "targets_per_s": n / wall, "p": p, "leaf_cap": cap,
             "translation_rel_diff": diff, "stages_ms": stages,
-            "workload": "%d uniform points in the unit cube, %s, PXYZ, sum f = 0" % (n, kernel)}
+            "workload": "%d uniform points in the unit cube, %s, PXYZ, zero net force%s%s" % (
+                n, kernel, ", flux and tr D" if kernel == "PVel" else "",
+                "; " + what[kernel] if kernel in what else "")}
 
 
 def tree_build(FMM, x):
@@ -252,7 +277,8 @@ def main():
         print(json.dumps({"plan_ms": tree_build(FMM, x)}), flush=True)
         return
     if args.only_periodic:
-        print(json.dumps({"stokeslet_pxyz_p8": periodic_stokeslet(FMM, torch, args.n, args)}), flush=True)
+        print(json.dumps({k.lower() + "_pxyz_p8": periodic_stokeslet(FMM, torch, args.n, args, kernel=k)
+                          for k in ("Stokeslet", "RPY", "PVel")}), flush=True)
         return
     fmm = FMM()
     fmm.set_predictor(load_weights())
@@ -303,6 +329,7 @@ def main():
             "rpy_wall_p10": measure(fmm, torch, W, "RPY", x, fb, 10, 1000, args, bc="wall"),
             "stokeslet_pxyz_p8": periodic_stokeslet(FMM, torch, n, args),
             "rpy_pxyz_p8": periodic_stokeslet(FMM, torch, n, args, kernel="RPY"),
+            "pvel_pxyz_p8": periodic_stokeslet(FMM, torch, n, args, kernel="PVel"),
         }
         line["plan_ms"] = tree_build(FMM, x)
     fmm.close()

@@ -1036,9 +1036,10 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     if (bc != STKFMM_BC_OPEN && bc != STKFMM_BC_PXYZ)
         return fail(c, STKFMM_E_UNSUPPORTED, "only open, triply periodic and wall boundaries are implemented");
     if (bc == STKFMM_BC_PXYZ && kernel != STKFMM_LAP_PGRAD && kernel != STKFMM_LAP_PGRADGRAD &&
-        kernel != STKFMM_LAP_QPGRADGRAD && kernel != STKFMM_STOKESLET && kernel != STKFMM_RPY)
+        kernel != STKFMM_LAP_QPGRADGRAD && kernel != STKFMM_STOKESLET && kernel != STKFMM_RPY &&
+        kernel != STKFMM_PVEL)
         return fail(c, STKFMM_E_UNSUPPORTED,
-                    "triply periodic boundary is implemented for the Laplace kernels, STOKESLET and RPY");
+                    "triply periodic boundary is implemented for the Laplace kernels, STOKESLET, RPY and PVEL");
     const bool periodic = bc == STKFMM_BC_PXYZ;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(c, hipSetDevice(c->device));
@@ -1148,12 +1149,13 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     stkfmm_status st = get_ops(c, p, periodic, m2l_tol, &ops);
     if (st != STKFMM_OK) return st;
     c->stk = nullptr;
-    if (periodic && (kernel == STKFMM_STOKESLET || kernel == STKFMM_RPY)) {
+    if (periodic && (kernel == STKFMM_STOKESLET || kernel == STKFMM_RPY || kernel == STKFMM_PVEL)) {
         st = get_periodic_stokes(c, &c->stk);
         if (st != STKFMM_OK) return st;
         const int Mf = c->stk->M;
-        HIP_TRY(c, c->stk_F.ensure(size_t(6) * Mf * sizeof(double)));
-        HIP_TRY(c, c->stk_part.ensure(size_t(std::max(stokes_root_chunks(n_sl), 1)) * 3 * Mf * sizeof(double)));
+        const int nch = stokes_root_chunks(n_sl) + stokes_root_chunks(n_dl);
+        HIP_TRY(c, c->stk_F.ensure((size_t(6) * Mf + 3) * sizeof(double)));
+        HIP_TRY(c, c->stk_part.ensure(size_t(std::max(nch, 1)) * (3 * Mf + 3) * sizeof(double)));
     }
     c->ops = ops;
     c->kernel = kernel;
@@ -1608,9 +1610,9 @@ __global__ void pack_values_kernel(int64_t n, const double *__restrict__ val, co
             o[6] = float(v[0] * inv_len); o[7] = float(v[1] * inv_len); o[8] = float(v[2] * inv_len);
             break;
         }
-        case 4: {
+        case 4: {   // force f and flux q / L (its flow q r/r^3 falls one power faster than f/r)
             const double *v = val + 4 * j;
-            o[6] = float(v[0]); o[7] = float(v[1]); o[8] = float(v[2]); o[9] = float(v[3]);
+            o[6] = float(v[0]); o[7] = float(v[1]); o[8] = float(v[2]); o[9] = float(v[3] * inv_len);
             break;
         }
         case 5: {
@@ -1699,23 +1701,45 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
     const int nc = ki.ncomp;
     const bool periodic = c->bc == STKFMM_BC_PXYZ;
     if (c->n_trg == 0) return STKFMM_OK;
-    const bool pstokes = periodic && (c->kernel == kStokeslet || c->kernel == kRPY);
-    if (pstokes && c->n_sl > 0) {
-        // zero net force (the Ewald convention drops the k = 0 mode)
+    const bool pstokes = periodic && (c->kernel == kStokeslet || c->kernel == kRPY || c->kernel == kPVel);
+    // sums of the first ncomp values of each source and of their absolute
+    // values (one reduction on the device, a fixed order on the host)
+    auto value_sums = [&](int64_t n, const double *v, int stride, int ncomp, double *sum,
+                          double *abs_sum) -> stkfmm_status {
         const int nbk = 256;
-        HIP_TRY(c, launch_force_partials(c->n_sl, sl_val, ki.k_sl, nbk, c->partial.as<double>(), s));
-        std::vector<double> hp(4 * nbk);
+        HIP_TRY(c, launch_value_partials(n, v, stride, ncomp, nbk, c->partial.as<double>(), s));
+        std::vector<double> hp(size_t(ncomp + 1) * nbk);
         HIP_TRY(c, hipMemcpyAsync(hp.data(), c->partial.p, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(c, hipStreamSynchronize(s));
-        double f[3] = {0, 0, 0}, fa = 0;
+        for (int k = 0; k <= ncomp; ++k) (k < ncomp ? sum[k] : *abs_sum) = 0.0;
         for (int i = 0; i < nbk; ++i) {
-            for (int k = 0; k < 3; ++k) f[k] += hp[4 * i + k];
-            fa += hp[4 * i + 3];
+            for (int k = 0; k < ncomp; ++k) sum[k] += hp[size_t(ncomp + 1) * i + k];
+            *abs_sum += hp[size_t(ncomp + 1) * i + ncomp];
         }
+        return STKFMM_OK;
+    };
+    if (pstokes && c->n_sl > 0) {
+        // zero net force (the Ewald convention drops the k = 0 mode) and,
+        // for PVel, zero net flux q
+        const int ncomp = c->kernel == kPVel ? 4 : 3;
+        double f[4], fa;
+        stkfmm_status st = value_sums(c->n_sl, sl_val, ki.k_sl, ncomp, f, &fa);
+        if (st != STKFMM_OK) return st;
         for (int k = 0; k < 3; ++k)
             if (std::fabs(f[k]) > 1e-9 * std::max(1.0, fa))
                 return fail(c, STKFMM_E_DOMAIN, "periodic Stokes needs zero net force");
-    } else if (periodic && c->n_sl > 0 && c->kernel != kLapQPGradGrad) {
+        if (ncomp == 4 && std::fabs(f[3]) > 1e-9 * std::max(1.0, fa))
+            return fail(c, STKFMM_E_DOMAIN, "periodic PVel needs zero net flux (sum of q)");
+    }
+    if (pstokes && c->n_dl > 0) {
+        // the trace of D carries a flux (tr D r/r^3): its sum must vanish
+        double d[9], da;
+        stkfmm_status st = value_sums(c->n_dl, dl_val, ki.k_dl, 9, d, &da);
+        if (st != STKFMM_OK) return st;
+        if (std::fabs(d[0] + d[4] + d[8]) > 1e-9 * std::max(1.0, da))
+            return fail(c, STKFMM_E_DOMAIN, "periodic PVel needs a zero sum of tr D over the double layer");
+    }
+    if (!pstokes && periodic && c->n_sl > 0 && c->kernel != kLapQPGradGrad) {
         // zero net charge (tin-foil Ewald convention needs a neutral cell;
         // quadrupoles carry none)
         const int nbk = 256;
@@ -1832,11 +1856,20 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 4 M2L
         HIP_TRY(c, s2c(c->s2l, kAlphaIn, dnchk, 1));
         if (periodic && nc == 1) HIP_TRY(c, launch_periodic(o.tm2l.as<double>(), updens, dnchk, o.M, o.Mp, nc, 0, s));
-        if (pstokes)
-            HIP_TRY(c, launch_stokes_far_forces(c->n_sl, c->sl_rec.as<float>(), ki.rec_sl, c->kernel == kRPY,
-                                                c->stk->X.as<double>(),
-                                                c->stk->Q.as<double>(), c->stk->M, c->stk_part.as<double>(),
-                                                c->stk_F.as<double>(), c->stk_F.as<double>() + 3 * c->stk->M, s));
+        if (pstokes) {
+            // the root's flow at its check points: single layer, then double
+            // layer chunks, summed in that order
+            const int M = c->stk->M;
+            const int nch_sl = stokes_root_chunks(c->n_sl), nch_dl = stokes_root_chunks(c->n_dl);
+            double *part = c->stk_part.as<double>();
+            const int kind = c->kernel == kRPY ? 1 : c->kernel == kPVel ? 2 : 0;
+            HIP_TRY(c, launch_stokes_root_check(kind, c->n_sl, c->sl_rec.as<float>(), ki.rec_sl,
+                                                c->stk->X.as<double>(), M, part, s));
+            HIP_TRY(c, launch_stokes_root_check(3, c->n_dl, c->dl_rec.as<float>(), ki.rec_dl,
+                                                c->stk->X.as<double>(), M, part + size_t(nch_sl) * (3 * M + 3), s));
+            HIP_TRY(c, launch_stokes_far_forces(nch_sl + nch_dl, c->stk->Q.as<double>(), M, part,
+                                                c->stk_F.as<double>(), c->stk_F.as<double>() + 3 * M + 3, s));
+        }
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 5 S2L + periodic
         for (int l = c->lmin_dn; l <= t.depth; ++l) {
             const L2LLevel &ll = c->l2l[l];
@@ -1883,12 +1916,17 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         a.map = combine_map(c->kernel, c->box_len);
         a.out = trg_val;
         HIP_TRY(c, launch_combine(c->nchunks, a, s));
-        if (pstokes)
+        if (pstokes) {
+            // far images: u (scale 1/L) and RPY's lap u (1/L^3) or PVel's p (1/L^2)
+            const double L = c->box_len;
+            const int mode = c->kernel == kRPY ? 1 : c->kernel == kPVel ? 2 : 0;
+            const int M = c->stk->M;
+            const double *V = c->stk_F.as<double>();    // check flow [3M], flux moment [3], forces [3M]
             HIP_TRY(c, launch_stokes_far_targets(c->n_trg, c->trg_rec.as<float>(), at<int32_t>(c, c->a_perm_trg),
-                                                 c->kernel == kRPY, c->stk_F.as<double>() + 3 * c->stk->M,
-                                                 c->stk->Z.as<double>(), c->stk->M, 1.0 / c->box_len,
-                                                 1.0 / (c->box_len * c->box_len * c->box_len),
+                                                 mode, V + 3 * M + 3, c->stk->Z.as<double>(), M, 1.0 / L,
+                                                 mode == 1 ? 1.0 / (L * L * L) : 1.0 / (L * L), V + 3 * M,
                                                  trg_val, s));
+        }
     }
     HIP_TRY(c, hipEventRecord(ev[ne++], s));                  // end
     HIP_TRY(c, hipStreamSynchronize(s));

@@ -184,19 +184,26 @@ struct WallAssembleArgs {
 hipError_t launch_wall_positions(int64_t n, const double *y, double zw, double *y2, double *yi, hipStream_t s);
 hipError_t launch_wall_values(const WallValueArgs &a, hipStream_t s);
 hipError_t launch_wall_assemble(const WallAssembleArgs &a, hipStream_t s);
-// Triply periodic Stokeslet (periodic.hip): the root's flow V at its upward
-// check points X (sorted SL records, chunks of 4096 sources, partial sums in
-// part [chunks][3M]), then the far images' forces F = Q V / (8 pi); targets
-// (sorted, unit-box records) add scale * sum_m G(x - Z_m) F_m in user order
-// (RPY: also lap u, scale_lap); per-block sums of f and |f| (4 doubles per
-// block, values `stride` apart).
+// Triply periodic Stokes kernels (periodic.hip): the root's flow at its
+// upward check points X from sorted source records of a kind (0 Stokeslet,
+// 1 RPY, 2 PVel single layer, 3 PVel double layer; chunks of 4096 sources,
+// partial sums part [chunks][3M + 3], the last 3 the flux moment); then
+// V [3M + 3] = the chunks' sum and the far images' forces F = Q V / (8 pi)
+// [3M]; targets (sorted, unit-box records) add their far-image values in
+// user order (mode 0: u, 1: u and lap u, 2: p and u less the flux moment's
+// uniform flow, mom = V + 3M; scale for u, scale2 for lap u or p);
+// per-block sums of the first ncomp values of each source and of their
+// absolute values.
 int stokes_root_chunks(int64_t n);
-hipError_t launch_stokes_far_forces(int64_t n_src, const float *src, int rec, bool rpy, const double *X,
-                                    const double *Q, int M, double *part, double *V, double *F, hipStream_t s);
-hipError_t launch_stokes_far_targets(int64_t n, const float *trg, const int32_t *perm, bool rpy, const double *F,
-                                     const double *Z, int M, double scale, double scale_lap, double *out,
-                                     hipStream_t s);
-hipError_t launch_force_partials(int64_t n, const double *f, int stride, int nblocks, double *part, hipStream_t s);
+hipError_t launch_stokes_root_check(int kind, int64_t n_src, const float *src, int rec, const double *X, int M,
+                                    double *part, hipStream_t s);
+hipError_t launch_stokes_far_forces(int nchunks, const double *Q, int M, const double *part, double *V, double *F,
+                                    hipStream_t s);
+hipError_t launch_stokes_far_targets(int64_t n, const float *trg, const int32_t *perm, int mode, const double *F,
+                                     const double *Z, int M, double scale, double scale2, const double *mom,
+                                     double *out, hipStream_t s);
+hipError_t launch_value_partials(int64_t n, const double *f, int stride, int ncomp, int nblocks, double *part,
+                                 hipStream_t s);
 hipError_t launch_periodic(const double *T, const float *dens, double *chk, int M, int Mp, int nc, int root,
                            hipStream_t s);
 hipError_t launch_l2t(int kernel, int ntasks, const L2TArgs &a, hipStream_t s);

@@ -22,12 +22,24 @@ constexpr int kRootPer = 6;        // check points per thread (M <= 1536)
 // part[chunk][3m + a] = 8 pi x the flow at check point X_m (relative to the
 // root centre) of the chunk's sources (sorted records: hi, lo position in the
 // unit box, f at slots 6..8); FP32 pair sums per LDS tile, FP64 across tiles
-// RPY sources (b^2 at slot 9, unit-box units) add (b^2/6) lap G f.
-template <bool RPY>
+// Source kinds of the check-surface sum (sorted records, unit-box units):
+//   0 Stokeslet  f at slots 6..8:           G f
+//   1 RPY        f, b^2 at 9:              G f + (b^2/6) lap G f
+//   2 PVel SL    f, q at 9:                G f - q r/r^3
+//   3 PVel DL    D^s (xx xy xz yy yz zz) at 6..11:  -3 r (r.D.r)/r^5
+// (all times 8 pi).  Row stride 3M + 3: the last three entries hold the
+// chunk's flux moment sum_j w_j y_j (w = q for kind 2, tr D for kind 3, 0
+// otherwise; y relative to the root centre), which sets the uniform flow
+// that the Stokeslet fit cannot carry (see stokes_far_targets_kernel).
+template <int KIND>
 __global__ __launch_bounds__(256) void stokes_root_check_kernel(int64_t n, const float *__restrict__ src, int rec,
                                                                 const double *__restrict__ X, int M,
                                                                 double *__restrict__ part) {
-    __shared__ float tile[256 * 7];
+    constexpr int NV = KIND == 3 ? 9 : 7;
+    constexpr bool kFlux = KIND == 2 || KIND == 3;
+    __shared__ float tile[256 * NV];
+    __shared__ double mred[kFlux ? 3 * 256 : 1];
+    double mw[3] = {0.0, 0.0, 0.0};
     const int64_t j0 = int64_t(blockIdx.x) * kRootChunk, j1 = min(n, j0 + kRootChunk);
     float x[kRootPer][3];
     double acc[kRootPer][3];
@@ -44,12 +56,18 @@ __global__ __launch_bounds__(256) void stokes_root_check_kernel(int64_t n, const
         __syncthreads();
         if (int(threadIdx.x) < cnt) {
             const float *r = src + (t0 + threadIdx.x) * rec;
-            float *o = tile + 7 * threadIdx.x;
-            for (int k = 0; k < 3; ++k) {
-                o[k] = float((double(r[k]) - 0.5) + double(r[3 + k]));
-                o[3 + k] = r[6 + k];
+            float *o = tile + NV * threadIdx.x;
+            for (int k = 0; k < 3; ++k) o[k] = float((double(r[k]) - 0.5) + double(r[3 + k]));
+            if (kFlux) {
+                const double w = KIND == 2 ? double(r[9]) : double(r[6]) + double(r[9]) + double(r[11]);
+                for (int k = 0; k < 3; ++k) mw[k] += w * double(o[k]);
             }
-            o[6] = RPY ? r[9] * (1.0f / 6.0f) : 0.0f;
+            if (KIND == 3) {
+                for (int k = 0; k < 6; ++k) o[3 + k] = r[6 + k];
+            } else {
+                for (int k = 0; k < 3; ++k) o[3 + k] = r[6 + k];
+                o[6] = KIND == 1 ? r[9] * (1.0f / 6.0f) : KIND == 2 ? r[9] : 0.0f;
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -57,33 +75,57 @@ __global__ __launch_bounds__(256) void stokes_root_check_kernel(int64_t n, const
             if (int(threadIdx.x) + 256 * q >= M) continue;
             float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
             for (int j = 0; j < cnt; ++j) {
-                const float *y = tile + 7 * j;
+                const float *y = tile + NV * j;
                 const float r0 = x[q][0] - y[0], r1 = x[q][1] - y[1], r2 = x[q][2] - y[2];
                 const float ri = __builtin_amdgcn_rsqf(r0 * r0 + r1 * r1 + r2 * r2);
                 const float ri2 = ri * ri, ri3 = ri2 * ri;
-                const float rdf = r0 * y[3] + r1 * y[4] + r2 * y[5];
-                // G f = f/r + r (r.f)/r^3;  (b^2/6) lap G f = (b^2/6) (2 f/r^3 - 6 r (r.f)/r^5)
-                const float cf = RPY ? ri + 2.0f * y[6] * ri3 : ri;
-                const float cr = RPY ? (rdf * ri3) * (1.0f - 6.0f * y[6] * ri2) : rdf * ri3;
-                u0 += y[3] * cf + r0 * cr;
-                u1 += y[4] * cf + r1 * cr;
-                u2 += y[5] * cf + r2 * cr;
+                if (KIND == 3) {
+                    const float w0 = y[3] * r0 + y[4] * r1 + y[5] * r2;
+                    const float w1 = y[4] * r0 + y[6] * r1 + y[7] * r2;
+                    const float w2 = y[5] * r0 + y[7] * r1 + y[8] * r2;
+                    const float c = -3.0f * (r0 * w0 + r1 * w1 + r2 * w2) * ri3 * ri2;
+                    u0 += r0 * c;
+                    u1 += r1 * c;
+                    u2 += r2 * c;
+                } else {
+                    const float rdf = r0 * y[3] + r1 * y[4] + r2 * y[5];
+                    // G f = f/r + r (r.f)/r^3;  RPY: + (b^2/6)(2 f/r^3 - 6 r (r.f)/r^5);  PVel: - q r/r^3
+                    const float cf = KIND == 1 ? ri + 2.0f * y[6] * ri3 : ri;
+                    const float cr = KIND == 1   ? (rdf * ri3) * (1.0f - 6.0f * y[6] * ri2)
+                                     : KIND == 2 ? (rdf - y[6]) * ri3
+                                                 : rdf * ri3;
+                    u0 += y[3] * cf + r0 * cr;
+                    u1 += y[4] * cf + r1 * cr;
+                    u2 += y[5] * cf + r2 * cr;
+                }
             }
             acc[q][0] += double(u0);
             acc[q][1] += double(u1);
             acc[q][2] += double(u2);
         }
     }
-    double *o = part + int64_t(blockIdx.x) * 3 * M;
+    double *o = part + int64_t(blockIdx.x) * (3 * M + 3);
 #pragma unroll
     for (int q = 0; q < kRootPer; ++q) {
         const int m = int(threadIdx.x) + 256 * q;
         if (m < M)
             for (int k = 0; k < 3; ++k) o[3 * m + k] = acc[q][k];
     }
+    if constexpr (kFlux) {
+        for (int k = 0; k < 3; ++k) mred[256 * k + threadIdx.x] = mw[k];
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (int(threadIdx.x) < w)
+                for (int k = 0; k < 3; ++k) mred[256 * k + threadIdx.x] += mred[256 * k + threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x < 3) o[3 * M + threadIdx.x] = mred[256 * threadIdx.x];
+    } else {
+        if (threadIdx.x < 3) o[3 * M + threadIdx.x] = 0.0;
+    }
 }
 
-// V[r] = sum over chunks of part[chunk][r], in chunk order
+// V[r] = sum over chunks of part[chunk][r], in chunk order (r < 3M + 3)
 __global__ __launch_bounds__(256) void stokes_root_reduce_kernel(const double *__restrict__ part, int nchunks, int n3,
                                                                  double *__restrict__ V) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -116,13 +158,22 @@ __global__ __launch_bounds__(256) void stokes_far_forces_kernel(const double *__
 // (hi + lo, unit box) relative to the root centre; F and z staged in LDS.
 // The far images' flow is smooth in the box (z_m lie outside it): FP32 pair
 // terms, summed per tile in FP32 and across tiles in FP64.
-// RPY targets also take lap u = sum_m lap G(x - z_m) F_m (scale_lap).
-template <bool RPY>
+// Output modes: 0 u (stride 3); 1 RPY (u, lap u = sum_m lap G(x - z_m) F_m
+// with scale_lap; stride 6); 2 PVel (p = sum_m (r.F_m)/(4 pi r^3) with
+// scale_lap, u; stride 4).
+// PVel's flux sources (q, tr D) are potential dipoles in total (zero net
+// flux).  Their Ewald sum (the k = 0 mode dropped) has zero mean velocity;
+// the Stokeslet fit carries them in divergence-free form, whose transform
+// differs from theirs by the constant P/2 at k -> 0 (P = sum_j w_j y_j, the
+// flux moment): mode 2 removes the resulting uniform flow P/(2 L^3),
+// mom = P in unit-box records (w/L), scaled by 1/L like u.
+template <int OUT>
 __global__ __launch_bounds__(256) void stokes_far_targets_kernel(int64_t n, const float *__restrict__ trg,
                                                                  const int32_t *__restrict__ perm,
                                                                  const double *__restrict__ F,
                                                                  const double *__restrict__ Z, int M, double scale,
-                                                                 double scale_lap, double *__restrict__ out) {
+                                                                 double scale_lap, const double *__restrict__ mom,
+                                                                 double *__restrict__ out) {
     __shared__ float tile[256 * 6];
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const bool active = i < n;
@@ -159,12 +210,14 @@ __global__ __launch_bounds__(256) void stokes_far_targets_kernel(int64_t n, cons
             v0 += t[3] * ri + r0 * rf;
             v1 += t[4] * ri + r1 * rf;
             v2 += t[5] * ri + r2 * rf;
-            if (RPY) {
+            if (OUT == 1) {
                 // lap G F = 2 F/r^3 - 6 r (r.F)/r^5
                 const float c6 = -6.0f * rf * ri2;
                 l0 += 2.0f * t[3] * ri3 + r0 * c6;
                 l1 += 2.0f * t[4] * ri3 + r1 * c6;
                 l2 += 2.0f * t[5] * ri3 + r2 * c6;
+            } else if (OUT == 2) {
+                l0 += rf;                                // 8 pi p = 2 (r.F)/r^3
             }
         }
         u[0] += double(v0);
@@ -175,72 +228,92 @@ __global__ __launch_bounds__(256) void stokes_far_targets_kernel(int64_t n, cons
         w[2] += double(l2);
     }
     if (!active) return;
-    double *o = out + (RPY ? 6 : 3) * int64_t(perm[i]);
+    if (OUT == 2) {
+        double *o = out + 4 * int64_t(perm[i]);
+        o[0] += scale_lap * kInv8Pi * 2.0 * w[0];
+        for (int k = 0; k < 3; ++k) o[1 + k] += scale * (kInv8Pi * u[k] - 0.5 * mom[k]);
+        return;
+    }
+    double *o = out + (OUT == 1 ? 6 : 3) * int64_t(perm[i]);
     for (int k = 0; k < 3; ++k) o[k] += scale * kInv8Pi * u[k];
-    if (RPY)
+    if (OUT == 1)
         for (int k = 0; k < 3; ++k) o[3 + k] += scale_lap * kInv8Pi * w[k];
 }
 
-// per-block partial sums of f (3 components) and |f| (net-force check)
-__global__ __launch_bounds__(256) void force_partials_kernel(int64_t n, const double *__restrict__ f, int stride,
-                                                             double *__restrict__ part) {
-    __shared__ double s[4][256];
-    double a[4] = {0, 0, 0, 0};
+// per-block partial sums of the first ncomp (<= 9) values of each source
+// (stride apart) and of their absolute values: part[block][ncomp + 1]
+__global__ __launch_bounds__(256) void value_partials_kernel(int64_t n, const double *__restrict__ f, int stride,
+                                                             int ncomp, double *__restrict__ part) {
+    __shared__ double s[10][256];
+    double a[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < ncomp; ++k) {
             const double v = f[stride * i + k];
             a[k] += v;
-            a[3] += fabs(v);
+            a[9] += fabs(v);
         }
-    for (int k = 0; k < 4; ++k) s[k][threadIdx.x] = a[k];
+    for (int k = 0; k < 10; ++k) s[k][threadIdx.x] = a[k];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (int(threadIdx.x) < w)
-            for (int k = 0; k < 4; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+            for (int k = 0; k < 10; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 4; ++k) part[4 * blockIdx.x + k] = s[k][0];
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < ncomp; ++k) part[(ncomp + 1) * blockIdx.x + k] = s[k][0];
+        part[(ncomp + 1) * blockIdx.x + ncomp] = s[9][0];
+    }
 }
 
 }  // namespace
 
 int stokes_root_chunks(int64_t n) { return int((n + kRootChunk - 1) / kRootChunk); }
 
-hipError_t launch_stokes_far_forces(int64_t n_src, const float *src, int rec, bool rpy, const double *X,
-                                    const double *Q, int M, double *part, double *V, double *F, hipStream_t s) {
+hipError_t launch_stokes_root_check(int kind, int64_t n_src, const float *src, int rec, const double *X, int M,
+                                    double *part, hipStream_t s) {
+    const int nch = stokes_root_chunks(n_src);
+    if (nch == 0) return hipSuccess;
     if (M > 256 * kRootPer) return hipErrorInvalidValue;
-    if (rpy && rec < 10) return hipErrorInvalidValue;
-    const int nch = stokes_root_chunks(n_src), n3 = 3 * M;
-    if (nch > 0) {
-        if (rpy)
-            hipLaunchKernelGGL(stokes_root_check_kernel<true>, dim3(nch), dim3(256), 0, s, n_src, src, rec, X, M, part);
-        else
-            hipLaunchKernelGGL(stokes_root_check_kernel<false>, dim3(nch), dim3(256), 0, s, n_src, src, rec, X, M, part);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    if (rec < (kind == 0 ? 9 : kind == 3 ? 12 : 10)) return hipErrorInvalidValue;
+    const dim3 g(nch), b(256);
+    switch (kind) {
+        case 0: hipLaunchKernelGGL(stokes_root_check_kernel<0>, g, b, 0, s, n_src, src, rec, X, M, part); break;
+        case 1: hipLaunchKernelGGL(stokes_root_check_kernel<1>, g, b, 0, s, n_src, src, rec, X, M, part); break;
+        case 2: hipLaunchKernelGGL(stokes_root_check_kernel<2>, g, b, 0, s, n_src, src, rec, X, M, part); break;
+        case 3: hipLaunchKernelGGL(stokes_root_check_kernel<3>, g, b, 0, s, n_src, src, rec, X, M, part); break;
+        default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(stokes_root_reduce_kernel, dim3((n3 + 255) / 256), dim3(256), 0, s, part, nch, n3, V);
+    return hipGetLastError();
+}
+
+hipError_t launch_stokes_far_forces(int nchunks, const double *Q, int M, const double *part, double *V, double *F,
+                                    hipStream_t s) {
+    const int n3 = 3 * M, n3p = 3 * M + 3;
+    hipLaunchKernelGGL(stokes_root_reduce_kernel, dim3((n3p + 255) / 256), dim3(256), 0, s, part, nchunks, n3p, V);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(stokes_far_forces_kernel, dim3(n3), dim3(256), 0, s, Q, V, n3, F);
     return hipGetLastError();
 }
 
-hipError_t launch_stokes_far_targets(int64_t n, const float *trg, const int32_t *perm, bool rpy, const double *F,
-                                     const double *Z, int M, double scale, double scale_lap, double *out,
-                                     hipStream_t s) {
+hipError_t launch_stokes_far_targets(int64_t n, const float *trg, const int32_t *perm, int mode, const double *F,
+                                     const double *Z, int M, double scale, double scale2, const double *mom,
+                                     double *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const dim3 g(int((n + 255) / 256)), b(256);
-    if (rpy)
-        hipLaunchKernelGGL(stokes_far_targets_kernel<true>, g, b, 0, s, n, trg, perm, F, Z, M, scale, scale_lap, out);
-    else
-        hipLaunchKernelGGL(stokes_far_targets_kernel<false>, g, b, 0, s, n, trg, perm, F, Z, M, scale, scale_lap, out);
+    switch (mode) {
+        case 0: hipLaunchKernelGGL(stokes_far_targets_kernel<0>, g, b, 0, s, n, trg, perm, F, Z, M, scale, scale2, mom, out); break;
+        case 1: hipLaunchKernelGGL(stokes_far_targets_kernel<1>, g, b, 0, s, n, trg, perm, F, Z, M, scale, scale2, mom, out); break;
+        case 2: hipLaunchKernelGGL(stokes_far_targets_kernel<2>, g, b, 0, s, n, trg, perm, F, Z, M, scale, scale2, mom, out); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_force_partials(int64_t n, const double *f, int stride, int nblocks, double *part, hipStream_t s) {
-    hipLaunchKernelGGL(force_partials_kernel, dim3(nblocks), dim3(256), 0, s, n, f, stride, part);
+hipError_t launch_value_partials(int64_t n, const double *f, int stride, int ncomp, int nblocks, double *part,
+                                 hipStream_t s) {
+    if (ncomp < 1 || ncomp > 9) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(value_partials_kernel, dim3(nblocks), dim3(256), 0, s, n, f, stride, ncomp, part);
     return hipGetLastError();
 }
 

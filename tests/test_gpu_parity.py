@@ -118,6 +118,29 @@ def test_fmm_clustered(fmm, kernel):
         assert e < 1e-5
 
 
+@pytest.mark.parametrize("kernel", ["PVel", "Traction", "PVelGrad", "PVelLaplacian"])
+def test_fmm_shifted_box(kernel):
+    # a box of side 2.5 away from the origin: every source value enters the
+    # unit-box pass with its own power of the box size (the flux q one power
+    # above the force f)
+    from paper_2010_15155_amd import FMM
+    L, org = 2.5, np.array([-1.0, 0.4, 2.0])
+    pb = problem(kernel, 9000, 8)
+    for k in ("sl_xyz", "dl_xyz", "trg_xyz"):
+        pb[k] = org + L * pb[k]
+    idx = W.sample_indices(len(pb["trg_xyz"]), 400, 9)
+    ref = direct.evaluate(kernel, pb["sl_xyz"], pb["sl_val"], pb["dl_xyz"], pb["dl_val"], pb["trg_xyz"][idx])
+    f = FMM(origin=tuple(org), box_len=L)
+    try:
+        got = gpu_eval(f, kernel, pb, p=8, cap=150)[idx]
+    finally:
+        f.close()
+    errs = field_errors(kernel, got, ref)
+    print(kernel, "fmm p=8, box of side 2.5", errs, flush=True)
+    for e in errs.values():
+        assert e < 1e-5
+
+
 # Relative L2 bounds of the far-field-only problem at p = 8.  Values and first
 # derivatives of the tree potentials meet the 1e-5 budget; outputs built from
 # second derivatives (lap u, sigma, grad u, grad p of the Stokes double layer,

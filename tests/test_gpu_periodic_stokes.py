@@ -7,13 +7,18 @@
 * the translation test (moving all points together changes nothing);
 * a non-zero net force is rejected;
 * RPY (u and lap u) on the same path: the root's check-surface flow takes
-  the (b^2/6) lap G term, the targets the far images' lap u.
+  the (b^2/6) lap G term, the targets the far images' lap u;
+* PVel (p, u) of single-layer (f, q) and double-layer D sources (zero net
+  force, flux and tr D), on the unit box and on a shifted box of side 2.5:
+  u against the oracle's Ewald sums, p up to an additive constant (the far
+  images' pressure is fitted through their flow, which fixes it only up to
+  one); non-zero net flux or tr D is rejected.
 """
 import numpy as np
 import pytest
 import torch
 
-from oracle.stokes_periodic import rpy_periodic, stokeslet_periodic
+from oracle.stokes_periodic import pvel_periodic, rpy_periodic, stokeslet_periodic
 from paper_2010_15155_amd import FMM, StkfmmError, workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -132,3 +137,94 @@ def test_separate_targets(fmm):
     print("periodic Stokeslet, separate targets", e, flush=True)
     assert e < 1e-5
 
+
+
+def _pvel(n_sl, n_dl, seed, clustered=False):
+    y, f = _problem(n_sl, seed, clustered)
+    rng = np.random.default_rng(seed + 200)
+    q = rng.standard_normal(n_sl)
+    q -= q.mean()
+    x = rng.random((n_dl, 3))
+    D = rng.standard_normal((n_dl, 9))
+    D[:, [0, 4, 8]] -= (D[:, 0] + D[:, 4] + D[:, 8]).mean() / 3.0
+    return y, np.concatenate([f, q[:, None]], 1), x, D
+
+
+def _pvel_errors(out, ref):
+    d = out[:, 0] - ref[:, 0]
+    p0 = ref[:, 0] - ref[:, 0].mean()
+    return rel(out[:, 1:], ref[:, 1:]), float(np.linalg.norm(d - d.mean()) / np.linalg.norm(p0))
+
+
+@pytest.mark.parametrize("n,cap,p,tol_u,tol_p", [(600, 2000, 8, 1e-5, 1e-5), (6000, 64, 8, 1e-5, 2e-5),
+                                                 (6000, 64, 10, 5e-6, 1e-5)])
+def test_pvel(fmm, n, cap, p, tol_u, tol_p):
+    y, fq, x, D = _pvel(n // 2, n // 2, 21)
+    t = np.concatenate([y, x])
+    print("periodic PVel", n, "sources, p", p, flush=True)
+    out = fmm.evaluate("PVel", sl_xyz=cu(y), sl_val=cu(fq), dl_xyz=cu(x), dl_val=cu(D), trg_xyz=cu(t), p=p,
+                       leaf_cap=cap, bc="PXYZ").cpu().numpy()
+    idx = W.sample_indices(len(t), min(len(t), 300), 6)
+    ref = pvel_periodic(y, fq, x, D, t[idx])
+    e_u, e_p = _pvel_errors(out[idx], ref)
+    print("  rel L2 u", e_u, "p (up to a constant)", e_p, flush=True)
+    assert e_u < tol_u and e_p < tol_p
+
+
+@pytest.mark.parametrize("layers", ["sl", "dl"])
+def test_pvel_one_layer_scaled_box(layers):
+    # a box of side 2.5 away from the origin: the flux q and D enter with
+    # their own powers of the box size
+    L, org = 2.5, np.array([-1.0, 0.4, 2.0])
+    y, fq, x, D = _pvel(3000, 3000, 22)
+    y, x = org + L * y, org + L * x
+    t = np.concatenate([y, x]) if layers == "sl" else x
+    kw = dict(sl_xyz=cu(y), sl_val=cu(fq)) if layers == "sl" else dict(dl_xyz=cu(x), dl_val=cu(D))
+    print("periodic PVel, box of side 2.5,", layers, flush=True)
+    f = FMM(origin=tuple(org), box_len=L)
+    try:
+        out = f.evaluate("PVel", trg_xyz=cu(t), p=8, leaf_cap=64, bc="PXYZ", **kw).cpu().numpy()
+    finally:
+        f.close()
+    idx = W.sample_indices(len(t), 300, 7)
+    ref = pvel_periodic(y if layers == "sl" else None, fq, x if layers == "dl" else None, D, t[idx], L=L)
+    e_u, e_p = _pvel_errors(out[idx], ref)
+    print("  rel L2 u", e_u, "p (up to a constant)", e_p, flush=True)
+    assert e_u < 1e-5 and e_p < 2e-5
+
+
+def test_pvel_rejects_net_flux(fmm):
+    y, fq, x, D = _pvel(2000, 2000, 23)
+    t = np.concatenate([y, x])
+    fmm.set_points("PVel", cu(y), cu(x), cu(t), p=6, leaf_cap=100, bc="PXYZ")
+    bad = fq.copy()
+    bad[:, 3] += 1e-3
+    with pytest.raises(StkfmmError) as ei:
+        fmm.run(cu(bad), cu(D))
+    assert ei.value.status == "E_DOMAIN" and "flux" in str(ei.value)
+    bad = D.copy()
+    bad[:, 4] += 1e-3
+    with pytest.raises(StkfmmError) as ei:
+        fmm.run(cu(fq), cu(bad))
+    assert ei.value.status == "E_DOMAIN" and "tr D" in str(ei.value)
+    bad = fq.copy()
+    bad[:, 1] += 1e-3
+    with pytest.raises(StkfmmError) as ei:
+        fmm.run(cu(bad), cu(D))
+    assert ei.value.status == "E_DOMAIN" and "force" in str(ei.value)
+
+
+def test_pvel_translation(fmm):
+    # moving every point by the same shift (wrapped into the box) changes
+    # which image of each source the plan holds, and so the flux moment;
+    # the result must not change
+    y, fq, x, D = _pvel(6000, 6000, 24)
+    t = np.concatenate([y, x])
+    outs = []
+    for s in (np.zeros(3), np.array([0.31, 0.77, 0.58])):
+        w = lambda a: np.mod(a + s, 1.0)
+        outs.append(fmm.evaluate("PVel", sl_xyz=cu(w(y)), sl_val=cu(fq), dl_xyz=cu(w(x)), dl_val=cu(D),
+                                 trg_xyz=cu(w(t)), p=8, leaf_cap=64, bc="PXYZ").cpu().numpy())
+    e_u, e_p = _pvel_errors(outs[1], outs[0])
+    print("periodic PVel translation: u", e_u, "p", e_p, flush=True)
+    assert e_u < 3e-5 and e_p < 3e-5
