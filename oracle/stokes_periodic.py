@@ -24,6 +24,10 @@ Ewald split with the Hasimoto factor phi(k) = (1 + k^2/(4 xi^2)) e^{-k^2/(4 xi^2
 The real part's integral vanishes (1 - phi = O(k^4)), so no constant term
 arises.  FP64: the real part by plain loops in ewald.c, the reciprocal part
 with NumPy.
+
+The same module holds the RPY sum (with lap G), the double layer
+(grad G : D^s), PVel's (p, u) built from these and the Laplace Ewald sums,
+and PVel's derivative outputs by central differences of (p, u).
 """
 import numpy as np
 
@@ -179,3 +183,58 @@ def pvel_periodic(sl, fq, dl, D, trg, L=1.0, tol=1e-13):
         out[:, 0] += ewald.laplace_periodic(dl, None, None, x, L, tol=tol, Q=-Ds)[:, 0]
     return out
 
+
+
+def _stencil(x, h):
+    """The target and its four neighbours at +-h, +-2h along each axis:
+    [13 m, 3] (x first, then axis j, offsets h, -h, 2h, -2h)."""
+    pts = [x]
+    for j in range(3):
+        for s in (h, -h, 2.0 * h, -2.0 * h):
+            y = x.copy()
+            y[:, j] += s
+            pts.append(y)
+    return np.concatenate(pts)
+
+
+def _derivatives(v, m, h):
+    """From values on the stencil [13 m, c]: the centre value [m, c], the
+    first derivatives [m, c, 3] and the second derivatives along each axis
+    [m, c, 3], by the five-point central formulas (error O(h^4))."""
+    v = v.reshape(13, m, -1)
+    d1 = np.empty(v.shape[1:] + (3,))
+    d2 = np.empty(v.shape[1:] + (3,))
+    for j in range(3):
+        a, b, c, d = v[1 + 4 * j], v[2 + 4 * j], v[3 + 4 * j], v[4 + 4 * j]
+        d1[..., j] = (8.0 * (a - b) - (c - d)) / (12.0 * h)
+        d2[..., j] = (16.0 * (a + b) - (c + d) - 30.0 * v[0]) / (12.0 * h * h)
+    return v[0], d1, d2
+
+
+def pvel_derivs_periodic(sl, fq, dl, D, trg, L=1.0, h=None, kind="PVelGrad"):
+    """Periodic PVel with derivative outputs (the pressure-velocity kernels'
+    gradient, Laplacian and stress outputs of the paper's table of supported
+    kernels) at targets away from every source: the derivatives of
+    pvel_periodic by five-point central differences (step h, default
+    L/1000; the targets must lie much farther than 2h from every source
+    image).  kind
+      "PVelGrad"      -> [m, 16]: p, u, grad p, grad u (d_j u_i row-major),
+      "PVelLaplacian" -> [m, 7]:  p, u, lap u (sum of second differences),
+      "Traction"      -> [m, 9]:  sigma = -p I + grad u + grad u^T (row-major).
+    The pressure (and so sigma's isotropic part) is that of pvel_periodic:
+    zero mean over the cell."""
+    x = np.ascontiguousarray(trg, dtype=np.float64).reshape(-1, 3)
+    m = len(x)
+    h = 1e-3 * L if h is None else h
+    v = pvel_periodic(sl, fq, dl, D, _stencil(x, h), L)
+    c, d1, d2 = _derivatives(v, m, h)
+    p, u = c[:, 0], c[:, 1:]
+    gp, gu = d1[:, 0, :], d1[:, 1:, :]                  # gu[:, i, j] = d_j u_i
+    if kind == "PVelGrad":
+        return np.concatenate([p[:, None], u, gp, gu.reshape(m, 9)], 1)
+    if kind == "PVelLaplacian":
+        return np.concatenate([p[:, None], u, d2[:, 1:, :].sum(axis=2)], 1)
+    if kind == "Traction":
+        sig = -p[:, None, None] * np.eye(3)[None] + gu + gu.transpose(0, 2, 1)
+        return sig.reshape(m, 9)
+    raise ValueError(kind)

@@ -177,3 +177,71 @@ def test_pvel_divergence_free():
         div += (pvel_periodic(sl, fq, dl, D, x + e)[:, 1 + k] - pvel_periodic(sl, fq, dl, D, x - e)[:, 1 + k]) / (2 * h)
     grad_scale = np.abs(pvel_periodic(sl, fq, dl, D, x)[:, 1:]).max() / 0.05
     assert np.abs(div).max() < 1e-6 * grad_scale
+
+
+def _away_from(sources, k, rng, dmin=0.1):
+    """k points at least dmin from every source image."""
+    out = []
+    while len(out) < k:
+        c = rng.random(3)
+        d = c - sources
+        d -= np.round(d)
+        if np.min(np.linalg.norm(d, axis=1)) >= dmin:
+            out.append(c)
+    return np.array(out)
+
+
+def test_pvel_derivatives_satisfy_the_stokes_equations():
+    # lap u (second differences of u) = grad p (first differences of p): the
+    # velocity's and the pressure's Ewald sums are separate, so this ties
+    # them together; and div u = tr grad u = 0 between the sources
+    from oracle.stokes_periodic import pvel_derivs_periodic
+    rng, sl, fq, dl, D = _dl_problem(25)
+    x = _away_from(np.concatenate([sl, dl]), 4, rng)
+    g = pvel_derivs_periodic(sl, fq, dl, D, x, kind="PVelGrad")
+    lap = pvel_derivs_periodic(sl, fq, dl, D, x, kind="PVelLaplacian")
+    assert np.allclose(g[:, :4], lap[:, :4], rtol=1e-13, atol=0)
+    scale = np.abs(g[:, 4:7]).max()
+    assert np.abs(lap[:, 4:7] - g[:, 4:7]).max() < 1e-6 * scale
+    gu = g[:, 7:].reshape(-1, 3, 3)
+    assert np.abs(np.trace(gu, axis1=1, axis2=2)).max() < 1e-8 * np.abs(gu).max()
+    sig = pvel_derivs_periodic(sl, fq, dl, D, x, kind="Traction").reshape(-1, 3, 3)
+    assert np.allclose(sig, sig.transpose(0, 2, 1), rtol=0, atol=1e-12 * np.abs(sig).max())
+    # tr sigma = -3 p + 2 div u
+    assert np.abs(np.trace(sig, axis1=1, axis2=2) + 3 * g[:, 0]).max() < 1e-7 * np.abs(gu).max()
+
+
+def test_pvel_derivatives_converge_at_fourth_order():
+    # halving the step divides the change by about 16 (five-point formulas),
+    # and at h = 5e-4, 0.1 from every source, the derivatives are settled to
+    # a few 1e-8
+    from oracle.stokes_periodic import pvel_derivs_periodic
+    rng, sl, fq, dl, D = _dl_problem(26)
+    x = _away_from(np.concatenate([sl, dl]), 3, rng)
+    a, b, c = (pvel_derivs_periodic(sl, fq, dl, D, x, h=h, kind="PVelGrad")[:, 4:] for h in (2e-3, 1e-3, 5e-4))
+    d1, d2 = np.abs(a - b).max(), np.abs(b - c).max()
+    assert 10.0 < d1 / d2 < 25.0
+    assert d2 < 5e-8 * np.abs(c).max()
+
+
+@pytest.mark.parametrize("layer", ["sl", "dl"])
+def test_pvel_derivatives_next_to_a_source(layer):
+    # 1e-3 from one source its own free-space term (the oracle's direct
+    # PVelGrad and Traction kernels) dominates by 1e5 : 1 or more; the rest
+    # of the periodic sum is smooth there (a wrong sign, index or layout
+    # would leave an O(1) relative difference)
+    from oracle import direct
+    from oracle.stokes_periodic import pvel_derivs_periodic
+    rng, sl, fq, dl, D = _dl_problem(27)
+    r, e = 1e-3, np.array([0.48, -0.6, 0.64])
+    y = (sl if layer == "sl" else dl)[0]
+    x = (y + r * e)[None]
+    one = dict(sl=sl[:1], fq=fq[:1]) if layer == "sl" else dict(dl=dl[:1], D=D[:1])
+    for kind in ("PVelGrad", "Traction"):
+        got = pvel_derivs_periodic(sl, fq, dl, D, x, h=1e-5, kind=kind)
+        if kind == "PVelGrad":
+            want = direct.pvel_grad(one.get("sl"), one.get("fq"), one.get("dl"), one.get("D"), x)
+            got, want = got[:, 4:], want[:, 4:]            # the derivatives
+        else:
+            want = direct.traction(one.get("sl"), one.get("fq"), one.get("dl"), one.get("D"), x)
+        assert np.abs(got - want).max() < 1e-5 * np.abs(want).max(), kind
