@@ -92,10 +92,12 @@ typedef enum {
 /* Boundary conditions (Sec. III and its appendix on periodicity).  PXYZ is
  * implemented for LAP_PGRAD, LAP_PGRADGRAD and LAP_QPGRADGRAD (zero net
  * charge; Ewald's convention: no k = 0 term, no surface term) and for
- * STOKESLET, RPY and PVEL (zero net force, and for PVEL zero net flux q and
- * zero sum of tr D; the Fourier series of the periodic Stokes equations
- * without its k = 0 term, i.e. zero mean velocity, summed with Hasimoto's
- * Ewald split; PVEL's pressure is defined up to an additive constant).  WALL (Sec. III, the no-slip wall section,
+ * STOKESLET, RPY, PVEL, PVEL_GRAD, PVEL_LAPLACIAN and TRACTION (zero net
+ * force, and for the PVEL family zero net flux q and zero sum of tr D; the
+ * Fourier series of the periodic Stokes equations without its k = 0 term,
+ * i.e. zero mean velocity, summed with Hasimoto's Ewald split; the pressure,
+ * and so TRACTION's isotropic part, is defined up to an additive
+ * constant).  WALL (Sec. III, the no-slip wall section,
  * tab:rpywall) is an open domain bounded below by a no-slip wall on the
  * plane z = origin[2], for STOKESLET and RPY only, fixed p and leaf_cap only:
  * the flow is assembled from three (Stokeslet) or four (RPY) free-space
@@ -142,11 +144,13 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *ctx, stkfmm_kernel kernel, stkfmm_bc
  * (overwritten, user order).  Periodic LAP_PGRAD requires sum q = 0
  * (relative to sum |q|, 1e-9), else E_DOMAIN; its potential is defined up to
  * an additive constant (the Ewald convention with the k = 0 term dropped).
- * Periodic STOKESLET, RPY and PVEL require each component of sum f to
- * vanish (relative to sum |f_k|, 1e-9), else E_DOMAIN; periodic PVEL also
- * requires sum q = 0 (relative to the sum of |f_k| and |q|) and sum tr D = 0
- * over the double layer (relative to the sum of |D_jk|), else E_DOMAIN, and
- * its pressure is determined up to an additive constant.
+ * Periodic Stokes kernels require each component of sum f to vanish
+ * (relative to sum |f_k|, 1e-9), else E_DOMAIN; the periodic PVEL family
+ * (PVEL, PVEL_GRAD, PVEL_LAPLACIAN, TRACTION) also requires sum q = 0
+ * (relative to the sum of |f_k| and |q|) and sum tr D = 0 over the double
+ * layer (relative to the sum of |D_jk|), else E_DOMAIN, and its pressure
+ * (TRACTION: sigma's isotropic part) is determined up to an additive
+ * constant.
  * Errors: E_STATE (no points set), E_ARG, E_DOMAIN, E_NOMEM, E_DEVICE. */
 stkfmm_status stkfmm_run(stkfmm_ctx *ctx, const double *sl_val, const double *dl_val,
                          double *trg_val, void *hip_stream);

@@ -241,6 +241,9 @@ stkfmm_status fail(stkfmm_ctx *c, stkfmm_status s, const std::string &msg) {
 bool kernel_ok(int k) { return k >= 0 && k < kNumKernels; }
 
 // source kinds of the packing kernel; stage_kind: of the surface tiles
+// PVel and its derivative outputs: single layer (f, q), double layer D
+bool pvel_family(int k) { return k == kPVel || k == kPVelGrad || k == kPVelLaplacian || k == kTraction; }
+
 int sl_kind(int k) {
     switch (k) {
         case kStokeslet: return 0;
@@ -1037,9 +1040,10 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
         return fail(c, STKFMM_E_UNSUPPORTED, "only open, triply periodic and wall boundaries are implemented");
     if (bc == STKFMM_BC_PXYZ && kernel != STKFMM_LAP_PGRAD && kernel != STKFMM_LAP_PGRADGRAD &&
         kernel != STKFMM_LAP_QPGRADGRAD && kernel != STKFMM_STOKESLET && kernel != STKFMM_RPY &&
-        kernel != STKFMM_PVEL)
+        !pvel_family(kernel))
         return fail(c, STKFMM_E_UNSUPPORTED,
-                    "triply periodic boundary is implemented for the Laplace kernels, STOKESLET, RPY and PVEL");
+                    "triply periodic boundary is implemented for the Laplace kernels, STOKESLET, RPY, PVEL, "
+                    "PVEL_GRAD, PVEL_LAPLACIAN and TRACTION");
     const bool periodic = bc == STKFMM_BC_PXYZ;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(c, hipSetDevice(c->device));
@@ -1149,7 +1153,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     stkfmm_status st = get_ops(c, p, periodic, m2l_tol, &ops);
     if (st != STKFMM_OK) return st;
     c->stk = nullptr;
-    if (periodic && (kernel == STKFMM_STOKESLET || kernel == STKFMM_RPY || kernel == STKFMM_PVEL)) {
+    if (periodic && (kernel == STKFMM_STOKESLET || kernel == STKFMM_RPY || pvel_family(kernel))) {
         st = get_periodic_stokes(c, &c->stk);
         if (st != STKFMM_OK) return st;
         const int Mf = c->stk->M;
@@ -1701,7 +1705,7 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
     const int nc = ki.ncomp;
     const bool periodic = c->bc == STKFMM_BC_PXYZ;
     if (c->n_trg == 0) return STKFMM_OK;
-    const bool pstokes = periodic && (c->kernel == kStokeslet || c->kernel == kRPY || c->kernel == kPVel);
+    const bool pstokes = periodic && (c->kernel == kStokeslet || c->kernel == kRPY || pvel_family(c->kernel));
     // sums of the first ncomp values of each source and of their absolute
     // values (one reduction on the device, a fixed order on the host)
     auto value_sums = [&](int64_t n, const double *v, int stride, int ncomp, double *sum,
@@ -1721,7 +1725,7 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
     if (pstokes && c->n_sl > 0) {
         // zero net force (the Ewald convention drops the k = 0 mode) and,
         // for PVel, zero net flux q
-        const int ncomp = c->kernel == kPVel ? 4 : 3;
+        const int ncomp = pvel_family(c->kernel) ? 4 : 3;
         double f[4], fa;
         stkfmm_status st = value_sums(c->n_sl, sl_val, ki.k_sl, ncomp, f, &fa);
         if (st != STKFMM_OK) return st;
@@ -1862,7 +1866,7 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
             const int M = c->stk->M;
             const int nch_sl = stokes_root_chunks(c->n_sl), nch_dl = stokes_root_chunks(c->n_dl);
             double *part = c->stk_part.as<double>();
-            const int kind = c->kernel == kRPY ? 1 : c->kernel == kPVel ? 2 : 0;
+            const int kind = c->kernel == kRPY ? 1 : pvel_family(c->kernel) ? 2 : 0;
             HIP_TRY(c, launch_stokes_root_check(kind, c->n_sl, c->sl_rec.as<float>(), ki.rec_sl,
                                                 c->stk->X.as<double>(), M, part, s));
             HIP_TRY(c, launch_stokes_root_check(3, c->n_dl, c->dl_rec.as<float>(), ki.rec_dl,
@@ -1917,14 +1921,14 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         a.out = trg_val;
         HIP_TRY(c, launch_combine(c->nchunks, a, s));
         if (pstokes) {
-            // far images: u (scale 1/L) and RPY's lap u (1/L^3) or PVel's p (1/L^2)
+            // far images (each output with its power of 1/L)
             const double L = c->box_len;
-            const int mode = c->kernel == kRPY ? 1 : c->kernel == kPVel ? 2 : 0;
+            const int mode = c->kernel == kRPY ? 1 : c->kernel == kPVel ? 2 : c->kernel == kPVelGrad ? 3
+                           : c->kernel == kPVelLaplacian ? 4 : c->kernel == kTraction ? 5 : 0;
             const int M = c->stk->M;
             const double *V = c->stk_F.as<double>();    // check flow [3M], flux moment [3], forces [3M]
             HIP_TRY(c, launch_stokes_far_targets(c->n_trg, c->trg_rec.as<float>(), at<int32_t>(c, c->a_perm_trg),
-                                                 mode, V + 3 * M + 3, c->stk->Z.as<double>(), M, 1.0 / L,
-                                                 mode == 1 ? 1.0 / (L * L * L) : 1.0 / (L * L), V + 3 * M,
+                                                 mode, V + 3 * M + 3, c->stk->Z.as<double>(), M, 1.0 / L, V + 3 * M,
                                                  trg_val, s));
         }
     }

@@ -190,8 +190,10 @@ hipError_t launch_wall_assemble(const WallAssembleArgs &a, hipStream_t s);
 // partial sums part [chunks][3M + 3], the last 3 the flux moment); then
 // V [3M + 3] = the chunks' sum and the far images' forces F = Q V / (8 pi)
 // [3M]; targets (sorted, unit-box records) add their far-image values in
-// user order (mode 0: u, 1: u and lap u, 2: p and u less the flux moment's
-// uniform flow, mom = V + 3M; scale for u, scale2 for lap u or p);
+// user order (mode 0 Stokeslet u; 1 RPY u, lap u; 2 PVel p, u; 3 PVelGrad
+// p, u, grad p, grad u; 4 PVelLaplacian p, u, lap u; 5 Traction sigma;
+// modes 2-4 less the flux moment's uniform flow, mom = V + 3M; inv_len =
+// 1/L sets each output's power of the box size);
 // per-block sums of the first ncomp values of each source and of their
 // absolute values.
 int stokes_root_chunks(int64_t n);
@@ -200,8 +202,8 @@ hipError_t launch_stokes_root_check(int kind, int64_t n_src, const float *src, i
 hipError_t launch_stokes_far_forces(int nchunks, const double *Q, int M, const double *part, double *V, double *F,
                                     hipStream_t s);
 hipError_t launch_stokes_far_targets(int64_t n, const float *trg, const int32_t *perm, int mode, const double *F,
-                                     const double *Z, int M, double scale, double scale2, const double *mom,
-                                     double *out, hipStream_t s);
+                                     const double *Z, int M, double inv_len, const double *mom, double *out,
+                                     hipStream_t s);
 hipError_t launch_value_partials(int64_t n, const double *f, int stride, int ncomp, int nblocks, double *part,
                                  hipStream_t s);
 hipError_t launch_periodic(const double *T, const float *dens, double *chk, int M, int Mp, int nc, int root,

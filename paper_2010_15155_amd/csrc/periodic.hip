@@ -158,22 +158,35 @@ __global__ __launch_bounds__(256) void stokes_far_forces_kernel(const double *__
 // (hi + lo, unit box) relative to the root centre; F and z staged in LDS.
 // The far images' flow is smooth in the box (z_m lie outside it): FP32 pair
 // terms, summed per tile in FP32 and across tiles in FP64.
-// Output modes: 0 u (stride 3); 1 RPY (u, lap u = sum_m lap G(x - z_m) F_m
-// with scale_lap; stride 6); 2 PVel (p = sum_m (r.F_m)/(4 pi r^3) with
-// scale_lap, u; stride 4).
+// Output modes (values of the Stokeslets F at z_m, times 1/(8 pi)):
+//   0 Stokeslet      u                                   stride 3
+//   1 RPY            u, lap u = 2 F/r^3 - 6 r (r.F)/r^5    stride 6
+//   2 PVel           p = 2 (r.F)/r^3, u                   stride 4
+//   3 PVelGrad       p, u, grad p, grad u (d_j u_i row-major)  stride 16
+//   4 PVelLaplacian  p, u, lap u (= grad p)               stride 7
+//   5 Traction       sigma = -p I + grad u + grad u^T
+//                          = -6 r r^T (r.F)/r^5          stride 9
+// with grad p = 2 F/r^3 - 6 r (r.F)/r^5 and
+// d_j u_i = (r_i F_j - F_i r_j + delta_ij (r.F))/r^3 - 3 (r.F) r_i r_j/r^5.
+// Scales: u by s1 = 1/L, p and sigma and grad u by 1/L^2, lap u and grad p
+// by 1/L^3 (unit-box records).
 // PVel's flux sources (q, tr D) are potential dipoles in total (zero net
 // flux).  Their Ewald sum (the k = 0 mode dropped) has zero mean velocity;
 // the Stokeslet fit carries them in divergence-free form, whose transform
 // differs from theirs by the constant P/2 at k -> 0 (P = sum_j w_j y_j, the
-// flux moment): mode 2 removes the resulting uniform flow P/(2 L^3),
-// mom = P in unit-box records (w/L), scaled by 1/L like u.
+// flux moment): modes 2-4 remove the resulting uniform flow P/(2 L^3) from u
+// (mom = P in unit-box records (w/L), scaled by 1/L like u); derivatives do
+// not see it.
 template <int OUT>
 __global__ __launch_bounds__(256) void stokes_far_targets_kernel(int64_t n, const float *__restrict__ trg,
                                                                  const int32_t *__restrict__ perm,
                                                                  const double *__restrict__ F,
-                                                                 const double *__restrict__ Z, int M, double scale,
-                                                                 double scale_lap, const double *__restrict__ mom,
+                                                                 const double *__restrict__ Z, int M, double s1,
+                                                                 const double *__restrict__ mom,
                                                                  double *__restrict__ out) {
+    constexpr bool kP = OUT >= 2;                   // pressure
+    constexpr bool kGP = OUT == 1 || OUT == 3 || OUT == 4;   // grad p (= lap u)
+    constexpr bool kGU = OUT == 3 || OUT == 5;      // grad u
     __shared__ float tile[256 * 6];
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const bool active = i < n;
@@ -185,7 +198,7 @@ __global__ __launch_bounds__(256) void stokes_far_targets_kernel(int64_t n, cons
         x1 = float((double(h.y) - 0.5) + double(l.y));
         x2 = float((double(h.z) - 0.5) + double(l.z));
     }
-    double u[3] = {0, 0, 0}, w[3] = {0, 0, 0};
+    double u[3] = {0, 0, 0}, pp = 0.0, gp[3] = {0, 0, 0}, gu[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int j0 = 0; j0 < M; j0 += 256) {
         const int cnt = min(256, M - j0);
         __syncthreads();
@@ -199,45 +212,60 @@ __global__ __launch_bounds__(256) void stokes_far_targets_kernel(int64_t n, cons
         }
         __syncthreads();
         if (!active) continue;
-        float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f, l0 = 0.0f, l1 = 0.0f, l2 = 0.0f;
+        float v[3] = {0.0f, 0.0f, 0.0f}, pv = 0.0f, g[3] = {0.0f, 0.0f, 0.0f};
+        float h[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         for (int j = 0; j < cnt; ++j) {
             const float *t = tile + 6 * j;
-            const float r0 = x0 - t[0], r1 = x1 - t[1], r2 = x2 - t[2];
-            const float ri = __builtin_amdgcn_rsqf(r0 * r0 + r1 * r1 + r2 * r2);
+            const float r[3] = {x0 - t[0], x1 - t[1], x2 - t[2]};
+            const float ri = __builtin_amdgcn_rsqf(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
             const float ri2 = ri * ri, ri3 = ri2 * ri;
-            const float rdf = r0 * t[3] + r1 * t[4] + r2 * t[5];
+            const float rdf = r[0] * t[3] + r[1] * t[4] + r[2] * t[5];
             const float rf = rdf * ri3;
-            v0 += t[3] * ri + r0 * rf;
-            v1 += t[4] * ri + r1 * rf;
-            v2 += t[5] * ri + r2 * rf;
-            if (OUT == 1) {
-                // lap G F = 2 F/r^3 - 6 r (r.F)/r^5
+#pragma unroll
+            for (int a = 0; a < 3; ++a) v[a] += t[3 + a] * ri + r[a] * rf;
+            if (kP) pv += rf;
+            if (kGP) {
                 const float c6 = -6.0f * rf * ri2;
-                l0 += 2.0f * t[3] * ri3 + r0 * c6;
-                l1 += 2.0f * t[4] * ri3 + r1 * c6;
-                l2 += 2.0f * t[5] * ri3 + r2 * c6;
-            } else if (OUT == 2) {
-                l0 += rf;                                // 8 pi p = 2 (r.F)/r^3
+#pragma unroll
+                for (int a = 0; a < 3; ++a) g[a] += 2.0f * t[3 + a] * ri3 + r[a] * c6;
+            }
+            if (kGU) {
+                const float c3 = -3.0f * rf * ri2;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+                        h[3 * a + b] += (r[a] * t[3 + b] - t[3 + a] * r[b]) * ri3 + r[a] * r[b] * c3 +
+                                        (a == b ? rf : 0.0f);
             }
         }
-        u[0] += double(v0);
-        u[1] += double(v1);
-        u[2] += double(v2);
-        w[0] += double(l0);
-        w[1] += double(l1);
-        w[2] += double(l2);
+        for (int a = 0; a < 3; ++a) u[a] += double(v[a]);
+        pp += 2.0 * double(pv);
+        for (int a = 0; a < 3; ++a) gp[a] += double(g[a]);
+        for (int a = 0; a < 9; ++a) gu[a] += double(h[a]);
     }
     if (!active) return;
-    if (OUT == 2) {
-        double *o = out + 4 * int64_t(perm[i]);
-        o[0] += scale_lap * kInv8Pi * 2.0 * w[0];
-        for (int k = 0; k < 3; ++k) o[1 + k] += scale * (kInv8Pi * u[k] - 0.5 * mom[k]);
+    constexpr int kStride[6] = {3, 6, 4, 16, 7, 9};
+    double *o = out + kStride[OUT] * int64_t(perm[i]);
+    const double s2 = s1 * s1, s3 = s2 * s1;
+    if (OUT == 0 || OUT == 1) {
+        for (int k = 0; k < 3; ++k) o[k] += s1 * kInv8Pi * u[k];
+        if (OUT == 1)
+            for (int k = 0; k < 3; ++k) o[3 + k] += s3 * kInv8Pi * gp[k];
         return;
     }
-    double *o = out + (OUT == 1 ? 6 : 3) * int64_t(perm[i]);
-    for (int k = 0; k < 3; ++k) o[k] += scale * kInv8Pi * u[k];
-    if (OUT == 1)
-        for (int k = 0; k < 3; ++k) o[3 + k] += scale_lap * kInv8Pi * w[k];
+    if (OUT == 5) {
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                o[3 * a + b] += s2 * kInv8Pi * ((a == b ? -pp : 0.0) + gu[3 * a + b] + gu[3 * b + a]);
+        return;
+    }
+    o[0] += s2 * kInv8Pi * pp;
+    for (int k = 0; k < 3; ++k) o[1 + k] += s1 * (kInv8Pi * u[k] - 0.5 * mom[k]);
+    if (OUT == 3 || OUT == 4)
+        for (int k = 0; k < 3; ++k) o[4 + k] += s3 * kInv8Pi * gp[k];
+    if (OUT == 3)
+        for (int k = 0; k < 9; ++k) o[7 + k] += s2 * kInv8Pi * gu[k];
 }
 
 // per-block partial sums of the first ncomp (<= 9) values of each source
@@ -297,14 +325,21 @@ hipError_t launch_stokes_far_forces(int nchunks, const double *Q, int M, const d
 }
 
 hipError_t launch_stokes_far_targets(int64_t n, const float *trg, const int32_t *perm, int mode, const double *F,
-                                     const double *Z, int M, double scale, double scale2, const double *mom,
-                                     double *out, hipStream_t s) {
+                                     const double *Z, int M, double inv_len, const double *mom, double *out,
+                                     hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const dim3 g(int((n + 255) / 256)), b(256);
     switch (mode) {
-        case 0: hipLaunchKernelGGL(stokes_far_targets_kernel<0>, g, b, 0, s, n, trg, perm, F, Z, M, scale, scale2, mom, out); break;
-        case 1: hipLaunchKernelGGL(stokes_far_targets_kernel<1>, g, b, 0, s, n, trg, perm, F, Z, M, scale, scale2, mom, out); break;
-        case 2: hipLaunchKernelGGL(stokes_far_targets_kernel<2>, g, b, 0, s, n, trg, perm, F, Z, M, scale, scale2, mom, out); break;
+#define KAFMM_FAR_TARGETS(K)                                                                                     \
+    case K: hipLaunchKernelGGL(stokes_far_targets_kernel<K>, g, b, 0, s, n, trg, perm, F, Z, M, inv_len, mom, out); \
+        break;
+        KAFMM_FAR_TARGETS(0)
+        KAFMM_FAR_TARGETS(1)
+        KAFMM_FAR_TARGETS(2)
+        KAFMM_FAR_TARGETS(3)
+        KAFMM_FAR_TARGETS(4)
+        KAFMM_FAR_TARGETS(5)
+#undef KAFMM_FAR_TARGETS
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -12,13 +12,17 @@
   force, flux and tr D), on the unit box and on a shifted box of side 2.5:
   u against the oracle's Ewald sums, p up to an additive constant (the far
   images' pressure is fitted through their flow, which fixes it only up to
-  one); non-zero net flux or tr D is rejected.
+  one); non-zero net flux or tr D is rejected;
+* PVelGrad, PVelLaplacian and Traction on the same sources, at targets
+  kept 0.02 from every source image (their oracle takes central differences
+  of the periodic (p, u)); p and the isotropic part of sigma up to a
+  constant.
 """
 import numpy as np
 import pytest
 import torch
 
-from oracle.stokes_periodic import pvel_periodic, rpy_periodic, stokeslet_periodic
+from oracle.stokes_periodic import pvel_derivs_periodic, pvel_periodic, rpy_periodic, stokeslet_periodic
 from paper_2010_15155_amd import FMM, StkfmmError, workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -228,3 +232,67 @@ def test_pvel_translation(fmm):
     e_u, e_p = _pvel_errors(outs[1], outs[0])
     print("periodic PVel translation: u", e_u, "p", e_p, flush=True)
     assert e_u < 3e-5 and e_p < 3e-5
+
+
+def _targets_away(sources, k, seed, dmin=0.02):
+    from scipy.spatial import cKDTree
+    tree = cKDTree(np.mod(sources, 1.0), boxsize=1.0)
+    rng = np.random.default_rng(seed)
+    out = np.zeros((0, 3))
+    while len(out) < k:
+        c = rng.random((4 * k, 3))
+        out = np.concatenate([out, c[tree.query(c)[0] >= dmin]])
+    return out[:k]
+
+
+DERIV_FIELDS = {"PVelGrad": [("p", 0, 1), ("u", 1, 4), ("grad p", 4, 7), ("grad u", 7, 16)],
+                "PVelLaplacian": [("p", 0, 1), ("u", 1, 4), ("lap u", 4, 7)],
+                "Traction": [("sigma", 0, 9)]}
+
+
+def _deriv_errors(kernel, got, ref):
+    errs = {}
+    for name, a, b in DERIV_FIELDS[kernel]:
+        d, r = got[:, a:b] - ref[:, a:b], ref[:, a:b].copy()
+        if name == "p":                       # up to a constant
+            d, r = d - d.mean(), r - r.mean()
+        if name == "sigma":                   # up to a constant times I
+            for x in (d, r):
+                x[:, [0, 4, 8]] -= x[:, [0, 4, 8]].mean()
+        errs[name] = float(np.linalg.norm(d) / np.linalg.norm(r))
+    return errs
+
+
+@pytest.mark.parametrize("kernel,p,tol", [("PVelGrad", 8, 2e-5), ("PVelLaplacian", 8, 2e-5), ("Traction", 8, 2e-5),
+                                          ("PVelGrad", 10, 5e-6)])
+def test_pvel_derivative_kernels(fmm, kernel, p, tol):
+    y, fq, x, D = _pvel(3000, 3000, 31)
+    t = _targets_away(np.concatenate([y, x]), 2000, 32)
+    print("periodic", kernel, "6000 sources, 2000 targets, p", p, flush=True)
+    out = fmm.evaluate(kernel, sl_xyz=cu(y), sl_val=cu(fq), dl_xyz=cu(x), dl_val=cu(D), trg_xyz=cu(t), p=p,
+                       leaf_cap=64, bc="PXYZ").cpu().numpy()
+    idx = W.sample_indices(len(t), 60, 33)
+    ref = pvel_derivs_periodic(y, fq, x, D, t[idx], h=2e-4, kind=kernel)
+    errs = _deriv_errors(kernel, out[idx], ref)
+    print("  rel L2", errs, flush=True)
+    for e in errs.values():
+        assert e < tol
+
+
+def test_traction_shifted_box():
+    # a box of side 2.5 away from the origin: sigma scales as 1/L^2
+    L, org = 2.5, np.array([-1.0, 0.4, 2.0])
+    y, fq, x, D = _pvel(3000, 3000, 34)
+    t = _targets_away(np.concatenate([y, x]), 1000, 35)
+    f = FMM(origin=tuple(org), box_len=L)
+    print("periodic Traction, box of side 2.5", flush=True)
+    try:
+        out = f.evaluate("Traction", sl_xyz=cu(org + L * y), sl_val=cu(fq), dl_xyz=cu(org + L * x), dl_val=cu(D),
+                         trg_xyz=cu(org + L * t), p=8, leaf_cap=64, bc="PXYZ").cpu().numpy()
+    finally:
+        f.close()
+    idx = W.sample_indices(len(t), 40, 36)
+    ref = pvel_derivs_periodic(org + L * y, fq, org + L * x, D, org + L * t[idx], L=L, h=2e-4 * L, kind="Traction")
+    errs = _deriv_errors("Traction", out[idx], ref)
+    print("  rel L2", errs, flush=True)
+    assert errs["sigma"] < 2e-5
