@@ -238,3 +238,40 @@ def pvel_derivs_periodic(sl, fq, dl, D, trg, L=1.0, h=None, kind="PVelGrad"):
         sig = -p[:, None, None] * np.eye(3)[None] + gu + gu.transpose(0, 2, 1)
         return sig.reshape(m, 9)
     raise ValueError(kind)
+
+
+def _lap_g(src, wf, trg):
+    """Free-space lap G applied to wf [n, 3]: (2 wf/r^3 - 6 r (r.wf)/r^5)/(8 pi)
+    summed over the sources, pairs at r = 0 left out."""
+    u = np.zeros((len(trg), 3))
+    for i0 in range(0, len(trg), 256):
+        r = trg[i0:i0 + 256, None, :] - src[None, :, :]
+        rr = np.sum(r * r, axis=2)
+        ok = rr > 0
+        ri = np.where(ok, 1.0 / np.sqrt(np.where(ok, rr, 1.0)), 0.0)
+        ri3 = ri ** 3
+        rw = np.sum(r * wf[None], axis=2)
+        u[i0:i0 + 256] = np.sum(2.0 * wf[None] * ri3[..., None] - 6.0 * r * (rw * ri3 * ri * ri)[..., None], axis=1)
+    return u / (8.0 * PI)
+
+
+def stokes_reg_periodic(src, fe, trg, L=1.0, images=1, tol=1e-15):
+    """Periodic regularized Stokeslet [f, eps] -> u [m, 3] (Sec. II.B's
+    regularized kernel, tab:ktab_reg; zero net force).  Away from a blob
+    G^eps = G + (eps^2/4) lap G + O(eps^4/r^5), so the lattice sum is the
+    Ewald sum of that far-field form (the Stokeslet and lap G sums above,
+    same convention) plus the absolutely convergent sum of the remainder
+    G^eps - G - (eps^2/4) lap G over the images with max|n_k| <= images.  A
+    target on a source takes G^eps(0) f from its own blob (the Ewald sums
+    leave r = 0 out)."""
+    from . import direct
+    y = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3)
+    fe = np.ascontiguousarray(fe, dtype=np.float64).reshape(-1, 4)
+    x = np.ascontiguousarray(trg, dtype=np.float64).reshape(-1, 3)
+    f, w = fe[:, :3], 0.25 * fe[:, 3] ** 2
+    u = stokeslet_periodic(y, f, x, L, tol=tol) + stokes_lap_periodic(y, f, w, x, L, tol=tol)
+    m = np.arange(-images, images + 1)
+    for n in np.stack(np.meshgrid(m, m, m, indexing="ij"), -1).reshape(-1, 3):
+        yn = y + L * n
+        u += direct.stokes_reg(yn, fe, x) - direct.stokeslet(yn, f, x) - _lap_g(yn, w[:, None] * f, x)
+    return u

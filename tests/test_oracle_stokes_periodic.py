@@ -245,3 +245,63 @@ def test_pvel_derivatives_next_to_a_source(layer):
         else:
             want = direct.traction(one.get("sl"), one.get("fq"), one.get("dl"), one.get("D"), x)
         assert np.abs(got - want).max() < 1e-5 * np.abs(want).max(), kind
+
+
+def _reg_problem(n, seed, eps=(1e-3, 3e-3)):
+    rng = np.random.default_rng(seed)
+    y = rng.random((n, 3))
+    f = rng.standard_normal((n, 3))
+    f -= f.mean(axis=0)
+    return rng, y, np.concatenate([f, rng.uniform(*eps, (n, 1))], 1)
+
+
+def test_regularized_without_blobs_is_the_stokeslet():
+    from oracle.stokes_periodic import stokes_reg_periodic
+    rng, y, fe = _reg_problem(30, 41)
+    x = np.concatenate([rng.random((10, 3)), y[:4]])
+    fe[:, 3] = 0.0
+    x = x[np.min(np.linalg.norm((x[:, None] - y[None] + 0.5) % 1.0 - 0.5, axis=2), axis=1) > 0]
+    got = stokes_reg_periodic(y[:], fe, x[:10])
+    assert np.allclose(got, stokeslet_periodic(y, fe[:, :3], x[:10]), rtol=0, atol=1e-13 * np.abs(got).max())
+
+
+def test_regularized_remainder_converges_absolutely():
+    # the remainder's images beyond the nearest 27 change nothing at FP64
+    from oracle.stokes_periodic import stokes_reg_periodic
+    rng, y, fe = _reg_problem(40, 42)
+    x = np.concatenate([rng.random((10, 3)), y[:5]])
+    a = stokes_reg_periodic(y, fe, x, images=1)
+    b = stokes_reg_periodic(y, fe, x, images=2)
+    assert np.abs(a - b).max() < 1e-12 * np.abs(a).max()
+
+
+def test_regularized_far_from_blobs_is_rpy_with_matching_radius():
+    # b^2 = 3 eps^2 / 2 gives (1 + b^2/6 lap) G = G + (eps^2/4) lap G: the two
+    # periodic sums (one through the RPY oracle) differ by O(eps^4/r^5) at
+    # targets 0.1 from every blob: below 1e-5 per unit force for eps <= 3e-3,
+    # while a wrong eps^2 term would leave O(eps^2/r^3), about 1e-2
+    from oracle.stokes_periodic import rpy_periodic, stokes_reg_periodic
+    rng, y, fe = _reg_problem(40, 43)
+    x = []
+    while len(x) < 6:
+        c = rng.random(3)
+        d = c - y
+        d -= np.round(d)
+        if np.min(np.linalg.norm(d, axis=1)) > 0.1:
+            x.append(c)
+    x = np.array(x)
+    fb = np.concatenate([fe[:, :3], np.sqrt(1.5) * fe[:, 3:]], 1)
+    got = stokes_reg_periodic(y, fe, x)
+    assert np.abs(got - rpy_periodic(y, fb, x)[:, :3]).max() < 1e-6 * np.abs(got).max()
+
+
+def test_regularized_on_a_blob():
+    # a target on a blob: its own G^eps(0) f = 2 f/(8 pi eps) plus the smooth
+    # rest, which the target 1e-7 off the blob shares to O(1e-7 / eps)
+    from oracle import direct
+    from oracle.stokes_periodic import stokes_reg_periodic
+    rng, y, fe = _reg_problem(30, 44)
+    on = stokes_reg_periodic(y, fe, y[:1])[0]
+    near = stokes_reg_periodic(y, fe, y[:1] + 1e-7)[0]
+    assert np.allclose(direct.stokes_reg(y[:1], fe[:1], y[:1])[0], 2 * fe[0, :3] / (8 * np.pi * fe[0, 3]))
+    assert np.abs(on - near).max() < 1e-3 * np.abs(on).max()
