@@ -243,6 +243,8 @@ bool kernel_ok(int k) { return k >= 0 && k < kNumKernels; }
 // source kinds of the packing kernel; stage_kind: of the surface tiles
 // PVel and its derivative outputs: single layer (f, q), double layer D
 bool pvel_family(int k) { return k == kPVel || k == kPVelGrad || k == kPVelLaplacian || k == kTraction; }
+// Stokes kernels with a triply periodic plan (far images through the root)
+bool periodic_stokes(int k) { return k == kStokeslet || k == kRPY || k == kStokesRegVel || pvel_family(k); }
 
 int sl_kind(int k) {
     switch (k) {
@@ -1039,11 +1041,10 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     if (bc != STKFMM_BC_OPEN && bc != STKFMM_BC_PXYZ)
         return fail(c, STKFMM_E_UNSUPPORTED, "only open, triply periodic and wall boundaries are implemented");
     if (bc == STKFMM_BC_PXYZ && kernel != STKFMM_LAP_PGRAD && kernel != STKFMM_LAP_PGRADGRAD &&
-        kernel != STKFMM_LAP_QPGRADGRAD && kernel != STKFMM_STOKESLET && kernel != STKFMM_RPY &&
-        !pvel_family(kernel))
+        kernel != STKFMM_LAP_QPGRADGRAD && !periodic_stokes(kernel))
         return fail(c, STKFMM_E_UNSUPPORTED,
-                    "triply periodic boundary is implemented for the Laplace kernels, STOKESLET, RPY, PVEL, "
-                    "PVEL_GRAD, PVEL_LAPLACIAN and TRACTION");
+                    "triply periodic boundary is implemented for the Laplace kernels, STOKESLET, RPY, "
+                    "STOKES_REG_VEL, PVEL, PVEL_GRAD, PVEL_LAPLACIAN and TRACTION");
     const bool periodic = bc == STKFMM_BC_PXYZ;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(c, hipSetDevice(c->device));
@@ -1153,7 +1154,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     stkfmm_status st = get_ops(c, p, periodic, m2l_tol, &ops);
     if (st != STKFMM_OK) return st;
     c->stk = nullptr;
-    if (periodic && (kernel == STKFMM_STOKESLET || kernel == STKFMM_RPY || pvel_family(kernel))) {
+    if (periodic && periodic_stokes(kernel)) {
         st = get_periodic_stokes(c, &c->stk);
         if (st != STKFMM_OK) return st;
         const int Mf = c->stk->M;
@@ -1705,7 +1706,7 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
     const int nc = ki.ncomp;
     const bool periodic = c->bc == STKFMM_BC_PXYZ;
     if (c->n_trg == 0) return STKFMM_OK;
-    const bool pstokes = periodic && (c->kernel == kStokeslet || c->kernel == kRPY || pvel_family(c->kernel));
+    const bool pstokes = periodic && periodic_stokes(c->kernel);
     // sums of the first ncomp values of each source and of their absolute
     // values (one reduction on the device, a fixed order on the host)
     auto value_sums = [&](int64_t n, const double *v, int stride, int ncomp, double *sum,
@@ -1866,7 +1867,9 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
             const int M = c->stk->M;
             const int nch_sl = stokes_root_chunks(c->n_sl), nch_dl = stokes_root_chunks(c->n_dl);
             double *part = c->stk_part.as<double>();
-            const int kind = c->kernel == kRPY ? 1 : pvel_family(c->kernel) ? 2 : 0;
+            // the regularized Stokeslet's records carry b^2 = 3 eps^2 / 2: its far
+            // field is RPY's
+            const int kind = c->kernel == kRPY || c->kernel == kStokesRegVel ? 1 : pvel_family(c->kernel) ? 2 : 0;
             HIP_TRY(c, launch_stokes_root_check(kind, c->n_sl, c->sl_rec.as<float>(), ki.rec_sl,
                                                 c->stk->X.as<double>(), M, part, s));
             HIP_TRY(c, launch_stokes_root_check(3, c->n_dl, c->dl_rec.as<float>(), ki.rec_dl,
