@@ -301,8 +301,9 @@ def test_traction_shifted_box():
     assert errs["sigma"] < 2e-5
 
 
-# p = 10 gains less here than for the Stokeslet (8.1e-6 -> 5.9e-6 at
-# separate targets; RPY too: 5.8e-6 -> 3.3e-6), hence one bound for both
+# p = 10 gains little here (8.1e-6 -> 5.9e-6 at separate targets): on these
+# 8192 points the periodic plans keep a floor of a few 1e-6 whatever the
+# order (the Stokeslet too), hence one bound for both
 @pytest.mark.parametrize("on_blobs,p,tol", [(False, 8, 1e-5), (True, 8, 1e-5), (False, 10, 1e-5)])
 def test_regularized(fmm, on_blobs, p, tol):
     x, f = _problem(8192, 41)
