@@ -275,3 +275,91 @@ def stokes_reg_periodic(src, fe, trg, L=1.0, images=1, tol=1e-15):
         yn = y + L * n
         u += direct.stokes_reg(yn, fe, x) - direct.stokeslet(yn, f, x) - _lap_g(yn, w[:, None] * f, x)
     return u
+
+
+def rotlet_periodic(src, t, trg, L=1.0, xi=None, tol=1e-15):
+    """Periodic rotlet sum [m, 3]: u = sum (t_j x r)/(8 pi r^3) over the
+    lattice, i.e. half the curl of the periodic Stokeslet sum with forces t
+    (curl G t = 2 (t x r)/(8 pi r^3)); k = 0 dropped, pairs at r = 0 left
+    out (the smooth part is odd).  Ewald split of the Stokeslet's:
+      real        (erfc(xi r)/r^3 + c e/r^2 - c xi^2 e) (t x r)/(8 pi),
+                  c = 2 xi/sqrt(pi), e = exp(-xi^2 r^2)  (half the curl of G_R t);
+      reciprocal  (1/(2V)) sum_{k != 0} phi(k)/k^2 Re[i k x S(k) e^{i k.x}]."""
+    from scipy.special import erfc
+    y = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3)
+    t = np.ascontiguousarray(t, dtype=np.float64).reshape(-1, 3)
+    x = np.ascontiguousarray(trg, dtype=np.float64).reshape(-1, 3)
+    xi, rc, nmax = parameters(L, xi, tol)
+    nmax += 1
+    u = np.zeros((len(x), 3))
+    if len(y) == 0 or len(x) == 0:
+        return u
+    c = 2.0 * xi / np.sqrt(PI)
+    nimg = int(np.ceil(rc / L))
+    m = np.arange(-nimg, nimg + 1)
+    imgs = np.stack(np.meshgrid(m, m, m, indexing="ij"), -1).reshape(-1, 3) * L
+    for i0 in range(0, len(x), 64):
+        d0 = x[i0:i0 + 64, None, :] - y[None, :, :]
+        d0 -= L * np.round(d0 / L)
+        for n in imgs:
+            r = d0 + n
+            rr = np.sum(r * r, axis=2)
+            ok = (rr > 0) & (rr < rc * rc)
+            rs = np.sqrt(np.where(ok, rr, 1.0))
+            e = np.exp(-xi * xi * rs * rs)
+            g = np.where(ok, erfc(xi * rs) / rs ** 3 + c * e / rs ** 2 - c * xi * xi * e, 0.0)
+            u[i0:i0 + 64] += np.sum(g[..., None] * np.cross(t[None, :, :], r), axis=1)
+    u /= 8.0 * PI
+    mm = np.arange(-nmax, nmax + 1)
+    K = np.stack(np.meshgrid(mm, mm, mm, indexing="ij"), axis=-1).reshape(-1, 3).astype(np.float64)
+    K = K[np.any(K != 0, axis=1)] * (2.0 * PI / L)
+    k2 = np.sum(K * K, axis=1)
+    phi = (1.0 + k2 / (4.0 * xi * xi)) * np.exp(-k2 / (4.0 * xi * xi))
+    S = np.zeros((len(K), 3), dtype=np.complex128)
+    for j0 in range(0, len(y), 512):
+        S += np.exp(-1j * (K @ y[j0:j0 + 512].T)) @ t[j0:j0 + 512]
+    Wk = 1j * np.cross(K, S) * (phi / k2)[:, None] / (2.0 * L ** 3)
+    for i0 in range(0, len(x), 1024):
+        u[i0:i0 + 1024] += np.real(np.exp(1j * (x[i0:i0 + 1024] @ K.T)) @ Wk)
+    return u
+
+
+def _rotlet(src, t, trg):
+    """Free-space rotlet sum (t x r)/(8 pi r^3), pairs at r = 0 left out."""
+    u = np.zeros((len(trg), 3))
+    for i0 in range(0, len(trg), 256):
+        r = trg[i0:i0 + 256, None, :] - src[None, :, :]
+        rr = np.sum(r * r, axis=2)
+        ok = rr > 0
+        ri3 = np.where(ok, 1.0 / np.sqrt(np.where(ok, rr, 1.0)) ** 3, 0.0)
+        u[i0:i0 + 256] = np.sum(ri3[..., None] * np.cross(t[None, :, :], r), axis=1)
+    return u / (8.0 * PI)
+
+
+def stokes_reg_ft_periodic(src, fte, trg, L=1.0, images=1, tol=1e-15):
+    """Periodic regularized force and torque [f, t, eps] -> [u, omega] [m, 6]
+    (Sec. II.B's force-torque extension; zero net force and torque).  Far
+    from a blob the kernels become
+      u     = G f + (eps^2/4) lap G f + rotlet(t),
+      omega = curl(u)/2 = rotlet(f) - (1/4) lap G t
+    (the rotlet is harmonic, so its eps^2 term vanishes, as does curl lap G f),
+    each summed by Ewald (same convention as above); the remainder of the
+    exact kernels is summed over the images with max|n_k| <= images."""
+    from . import direct
+    y = np.ascontiguousarray(src, dtype=np.float64).reshape(-1, 3)
+    fte = np.ascontiguousarray(fte, dtype=np.float64).reshape(-1, 7)
+    x = np.ascontiguousarray(trg, dtype=np.float64).reshape(-1, 3)
+    f, t, w = fte[:, :3], fte[:, 3:6], 0.25 * fte[:, 6] ** 2
+    q = -0.25 * np.ones(len(y))
+    out = np.zeros((len(x), 6))
+    out[:, :3] = (stokeslet_periodic(y, f, x, L, tol=tol) + stokes_lap_periodic(y, f, w, x, L, tol=tol)
+                  + rotlet_periodic(y, t, x, L, tol=tol))
+    out[:, 3:] = rotlet_periodic(y, f, x, L, tol=tol) + stokes_lap_periodic(y, t, q, x, L, tol=tol)
+    m = np.arange(-images, images + 1)
+    for n in np.stack(np.meshgrid(m, m, m, indexing="ij"), -1).reshape(-1, 3):
+        yn = y + L * n
+        far = np.zeros((len(x), 6))
+        far[:, :3] = direct.stokeslet(yn, f, x) + _lap_g(yn, w[:, None] * f, x) + _rotlet(yn, t, x)
+        far[:, 3:] = _rotlet(yn, f, x) + _lap_g(yn, q[:, None] * t, x)
+        out += direct.stokes_reg_ft(yn, fte, x) - far
+    return out

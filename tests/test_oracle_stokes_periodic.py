@@ -305,3 +305,63 @@ def test_regularized_on_a_blob():
     near = stokes_reg_periodic(y, fe, y[:1] + 1e-7)[0]
     assert np.allclose(direct.stokes_reg(y[:1], fe[:1], y[:1])[0], 2 * fe[0, :3] / (8 * np.pi * fe[0, 3]))
     assert np.abs(on - near).max() < 1e-3 * np.abs(on).max()
+
+
+def _curl_fd(fun, x, h=1e-3):
+    """Curl of fun [m, 3] at x by five-point central differences."""
+    J = np.zeros((len(x), 3, 3))                        # J[:, i, j] = d_j u_i
+    for j in range(3):
+        e = np.zeros(3)
+        e[j] = h
+        J[:, :, j] = (8 * (fun(x + e) - fun(x - e)) - (fun(x + 2 * e) - fun(x - 2 * e))) / (12 * h)
+    return np.stack([J[:, 2, 1] - J[:, 1, 2], J[:, 0, 2] - J[:, 2, 0], J[:, 1, 0] - J[:, 0, 1]], 1)
+
+
+def test_rotlet_split_parameter_independence():
+    from oracle.stokes_periodic import rotlet_periodic
+    rng, y, t = _problem(30, 51)
+    x = np.concatenate([rng.random((10, 3)), y[:4]])
+    u = [rotlet_periodic(y, t, x, xi=xi) for xi in (4.0, 6.0, 9.0)]
+    assert np.abs(u[1] - u[0]).max() < 1e-12 * np.abs(u[0]).max()
+    assert np.abs(u[2] - u[0]).max() < 1e-12 * np.abs(u[0]).max()
+
+
+def test_rotlet_is_half_the_curl_of_the_stokeslet_sum():
+    from oracle.stokes_periodic import rotlet_periodic
+    rng, y, t = _problem(30, 52)
+    x = _away_from(y, 4, rng)
+    want = 0.5 * _curl_fd(lambda p: stokeslet_periodic(y, t, p), x)
+    got = rotlet_periodic(y, t, x)
+    assert np.abs(got - want).max() < 1e-7 * np.abs(got).max()
+
+
+def _ft_problem(n, seed):
+    rng = np.random.default_rng(seed)
+    y = rng.random((n, 3))
+    ft = rng.standard_normal((n, 6))
+    ft -= ft.mean(axis=0)
+    return rng, y, np.concatenate([ft, rng.uniform(1e-3, 3e-3, (n, 1))], 1)
+
+
+def test_regularized_ft_omega_is_half_the_curl_of_u():
+    from oracle.stokes_periodic import stokes_reg_ft_periodic
+    rng, y, fte = _ft_problem(25, 53)
+    x = _away_from(y, 3, rng)
+    got = stokes_reg_ft_periodic(y, fte, x)
+    want = 0.5 * _curl_fd(lambda p: stokes_reg_ft_periodic(y, fte, p)[:, :3], x)
+    assert np.abs(got[:, 3:] - want).max() < 1e-7 * np.abs(got[:, 3:]).max()
+
+
+def test_regularized_ft_remainder_and_blob_value():
+    from oracle import direct
+    from oracle.stokes_periodic import stokes_reg_ft_periodic
+    rng, y, fte = _ft_problem(25, 54)
+    x = np.concatenate([rng.random((6, 3)), y[:3]])
+    a = stokes_reg_ft_periodic(y, fte, x, images=1)
+    b = stokes_reg_ft_periodic(y, fte, x, images=2)
+    assert np.abs(a - b).max() < 1e-12 * np.abs(a).max()
+    # on a blob: its own regularized value plus a smooth rest
+    near = stokes_reg_ft_periodic(y, fte, y[:1] + 1e-7)[0]
+    assert np.abs(a[6] - near).max() < 1e-3 * np.abs(a[6]).max()
+    own = direct.stokes_reg_ft(y[:1], fte[:1], y[:1])[0]
+    assert np.abs(own).max() > 0.1 * np.abs(a[6]).max()
