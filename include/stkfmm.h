@@ -92,8 +92,7 @@ typedef enum {
 /* Boundary conditions (Sec. III and its appendix on periodicity).  PXYZ is
  * implemented for LAP_PGRAD, LAP_PGRADGRAD and LAP_QPGRADGRAD (zero net
  * charge; Ewald's convention: no k = 0 term, no surface term) and for
- * STOKESLET, RPY, STOKES_REG_VEL, PVEL, PVEL_GRAD, PVEL_LAPLACIAN and
- * TRACTION (zero net force, and for the PVEL family zero net flux q and zero sum of tr D; the
+ * every Stokes kernel (zero net force; a net torque is allowed, and for the PVEL family zero net flux q and zero sum of tr D; the
  * Fourier series of the periodic Stokes equations without its k = 0 term,
  * i.e. zero mean velocity, summed with Hasimoto's Ewald split; the pressure,
  * and so TRACTION's isotropic part, is defined up to an additive

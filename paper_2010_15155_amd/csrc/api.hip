@@ -244,7 +244,9 @@ bool kernel_ok(int k) { return k >= 0 && k < kNumKernels; }
 // PVel and its derivative outputs: single layer (f, q), double layer D
 bool pvel_family(int k) { return k == kPVel || k == kPVelGrad || k == kPVelLaplacian || k == kTraction; }
 // Stokes kernels with a triply periodic plan (far images through the root)
-bool periodic_stokes(int k) { return k == kStokeslet || k == kRPY || k == kStokesRegVel || pvel_family(k); }
+bool periodic_stokes(int k) {
+    return k == kStokeslet || k == kRPY || k == kStokesRegVel || k == kStokesRegVelOmega || pvel_family(k);
+}
 
 int sl_kind(int k) {
     switch (k) {
@@ -1043,8 +1045,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     if (bc == STKFMM_BC_PXYZ && kernel != STKFMM_LAP_PGRAD && kernel != STKFMM_LAP_PGRADGRAD &&
         kernel != STKFMM_LAP_QPGRADGRAD && !periodic_stokes(kernel))
         return fail(c, STKFMM_E_UNSUPPORTED,
-                    "triply periodic boundary is implemented for the Laplace kernels, STOKESLET, RPY, "
-                    "STOKES_REG_VEL, PVEL, PVEL_GRAD, PVEL_LAPLACIAN and TRACTION");
+                    "triply periodic boundary is implemented for the Laplace kernels and the Stokes kernels");
     const bool periodic = bc == STKFMM_BC_PXYZ;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(c, hipSetDevice(c->device));
@@ -1869,7 +1870,10 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
             double *part = c->stk_part.as<double>();
             // the regularized Stokeslet's records carry b^2 = 3 eps^2 / 2: its far
             // field is RPY's
-            const int kind = c->kernel == kRPY || c->kernel == kStokesRegVel ? 1 : pvel_family(c->kernel) ? 2 : 0;
+            const int kind = c->kernel == kRPY || c->kernel == kStokesRegVel ? 1
+                           : pvel_family(c->kernel)         ? 2
+                           : c->kernel == kStokesRegVelOmega ? 4
+                                                             : 0;
             HIP_TRY(c, launch_stokes_root_check(kind, c->n_sl, c->sl_rec.as<float>(), ki.rec_sl,
                                                 c->stk->X.as<double>(), M, part, s));
             HIP_TRY(c, launch_stokes_root_check(3, c->n_dl, c->dl_rec.as<float>(), ki.rec_dl,
@@ -1927,7 +1931,8 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
             // far images (each output with its power of 1/L)
             const double L = c->box_len;
             const int mode = c->kernel == kRPY ? 1 : c->kernel == kPVel ? 2 : c->kernel == kPVelGrad ? 3
-                           : c->kernel == kPVelLaplacian ? 4 : c->kernel == kTraction ? 5 : 0;
+                           : c->kernel == kPVelLaplacian ? 4 : c->kernel == kTraction ? 5
+                           : c->kernel == kStokesRegVelOmega ? 6 : 0;
             const int M = c->stk->M;
             const double *V = c->stk_F.as<double>();    // check flow [3M], flux moment [3], forces [3M]
             HIP_TRY(c, launch_stokes_far_targets(c->n_trg, c->trg_rec.as<float>(), at<int32_t>(c, c->a_perm_trg),

@@ -186,12 +186,14 @@ hipError_t launch_wall_values(const WallValueArgs &a, hipStream_t s);
 hipError_t launch_wall_assemble(const WallAssembleArgs &a, hipStream_t s);
 // Triply periodic Stokes kernels (periodic.hip): the root's flow at its
 // upward check points X from sorted source records of a kind (0 Stokeslet,
-// 1 RPY, 2 PVel single layer, 3 PVel double layer; chunks of 4096 sources,
+// 1 RPY, 2 PVel single layer, 3 PVel double layer, 4 regularized force and
+// torque; chunks of 4096 sources,
 // partial sums part [chunks][3M + 3], the last 3 the flux moment); then
 // V [3M + 3] = the chunks' sum and the far images' forces F = Q V / (8 pi)
 // [3M]; targets (sorted, unit-box records) add their far-image values in
 // user order (mode 0 Stokeslet u; 1 RPY u, lap u; 2 PVel p, u; 3 PVelGrad
 // p, u, grad p, grad u; 4 PVelLaplacian p, u, lap u; 5 Traction sigma;
+// 6 force-torque u, omega;
 // modes 2-4 less the flux moment's uniform flow, mom = V + 3M; inv_len =
 // 1/L sets each output's power of the box size);
 // per-block sums of the first ncomp values of each source and of their

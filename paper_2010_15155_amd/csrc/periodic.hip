@@ -27,6 +27,8 @@ constexpr int kRootPer = 6;        // check points per thread (M <= 1536)
 //   1 RPY        f, b^2 at 9:              G f + (b^2/6) lap G f
 //   2 PVel SL    f, q at 9:                G f - q r/r^3
 //   3 PVel DL    D^s (xx xy xz yy yz zz) at 6..11:  -3 r (r.D.r)/r^5
+//   4 regularized force and torque: f, t at 9..11, b^2 = 3 eps^2/2 at 12:
+//                G f + (b^2/6) lap G f + (t x r)/r^3 (the blobs' far field)
 // (all times 8 pi).  Row stride 3M + 3: the last three entries hold the
 // chunk's flux moment sum_j w_j y_j (w = q for kind 2, tr D for kind 3, 0
 // otherwise; y relative to the root centre), which sets the uniform flow
@@ -35,7 +37,7 @@ template <int KIND>
 __global__ __launch_bounds__(256) void stokes_root_check_kernel(int64_t n, const float *__restrict__ src, int rec,
                                                                 const double *__restrict__ X, int M,
                                                                 double *__restrict__ part) {
-    constexpr int NV = KIND == 3 ? 9 : 7;
+    constexpr int NV = KIND == 3 ? 9 : KIND == 4 ? 10 : 7;
     constexpr bool kFlux = KIND == 2 || KIND == 3;
     __shared__ float tile[256 * NV];
     __shared__ double mred[kFlux ? 3 * 256 : 1];
@@ -66,7 +68,9 @@ __global__ __launch_bounds__(256) void stokes_root_check_kernel(int64_t n, const
                 for (int k = 0; k < 6; ++k) o[3 + k] = r[6 + k];
             } else {
                 for (int k = 0; k < 3; ++k) o[3 + k] = r[6 + k];
-                o[6] = KIND == 1 ? r[9] * (1.0f / 6.0f) : KIND == 2 ? r[9] : 0.0f;
+                o[6] = KIND == 1 ? r[9] * (1.0f / 6.0f) : KIND == 2 ? r[9] : KIND == 4 ? r[12] * (1.0f / 6.0f) : 0.0f;
+                if (KIND == 4)
+                    for (int k = 0; k < 3; ++k) o[7 + k] = r[9 + k];
             }
         }
         __syncthreads();
@@ -90,13 +94,18 @@ __global__ __launch_bounds__(256) void stokes_root_check_kernel(int64_t n, const
                 } else {
                     const float rdf = r0 * y[3] + r1 * y[4] + r2 * y[5];
                     // G f = f/r + r (r.f)/r^3;  RPY: + (b^2/6)(2 f/r^3 - 6 r (r.f)/r^5);  PVel: - q r/r^3
-                    const float cf = KIND == 1 ? ri + 2.0f * y[6] * ri3 : ri;
-                    const float cr = KIND == 1   ? (rdf * ri3) * (1.0f - 6.0f * y[6] * ri2)
+                    const float cf = KIND == 1 || KIND == 4 ? ri + 2.0f * y[6] * ri3 : ri;
+                    const float cr = KIND == 1 || KIND == 4 ? (rdf * ri3) * (1.0f - 6.0f * y[6] * ri2)
                                      : KIND == 2 ? (rdf - y[6]) * ri3
                                                  : rdf * ri3;
                     u0 += y[3] * cf + r0 * cr;
                     u1 += y[4] * cf + r1 * cr;
                     u2 += y[5] * cf + r2 * cr;
+                    if (KIND == 4) {    // rotlet (t x r)/r^3
+                        u0 += (y[8] * r2 - y[9] * r1) * ri3;
+                        u1 += (y[9] * r0 - y[7] * r2) * ri3;
+                        u2 += (y[7] * r1 - y[8] * r0) * ri3;
+                    }
                 }
             }
             acc[q][0] += double(u0);
@@ -166,9 +175,10 @@ __global__ __launch_bounds__(256) void stokes_far_forces_kernel(const double *__
 //   4 PVelLaplacian  p, u, lap u (= grad p)               stride 7
 //   5 Traction       sigma = -p I + grad u + grad u^T
 //                          = -6 r r^T (r.F)/r^5          stride 9
+//   6 force-torque   u, omega = curl(u)/2 = (F x r)/r^3    stride 6
 // with grad p = 2 F/r^3 - 6 r (r.F)/r^5 and
 // d_j u_i = (r_i F_j - F_i r_j + delta_ij (r.F))/r^3 - 3 (r.F) r_i r_j/r^5.
-// Scales: u by s1 = 1/L, p and sigma and grad u by 1/L^2, lap u and grad p
+// Scales: u by s1 = 1/L, p, sigma, grad u and omega by 1/L^2, lap u and grad p
 // by 1/L^3 (unit-box records).
 // PVel's flux sources (q, tr D) are potential dipoles in total (zero net
 // flux).  Their Ewald sum (the k = 0 mode dropped) has zero mean velocity;
@@ -187,6 +197,7 @@ __global__ __launch_bounds__(256) void stokes_far_targets_kernel(int64_t n, cons
     constexpr bool kP = OUT >= 2;                   // pressure
     constexpr bool kGP = OUT == 1 || OUT == 3 || OUT == 4;   // grad p (= lap u)
     constexpr bool kGU = OUT == 3 || OUT == 5;      // grad u
+    constexpr bool kW = OUT == 6;                   // omega
     __shared__ float tile[256 * 6];
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const bool active = i < n;
@@ -224,6 +235,11 @@ __global__ __launch_bounds__(256) void stokes_far_targets_kernel(int64_t n, cons
 #pragma unroll
             for (int a = 0; a < 3; ++a) v[a] += t[3 + a] * ri + r[a] * rf;
             if (kP) pv += rf;
+            if (kW) {
+                g[0] += (t[4] * r[2] - t[5] * r[1]) * ri3;
+                g[1] += (t[5] * r[0] - t[3] * r[2]) * ri3;
+                g[2] += (t[3] * r[1] - t[4] * r[0]) * ri3;
+            }
             if (kGP) {
                 const float c6 = -6.0f * rf * ri2;
 #pragma unroll
@@ -245,13 +261,15 @@ __global__ __launch_bounds__(256) void stokes_far_targets_kernel(int64_t n, cons
         for (int a = 0; a < 9; ++a) gu[a] += double(h[a]);
     }
     if (!active) return;
-    constexpr int kStride[6] = {3, 6, 4, 16, 7, 9};
+    constexpr int kStride[7] = {3, 6, 4, 16, 7, 9, 6};
     double *o = out + kStride[OUT] * int64_t(perm[i]);
     const double s2 = s1 * s1, s3 = s2 * s1;
-    if (OUT == 0 || OUT == 1) {
+    if (OUT == 0 || OUT == 1 || OUT == 6) {
         for (int k = 0; k < 3; ++k) o[k] += s1 * kInv8Pi * u[k];
         if (OUT == 1)
             for (int k = 0; k < 3; ++k) o[3 + k] += s3 * kInv8Pi * gp[k];
+        if (OUT == 6)
+            for (int k = 0; k < 3; ++k) o[3 + k] += s2 * kInv8Pi * gp[k];
         return;
     }
     if (OUT == 5) {
@@ -302,13 +320,14 @@ hipError_t launch_stokes_root_check(int kind, int64_t n_src, const float *src, i
     const int nch = stokes_root_chunks(n_src);
     if (nch == 0) return hipSuccess;
     if (M > 256 * kRootPer) return hipErrorInvalidValue;
-    if (rec < (kind == 0 ? 9 : kind == 3 ? 12 : 10)) return hipErrorInvalidValue;
+    if (rec < (kind == 0 ? 9 : kind == 3 ? 12 : kind == 4 ? 13 : 10)) return hipErrorInvalidValue;
     const dim3 g(nch), b(256);
     switch (kind) {
         case 0: hipLaunchKernelGGL(stokes_root_check_kernel<0>, g, b, 0, s, n_src, src, rec, X, M, part); break;
         case 1: hipLaunchKernelGGL(stokes_root_check_kernel<1>, g, b, 0, s, n_src, src, rec, X, M, part); break;
         case 2: hipLaunchKernelGGL(stokes_root_check_kernel<2>, g, b, 0, s, n_src, src, rec, X, M, part); break;
         case 3: hipLaunchKernelGGL(stokes_root_check_kernel<3>, g, b, 0, s, n_src, src, rec, X, M, part); break;
+        case 4: hipLaunchKernelGGL(stokes_root_check_kernel<4>, g, b, 0, s, n_src, src, rec, X, M, part); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -339,6 +358,7 @@ hipError_t launch_stokes_far_targets(int64_t n, const float *trg, const int32_t 
         KAFMM_FAR_TARGETS(3)
         KAFMM_FAR_TARGETS(4)
         KAFMM_FAR_TARGETS(5)
+        KAFMM_FAR_TARGETS(6)
 #undef KAFMM_FAR_TARGETS
         default: return hipErrorInvalidValue;
     }

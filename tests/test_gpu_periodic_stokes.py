@@ -18,14 +18,16 @@
   of the periodic (p, u)); p and the isotropic part of sigma up to a
   constant;
 * the regularized Stokeslet (blobs eps in [1e-4, 1e-3]): its far field is
-  RPY's with b^2 = 3 eps^2/2, at separate targets and on the blobs.
+  RPY's with b^2 = 3 eps^2/2, at separate targets and on the blobs;
+* the regularized force and torque (u, omega), with and without a net
+  torque (only the net force must vanish).
 """
 import numpy as np
 import pytest
 import torch
 
 from oracle.stokes_periodic import (pvel_derivs_periodic, pvel_periodic, rpy_periodic, stokeslet_periodic,
-                                    stokes_reg_periodic)
+                                    stokes_reg_ft_periodic, stokes_reg_periodic)
 from paper_2010_15155_amd import FMM, StkfmmError, workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -317,3 +319,23 @@ def test_regularized(fmm, on_blobs, p, tol):
     e = rel(out[idx], ref)
     print("  rel L2", e, flush=True)
     assert e < tol
+
+
+@pytest.mark.parametrize("on_blobs,net_torque", [(False, False), (True, False), (False, True)])
+def test_regularized_force_torque(fmm, on_blobs, net_torque):
+    rng = np.random.default_rng(51)
+    x = rng.random((4096, 3))
+    ft = rng.standard_normal((len(x), 6))
+    ft[:, :3] -= ft[:, :3].mean(axis=0)
+    if not net_torque:
+        ft[:, 3:] -= ft[:, 3:].mean(axis=0)
+    fte = np.concatenate([ft, rng.uniform(1e-4, 1e-3, (len(x), 1))], 1)
+    t = x if on_blobs else rng.random((2000, 3))
+    print("periodic StokesRegVelOmega, 4096 blobs, on blobs", on_blobs, "net torque", net_torque, flush=True)
+    out = fmm.evaluate("StokesRegVelOmega", sl_xyz=cu(x), sl_val=cu(fte), trg_xyz=cu(t), p=8, leaf_cap=64,
+                       bc="PXYZ").cpu().numpy()
+    idx = W.sample_indices(len(t), 200, 52)
+    ref = stokes_reg_ft_periodic(x, fte, t[idx])
+    e_u, e_w = rel(out[idx, :3], ref[:, :3]), rel(out[idx, 3:], ref[:, 3:])
+    print("  rel L2 u", e_u, "omega", e_w, flush=True)
+    assert e_u < 1e-5 and e_w < 1e-5
