@@ -92,11 +92,11 @@ typedef enum {
 /* Boundary conditions (Sec. III and its appendix on periodicity).  PXYZ is
  * implemented for LAP_PGRAD, LAP_PGRADGRAD and LAP_QPGRADGRAD (zero net
  * charge; Ewald's convention: no k = 0 term, no surface term) and for
- * every Stokes kernel (zero net force; a net torque is allowed, and for the PVEL family zero net flux q and zero sum of tr D; the
- * Fourier series of the periodic Stokes equations without its k = 0 term,
- * i.e. zero mean velocity, summed with Hasimoto's Ewald split; the pressure,
- * and so TRACTION's isotropic part, is defined up to an additive
- * constant).  WALL (Sec. III, the no-slip wall section,
+ * every Stokes kernel: zero net force (a net torque is allowed), and for
+ * the PVEL family also zero net flux q and a zero sum of tr D; the Fourier
+ * series of the periodic Stokes equations without its k = 0 term, i.e. zero
+ * mean velocity, summed with Hasimoto's Ewald split; the pressure, and so
+ * TRACTION's isotropic part, is defined up to an additive constant.  WALL (Sec. III, the no-slip wall section,
  * tab:rpywall) is an open domain bounded below by a no-slip wall on the
  * plane z = origin[2], for STOKESLET and RPY only, fixed p and leaf_cap only:
  * the flow is assembled from three (Stokeslet) or four (RPY) free-space
