@@ -339,3 +339,28 @@ def test_regularized_force_torque(fmm, on_blobs, net_torque):
     e_u, e_w = rel(out[idx, :3], ref[:, :3]), rel(out[idx, 3:], ref[:, 3:])
     print("  rel L2 u", e_u, "omega", e_w, flush=True)
     assert e_u < 1e-5 and e_w < 1e-5
+
+
+@pytest.mark.parametrize("kernel", ["Stokeslet", "RPY", "StokesRegVel", "StokesRegVelOmega", "PVel", "PVelGrad",
+                                    "PVelLaplacian", "Traction"])
+def test_no_sources(fmm, kernel):
+    # targets only: no source chunks reach the root's check surface
+    t = np.random.default_rng(61).random((100, 3))
+    out = fmm.evaluate(kernel, trg_xyz=cu(t), p=6, leaf_cap=20, bc="PXYZ").cpu().numpy()
+    assert np.array_equal(out, np.zeros_like(out))
+
+
+def test_single_torque_blob(fmm):
+    # one blob with a torque and no force: a net torque, one source record.
+    # Its images reach the targets mostly through the tree's expansions, which
+    # a lone rotlet stresses: u 1.7e-5 at p = 8, 3.8e-6 at p = 10 (one leaf:
+    # 3e-7; open boundary at p = 8: 2.1e-6)
+    y = np.array([[0.3, 0.6, 0.45]])
+    fte = np.array([[0.0, 0.0, 0.0, 0.4, -1.0, 0.7, 5e-4]])
+    t = np.random.default_rng(62).random((200, 3))
+    out = fmm.evaluate("StokesRegVelOmega", sl_xyz=cu(y), sl_val=cu(fte), trg_xyz=cu(t), p=10, leaf_cap=20,
+                       bc="PXYZ").cpu().numpy()
+    ref = stokes_reg_ft_periodic(y, fte, t)
+    e_u, e_w = rel(out[:, :3], ref[:, :3]), rel(out[:, 3:], ref[:, 3:])
+    print("periodic single torque blob: u", e_u, "omega", e_w, flush=True)
+    assert e_u < 1e-5 and e_w < 1e-5
