@@ -28,8 +28,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # algorithmic FP32 flops per P2P pair (FMA = 2, rsqrt = 1), counted on the
-# kernel formulas without the hi/lo coordinate refinement
-P2P_FLOPS = {"Stokeslet": 28, "RPY": 50}
+# kernel formulas without the hi/lo coordinate refinement: r, r^2 and rsqrt
+# 9, then Stokeslet +19, RPY +41, Laplace charge +11 and dipole +24 (the
+# periodic Laplace row has as many dipole as charge pairs: 26.5 on average),
+# double-layer PVel +37 and Traction +72
+P2P_FLOPS = {"Stokeslet": 28, "RPY": 50, "LapPGrad": 26.5, "PVel": 46, "Traction": 81}
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 PROFILE = os.path.join(ROOT, "profiles", "p2p_stokeslet_1M_clustered_learned.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2010_15155_amd", "csrc", f) for f in ("kernels.hip", "kernel_math.hpp")]
@@ -144,6 +147,8 @@ def measure(fmm, torch, W, kernel, x, val, p, cap, args, precision="fp32", bc="o
     serial = fmm.timings()
     fmm.set_option("overlap", "1")
     idx = torch.from_numpy(W.sample_indices(len(x), args.samples, 7)).cuda()
+    # the FP64 GPU direct sum on sampled targets (the library's own judge);
+    # the error against the CPU oracle is added by the cpu_baseline leg
     if bc == "wall":
         ref = wall_direct(fmm, torch, x, val, x[idx].contiguous())
     else:
@@ -153,9 +158,9 @@ def measure(fmm, torch, W, kernel, x, val, p, cap, args, precision="fp32", bc="o
     errs = {n: float(torch.linalg.norm(got[:, a:b] - ref[:, a:b]) / torch.linalg.norm(ref[:, a:b]))
             for n, a, b in fields}
     fmm.set_option("precision", "fp32")
-    r = {"ms_per_step": wall * 1e3, "targets_per_s": len(x) / wall, "run_ms_median": float(np.median(run_ms)),
+    r = {"_out": out, "ms_per_step": wall * 1e3, "targets_per_s": len(x) / wall, "run_ms_median": float(np.median(run_ms)),
          "p2p_ms": float(np.mean(p2p_ms)), "p2p_pairs_per_s": st["p2p_pairs"] / (np.mean(p2p_ms) * 1e-3),
-         "rel_l2": errs, "t_tree_ms": t_tree, "t_plan_ms": t_plan, "stages_ms": tm["stages_ms"],
+         "rel_l2_gpu_fp64_direct": errs, "t_tree_ms": t_tree, "t_plan_ms": t_plan, "stages_ms": tm["stages_ms"],
          "stages_serial_ms": serial["stages_ms"], "run_serial_ms": serial["t_run_ms"], "plan": st,
          "p": info["p"] if info else p, "leaf_cap": "per leaf" if cap == 0 else cap, "precision": precision,
          "bc": bc}
@@ -259,6 +264,108 @@ def tree_build(FMM, x):
     return out
 
 
+def periodic_laplace_4m(FMM, torch, W, args, n=4_194_304, p=12, cap=2000):
+    """Triply periodic Laplace charges + dipoles (zero net charge) on n uniform
+    points, SL = DL = targets, p = 12, leaf_cap 2000: time per pass, P2P rate,
+    the translation test of the periodic boundary (all points moved by one
+    vector, wrapped), and the sampled outputs that the cpu_baseline leg checks
+    against the Ewald oracle."""
+    d = W.periodic_laplace(n, 301)
+    x = torch.from_numpy(d["xyz"]).cuda()
+    q = torch.from_numpy(d["q"][:, None].copy()).cuda()
+    dp = torch.from_numpy(d["d"]).cuda()
+    fmm = FMM()
+    fmm.set_points("LapPGrad", x, x, x, p=p, leaf_cap=cap, bc="PXYZ")
+    r = timed_runs(fmm, torch, args, q, dp)
+    out = r.pop("_out")
+    idx = W.sample_indices(n, 24, 9)
+    r["_sample"] = {"idx": idx, "got": out[torch.from_numpy(idx).cuda()].cpu().numpy(), "d": d}
+    s = np.array([0.37, 0.61, 0.18])
+    xs = torch.from_numpy(np.mod(d["xyz"] + s, 1.0)).cuda()
+    fmm.set_points("LapPGrad", xs, xs, xs, p=p, leaf_cap=cap, bc="PXYZ")
+    out2 = fmm.run(q, dp)
+    dphi = out2[:, 0] - out[:, 0]
+    r["translation_rel_diff"] = {
+        "phi": float(torch.linalg.norm(dphi - dphi.mean()) / torch.linalg.norm(out[:, 0] - out[:, 0].mean())),
+        "grad_phi": float(torch.linalg.norm(out2[:, 1:] - out[:, 1:]) / torch.linalg.norm(out[:, 1:]))}
+    fmm.close()
+    r.update({"p": p, "leaf_cap": cap, "roofline": p2p_roofline("LapPGrad", r),
+              "workload": "%d uniform points in the unit cube, Laplace charges N(0,1) minus their mean and "
+                          "dipoles N(0,1)^3, SL = DL = targets, PXYZ" % n})
+    return r
+
+
+def sphere_doublelayer_2m(FMM, torch, W, args, p=10, cap=2000):
+    """Stokes double layer on the surfaces of 2000 spheres (radius 0.01, 1000
+    Fibonacci points each, N = 2,000,000), D = v n^T, DL = targets, p = 10,
+    leaf_cap 2000: PVel -> (p, u) and Traction -> sigma, each timed, with
+    sampled outputs for the cpu_baseline leg's oracle check."""
+    d = W.sphere_doublelayer(n_spheres=2000, pts_per_sphere=1000, seed=401)
+    x = torch.from_numpy(d["xyz"]).cuda()
+    D = torch.from_numpy(d["D"]).cuda()
+    idx = W.sample_indices(len(d["xyz"]), 1500, 4)
+    rows = {}
+    fmm = FMM()
+    for kernel in ("PVel", "Traction"):
+        fmm.set_points(kernel, None, x, x, p=p, leaf_cap=cap)
+        r = timed_runs(fmm, torch, args, None, D)
+        out = r.pop("_out")
+        r["_sample"] = {"idx": idx, "got": out[torch.from_numpy(idx).cuda()].cpu().numpy()}
+        r.update({"p": p, "leaf_cap": cap, "roofline": p2p_roofline(kernel, r)})
+        rows[kernel] = r
+    fmm.close()
+    rows["_d"] = d
+    rows["workload"] = ("%d points on 2000 spheres of radius 0.01 (1000 Fibonacci points each), Stokes "
+                        "double layer D = v n^T, v ~ N(0,1)^3, DL = targets, open BC" % len(d["xyz"]))
+    return rows
+
+
+def timed_runs(fmm, torch, args, sl, dl):
+    """Warm-up and timed passes of the current plan, with P2P launch times."""
+    for _ in range(args.warmup):
+        fmm.run(sl, dl)
+    torch.cuda.synchronize()
+    p2p_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = fmm.run(sl, dl)
+        p2p_ms.append(fmm.timings()["stages_ms"]["p2p"])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    st = fmm.stats()
+    fmm.set_option("overlap", "0")
+    fmm.run(sl, dl)
+    serial = fmm.timings()
+    fmm.set_option("overlap", "1")
+    n_trg = st["n_trg"]
+    return {"_out": out, "ms_per_step": wall * 1e3, "targets_per_s": n_trg / wall, "p2p_ms": float(np.mean(p2p_ms)),
+            "p2p_pairs_per_s": st["p2p_pairs"] / (np.mean(p2p_ms) * 1e-3), "stages_serial_ms": serial["stages_ms"],
+            "run_serial_ms": serial["t_run_ms"], "plan": st}
+
+
+def p2p_roofline(kernel, r):
+    """Roofline entry of the P2P kernel of a row: algorithmic FP32 flops
+    (P2P_FLOPS per pair) over its live launch time against the FP32 vector peak."""
+    f = P2P_FLOPS[kernel] * r["plan"]["p2p_pairs"] / (r["p2p_ms"] * 1e-3) / 1e12
+    return {"kernel": "p2p_kernel", "bound": "alu", "achieved": f, "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": f / FP32_VECTOR_PEAK_TFLOPS, "flops_per_pair": P2P_FLOPS[kernel],
+            "pairs_per_launch": r["plan"]["p2p_pairs"], "avg_launch_ms": r["p2p_ms"]}
+
+
+def uniform_capacities(FMM, torch, W, x, f, args, p=8, m2l_tol="2e-7"):
+    """Fixed order p with one leaf capacity everywhere, at the translation
+    rank the learned plan uses (m2l_tol = tol/50), on a context of its own:
+    the best of these is what the network's per-leaf capacities are measured
+    against."""
+    rows = {}
+    fmm = FMM()
+    fmm.set_option("m2l_tol", m2l_tol)
+    for cap in (250, 500, 1000, 2000):
+        rows["cap_%d" % cap] = measure(fmm, torch, W, "Stokeslet", x, f, p, cap, args)
+    fmm.close()
+    return rows
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -303,7 +410,7 @@ def main():
                                "sigma 0.05), sources = targets, open BC" % n,
                    "order_mode": "learned (order and per-leaf leaf_cap predicted for tol 1e-5, "
                                  "fallback fixed p=10, leaf_cap 2000)"},
-        "rel_l2": L["rel_l2"],
+        "rel_l2_gpu_fp64_direct": L["rel_l2_gpu_fp64_direct"],
         "p2p_pairs_per_s": L["p2p_pairs_per_s"],
         "learned": L,
         "roofline": {"kernel": "p2p_kernel<DStokeslet>", "bound": "alu", "achieved": achieved,
@@ -312,13 +419,24 @@ def main():
                      "flops_per_pair": P2P_FLOPS["Stokeslet"], "pairs_per_launch": L["plan"]["p2p_pairs"],
                      "avg_launch_ms": L["p2p_ms"]},
     }
+    checked = {"learned": L}          # rows whose outputs the cpu_baseline leg checks against the oracle
+    configs = {}
     if not args.only_headline:
         F = measure(fmm, torch, W, "Stokeslet", x, f, 10, 2000, args)
-        line["fixed_p10"] = F
+        line["fixed_p10"] = checked["fixed_p10"] = F
         line["learned_speedup_vs_fixed_p10"] = F["ms_per_step"] / L["ms_per_step"]
-        line["learned_split_bf16"] = measure(fmm, torch, W, "Stokeslet", x, f, 0, 0, args, "split_bf16")
+        line["learned_split_bf16"] = checked["learned_split_bf16"] = measure(
+            fmm, torch, W, "Stokeslet", x, f, 0, 0, args, "split_bf16")
         fb = torch.from_numpy(np.concatenate([d["f"], d["b"][:, None]], 1)).cuda()
-        line["rpy_fixed_p10"] = measure(fmm, torch, W, "RPY", x, fb, 10, 2000, args)
+        line["rpy_fixed_p10"] = checked["rpy_fixed_p10"] = measure(fmm, torch, W, "RPY", x, fb, 10, 2000, args)
+        U = uniform_capacities(FMM, torch, W, x, f, args)
+        best = min(U, key=lambda k: U[k]["ms_per_step"])
+        line["uniform_capacities_p8"] = {k: {"ms_per_step": v["ms_per_step"], "rel_l2_gpu_fp64_direct":
+                                             v["rel_l2_gpu_fp64_direct"], "leaf_cap": v["leaf_cap"]}
+                                         for k, v in U.items()}
+        line["learned_speedup_vs_best_uniform_p8"] = U[best]["ms_per_step"] / L["ms_per_step"]
+        for v in U.values():
+            v.pop("_out")
         # the widened rows on the same points: regularized Stokeslet (blob
         # sizes well below the smallest leaves) and RPY above a no-slip wall
         # at z = 0 (the points lie above it)
@@ -331,10 +449,23 @@ def main():
             "rpy_pxyz_p8": periodic_stokeslet(FMM, torch, n, args, kernel="RPY"),
             "pvel_pxyz_p8": periodic_stokeslet(FMM, torch, n, args, kernel="PVel"),
         }
+        for k in ("stokes_reg_vel_p8", "rpy_wall_p10"):
+            line["widened"][k].pop("_out")
+        configs["periodic_laplace_4M_p12"] = periodic_laplace_4m(FMM, torch, W, args)
+        configs["sphere_doublelayer_2M_p10"] = sphere_doublelayer_2m(FMM, torch, W, args)
         line["plan_ms"] = tree_build(FMM, x)
     fmm.close()
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(d, args.cpu_seconds, checked, configs)
+        line["rel_l2"] = line["cpu_baseline"]["rel_l2_vs_oracle"]["learned"]
+    for r in checked.values():
+        r.pop("_out", None)
+    if configs:
+        line["configs"] = configs
+        for c in configs.values():
+            c.pop("_d", None)
+            for r in [c] + [v for v in c.values() if isinstance(v, dict)]:
+                r.pop("_sample", None)
     if args.calibrate_copy > 0:
         src = torch.ones(args.calibrate_copy * (1 << 20) // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -345,26 +476,90 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(d, budget_s):
-    """The FP64 oracle direct sum on the host cores, on a bounded sample of
-    targets (all sources), scaled to targets/s."""
-    from oracle import direct
+def rel_fields(got, ref, fields):
+    return {name: float(np.linalg.norm(got[:, a:b] - ref[:, a:b]) / np.linalg.norm(ref[:, a:b]))
+            for name, a, b in fields}
+
+
+def cpu_baseline(d, budget_s, checked, configs):
+    """The CPU leg.  Times the FP64 oracle direct sum on the host cores on a
+    bounded sample of targets (all sources), scaled to targets/s, with all its
+    OpenMP threads and with one; then judges the GPU rows by the oracle: the
+    1M Stokeslet / RPY plans on those sampled targets, the periodic Laplace
+    row against the Ewald oracle on 24 sampled targets and the sphere double
+    layer rows against the direct sums on 1500 sampled targets."""
+    import platform
+    from oracle import direct, ewald
     from paper_2010_15155_amd import workloads as W
     x, f = d["xyz"], d["f"]
     n = len(x)
+    threads = direct.max_threads()
     # calibrate on a small sample, then size the timed sample to the budget
     t0 = time.perf_counter()
-    direct.stokeslet(x, f, x[:64])
-    per_target = (time.perf_counter() - t0) / 64
-    k = int(max(64, min(n, budget_s / max(per_target, 1e-9))))
+    direct.stokeslet(x, f, x[:512])
+    per_target = (time.perf_counter() - t0) / 512
+    k = int(max(512, min(n, budget_s / max(per_target, 1e-9))))
     idx = W.sample_indices(n, k, 11)
     t0 = time.perf_counter()
-    direct.stokeslet(x, f, x[idx])
+    ref = direct.stokeslet(x, f, x[idx])
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": k / dt, "unit": "targets/s", "cores": cores, "kind": "oracle",
-            "sample": "%d sampled targets x %d sources, FP64 direct Stokeslet sum (C, OpenMP)" % (k, n),
-            "seconds": dt, "pairs_per_s": k * n / dt}
+    # one thread, on a sample sized to about a tenth of the budget
+    k1 = int(max(16, min(k, 0.1 * budget_s / max(per_target * threads, 1e-9))))
+    direct.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        direct.stokeslet(x, f, x[idx[:k1]])
+        dt1 = time.perf_counter() - t0
+    finally:
+        direct.set_threads(threads)
+    model = ""
+    try:
+        model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        model = platform.processor()
+    out = {"value": k / dt, "unit": "targets/s", "cores": threads, "kind": "oracle",
+           "sample": "%d sampled targets x %d sources, FP64 direct Stokeslet sum (C, OpenMP, %d threads)"
+                     % (k, n, threads),
+           "seconds": dt, "pairs_per_s": k * n / dt, "cpu_model": model, "host_cpus": os.cpu_count(),
+           "one_thread": {"value": k1 / dt1, "unit": "targets/s", "targets": k1, "seconds": dt1,
+                          "pairs_per_s": k1 * n / dt1}}
+    # the GPU rows judged by the oracle on the same sampled targets
+    errs = {}
+    fb = np.concatenate([f, d["b"][:, None]], 1)
+    ref_rpy = None
+    for name, r in checked.items():
+        got = r["_out"][torch_index(r["_out"], idx)].cpu().numpy()
+        if name.startswith("rpy"):
+            if ref_rpy is None:
+                kr = min(k, 4096)
+                ref_rpy = direct.rpy(x, fb, x[idx[:kr]])
+            errs[name] = rel_fields(got[:len(ref_rpy)], ref_rpy, FIELDS["RPY"])
+        else:
+            errs[name] = rel_fields(got, ref, FIELDS["Stokeslet"])
+    out["rel_l2_vs_oracle"] = errs
+    c3 = configs.get("periodic_laplace_4M_p12")
+    if c3:
+        sm = c3["_sample"]
+        dd = sm["d"]
+        refp = ewald.laplace_periodic(dd["xyz"], dd["q"], dd["d"], dd["xyz"][sm["idx"]], 1.0, xi=4.0, tol=1e-12)
+        dphi = sm["got"][:, 0] - refp[:, 0]
+        c3["rel_l2_vs_oracle"] = {
+            "phi": float(np.linalg.norm(dphi - dphi.mean()) / np.linalg.norm(refp[:, 0] - refp[:, 0].mean())),
+            "grad_phi": float(np.linalg.norm(sm["got"][:, 1:] - refp[:, 1:]) / np.linalg.norm(refp[:, 1:])),
+            "targets": len(sm["idx"]), "oracle": "Ewald sum (FP64, tin-foil, k = 0 term dropped)"}
+    c4 = configs.get("sphere_doublelayer_2M_p10")
+    if c4:
+        dd = c4["_d"]
+        for kernel, fields in (("PVel", [("p", 0, 1), ("u", 1, 4)]), ("Traction", [("sigma", 0, 9)])):
+            sm = c4[kernel]["_sample"]
+            refd = direct.evaluate(kernel, None, None, dd["xyz"], dd["D"], dd["xyz"][sm["idx"]])
+            c4[kernel]["rel_l2_vs_oracle"] = dict(rel_fields(sm["got"], refd, fields), targets=len(sm["idx"]))
+    return out
+
+
+def torch_index(t, idx):
+    import torch
+    return torch.from_numpy(np.asarray(idx)).to(t.device)
 
 
 if __name__ == "__main__":

@@ -289,9 +289,10 @@ stkfmm_status stkfmm_get_plan_work(stkfmm_ctx *ctx, double *work);
  * x [batch][12], logits [batch][8], labels [batch][2] (order class, capacity
  * class), work >= stkfmm_mlp_workspace(batch) floats; grad, m, v [nparam].
  * loss_grad writes the mean cross-entropy (two heads, averaged) to *loss
- * (device) and its gradient; adam applies one bias-corrected Adam step
- * (beta 0.9, 0.999, eps 1e-8; the input scaling is not updated), step >= 1.
- * Errors: E_ARG, E_DEVICE. */
+ * (device) and its gradient; it copies the labels to the host first and
+ * returns E_ARG unless every label lies in 0..3.  adam applies one
+ * bias-corrected Adam step (beta 0.9, 0.999, eps 1e-8; the input scaling is
+ * not updated), step >= 1.  Errors: E_ARG, E_DEVICE. */
 stkfmm_status stkfmm_mlp_forward(const float *params, int64_t batch, const float *x, float *logits,
                                  float *work, void *hip_stream);
 stkfmm_status stkfmm_mlp_loss_grad(const float *params, int64_t batch, const float *x, const int32_t *labels,

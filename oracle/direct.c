@@ -30,9 +30,15 @@
  * strings in direct.py): Hessian (xx,xy,xz,yy,yz,zz), D and sigma row-major.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 
 #define PI 3.14159265358979323846
+
+/* Threads the parallel loops below use, and a way to change that (the
+ * benchmark's CPU baseline times the oracle on all host threads and on one). */
+int oracle_max_threads(void) { return omp_get_max_threads(); }
+void oracle_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 
 /* Stokeslet: f (3) -> u (3). */
 void oracle_stokeslet(int64_t ns, const double *ys, const double *f,

@@ -32,6 +32,9 @@ def lib():
         for name in ("oracle_stokeslet", "oracle_rpy", "oracle_stokes_reg", "oracle_stokes_reg_ft"):
             getattr(_lib, name).argtypes = [_i64, _dp, _dp, _i64, _dp, _dp]
         _lib.oracle_laplace.argtypes = [_i64, _dp, _dp, _i64, _dp, _dp, _i64, _dp, _dp, ctypes.c_int]
+        _lib.oracle_max_threads.argtypes = []
+        _lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        _lib.oracle_set_threads.restype = None
         _lib.oracle_laplace_quad.argtypes = [_i64, _dp, _dp, _i64, _dp, _dp]
         _lib.oracle_pvel_deriv.argtypes = [_i64, _dp, _dp, _i64, _dp, _dp, _i64, _dp, _dp, ctypes.c_int]
         for name in ("oracle_pvel", "oracle_traction"):
@@ -48,6 +51,15 @@ def lib():
         _lib.oracle_stokes_dl_ewald_real.argtypes = [_i64, _dp, _dp, _i64, _dp, ctypes.c_double, ctypes.c_double,
                                                      ctypes.c_double, _dp]
     return _lib
+
+
+def max_threads():
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().oracle_max_threads())
+
+
+def set_threads(n):
+    lib().oracle_set_threads(int(n))
 
 
 def _arr(a, cols=None):

@@ -86,21 +86,31 @@ def kernel_dims(kernel):
     return k_sl.value, k_dl.value, k_t.value
 
 
-def _ptr(t, n_cols, name):
-    """Device pointer of a contiguous float64 CUDA tensor (or None)."""
+def _ptr(t, n_cols, name, device=None, rows=None):
+    """Device pointer and row count of a contiguous float64 CUDA tensor (or
+    (None, 0)).  With `device` the tensor must live on cuda:device; with
+    `rows` it must hold exactly that many rows (the library reads or writes
+    every one of them)."""
     if t is None:
+        if rows:
+            raise ValueError("%s is required: the plan has %d of its points" % (name, rows))
         return None, 0
     import torch
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise ValueError("%s must be a contiguous float64 tensor on the GPU" % name)
+    if device is not None and t.device.index != device:
+        raise ValueError("%s is on %s, the context on cuda:%d" % (name, t.device, device))
     if n_cols and (t.dim() != 2 or t.shape[1] != n_cols) and not (n_cols == 1 and t.dim() == 1):
         raise ValueError("%s must have shape [n, %d]" % (name, n_cols))
+    if rows is not None and t.shape[0] != rows:
+        raise ValueError("%s has %d rows, the plan %d" % (name, t.shape[0], rows))
     return ctypes.c_void_p(t.data_ptr()), t.shape[0]
 
 
-def _stream():
+def _stream(device):
+    """The current torch stream of cuda:device."""
     import torch
-    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
 class FMM:
@@ -114,7 +124,7 @@ class FMM:
             raise StkfmmError(st, "stkfmm_setup")
         self.device = device
         self.kernel = None
-        self.n_trg = 0
+        self.n_sl = self.n_dl = self.n_trg = 0
 
     def _check(self, st, what):
         if st != 0:
@@ -135,24 +145,30 @@ class FMM:
         self._check(lib().stkfmm_set_option(self._h, key.encode(), str(value).encode()), "set_option")
 
     def set_points(self, kernel, sl_xyz=None, dl_xyz=None, trg_xyz=None, p=10, leaf_cap=2000, bc="open"):
-        s, ns = _ptr(sl_xyz, 3, "sl_xyz")
-        d, nd = _ptr(dl_xyz, 3, "dl_xyz")
-        t, nt = _ptr(trg_xyz, 3, "trg_xyz")
+        s, ns = _ptr(sl_xyz, 3, "sl_xyz", self.device)
+        d, nd = _ptr(dl_xyz, 3, "dl_xyz", self.device)
+        t, nt = _ptr(trg_xyz, 3, "trg_xyz", self.device)
+        self.kernel = None
         st = lib().stkfmm_set_points(self._h, KERNELS[kernel], BCS[bc], ns, s, nd, d, nt, t,
-                                     int(p), int(leaf_cap), _stream())
+                                     int(p), int(leaf_cap), _stream(self.device))
         self._check(st, "set_points")
         self.kernel = kernel
-        self.n_trg = nt
+        self.n_sl, self.n_dl, self.n_trg = ns, nd, nt
 
     def run(self, sl_val=None, dl_val=None, out=None):
+        """Evaluation pass on the points of the last set_points: sl_val [n_sl, k_sl],
+        dl_val [n_dl, k_dl] (row counts as planned), out [n_trg, k_trg] (allocated
+        when None)."""
         import torch
+        if self.kernel is None:
+            raise RuntimeError("run before a successful set_points")
         k_sl, k_dl, k_t = kernel_dims(self.kernel)
-        s, _ = _ptr(sl_val, k_sl, "sl_val")
-        d, _ = _ptr(dl_val, k_dl, "dl_val")
+        s, _ = _ptr(sl_val, k_sl, "sl_val", self.device, self.n_sl)
+        d, _ = _ptr(dl_val, k_dl, "dl_val", self.device, self.n_dl)
         if out is None:
             out = torch.empty((self.n_trg, k_t), dtype=torch.float64, device="cuda:%d" % self.device)
-        o, _ = _ptr(out, k_t, "trg_val")
-        self._check(lib().stkfmm_run(self._h, s, d, o, _stream()), "run")
+        o, _ = _ptr(out, k_t, "trg_val", self.device, self.n_trg)
+        self._check(lib().stkfmm_run(self._h, s, d, o, _stream(self.device)), "run")
         return out
 
     def evaluate(self, kernel, sl_xyz=None, sl_val=None, dl_xyz=None, dl_val=None, trg_xyz=None,
@@ -164,14 +180,15 @@ class FMM:
         """FP64 direct sum on the GPU (error judge)."""
         import torch
         k_sl, k_dl, k_t = kernel_dims(kernel)
-        s, ns = _ptr(sl_xyz, 3, "sl_xyz")
-        sv, _ = _ptr(sl_val, k_sl, "sl_val")
-        d, nd = _ptr(dl_xyz, 3, "dl_xyz")
-        dv, _ = _ptr(dl_val, k_dl, "dl_val")
-        t, nt = _ptr(trg_xyz, 3, "trg_xyz")
+        s, ns = _ptr(sl_xyz, 3, "sl_xyz", self.device)
+        sv, _ = _ptr(sl_val, k_sl, "sl_val", self.device, ns)
+        d, nd = _ptr(dl_xyz, 3, "dl_xyz", self.device)
+        dv, _ = _ptr(dl_val, k_dl, "dl_val", self.device, nd)
+        t, nt = _ptr(trg_xyz, 3, "trg_xyz", self.device)
         out = torch.empty((nt, k_t), dtype=torch.float64, device="cuda:%d" % self.device)
         o, _ = _ptr(out, k_t, "trg_val")
-        st = lib().stkfmm_direct(self._h, KERNELS[kernel], ns, s, sv, nd, d, dv, nt, t, o, _stream())
+        st = lib().stkfmm_direct(self._h, KERNELS[kernel], ns, s, sv, nd, d, dv, nt, t, o,
+                                 _stream(self.device))
         self._check(st, "direct")
         return out
 
@@ -274,7 +291,7 @@ def mlp_forward(params, x):
     w = _work(x.shape[0], x.device)
     st = lib().stkfmm_mlp_forward(_dev(params, torch.float32, "params"), int(x.shape[0]),
                                   _dev(x, torch.float32, "x"), _dev(out, torch.float32, "logits"),
-                                  _dev(w, torch.float32, "work"), _stream())
+                                  _dev(w, torch.float32, "work"), _stream(x.device.index))
     if st != 0:
         raise StkfmmError(st, "mlp_forward")
     return out
@@ -289,7 +306,7 @@ def mlp_loss_grad(params, x, labels):
     st = lib().stkfmm_mlp_loss_grad(_dev(params, torch.float32, "params"), int(x.shape[0]),
                                     _dev(x, torch.float32, "x"), _dev(labels, torch.int32, "labels"),
                                     _dev(grad, torch.float32, "grad"), _dev(loss, torch.float32, "loss"),
-                                    _dev(w, torch.float32, "work"), _stream())
+                                    _dev(w, torch.float32, "work"), _stream(x.device.index))
     if st != 0:
         raise StkfmmError(st, "mlp_loss_grad")
     return loss, grad
@@ -300,6 +317,6 @@ def mlp_adam(params, grad, m, v, step, lr):
     import torch
     st = lib().stkfmm_mlp_adam(_dev(params, torch.float32, "params"), _dev(grad, torch.float32, "grad"),
                                _dev(m, torch.float32, "m"), _dev(v, torch.float32, "v"), int(step), float(lr),
-                               _stream())
+                               _stream(params.device.index))
     if st != 0:
         raise StkfmmError(st, "mlp_adam")

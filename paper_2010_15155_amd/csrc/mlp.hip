@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <vector>
 
 #include "../../include/stkfmm.h"
 
@@ -159,6 +160,14 @@ stkfmm_status stkfmm_mlp_loss_grad(const float *params, int64_t batch, const flo
     if (!params || batch <= 0 || !x || !labels || !grad || !loss || !work) return STKFMM_E_ARG;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t B = batch;
+    {   // softmax_ce indexes the logits by label: every label must name one of the 4 classes
+        std::vector<int32_t> h(size_t(2 * B));
+        if (hipMemcpyAsync(h.data(), labels, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return STKFMM_E_DEVICE;
+        for (int32_t y : h)
+            if (y < 0 || y > 3) return STKFMM_E_ARG;
+    }
     if (run_forward(params, B, x, work, nullptr, s) != hipSuccess) return STKFMM_E_DEVICE;
     hipLaunchKernelGGL(softmax_ce, dim3(nb(B)), dim3(256), 0, s, B, labels, work);
     hipLaunchKernelGGL(loss_sum, dim3(1), dim3(1), 0, s, B, work, loss);

@@ -7,7 +7,9 @@
 * triply periodic Laplace charges + dipoles (zero net charge) against the
   Ewald oracle, at a small size on all of its structure and at N=4,194,304
   on sampled targets; plus the paper's translation test (Sec. III.C);
-* sphere double layer (PVel, Traction) on Fibonacci surface points.
+* sphere double layer (PVel, Traction) on 2000 spheres x 1000 Fibonacci
+  surface points (N = 2,000,000), p=10, leaf_cap=2000, on 1500 sampled
+  targets against the oracle's direct sums.
 """
 import numpy as np
 import pytest
@@ -158,15 +160,23 @@ def test_periodic_laplace_4M(fmm):
     assert e_phi < 1e-5 and e_grad < 1e-5
 
 
+@pytest.fixture(scope="module")
+def spheres():
+    # the sphere double-layer configuration at its full size: 2000 spheres of
+    # radius 0.01, 1000 Fibonacci points each (N = 2,000,000)
+    return W.sphere_doublelayer(n_spheres=2000, pts_per_sphere=1000, seed=401)
+
+
 @pytest.mark.parametrize("kernel", ["PVel", "Traction"])
-def test_sphere_double_layer(fmm, kernel):
-    d = W.sphere_doublelayer(n_spheres=300, pts_per_sphere=1000, seed=401)
-    x, D = d["xyz"], d["D"]
+def test_sphere_double_layer_2M(fmm, spheres, kernel):
+    x, D = spheres["xyz"], spheres["D"]
+    assert len(x) == 2_000_000
+    print("sphere double layer 2M", kernel, flush=True)
     out = fmm.evaluate(kernel, None, None, cu(x), cu(D), cu(x), p=10, leaf_cap=2000)
     idx = W.sample_indices(len(x), 1500, 4)
     got = out[torch.from_numpy(idx).cuda()].cpu().numpy()
     ref = direct.evaluate(kernel, None, None, x, D, x[idx])
     fields = [(0, 1), (1, 4)] if kernel == "PVel" else [(0, 9)]
     errs = [rel(got[:, a:b], ref[:, a:b]) for a, b in fields]
-    print(kernel, "spheres 300k", fmm.stats(), errs, flush=True)
+    print(kernel, "spheres 2M", fmm.stats(), errs, flush=True)
     assert max(errs) < 1e-5
