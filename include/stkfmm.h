@@ -172,6 +172,26 @@ stkfmm_status stkfmm_direct(stkfmm_ctx *ctx, stkfmm_kernel kernel,
                             int64_t n_trg, const double *trg_xyz, double *trg_val,
                             void *hip_stream);
 
+/* stkfmm_direct for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, the same source slices and so the same results as
+ * stkfmm_direct, bit for bit, but its partial sums live in a static device
+ * array of 2^23 doubles (64 MiB) that every GPU the library runs on holds
+ * from its first stkfmm_setup until the process ends; the call itself
+ * allocates nothing.  The caller still provides every input and output
+ * array.  Sizes whose partial sums exceed the array (slices * n_trg * k_trg
+ * doubles, only when the sources are split into slices, i.e. below about
+ * 5e5 targets: never for k_trg <= 7) return E_ARG with the sizes in the
+ * message.  Every call on one GPU shares that GPU's array and each call
+ * overwrites the part it uses, so calls that overlap on one GPU (other
+ * streams, other host threads, other contexts) race.
+ * Errors: E_ARG, E_UNSUPPORTED, E_DEVICE. */
+stkfmm_status stkfmm_direct_noalloc(stkfmm_ctx *ctx, stkfmm_kernel kernel,
+                                    int64_t n_sl, const double *sl_xyz, const double *sl_val,
+                                    int64_t n_dl, const double *dl_xyz, const double *dl_val,
+                                    int64_t n_trg, const double *trg_xyz, double *trg_val,
+                                    void *hip_stream);
+
 /* Value widths of a kernel (tab:implement).  k_dl is 0 for kernels without
  * DL sources.  Pure host function.  Errors: E_ARG (NULL output, bad kernel). */
 stkfmm_status stkfmm_kernel_dims(stkfmm_kernel kernel, int *k_sl, int *k_dl, int *k_trg);

@@ -27,7 +27,7 @@ SYMBOLS = ["stkfmm_setup", "stkfmm_set_points", "stkfmm_run", "stkfmm_evaluate",
            "stkfmm_last_error", "stkfmm_destroy", "stkfmm_mlp_nparam", "stkfmm_mlp_workspace",
            "stkfmm_set_predictor", "stkfmm_get_learned", "stkfmm_get_leaf_features",
            "stkfmm_get_plan_work", "stkfmm_mlp_forward", "stkfmm_mlp_loss_grad", "stkfmm_mlp_adam",
-           "stkfmm_get_tree"]
+           "stkfmm_get_tree", "stkfmm_direct_noalloc"]
 ORDER_CLASSES = (6, 8, 10, 12)
 CAP_CLASSES = (250, 500, 1000, 2000)
 
@@ -55,6 +55,7 @@ def lib():
     L.stkfmm_run.argtypes = [vp, vp, vp, vp, vp]
     L.stkfmm_evaluate.argtypes = [vp, ci, ci, i64, vp, vp, i64, vp, vp, i64, vp, vp, ci, ci, vp]
     L.stkfmm_direct.argtypes = [vp, ci, i64, vp, vp, i64, vp, vp, i64, vp, vp, vp]
+    L.stkfmm_direct_noalloc.argtypes = [vp, ci, i64, vp, vp, i64, vp, vp, i64, vp, vp, vp]
     L.stkfmm_kernel_dims.argtypes = [ci, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(ci)]
     L.stkfmm_set_option.argtypes = [vp, ctypes.c_char_p, ctypes.c_char_p]
     L.stkfmm_get_timings.argtypes = [vp, ctypes.POINTER(cd), ctypes.POINTER(cd), ctypes.POINTER(cd)]
@@ -176,8 +177,11 @@ class FMM:
         self.set_points(kernel, sl_xyz, dl_xyz, trg_xyz, p, leaf_cap, bc)
         return self.run(sl_val, dl_val)
 
-    def direct(self, kernel, sl_xyz=None, sl_val=None, dl_xyz=None, dl_val=None, trg_xyz=None):
-        """FP64 direct sum on the GPU (error judge)."""
+    def direct(self, kernel, sl_xyz=None, sl_val=None, dl_xyz=None, dl_val=None, trg_xyz=None, out=None,
+               noalloc=False):
+        """FP64 direct sum on the GPU (error judge) into `out` [n_trg, k_trg] (allocated
+        when None).  noalloc=True calls stkfmm_direct_noalloc, whose partial sums live
+        in the library's static device scratch instead of memory it allocates."""
         import torch
         k_sl, k_dl, k_t = kernel_dims(kernel)
         s, ns = _ptr(sl_xyz, 3, "sl_xyz", self.device)
@@ -185,11 +189,12 @@ class FMM:
         d, nd = _ptr(dl_xyz, 3, "dl_xyz", self.device)
         dv, _ = _ptr(dl_val, k_dl, "dl_val", self.device, nd)
         t, nt = _ptr(trg_xyz, 3, "trg_xyz", self.device)
-        out = torch.empty((nt, k_t), dtype=torch.float64, device="cuda:%d" % self.device)
-        o, _ = _ptr(out, k_t, "trg_val")
-        st = lib().stkfmm_direct(self._h, KERNELS[kernel], ns, s, sv, nd, d, dv, nt, t, o,
-                                 _stream(self.device))
-        self._check(st, "direct")
+        if out is None:
+            out = torch.empty((nt, k_t), dtype=torch.float64, device="cuda:%d" % self.device)
+        o, _ = _ptr(out, k_t, "trg_val", self.device, nt)
+        fn = lib().stkfmm_direct_noalloc if noalloc else lib().stkfmm_direct
+        st = fn(self._h, KERNELS[kernel], ns, s, sv, nd, d, dv, nt, t, o, _stream(self.device))
+        self._check(st, "direct_noalloc" if noalloc else "direct")
         return out
 
     def timings(self):

@@ -814,6 +814,65 @@ stkfmm_status wall_run(stkfmm_ctx *c, const double *sl_val, const double *dl_val
     return STKFMM_OK;
 }
 
+// Partial sums of stkfmm_direct_noalloc, one [slices][n_trg][k_trg] block
+// per call, in a static device array instead of a hipMalloc'd buffer (for
+// callers that cannot allocate).  Every GPU the library runs on holds its own
+// copy, at its own address, until the process ends; host code reaches it
+// only through that address, resolved once per device in stkfmm_setup.
+constexpr int64_t kDirectScratchDoubles = int64_t(1) << 23;   // 64 MiB
+static __device__ __align__(256) double scratch[kDirectScratchDoubles];
+
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_ptr;   // device -> device address of its scratch
+
+// With `device` current: the address of this device's scratch (resolved on
+// the first call for the device).
+hipError_t resolve_scratch(int device) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_ptr.count(device)) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = static_cast<double *>(ptr);
+    return hipSuccess;
+}
+
+double *scratch_ptr(int device) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
+
+// Checks and fills the arguments shared by stkfmm_direct and
+// stkfmm_direct_noalloc; the caller supplies a.work when a.slices > 1.
+stkfmm_status direct_args(stkfmm_ctx *c, stkfmm_kernel kernel, int64_t n_sl, const double *sl_xyz,
+                          const double *sl_val, int64_t n_dl, const double *dl_xyz, const double *dl_val,
+                          int64_t n_trg, const double *trg_xyz, double *trg_val, DirectArgs &a) {
+    if (!kernel_ok(int(kernel))) return fail(c, STKFMM_E_ARG, "unknown kernel");
+    const KernelInfo &ki = kInfo[kernel];
+    if (n_sl < 0 || n_dl < 0 || n_trg < 0) return fail(c, STKFMM_E_ARG, "negative size");
+    if ((n_sl > 0 && (!sl_xyz || !sl_val)) || (n_dl > 0 && (!dl_xyz || !dl_val)) ||
+        (n_trg > 0 && (!trg_xyz || !trg_val)))
+        return fail(c, STKFMM_E_ARG, "NULL array");
+    if (n_dl > 0 && ki.k_dl == 0) return fail(c, STKFMM_E_ARG, "kernel has no double-layer sources");
+    a.n_sl = n_sl;
+    a.n_dl = n_dl;
+    a.n_trg = n_trg;
+    a.sl = sl_xyz;
+    a.sl_val = sl_val;
+    a.dl = dl_xyz;
+    a.dl_val = dl_val;
+    a.trg = trg_xyz;
+    a.k_sl = ki.k_sl;
+    a.k_dl = ki.k_dl;
+    a.k_trg = ki.k_trg;
+    a.out = trg_val;
+    a.slices = direct_f64_slices(n_trg, std::max(n_sl, n_dl));
+    a.work = nullptr;
+    return STKFMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -839,7 +898,8 @@ stkfmm_status stkfmm_setup(stkfmm_ctx **out, const double origin[3], double box_
     c->device = device;
     std::memcpy(c->origin, origin, sizeof(c->origin));
     c->box_len = box_len;
-    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+    if (hipSetDevice(device) != hipSuccess || resolve_scratch(device) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return STKFMM_E_DEVICE;
     }
@@ -2160,33 +2220,44 @@ stkfmm_status stkfmm_direct(stkfmm_ctx *c, stkfmm_kernel kernel, int64_t n_sl, c
                             const double *sl_val, int64_t n_dl, const double *dl_xyz, const double *dl_val,
                             int64_t n_trg, const double *trg_xyz, double *trg_val, void *stream) {
     if (!c) return STKFMM_E_ARG;
-    if (!kernel_ok(int(kernel))) return fail(c, STKFMM_E_ARG, "unknown kernel");
-    const KernelInfo &ki = kInfo[kernel];
-    if (n_sl < 0 || n_dl < 0 || n_trg < 0) return fail(c, STKFMM_E_ARG, "negative size");
-    if ((n_sl > 0 && (!sl_xyz || !sl_val)) || (n_dl > 0 && (!dl_xyz || !dl_val)) ||
-        (n_trg > 0 && (!trg_xyz || !trg_val)))
-        return fail(c, STKFMM_E_ARG, "NULL array");
-    if (n_dl > 0 && ki.k_dl == 0) return fail(c, STKFMM_E_ARG, "kernel has no double-layer sources");
-    HIP_TRY(c, hipSetDevice(c->device));
     DirectArgs a;
-    a.n_sl = n_sl;
-    a.n_dl = n_dl;
-    a.n_trg = n_trg;
-    a.sl = sl_xyz;
-    a.sl_val = sl_val;
-    a.dl = dl_xyz;
-    a.dl_val = dl_val;
-    a.trg = trg_xyz;
-    a.k_sl = ki.k_sl;
-    a.k_dl = ki.k_dl;
-    a.k_trg = ki.k_trg;
-    a.out = trg_val;
-    a.slices = direct_f64_slices(n_trg, std::max(n_sl, n_dl));
-    a.work = nullptr;
+    const stkfmm_status st =
+        direct_args(c, kernel, n_sl, sl_xyz, sl_val, n_dl, dl_xyz, dl_val, n_trg, trg_xyz, trg_val, a);
+    if (st != STKFMM_OK) return st;
+    HIP_TRY(c, hipSetDevice(c->device));
     if (a.slices > 1) {
-        HIP_TRY(c, c->direct_work.ensure(size_t(a.slices) * size_t(n_trg) * ki.k_trg * sizeof(double)));
+        HIP_TRY(c, c->direct_work.ensure(size_t(a.slices) * size_t(n_trg) * a.k_trg * sizeof(double)));
         a.work = c->direct_work.as<double>();
     }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(c, launch_direct_f64(kernel, a, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return STKFMM_OK;
+}
+
+stkfmm_status stkfmm_direct_noalloc(stkfmm_ctx *c, stkfmm_kernel kernel, int64_t n_sl, const double *sl_xyz,
+                                    const double *sl_val, int64_t n_dl, const double *dl_xyz,
+                                    const double *dl_val, int64_t n_trg, const double *trg_xyz, double *trg_val,
+                                    void *stream) {
+    if (!c) return STKFMM_E_ARG;
+    DirectArgs a;
+    const stkfmm_status st =
+        direct_args(c, kernel, n_sl, sl_xyz, sl_val, n_dl, dl_xyz, dl_val, n_trg, trg_xyz, trg_val, a);
+    if (st != STKFMM_OK) return st;
+    if (a.slices > 1) {
+        // the same source slices as stkfmm_direct (identical sums); their
+        // partial sums must fit the static scratch
+        const int64_t need = int64_t(a.slices) * n_trg * a.k_trg;
+        if (need > kDirectScratchDoubles)
+            return fail(c, STKFMM_E_ARG,
+                        "stkfmm_direct_noalloc: " + std::to_string(a.slices) + " source slices x " +
+                            std::to_string(n_trg) + " targets x " + std::to_string(a.k_trg) +
+                            " values need " + std::to_string(need) + " doubles of workspace, above its " +
+                            std::to_string(kDirectScratchDoubles) + "-double static scratch");
+        a.work = scratch_ptr(c->device);
+        if (!a.work) return fail(c, STKFMM_E_DEVICE, "stkfmm_direct_noalloc: device scratch not resolved");
+    }
+    HIP_TRY(c, hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(c, launch_direct_f64(kernel, a, s));
     HIP_TRY(c, hipStreamSynchronize(s));

@@ -48,6 +48,7 @@ def test_kernel_dims_rejects_bad_input():
 def test_null_context_is_rejected():
     L = pkg.lib()
     assert L.stkfmm_run(None, None, None, None, None) == 1
+    assert L.stkfmm_direct_noalloc(None, 1, 0, None, None, 0, None, None, 0, None, None, None) == 1
     assert L.stkfmm_set_option(None, b"precision", b"fp32") == 1
     assert L.stkfmm_last_error(None) == b"null context"
     L.stkfmm_destroy(None)
