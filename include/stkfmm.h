@@ -112,7 +112,8 @@ typedef enum {
 } stkfmm_bc;
 
 /* Create a context for the cube [origin, origin + box_len)^3 on HIP device
- * `device`.  flags: reserved, pass 0.  Operators (surface pseudo-inverses,
+ * `device` (Sec. III: the points live in a cubic computational box, [0, L)^3
+ * in the paper's benchmarks).  flags: reserved, pass 0.  Operators (surface pseudo-inverses,
  * M2M/L2L/M2L matrices, periodic operator) are built lazily per order p on
  * first use and shared by all contexts of the process on that device (one
  * set per p, periodicity, "svd_tol" and "m2l_tol"), kept until it exits.
@@ -154,7 +155,10 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *ctx, stkfmm_kernel kernel, stkfmm_bc
 stkfmm_status stkfmm_run(stkfmm_ctx *ctx, const double *sl_val, const double *dl_val,
                          double *trg_val, void *hip_stream);
 
-/* stkfmm_set_points followed by stkfmm_run. */
+/* The kernel summation problem of Sec. I (Eq. kernelsumlinear) for two sets
+ * of sources, single layer and double layer, and one set of targets, all
+ * three independent (Sec. III, implementation): stkfmm_set_points followed
+ * by stkfmm_run. */
 stkfmm_status stkfmm_evaluate(stkfmm_ctx *ctx, stkfmm_kernel kernel, stkfmm_bc bc,
                               int64_t n_sl, const double *sl_xyz, const double *sl_val,
                               int64_t n_dl, const double *dl_xyz, const double *dl_val,
@@ -196,7 +200,10 @@ stkfmm_status stkfmm_direct_noalloc(stkfmm_ctx *ctx, stkfmm_kernel kernel,
  * DL sources.  Pure host function.  Errors: E_ARG (NULL output, bad kernel). */
 stkfmm_status stkfmm_kernel_dims(stkfmm_kernel kernel, int *k_sl, int *k_dl, int *k_trg);
 
-/* Options (strings):  "precision" = "fp32" | "split_bf16"  (M2L arithmetic),
+/* Options (strings) of the method's knobs: the equivalent-surface order and
+ * leaf size are arguments of stkfmm_set_points (Sec. III); these set the
+ * arithmetic and the other parameters.
+ * "precision" = "fp32" | "split_bf16"  (M2L arithmetic),
  * "svd_tol" = relative truncation of the check-to-equivalent pseudo-inverse
  * (default 1e-7), "overlap" = "1" (P2P concurrent with the far field, the
  * default) | "0" (serial, for per-stage timing), "tol" = accuracy target of
@@ -213,7 +220,8 @@ stkfmm_status stkfmm_kernel_dims(stkfmm_kernel kernel, int *k_sl, int *k_dl, int
 stkfmm_status stkfmm_set_option(stkfmm_ctx *ctx, const char *key, const char *value);
 
 /* Timings of the last set_points (t_tree_ms) and run (t_run_ms, device event
- * time).  stage_ms[16] (may be NULL) receives per-stage device times of the
+ * time): the tree-construction and tree-traversal times the paper reports
+ * separately (Sec. III, t_tree and t_run).  stage_ms[16] (may be NULL) receives per-stage device times of the
  * last run in the order: 0 pack, 1 S2M, 2 M2M+UC2UE, 3 M2L, 4 S2L (X list)
  * and the periodic operator, 5 L2L+DC2DE, 6 L2T+M2T, 7 P2P, 8 combine;
  * others 0.  P2P runs on an internal stream concurrently with stages 1-6

@@ -480,8 +480,10 @@ __global__ __launch_bounds__(128 * WR) void gemm_f32_mfma(GemmArgs a) {
         const int c = bcol_ok[i] ? a.bcol[tile.y + br[i]] : 0;
         bptr[i] = a.X + int64_t(c) * a.xs;
     }
-    for (int k0 = 0; k0 < a.Mk; k0 += kGK) {
-        float4 ra[NA], rb[NB];
+    // the next K step's tiles are fetched into registers while the MFMAs
+    // run on the current one (one LDS buffer, two barriers per step)
+    float4 ra[NA], rb[NB];
+    auto fetch = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < NA; ++i)
             ra[i] = arow_ok[i] ? *reinterpret_cast<const float4 *>(A + int64_t(row0 + ar[i]) * a.K + k0 + ak[i])
@@ -489,6 +491,9 @@ __global__ __launch_bounds__(128 * WR) void gemm_f32_mfma(GemmArgs a) {
 #pragma unroll
         for (int i = 0; i < NB; ++i)
             rb[i] = bcol_ok[i] ? *reinterpret_cast<const float4 *>(bptr[i] + k0 + bk[i]) : make_float4(0, 0, 0, 0);
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < a.Mk; k0 += kGK) {
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
@@ -502,6 +507,7 @@ __global__ __launch_bounds__(128 * WR) void gemm_f32_mfma(GemmArgs a) {
             db[0] = rb[i].x; db[1] = rb[i].y; db[2] = rb[i].z; db[3] = rb[i].w;
         }
         __syncthreads();
+        if (k0 + kGK < a.Mk) fetch(k0 + kGK);
         const int kend = min(kGK, a.Mk - k0);
 #pragma unroll
         for (int kk = 0; kk < kGK; kk += 2) {
@@ -1410,11 +1416,17 @@ static bool gemm_args_ok(const GemmArgs &a) {
 hipError_t launch_gemm_f32(int ntiles, const GemmArgs &a, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     if (!gemm_args_ok(a)) return hipErrorInvalidValue;
-    // 192-row tiles when they cover R exactly and 128-row tiles do not
-    if (a.R % 192 == 0 && a.R % 128 != 0)
-        hipLaunchKernelGGL(gemm_f32_mfma<3>, dim3(ntiles, a.R / 192), dim3(384), 0, s, a);
-    else
-        hipLaunchKernelGGL(gemm_f32_mfma<2>, dim3(ntiles, (a.R + kGT - 1) / kGT), dim3(256), 0, s, a);
+    // row tiles of 64 WR rows (WR = 2..4): the fewest padded rows, then the
+    // fewest row blocks (each row block reads the column tile again)
+    int wr = 2;
+    for (int w = 3; w <= 4; ++w) {
+        const int pad_w = (a.R + 64 * w - 1) / (64 * w) * 64 * w, pad_r = (a.R + 64 * wr - 1) / (64 * wr) * 64 * wr;
+        if (pad_w < pad_r || (pad_w == pad_r && pad_w / (64 * w) < pad_r / (64 * wr))) wr = w;
+    }
+    const int rblocks = (a.R + 64 * wr - 1) / (64 * wr);
+    if (wr == 4) hipLaunchKernelGGL(gemm_f32_mfma<4>, dim3(ntiles, rblocks), dim3(512), 0, s, a);
+    else if (wr == 3) hipLaunchKernelGGL(gemm_f32_mfma<3>, dim3(ntiles, rblocks), dim3(384), 0, s, a);
+    else hipLaunchKernelGGL(gemm_f32_mfma<2>, dim3(ntiles, rblocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
