@@ -7,7 +7,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["direct.c", "ewald.c"]
+SOURCES = ["direct.c", "ewald.c", "stokes_dp.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
