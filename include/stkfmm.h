@@ -96,7 +96,14 @@ typedef enum {
  * the PVEL family also zero net flux q and a zero sum of tr D; the Fourier
  * series of the periodic Stokes equations without its k = 0 term, i.e. zero
  * mean velocity, summed with Hasimoto's Ewald split; the pressure, and so
- * TRACTION's isotropic part, is defined up to an additive constant.  WALL (Sec. III, the no-slip wall section,
+ * TRACTION's isotropic part, is defined up to an additive constant.  PXY
+ * (periodic in x and y with period box_len, open in z) is implemented for
+ * STOKESLET and RPY: zero net force; the Fourier series in x and y whose
+ * k = 0 mode is the sheet flow u_xy(z) = -(1/2A) sum_j f_j,xy |z - z_j|
+ * (A = box_len^2, no added constant: far above and below the sources the
+ * flow tends to +-(1/2A) sum_j f_j,xy z_j), summed with Hasimoto's Ewald
+ * split; points are wrapped in x and y and must lie in
+ * [origin_z, origin_z + box_len) in z.  WALL (Sec. III, the no-slip wall section,
  * tab:rpywall) is an open domain bounded below by a no-slip wall on the
  * plane z = origin[2], for STOKESLET and RPY only, fixed p and leaf_cap only:
  * the flow is assembled from three (Stokeslet) or four (RPY) free-space
@@ -131,7 +138,7 @@ stkfmm_status stkfmm_setup(stkfmm_ctx **out, const double origin[3], double box_
  * targets, SL or DL sources (Sec. III uses 2000); >= 1, or 0 for learned
  * per-leaf capacities (see the learned mode below).
  * Open BC: every point must lie in [origin, origin+box_len)^3, else E_DOMAIN.
- * PXYZ: points are wrapped into the box.
+ * PXYZ: points are wrapped into the box; PXY: wrapped in x and y.
  * Errors: E_ARG, E_DOMAIN, E_UNSUPPORTED, E_NOMEM, E_DEVICE. */
 stkfmm_status stkfmm_set_points(stkfmm_ctx *ctx, stkfmm_kernel kernel, stkfmm_bc bc,
                                 int64_t n_sl, const double *sl_xyz,
@@ -144,7 +151,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *ctx, stkfmm_kernel kernel, stkfmm_bc
  * (overwritten, user order).  Periodic LAP_PGRAD requires sum q = 0
  * (relative to sum |q|, 1e-9), else E_DOMAIN; its potential is defined up to
  * an additive constant (the Ewald convention with the k = 0 term dropped).
- * Periodic Stokes kernels require each component of sum f to vanish
+ * Periodic Stokes kernels (PXYZ and PXY) require each component of sum f to vanish
  * (relative to sum |f_k|, 1e-9), else E_DOMAIN; the periodic PVEL family
  * (PVEL, PVEL_GRAD, PVEL_LAPLACIAN, TRACTION) also requires sum q = 0
  * (relative to the sum of |f_k| and |q|) and sum tr D = 0 over the double

@@ -248,6 +248,13 @@ bool periodic_stokes(int k) {
     return k == kStokeslet || k == kRPY || k == kStokesRegVel || k == kStokesRegVelOmega || pvel_family(k);
 }
 
+// Stokes kernels with a doubly periodic plan: point forces, with or without
+// the RPY correction
+bool doubly_periodic_stokes(int k) { return k == kStokeslet || k == kRPY; }
+
+// periodic axes of a boundary condition: bit k set = periodic in axis k
+int bc_axes(int bc) { return bc == STKFMM_BC_PXYZ ? 7 : bc == STKFMM_BC_PXY ? 3 : 0; }
+
 int sl_kind(int k) {
     switch (k) {
         case kStokeslet: return 0;
@@ -362,21 +369,21 @@ stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, double m2l_tol, Devic
     return STKFMM_OK;
 }
 
-// The triply periodic Stokeslet's far-image operator, one per (device,
-// svd_tol), built on first use and kept like the operator sets.
-std::map<std::tuple<int, double>, std::unique_ptr<StokesFarOps>> *g_stk =
-    new std::map<std::tuple<int, double>, std::unique_ptr<StokesFarOps>>();
+// The periodic Stokeslet's far-image operator, one per (device, periodic
+// axes, svd_tol), built on first use and kept like the operator sets.
+std::map<std::tuple<int, int, double>, std::unique_ptr<StokesFarOps>> *g_stk =
+    new std::map<std::tuple<int, int, double>, std::unique_ptr<StokesFarOps>>();
 
-stkfmm_status get_periodic_stokes(stkfmm_ctx *c, StokesFarOps **out) {
+stkfmm_status get_periodic_stokes(stkfmm_ctx *c, int pmask, StokesFarOps **out) {
     std::lock_guard<std::mutex> lock(g_ops_mutex);
-    const auto key = std::make_tuple(c->device, c->svd_tol);
+    const auto key = std::make_tuple(c->device, pmask, c->svd_tol);
     auto it = g_stk->find(key);
     if (it != g_stk->end()) {
         *out = it->second.get();
         return STKFMM_OK;
     }
     std::vector<double> Q, X, Z;
-    std::string e = build_periodic_stokes(kStokesFarOrder, c->svd_tol, Q, X, Z);
+    std::string e = build_periodic_stokes(kStokesFarOrder, c->svd_tol, pmask == 3, Q, X, Z);
     if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
     auto d = std::make_unique<StokesFarOps>();
     d->M = int(X.size() / 3);
@@ -621,11 +628,11 @@ stkfmm_status run_pinv(stkfmm_ctx *c, const PinvLevel &pl, const double *P, cons
     return STKFMM_OK;
 }
 
-stkfmm_status validate_points(stkfmm_ctx *c, const std::vector<double> &h, int64_t n, bool periodic,
+stkfmm_status validate_points(stkfmm_ctx *c, const std::vector<double> &h, int64_t n, int pmask,
                               const char *what) {
     for (int64_t i = 0; i < 3 * n; ++i) {
         if (!std::isfinite(h[i])) return fail(c, STKFMM_E_ARG, std::string(what) + ": non-finite coordinate");
-        if (!periodic) {
+        if (!((pmask >> (i % 3)) & 1)) {
             double u = (h[i] - c->origin[i % 3]) / c->box_len;
             if (!(u >= 0.0 && u < 1.0))
                 return fail(c, STKFMM_E_DOMAIN, std::string(what) + ": point outside [origin, origin+box_len)");
@@ -635,8 +642,8 @@ stkfmm_status validate_points(stkfmm_ctx *c, const std::vector<double> &h, int64
 }
 
 // Host copies of point sets (device [n][3]) normalised to the unit box,
-// wrapped if periodic; optionally validated first.
-stkfmm_status copy_coords(stkfmm_ctx *c, const double *const src[3], const int64_t cnt[3], bool periodic,
+// wrapped in the periodic axes (bits of pmask); optionally validated first.
+stkfmm_status copy_coords(stkfmm_ctx *c, const double *const src[3], const int64_t cnt[3], int pmask,
                           bool validate, std::vector<double> h[3], hipStream_t s) {
     for (int k = 0; k < 3; ++k) {
         h[k].resize(3 * cnt[k]);
@@ -647,12 +654,12 @@ stkfmm_status copy_coords(stkfmm_ctx *c, const double *const src[3], const int64
     const char *names[3] = {"sl_xyz", "dl_xyz", "trg_xyz"};
     for (int k = 0; k < 3; ++k) {
         if (validate) {
-            stkfmm_status st = validate_points(c, h[k], cnt[k], periodic, names[k]);
+            stkfmm_status st = validate_points(c, h[k], cnt[k], pmask, names[k]);
             if (st != STKFMM_OK) return st;
         }
         for (int64_t i = 0; i < 3 * cnt[k]; ++i) {
             double u = (h[k][i] - c->origin[i % 3]) / c->box_len;
-            if (periodic) {
+            if ((pmask >> (i % 3)) & 1) {
                 u -= std::floor(u);
                 if (u >= 1.0) u = 0.0;
             }
@@ -1100,13 +1107,18 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     if (learned && bc != STKFMM_BC_OPEN) return fail(c, STKFMM_E_UNSUPPORTED, "learned mode is open-boundary only");
     if (bc == STKFMM_BC_WALL)
         return wall_set_points(c, int(kernel), n_sl, sl_xyz, n_trg, trg_xyz, p, leaf_cap, stream);
-    if (bc != STKFMM_BC_OPEN && bc != STKFMM_BC_PXYZ)
-        return fail(c, STKFMM_E_UNSUPPORTED, "only open, triply periodic and wall boundaries are implemented");
+    if (bc != STKFMM_BC_OPEN && bc != STKFMM_BC_PXYZ && bc != STKFMM_BC_PXY)
+        return fail(c, STKFMM_E_UNSUPPORTED,
+                    "only open, doubly and triply periodic and wall boundaries are implemented");
     if (bc == STKFMM_BC_PXYZ && kernel != STKFMM_LAP_PGRAD && kernel != STKFMM_LAP_PGRADGRAD &&
         kernel != STKFMM_LAP_QPGRADGRAD && !periodic_stokes(kernel))
         return fail(c, STKFMM_E_UNSUPPORTED,
                     "triply periodic boundary is implemented for the Laplace kernels and the Stokes kernels");
-    const bool periodic = bc == STKFMM_BC_PXYZ;
+    if (bc == STKFMM_BC_PXY && !doubly_periodic_stokes(kernel))
+        return fail(c, STKFMM_E_UNSUPPORTED,
+                    "doubly periodic boundary is implemented for the Stokeslet and RPY");
+    const int pmask = bc_axes(bc);
+    const bool periodic = pmask != 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(c, hipSetDevice(c->device));
     auto t0 = std::chrono::steady_clock::now();
@@ -1119,12 +1131,12 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     std::vector<double> h[3];
     const bool host_coords = learned || !c->tree_gpu;
     if (host_coords) {
-        stkfmm_status st = copy_coords(c, src, cnt, periodic, true, h, s);
+        stkfmm_status st = copy_coords(c, src, cnt, pmask, true, h, s);
         if (st != STKFMM_OK) return st;
     } else {
         for (int k = 0; k < 3; ++k) {
             bool nonfinite = false, outside = false;
-            std::string e = check_points_gpu(src[k], cnt[k], c->origin, c->box_len, periodic, &nonfinite, &outside, stream);
+            std::string e = check_points_gpu(src[k], cnt[k], c->origin, c->box_len, pmask, &nonfinite, &outside, stream);
             if (!e.empty()) return fail(c, STKFMM_E_DEVICE, e);
             if (nonfinite) return fail(c, STKFMM_E_ARG, std::string(names[k]) + ": non-finite coordinate");
             if (outside)
@@ -1147,17 +1159,17 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     std::string e;
     // the octree on the GPU from the caller's coordinates, or on the host
     // from the normalised copies (the same tree)
-    auto build = [&](int cap, bool per, const std::unordered_map<uint64_t, int> *caps) {
-        if (c->tree_gpu) return build_tree_gpu(src, cnt, c->origin, c->box_len, cap, per, t, caps, stream);
-        return build_tree(h[0].data(), n_sl, h[1].data(), n_dl, h[2].data(), n_trg, cap, per, t, caps);
+    auto build = [&](int cap, int pm, const std::unordered_map<uint64_t, int> *caps) {
+        if (c->tree_gpu) return build_tree_gpu(src, cnt, c->origin, c->box_len, cap, pm, t, caps, stream);
+        return build_tree(h[0].data(), n_sl, h[1].data(), n_dl, h[2].data(), n_trg, cap, pm, t, caps);
     };
     if (!learned) {
-        e = build(leaf_cap, periodic, nullptr);
+        e = build(leaf_cap, pmask, nullptr);
         if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
     } else {
         // reference tree, per-leaf features, network on the GPU
         const int ref_cap = leaf_cap ? leaf_cap : kReferenceCap;
-        e = build(ref_cap, false, nullptr);
+        e = build(ref_cap, 0, nullptr);
         if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
         std::vector<float> feat;
         leaf_features(t, h[0].data(), h[1].data(), h[2].data(), c->tol, feat);
@@ -1212,11 +1224,12 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     // learned plans size the translation compression to the error budget
     // (rank 160 at p = 8 for tol 1e-5) unless the caller set m2l_tol
     const double m2l_tol = learned && !c->m2l_tol_set && c->m2l_tol > 0 ? c->tol / 50.0 : c->m2l_tol;
-    stkfmm_status st = get_ops(c, p, periodic, m2l_tol, &ops);
+    // the Laplace far-image operator is for triply periodic Laplace plans
+    stkfmm_status st = get_ops(c, p, bc == STKFMM_BC_PXYZ, m2l_tol, &ops);
     if (st != STKFMM_OK) return st;
     c->stk = nullptr;
     if (periodic && periodic_stokes(kernel)) {
-        st = get_periodic_stokes(c, &c->stk);
+        st = get_periodic_stokes(c, pmask, &c->stk);
         if (st != STKFMM_OK) return st;
         const int Mf = c->stk->M;
         const int nch = stokes_root_chunks(n_sl) + stokes_root_chunks(n_dl);
@@ -1765,7 +1778,7 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
     const Tree &t = c->tree;
     const DeviceOps &o = *c->ops;
     const int nc = ki.ncomp;
-    const bool periodic = c->bc == STKFMM_BC_PXYZ;
+    const bool periodic = bc_axes(c->bc) != 0;
     if (c->n_trg == 0) return STKFMM_OK;
     const bool pstokes = periodic && periodic_stokes(c->kernel);
     // sums of the first ncomp values of each source and of their absolute
@@ -1921,7 +1934,7 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         if (st != STKFMM_OK) return st;
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 4 M2L
         HIP_TRY(c, s2c(c->s2l, kAlphaIn, dnchk, 1));
-        if (periodic && nc == 1) HIP_TRY(c, launch_periodic(o.tm2l.as<double>(), updens, dnchk, o.M, o.Mp, nc, 0, s));
+        if (c->bc == STKFMM_BC_PXYZ && nc == 1) HIP_TRY(c, launch_periodic(o.tm2l.as<double>(), updens, dnchk, o.M, o.Mp, nc, 0, s));
         if (pstokes) {
             // the root's flow at its check points: single layer, then double
             // layer chunks, summed in that order
@@ -2169,7 +2182,7 @@ stkfmm_status stkfmm_get_leaf_features(stkfmm_ctx *c, float *features, int32_t *
         if (!c->hcoords_valid) {
             const double *src[3] = {c->coords[0].as<double>(), c->coords[1].as<double>(), c->coords[2].as<double>()};
             const int64_t cnt[3] = {c->n_sl, c->n_dl, c->n_trg};
-            stkfmm_status st = copy_coords(c, src, cnt, c->bc == STKFMM_BC_PXYZ, false, c->hcoords, nullptr);
+            stkfmm_status st = copy_coords(c, src, cnt, bc_axes(c->bc), false, c->hcoords, nullptr);
             if (st != STKFMM_OK) return st;
             c->hcoords_valid = true;
         }

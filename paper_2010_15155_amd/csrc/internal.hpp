@@ -62,7 +62,7 @@ struct Tree {
     std::vector<int32_t> perm_sl, perm_dl, perm_trg;  // sorted position -> user index
     std::vector<uint64_t> keys_sl, keys_dl, keys_trg; // sorted Morton keys
     int depth = 0;
-    bool periodic = false;
+    int pmask = 0;                   // periodic axes: bit k set = periodic in axis k
     // Interaction lists (CSR by box id).
     std::vector<int> u_off, w_off, x_off, v_off;
     std::vector<Entry> u, w, x;      // U, W per leaf; X per box
@@ -73,24 +73,24 @@ struct Tree {
 };
 
 // Build the octree and interaction lists.  Coordinates are normalised to
-// [0,1) (already wrapped for periodic trees).  Returns an empty string or an
+// [0,1) (already wrapped in the periodic axes, bits of pmask).  Returns an empty string or an
 // error message.
 // leaf_caps (optional): capacity of the boxes named by box_hash and of their
 // descendants; other boxes use leaf_cap.
 std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t n_dl,
-                       const double *trg, int64_t n_trg, int leaf_cap, bool periodic, Tree &t,
+                       const double *trg, int64_t n_trg, int leaf_cap, int pmask, Tree &t,
                        const std::unordered_map<uint64_t, int> *leaf_caps = nullptr);
 
 // The same tree built on the GPU from the caller's device coordinates
 // (sl, dl, trg: [n][3] FP64, normalised with origin and box_len, wrapped if
-// periodic), on the HIP stream `stream`.  Leaves keys_* empty.
+// in the periodic axes of pmask), on the HIP stream `stream`.  Leaves keys_* empty.
 std::string build_tree_gpu(const double *const xyz[3], const int64_t n[3], const double origin[3], double box_len,
-                           int leaf_cap, bool periodic, Tree &t,
+                           int leaf_cap, int pmask, Tree &t,
                            const std::unordered_map<uint64_t, int> *leaf_caps, void *stream);
 
 // Checks the caller's device coordinates [n][3] on the GPU: any not finite,
-// and (open boundary) any point outside [origin, origin + box_len)^3.
-std::string check_points_gpu(const double *xyz, int64_t n, const double origin[3], double box_len, bool periodic,
+// and any coordinate of an open (non-periodic) axis outside [origin, origin + box_len).
+std::string check_points_gpu(const double *xyz, int64_t n, const double origin[3], double box_len, int pmask,
                              bool *nonfinite, bool *outside, void *stream);
 
 // V-list anchor offsets, local-expansion flags and the P2P pair count of a
@@ -133,14 +133,15 @@ struct Operators {
 // them dense.
 std::string build_operators(int p, double svd_tol, bool periodic, Operators &ops, double m2l_tol = 0.0);
 
-// Far images of the triply periodic Stokeslet at the root (unit box centred
-// at the origin): Q [3M][3M] maps the root's flow at its M upward check
-// points X [M][3] (the Stokeslet sum of the sources inside the root) to
-// Stokeslet forces on the M downward equivalent points Z [M][3] whose flow
-// inside the root is that of all images n with max|n_k| >= 2 (Hasimoto's
-// Ewald sum, zero net force).
-std::string build_periodic_stokes(int p, double svd_tol, std::vector<double> &Q, std::vector<double> &X,
-                                  std::vector<double> &Z);
+// Far images of the periodic Stokeslet at the root (unit box centred at the
+// origin): Q [3M][3M] maps the root's flow at its M upward check points
+// X [M][3] (the Stokeslet sum of the sources inside the root) to Stokeslet
+// forces on the M downward equivalent points Z [M][3] whose flow inside the
+// root is that of the far images (Hasimoto's Ewald sums, zero net force):
+// triply periodic, every n with max|n_k| >= 2; doubly periodic (x, y), the
+// in-plane n = (n_x, n_y, 0) with max(|n_x|, |n_y|) >= 2.
+std::string build_periodic_stokes(int p, double svd_tol, bool doubly, std::vector<double> &Q,
+                                  std::vector<double> &X, std::vector<double> &Z);
 
 // Index of a relative offset o in [-3,3]^3.
 inline int offset_index(int ox, int oy, int oz) { return ((oz + 3) * 7 + (oy + 3)) * 7 + (ox + 3); }

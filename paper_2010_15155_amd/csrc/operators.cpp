@@ -274,6 +274,107 @@ struct StokesFarImages {
     }
 };
 
+// Far images of the doubly periodic Stokeslet (periods 1 in x and y, open in
+// z) of a unit force at separation r: the in-plane images n = (n_x, n_y, 0)
+// with max(|n_x|, |n_y|) >= 2, i.e. the doubly periodic Ewald sum minus the 9
+// near images.  The sum is the Fourier series in x and y; its k_par = 0 mode
+// is the sheet flow -|z|/2 (zero net force, no added constant).  With
+// Hasimoto's split and kappa = |k_par|:
+//   real part     the screened kernel G_R (as above) over the far images;
+//   near images   minus their smooth part G - G_R (2c I/(8 pi) at r = 0);
+//   spectral      per mode k_par != 0 the k_z integral of phi (I - k k^T/k^2)/k^2:
+//                 G_ab = cos(k.r) (delta_ab I2 - k_a k_b I4),
+//                 G_az = G_za = sin(k.r) k_a z E2/2,  G_zz = cos(k.r) kappa^2 I4,
+//                 E2 = (e^{kappa z} erfc(kappa/2xi + xi z) + e^{-kappa z} erfc(kappa/2xi - xi z))/(4 kappa),
+//                 E0 = (xi/sqrt(pi)) g, g = e^{-kappa^2/4xi^2 - xi^2 z^2},  I2 = E2 + E0/(4 xi^2),
+//                 I4 = -(1/2 kappa) dE2/dkappa
+//                    = E2/(2 kappa^2) - (z D - 2 g/(xi sqrt(pi)))/(8 kappa^2),
+//                 D = e^{kappa z} erfc(kappa/2xi + xi z) - e^{-kappa z} erfc(kappa/2xi - xi z);
+//                 the mode k_par = 0: G_ab = delta_ab (-z erf(xi z)/2 - e^{-xi^2 z^2}/(4 xi sqrt(pi))).
+struct StokesFarImages2P {
+    double xi, rc, c;
+    int nk;
+
+    StokesFarImages2P() {
+        xi = 4.0;
+        const double s = std::sqrt(-std::log(1e-16)) + 0.5;
+        rc = s / xi;
+        c = 2.0 * xi / std::sqrt(kPi);
+        nk = int(std::ceil(2.0 * xi * s / (2.0 * kPi)));
+    }
+
+    // e^{sg kappa Z} erfc(kappa/2xi + sg xi Z), Z >= 0, without overflow:
+    // g * exp(a^2) erfc(a) when a >= 0 (asymptotic series for large a)
+    double exp_erfc(double kap, double Z, double g, double sg) const {
+        const double a = kap / (2.0 * xi) + sg * xi * Z;
+        if (a < 0.0) return std::exp(sg * kap * Z) * std::erfc(a);
+        double sx;
+        if (a < 26.0) {
+            sx = std::exp(a * a) * std::erfc(a);
+        } else {
+            double term = 1.0, sum = 1.0;
+            const double h = 1.0 / (2.0 * a * a);
+            for (int n = 1; n < 40; ++n) {
+                const double nx = -term * (2 * n - 1) * h;
+                if (std::fabs(nx) >= std::fabs(term) || std::fabs(nx) < 1e-17) break;
+                term = nx;
+                sum += nx;
+            }
+            sx = sum / (a * std::sqrt(kPi));
+        }
+        return g * sx;
+    }
+
+    // far-image block at separation r, added to B (3x3)
+    void block(const double r[3], double B[9]) const {
+        const double inv8pi = 1.0 / (8.0 * kPi);
+        auto add = [&](const double x[3], double A, double Bc) {
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) B[3 * i + j] += (i == j ? A : 0.0) + Bc * x[i] * x[j];
+        };
+        const int nr = int(std::ceil(rc)) + 2;
+        for (int a = -nr; a <= nr; ++a)
+            for (int b = -nr; b <= nr; ++b) {
+                const double x[3] = {r[0] + a, r[1] + b, r[2]};
+                const double rr = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+                if (std::abs(a) <= 1 && std::abs(b) <= 1) {
+                    if (rr == 0.0) {
+                        add(x, -2.0 * c * inv8pi, 0.0);
+                        continue;
+                    }
+                    const double rho = std::sqrt(rr), e = std::exp(-xi * xi * rr), ef = std::erf(xi * rho) / rho;
+                    add(x, -(ef + c * e) * inv8pi, -(ef - c * e) / rr * inv8pi);
+                    continue;
+                }
+                if (rr >= rc * rc) continue;
+                const double rho = std::sqrt(rr), e = std::exp(-xi * xi * rr), ec = std::erfc(xi * rho) / rho;
+                add(x, (ec - c * e) * inv8pi, (ec + c * e) / rr * inv8pi);
+            }
+        const double z = r[2], Z = std::fabs(z), sg = z < 0.0 ? -1.0 : 1.0, x2 = xi * xi;
+        for (int mx = -nk; mx <= nk; ++mx)
+            for (int my = -nk; my <= nk; ++my) {
+                if (mx == 0 && my == 0) continue;
+                const double kx = 2.0 * kPi * mx, ky = 2.0 * kPi * my, k2 = kx * kx + ky * ky, kap = std::sqrt(k2);
+                const double ph = kx * r[0] + ky * r[1], cs = std::cos(ph), sn = std::sin(ph);
+                const double g = std::exp(-k2 / (4.0 * x2) - x2 * z * z);
+                const double P = exp_erfc(kap, Z, g, 1.0), Q = exp_erfc(kap, Z, g, -1.0);
+                const double E2 = (P + Q) / (4.0 * kap), D = sg * (P - Q), E0 = g * xi / std::sqrt(kPi);
+                const double I2 = E2 + E0 / (4.0 * x2);
+                const double I4 = E2 / (2.0 * k2) - (z * D - 2.0 * g / (xi * std::sqrt(kPi))) / (8.0 * k2);
+                const double kv[2] = {kx, ky};
+                for (int a = 0; a < 2; ++a) {
+                    for (int b = 0; b < 2; ++b) B[3 * a + b] += cs * ((a == b ? I2 : 0.0) - kv[a] * kv[b] * I4);
+                    B[3 * a + 2] += sn * kv[a] * z * E2 / 2.0;
+                    B[6 + a] += sn * kv[a] * z * E2 / 2.0;
+                }
+                B[8] += cs * k2 * I4;
+            }
+        const double s0 = -z * std::erf(xi * z) / 2.0 - std::exp(-x2 * z * z) / (4.0 * xi * std::sqrt(kPi));
+        B[0] += s0;
+        B[4] += s0;
+    }
+};
+
 // Stokeslet block G(x - y) (row-major 3x3)
 void stokeslet_block(const double x[3], const double y[3], double G[9]) {
     const double r[3] = {x[0] - y[0], x[1] - y[1], x[2] - y[2]};
@@ -312,8 +413,8 @@ void apply_pinv(Pool &pool, const std::vector<double> &G, int n, double tol, std
 
 }  // namespace
 
-std::string build_periodic_stokes(int p, double svd_tol, std::vector<double> &Q, std::vector<double> &X,
-                                  std::vector<double> &Z) {
+std::string build_periodic_stokes(int p, double svd_tol, bool doubly, std::vector<double> &Q,
+                                  std::vector<double> &X, std::vector<double> &Z) {
     if (p < 2 || p > 16) return "p must lie in [2, 16]";
     Pool pool(pool_threads());
     std::vector<double> g;
@@ -347,43 +448,69 @@ std::string build_periodic_stokes(int p, double svd_tol, std::vector<double> &Q,
     apply_pinv(pool, G, n3, svd_tol, W, n3);
     // their far images at the downward check points (radius a_in, as the
     // upward equivalent points)
-    StokesFarImages far;
-    const int nk = int(far.kw.size());
-    std::vector<double> C(size_t(M) * nk), S(size_t(M) * nk), KK(size_t(6) * nk);
-    for (int k = 0; k < nk; ++k) {
-        const double kk = far.kx[k] * far.kx[k] + far.ky[k] * far.ky[k] + far.kz[k] * far.kz[k];
-        const double kv[3] = {far.kx[k], far.ky[k], far.kz[k]};
-        int q = 0;
-        for (int a = 0; a < 3; ++a)
-            for (int b = a; b < 3; ++b) KK[size_t(q++) * nk + k] = kv[a] * kv[b] / kk;
-    }
-    for (int i = 0; i < M; ++i)
-        for (int k = 0; k < nk; ++k) {
-            const double ph = aIn * (far.kx[k] * g[3 * i] + far.ky[k] * g[3 * i + 1] + far.kz[k] * g[3 * i + 2]);
-            C[size_t(i) * nk + k] = std::cos(ph);
-            S[size_t(i) * nk + k] = std::sin(ph);
-        }
     std::vector<double> T(size_t(n3) * n3);
-    pool.parallel_for(M, [&](int i) {
-        for (int m = 0; m < M; ++m) {
-            const double r[3] = {aIn * (g[3 * i] - g[3 * m]), aIn * (g[3 * i + 1] - g[3 * m + 1]),
-                                 aIn * (g[3 * i + 2] - g[3 * m + 2])};
-            double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            far.real_part(r, B);
-            double s0 = 0.0, sq[6] = {0, 0, 0, 0, 0, 0};
-            const double *ci = &C[size_t(i) * nk], *cm = &C[size_t(m) * nk];
-            const double *si = &S[size_t(i) * nk], *sm = &S[size_t(m) * nk];
-            for (int k = 0; k < nk; ++k) {
-                const double w = far.kw[k] * (ci[k] * cm[k] + si[k] * sm[k]);
-                s0 += w;
-                for (int q = 0; q < 6; ++q) sq[q] += w * KK[size_t(q) * nk + k];
+    if (doubly) {
+        // separations are a_in * 2 d/(p - 1) for integer d in [-(p-1), p-1]^3:
+        // one block per d
+        const int w = 2 * p - 1;
+        StokesFarImages2P far2;
+        std::vector<double> blocks(size_t(w) * w * w * 9);
+        pool.parallel_for(w * w * w, [&](int q) {
+            const int d[3] = {q % w - (p - 1), (q / w) % w - (p - 1), q / (w * w) - (p - 1)};
+            const double r[3] = {aIn * 2.0 * d[0] / (p - 1), aIn * 2.0 * d[1] / (p - 1), aIn * 2.0 * d[2] / (p - 1)};
+            double *B = &blocks[size_t(q) * 9];
+            for (int k = 0; k < 9; ++k) B[k] = 0.0;
+            far2.block(r, B);
+        });
+        auto lattice = [&](double v) { return int(std::lround((v + 1.0) * (p - 1) / 2.0)); };
+        pool.parallel_for(M, [&](int i) {
+            for (int m = 0; m < M; ++m) {
+                const int q = (lattice(g[3 * i]) - lattice(g[3 * m]) + p - 1) +
+                              w * (lattice(g[3 * i + 1]) - lattice(g[3 * m + 1]) + p - 1) +
+                              w * w * (lattice(g[3 * i + 2]) - lattice(g[3 * m + 2]) + p - 1);
+                const double *B = &blocks[size_t(q) * 9];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) T[size_t(3 * i + a) * n3 + 3 * m + b] = B[3 * a + b];
             }
-            const int qi[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+        });
+    } else {
+        StokesFarImages far;
+        const int nk = int(far.kw.size());
+        std::vector<double> C(size_t(M) * nk), S(size_t(M) * nk), KK(size_t(6) * nk);
+        for (int k = 0; k < nk; ++k) {
+            const double kk = far.kx[k] * far.kx[k] + far.ky[k] * far.ky[k] + far.kz[k] * far.kz[k];
+            const double kv[3] = {far.kx[k], far.ky[k], far.kz[k]};
+            int q = 0;
             for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b)
-                    T[size_t(3 * i + a) * n3 + 3 * m + b] = B[3 * a + b] + (a == b ? s0 : 0.0) - sq[qi[a][b]];
+                for (int b = a; b < 3; ++b) KK[size_t(q++) * nk + k] = kv[a] * kv[b] / kk;
         }
-    });
+        for (int i = 0; i < M; ++i)
+            for (int k = 0; k < nk; ++k) {
+                const double ph = aIn * (far.kx[k] * g[3 * i] + far.ky[k] * g[3 * i + 1] + far.kz[k] * g[3 * i + 2]);
+                C[size_t(i) * nk + k] = std::cos(ph);
+                S[size_t(i) * nk + k] = std::sin(ph);
+            }
+        pool.parallel_for(M, [&](int i) {
+            for (int m = 0; m < M; ++m) {
+                const double r[3] = {aIn * (g[3 * i] - g[3 * m]), aIn * (g[3 * i + 1] - g[3 * m + 1]),
+                                     aIn * (g[3 * i + 2] - g[3 * m + 2])};
+                double B[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+                far.real_part(r, B);
+                double s0 = 0.0, sq[6] = {0, 0, 0, 0, 0, 0};
+                const double *ci = &C[size_t(i) * nk], *cm = &C[size_t(m) * nk];
+                const double *si = &S[size_t(i) * nk], *sm = &S[size_t(m) * nk];
+                for (int k = 0; k < nk; ++k) {
+                    const double w = far.kw[k] * (ci[k] * cm[k] + si[k] * sm[k]);
+                    s0 += w;
+                    for (int q = 0; q < 6; ++q) sq[q] += w * KK[size_t(q) * nk + k];
+                }
+                const int qi[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        T[size_t(3 * i + a) * n3 + 3 * m + b] = B[3 * a + b] + (a == b ? s0 : 0.0) - sq[qi[a][b]];
+            }
+        });
+    }
     std::vector<double> TW(size_t(n3) * n3, 0.0);   // T W
     pool.parallel_for(n3, [&](int i) {
         double *y = &TW[size_t(i) * n3];

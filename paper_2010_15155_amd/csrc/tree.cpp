@@ -144,7 +144,7 @@ class Lister {
                     bool ok = true;
                     for (int k = 0; k < 3; ++k) {
                         int32_t v = B.anchor[k] + d[k];
-                        if (t_.periodic) {
+                        if ((t_.pmask >> k) & 1) {
                             int32_t q = (v >= 0) ? v / n : -((-v + n - 1) / n);
                             v -= q * n;
                             s[k] = int8_t(q);
@@ -184,10 +184,10 @@ inline int64_t ntrg(const Box &b) { return b.trg[1] - b.trg[0]; }
 }  // namespace
 
 std::string build_tree(const double *sl, int64_t n_sl, const double *dl, int64_t n_dl,
-                       const double *trg, int64_t n_trg, int leaf_cap, bool periodic, Tree &t,
+                       const double *trg, int64_t n_trg, int leaf_cap, int pmask, Tree &t,
                        const std::unordered_map<uint64_t, int> *leaf_caps) {
     t = Tree();
-    t.periodic = periodic;
+    t.pmask = pmask;
     // sets given by the same array are sorted once
     Pool pool(pool_threads());
     Sorted S[3];
@@ -368,7 +368,7 @@ void finish_tree(Tree &t) {
         if (B.ntrg_sub == 0) continue;
         bool loc = (t.v_off[b + 1] > t.v_off[b]) || (t.x_off[b + 1] > t.x_off[b]);
         if (B.parent >= 0 && t.has_local[B.parent]) loc = true;
-        if (b == 0 && t.periodic) loc = true;
+        if (b == 0 && t.pmask) loc = true;
         t.has_local[b] = loc;
     }
     t.p2p_pairs = 0;

@@ -84,7 +84,7 @@ struct KeyArgs {
     int64_t n;
     const double *xyz;       // user coordinates [n][3]
     double origin[3], len;
-    int periodic;
+    int pmask;               // bit k: axis k periodic (coordinates wrapped)
     uint64_t *key;
     int32_t *idx;
 };
@@ -96,7 +96,7 @@ __global__ void keys_kernel(KeyArgs a) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         double u = (a.xyz[3 * i + k] - a.origin[k]) / a.len;
-        if (a.periodic) {
+        if ((a.pmask >> k) & 1) {
             u -= floor(u);
             if (u >= 1.0) u = 0.0;
         }
@@ -394,7 +394,7 @@ struct ListView {
     const uint64_t *bkey;         // Morton key of each box's anchor at its level
     int level_start[kLevels + 1]; // boxes of level l: [level_start[l], level_start[l + 1])
     int depth;
-    int periodic;
+    int pmask;               // bit k: axis k periodic
 };
 
 // an entry: (box << 5) | shift code, code = 9 (s0 + 1) + 3 (s1 + 1) + (s2 + 1);
@@ -445,7 +445,7 @@ __device__ int colleagues(const ListView &v, int b, uint64_t out[27]) {
                 bool ok = true;
                 for (int k = 0; k < 3; ++k) {
                     int32_t w = B.anchor[k] + d[k];
-                    if (v.periodic) {
+                    if ((v.pmask >> k) & 1) {
                         const int32_t q = w >= 0 ? w / n : -((-w + n - 1) / n);
                         w -= q * n;
                         s[k] = q;
@@ -634,10 +634,11 @@ __global__ void key_entries_kernel(int64_t n, const uint64_t *key, uint64_t *ent
     ent[i] = key[i] & ((uint64_t(1) << 30) - 1);
 }
 
-// flags[0]: some coordinate is not finite; flags[1]: (open boundary) some
-// point lies outside [origin, origin + len)^3, with the host's expression
+// flags[0]: some coordinate is not finite; flags[1]: some coordinate of an
+// open (non-periodic) axis lies outside [origin, origin + len), with the
+// host's expression
 __global__ void check_points_kernel(int64_t n3, const double *xyz, double ox, double oy, double oz, double len,
-                                    int periodic, uint32_t *flags) {
+                                    int pmask, uint32_t *flags) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n3) return;
     const double v = xyz[i];
@@ -645,8 +646,8 @@ __global__ void check_points_kernel(int64_t n3, const double *xyz, double ox, do
         atomicOr(&flags[0], 1u);
         return;
     }
-    if (periodic) return;
     const int k = int(i % 3);
+    if ((pmask >> k) & 1) return;
     const double u = (v - (k == 0 ? ox : k == 1 ? oy : oz)) / len;
     if (!(u >= 0.0 && u < 1.0)) atomicOr(&flags[1], 1u);
 }
@@ -658,7 +659,7 @@ __global__ void fill_u32(uint32_t *d, int64_t n, uint32_t v) {
 
 }  // namespace
 
-std::string check_points_gpu(const double *xyz, int64_t n, const double origin[3], double box_len, bool periodic,
+std::string check_points_gpu(const double *xyz, int64_t n, const double origin[3], double box_len, int pmask,
                              bool *nonfinite, bool *outside, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     *nonfinite = *outside = false;
@@ -668,7 +669,7 @@ std::string check_points_gpu(const double *xyz, int64_t n, const double origin[3
     hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, s, flags.as<uint32_t>(), int64_t(2), 0u);
     TRY(hipGetLastError());
     hipLaunchKernelGGL(check_points_kernel, dim3(nblk(3 * n, 256)), dim3(256), 0, s, 3 * n, xyz, origin[0], origin[1],
-                       origin[2], box_len, periodic ? 1 : 0, flags.as<uint32_t>());
+                       origin[2], box_len, pmask, flags.as<uint32_t>());
     TRY(hipGetLastError());
     uint32_t h[2] = {0, 0};
     TRY(hipMemcpyAsync(h, flags.p, 8, hipMemcpyDeviceToHost, s));
@@ -679,11 +680,11 @@ std::string check_points_gpu(const double *xyz, int64_t n, const double origin[3
 }
 
 std::string build_tree_gpu(const double *const xyz[3], const int64_t n[3], const double origin[3], double box_len,
-                           int leaf_cap, bool periodic, Tree &t,
+                           int leaf_cap, int pmask, Tree &t,
                            const std::unordered_map<uint64_t, int> *leaf_caps, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     t = Tree();
-    t.periodic = periodic;
+    t.pmask = pmask;
     for (int k = 0; k < 3; ++k)
         if (n[k] > INT32_MAX / 2) return "GPU tree build: too many points";
     // ---------------------------------------------------------------- keys and sort
@@ -698,7 +699,7 @@ std::string build_tree_gpu(const double *const xyz[3], const int64_t n[3], const
         TRY(key[k].ensure(std::max<int64_t>(n[k], 1) * 8));
         TRY(perm[k].ensure(std::max<int64_t>(n[k], 1) * 4));
         if (n[k] == 0) continue;
-        KeyArgs ka{n[k], xyz[k], {origin[0], origin[1], origin[2]}, box_len, periodic ? 1 : 0,
+        KeyArgs ka{n[k], xyz[k], {origin[0], origin[1], origin[2]}, box_len, pmask,
                    key[k].as<uint64_t>(), perm[k].as<int32_t>()};
         hipLaunchKernelGGL(keys_kernel, dim3(nblk(n[k], 256)), dim3(256), 0, s, ka);
         TRY(hipGetLastError());
@@ -803,7 +804,7 @@ std::string build_tree_gpu(const double *const xyz[3], const int64_t n[3], const
     lv.bkey = bkey.as<uint64_t>();
     for (int l = 0; l <= kLevels; ++l) lv.level_start[l] = l <= depth + 1 ? level_start[l] : nb;
     lv.depth = depth;
-    lv.periodic = periodic ? 1 : 0;
+    lv.pmask = pmask;
     DevArr dleaves, vcnt, vent, cnt3, oflow;
     DevArr lkey[3], lval[3], lent[3], lcnt[3];   // U, W, X: keys, sort payload, entries, counts by box
     TRY(dleaves.ensure(size_t(std::max(nleaf, 1)) * 4));

@@ -144,8 +144,12 @@ def test_fmm_shifted_box(kernel):
 # Relative L2 bounds of the far-field-only problem at p = 8.  Values and first
 # derivatives of the tree potentials meet the 1e-5 budget; outputs built from
 # second derivatives (lap u, sigma, grad u, grad p of the Stokes double layer,
-# the Laplace Hessian) lose about one digit, since the leaves' equivalent
-# densities sit close to the targets near a leaf's faces.  Quadrupole sources
+# the Laplace Hessian) lose more than a digit.  That loss is the method's:
+# the truncated check-to-equivalent pseudo-inverse discards high-frequency
+# modes that second derivatives amplify.  The plain FP64 KIFMM with the
+# paper's tables gives RPY lap u 4.2e-3 on this problem at the same cut
+# (2.3e-4 at a cut of 1e-12), and higher orders do not remove it.  With
+# the near field present, every field meets 1e-5 (test_fmm_clustered).  Quadrupole sources
 # (LapQPGradGrad) carry no charge or dipole moment; the upward densities are
 # fitted without those moments (errors in them would decay more slowly than
 # the true field), and what is left of the FP32 error is a few 1e-5 at

@@ -160,6 +160,21 @@ def test_gpu_tree_equals_host_tree_periodic(n, cap):
     assert np.any(g["U"][:, 1:] != 0) and np.any(g["V"][:, 1:] != 0)
 
 
+@pytest.mark.parametrize("n,cap", [(40, 3), (5000, 20), (200_000, 500)])
+def test_gpu_tree_equals_host_tree_doubly_periodic(n, cap):
+    rng = np.random.default_rng(n + 1)
+    # x and y outside the box too (wrapped), z inside it (open)
+    x = rng.uniform(-0.5, 1.5, (n, 3))
+    x[:, 2] = rng.random(n)
+    x = _cuda(x)
+    print("tree gpu vs host: doubly periodic", n, cap, flush=True)
+    g = _tree("Stokeslet", x, None, x, cap, "gpu", bc="PXY")
+    h = _tree("Stokeslet", x, None, x, cap, "host", bc="PXY")
+    _equal(g, h)
+    ents = np.concatenate([g[k] for k in "UVWX"])
+    assert np.all(ents[:, 3] == 0) and np.any(ents[:, 1:3] != 0)
+
+
 def test_gpu_tree_equals_host_tree_coincident_points():
     rng = np.random.default_rng(9)
     x = np.concatenate([np.full((3000, 3), 0.625), rng.random((20_000, 3))])
