@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-headline", action="store_true",
                     help="measure the learned Stokeslet plan only (for profiler runs)")
+    ap.add_argument("--only-variant", choices=["fixed_p10", "learned_split_bf16"], default=None,
+                    help="measure one other 1M Stokeslet plan only (for profiler runs)")
     ap.add_argument("--only-plan", action="store_true",
                     help="measure the plan time with the GPU and the host tree builders only")
     ap.add_argument("--only-periodic", action="store_true",
@@ -264,35 +266,41 @@ def tree_build(FMM, x):
     return out
 
 
-def periodic_laplace_4m(FMM, torch, W, args, n=4_194_304, p=12, cap=2000):
+def periodic_laplace_4m(FMM, torch, W, args, n=4_194_304, p=12, caps=(2000, 500)):
     """Triply periodic Laplace charges + dipoles (zero net charge) on n uniform
-    points, SL = DL = targets, p = 12, leaf_cap 2000: time per pass, P2P rate,
-    the translation test of the periodic boundary (all points moved by one
-    vector, wrapped), and the sampled outputs that the cpu_baseline leg checks
-    against the Ewald oracle."""
+    points, SL = DL = targets, p = 12: at leaf_cap 2000 (the paper's leaf
+    size) and at 500 (eight times fewer P2P pairs on uniform points), each
+    with time per pass, P2P rate, the translation test of the periodic
+    boundary (all points moved by one vector, wrapped) and the sampled
+    outputs that the cpu_baseline leg checks against the Ewald oracle."""
     d = W.periodic_laplace(n, 301)
     x = torch.from_numpy(d["xyz"]).cuda()
     q = torch.from_numpy(d["q"][:, None].copy()).cuda()
     dp = torch.from_numpy(d["d"]).cuda()
-    fmm = FMM()
-    fmm.set_points("LapPGrad", x, x, x, p=p, leaf_cap=cap, bc="PXYZ")
-    r = timed_runs(fmm, torch, args, q, dp)
-    out = r.pop("_out")
     idx = W.sample_indices(n, 24, 9)
-    r["_sample"] = {"idx": idx, "got": out[torch.from_numpy(idx).cuda()].cpu().numpy(), "d": d}
     s = np.array([0.37, 0.61, 0.18])
     xs = torch.from_numpy(np.mod(d["xyz"] + s, 1.0)).cuda()
-    fmm.set_points("LapPGrad", xs, xs, xs, p=p, leaf_cap=cap, bc="PXYZ")
-    out2 = fmm.run(q, dp)
-    dphi = out2[:, 0] - out[:, 0]
-    r["translation_rel_diff"] = {
-        "phi": float(torch.linalg.norm(dphi - dphi.mean()) / torch.linalg.norm(out[:, 0] - out[:, 0].mean())),
-        "grad_phi": float(torch.linalg.norm(out2[:, 1:] - out[:, 1:]) / torch.linalg.norm(out[:, 1:]))}
+    rows = {}
+    fmm = FMM()
+    for cap in caps:
+        fmm.set_points("LapPGrad", x, x, x, p=p, leaf_cap=cap, bc="PXYZ")
+        r = timed_runs(fmm, torch, args, q, dp)
+        out = r.pop("_out")
+        r["_sample"] = {"idx": idx, "got": out[torch.from_numpy(idx).cuda()].cpu().numpy()}
+        fmm.set_points("LapPGrad", xs, xs, xs, p=p, leaf_cap=cap, bc="PXYZ")
+        out2 = fmm.run(q, dp)
+        dphi = out2[:, 0] - out[:, 0]
+        r["translation_rel_diff"] = {
+            "phi": float(torch.linalg.norm(dphi - dphi.mean()) / torch.linalg.norm(out[:, 0] - out[:, 0].mean())),
+            "grad_phi": float(torch.linalg.norm(out2[:, 1:] - out[:, 1:]) / torch.linalg.norm(out[:, 1:]))}
+        del out, out2
+        r.update({"p": p, "leaf_cap": cap, "roofline": p2p_roofline("LapPGrad", r)})
+        rows["leaf_cap_%d" % cap] = r
     fmm.close()
-    r.update({"p": p, "leaf_cap": cap, "roofline": p2p_roofline("LapPGrad", r),
-              "workload": "%d uniform points in the unit cube, Laplace charges N(0,1) minus their mean and "
-                          "dipoles N(0,1)^3, SL = DL = targets, PXYZ" % n})
-    return r
+    rows["_d"] = d
+    rows["workload"] = ("%d uniform points in the unit cube, Laplace charges N(0,1) minus their mean and "
+                        "dipoles N(0,1)^3, SL = DL = targets, PXYZ" % n)
+    return rows
 
 
 def sphere_doublelayer_2m(FMM, torch, W, args, p=10, cap=2000):
@@ -389,6 +397,13 @@ def main():
         return
     fmm = FMM()
     fmm.set_predictor(load_weights())
+    if args.only_variant:
+        p, cap, prec = (10, 2000, "fp32") if args.only_variant == "fixed_p10" else (0, 0, "split_bf16")
+        r = measure(fmm, torch, W, "Stokeslet", x, f, p, cap, args, prec)
+        r.pop("_out")
+        fmm.close()
+        print(json.dumps({args.only_variant: r}), flush=True)
+        return
     L = measure(fmm, torch, W, "Stokeslet", x, f, 0, 0, args)
     n = args.n
     flops = P2P_FLOPS["Stokeslet"] * L["plan"]["p2p_pairs"]
@@ -539,14 +554,17 @@ def cpu_baseline(d, budget_s, checked, configs):
     out["rel_l2_vs_oracle"] = errs
     c3 = configs.get("periodic_laplace_4M_p12")
     if c3:
-        sm = c3["_sample"]
-        dd = sm["d"]
-        refp = ewald.laplace_periodic(dd["xyz"], dd["q"], dd["d"], dd["xyz"][sm["idx"]], 1.0, xi=4.0, tol=1e-12)
-        dphi = sm["got"][:, 0] - refp[:, 0]
-        c3["rel_l2_vs_oracle"] = {
-            "phi": float(np.linalg.norm(dphi - dphi.mean()) / np.linalg.norm(refp[:, 0] - refp[:, 0].mean())),
-            "grad_phi": float(np.linalg.norm(sm["got"][:, 1:] - refp[:, 1:]) / np.linalg.norm(refp[:, 1:])),
-            "targets": len(sm["idx"]), "oracle": "Ewald sum (FP64, tin-foil, k = 0 term dropped)"}
+        dd = c3["_d"]
+        rows = [v for v in c3.values() if isinstance(v, dict) and "_sample" in v]
+        idx3 = rows[0]["_sample"]["idx"]
+        refp = ewald.laplace_periodic(dd["xyz"], dd["q"], dd["d"], dd["xyz"][idx3], 1.0, xi=4.0, tol=1e-12)
+        for r in rows:
+            got = r["_sample"]["got"]
+            dphi = got[:, 0] - refp[:, 0]
+            r["rel_l2_vs_oracle"] = {
+                "phi": float(np.linalg.norm(dphi - dphi.mean()) / np.linalg.norm(refp[:, 0] - refp[:, 0].mean())),
+                "grad_phi": float(np.linalg.norm(got[:, 1:] - refp[:, 1:]) / np.linalg.norm(refp[:, 1:])),
+                "targets": len(idx3), "oracle": "Ewald sum (FP64, tin-foil, k = 0 term dropped)"}
     c4 = configs.get("sphere_doublelayer_2M_p10")
     if c4:
         dd = c4["_d"]
