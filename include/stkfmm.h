@@ -237,7 +237,7 @@ stkfmm_status stkfmm_set_option(stkfmm_ctx *ctx, const char *key, const char *va
 stkfmm_status stkfmm_get_timings(const stkfmm_ctx *ctx, double *t_tree_ms, double *t_run_ms,
                                  double stage_ms[16]);
 
-/* Plan statistics of the last set_points; stats[20] receives:
+/* Plan statistics of the last set_points; stats[21] receives:
  * 0 boxes, 1 leaves, 2 depth, 3 U-list pairs (sum over target leaves of
  * n_trg * sum of U-list source counts), 4 V-list pairs, 5 W-list pairs,
  * 6 X-list pairs, 7 M (points per surface), 8 n_trg, 9 n_sl, 10 n_dl,
@@ -246,10 +246,14 @@ stkfmm_status stkfmm_get_timings(const stkfmm_ctx *ctx, double *t_tree_ms, doubl
  * directly, 14 X pairs summed directly, 15 P2P tasks, 16 rank of the
  * compressed V-list translations (0: dense), 17 Mp (M padded to 32),
  * 18 rank of the check-to-equivalent pseudo-inverse, 19 P2P lane pairs
- * (pairs including the idle lanes of partly filled 64-target waves).
+ * (pairs including the idle lanes of partly filled 64-target waves; a wave
+ * left with at most 32 targets splits the sources over its lanes),
+ * 20 1 if the Stokeslet P2P of this plan forms r from the hi/lo coordinates
+ * rather than from leaf-relative FP32 positions, because two distinct points
+ * of different leaves lie closer than 1/4096 of a leaf side (else 0).
  * For a WALL plan: the statistics of its Stokes summation (sources and
  * their images).  Errors: E_ARG, E_STATE. */
-stkfmm_status stkfmm_get_stats(const stkfmm_ctx *ctx, int64_t stats[20]);
+stkfmm_status stkfmm_get_stats(const stkfmm_ctx *ctx, int64_t stats[21]);
 
 /* The adaptive octree and interaction lists of the last set_points (Sec. II:
  * the tree and the U, V, W, X lists of KIFMM), copied to caller-owned host
@@ -312,8 +316,9 @@ stkfmm_status stkfmm_get_leaf_features(stkfmm_ctx *ctx, float *features, int32_t
                                        int64_t *n_leaf);
 
 /* Work of the current plan attributed to its targets (host [n_trg][5],
- * user order): 0 P2P lane pairs (targets counted in whole 64-lane waves
- * times the sources of the leaf's direct list), 1 P2P wave entries, 2 M2L
+ * user order): 0 P2P lane pairs (as stats[19]: the leaf's targets in
+ * 64-lane waves times the sources of its direct list, partly filled waves
+ * with their sources split over the lanes), 1 P2P wave entries, 2 M2L
  * flops, 3 surface evaluations (S2M, S2L, L2T, M2T), 4 boxes.  Each box's
  * work is shared equally by the targets in it.  Used to price capacity
  * labels for the learned mode.  Errors: E_ARG, E_STATE, E_UNSUPPORTED

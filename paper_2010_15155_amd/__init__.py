@@ -205,11 +205,11 @@ class FMM:
                 "stages_ms": {k: stg[i] for i, k in enumerate(STAGES)}}
 
     def stats(self):
-        a = (ctypes.c_int64 * 20)()
+        a = (ctypes.c_int64 * 21)()
         self._check(lib().stkfmm_get_stats(self._h, a), "stats")
         names = ["boxes", "leaves", "depth", "u_pairs", "v_pairs", "w_pairs", "x_pairs", "M",
                  "n_trg", "n_sl", "n_dl", "u_entries", "p2p_pairs", "w_direct", "x_direct", "p2p_tasks",
-                 "m2l_rank", "Mp", "pinv_rank", "p2p_lane_pairs"]
+                 "m2l_rank", "Mp", "pinv_rank", "p2p_lane_pairs", "p2p_exact_r"]
         return {n: int(a[i]) for i, n in enumerate(names)}
 
     def tree(self):

@@ -174,6 +174,7 @@ struct stkfmm_ctx {
     double svd_tol = 1e-7;
     double m2l_tol = 5e-8;      // compression of the V-list translations (0: dense)
     bool m2l_tol_set = false;   // set by the caller (else learned plans use tol / 50)
+    bool rel_exact = false;     // P2P forms r from hi/lo coordinates (close pairs across leaves)
     int precision = 0;          // 0 fp32, 1 split_bf16
     hipStream_t side = nullptr; // P2P stream
     hipEvent_t ev[24] = {};
@@ -882,6 +883,10 @@ stkfmm_status direct_args(stkfmm_ctx *c, stkfmm_kernel kernel, int64_t n_sl, con
 
 }  // namespace
 
+namespace {
+P2PArgs p2p_args(stkfmm_ctx *c);
+}
+
 extern "C" {
 
 stkfmm_status stkfmm_kernel_dims(stkfmm_kernel k, int *k_sl, int *k_dl, int *k_trg) {
@@ -1010,17 +1015,17 @@ stkfmm_status stkfmm_get_timings(const stkfmm_ctx *c, double *t_tree, double *t_
     return STKFMM_OK;
 }
 
-stkfmm_status stkfmm_get_stats(const stkfmm_ctx *c, int64_t st[20]) {
+stkfmm_status stkfmm_get_stats(const stkfmm_ctx *c, int64_t st[21]) {
     if (!c || !st) return STKFMM_E_ARG;
     if (!c->planned) return STKFMM_E_STATE;
     if (c->bc == STKFMM_BC_WALL) {
         if (c->wall && c->wall->sub[0] && c->wall->sub[0]->planned) return stkfmm_get_stats(c->wall->sub[0], st);
-        std::memset(st, 0, 20 * sizeof(int64_t));
+        std::memset(st, 0, 21 * sizeof(int64_t));
         st[8] = c->n_trg;
         st[9] = c->n_sl;
         return STKFMM_OK;
     }
-    std::memset(st, 0, 20 * sizeof(int64_t));
+    std::memset(st, 0, 21 * sizeof(int64_t));
     const Tree &t = c->tree;
     st[0] = int64_t(t.boxes.size());
     st[1] = int64_t(t.leaves.size());
@@ -1042,6 +1047,7 @@ stkfmm_status stkfmm_get_stats(const stkfmm_ctx *c, int64_t st[20]) {
     st[17] = c->ops ? c->ops->Mp : 0;
     st[18] = c->ops ? c->ops->rank : 0;
     st[19] = c->p2p_lane_pairs;
+    st[20] = c->rel_exact ? 1 : 0;
     return STKFMM_OK;
 }
 
@@ -1344,6 +1350,22 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     std::vector<int2> p2p_ent, l2t_ent;
     c->direct_pairs = 0;
     c->p2p_lane_pairs = 0;
+    // lane pairs of the P2P waves of a chunk of nt targets of leaf b: a full
+    // wave takes one source per step; a wave left with m <= 32 targets splits
+    // each entry's sources over floor(64/m) lane groups (p2p_kernel)
+    auto chunk_lane_pairs = [&](int b, int64_t nt) {
+        int64_t nsrc_all = 0;
+        for (const int2 &e : dlist[b]) nsrc_all += t.boxes[e.x].nsrc_sub;
+        int64_t lp = nsrc_all * (nt / 64 * 64);
+        const int64_t m = nt % 64;
+        if (m > 32) {
+            lp += nsrc_all * 64;
+        } else if (m > 0) {
+            const int64_t g = 64 / m;
+            for (const int2 &e : dlist[b]) lp += 64 * ((t.boxes[e.x].nsrc_sub + g - 1) / g);
+        }
+        return lp;
+    };
     for (int b : t.leaves) {
         const Box &B = t.boxes[b];
         if (B.trg[1] == B.trg[0]) continue;
@@ -1358,7 +1380,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
         for (int e = e0; e < e1; ++e) nsrc_all += t.boxes[p2p_ent[e].x].nsrc_sub;
         c->direct_pairs += nsrc_all * (B.trg[1] - B.trg[0]);
         for (int64_t t0i = B.trg[0]; t0i < B.trg[1]; t0i += 256)
-            c->p2p_lane_pairs += nsrc_all * ((std::min<int64_t>(t0i + 256, B.trg[1]) - t0i + 63) / 64 * 64);
+            c->p2p_lane_pairs += chunk_lane_pairs(b, std::min<int64_t>(t0i + 256, B.trg[1]) - t0i);
         for (int64_t t0i = B.trg[0]; t0i < B.trg[1]; t0i += 256) {
             const int ci = int(chunks.size());
             chunks.push_back(make_int4(b, int(t0i), int(std::min<int64_t>(t0i + 256, B.trg[1])), 0));
@@ -1402,7 +1424,7 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
             int ne = 0;
             for (const int2 &e : dlist[b]) nsrc_all += t.boxes[e.x].nsrc_sub, ++ne;
             const double waves = double((ch.z - ch.y + 63) / 64);
-            c->box_work[b][0] += 64.0 * waves * double(nsrc_all);
+            c->box_work[b][0] += double(chunk_lane_pairs(b, ch.z - ch.y));
             c->box_work[b][1] += waves * ne;
         }
         for (int b = 0; b < nb; ++b) {
@@ -1604,9 +1626,20 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
     HIP_TRY(c, launch_pack_sources(n_dl, dl_xyz, at<int32_t>(c, c->a_perm_dl), org, inv, std::max(ki.rec_dl, 8),
                                    c->dl_rec.as<float>(), s));
     HIP_TRY(c, launch_pack_targets(n_trg, trg_xyz, at<int32_t>(c, c->a_perm_trg), org, inv, c->trg_rec.as<float>(), s));
-    if (p2p_uses_rel(c->kernel))
+    c->rel_exact = false;
+    if (p2p_uses_rel(c->kernel)) {
         HIP_TRY(c, launch_rel_positions(c->n_leaves_sl, at<int>(c, c->a_leaves_sl), at<int2>(c, c->a_box_sl),
                                         at<double4>(c, c->a_geom), ki.rec_sl, c->sl_rec.as<float>(), s));
+        // distinct points of different leaves closer than the leaf-relative
+        // positions resolve: this plan forms r from hi/lo coordinates instead
+        unsigned *flag = reinterpret_cast<unsigned *>(c->partial.as<double>());
+        HIP_TRY(c, launch_fill_f32(reinterpret_cast<float *>(flag), 1, 0.0f, s));
+        HIP_TRY(c, launch_rel_check(c->n_p2p_tasks, p2p_args(c), ki.rec_sl, flag, s));
+        unsigned h = 0;
+        HIP_TRY(c, hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        c->rel_exact = h != 0;
+    }
     HIP_TRY(c, hipStreamSynchronize(s));
     c->t_tree_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     c->planned = true;
@@ -1617,6 +1650,21 @@ stkfmm_status stkfmm_set_points(stkfmm_ctx *c, stkfmm_kernel kernel, stkfmm_bc b
 
 namespace {
 
+
+P2PArgs p2p_args(stkfmm_ctx *c) {
+    P2PArgs a;
+    a.tasks = at<int4>(c, c->a_p2p_tasks);
+    a.chunks = at<int4>(c, c->a_chunks);
+    a.trg = c->trg_rec.as<float>();
+    a.ent = at<int2>(c, c->a_p2p_ent);
+    a.box_sl = at<int2>(c, c->a_box_sl);
+    a.box_dl = at<int2>(c, c->a_box_dl);
+    a.sl = c->sl_rec.as<float>();
+    a.dl = c->dl_rec.as<float>();
+    a.geom = at<double4>(c, c->a_geom);
+    a.part = c->near_part.as<double>();
+    return a;
+}
 
 CombineMap combine_map(int k, double L) {
     CombineMap m;
@@ -1851,20 +1899,7 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
     hipStream_t ps = c->overlap ? c->side : s;
     if (c->overlap) HIP_TRY(c, hipStreamWaitEvent(c->side, ev[1], 0));
     HIP_TRY(c, hipEventRecord(ev[20], ps));
-    {
-        P2PArgs a;
-        a.tasks = at<int4>(c, c->a_p2p_tasks);
-        a.chunks = at<int4>(c, c->a_chunks);
-        a.trg = c->trg_rec.as<float>();
-        a.ent = at<int2>(c, c->a_p2p_ent);
-        a.box_sl = at<int2>(c, c->a_box_sl);
-        a.box_dl = at<int2>(c, c->a_box_dl);
-        a.sl = c->sl_rec.as<float>();
-        a.dl = c->dl_rec.as<float>();
-        a.geom = at<double4>(c, c->a_geom);
-        a.part = c->near_part.as<double>();
-        HIP_TRY(c, launch_p2p(c->kernel, c->n_p2p_tasks, a, ps));
-    }
+    HIP_TRY(c, launch_p2p(c->kernel, c->n_p2p_tasks, p2p_args(c), c->rel_exact, ps));
     HIP_TRY(c, hipEventRecord(ev[21], ps));
     if (!c->overlap) HIP_TRY(c, hipEventRecord(ev[1], s));   // far-field stages start after P2P
     // ---- far field

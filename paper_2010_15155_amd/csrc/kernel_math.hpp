@@ -80,6 +80,13 @@ struct DStokeslet {       // SL f0 f1 f2 ; leaf-relative position at 9..11
     __device__ static void dl(float, float, float, float, const float *, float *) {}
 };
 
+// The Stokeslet with r from the hi/lo coordinates (slots 0..5) instead of
+// the leaf-relative positions: the form of plans in which two distinct
+// points of different leaves are too close for the leaf-relative one.
+struct DStokesletExact : DStokeslet {
+    static constexpr bool REL = false;
+};
+
 struct DStokesReg {       // SL f0 f1 f2, (3/2) eps^2, eps^2
     static constexpr int RS = 12, RD = 0, NACC = 3;
     static constexpr bool REL = false;

@@ -151,13 +151,122 @@ __device__ __forceinline__ void p2p_run(const float *__restrict__ src, int j0, i
     }
 }
 
+// A wave whose chunk leaves it m <= 32 targets spreads each target over
+// g = floor(64/m) lanes: lane l serves target l mod m and the sources
+// j0 + l/m, j0 + l/m + g, ... of every list entry (per-lane loads instead of
+// wave-uniform ones), and the g partial sums of a target are added in lane
+// order through cross-lane reads, so the result is deterministic.  Lanes
+// past g m take no sources.
+template <class K, bool GUARD>
+__device__ __forceinline__ void p2p_rel_split(const float *__restrict__ src, int j0, int j1, int g, float xr,
+                                              float yr, float zr, double *acc) {
+    for (int r0 = j0; r0 < j1; r0 += 64 * g) {
+        const int r1 = min(r0 + 64 * g, j1);
+        float part[K::NACC];
+#pragma unroll
+        for (int k = 0; k < K::NACC; ++k) part[k] = 0.0f;
+        for (int j = r0; j < r1; j += g) {
+            const float *s = src + int64_t(j) * K::RS;
+            const float dx = xr - s[9], dy = yr - s[10], dz = zr - s[11];
+            const float r2 = dot3(dx, dy, dz, dx, dy, dz);
+            const float ri = GUARD ? rsq_or_zero(r2) : __builtin_amdgcn_rsqf(r2);
+            K::sl(dx, dy, dz, ri, s + 6, part);
+        }
+#pragma unroll
+        for (int k = 0; k < K::NACC; ++k) acc[k] += double(part[k]);
+    }
+}
+
+template <class K>
+__device__ __forceinline__ void p2p_run_split(const float *__restrict__ src, int j0, int j1, int g, float xh,
+                                              float yh, float zh, float xl, float yl, float zl, double *acc,
+                                              bool dl) {
+    const int rs = dl ? (K::RD > 0 ? K::RD : 1) : K::RS;
+    for (int r0 = j0; r0 < j1; r0 += 64 * g) {
+        const int r1 = min(r0 + 64 * g, j1);
+        float part[K::NACC];
+#pragma unroll
+        for (int k = 0; k < K::NACC; ++k) part[k] = 0.0f;
+        for (int j = r0; j < r1; j += g) {
+            const float *s = src + int64_t(j) * rs;
+            const float dx = (xh - s[0]) + (xl - s[3]);
+            const float dy = (yh - s[1]) + (yl - s[4]);
+            const float dz = (zh - s[2]) + (zl - s[5]);
+            const float ri = rsq_or_zero(dot3(dx, dy, dz, dx, dy, dz));
+            if (dl) K::dl(dx, dy, dz, ri, s + 6, part);
+            else K::sl(dx, dy, dz, ri, s + 6, part);
+        }
+#pragma unroll
+        for (int k = 0; k < K::NACC; ++k) acc[k] += double(part[k]);
+    }
+}
+
+template <class K>
+__device__ __forceinline__ void p2p_wave_split(const P2PArgs &a, int4 task, int4 ch, int first, int m, int wbase) {
+    const int lane = int(threadIdx.x) & 63;
+    const int g = 64 / m;
+    const int tl = lane % m, sg = lane / m;       // target slot and source group of this lane
+    const bool works = sg < g;
+    const int ti = first + tl;
+    const float4 p0 = reinterpret_cast<const float4 *>(a.trg)[2 * ti];
+    const float4 p1 = reinterpret_cast<const float4 *>(a.trg)[2 * ti + 1];
+    double acc[K::NACC];
+#pragma unroll
+    for (int k = 0; k < K::NACC; ++k) acc[k] = 0.0;
+    for (int e = task.y; e < task.z; ++e) {
+        const int2 en = a.ent[e];
+        const int sx = shift_comp(en.y, 0), sy = shift_comp(en.y, 1), sz = shift_comp(en.y, 2);
+        const int2 rs = a.box_sl[en.x];
+        const int j0 = works ? rs.x + sg : rs.y;
+        if (K::REL) {
+            const double4 gm = a.geom[en.x];
+            const float xr = float((double(p0.x) - (gm.x + sx)) + double(p1.x));
+            const float yr = float((double(p0.y) - (gm.y + sy)) + double(p1.y));
+            const float zr = float((double(p0.z) - (gm.z + sz)) + double(p1.z));
+            if (en.x == ch.x && en.y == kZeroShift) p2p_rel_split<K, true>(a.sl, j0, rs.y, g, xr, yr, zr, acc);
+            else p2p_rel_split<K, false>(a.sl, j0, rs.y, g, xr, yr, zr, acc);
+        } else {
+            float xh = p0.x, yh = p0.y, zh = p0.z, xl = p1.x, yl = p1.y, zl = p1.z;
+            if (sx) two_sum_shift(xh, xl, float(sx));
+            if (sy) two_sum_shift(yh, yl, float(sy));
+            if (sz) two_sum_shift(zh, zl, float(sz));
+            p2p_run_split<K>(a.sl, j0, rs.y, g, xh, yh, zh, xl, yl, zl, acc, false);
+            if (K::RD > 0) {
+                const int2 rd = a.box_dl[en.x];
+                p2p_run_split<K>(a.dl, works ? rd.x + sg : rd.y, rd.y, g, xh, yh, zh, xl, yl, zl, acc, true);
+            }
+        }
+    }
+    // lane tl (< m) adds the partial sums of lanes tl + q m, q = 1 .. g-1, in order
+#pragma unroll
+    for (int k = 0; k < K::NACC; ++k) {
+        double v = acc[k];
+        for (int q = 1; q < g; ++q) {
+            const double w = __shfl(acc[k], tl + q * m, 64);
+            v += w;
+        }
+        acc[k] = v;
+    }
+    if (lane < m) {
+        double *o = a.part + (int64_t(blockIdx.x) * 256 + wbase + lane) * K::NACC;
+#pragma unroll
+        for (int k = 0; k < K::NACC; ++k) o[k] = acc[k];
+    }
+}
+
 template <class K>
 __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs a) {
     static_assert(!K::REL || K::RD == 0, "REL positions exist for single-layer records only");
     const int4 task = a.tasks[blockIdx.x];
     const int4 ch = a.chunks[task.x];
-    const int first = ch.y + int(threadIdx.x & ~63u);
+    const int wbase = int(threadIdx.x & ~63u);
+    const int first = ch.y + wbase;
     if (first >= ch.z) return;                       // whole wave idle
+    const int m = min(64, ch.z - first);             // targets of this wave
+    if (m <= 32) {                                   // partly filled wave: sources split over lanes
+        p2p_wave_split<K>(a, task, ch, first, m, wbase);
+        return;
+    }
     const int t = ch.y + int(threadIdx.x);
     const bool active = t < ch.z;
     const int ti = active ? t : ch.z - 1;
@@ -194,6 +303,46 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs a) {
         double *o = a.part + (int64_t(blockIdx.x) * 256 + threadIdx.x) * K::NACC;
 #pragma unroll
         for (int k = 0; k < K::NACC; ++k) o[k] = acc[k];
+    }
+}
+
+// Plan-time check of the leaf-relative P2P form (one block per P2P task, a
+// target per thread, as p2p_kernel): for every entry other than the
+// target's own leaf, a target within delta = 2^-12 of the source leaf's side
+// from that (image-shifted) leaf's box is compared with each of its
+// sources in FP64; a pair closer than delta sets *flag.  Such a pair's
+// leaf-relative r would carry a relative error above about 2^-11 (or be 0).
+__global__ __launch_bounds__(256) void rel_check_kernel(P2PArgs a, int rec, unsigned *flag) {
+    const int4 task = a.tasks[blockIdx.x];
+    const int4 ch = a.chunks[task.x];
+    const int t = ch.y + int(threadIdx.x);
+    if (t >= ch.z) return;
+    const float4 p0 = reinterpret_cast<const float4 *>(a.trg)[2 * t];
+    const float4 p1 = reinterpret_cast<const float4 *>(a.trg)[2 * t + 1];
+    const double x[3] = {double(p0.x) + double(p1.x), double(p0.y) + double(p1.y), double(p0.z) + double(p1.z)};
+    for (int e = task.y; e < task.z; ++e) {
+        const int2 en = a.ent[e];
+        if (en.x == ch.x && en.y == kZeroShift) continue;
+        const double sh[3] = {double(shift_comp(en.y, 0)), double(shift_comp(en.y, 1)), double(shift_comp(en.y, 2))};
+        const double4 g = a.geom[en.x];
+        const double delta = g.w * (1.0 / 4096.0);
+        const double c[3] = {g.x + sh[0], g.y + sh[1], g.z + sh[2]};
+        double db = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double o = fmax(fabs(x[k] - c[k]) - 0.5 * g.w, 0.0);
+            db += o * o;
+        }
+        if (db >= delta * delta) continue;
+        const int2 rs = a.box_sl[en.x];
+        for (int j = rs.x; j < rs.y; ++j) {
+            const float *s = a.sl + int64_t(j) * rec;
+            double d2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double d = x[k] - (double(s[k]) + double(s[3 + k]) + sh[k]);
+                d2 += d * d;
+            }
+            if (d2 < delta * delta) atomicOr(flag, 1u);
+        }
     }
 }
 
@@ -438,6 +587,17 @@ constexpr int kGLd = kGK + 1;
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
+// Workgroups are dealt to the 8 XCDs in turn (workgroup i to XCD i mod 8).
+// Tiles sharing an operator are consecutive, so tile t of n is given to
+// workgroup i such that each XCD runs one contiguous range of tiles and
+// keeps their operator in its own L2: XCD k = i mod 8 takes tiles
+// [k q + min(k, r), ...) in order, q = n / 8, r = n mod 8 (a bijection of
+// [0, n)).
+__device__ __forceinline__ int xcd_tile(int i, int n) {
+    const int k = i & 7, j = i >> 3, q = n >> 3, r = n & 7;
+    return k * q + min(k, r) + j;
+}
+
 // WR row waves x 2 column waves: block tile (64 WR) rows x 128 columns.
 template <int WR>
 __global__ __launch_bounds__(128 * WR) void gemm_f32_mfma(GemmArgs a) {
@@ -445,7 +605,7 @@ __global__ __launch_bounds__(128 * WR) void gemm_f32_mfma(GemmArgs a) {
     constexpr int NA = TR * 8 / NT, NB = (kGT * 8 + NT - 1) / NT;   // float4 slots per thread
     __shared__ float As[TR * kGLd];
     __shared__ float Bs[kGT * kGLd];
-    const int4 tile = a.tiles[blockIdx.x];            // op, col0, ncol, -
+    const int4 tile = a.tiles[xcd_tile(int(blockIdx.x), int(gridDim.x))];            // op, col0, ncol, -
     const int row0 = blockIdx.y * TR;
     const float *A = a.ops + int64_t(tile.x) * a.opsz;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -557,7 +717,7 @@ constexpr int kBLd = 40;   // LDS row stride in bf16 (32 + 8): conflict-free 16-
 
 __global__ __launch_bounds__(256) void gemm_bf16x3_mfma(GemmArgs a) {
     __shared__ __bf16 Ah[kGT * kBLd], Al[kGT * kBLd], Bh[kGT * kBLd], Bl[kGT * kBLd];
-    const int4 tile = a.tiles[blockIdx.x];
+    const int4 tile = a.tiles[xcd_tile(int(blockIdx.x), int(gridDim.x))];
     const int row0 = blockIdx.y * kGT;
     const float *A = a.ops + int64_t(tile.x) * a.opsz;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1321,8 +1481,18 @@ hipError_t launch_pack_targets(int64_t n, const double *xyz, const int32_t *perm
     return hipGetLastError();
 }
 
-hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, hipStream_t s) {
+hipError_t launch_rel_check(int ntasks, const P2PArgs &a, int rec, unsigned *flag, hipStream_t s) {
     if (ntasks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(rel_check_kernel, dim3(ntasks), dim3(256), 0, s, a, rec, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, bool exact_r, hipStream_t s) {
+    if (ntasks <= 0) return hipSuccess;
+    if (exact_r && kernel == kStokeslet) {
+        hipLaunchKernelGGL(p2p_kernel<DStokesletExact>, dim3(ntasks), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     switch (kernel) {
         case kStokeslet: hipLaunchKernelGGL(p2p_kernel<DStokeslet>, dim3(ntasks), dim3(256), 0, s, a); break;
         case kRPY: hipLaunchKernelGGL(p2p_kernel<DRPY>, dim3(ntasks), dim3(256), 0, s, a); break;

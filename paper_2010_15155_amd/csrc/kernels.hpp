@@ -143,7 +143,13 @@ hipError_t launch_pack_sources(int64_t n, const double *xyz, const int32_t *perm
                                int rec, float *out, hipStream_t s);
 hipError_t launch_pack_targets(int64_t n, const double *xyz, const int32_t *perm, double3 origin,
                                double inv_len, float *out, hipStream_t s);
-hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, hipStream_t s);
+// exact_r: the Stokeslet with r from hi/lo coordinates (plans that
+// launch_rel_check flagged)
+hipError_t launch_p2p(int kernel, int ntasks, const P2PArgs &a, bool exact_r, hipStream_t s);
+// Plan-time check of the leaf-relative P2P form: *flag != 0 if two distinct
+// points of different direct-list entries lie closer than 2^-12 of the
+// source leaf's side (the flag is ORed, the caller clears it).
+hipError_t launch_rel_check(int ntasks, const P2PArgs &a, int rec, unsigned *flag, hipStream_t s);
 hipError_t launch_s2c(int src_kind, int ntasks, const S2CArgs &a, hipStream_t s);
 // Floats per staged source record of a source kind (0 for an unknown kind).
 int s2c_stage_stride(int src_kind);
