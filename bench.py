@@ -34,17 +34,20 @@ sys.path.insert(0, ROOT)
 # double-layer PVel +37 and Traction +72
 P2P_FLOPS = {"Stokeslet": 28, "RPY": 50, "LapPGrad": 26.5, "PVel": 46, "Traction": 81}
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_MFMA_PEAK_TFLOPS = 157.3      # dense MFMA, MI355X
+BF16_MFMA_PEAK_TFLOPS = 2500.0
 PROFILE = os.path.join(ROOT, "profiles", "p2p_stokeslet_1M_clustered_learned.md")
+PROFILE_M2L = os.path.join(ROOT, "profiles", "m2l_gemm_1M_clustered_learned.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2010_15155_amd", "csrc", f) for f in ("kernels.hip", "kernel_math.hpp")]
 
 
-def measured_traffic():
-    """HBM bytes per P2P launch of the learned-mode plan from the committed
-    PMC summary, or None when the kernel sources changed since the counters
-    were taken."""
+def measured_traffic(profile=PROFILE):
+    """HBM bytes per launch of a kernel of the learned-mode plan from its
+    committed PMC summary (P2P by default), or None when the kernel sources
+    changed since the counters were taken."""
     import hashlib
     try:
-        fields = dict(l.split(": ", 1) for l in open(PROFILE).read().splitlines() if ": " in l
+        fields = dict(l.split(": ", 1) for l in open(profile).read().splitlines() if ": " in l
                       and l.split(": ", 1)[0] in ("traffic_bytes_per_launch", "source_sha256"))
         h = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()[:16]
         if fields.get("source_sha256", "").strip() != h:
@@ -132,12 +135,13 @@ def measure(fmm, torch, W, kernel, x, val, p, cap, args, precision="fp32", bc="o
     for _ in range(args.warmup):
         fmm.run(val)
     torch.cuda.synchronize()
-    p2p_ms, run_ms = [], []
+    p2p_ms, run_ms, gemm_ms = [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         out = fmm.run(val)
         tm = fmm.timings()
         p2p_ms.append(tm["stages_ms"]["p2p"])
+        gemm_ms.append(tm["stages_ms"]["m2l_gemm"])
         run_ms.append(tm["t_run_ms"])
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps
@@ -162,6 +166,7 @@ def measure(fmm, torch, W, kernel, x, val, p, cap, args, precision="fp32", bc="o
     fmm.set_option("precision", "fp32")
     r = {"_out": out, "ms_per_step": wall * 1e3, "targets_per_s": len(x) / wall, "run_ms_median": float(np.median(run_ms)),
          "p2p_ms": float(np.mean(p2p_ms)), "p2p_pairs_per_s": st["p2p_pairs"] / (np.mean(p2p_ms) * 1e-3),
+         "m2l_gemm_ms": float(np.mean(gemm_ms)),
          "rel_l2_gpu_fp64_direct": errs, "t_tree_ms": t_tree, "t_plan_ms": t_plan, "stages_ms": tm["stages_ms"],
          "stages_serial_ms": serial["stages_ms"], "run_serial_ms": serial["t_run_ms"], "plan": st,
          "p": info["p"] if info else p, "leaf_cap": "per leaf" if cap == 0 else cap, "precision": precision,
@@ -351,6 +356,24 @@ def timed_runs(fmm, torch, args, sl, dl):
             "run_serial_ms": serial["t_run_ms"], "plan": st}
 
 
+def m2l_roofline(r, ncomp=4, learned_fp32=False):
+    """Roofline entry of the V-list GEMM (compressed translations) of a row:
+    2 kc^2 ncomp flops per V pair over the launch's live time (HIP events
+    around that launch on the far-field stream) against the MFMA peak of its
+    arithmetic: FP32, or BF16 for the three-pass split (3x the flops)."""
+    kc, npairs = r["plan"]["m2l_rank"], r["plan"]["v_pairs"]
+    if kc == 0 or r["m2l_gemm_ms"] <= 0:
+        return None
+    passes, peak = (3, BF16_MFMA_PEAK_TFLOPS) if r["precision"] == "split_bf16" else (1, FP32_MFMA_PEAK_TFLOPS)
+    flops = passes * 2.0 * kc * kc * ncomp * npairs
+    f = flops / (r["m2l_gemm_ms"] * 1e-3) / 1e12
+    # the committed counters cover the learned FP32 plan's launch only
+    traffic = measured_traffic(PROFILE_M2L) if learned_fp32 else None
+    return {"kernel": "gemm_bf16x3_mfma" if passes == 3 else "gemm_f32_mfma", "bound": "mfma", "achieved": f,
+            "peak": peak, "unit": "TFLOP/s", "frac": f / peak, "traffic": traffic,
+            "flops_per_launch": flops, "rank": kc, "v_pairs": npairs, "avg_launch_ms": r["m2l_gemm_ms"]}
+
+
 def p2p_roofline(kernel, r):
     """Roofline entry of the P2P kernel of a row: algorithmic FP32 flops
     (P2P_FLOPS per pair) over its live launch time against the FP32 vector peak."""
@@ -401,6 +424,7 @@ def main():
         p, cap, prec = (10, 2000, "fp32") if args.only_variant == "fixed_p10" else (0, 0, "split_bf16")
         r = measure(fmm, torch, W, "Stokeslet", x, f, p, cap, args, prec)
         r.pop("_out")
+        r["roofline_m2l"] = m2l_roofline(r)
         fmm.close()
         print(json.dumps({args.only_variant: r}), flush=True)
         return
@@ -433,6 +457,7 @@ def main():
                      "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "flops_per_pair": P2P_FLOPS["Stokeslet"], "pairs_per_launch": L["plan"]["p2p_pairs"],
                      "avg_launch_ms": L["p2p_ms"]},
+        "roofline_m2l": m2l_roofline(L, learned_fp32=True),
     }
     checked = {"learned": L}          # rows whose outputs the cpu_baseline leg checks against the oracle
     configs = {}
@@ -442,6 +467,8 @@ def main():
         line["learned_speedup_vs_fixed_p10"] = F["ms_per_step"] / L["ms_per_step"]
         line["learned_split_bf16"] = checked["learned_split_bf16"] = measure(
             fmm, torch, W, "Stokeslet", x, f, 0, 0, args, "split_bf16")
+        F["roofline_m2l"] = m2l_roofline(F)
+        line["learned_split_bf16"]["roofline_m2l"] = m2l_roofline(line["learned_split_bf16"])
         fb = torch.from_numpy(np.concatenate([d["f"], d["b"][:, None]], 1)).cuda()
         line["rpy_fixed_p10"] = checked["rpy_fixed_p10"] = measure(fmm, torch, W, "RPY", x, fb, 10, 2000, args)
         U = uniform_capacities(FMM, torch, W, x, f, args)

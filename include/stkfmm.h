@@ -230,8 +230,9 @@ stkfmm_status stkfmm_set_option(stkfmm_ctx *ctx, const char *key, const char *va
  * time): the tree-construction and tree-traversal times the paper reports
  * separately (Sec. III, t_tree and t_run).  stage_ms[16] (may be NULL) receives per-stage device times of the
  * last run in the order: 0 pack, 1 S2M, 2 M2M+UC2UE, 3 M2L, 4 S2L (X list)
- * and the periodic operator, 5 L2L+DC2DE, 6 L2T+M2T, 7 P2P, 8 combine;
- * others 0.  P2P runs on an internal stream concurrently with stages 1-6
+ * and the periodic operator, 5 L2L+DC2DE, 6 L2T+M2T, 7 P2P, 8 combine,
+ * 9 the V-list GEMM launch alone (part of stage 3: the translations before
+ * their per-destination sum); others 0.  P2P runs on an internal stream concurrently with stages 1-6
  * unless the option "overlap" is "0".  For a WALL plan the times and stages
  * are summed over its summations. */
 stkfmm_status stkfmm_get_timings(const stkfmm_ctx *ctx, double *t_tree_ms, double *t_run_ms,

@@ -16,7 +16,7 @@ KERNELS = {"LapPGrad": 0, "Stokeslet": 1, "RPY": 2, "PVel": 3, "Traction": 4, "S
 BCS = {"open": 0, "PX": 1, "PXY": 2, "PXYZ": 3, "wall": 4}
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_DOMAIN", 3: "E_UNSUPPORTED", 4: "E_NOMEM", 5: "E_DEVICE",
           6: "E_ACCURACY", 7: "E_STATE"}
-STAGES = ["pack", "s2m", "upward", "m2l", "s2l", "downward", "l2t", "p2p", "combine"]
+STAGES = ["pack", "s2m", "upward", "m2l", "s2l", "downward", "l2t", "p2p", "combine", "m2l_gemm"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libstkfmm.so")

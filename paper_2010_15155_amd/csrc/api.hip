@@ -553,7 +553,8 @@ template <class T> T *at(stkfmm_ctx *c, size_t off) { return reinterpret_cast<T 
 // densities, or, compressed, kc x kc cores on basis coefficients X) and the
 // reduce into the destination check values.
 stkfmm_status run_batch(stkfmm_ctx *c, const Batch &b, const float *ops, const float *X, double *chk,
-                        hipStream_t s, bool split_bf16 = false, bool compressed = false) {
+                        hipStream_t s, bool split_bf16 = false, bool compressed = false,
+                        hipEvent_t gemm_begin = nullptr, hipEvent_t gemm_end = nullptr) {
     if (b.npairs == 0) return STKFMM_OK;
     const DeviceOps &o = *c->ops;
     const int nc = kernel_info(c->kernel).ncomp;
@@ -569,8 +570,10 @@ stkfmm_status run_batch(stkfmm_ctx *c, const Batch &b, const float *ops, const f
     g.R = g.K = g.xs = g.ys = side;
     g.Mr = compressed ? o.kc : o.M;
     g.Mk = compressed ? o.kc : std::min(o.Mp, (o.M + 15) / 16 * 16);
+    if (gemm_begin) HIP_TRY(c, hipEventRecord(gemm_begin, s));
     if (split_bf16) HIP_TRY(c, launch_gemm_bf16x3(b.ntiles, g, s));
     else HIP_TRY(c, launch_gemm_f32(b.ntiles, g, s));
+    if (gemm_end) HIP_TRY(c, hipEventRecord(gemm_end, s));
     ReduceArgs r;
     r.dst = at<int>(c, b.rdst);
     r.off = at<int>(c, b.roff);
@@ -1882,6 +1885,7 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
     }
     hipEvent_t *ev = c->ev;
     int ne = 0;
+    bool m2l_timed = false;                                    // ev[22], ev[23]: the V-list GEMM
     HIP_TRY(c, hipEventRecord(ev[ne++], s));                  // 0 start
     const double inv = 1.0 / c->box_len;
     if (c->n_sl > 0) {
@@ -1962,10 +1966,13 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
         if (o.kc > 0) {
             st = run_compress(c, updens, c->up_cmp.as<float>(), s);
             if (st != STKFMM_OK) return st;
-            st = run_batch(c, c->m2l, o.m2l_c.as<float>(), c->up_cmp.as<float>(), dnchk, s, c->precision == 1, true);
+            st = run_batch(c, c->m2l, o.m2l_c.as<float>(), c->up_cmp.as<float>(), dnchk, s, c->precision == 1, true,
+                           ev[22], ev[23]);
         } else {
-            st = run_batch(c, c->m2l, o.m2l.as<float>(), updens, dnchk, s, c->precision == 1);
+            st = run_batch(c, c->m2l, o.m2l.as<float>(), updens, dnchk, s, c->precision == 1, false, ev[22],
+                           ev[23]);
         }
+        m2l_timed = c->m2l.npairs > 0;
         if (st != STKFMM_OK) return st;
         HIP_TRY(c, hipEventRecord(ev[ne++], s));              // 4 M2L
         HIP_TRY(c, s2c(c->s2l, kAlphaIn, dnchk, 1));
@@ -2066,6 +2073,10 @@ stkfmm_status run_pass(stkfmm_ctx *c, const double *sl_val, const double *dl_val
     c->stage_ms[7] = ms;
     HIP_TRY(c, hipEventElapsedTime(&ms, ev[ne - 2], ev[ne - 1]));
     c->stage_ms[8] = ms;
+    if (m2l_timed) {
+        HIP_TRY(c, hipEventElapsedTime(&ms, ev[22], ev[23]));
+        c->stage_ms[9] = ms;
+    }
     return STKFMM_OK;
 }
 
