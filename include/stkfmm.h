@@ -223,8 +223,30 @@ stkfmm_status stkfmm_kernel_dims(stkfmm_kernel kernel, int *k_sl, int *k_dl, int
  * p = 8 for tol 1e-5; "0" keeps them dense), "tree" = "gpu" (the default:
  * Morton keys, the sort, the refinement and the U/V/W/X lists are built by
  * the library's HIP kernels from the device coordinates) | "host" (the same
- * tree built on host threads).  Errors: E_ARG. */
+ * tree built on host threads), "operator_cache" = directory of the on-disk
+ * operator cache ("" = none; default $STKFMM_OPERATOR_CACHE, else
+ * $XDG_CACHE_HOME/stkfmm_operators, else $HOME/.cache/stkfmm_operators; see
+ * stkfmm_prepare_operators).  Errors: E_ARG. */
 stkfmm_status stkfmm_set_option(stkfmm_ctx *ctx, const char *key, const char *value);
+
+/* The FP64 operator precomputation of Sec. II for order p and boundary bc
+ * (check-to-equivalent pseudo-inverses, M2M/L2L, the V-list translations
+ * and, with m2l_tol > 0, their compressed basis; the far images for PXYZ,
+ * and for PXY and PXYZ the periodic Stokeslet's far-image fit), built or
+ * loaded from cache_dir and stored there when built.  Host only: it touches
+ * no device, so the cache can be filled before a run (the contexts read the
+ * same files).  svd_tol and m2l_tol as the options of those names (0 keeps
+ * the translations dense); cache_dir NULL or "" builds without the cache.
+ * One file per set, named by its parameters and by a hash of the library's
+ * operator sources (a changed library ignores older files); a file whose
+ * size, parameters or trailing checksum do not match is rebuilt and
+ * replaced; files are written to a temporary name and renamed, so
+ * concurrent processes are safe.  *loaded (may be NULL) receives 1 when
+ * every part came from the cache; *digest (may be NULL) a 64-bit hash of
+ * the set (equal for a built and a loaded set).  Errors: E_ARG (p outside
+ * [2, 16], tolerances outside (0, 1) / [0, 1), bad bc), E_NOMEM. */
+stkfmm_status stkfmm_prepare_operators(int p, stkfmm_bc bc, double svd_tol, double m2l_tol, const char *cache_dir,
+                                       int *loaded, uint64_t *digest);
 
 /* Timings of the last set_points (t_tree_ms) and run (t_run_ms, device event
  * time): the tree-construction and tree-traversal times the paper reports

@@ -27,7 +27,7 @@ SYMBOLS = ["stkfmm_setup", "stkfmm_set_points", "stkfmm_run", "stkfmm_evaluate",
            "stkfmm_last_error", "stkfmm_destroy", "stkfmm_mlp_nparam", "stkfmm_mlp_workspace",
            "stkfmm_set_predictor", "stkfmm_get_learned", "stkfmm_get_leaf_features",
            "stkfmm_get_plan_work", "stkfmm_mlp_forward", "stkfmm_mlp_loss_grad", "stkfmm_mlp_adam",
-           "stkfmm_get_tree", "stkfmm_direct_noalloc"]
+           "stkfmm_get_tree", "stkfmm_direct_noalloc", "stkfmm_prepare_operators"]
 ORDER_CLASSES = (6, 8, 10, 12)
 CAP_CLASSES = (250, 500, 1000, 2000)
 
@@ -72,6 +72,8 @@ def lib():
     L.stkfmm_get_learned.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(cd)]
     L.stkfmm_get_leaf_features.argtypes = [vp, vp, vp, ctypes.POINTER(i64)]
     L.stkfmm_get_plan_work.argtypes = [vp, vp]
+    L.stkfmm_prepare_operators.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_char_p, vp, vp]
     L.stkfmm_mlp_forward.argtypes = [vp, i64, vp, vp, vp, vp]
     L.stkfmm_mlp_loss_grad.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
     L.stkfmm_mlp_adam.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, vp]
@@ -85,6 +87,19 @@ def kernel_dims(kernel):
     if st != 0:
         raise StkfmmError(st, "kernel_dims")
     return k_sl.value, k_dl.value, k_t.value
+
+
+def prepare_operators(p, bc="open", svd_tol=1e-7, m2l_tol=0.0, cache_dir=None):
+    """Build or load the host operator set of order p for boundary bc through
+    the on-disk cache (stkfmm_prepare_operators; host only, no device).
+    Returns (loaded, digest): loaded is True when the set came from cache_dir."""
+    loaded, digest = ctypes.c_int(), ctypes.c_uint64()
+    d = None if cache_dir is None else os.fsencode(cache_dir)
+    st = lib().stkfmm_prepare_operators(int(p), BCS[bc], float(svd_tol), float(m2l_tol), d,
+                                        ctypes.byref(loaded), ctypes.byref(digest))
+    if st != 0:
+        raise StkfmmError(st, "prepare_operators")
+    return bool(loaded.value), int(digest.value)
 
 
 def _ptr(t, n_cols, name, device=None, rows=None):

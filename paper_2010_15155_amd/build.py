@@ -11,7 +11,10 @@ LIB = os.path.join(HERE, "libstkfmm.so")
 ARCH = os.environ.get("STKFMM_ARCH", "gfx950")
 
 HIP_SOURCES = ["kernels.hip", "api.hip", "mlp.hip", "wall.hip", "tree_gpu.hip", "periodic.hip"]
-CPP_SOURCES = ["tree.cpp", "operators.cpp", "learn.cpp"]
+CPP_SOURCES = ["tree.cpp", "operators.cpp", "learn.cpp", "opcache.cpp"]
+# the sources that compute the cached operators: their hash names the cache
+# files, so a library built from changed operator code ignores older files
+OPERATOR_SOURCES = ["operators.cpp", "internal.hpp", "pool.hpp", "opcache.cpp"]
 HIP_FLAGS = ["-O3", "--offload-arch=" + ARCH, "-std=c++17", "-fPIC", "-Wall",
              # no packed FP32 instructions (v_pk_*_f32) anywhere
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -38,9 +41,19 @@ def _run(cmds, verbose):
         raise RuntimeError("build failed:\n" + msg)
 
 
+def operator_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in OPERATOR_SOURCES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     objs, cmds = [], []
+    cpp_flags = CPP_FLAGS + ['-DKAFMM_OPS_SOURCE_HASH="%s"' % operator_source_hash()]
     for s in HIP_SOURCES:
         o = os.path.join(BUILD, s + ".o")
         objs.append(o)
@@ -48,7 +61,7 @@ def build(verbose=False):
     for s in CPP_SOURCES:
         o = os.path.join(BUILD, s + ".o")
         objs.append(o)
-        cmds.append(["g++"] + CPP_FLAGS + ["-c", os.path.join(CSRC, s), "-o", o])
+        cmds.append(["g++"] + cpp_flags + ["-c", os.path.join(CSRC, s), "-o", o])
     _run(cmds, verbose)
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([["hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH, "-pthread", "-o", tmp] + objs], verbose)

@@ -172,6 +172,7 @@ struct stkfmm_ctx {
     double box_len = 1.0;
     std::string err;
     double svd_tol = 1e-7;
+    std::string op_cache = default_operator_cache_dir();   // operator cache directory ("" = none)
     double m2l_tol = 5e-8;      // compression of the V-list translations (0: dense)
     bool m2l_tol_set = false;   // set by the caller (else learned plans use tol / 50)
     bool rel_exact = false;     // P2P forms r from hi/lo coordinates (close pairs across leaves)
@@ -291,7 +292,7 @@ stkfmm_status get_ops(stkfmm_ctx *c, int p, bool periodic, double m2l_tol, Devic
         return STKFMM_OK;
     }
     Operators h;
-    std::string e = build_operators(p, c->svd_tol, periodic, h, m2l_tol);
+    std::string e = cached_operators(c->op_cache, p, c->svd_tol, periodic, m2l_tol, h, nullptr);
     if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
     auto d = std::make_unique<DeviceOps>();
     d->p = p;
@@ -384,7 +385,7 @@ stkfmm_status get_periodic_stokes(stkfmm_ctx *c, int pmask, StokesFarOps **out) 
         return STKFMM_OK;
     }
     std::vector<double> Q, X, Z;
-    std::string e = build_periodic_stokes(kStokesFarOrder, c->svd_tol, pmask == 3, Q, X, Z);
+    std::string e = cached_periodic_stokes(c->op_cache, kStokesFarOrder, c->svd_tol, pmask == 3, Q, X, Z, nullptr);
     if (!e.empty()) return fail(c, STKFMM_E_ARG, e);
     auto d = std::make_unique<StokesFarOps>();
     d->M = int(X.size() / 3);
@@ -712,6 +713,7 @@ stkfmm_status wall_set_points(stkfmm_ctx *c, int kernel, int64_t n_src, const do
         if (st != STKFMM_OK) return fail(c, st, "wall summation context");
         stkfmm_ctx *sc = w.sub[k];
         sc->svd_tol = c->svd_tol;
+        sc->op_cache = c->op_cache;
         sc->m2l_tol = c->m2l_tol;
         sc->precision = c->precision;
         sc->overlap = c->overlap;
@@ -1007,7 +1009,40 @@ stkfmm_status stkfmm_set_option(stkfmm_ctx *c, const char *key, const char *valu
         c->planned = false;
         return STKFMM_OK;
     }
+    if (k == "operator_cache") {
+        c->op_cache = v;
+        return STKFMM_OK;
+    }
     return fail(c, STKFMM_E_ARG, "unknown option " + k);
+}
+
+stkfmm_status stkfmm_prepare_operators(int p, stkfmm_bc bc, double svd_tol, double m2l_tol, const char *cache_dir,
+                                       int *loaded, uint64_t *digest) {
+    if (p < 2 || p > 16 || !(svd_tol > 0) || !(svd_tol < 1) || !(m2l_tol >= 0) || !(m2l_tol < 1))
+        return STKFMM_E_ARG;
+    if (bc != STKFMM_BC_OPEN && bc != STKFMM_BC_PXYZ && bc != STKFMM_BC_PXY && bc != STKFMM_BC_WALL)
+        return STKFMM_E_ARG;
+    const std::string dir = cache_dir ? cache_dir : "";
+    const bool periodic = bc == STKFMM_BC_PXYZ;
+    try {
+        Operators h;
+        bool ld = false;
+        if (!cached_operators(dir, p, svd_tol, periodic, m2l_tol, h, &ld).empty()) return STKFMM_E_ARG;
+        uint64_t dg = operators_digest(h, periodic);
+        if (bc == STKFMM_BC_PXYZ || bc == STKFMM_BC_PXY) {
+            std::vector<double> Q, X, Z;
+            bool ls = false;
+            if (!cached_periodic_stokes(dir, kStokesFarOrder, svd_tol, bc == STKFMM_BC_PXY, Q, X, Z, &ls).empty())
+                return STKFMM_E_ARG;
+            dg ^= stokes_far_digest(kStokesFarOrder, svd_tol, bc == STKFMM_BC_PXY, Q, X, Z) * 0x9e3779b97f4a7c15ull;
+            ld = ld && ls;
+        }
+        if (loaded) *loaded = ld ? 1 : 0;
+        if (digest) *digest = dg;
+    } catch (const std::bad_alloc &) {
+        return STKFMM_E_NOMEM;
+    }
+    return STKFMM_OK;
 }
 
 stkfmm_status stkfmm_get_timings(const stkfmm_ctx *c, double *t_tree, double *t_run, double stage_ms[16]) {

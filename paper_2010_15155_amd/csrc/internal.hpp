@@ -143,6 +143,22 @@ std::string build_operators(int p, double svd_tol, bool periodic, Operators &ops
 std::string build_periodic_stokes(int p, double svd_tol, bool doubly, std::vector<double> &Q,
                                   std::vector<double> &X, std::vector<double> &Z);
 
+// On-disk operator cache (opcache.cpp, best effort).  cached_operators and
+// cached_periodic_stokes load the set from a file of directory dir whose
+// parameters and source hash match (*loaded = true), else build it and store
+// it there; dir "" builds only.  They return the builders' error strings.
+std::string cached_operators(const std::string &dir, int p, double svd_tol, bool periodic, double m2l_tol,
+                             Operators &ops, bool *loaded);
+std::string cached_periodic_stokes(const std::string &dir, int p, double svd_tol, bool doubly, std::vector<double> &Q,
+                                   std::vector<double> &X, std::vector<double> &Z, bool *loaded);
+// The cache directory by default: $STKFMM_OPERATOR_CACHE ("" disables),
+// else $XDG_CACHE_HOME/stkfmm_operators, else $HOME/.cache/stkfmm_operators.
+std::string default_operator_cache_dir();
+// 64-bit hashes of a set as the cache file stores it (equal for a built and a loaded set).
+uint64_t operators_digest(const Operators &ops, bool periodic);
+uint64_t stokes_far_digest(int p, double svd_tol, bool doubly, const std::vector<double> &Q,
+                           const std::vector<double> &X, const std::vector<double> &Z);
+
 // Index of a relative offset o in [-3,3]^3.
 inline int offset_index(int ox, int oy, int oz) { return ((oz + 3) * 7 + (oy + 3)) * 7 + (ox + 3); }
 

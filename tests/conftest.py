@@ -7,6 +7,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# the tests build their operators in memory; the on-disk operator cache is
+# exercised by its own tests with their own directories
+os.environ.setdefault("STKFMM_OPERATOR_CACHE", "")
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
