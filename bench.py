@@ -333,6 +333,21 @@ def sphere_doublelayer_2m(FMM, torch, W, args, p=10, cap=2000):
     return rows
 
 
+def uniform_4096(FMM, torch, W, args, p=8, cap=64):
+    """The small configuration (4096 uniform points, seed 101; the case the
+    plain FP64 oracle KIFMM also runs): the GPU pass here, while the CPU leg
+    times that oracle KIFMM on the same points and judges both against the
+    oracle's direct sum over all 4096 targets."""
+    d = W.uniform_stokeslet()
+    fmm = FMM()
+    r = measure(fmm, torch, W, "Stokeslet", torch.from_numpy(d["xyz"]).cuda(), torch.from_numpy(d["f"]).cuda(),
+                p, cap, args)
+    fmm.close()
+    r["_sample"] = {"got": r.pop("_out").cpu().numpy()}
+    r["_d"] = d
+    return r
+
+
 def timed_runs(fmm, torch, args, sl, dl):
     """Warm-up and timed passes of the current plan, with P2P launch times."""
     for _ in range(args.warmup):
@@ -493,6 +508,7 @@ def main():
         }
         for k in ("stokes_reg_vel_p8", "rpy_wall_p10"):
             line["widened"][k].pop("_out")
+        configs["uniform_4096_p8"] = uniform_4096(FMM, torch, W, args)
         configs["periodic_laplace_4M_p12"] = periodic_laplace_4m(FMM, torch, W, args)
         configs["sphere_doublelayer_2M_p10"] = sphere_doublelayer_2m(FMM, torch, W, args)
         line["plan_ms"] = tree_build(FMM, x)
@@ -579,6 +595,20 @@ def cpu_baseline(d, budget_s, checked, configs):
         else:
             errs[name] = rel_fields(got, ref, FIELDS["Stokeslet"])
     out["rel_l2_vs_oracle"] = errs
+    c1 = configs.get("uniform_4096_p8")
+    if c1:
+        from oracle import kifmm
+        dd = c1["_d"]
+        ref1 = direct.stokeslet(dd["xyz"], dd["f"], dd["xyz"])
+        c1["rel_l2_vs_oracle"] = rel_fields(c1["_sample"]["got"], ref1, FIELDS["Stokeslet"])
+        t0 = time.perf_counter()
+        uk = kifmm.evaluate("Stokeslet", dd["xyz"], dd["f"], None, None, dd["xyz"], p=c1["p"], leaf_cap=c1["leaf_cap"])
+        dtk = time.perf_counter() - t0
+        out["kifmm_oracle_4096"] = {
+            "value": len(dd["xyz"]) / dtk, "unit": "targets/s", "seconds": dtk, "p": c1["p"],
+            "leaf_cap": c1["leaf_cap"], "rel_l2_vs_direct": rel_fields(uk, ref1, FIELDS["Stokeslet"]),
+            "kind": "plain FP64 KIFMM oracle (NumPy, the paper's kernel tables)",
+            "gpu_ms_per_step_same_points": c1["ms_per_step"]}
     c3 = configs.get("periodic_laplace_4M_p12")
     if c3:
         dd = c3["_d"]
