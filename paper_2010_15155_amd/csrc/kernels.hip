@@ -706,6 +706,108 @@ __global__ __launch_bounds__(128 * WR) void gemm_f32_mfma(GemmArgs a) {
     }
 }
 
+// Row-strip variant for operator sides that 64-row tiles would pad (R = 32 NR
+// rows): two waves per 32-row strip of all NR strips, each owning 32 rows x
+// 64 of the tile's 128 columns (two 32 x 32 accumulators), so no wave
+// computes padding rows and the 2 NR equal waves spread evenly over a CU's
+// 4 SIMDs (with one wave per strip and 128 columns each, a block's 5 waves
+// could not, and the launch ran 37 % slower).  Same staging, K steps
+// and per-output MFMA order as gemm_f32_mfma, hence the same results.
+template <int NR>
+__global__ __launch_bounds__(128 * NR) void gemm_f32_strip(GemmArgs a) {
+    constexpr int TR = 32 * NR, NT = 128 * NR;
+    constexpr int NA = TR * 8 / NT, NB = (kGT * 8 + NT - 1) / NT;   // float4 slots per thread
+    __shared__ float As[TR * kGLd];
+    __shared__ float Bs[kGT * kGLd];
+    const int4 tile = a.tiles[xcd_tile(int(blockIdx.x), int(gridDim.x))];            // op, col0, ncol, -
+    const float *A = a.ops + int64_t(tile.x) * a.opsz;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 64;   // two waves per strip, 64 columns each
+    const bool live = wr < a.Mr;                     // rows at or past Mr are zero padding
+    floatx16 acc[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[j][v] = 0.0f;
+    int ar[NA], ak[NA], br[NB], bk[NB];
+    bool arow_ok[NA], bcol_ok[NB], bslot[NB];
+    const float *bptr[NB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int idx = tid + NT * i;
+        ar[i] = idx >> 3;
+        ak[i] = (idx & 7) * 4;
+        arow_ok[i] = ar[i] < a.R;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int idx = tid + NT * i;
+        br[i] = idx >> 3;
+        bk[i] = (idx & 7) * 4;
+        bslot[i] = idx < kGT * 8;
+        bcol_ok[i] = bslot[i] && br[i] < tile.z;
+        const int c = bcol_ok[i] ? a.bcol[tile.y + br[i]] : 0;
+        bptr[i] = a.X + int64_t(c) * a.xs;
+    }
+    float4 ra[NA], rb[NB];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+            ra[i] = arow_ok[i] ? *reinterpret_cast<const float4 *>(A + int64_t(ar[i]) * a.K + k0 + ak[i])
+                               : make_float4(0, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            rb[i] = bcol_ok[i] ? *reinterpret_cast<const float4 *>(bptr[i] + k0 + bk[i]) : make_float4(0, 0, 0, 0);
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < a.Mk; k0 += kGK) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            float *da = As + ar[i] * kGLd + ak[i];
+            da[0] = ra[i].x; da[1] = ra[i].y; da[2] = ra[i].z; da[3] = ra[i].w;
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            if (!bslot[i]) continue;
+            float *db = Bs + br[i] * kGLd + bk[i];
+            db[0] = rb[i].x; db[1] = rb[i].y; db[2] = rb[i].z; db[3] = rb[i].w;
+        }
+        __syncthreads();
+        if (k0 + kGK < a.Mk) fetch(k0 + kGK);
+        const int kend = min(kGK, a.Mk - k0);
+        if (live) {
+#pragma unroll
+            for (int kk = 0; kk < kGK; kk += 2) {
+                if (kk < kend) {
+                    const int k = kk + (lane >> 5);
+                    const float av = As[(wr + (lane & 31)) * kGLd + k];
+                    float bv[2];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) bv[j] = Bs[(wc + 32 * j + (lane & 31)) * kGLd + k];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[j], acc[j], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // epilogue: lane holds column (lane & 31) and rows 8*(v/4) + 4*(lane/32) + v%4
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = wc + 32 * j + (lane & 31);
+        if (col >= tile.z) continue;
+        float *Y = a.Y + int64_t(a.ycol[tile.y + col]) * a.ys;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int row = wr + 8 * g + 4 * (lane >> 5);
+            if (row < a.R) {
+                float4 v = make_float4(acc[j][4 * g], acc[j][4 * g + 1], acc[j][4 * g + 2], acc[j][4 * g + 3]);
+                *reinterpret_cast<float4 *>(Y + row) = v;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ split-BF16 grouped GEMM
 // Same tiling as gemm_f32_mfma, arithmetic in three BF16 passes:
 // A = Ah + Al, X = Xh + Xl (hi = RN_bf16(v), lo = RN_bf16(v - hi)), and
@@ -1586,6 +1688,15 @@ static bool gemm_args_ok(const GemmArgs &a) {
 hipError_t launch_gemm_f32(int ntiles, const GemmArgs &a, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     if (!gemm_args_ok(a)) return hipErrorInvalidValue;
+    // 160-row operators (rank 160, the learned plans' translations): the
+    // row-strip kernel, which computes no padding rows (measured 1.64 against
+    // 1.72 ms for the 1M V-list launch); at 224 rows the 256-row tile of
+    // gemm_f32_mfma<4> measured faster (0.67 against 0.76 ms), and 192 rows
+    // need no padding
+    if (a.R == 160) {
+        hipLaunchKernelGGL(gemm_f32_strip<5>, dim3(ntiles), dim3(640), 0, s, a);
+        return hipGetLastError();
+    }
     // row tiles of 64 WR rows (WR = 2..4): the fewest padded rows, then the
     // fewest row blocks (each row block reads the column tile again)
     int wr = 2;
