@@ -384,7 +384,7 @@ def m2l_roofline(r, ncomp=4, learned_fp32=False):
     f = flops / (r["m2l_gemm_ms"] * 1e-3) / 1e12
     # the committed counters cover the learned FP32 plan's launch only
     traffic = measured_traffic(PROFILE_M2L) if learned_fp32 else None
-    name = "gemm_bf16x3_mfma" if passes == 3 else "gemm_f32_strip<5>" if kc == 160 else "gemm_f32_mfma"
+    name = ("gemm_bf16x3_" if passes == 3 else "gemm_f32_") + ("strip<5>" if kc == 160 else "mfma")
     return {"kernel": name, "bound": "mfma", "achieved": f,
             "peak": peak, "unit": "TFLOP/s", "frac": f / peak, "traffic": traffic,
             "flops_per_launch": flops, "rank": kc, "v_pairs": npairs, "avg_launch_ms": r["m2l_gemm_ms"]}

@@ -922,6 +922,121 @@ __global__ __launch_bounds__(256) void gemm_bf16x3_mfma(GemmArgs a) {
     }
 }
 
+// Row-strip form of gemm_bf16x3_mfma for 160-row operators (rank 160): one
+// block covers all rows, two waves per 32-row strip with 64 columns each
+// (10 equal waves), so each column tile's source coefficients are gathered
+// once and no wave computes padding rows; hi/lo values are staged with one
+// 8-byte LDS write per four.  Same arithmetic per output as
+// gemm_bf16x3_mfma.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+template <int NR>
+__global__ __launch_bounds__(128 * NR) void gemm_bf16x3_strip(GemmArgs a) {
+    constexpr int TR = 32 * NR, NT = 128 * NR;
+    constexpr int NA = TR * 8 / NT, NB = (kGT * 8 + NT - 1) / NT;   // float4 slots per thread
+    __shared__ __align__(16) __bf16 Ah[TR * kBLd], Al[TR * kBLd], Bh[kGT * kBLd], Bl[kGT * kBLd];
+    const int4 tile = a.tiles[xcd_tile(int(blockIdx.x), int(gridDim.x))];
+    const float *A = a.ops + int64_t(tile.x) * a.opsz;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 64;
+    const bool live = wr < a.Mr;
+    floatx16 acc[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[j][v] = 0.0f;
+    int ar[NA], ak[NA], br[NB], bk[NB];
+    bool arow_ok[NA], bcol_ok[NB], bslot[NB];
+    const float *bptr[NB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int idx = tid + NT * i;
+        ar[i] = idx >> 3;
+        ak[i] = (idx & 7) * 4;
+        arow_ok[i] = ar[i] < a.R;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int idx = tid + NT * i;
+        br[i] = idx >> 3;
+        bk[i] = (idx & 7) * 4;
+        bslot[i] = idx < kGT * 8;
+        bcol_ok[i] = bslot[i] && br[i] < tile.z;
+        const int c = bcol_ok[i] ? a.bcol[tile.y + br[i]] : 0;
+        bptr[i] = a.X + int64_t(c) * a.xs;
+    }
+    float4 ra[NA], rb[NB];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+            ra[i] = arow_ok[i] ? *reinterpret_cast<const float4 *>(A + int64_t(ar[i]) * a.K + k0 + ak[i])
+                               : make_float4(0, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            rb[i] = bcol_ok[i] ? *reinterpret_cast<const float4 *>(bptr[i] + k0 + bk[i]) : make_float4(0, 0, 0, 0);
+    };
+    auto split4 = [](float4 v, __bf16 *hi, __bf16 *lo) {
+        bf16x4 h, l;
+        h[0] = __bf16(v.x); l[0] = __bf16(v.x - float(h[0]));
+        h[1] = __bf16(v.y); l[1] = __bf16(v.y - float(h[1]));
+        h[2] = __bf16(v.z); l[2] = __bf16(v.z - float(h[2]));
+        h[3] = __bf16(v.w); l[3] = __bf16(v.w - float(h[3]));
+        *reinterpret_cast<bf16x4 *>(hi) = h;
+        *reinterpret_cast<bf16x4 *>(lo) = l;
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < a.Mk; k0 += kGK) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int o = ar[i] * kBLd + ak[i];
+            split4(ra[i], Ah + o, Al + o);
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            if (!bslot[i]) continue;
+            const int o = br[i] * kBLd + bk[i];
+            split4(rb[i], Bh + o, Bl + o);
+        }
+        __syncthreads();
+        if (k0 + kGK < a.Mk) fetch(k0 + kGK);
+        const int kend = min(kGK, a.Mk - k0);
+        if (live) {
+#pragma unroll
+            for (int kk = 0; kk < kGK; kk += 16) {
+                if (kk >= kend) continue;
+                const int ko = kk + 8 * (lane >> 5);
+                const int ra0 = (wr + (lane & 31)) * kBLd + ko;
+                const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(Ah + ra0);
+                const bf16x8 al = *reinterpret_cast<const bf16x8 *>(Al + ra0);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int rb0 = (wc + 32 * j + (lane & 31)) * kBLd + ko;
+                    const bf16x8 bh = *reinterpret_cast<const bf16x8 *>(Bh + rb0);
+                    const bf16x8 bl = *reinterpret_cast<const bf16x8 *>(Bl + rb0);
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[j], 0, 0, 0);
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[j], 0, 0, 0);
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[j], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int col = wc + 32 * j + (lane & 31);
+        if (col >= tile.z) continue;
+        float *Y = a.Y + int64_t(a.ycol[tile.y + col]) * a.ys;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int row = wr + 8 * g + 4 * (lane >> 5);
+            if (row < a.R) {
+                float4 v = make_float4(acc[j][4 * g], acc[j][4 * g + 1], acc[j][4 * g + 2], acc[j][4 * g + 3]);
+                *reinterpret_cast<float4 *>(Y + row) = v;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ FP64 GEMM (pseudo-inverse)
 // C[col][i] = scale(col) * sum_k A[i][k] * B[col][k],  i < R, k < K.
 // B columns are FP64 (check values or scratch); C is FP64 scratch or FP32
@@ -1714,6 +1829,10 @@ hipError_t launch_gemm_f32(int ntiles, const GemmArgs &a, hipStream_t s) {
 hipError_t launch_gemm_bf16x3(int ntiles, const GemmArgs &a, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     if (!gemm_args_ok(a)) return hipErrorInvalidValue;
+    if (a.R == 160) {
+        hipLaunchKernelGGL(gemm_bf16x3_strip<5>, dim3(ntiles), dim3(640), 0, s, a);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(gemm_bf16x3_mfma, dim3(ntiles, (a.R + kGT - 1) / kGT), dim3(256), 0, s, a);
     return hipGetLastError();
 }
