@@ -38,7 +38,9 @@ FP32_MFMA_PEAK_TFLOPS = 157.3      # dense MFMA, MI355X
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 PROFILE = os.path.join(ROOT, "profiles", "p2p_stokeslet_1M_clustered_learned.md")
 PROFILE_M2L = os.path.join(ROOT, "profiles", "m2l_gemm_1M_clustered_learned.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2010_15155_amd", "csrc", f) for f in ("kernels.hip", "kernel_math.hpp")]
+# the sources that decide a launch's work and traffic: the kernels and the
+# plan that sizes their tasks
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2010_15155_amd", "csrc", f) for f in ("kernels.hip", "kernel_math.hpp", "api.hip")]
 
 
 def measured_traffic(profile=PROFILE):

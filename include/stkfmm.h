@@ -215,7 +215,7 @@ stkfmm_status stkfmm_kernel_dims(stkfmm_kernel kernel, int *k_sl, int *k_dl, int
  * (default 1e-7), "overlap" = "1" (P2P concurrent with the far field, the
  * default) | "0" (serial, for per-stage timing), "tol" = accuracy target of
  * the learned mode (default 1e-5), "p2p_task_sources" = sources per P2P task
- * (default 2048), "w_direct_frac" / "x_direct_frac" = W / X pairs whose source
+ * (default 1024), "w_direct_frac" / "x_direct_frac" = W / X pairs whose source
  * count / target count is below this fraction of M are summed directly
  * (defaults 0.73 / 0.5), "m2l_tol" = relative singular-value cut of the
  * shared basis that compresses the V-list translations (default 5e-8: rank

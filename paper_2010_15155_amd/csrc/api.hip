@@ -215,7 +215,7 @@ struct stkfmm_ctx {
     std::vector<double> hcoords[3];      // normalised user-order coordinates of the last plan
     bool hcoords_valid = false;          // (else copied from coords[] when asked for)
     double w_direct_frac = 0.73, x_direct_frac = 0.5;
-    int64_t p2p_task_sources = 2048;
+    int64_t p2p_task_sources = 1024;  // measured on the 1M learned plan: 8.46 ms per pass against 8.60 at 2048
     Batch m2l;
     std::vector<Batch> m2m;                 // by parent level
     std::vector<L2LLevel> l2l;              // by child level
