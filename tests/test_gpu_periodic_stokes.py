@@ -236,9 +236,9 @@ def test_pvel_translation(fmm):
                                  trg_xyz=cu(w(t)), p=8, leaf_cap=64, bc="PXYZ").cpu().numpy())
     e_u, e_p = _pvel_errors(outs[1], outs[0])
     print("periodic PVel translation: u", e_u, "p", e_p, flush=True)
-    # two p = 8 evaluations, each within 1e-5 (u) and 2e-5 (p) of the sum
-    # (measured 7.0e-6 and 1.3e-7)
-    assert e_u < 2e-5 and e_p < 4e-5
+    # two p = 8 evaluations, each within 1e-5 (u) of the sum (measured
+    # 7.0e-6 for u and 1.3e-7 for p)
+    assert e_u < 2e-5 and e_p < 2e-5
 
 
 def _targets_away(sources, k, seed, dmin=0.02):
